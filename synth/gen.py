@@ -1,0 +1,274 @@
+"""Seeded generators: parameters, cameras, scenes, clouds, images (inputs only)."""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Degree-0 colour encoding used for inputs: colour = f00 * Y00 + 1/2 with the
+# orthonormal constant Y00 = 1 / (2 sqrt(pi)); f00 = (colour - 1/2) * 2 sqrt(pi).
+_DC_SCALE = 2.0 * math.sqrt(math.pi)
+
+
+def param_rows(sh_degree: int) -> int:
+    """Number of canonical rows for SH degree D: 11 + 3 (D+1)^2."""
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def sh_coeffs(sh_degree: int) -> int:
+    return (sh_degree + 1) ** 2
+
+
+def make_camera(width, height, fx, fy, cx, cy, R, t) -> dict:
+    vm = np.zeros((3, 4), np.float32)
+    vm[:, :3] = np.asarray(R, np.float64)
+    vm[:, 3] = np.asarray(t, np.float64)
+    return dict(width=int(width), height=int(height), fx=float(np.float32(fx)),
+                fy=float(np.float32(fy)), cx=float(np.float32(cx)),
+                cy=float(np.float32(cy)), viewmat=vm)
+
+
+def look_at_camera(eye, target, width, height, hfov_deg=60.0, up=(0.0, 1.0, 0.0)) -> dict:
+    """Pinhole camera at `eye` looking at `target`; OpenCV axes, world +y up.
+
+    fx = fy = W / (2 tan(hfov/2)), principal point at the image centre.
+    """
+    eye = np.asarray(eye, np.float64)
+    f = np.asarray(target, np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.asarray(up, np.float64))
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    t = -R @ eye
+    fx = width / (2.0 * math.tan(math.radians(hfov_deg) / 2.0))
+    return make_camera(width, height, fx, fx, width / 2.0, height / 2.0, R, t)
+
+
+def ring_cameras(n=60, width=1920, height=1440, radius=4.5, height_y=0.8,
+                 target=(0.0, 0.3, 0.0), hfov_deg=60.0) -> list:
+    """n cameras evenly spaced on a horizontal ring, all looking at `target`."""
+    cams = []
+    for i in range(n):
+        a = 2.0 * math.pi * i / n
+        eye = (radius * math.sin(a), height_y, radius * math.cos(a))
+        cams.append(look_at_camera(eye, target, width, height, hfov_deg))
+    return cams
+
+
+def random_image(seed, height, width, lo=0.0, hi=1.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, (3, height, width)).astype(np.float32)
+
+
+def cfg1_inputs(seed=0, n=1000, width=128, height=128, focal=128.0):
+    """Small parity workload.
+
+    Draw order: means U[-1,1]^3 (n,3); log-scales N(-3, 0.5^2) (n,3);
+    quaternions N(0, I4) normalised (n,4); opacity logits N(0,1) (n,);
+    DC colour coefficients U[-sqrt(pi), sqrt(pi)] (n,3), i.e. degree-0 colours
+    uniform in [0, 1]; target image U[0,1]^(3,H,W).  Means are then shifted by
+    +4 along z.  Camera: identity pose, fx = fy = focal, principal point at the
+    image centre.
+    """
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, (n, 3))
+    log_s = rng.normal(-3.0, 0.5, (n, 3))
+    q = rng.normal(0.0, 1.0, (n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    logit = rng.normal(0.0, 1.0, n)
+    half = math.sqrt(math.pi)
+    dc = rng.uniform(-half, half, (n, 3))
+    target = rng.uniform(0.0, 1.0, (3, height, width))
+    means[:, 2] += 4.0
+    P = np.zeros((param_rows(0), n), np.float32)
+    P[0:3] = means.T
+    P[3:6] = log_s.T
+    P[6:10] = q.T
+    P[10] = logit
+    P[11:14] = dc.T
+    cam = make_camera(width, height, focal, focal, width / 2.0, height / 2.0,
+                      np.eye(3), np.zeros(3))
+    return P, cam, target.astype(np.float32)
+
+
+def random_gaussians(seed, n, sh_degree=0, centre=(0.0, 0.0, 4.0), spread=1.0,
+                     log_scale_mu=-3.0, log_scale_sigma=0.5, sh_sigma=0.3):
+    """Generic random Gaussians around `centre` (used for edge-case tests).
+
+    Draw order: means, log-scales, quaternions, logits, DC, higher SH.
+    """
+    rng = np.random.default_rng(seed)
+    K = sh_coeffs(sh_degree)
+    means = rng.uniform(-spread, spread, (n, 3)) + np.asarray(centre)
+    log_s = rng.normal(log_scale_mu, log_scale_sigma, (n, 3))
+    q = rng.normal(0.0, 1.0, (n, 4))
+    logit = rng.normal(0.0, 1.0, n)
+    half = math.sqrt(math.pi)
+    dc = rng.uniform(-half, half, (n, 3))
+    hi = rng.normal(0.0, sh_sigma, (n, K - 1, 3))
+    P = np.zeros((param_rows(sh_degree), n), np.float32)
+    P[0:3] = means.T
+    P[3:6] = log_s.T
+    P[6:10] = q.T
+    P[10] = logit
+    P[11:14] = dc.T
+    if K > 1:
+        P[14:] = hi.reshape(n, -1).T
+    return P
+
+
+# ---------------------------------------------------------------------------
+# Spheres + planes scene
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Scene:
+    centres: np.ndarray          # (S, 3)
+    radii: np.ndarray            # (S,)
+    planes: list                 # [(origin, u_axis, v_axis, normal, u_len, v_len)]
+    base: np.ndarray             # (S + n_planes, 3) base colours
+    freq: np.ndarray             # (S + n_planes, 3) texture frequencies
+    phase: np.ndarray            # (S + n_planes, 3) texture phases
+    areas: np.ndarray = field(default=None)
+
+    @property
+    def total_area(self) -> float:
+        return float(self.areas.sum())
+
+
+def spheres_planes_scene(seed=0, n_spheres=20) -> Scene:
+    """20 random spheres (r in [0.2, 1]) plus floor, back wall and side wall.
+
+    Draw order: disc radius U (S,), disc angle U (S,), centre y U[-0.5,1.5] (S,),
+    radius U[0.2,1] (S,), base colours U[0.15,0.85] (S+3,3), texture
+    frequencies U[2,9] (S+3,3), phases U[0,2pi] (S+3,3).
+    """
+    rng = np.random.default_rng(seed)
+    rd = 2.5 * np.sqrt(rng.uniform(0, 1, n_spheres))
+    th = rng.uniform(0, 2 * np.pi, n_spheres)
+    cy = rng.uniform(-0.5, 1.5, n_spheres)
+    radii = rng.uniform(0.2, 1.0, n_spheres)
+    centres = np.stack([rd * np.cos(th), cy, rd * np.sin(th)], 1)
+    planes = [
+        # floor y = -1.5, x,z in [-6, 6], normal +y
+        (np.array([-6.0, -1.5, -6.0]), np.array([1.0, 0, 0]), np.array([0, 0, 1.0]),
+         np.array([0, 1.0, 0]), 12.0, 12.0),
+        # back wall z = -6, x in [-6,6], y in [-1.5, 4.5], normal +z
+        (np.array([-6.0, -1.5, -6.0]), np.array([1.0, 0, 0]), np.array([0, 1.0, 0]),
+         np.array([0, 0, 1.0]), 12.0, 6.0),
+        # side wall x = -6, z in [-6,6], y in [-1.5, 4.5], normal +x
+        (np.array([-6.0, -1.5, -6.0]), np.array([0, 0, 1.0]), np.array([0, 1.0, 0]),
+         np.array([1.0, 0, 0]), 12.0, 6.0),
+    ]
+    ns = n_spheres + len(planes)
+    base = rng.uniform(0.15, 0.85, (ns, 3))
+    freq = rng.uniform(2.0, 9.0, (ns, 3))
+    phase = rng.uniform(0.0, 2 * np.pi, (ns, 3))
+    areas = np.concatenate([4 * np.pi * radii ** 2,
+                            [p[4] * p[5] for p in planes]])
+    return Scene(centres, radii, planes, base, freq, phase, areas)
+
+
+def _texture(scene: Scene, sid: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """Procedural colour: base + sinusoidal detail + checker, clipped to [0.02, 0.98]."""
+    b = scene.base[sid]
+    f = scene.freq[sid]
+    ph = scene.phase[sid]
+    s = np.sin(f * p[:, [0, 1, 2]] + ph) * np.sin(f * p[:, [1, 2, 0]] * 0.7 + ph * 1.3)
+    chk = ((np.floor(p[:, 0] * 2.0) + np.floor(p[:, 1] * 2.0) + np.floor(p[:, 2] * 2.0)) % 2)
+    c = b + 0.25 * s + 0.08 * (chk[:, None] - 0.5)
+    return np.clip(c, 0.02, 0.98)
+
+
+def sample_surface(scene: Scene, n: int, seed: int):
+    """Area-weighted surface samples: returns points (n,3), normals (n,3), colours (n,3).
+
+    Draw order: surface choice (multinomial over areas), then per surface in
+    index order: spheres draw N(0,I3) directions; planes draw U[0,1]^2.
+    """
+    rng = np.random.default_rng(seed)
+    counts = rng.multinomial(n, scene.areas / scene.areas.sum())
+    pts, nrm, sid = [], [], []
+    S = len(scene.radii)
+    for s in range(len(counts)):
+        k = counts[s]
+        if k == 0:
+            continue
+        if s < S:
+            d = rng.normal(0, 1, (k, 3))
+            d /= np.linalg.norm(d, axis=1, keepdims=True)
+            pts.append(scene.centres[s] + scene.radii[s] * d)
+            nrm.append(d)
+        else:
+            o, ua, va, nn, ul, vl = scene.planes[s - S]
+            uv = rng.uniform(0, 1, (k, 2))
+            pts.append(o + uv[:, :1] * ul * ua + uv[:, 1:] * vl * va)
+            nrm.append(np.broadcast_to(nn, (k, 3)).copy())
+        sid.append(np.full(k, s))
+    pts = np.concatenate(pts)
+    nrm = np.concatenate(nrm)
+    sid = np.concatenate(sid)
+    col = _texture(scene, sid, pts)
+    return pts, nrm, col
+
+
+def _quat_mul(a, b):
+    w1, x1, y1, z1 = a.T
+    w2, x2, y2, z2 = b.T
+    return np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
+                     w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
+                     w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], 1)
+
+
+def surface_gaussians(scene: Scene, n: int, seed: int, sh_degree=0, opacity=None,
+                      logit_sigma=None, sh_sigma=0.05, thickness=0.1, size=0.6):
+    """Flat Gaussians on the scene surface (ground truth / workload scenes).
+
+    Tangential scale s_t = size * sqrt(A_total / n), normal scale
+    thickness * s_t; local z along the surface normal with a random in-plane
+    angle.  Opacity is either fixed (`opacity`) or logit ~ N(0, logit_sigma^2).
+    Draw order: surface samples (seed), then from default_rng(seed + 1): in-plane
+    angles U[0,2pi] (n,), logits (if random) (n,), higher SH N(0, sh_sigma^2).
+    """
+    pts, nrm, col = sample_surface(scene, n, seed)
+    rng = np.random.default_rng(seed + 1)
+    ang = rng.uniform(0, 2 * np.pi, n)
+    s_t = size * math.sqrt(scene.total_area / n)
+    # rotation taking +z onto the normal, composed with a spin about z
+    qa = np.stack([1.0 + nrm[:, 2], -nrm[:, 1], nrm[:, 0], np.zeros(n)], 1)
+    bad = qa[:, 0] < 1e-6                     # normal == -z: rotate pi about x
+    qa[bad] = np.array([0.0, 1.0, 0.0, 0.0])
+    qa /= np.linalg.norm(qa, axis=1, keepdims=True)
+    qs = np.stack([np.cos(ang / 2), np.zeros(n), np.zeros(n), np.sin(ang / 2)], 1)
+    q = _quat_mul(qa, qs)
+    if opacity is not None:
+        logit = np.full(n, math.log(opacity / (1.0 - opacity)))
+    else:
+        logit = rng.normal(0.0, logit_sigma if logit_sigma else 0.5, n)
+    K = sh_coeffs(sh_degree)
+    P = np.zeros((param_rows(sh_degree), n), np.float32)
+    P[0:3] = pts.T
+    P[3:5] = math.log(s_t)
+    P[5] = math.log(thickness * s_t)
+    P[6:10] = q.T
+    P[10] = logit
+    P[11:14] = ((col - 0.5) * _DC_SCALE).T
+    if K > 1:
+        P[14:] = rng.normal(0.0, sh_sigma, (n, (K - 1) * 3)).T
+    return P
+
+
+def noisy_cloud(scene: Scene, n: int, seed: int, noise=0.01):
+    """Point cloud standing in for the dense geometry prior: surface samples plus
+    isotropic N(0, noise^2) jitter.  Returns points (n,3) float32, colours (n,3).
+
+    Draw order: surface samples (seed), then jitter from default_rng(seed + 7).
+    """
+    pts, _, col = sample_surface(scene, n, seed)
+    rng = np.random.default_rng(seed + 7)
+    pts = pts + rng.normal(0.0, noise, pts.shape)
+    return pts.astype(np.float32), col.astype(np.float32)
