@@ -1,0 +1,229 @@
+"""Benchmark: training iterations/s of the splatting operator on one MI355X.
+
+Workload (mobile-budget training loop): 300k Gaussians seeded by PCA seeding
+from a 300k-point noisy cloud of the synthetic spheres-and-planes scene,
+1920x1440 ring cameras, targets rendered from a 500k-Gaussian ground truth,
+loss 0.8 L1 + 0.2 (1 - SSIM), Adam, FP32.  One step = project -> bin/sort ->
+composite with replay trace -> loss -> replay backward -> projection
+backward -> Adam, on one training camera (cycling a seeded shuffle).
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "fwd+bwd iters/s, 300k Gaussians @1920x1440; PSNR@500 it learned vs plain init"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--backward", choices=["cached", "recompute"], default="cached")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other backward variant")
+    ap.add_argument("--gaussians", type=int, default=300_000)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1440)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_times(trainer, steps, order, cams, targets):
+    """Per-stage average ms from HIP events recorded on the compute stream."""
+    import torch
+    acc = {}
+    for k in range(steps):
+        trainer.events = []
+        cid = order[k % len(order)]
+        trainer.step(cams[cid], targets[cid])
+        torch.cuda.synchronize()
+        evs = trainer.events
+        for (a, ea), (b, eb) in zip(evs[:-1], evs[1:]):
+            acc.setdefault(b, []).append(ea.elapsed_time(eb))
+    trainer.events = None
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def run_variant(wl, cached, steps, warmup, order):
+    import torch
+    from paper_2601_17354_amd.train import Trainer
+    tr = Trainer(wl["params0"].clone(), 0, wl["width"], wl["height"], cached=cached, lam=0.2,
+                 extent=4.5, k_max=64)
+    targets = wl["targets"]
+    # size buffers on every training view (synchronises), then warm up
+    for cid in order:
+        tr.prepare(wl["cams"][cid])
+    tr.rast.reserve(2.0, 2)
+    for k in range(warmup):
+        cid = order[k % len(order)]
+        tr.step(wl["cams"][cid], targets[cid])
+    torch.cuda.synchronize()
+    tr.rast.flags.zero_()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for k in range(steps):
+        cid = order[(warmup + k) % len(order)]
+        tr.step(wl["cams"][cid], targets[cid])
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / steps
+    flags = tr.rast.read_flags()
+    if flags:
+        raise RuntimeError(f"buffer overflow during the timed region (flags={flags})")
+    per = kernel_times(tr, min(20, steps), order, wl["cams"], targets)
+    # work counts of the last view for the algorithmic bytes
+    r = tr.rast
+    P = int(r.num_pairs.item())
+    E = int(r.trace["count"].sum().item()) if cached else 0
+    visible = int((r.radius > 0).sum().item())
+    stats = dict(pairs=P, entries=E, visible=visible, pixels=r.W * r.H, n=tr.n,
+                 trace_gb=r.trace_bytes() / 1e9, k_max=r.k_max, capacity=r.capacity,
+                 loss=float(tr.loss.item()))
+    return dict(ms=ms, wall_s=wall, kernels=per, stats=stats, trainer=tr)
+
+
+def render_bwd_bytes(st, cached):
+    """Algorithmic HBM bytes of one render_bwd launch: trace entries 20 B
+    (cached) + per pixel 28 B + per (tile, Gaussian) pair 40 B gather and
+    36 B atomic payload."""
+    b = 28 * st["pixels"] + (40 + 36) * st["pairs"]
+    if cached:
+        b += 20 * st["entries"]
+    return b
+
+
+def render_fwd_bytes(st, cached):
+    b = 20 * st["pixels"] + 40 * st["pairs"]
+    if cached:
+        b += 28 * st["entries"]
+    return b
+
+
+def cpu_baseline(width, height, n):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same
+    workload shape: full projection and binning of n scene Gaussians, then
+    compositing forward + backward on 12 sampled tiles, the projection VJP of
+    all visible Gaussians; scaled to one full iteration."""
+    import torch
+    torch.set_num_threads(1)
+    import synth
+    from oracle import binning, projection, render
+    scene = synth.spheres_planes_scene(0)
+    P = synth.surface_gaussians(scene, n, seed=3000, sh_degree=0, logit_sigma=0.5)
+    cam = synth.ring_cameras(60, width, height)[1]
+    t0 = time.perf_counter()
+    proj = projection.project(P, cam)
+    t1 = time.perf_counter()
+    bins = binning.bin_and_sort(proj)
+    t2 = time.perf_counter()
+    TX, TY = proj["tiles"]
+    lens = bins["ranges"][:, 1] - bins["ranges"][:, 0]
+    busy = np.nonzero(lens > 0)[0]
+    rng = np.random.default_rng(0)
+    sample = rng.choice(busy, size=min(12, busy.size), replace=False)
+    fwd = render.render_forward(proj, bins, cam, tiles=sample)
+    dl = rng.normal(size=(3, height, width))
+    g2d, _ = render.render_backward(proj, bins, fwd, dl, "cached")
+    t3 = time.perf_counter()
+    projection.project_vjp(P, cam, g2d, proj["visible"])
+    t4 = time.perf_counter()
+    # scale the sampled tiles by their share of all pairs
+    share = lens[sample].sum() / max(1, lens.sum())
+    per_iter = (t1 - t0) + (t2 - t1) + (t3 - t2) / max(share, 1e-9) + (t4 - t3)
+    return dict(value=1.0 / per_iter, unit="iters/s", cores=1, kind="oracle",
+                sample=(f"FP64 oracle, 1 thread, {n} scene Gaussians at {width}x{height}: full "
+                        f"projection ({t1 - t0:.1f} s), binning+sort of {bins['num_pairs']} pairs "
+                        f"({t2 - t1:.1f} s), compositing fwd+bwd on {len(sample)} tiles holding "
+                        f"{share * 100:.2f}% of the pairs ({t3 - t2:.1f} s, scaled to all tiles), "
+                        f"projection VJP ({t4 - t3:.1f} s); measured {t4 - t0:.1f} s"))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(3)
+    from paper_2601_17354_amd.workloads import training_workload
+    torch.manual_seed(0)
+    rng = np.random.default_rng(0)
+    t = time.perf_counter()
+    n_cams = 60
+    train_ids = [i for i in range(n_cams) if i % 8 != 0]
+    order = list(rng.permutation(train_ids))
+    wl = training_workload(n_train=args.gaussians, width=args.width, height=args.height,
+                           target_cams=train_ids)
+    log(f"workload ready in {time.perf_counter() - t:.1f} s")
+    cached = args.backward == "cached"
+    res = run_variant(wl, cached, args.steps, args.warmup, order)
+    log(f"{args.backward}: {res['ms']:.3f} ms/step, kernels {res['kernels']}, stats {res['stats']}")
+    other = None
+    if not args.no_compare:
+        del res["trainer"]
+        torch.cuda.empty_cache()
+        other = run_variant(wl, not cached, max(10, args.steps // 4), args.warmup, order)
+        log(f"other: {other['ms']:.3f} ms/step, kernels {other['kernels']}")
+        del other["trainer"]
+    kern = res["kernels"]
+    st = res["stats"]
+    dom = max(("render_fwd", "render_bwd"), key=lambda k: kern.get(k, 0.0))
+    nbytes = render_bwd_bytes(st, cached) if dom == "render_bwd" else render_fwd_bytes(st, cached)
+    achieved = nbytes / (kern[dom] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / res["ms"],
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mobile-budget training step: 300k PCA-seeded Gaussians, 1920x1440 "
+                               "ring camera, 0.8 L1 + 0.2 D-SSIM, Adam, SH degree 0",
+                   "gaussians": st["n"], "resolution": f"{args.width}x{args.height}", "tile": "16x16",
+                   "backward": args.backward, "step_includes": "project, bin_sort, render_fwd, loss, "
+                   "render_bwd, project_bwd, adam"},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": nbytes, "avg_ms": kern[dom]},
+        "kernels_ms": kern,
+        "work": st,
+    }
+    if other is not None:
+        out["other_backward"] = {"backward": "recompute" if cached else "cached",
+                                 "ms_per_step": other["ms"], "iters_per_s": 1000.0 / other["ms"],
+                                 "kernels_ms": other["kernels"], "trace_gb": other["stats"]["trace_gb"]}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(args.width, args.height, args.gaussians)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,291 @@
+/*
+ * pocketgs.h - C ABI of the gfx950 differentiable Gaussian-splatting library.
+ *
+ * Implements the hot path of the training operator T of PocketGS (arXiv
+ * 2601.17354, Sec. "Hardware-Aligned Differentiable Splatting Optimization"):
+ * projection of 3D Gaussians to 2D conics, tile binning with a (tile, depth)
+ * key sort, front-to-back compositing that records the forward replay trace
+ * S = {id, C_in, alpha} with per-pixel counters, the backward of the
+ * compositing recursion that replays S, and the index-mapped scatter of
+ * gradients to the canonical parameter buffer.  Support calls (losses, Adam,
+ * KNN/PCA seeding of Sec. "Prior-Conditioned Gaussian Parameterization") use
+ * the same conventions.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every pointer argument named *_dev is DEVICE memory (hipMalloc or any
+ *    allocator returning device pointers, e.g. PyTorch's caching allocator).
+ *    Pointers named *_host are host memory read during the call.  The caller
+ *    owns all memory; the library never allocates, frees or synchronises
+ *    inside these calls, so they are safe to enqueue under stream capture.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Calls only enqueue work and return; results are ready when the stream is.
+ *  - Return value: PGS_OK, or PGS_ERR_INVALID_ARG (bad size, unsupported
+ *    option or null pointer; nothing was enqueued) or PGS_ERR_HIP (a launch
+ *    failed; pgs_last_error() describes it).  Capacity overflow is detected on
+ *    the device and reported through a flags word (PGS_FLAG_*): outputs are
+ *    then incomplete and the caller must grow the buffer and run again.
+ *  - Canonical parameter buffer (float32, row-major [F][n], one row per
+ *    scalar field, F = 11 + 3 (D+1)^2 for SH degree D <= 3):
+ *      rows 0..2 mean, 3..5 log-scale, 6..9 quaternion (w, x, y, z, need not
+ *      be unit), 10 opacity logit, 11 + 3k + ch SH coefficient k of channel ch
+ *      (k = l*l + l + m, real orthonormal basis with the Condon-Shortley
+ *      phase).  Gradients and Adam moments use the same layout.  The
+ *      canonical order is never permuted (index-mapping subsection).
+ *  - Images are float32 planar [3][H][W]; pixel (x, y) has centre
+ *    (x + 1/2, y + 1/2).  Tiles are TW x TH pixels, TX = ceil(W/TW),
+ *    TY = ceil(H/TH), tile index ty*TX + tx.
+ */
+#ifndef POCKETGS_H
+#define POCKETGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pgs_status {
+    PGS_OK = 0,
+    PGS_ERR_INVALID_ARG = 1,
+    PGS_ERR_HIP = 2,
+} pgs_status;
+
+/* Bits of the device flags word. */
+#define PGS_FLAG_PAIR_OVERFLOW 1u  /* more (tile, Gaussian) pairs than capacity */
+#define PGS_FLAG_CACHE_OVERFLOW 2u /* a pixel has more than k_max trace entries */
+
+/* Projected-Gaussian fields, rows of a float32 [PGS_PROJ_FIELDS][n] buffer. */
+#define PGS_PROJ_U 0       /* pixel-space mean x */
+#define PGS_PROJ_V 1       /* pixel-space mean y */
+#define PGS_PROJ_DEPTH 2   /* camera-space z, the depth of the sort key */
+#define PGS_PROJ_A 3       /* conic [[A, B], [B, C]] = inverse 2D covariance */
+#define PGS_PROJ_B 4
+#define PGS_PROJ_C 5
+#define PGS_PROJ_OPACITY 6 /* sigmoid(logit) */
+#define PGS_PROJ_R 7       /* view-dependent colour */
+#define PGS_PROJ_G 8
+#define PGS_PROJ_BLUE 9
+#define PGS_PROJ_FIELDS 10
+
+/* Rows of the float32 [PGS_GRAD2D_FIELDS][n] 2D-gradient buffer. */
+#define PGS_GRAD2D_FIELDS 9 /* dL/d(u, v, A, B, C, opacity, r, g, b) */
+
+typedef struct pgs_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float viewmat[12]; /* world -> camera, row-major 3x4 [R | t], OpenCV axes */
+} pgs_camera;
+
+/* Forward replay trace S (replay-cache subsection).  Entry slot e of pixel p
+ * of tile t is stored at index ((t * k_max) + e) * (TW*TH) + p, p = the
+ * pixel's row-major index inside its tile, in four planes:
+ *   id     uint32  index of the splat in the sorted pair list (the sorted
+ *                  identifier; values[id] is its canonical index)
+ *   alpha  float32 the clamped opacity the splat had at the pixel
+ *   c_in   float32 [3][slots]: colour of everything behind the splat
+ * plus count[H*W] (row-major pixels), the number of valid entries per pixel.
+ * slots = n_tiles * k_max * TW * TH.  Only entries below count are ever
+ * written or read, so the planes need no clearing between iterations. */
+typedef struct pgs_replay {
+    uint32_t* id_dev;
+    float* alpha_dev;
+    float* c_in_dev;
+    uint32_t* count_dev;
+    int32_t k_max;
+} pgs_replay;
+
+/* Library version string (static storage). */
+const char* pgs_version(void);
+
+/* Description of the last PGS_ERR_* returned on the calling thread
+ * (thread-local static storage, valid until the next failing call). */
+const char* pgs_last_error(void);
+
+/*
+ * pgs_project - EWA projection of one view (inherited by PocketGS from 3D
+ * Gaussian Splatting; the compositing subsection consumes its "depth-sorted
+ * visible Gaussians").
+ *   params_dev   [F][n] canonical parameters, F = 11 + 3 (sh_degree+1)^2
+ *   cam_host     camera; near plane 0.2, dilation 0.3, J clamp 1.3 x half-FOV
+ *   tile_w/h     tile shape used for the rectangle
+ *   proj_dev     out [PGS_PROJ_FIELDS][n]
+ *   radius_dev   out [n] int32 ceil(3 sqrt(lambda_max)), 0 if culled
+ *   rect_dev     out [2][n] uint32 inclusive tile rectangle, packed
+ *                (x0 | y0 << 16) then (x1 | y1 << 16); 0 if culled
+ *   touched_dev  out [n] uint32 number of tiles in the rectangle, 0 if culled
+ * Every per-Gaussian quantity is computed in float64 and rounded once to
+ * float32.  n may be 0.  Errors: n < 0, sh_degree outside 0..3, non-positive
+ * image or tile size, more than 65535 tiles along an axis.
+ */
+pgs_status pgs_project(const float* params_dev, int32_t n, int32_t sh_degree,
+                       const pgs_camera* cam_host, int32_t tile_w, int32_t tile_h,
+                       float* proj_dev, int32_t* radius_dev, uint32_t* rect_dev,
+                       uint32_t* touched_dev, void* stream);
+
+/* Workspace bytes pgs_bin_sort needs for n Gaussians and `capacity` pairs. */
+size_t pgs_bin_sort_workspace(int32_t n, uint32_t capacity);
+
+/*
+ * pgs_bin_sort - tile binning and the sort that yields the permutation pi of
+ * the index-mapping subsection.  Emits one pair per (Gaussian, tile of its
+ * rectangle), key = (view_tile_offset + tile) << 32 | bits(float32 depth),
+ * value = canonical index, in canonical order with each rectangle row-major;
+ * stable-sorts them by key with a device LSD radix sort over the significant
+ * key bits only; writes per-tile [start, end) ranges ([0, 0) when empty).
+ *   touched_dev, rect_dev, proj_dev   outputs of pgs_project
+ *   tiles_x                           TX of the view
+ *   n_tiles                           number of tiles to range (>= offset + TX*TY)
+ *   view_tile_offset                  first global tile index of this view
+ *   keys_dev/values_dev   out [capacity] sorted pairs
+ *   ranges_dev            out [2][n_tiles]: start row then end row
+ *   num_pairs_dev         out, one uint32: total pairs (may exceed capacity)
+ *   flags_dev             in/out uint32 flags word; PGS_FLAG_PAIR_OVERFLOW is
+ *                         OR-ed in when pairs > capacity (then only the first
+ *                         `capacity` pairs are emitted and sorted)
+ *   workspace_dev         >= pgs_bin_sort_workspace(n, capacity) bytes
+ * The pair count never travels to the host.
+ */
+pgs_status pgs_bin_sort(int32_t n, const float* proj_dev, const uint32_t* rect_dev,
+                        const uint32_t* touched_dev, int32_t tiles_x, int32_t n_tiles,
+                        int32_t view_tile_offset, uint32_t capacity,
+                        uint64_t* keys_dev, uint32_t* values_dev, uint32_t* ranges_dev,
+                        uint32_t* num_pairs_dev, uint32_t* flags_dev,
+                        void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes pgs_sort_pairs needs for `capacity` pairs. */
+size_t pgs_sort_workspace(uint32_t capacity);
+
+/*
+ * pgs_sort_pairs - the stable LSD radix sort used by pgs_bin_sort, exposed on
+ * its own: sorts keys_dev[0..count) (count read from count_dev, clamped to
+ * capacity) ascending by their low `key_bits` bits (1..64; higher bits must
+ * be zero), carrying values_dev along; equal keys keep their input order.
+ * Sorted in place (the workspace holds the ping-pong copy).
+ */
+pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, const uint32_t* count_dev,
+                          uint32_t capacity, int32_t key_bits, void* workspace_dev,
+                          size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_render_fwd - per-tile front-to-back compositing (compositing subsection,
+ * equation C_out = C_in (1 - alpha) + alpha c, unrolled front to back):
+ * per pixel and splat of its tile's sorted list, alpha = min(0.99, o e^power),
+ * power = -1/2 d^T Q d; splats with power > 0 or alpha < 1/255 are skipped;
+ * the pixel stops before a splat that would take T below 1e-4.
+ *   width/height, tile_w/tile_h       image and tile shape (16x16 supported)
+ *   proj_dev, values_dev, ranges_dev  from pgs_project / pgs_bin_sort
+ *   bg_host                           3 floats, background colour
+ *   image_dev    out [3][H][W]
+ *   t_final_dev  out [H][W] transmittance after the last contributor
+ *   n_contrib_dev out [H][W] one plus the list position (within the tile's
+ *                range) of the last contributor, 0 if none
+ *   cache        NULL: no trace (recompute-T backward).  Otherwise the trace
+ *                S = {id, C_in, alpha} and count(u) are written (replay-cache
+ *                subsection); a pixel with more than k_max entries OR-s
+ *                PGS_FLAG_CACHE_OVERFLOW into flags_dev.
+ */
+pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
+                          const float* proj_dev, int32_t n, const uint32_t* values_dev,
+                          const uint32_t* ranges_dev, int32_t view_tile_offset,
+                          const float* bg_host, float* image_dev, float* t_final_dev,
+                          uint32_t* n_contrib_dev, const pgs_replay* cache,
+                          uint32_t* flags_dev, void* stream);
+
+/*
+ * pgs_render_bwd - backward of the compositing recursion (equation
+ * "backward_chain": dL/dC_in = dL/dC_out (1 - alpha), dL/dc = alpha dL/dC_out,
+ * dL/dalpha = <dL/dC_out, c - C_in>), chained through alpha to the 2D
+ * parameters and scattered to canonical index values[id] (index-mapping
+ * equation).
+ *   cache != NULL  replays the trace front to back over k < count(u)
+ *                  (the paper's backward);
+ *   cache == NULL  recomputes alpha and T back to front from t_final and
+ *                  n_contrib (the recompute-based backward of 3DGS).
+ *   dl_dimage_dev  [3][H][W]
+ *   grad2d_dev     [PGS_GRAD2D_FIELDS][n], ACCUMULATED (+=) with float atomics;
+ *                  the caller zeroes it.
+ */
+pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
+                          const float* proj_dev, int32_t n, const uint32_t* values_dev,
+                          const uint32_t* ranges_dev, int32_t view_tile_offset,
+                          const float* bg_host, const float* t_final_dev,
+                          const uint32_t* n_contrib_dev, const pgs_replay* cache,
+                          const float* dl_dimage_dev, float* grad2d_dev, void* stream);
+
+/*
+ * pgs_project_bwd - chain the 2D gradients of one view back to the canonical
+ * parameters (exact derivative of pgs_project with culling and clamps frozen:
+ * no gradient through a clamped colour channel or a clamped J entry).
+ *   grad2d_dev  [PGS_GRAD2D_FIELDS][n] from pgs_render_bwd
+ *   radius_dev  from pgs_project (culled Gaussians get no gradient)
+ *   grads_dev   [F][n] ACCUMULATED (+=); one thread per Gaussian, no atomics,
+ *               so views must be enqueued one after another on one stream.
+ */
+pgs_status pgs_project_bwd(const float* params_dev, int32_t n, int32_t sh_degree,
+                           const pgs_camera* cam_host, const int32_t* radius_dev,
+                           const float* grad2d_dev, float* grads_dev, void* stream);
+
+/*
+ * pgs_loss_l1_dssim - photometric loss (the paper does not state it; the 3D
+ * Gaussian Splatting form): L = (1 - lambda) mean|x - y| + lambda (1 - SSIM),
+ * SSIM with an 11x11 Gaussian window (sigma 1.5), C1 = 1e-4, C2 = 9e-4, zero
+ * padding, mean over pixels and channels.  lambda = 0 gives plain L1 and
+ * skips the SSIM kernels.
+ *   x_dev, y_dev   [3][H][W] rendered and target images
+ *   loss_dev       out, one float (overwritten)
+ *   dl_dx_dev      out [3][H][W] (overwritten)
+ *   workspace_dev  >= pgs_loss_workspace(width, height) bytes
+ */
+size_t pgs_loss_workspace(int32_t width, int32_t height);
+pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, int32_t width,
+                             int32_t height, float lambda, float* loss_dev,
+                             float* dl_dx_dev, void* workspace_dev, size_t workspace_bytes,
+                             void* stream);
+
+/*
+ * pgs_adam_step - Adam (Kingma & Ba) on the canonical layout, moments aligned
+ * with their parameters (index-mapping subsection):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr_row * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ *   params/grads/m/v  [rows][n] device; lr_host [rows] host; rows <= 64;
+ *   step >= 1.
+ */
+pgs_status pgs_adam_step(float* params_dev, const float* grads_dev, float* m_dev,
+                         float* v_dev, int32_t rows, int32_t n, const float* lr_host,
+                         int32_t step, float beta1, float beta2, float eps, void* stream);
+
+/*
+ * pgs_knn - exact k nearest neighbours (Sec. "Local Surface Statistics
+ * Estimation", K_n = 16): for every point i of points_dev [3][m] (float32),
+ * the k other points with the smallest squared distance
+ * ((dx*dx) + (dy*dy)) + (dz*dz) formed in float64, ties broken by the
+ * smaller index.  k in 1..32, m > k.
+ *   nbr_dev  out [k][m] int32 neighbour indices, nearest first
+ *   d2_dev   out [k][m] float64 squared distances
+ */
+pgs_status pgs_knn(const float* points_dev, int32_t m, int32_t k, int32_t* nbr_dev,
+                   double* d2_dev, void* stream);
+
+/*
+ * pgs_pca_seed - disc-like covariance seeding (Sec. "Disc-Like Covariance
+ * Seeding"): from the 16 neighbours, C_i = (1/16) sum (p - pbar)(p - pbar)^T,
+ * normal = eigenvector of its smallest eigenvalue, s_t = mean distance to the
+ * first 3 neighbours, s_n = r_normal s_t; writes canonical SH-degree-0
+ * parameters: mean = the point, log-scales (log s_t, log s_t, log s_n),
+ * quaternion whose local z is the normal, opacity logit(0.1), DC colour from
+ * colours_dev.
+ *   points_dev   [3][m] float32;  colours_dev [3][m] float32 in [0, 1]
+ *   nbr_dev/d2_dev  pgs_knn output with k >= 16
+ *   params_dev   out [14][m]
+ */
+pgs_status pgs_pca_seed(const float* points_dev, const float* colours_dev, int32_t m,
+                        const int32_t* nbr_dev, const double* d2_dev, int32_t k,
+                        float r_normal, float* params_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POCKETGS_H */

@@ -227,7 +227,7 @@ def render_backward(proj, bins, fwd, dL_dimage, variant="cached"):
     """Gradients of <dL_dimage, image> with respect to the 2D parameters.
 
     Returns (grad2d (9, n) float64 in GRAD_FIELDS order, indexed by canonical
-    id, and `tainted` (n,) bool: Gaussians listed in a tile that holds a
+    id, and `tainted` (n,) bool: Gaussians that could contribute at a
     marginal pixel).
     """
     n = proj["n"]
@@ -268,7 +268,16 @@ def render_backward(proj, bins, fwd, dL_dimage, variant="cached"):
         for f in range(9):
             np.add.at(grad[f], ids, sums[f])
         if tr["marg"].any():
-            # a near-threshold decision can add or drop any splat of the
-            # tile at that pixel and shifts T for all later ones
-            tainted[ids] = True
+            # A near-threshold decision at a pixel changes only that pixel's
+            # contributions: it can add or drop a splat there and shifts T
+            # and C_in for the others.  Every splat of the tile that could
+            # contribute at such a pixel under either decision is tainted.
+            for p in np.nonzero(tr["marg"])[0]:
+                dx = proj["u"][ids] - (tr["gx"][p] + 0.5)
+                dy = proj["v"][ids] - (tr["gy"][p] + 0.5)
+                power = -0.5 * (proj["A"][ids] * dx * dx + proj["C"][ids] * dy * dy) \
+                    - proj["B"][ids] * dx * dy
+                a = np.minimum(ALPHA_MAX, proj["o"][ids] * np.exp(power))
+                near = (power <= 0.0) & (a >= ALPHA_MIN * (1.0 - MARGIN_ALPHA))
+                tainted[ids[near]] = True
     return grad, tainted

@@ -1,0 +1,92 @@
+"""ctypes view of libpocketgs.so (declarations in include/pocketgs.h).
+
+Loading fails loudly when the library has not been built: there is no other
+implementation of these calls in this package.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_uint32, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpocketgs.so")
+
+PGS_OK = 0
+PGS_ERR_INVALID_ARG = 1
+PGS_ERR_HIP = 2
+PGS_FLAG_PAIR_OVERFLOW = 1
+PGS_FLAG_CACHE_OVERFLOW = 2
+PROJ_FIELDS = 10
+GRAD2D_FIELDS = 9
+
+
+class PgsCamera(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("viewmat", c_float * 12)]
+
+
+class PgsReplay(ctypes.Structure):
+    _fields_ = [("id_dev", c_void_p), ("alpha_dev", c_void_p), ("c_in_dev", c_void_p),
+                ("count_dev", c_void_p), ("k_max", c_int32)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "pgs_version": (c_char_p, []),
+    "pgs_last_error": (c_char_p, []),
+    "pgs_project": (c_int32, [c_void_p, c_int32, c_int32, POINTER(PgsCamera), c_int32, c_int32,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pgs_bin_sort_workspace": (c_size_t, [c_int32, c_uint32]),
+    "pgs_bin_sort": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                               c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_size_t, c_void_p]),
+    "pgs_sort_workspace": (c_size_t, [c_uint32]),
+    "pgs_sort_pairs": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint32, c_int32, c_void_p,
+                                 c_size_t, c_void_p]),
+    "pgs_render_fwd": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
+                                 c_void_p, c_int32, POINTER(c_float), c_void_p, c_void_p, c_void_p,
+                                 POINTER(PgsReplay), c_void_p, c_void_p]),
+    "pgs_render_bwd": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
+                                 c_void_p, c_int32, POINTER(c_float), c_void_p, c_void_p,
+                                 POINTER(PgsReplay), c_void_p, c_void_p, c_void_p]),
+    "pgs_project_bwd": (c_int32, [c_void_p, c_int32, c_int32, POINTER(PgsCamera), c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
+    "pgs_loss_workspace": (c_size_t, [c_int32, c_int32]),
+    "pgs_loss_l1_dssim": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_float, c_void_p,
+                                    c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pgs_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                POINTER(c_float), c_int32, c_float, c_float, c_float, c_void_p]),
+    "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "pgs_pca_seed": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float,
+                               c_void_p, c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load and type the library once; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2601_17354_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PgsError(RuntimeError):
+    pass
+
+
+def check(status: int, what: str) -> None:
+    if status != PGS_OK:
+        msg = load().pgs_last_error().decode(errors="replace")
+        raise PgsError(f"{what} failed with status {status}: {msg}")

@@ -1,0 +1,164 @@
+"""Thin Python binding: one function per C entry point, same names.
+
+Each function only checks tensor placement/dtype, marshals pointers and the
+current HIP stream, calls the library and raises on a non-OK status.  Every
+computation happens in the library's kernels; PyTorch supplies device memory
+and the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PgsCamera, PgsReplay, check
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def camera_struct(cam: dict) -> PgsCamera:
+    c = PgsCamera()
+    c.width = int(cam["width"])
+    c.height = int(cam["height"])
+    c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    vm = np.asarray(cam["viewmat"], np.float32).reshape(12)
+    for i in range(12):
+        c.viewmat[i] = float(vm[i])
+    return c
+
+
+def replay_struct(trace) -> PgsReplay | None:
+    if trace is None:
+        return None
+    r = PgsReplay()
+    r.id_dev = _ptr(trace["id"], torch.int32).value
+    r.alpha_dev = _ptr(trace["alpha"], torch.float32).value
+    r.c_in_dev = _ptr(trace["c_in"], torch.float32).value
+    r.count_dev = _ptr(trace["count"], torch.int32).value
+    r.k_max = int(trace["k_max"])
+    return r
+
+
+def _f3(v):
+    return (ctypes.c_float * 3)(*[float(x) for x in v])
+
+
+F32, I32, I64 = torch.float32, torch.int32, torch.int64
+
+
+def pgs_version() -> str:
+    return _lib.load().pgs_version().decode()
+
+
+def pgs_project(params, n, sh_degree, cam, tile_w, tile_h, proj, radius, rect, touched, stream=None):
+    lib = _lib.load()
+    c = camera_struct(cam)
+    check(lib.pgs_project(_ptr(params, F32), n, sh_degree, ctypes.byref(c), tile_w, tile_h,
+                          _ptr(proj, F32), _ptr(radius, I32), _ptr(rect, I32), _ptr(touched, I32),
+                          _stream(stream)), "pgs_project")
+
+
+def pgs_bin_sort_workspace(n, capacity) -> int:
+    return int(_lib.load().pgs_bin_sort_workspace(n, capacity))
+
+
+def pgs_bin_sort(n, proj, rect, touched, tiles_x, n_tiles, view_tile_offset, capacity, keys, values,
+                 ranges, num_pairs, flags, workspace, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_bin_sort(n, _ptr(proj, F32), _ptr(rect, I32), _ptr(touched, I32), tiles_x, n_tiles,
+                           view_tile_offset, capacity, _ptr(keys, I64), _ptr(values, I32),
+                           _ptr(ranges, I32), _ptr(num_pairs, I32), _ptr(flags, I32),
+                           _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)),
+          "pgs_bin_sort")
+
+
+def pgs_sort_workspace(capacity) -> int:
+    return int(_lib.load().pgs_sort_workspace(capacity))
+
+
+def pgs_sort_pairs(keys, values, count, capacity, key_bits, workspace, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_sort_pairs(_ptr(keys, I64), _ptr(values, I32), _ptr(count, I32), capacity, key_bits,
+                             _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)),
+          "pgs_sort_pairs")
+
+
+def pgs_render_fwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_tile_offset, bg,
+                   image, t_final, n_contrib, trace, flags, stream=None):
+    lib = _lib.load()
+    r = replay_struct(trace)
+    check(lib.pgs_render_fwd(width, height, tile_w, tile_h, _ptr(proj, F32), n, _ptr(values, I32),
+                             _ptr(ranges, I32), view_tile_offset, _f3(bg), _ptr(image, F32),
+                             _ptr(t_final, F32), _ptr(n_contrib, I32),
+                             ctypes.byref(r) if r is not None else None, _ptr(flags, I32),
+                             _stream(stream)), "pgs_render_fwd")
+
+
+def pgs_render_bwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_tile_offset, bg,
+                   t_final, n_contrib, trace, dl_dimage, grad2d, stream=None):
+    lib = _lib.load()
+    r = replay_struct(trace)
+    check(lib.pgs_render_bwd(width, height, tile_w, tile_h, _ptr(proj, F32), n, _ptr(values, I32),
+                             _ptr(ranges, I32), view_tile_offset, _f3(bg), _ptr(t_final, F32),
+                             _ptr(n_contrib, I32), ctypes.byref(r) if r is not None else None,
+                             _ptr(dl_dimage, F32), _ptr(grad2d, F32), _stream(stream)),
+          "pgs_render_bwd")
+
+
+def pgs_project_bwd(params, n, sh_degree, cam, radius, grad2d, grads, stream=None):
+    lib = _lib.load()
+    c = camera_struct(cam)
+    check(lib.pgs_project_bwd(_ptr(params, F32), n, sh_degree, ctypes.byref(c), _ptr(radius, I32),
+                              _ptr(grad2d, F32), _ptr(grads, F32), _stream(stream)), "pgs_project_bwd")
+
+
+def pgs_loss_workspace(width, height) -> int:
+    return int(_lib.load().pgs_loss_workspace(width, height))
+
+
+def pgs_loss_l1_dssim(x, y, width, height, lam, loss, dl_dx, workspace, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_loss_l1_dssim(_ptr(x, F32), _ptr(y, F32), width, height, float(lam), _ptr(loss, F32),
+                                _ptr(dl_dx, F32), _ptr(workspace, torch.uint8), workspace.numel(),
+                                _stream(stream)), "pgs_loss_l1_dssim")
+
+
+def pgs_adam_step(params, grads, m, v, rows, n, lr, step, beta1, beta2, eps, stream=None):
+    lib = _lib.load()
+    lr_arr = (ctypes.c_float * rows)(*[float(x) for x in lr])
+    check(lib.pgs_adam_step(_ptr(params, F32), _ptr(grads, F32), _ptr(m, F32), _ptr(v, F32), rows, n,
+                            lr_arr, int(step), float(beta1), float(beta2), float(eps), _stream(stream)),
+          "pgs_adam_step")
+
+
+def pgs_knn(points, m, k, nbr, d2, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_knn(_ptr(points, F32), m, k, _ptr(nbr, I32), _ptr(d2, torch.float64), _stream(stream)),
+          "pgs_knn")
+
+
+def pgs_pca_seed(points, colours, m, nbr, d2, k, r_normal, params, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_pca_seed(_ptr(points, F32), _ptr(colours, F32), m, _ptr(nbr, I32),
+                           _ptr(d2, torch.float64), k, float(r_normal), _ptr(params, F32),
+                           _stream(stream)), "pgs_pca_seed")

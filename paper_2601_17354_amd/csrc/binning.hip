@@ -1,0 +1,368 @@
+// Tile binning and the (tile, depth) key sort that yields the permutation pi
+// of PocketGS's index-mapping subsection.
+//
+//   scan     exclusive prefix sum of tiles_touched -> pair offsets + count
+//   emit     one (key, canonical id) pair per Gaussian x rectangle tile,
+//            key = tile << 32 | bits(float32 depth)
+//   sort     stable LSD radix sort, 8-bit digits, only the significant key
+//            bits (32 + ceil(log2 n_tiles)); every pass is histogram ->
+//            device scan of the digit-major histogram -> stable scatter
+//   ranges   per-tile [start, end)
+//
+// Every kernel reads the pair count from device memory and is launched on a
+// grid sized for the capacity, so nothing travels to the host and the whole
+// sequence can be captured in a HIP graph.
+#include "common.hpp"
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanIpt = 8;
+constexpr int kScanItems = kScanThreads * kScanIpt;  // 2048 per block
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;                       // 256 keys per round
+constexpr int kSortItems = kSortThreads * kSortRounds; // 4096 keys per block
+constexpr int kRadix = 256;
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// Block-wide exclusive scan of one value per thread (Hillis-Steele in LDS).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s, uint32_t& total) {
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        uint32_t add = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    total = s[kScanThreads - 1];
+    const uint32_t incl = s[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                              uint32_t n, uint32_t* __restrict__ partial) {
+    __shared__ uint32_t s[kScanThreads];
+    const uint32_t base = blockIdx.x * kScanItems + threadIdx.x * kScanIpt;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k)
+        if (base + k < n) sum += in[base + k];
+    uint32_t total;
+    block_exclusive_scan(sum, s, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Exclusive scan of the per-block partial sums by one block; writes the
+// grand total to *total_out (if not null).
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partial,
+                                                                uint32_t nb, uint32_t* __restrict__ total_out) {
+    __shared__ uint32_t s[kScanThreads];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += kScanItems) {
+        const uint32_t b0 = base + threadIdx.x * kScanIpt;
+        uint32_t loc[kScanIpt];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanIpt; ++k) {
+            loc[k] = (b0 + k < nb) ? partial[b0 + k] : 0u;
+            sum += loc[k];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan(sum, s, total);
+#pragma unroll
+        for (int k = 0; k < kScanIpt; ++k) {
+            if (b0 + k < nb) partial[b0 + k] = run;
+            run += loc[k];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __restrict__ in, uint32_t n,
+                                                             const uint32_t* __restrict__ partial,
+                                                             uint32_t* __restrict__ out) {
+    __shared__ uint32_t s[kScanThreads];
+    const uint32_t base = blockIdx.x * kScanItems + threadIdx.x * kScanIpt;
+    uint32_t loc[kScanIpt];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        loc[k] = (base + k < n) ? in[base + k] : 0u;
+        sum += loc[k];
+    }
+    uint32_t total;
+    uint32_t run = partial[blockIdx.x] + block_exclusive_scan(sum, s, total);
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += loc[k];
+    }
+}
+
+size_t scan_workspace(uint32_t n) { return align_up((size_t)div_up(n, kScanItems) * 4); }
+
+// Exclusive scan in -> out (may alias), total to total_out (device, may be null).
+pgs_status scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total_out,
+                    uint32_t* partial, hipStream_t s) {
+    const uint32_t nb = div_up(n, kScanItems);
+    if (nb == 0) return PGS_OK;
+    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, partial);
+    k_scan_partials<<<1, kScanThreads, 0, s>>>(partial, nb, total_out);
+    k_scan_apply<<<nb, kScanThreads, 0, s>>>(in, n, partial, out);
+    PGS_CHECK_LAUNCH("scan");
+    return PGS_OK;
+}
+
+__global__ __launch_bounds__(256) void k_emit(int n, const float* __restrict__ depth,
+                                              const uint32_t* __restrict__ rect,
+                                              const uint32_t* __restrict__ touched,
+                                              const uint32_t* __restrict__ offsets,
+                                              const uint32_t* __restrict__ num_pairs, int TX,
+                                              int tile_offset, uint32_t capacity,
+                                              uint64_t* __restrict__ keys,
+                                              uint32_t* __restrict__ values,
+                                              uint32_t* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && *num_pairs > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
+    if (i >= n) return;
+    const uint32_t cnt = touched[i];
+    if (cnt == 0) return;
+    uint32_t idx = offsets[i];
+    const uint32_t r0 = rect[i], r1 = rect[(size_t)n + i];
+    const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff, y1 = r1 >> 16;
+    const uint64_t dbits = (uint64_t)__float_as_uint(depth[i]);
+    for (uint32_t ty = y0; ty <= y1; ++ty)
+        for (uint32_t tx = x0; tx <= x1; ++tx, ++idx) {
+            if (idx >= capacity) return;
+            const uint64_t tile = (uint64_t)(tile_offset + ty * (uint32_t)TX + tx);
+            keys[idx] = (tile << 32) | dbits;
+            values[idx] = (uint32_t)i;
+        }
+}
+
+__device__ __forceinline__ uint32_t clamp_count(const uint32_t* num, uint32_t capacity) {
+    const uint32_t c = *num;
+    return c < capacity ? c : capacity;
+}
+
+// Digit histogram of each block's 4096-key chunk, stored digit-major
+// hist[d * nb + block] so that one exclusive scan yields every block's
+// output offset for every digit.
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ num,
+                                                             uint32_t capacity, int shift, uint32_t nb,
+                                                             uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kRadix];
+    const uint32_t count = clamp_count(num, capacity);
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortItems;
+    if (base < count) {
+        for (int r = 0; r < kSortRounds; ++r) {
+            const uint32_t idx = base + r * kSortThreads + threadIdx.x;
+            if (idx < count) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 0xffu], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter.  Each round handles 256 consecutive keys; a key's rank is
+// (keys of its digit already placed by this block) + (same digit in lower
+// waves of this round) + (same digit in lower lanes of its wave), the last
+// found by matching the 8 digit bits with wave ballots.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ num,
+    uint32_t capacity, int shift, uint32_t nb, const uint32_t* __restrict__ offs) {
+    constexpr int NW = kSortThreads / 64;
+    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_wcnt[NW][kRadix];
+    const uint32_t count = clamp_count(num, capacity);
+    const uint32_t base = blockIdx.x * kSortItems;
+    if (base >= count) return;  // uniform for the block
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    s_base[t] = offs[(size_t)t * nb + blockIdx.x];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kSortRounds; ++r) {
+        for (int w = 0; w < NW; ++w) s_wcnt[w][t] = 0;
+        __syncthreads();
+        const uint32_t idx = base + r * kSortThreads + t;
+        const bool valid = idx < count;
+        uint64_t key = 0;
+        uint32_t val = 0, digit = 0;
+        if (valid) {
+            key = kin[idx];
+            val = vin[idx];
+            digit = (uint32_t)(key >> shift) & 0xffu;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (digit >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) s_wcnt[wv][digit] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = s_base[digit] + rank;
+            for (int w = 0; w < wv; ++w) pos += s_wcnt[w][digit];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < NW; ++w) add += s_wcnt[w][t];
+        s_base[t] += add;
+        __syncthreads();  // counts read; the next round may clear them
+    }
+}
+
+__global__ void k_copy_pairs(const uint64_t* __restrict__ ks, const uint32_t* __restrict__ vs,
+                             uint64_t* __restrict__ kd, uint32_t* __restrict__ vd,
+                             const uint32_t* __restrict__ num, uint32_t capacity) {
+    const uint32_t count = clamp_count(num, capacity);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+__global__ void k_clear_u32(uint32_t* __restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ num,
+                         uint32_t capacity, uint32_t n_tiles, uint32_t* __restrict__ ranges) {
+    const uint32_t count = clamp_count(num, capacity);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const uint32_t tile = (uint32_t)(keys[i] >> 32);
+        if (tile >= n_tiles) continue;
+        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[tile] = i;
+        if (i + 1 == count || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[n_tiles + tile] = i + 1;
+    }
+}
+
+struct SortWs {
+    uint64_t* keys_alt;
+    uint32_t* vals_alt;
+    uint32_t* hist;
+    uint32_t* partial;
+    uint32_t nb;
+    size_t bytes;
+};
+
+SortWs sort_layout(void* base, uint32_t capacity) {
+    SortWs w{};
+    const uint32_t nb = div_up(capacity, kSortItems);
+    size_t off = 0;
+    char* p = static_cast<char*>(base);
+    w.keys_alt = reinterpret_cast<uint64_t*>(p + off); off += align_up((size_t)capacity * 8);
+    w.vals_alt = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)capacity * 4);
+    w.hist = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)nb * kRadix * 4);
+    w.partial = reinterpret_cast<uint32_t*>(p + off); off += scan_workspace(nb * kRadix);
+    w.nb = nb;
+    w.bytes = off;
+    return w;
+}
+
+pgs_status radix_sort(uint64_t* keys, uint32_t* vals, const uint32_t* num, uint32_t capacity,
+                      int key_bits, const SortWs& w, hipStream_t s) {
+    if (capacity == 0) return PGS_OK;
+    const int passes = (key_bits + 7) / 8;
+    uint64_t* kin = keys; uint32_t* vin = vals;
+    uint64_t* kout = w.keys_alt; uint32_t* vout = w.vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        k_radix_hist<<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
+        pgs_status st = scan_u32(w.hist, w.hist, w.nb * kRadix, nullptr, w.partial, s);
+        if (st != PGS_OK) return st;
+        k_radix_scatter<<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity, shift,
+                                                      w.nb, w.hist);
+        PGS_CHECK_LAUNCH("radix pass");
+        uint64_t* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+    }
+    if (kin != keys) {
+        k_copy_pairs<<<1024, 256, 0, s>>>(kin, vin, keys, vals, num, capacity);
+        PGS_CHECK_LAUNCH("radix copy");
+    }
+    return PGS_OK;
+}
+
+int bits_for(uint32_t v) {  // number of bits needed for values < v
+    int b = 0;
+    while (b < 32 && ((uint64_t)1 << b) < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+extern "C" size_t pgs_sort_workspace(uint32_t capacity) { return sort_layout(nullptr, capacity).bytes; }
+
+extern "C" pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, const uint32_t* count_dev,
+                                     uint32_t capacity, int32_t key_bits, void* workspace_dev,
+                                     size_t workspace_bytes, void* stream) {
+    PGS_REQUIRE(key_bits >= 1 && key_bits <= 64, "pgs_sort_pairs: key_bits %d", key_bits);
+    if (capacity == 0) return PGS_OK;
+    PGS_REQUIRE(keys_dev && values_dev && count_dev && workspace_dev, "pgs_sort_pairs: null pointer");
+    SortWs w = sort_layout(workspace_dev, capacity);
+    PGS_REQUIRE(workspace_bytes >= w.bytes, "pgs_sort_pairs: workspace %zu < %zu", workspace_bytes, w.bytes);
+    return radix_sort(keys_dev, values_dev, count_dev, capacity, key_bits, w, pgs::as_stream(stream));
+}
+
+extern "C" size_t pgs_bin_sort_workspace(int32_t n, uint32_t capacity) {
+    const uint32_t nn = n > 0 ? (uint32_t)n : 0u;
+    return align_up((size_t)nn * 4) + scan_workspace(nn) + sort_layout(nullptr, capacity).bytes;
+}
+
+extern "C" pgs_status pgs_bin_sort(int32_t n, const float* proj_dev, const uint32_t* rect_dev,
+                                   const uint32_t* touched_dev, int32_t tiles_x, int32_t n_tiles,
+                                   int32_t view_tile_offset, uint32_t capacity, uint64_t* keys_dev,
+                                   uint32_t* values_dev, uint32_t* ranges_dev, uint32_t* num_pairs_dev,
+                                   uint32_t* flags_dev, void* workspace_dev, size_t workspace_bytes,
+                                   void* stream) {
+    PGS_REQUIRE(n >= 0 && tiles_x > 0 && n_tiles > 0 && view_tile_offset >= 0 &&
+                    view_tile_offset < n_tiles, "pgs_bin_sort: bad sizes");
+    PGS_REQUIRE(ranges_dev && num_pairs_dev && flags_dev, "pgs_bin_sort: null pointer");
+    PGS_REQUIRE(n == 0 || (proj_dev && rect_dev && touched_dev), "pgs_bin_sort: null pointer");
+    PGS_REQUIRE(capacity == 0 || (keys_dev && values_dev), "pgs_bin_sort: null pointer");
+    const size_t need = pgs_bin_sort_workspace(n, capacity);
+    PGS_REQUIRE(workspace_dev && workspace_bytes >= need, "pgs_bin_sort: workspace %zu < %zu",
+                workspace_bytes, need);
+    hipStream_t s = pgs::as_stream(stream);
+    char* p = static_cast<char*>(workspace_dev);
+    uint32_t* offsets = reinterpret_cast<uint32_t*>(p);
+    p += align_up((size_t)n * 4);
+    uint32_t* partial = reinterpret_cast<uint32_t*>(p);
+    p += scan_workspace((uint32_t)n);
+    SortWs w = sort_layout(p, capacity);
+
+    k_clear_u32<<<256, 256, 0, s>>>(ranges_dev, 2u * (uint32_t)n_tiles);
+    k_clear_u32<<<1, 64, 0, s>>>(num_pairs_dev, 1u);
+    PGS_CHECK_LAUNCH("pgs_bin_sort clear");
+    if (n == 0) return PGS_OK;
+    pgs_status st = scan_u32(touched_dev, offsets, (uint32_t)n, num_pairs_dev, partial, s);
+    if (st != PGS_OK) return st;
+    k_emit<<<(n + 255) / 256, 256, 0, s>>>(n, proj_dev + (size_t)PGS_PROJ_DEPTH * n, rect_dev,
+                                            touched_dev, offsets, num_pairs_dev, tiles_x,
+                                            view_tile_offset, capacity, keys_dev, values_dev, flags_dev);
+    PGS_CHECK_LAUNCH("pgs_bin_sort emit");
+    if (capacity == 0) return PGS_OK;
+    const int key_bits = 32 + bits_for((uint32_t)n_tiles);
+    st = radix_sort(keys_dev, values_dev, num_pairs_dev, capacity, key_bits, w, s);
+    if (st != PGS_OK) return st;
+    const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
+    k_ranges<<<grid, 256, 0, s>>>(keys_dev, num_pairs_dev, capacity, (uint32_t)n_tiles, ranges_dev);
+    PGS_CHECK_LAUNCH("pgs_bin_sort ranges");
+    return PGS_OK;
+}

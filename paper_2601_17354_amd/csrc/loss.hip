@@ -1,0 +1,217 @@
+// Photometric loss L = (1 - lambda) L1 + lambda (1 - SSIM) and dL/dx.
+//
+// The paper does not state its loss; this is the 3D Gaussian Splatting form.
+// SSIM (Wang et al. 2004): 11x11 Gaussian window (sigma 1.5), C1 = 1e-4,
+// C2 = 9e-4, zero padding, mean over pixels and channels.
+//
+// Forward kernel, per 16x16 output tile and channel: x and y with a 5-pixel
+// halo go to LDS, a horizontal then a vertical pass of the separable window
+// give mu_x, mu_y, E[x^2], E[y^2], E[xy]; the kernel writes the SSIM map's
+// partial derivatives m1 = dS/dmu_x, m2 = dS/dE[x^2], m3 = dS/dE[xy] and adds
+// the tile's SSIM and |x - y| sums to two accumulators.  Backward kernel: the
+// same windowed pass over (m1, m2, m3) gives
+//     dSSIM/dx_p = (1/N) (w*m1 + 2 x_p w*m2 + y_p w*m3)(p),
+// the adjoint of the zero-padded blur being the zero-padded blur.
+#include <math.h>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kT = 16, kHalo = 5, kS = kT + 2 * kHalo;  // 26
+constexpr float kC1 = 1e-4f, kC2 = 9e-4f;
+
+struct Win {
+    float w[11];
+};
+
+inline Win gaussian_window() {
+    Win win;
+    double g[11], s = 0;
+    for (int i = 0; i < 11; ++i) {
+        const double d = i - 5;
+        g[i] = exp(-d * d / (2.0 * 1.5 * 1.5));
+        s += g[i];
+    }
+    for (int i = 0; i < 11; ++i) win.w[i] = (float)(g[i] / s);
+    return win;
+}
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+    // wave sums to lane 63, then the 4 wave totals
+    const float w = wave_sum_to_lane63(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) red[wv] = w;
+    __syncthreads();
+    float tot = 0.f;
+    if (threadIdx.x == 0) tot = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return tot;
+}
+
+__global__ void k_zero(float* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const float* __restrict__ y,
+                                            size_t N, float scale, float* __restrict__ dl,
+                                            float* __restrict__ acc) {
+    __shared__ float red[4];
+    float s = 0.f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const float d = x[i] - y[i];
+        s += fabsf(d);
+        dl[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+    }
+    const float tot = block_sum(s, red);
+    if (threadIdx.x == 0) unsafeAtomicAdd(&acc[0], tot);
+}
+
+__global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y,
+                                                  int W, int H, Win win, float* __restrict__ m,
+                                                  float* __restrict__ acc) {
+    __shared__ float sx[kS][kS + 1];
+    __shared__ float sy[kS][kS + 1];
+    __shared__ float hb[5][kS][kT + 1];
+    __shared__ float red[4];
+    const int ch = blockIdx.z, ox = blockIdx.x * kT, oy = blockIdx.y * kT, t = threadIdx.x;
+    const size_t plane = (size_t)W * H;
+    const float* xc = x + ch * plane;
+    const float* yc = y + ch * plane;
+    for (int idx = t; idx < kS * kS; idx += 256) {
+        const int r = idx / kS, c = idx % kS;
+        const int gx = ox + c - kHalo, gy = oy + r - kHalo;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        sx[r][c] = in ? xc[(size_t)gy * W + gx] : 0.f;
+        sy[r][c] = in ? yc[(size_t)gy * W + gx] : 0.f;
+    }
+    __syncthreads();
+    for (int idx = t; idx < kS * kT; idx += 256) {
+        const int r = idx / kT, c = idx % kT;
+        float a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) {
+            const float w = win.w[k], xv = sx[r][c + k], yv = sy[r][c + k];
+            a0 += w * xv;
+            a1 += w * yv;
+            a2 += w * xv * xv;
+            a3 += w * yv * yv;
+            a4 += w * xv * yv;
+        }
+        hb[0][r][c] = a0; hb[1][r][c] = a1; hb[2][r][c] = a2; hb[3][r][c] = a3; hb[4][r][c] = a4;
+    }
+    __syncthreads();
+    const int lx = t % kT, ly = t / kT, gx = ox + lx, gy = oy + ly;
+    float q[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+#pragma unroll
+        for (int f = 0; f < 5; ++f) q[f] += win.w[k] * hb[f][ly + k][lx];
+    float S = 0.f;
+    if (gx < W && gy < H) {
+        const float mx = q[0], my = q[1];
+        const float vx = q[2] - mx * mx, vy = q[3] - my * my, cxy = q[4] - mx * my;
+        const float N1 = 2.f * mx * my + kC1, N2 = 2.f * cxy + kC2;
+        const float D1 = mx * mx + my * my + kC1, D2 = vx + vy + kC2;
+        const float inv = 1.f / (D1 * D2);
+        S = N1 * N2 * inv;
+        const float m1 = (2.f * my * N2 - 2.f * my * N1) * inv - S * (2.f * mx / D1 - 2.f * mx / D2);
+        const float m2 = -S / D2;
+        const float m3 = 2.f * N1 * inv;
+        const size_t pix = (size_t)gy * W + gx;
+        m[(size_t)(3 * ch + 0) * plane + pix] = m1;
+        m[(size_t)(3 * ch + 1) * plane + pix] = m2;
+        m[(size_t)(3 * ch + 2) * plane + pix] = m3;
+    }
+    const float tot = block_sum(S, red);
+    if (t == 0) unsafeAtomicAdd(&acc[1], tot);
+}
+
+__global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y,
+                                                  int W, int H, Win win, const float* __restrict__ m,
+                                                  float l1_scale, float ssim_scale,
+                                                  float* __restrict__ dl, float* __restrict__ acc) {
+    __shared__ float sm[3][kS][kS + 1];
+    __shared__ float hb[3][kS][kT + 1];
+    __shared__ float red[4];
+    const int ch = blockIdx.z, ox = blockIdx.x * kT, oy = blockIdx.y * kT, t = threadIdx.x;
+    const size_t plane = (size_t)W * H;
+    for (int idx = t; idx < kS * kS; idx += 256) {
+        const int r = idx / kS, c = idx % kS;
+        const int gx = ox + c - kHalo, gy = oy + r - kHalo;
+        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const size_t pix = (size_t)gy * W + gx;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) sm[f][r][c] = in ? m[(size_t)(3 * ch + f) * plane + pix] : 0.f;
+    }
+    __syncthreads();
+    for (int idx = t; idx < kS * kT; idx += 256) {
+        const int r = idx / kT, c = idx % kT;
+        float a[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 11; ++k)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) a[f] += win.w[k] * sm[f][r][c + k];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) hb[f][r][c] = a[f];
+    }
+    __syncthreads();
+    const int lx = t % kT, ly = t / kT, gx = ox + lx, gy = oy + ly;
+    float b[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) b[f] += win.w[k] * hb[f][ly + k][lx];
+    float l1 = 0.f;
+    if (gx < W && gy < H) {
+        const size_t i = ch * plane + (size_t)gy * W + gx;
+        const float xv = x[i], yv = y[i], d = xv - yv;
+        l1 = fabsf(d);
+        const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        dl[i] = l1_scale * sgn - ssim_scale * (b[0] + 2.f * xv * b[1] + yv * b[2]);
+    }
+    const float tot = block_sum(l1, red);
+    if (t == 0) unsafeAtomicAdd(&acc[0], tot);
+}
+
+__global__ void k_loss_final(const float* __restrict__ acc, float lambda, float invN, float* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        const float l1 = acc[0] * invN;
+        out[0] = lambda > 0.f ? (1.f - lambda) * l1 + lambda * (1.f - acc[1] * invN) : l1;
+    }
+}
+
+}  // namespace
+
+extern "C" size_t pgs_loss_workspace(int32_t width, int32_t height) {
+    if (width <= 0 || height <= 0) return 256;
+    return 256 + (size_t)9 * width * height * sizeof(float);
+}
+
+extern "C" pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, int32_t width,
+                                        int32_t height, float lambda, float* loss_dev, float* dl_dx_dev,
+                                        void* workspace_dev, size_t workspace_bytes, void* stream) {
+    PGS_REQUIRE(width > 0 && height > 0, "pgs_loss_l1_dssim: bad size");
+    PGS_REQUIRE(lambda >= 0.f && lambda <= 1.f, "pgs_loss_l1_dssim: lambda %g", (double)lambda);
+    PGS_REQUIRE(x_dev && y_dev && loss_dev && dl_dx_dev && workspace_dev, "pgs_loss_l1_dssim: null pointer");
+    const size_t need = lambda > 0.f ? pgs_loss_workspace(width, height) : 256;
+    PGS_REQUIRE(workspace_bytes >= need, "pgs_loss_l1_dssim: workspace %zu < %zu", workspace_bytes, need);
+    hipStream_t s = pgs::as_stream(stream);
+    float* acc = static_cast<float*>(workspace_dev);
+    float* m = reinterpret_cast<float*>(static_cast<char*>(workspace_dev) + 256);
+    const size_t N = (size_t)3 * width * height;
+    const float invN = (float)(1.0 / (double)N);
+    k_zero<<<1, 64, 0, s>>>(acc, 2);
+    if (lambda == 0.f) {
+        k_l1<<<1024, 256, 0, s>>>(x_dev, y_dev, N, invN, dl_dx_dev, acc);
+    } else {
+        const Win win = gaussian_window();
+        const dim3 grid((width + kT - 1) / kT, (height + kT - 1) / kT, 3);
+        k_ssim_fwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, acc);
+        k_ssim_bwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, (1.f - lambda) * invN,
+                                        lambda * invN, dl_dx_dev, acc);
+    }
+    k_loss_final<<<1, 64, 0, s>>>(acc, lambda, invN, loss_dev);
+    PGS_CHECK_LAUNCH("pgs_loss_l1_dssim");
+    return PGS_OK;
+}

@@ -1,0 +1,136 @@
+"""Per-view rasterizer: owns the device buffers and sequences the C ABI calls.
+
+forward:  pgs_project -> pgs_bin_sort -> pgs_render_fwd (optionally recording
+          the replay trace S = {id, C_in, alpha} and count(u))
+backward: pgs_render_bwd (trace replay, or recompute-T) -> pgs_project_bwd
+
+Buffers are allocated with PyTorch once and reused; the pair capacity and the
+trace depth k_max grow when the device flags report an overflow (the caller
+runs `forward_checked`, which synchronises once to read the flags).
+"""
+
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import binding as B
+from ._lib import GRAD2D_FIELDS, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_FIELDS
+
+
+def param_rows(sh_degree: int) -> int:
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+class Rasterizer:
+    def __init__(self, n: int, sh_degree: int, width: int, height: int, tile=(16, 16),
+                 cached: bool = True, k_max: int = 64, capacity: int | None = None,
+                 device="cuda"):
+        self.n = int(n)
+        self.sh_degree = int(sh_degree)
+        self.W, self.H = int(width), int(height)
+        self.tw, self.th = tile
+        self.TX = (self.W + self.tw - 1) // self.tw
+        self.TY = (self.H + self.th - 1) // self.th
+        self.n_tiles = self.TX * self.TY
+        self.cached = cached
+        self.device = torch.device(device)
+        d = self.device
+        n = max(self.n, 1)
+        self.proj = torch.empty((PROJ_FIELDS, n), dtype=torch.float32, device=d)
+        self.radius = torch.empty(n, dtype=torch.int32, device=d)
+        self.rect = torch.empty((2, n), dtype=torch.int32, device=d)
+        self.touched = torch.empty(n, dtype=torch.int32, device=d)
+        self.ranges = torch.empty((2, self.n_tiles), dtype=torch.int32, device=d)
+        self.num_pairs = torch.zeros(1, dtype=torch.int32, device=d)
+        self.flags = torch.zeros(1, dtype=torch.int32, device=d)
+        self.image = torch.empty((3, self.H, self.W), dtype=torch.float32, device=d)
+        self.t_final = torch.empty((self.H, self.W), dtype=torch.float32, device=d)
+        self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
+        self.grad2d = torch.zeros((GRAD2D_FIELDS, n), dtype=torch.float32, device=d)
+        self.capacity = 0
+        self.k_max = 0
+        self.trace = None
+        self._alloc_pairs(capacity if capacity is not None else max(1024, 4 * self.n))
+        if cached:
+            self._alloc_trace(k_max)
+
+    # -- buffers ---------------------------------------------------------
+    def _alloc_pairs(self, capacity: int):
+        capacity = int(capacity)
+        d = self.device
+        self.capacity = capacity
+        self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=d)
+        self.values = torch.empty(max(capacity, 1), dtype=torch.int32, device=d)
+        ws = B.pgs_bin_sort_workspace(self.n, capacity)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=d)
+
+    def _alloc_trace(self, k_max: int):
+        self.k_max = int(k_max)
+        slots = self.n_tiles * self.k_max * self.tw * self.th
+        d = self.device
+        self.trace = dict(
+            id=torch.empty(slots, dtype=torch.int32, device=d),
+            alpha=torch.empty(slots, dtype=torch.float32, device=d),
+            c_in=torch.empty(3 * slots, dtype=torch.float32, device=d),
+            count=torch.empty(self.H * self.W, dtype=torch.int32, device=d),
+            k_max=self.k_max,
+        )
+
+    def reserve(self, pair_factor: float = 2.0, k_factor: int = 2):
+        """Enlarge the pair capacity and trace depth ahead of training, whose
+        Gaussians grow and so touch more tiles and pixels over time."""
+        self._alloc_pairs(int(self.capacity * pair_factor))
+        if self.cached:
+            self._alloc_trace(self.k_max * k_factor)
+
+    def trace_bytes(self) -> int:
+        if self.trace is None:
+            return 0
+        return sum(v.numel() * v.element_size() for k, v in self.trace.items() if k != "k_max")
+
+    # -- passes ----------------------------------------------------------
+    def forward(self, params: torch.Tensor, cam: dict, bg=(0.0, 0.0, 0.0)):
+        """Enqueue projection, binning/sort and compositing for one view."""
+        n = self.n
+        B.pgs_project(params, n, self.sh_degree, cam, self.tw, self.th, self.proj, self.radius,
+                      self.rect, self.touched)
+        B.pgs_bin_sort(n, self.proj, self.rect, self.touched, self.TX, self.n_tiles, 0,
+                       self.capacity, self.keys, self.values, self.ranges, self.num_pairs,
+                       self.flags, self.workspace)
+        B.pgs_render_fwd(self.W, self.H, self.tw, self.th, self.proj, n, self.values, self.ranges,
+                         0, bg, self.image, self.t_final, self.n_contrib,
+                         self.trace if self.cached else None, self.flags)
+        return self.image
+
+    def read_flags(self) -> int:
+        return int(self.flags.item())
+
+    def forward_checked(self, params, cam, bg=(0.0, 0.0, 0.0), max_retries=8, headroom=1.25):
+        """forward(), then grow the pair capacity / trace depth and rerun while
+        the device reports an overflow.  Synchronises once per attempt."""
+        for _ in range(max_retries + 1):
+            self.flags.zero_()
+            self.forward(params, cam, bg)
+            f = self.read_flags()
+            if f == 0:
+                return self.image
+            if f & PGS_FLAG_PAIR_OVERFLOW:
+                need = int(self.num_pairs.item())
+                self._alloc_pairs(int(math.ceil(need * headroom)) + 1024)
+            if f & PGS_FLAG_CACHE_OVERFLOW:
+                # counts are clamped at k_max, so the true depth is unknown
+                self._alloc_trace(self.k_max * 4)
+        raise RuntimeError("rasterizer buffers kept overflowing")
+
+    def backward(self, params, cam, dl_dimage, grads, bg=(0.0, 0.0, 0.0), zero_grad2d=True):
+        """Enqueue the compositing backward and the projection backward;
+        `grads` ([F][n]) is accumulated into."""
+        if zero_grad2d:
+            self.grad2d.zero_()
+        B.pgs_render_bwd(self.W, self.H, self.tw, self.th, self.proj, self.n, self.values,
+                         self.ranges, 0, bg, self.t_final, self.n_contrib,
+                         self.trace if self.cached else None, dl_dimage, self.grad2d)
+        B.pgs_project_bwd(params, self.n, self.sh_degree, cam, self.radius, self.grad2d, grads)
+        return grads

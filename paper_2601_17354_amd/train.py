@@ -1,0 +1,111 @@
+"""Training step of the operator T and PCA seeding of I, through the C ABI.
+
+One step (PocketGS Sec. "Hardware-Aligned Differentiable Splatting
+Optimization"): project -> bin/sort -> composite (recording the replay trace)
+-> loss -> replay backward -> projection backward (index-mapped into the
+canonical gradient buffer) -> Adam on the canonical layout.  Every stage is a
+libpocketgs kernel; PyTorch holds the buffers and provides the stream.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .raster import Rasterizer, param_rows
+
+BETA1, BETA2, EPS = 0.9, 0.999, 1e-15
+R_NORMAL = 0.1
+
+
+def learning_rates(sh_degree: int, extent: float = 1.0) -> np.ndarray:
+    """Per-row Adam learning rates (3D Gaussian Splatting defaults; PocketGS
+    names Adam but gives no rates): mean 1.6e-4 * extent, log-scale 5e-3,
+    rotation 1e-3, opacity 2.5e-2, SH DC 2.5e-3, higher SH 2.5e-3 / 20."""
+    F = param_rows(sh_degree)
+    lr = np.zeros(F, np.float32)
+    lr[0:3] = 1.6e-4 * extent
+    lr[3:6] = 5e-3
+    lr[6:10] = 1e-3
+    lr[10] = 2.5e-2
+    lr[11:14] = 2.5e-3
+    lr[14:] = 2.5e-3 / 20.0
+    return lr
+
+
+def seed_pca(points: torch.Tensor, colours: torch.Tensor, r_normal: float = R_NORMAL) -> torch.Tensor:
+    """Disc-like seeding from a point cloud: points/colours are [3][m] float32
+    device tensors; returns canonical SH-degree-0 parameters [14][m]."""
+    m = points.shape[1]
+    k = 16
+    nbr = torch.empty((k, m), dtype=torch.int32, device=points.device)
+    d2 = torch.empty((k, m), dtype=torch.float64, device=points.device)
+    B.pgs_knn(points, m, k, nbr, d2)
+    out = torch.empty((14, m), dtype=torch.float32, device=points.device)
+    B.pgs_pca_seed(points, colours, m, nbr, d2, k, r_normal, out)
+    return out
+
+
+class Trainer:
+    """Canonical parameters, Adam moments and one rasterizer per resolution."""
+
+    def __init__(self, params: torch.Tensor, sh_degree: int, width: int, height: int,
+                 cached: bool = True, lam: float = 0.2, extent: float = 1.0, k_max: int = 64,
+                 tile=(16, 16)):
+        self.params = params.contiguous()
+        self.sh_degree = sh_degree
+        self.F, self.n = self.params.shape
+        dev = self.params.device
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.lr = learning_rates(sh_degree, extent)
+        self.lam = lam
+        self.W, self.H = width, height
+        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached, k_max=k_max)
+        self.dl = torch.empty((3, height, width), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.loss_ws = torch.empty(B.pgs_loss_workspace(width, height), dtype=torch.uint8, device=dev)
+        self.step_count = 0
+        self.events = None
+
+    def prepare(self, cam: dict, bg=(0.0, 0.0, 0.0)):
+        """Grow the pair capacity and trace depth until a forward fits
+        (synchronises; call before timing)."""
+        self.rast.forward_checked(self.params, cam, bg)
+
+    def _mark(self, name):
+        if self.events is not None:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            self.events.append((name, ev))
+
+    def step(self, cam: dict, target: torch.Tensor, bg=(0.0, 0.0, 0.0), adam: bool = True):
+        r = self.rast
+        n = self.n
+        self._mark("start")
+        B.pgs_project(self.params, n, self.sh_degree, cam, r.tw, r.th, r.proj, r.radius, r.rect, r.touched)
+        self._mark("project")
+        B.pgs_bin_sort(n, r.proj, r.rect, r.touched, r.TX, r.n_tiles, 0, r.capacity, r.keys, r.values,
+                       r.ranges, r.num_pairs, r.flags, r.workspace)
+        self._mark("bin_sort")
+        B.pgs_render_fwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.image, r.t_final,
+                         r.n_contrib, r.trace if r.cached else None, r.flags)
+        self._mark("render_fwd")
+        B.pgs_loss_l1_dssim(r.image, target, r.W, r.H, self.lam, self.loss, self.dl, self.loss_ws)
+        self._mark("loss")
+        self.grads.zero_()
+        r.grad2d.zero_()
+        self._mark("zero")
+        B.pgs_render_bwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.t_final,
+                         r.n_contrib, r.trace if r.cached else None, self.dl, r.grad2d)
+        self._mark("render_bwd")
+        B.pgs_project_bwd(self.params, n, self.sh_degree, cam, r.radius, r.grad2d, self.grads)
+        self._mark("project_bwd")
+        if adam:
+            self.step_count += 1
+            B.pgs_adam_step(self.params, self.grads, self.m, self.v, self.F, n, self.lr, self.step_count,
+                            BETA1, BETA2, EPS)
+            self._mark("adam")
+        return self.loss

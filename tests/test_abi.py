@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+the header declares, and rejects bad arguments before touching a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2601_17354_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pocketgs.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(pgs_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("pgs_project", "pgs_bin_sort", "pgs_render_fwd", "pgs_render_bwd",
+                 "pgs_project_bwd", "pgs_sort_pairs", "pgs_loss_l1_dssim", "pgs_adam_step",
+                 "pgs_knn", "pgs_pca_seed", "pgs_last_error", "pgs_version"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(_lib.SIGNATURES)
+
+
+def test_version_string():
+    assert _lib.load().pgs_version().decode().startswith("pocketgs-gfx950")
+
+
+def test_invalid_arguments_are_rejected_on_the_host():
+    lib = _lib.load()
+    cam = _lib.PgsCamera()
+    cam.width, cam.height, cam.fx, cam.fy = 64, 48, 50.0, 50.0
+    st = lib.pgs_project(None, -1, 0, ctypes.byref(cam), 16, 16, None, None, None, None, None)
+    assert st == _lib.PGS_ERR_INVALID_ARG
+    assert b"n < 0" in lib.pgs_last_error()
+    st = lib.pgs_project(None, 10, 4, ctypes.byref(cam), 16, 16, None, None, None, None, None)
+    assert st == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_knn(None, 100, 5, None, None, None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_sort_pairs(None, None, None, 10, 70, None, 0, None) == _lib.PGS_ERR_INVALID_ARG
+    lr = (ctypes.c_float * 1)(0.1)
+    assert lib.pgs_adam_step(None, None, None, None, 65, 10, lr, 1, 0.9, 0.999, 1e-15, None) == \
+        _lib.PGS_ERR_INVALID_ARG
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    st = lib.pgs_render_fwd(64, 48, 8, 8, None, 0, None, None, 0, bg, None, None, None, None, None, None)
+    assert st == _lib.PGS_ERR_INVALID_ARG and b"unsupported tile" in lib.pgs_last_error()
+
+
+def test_workspace_queries_grow_with_size():
+    lib = _lib.load()
+    assert lib.pgs_bin_sort_workspace(1000, 1 << 20) > lib.pgs_bin_sort_workspace(1000, 1 << 10)
+    assert lib.pgs_sort_workspace(1 << 20) >= 12 * (1 << 20)
+    assert lib.pgs_loss_workspace(1920, 1440) >= 9 * 4 * 1920 * 1440
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    saved = _lib._lib
+    try:
+        _lib._lib = None
+        with pytest.raises(ImportError):
+            _lib.load(str(tmp_path / "nope.so"))
+    finally:
+        _lib._lib = saved
