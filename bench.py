@@ -63,12 +63,12 @@ def run_variant(wl, cached, steps, warmup, order):
     import torch
     from paper_2601_17354_amd.train import Trainer
     tr = Trainer(wl["params0"].clone(), 0, wl["width"], wl["height"], cached=cached, lam=0.2,
-                 extent=4.5, k_max=64)
+                 extent=4.5)
     targets = wl["targets"]
     # size buffers on every training view (synchronises), then warm up
     for cid in order:
         tr.prepare(wl["cams"][cid])
-    tr.rast.reserve(2.0, 2)
+    tr.rast.reserve(2.0)
     for k in range(warmup):
         cid = order[k % len(order)]
         tr.step(wl["cams"][cid], targets[cid])
@@ -95,7 +95,7 @@ def run_variant(wl, cached, steps, warmup, order):
     E = int(r.trace["count"].sum().item()) if cached else 0
     visible = int((r.radius > 0).sum().item())
     stats = dict(pairs=P, entries=E, visible=visible, pixels=r.W * r.H, n=tr.n,
-                 trace_gb=r.trace_bytes() / 1e9, k_max=r.k_max, capacity=r.capacity,
+                 trace_gb=r.trace_bytes() / 1e9, capacity=r.capacity,
                  loss=float(tr.loss.item()))
     return dict(ms=ms, wall_s=wall, kernels=per, stats=stats, trainer=tr)
 
@@ -120,7 +120,7 @@ def render_fwd_bytes(st, cached):
 def cpu_baseline(width, height, n):
     """The FP64 oracle, single-threaded, on a bounded sample of the same
     workload shape: full projection and binning of n scene Gaussians, then
-    compositing forward + backward on 12 sampled tiles, the projection VJP of
+    compositing forward + backward on 600 sampled tiles, the projection VJP of
     all visible Gaussians; scaled to one full iteration."""
     import torch
     torch.set_num_threads(1)
@@ -138,7 +138,7 @@ def cpu_baseline(width, height, n):
     lens = bins["ranges"][:, 1] - bins["ranges"][:, 0]
     busy = np.nonzero(lens > 0)[0]
     rng = np.random.default_rng(0)
-    sample = rng.choice(busy, size=min(12, busy.size), replace=False)
+    sample = rng.choice(busy, size=min(600, busy.size), replace=False)
     fwd = render.render_forward(proj, bins, cam, tiles=sample)
     dl = rng.normal(size=(3, height, width))
     g2d, _ = render.render_backward(proj, bins, fwd, dl, "cached")

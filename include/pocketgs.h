@@ -54,7 +54,7 @@ typedef enum pgs_status {
 
 /* Bits of the device flags word. */
 #define PGS_FLAG_PAIR_OVERFLOW 1u  /* more (tile, Gaussian) pairs than capacity */
-#define PGS_FLAG_CACHE_OVERFLOW 2u /* a pixel has more than k_max trace entries */
+#define PGS_FLAG_CACHE_OVERFLOW 2u /* a tile's pairs exceed the trace's pair capacity */
 
 /* Projected-Gaussian fields, rows of a float32 [PGS_PROJ_FIELDS][n] buffer. */
 #define PGS_PROJ_U 0       /* pixel-space mean x */
@@ -78,23 +78,38 @@ typedef struct pgs_camera {
     float viewmat[12]; /* world -> camera, row-major 3x4 [R | t], OpenCV axes */
 } pgs_camera;
 
-/* Forward replay trace S (replay-cache subsection).  Entry slot e of pixel p
- * of tile t is stored at index ((t * k_max) + e) * (TW*TH) + p, p = the
- * pixel's row-major index inside its tile, in four planes:
- *   id     uint32  index of the splat in the sorted pair list (the sorted
- *                  identifier; values[id] is its canonical index)
- *   alpha  float32 the clamped opacity the splat had at the pixel
- *   c_in   float32 [3][slots]: colour of everything behind the splat
- * plus count[H*W] (row-major pixels), the number of valid entries per pixel.
- * slots = n_tiles * k_max * TW * TH.  Only entries below count are ever
- * written or read, so the planes need no clearing between iterations. */
+/* Forward replay trace S = {id, C_in, alpha} (replay-cache subsection),
+ * stored per wave of 64 pixels (lanes = row-major pixels of the tile, wave w
+ * holds pixels 64w .. 64w+63) as groups, one group per sorted splat id:
+ *   mask_dev   [pair_capacity][TW*TH/64] uint64: bit l of mask[id][w] is set
+ *              when pixel (lane l of wave w) recorded an entry for splat id
+ *              (id = index in the sorted pair list; values[id] is the
+ *              canonical index, the permutation pi of the index map)
+ *   steps_dev  [n_tiles][TW*TH/64] uint32: per wave, the number of list
+ *              positions (from the tile's start) whose masks are valid; the
+ *              per-iteration counter that replaces a cache clear
+ *   alpha_dev  [entry_capacity] float32 clamped alpha of each entry
+ *   c_in_dev   [3][entry_capacity] float32 colour of everything behind the
+ *              splat at that pixel (plane stride entry_capacity)
+ *   count_dev  [H*W] uint32 entries per pixel, count(u)
+ * Entries of wave w of the tile whose pairs are [start, end) live at
+ * TW*TH*start + 64*(end-start)*w + cursor, where cursor counts the wave's
+ * entries of earlier groups and a group's entries follow in lane order.  So
+ * entry_capacity >= TW*TH * pair_capacity (pgs_trace_entries) bounds every
+ * iteration and the trace never overflows; only tiles whose pairs exceed
+ * pair_capacity go unrecorded (flagged PGS_FLAG_CACHE_OVERFLOW). */
 typedef struct pgs_replay {
-    uint32_t* id_dev;
+    uint64_t* mask_dev;
+    uint32_t* steps_dev;
     float* alpha_dev;
     float* c_in_dev;
     uint32_t* count_dev;
-    int32_t k_max;
+    uint64_t entry_capacity;
+    uint32_t pair_capacity;
 } pgs_replay;
+
+/* Entry capacity a trace needs for `pair_capacity` pairs and the tile shape. */
+size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int32_t tile_h);
 
 /* Library version string (static storage). */
 const char* pgs_version(void);
@@ -182,9 +197,9 @@ pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, const uint32
  *   n_contrib_dev out [H][W] one plus the list position (within the tile's
  *                range) of the last contributor, 0 if none
  *   cache        NULL: no trace (recompute-T backward).  Otherwise the trace
- *                S = {id, C_in, alpha} and count(u) are written (replay-cache
- *                subsection); a pixel with more than k_max entries OR-s
- *                PGS_FLAG_CACHE_OVERFLOW into flags_dev.
+ *                S = {id, C_in, alpha}, the per-wave step counters and
+ *                count(u) are written (replay-cache subsection; layout at
+ *                pgs_replay); flags_dev must then be given.
  */
 pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
                           const float* proj_dev, int32_t n, const uint32_t* values_dev,
@@ -199,8 +214,8 @@ pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile_w, int32_t
  * dL/dalpha = <dL/dC_out, c - C_in>), chained through alpha to the 2D
  * parameters and scattered to canonical index values[id] (index-mapping
  * equation).
- *   cache != NULL  replays the trace front to back over k < count(u)
- *                  (the paper's backward);
+ *   cache != NULL  replays the trace front to back over each pixel's entries
+ *                  (the paper's backward), visiting only recorded groups;
  *   cache == NULL  recomputes alpha and T back to front from t_final and
  *                  n_contrib (the recompute-based backward of 3DGS).
  *   dl_dimage_dev  [3][H][W]

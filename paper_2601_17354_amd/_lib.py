@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_uint32, c_void_p
+from ctypes import POINTER, c_char_p, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpocketgs.so")
@@ -28,8 +28,9 @@ class PgsCamera(ctypes.Structure):
 
 
 class PgsReplay(ctypes.Structure):
-    _fields_ = [("id_dev", c_void_p), ("alpha_dev", c_void_p), ("c_in_dev", c_void_p),
-                ("count_dev", c_void_p), ("k_max", c_int32)]
+    _fields_ = [("mask_dev", c_void_p), ("steps_dev", c_void_p), ("alpha_dev", c_void_p),
+                ("c_in_dev", c_void_p), ("count_dev", c_void_p), ("entry_capacity", c_uint64),
+                ("pair_capacity", c_uint32)]
 
 
 # name -> (restype, argtypes)
@@ -45,6 +46,7 @@ SIGNATURES = {
     "pgs_sort_workspace": (c_size_t, [c_uint32]),
     "pgs_sort_pairs": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint32, c_int32, c_void_p,
                                  c_size_t, c_void_p]),
+    "pgs_trace_entries": (c_size_t, [c_uint32, c_int32, c_int32]),
     "pgs_render_fwd": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                  c_void_p, c_int32, POINTER(c_float), c_void_p, c_void_p, c_void_p,
                                  POINTER(PgsReplay), c_void_p, c_void_p]),

@@ -51,12 +51,18 @@ def replay_struct(trace) -> PgsReplay | None:
     if trace is None:
         return None
     r = PgsReplay()
-    r.id_dev = _ptr(trace["id"], torch.int32).value
+    r.mask_dev = _ptr(trace["mask"], torch.int64).value
+    r.steps_dev = _ptr(trace["steps"], torch.int32).value
     r.alpha_dev = _ptr(trace["alpha"], torch.float32).value
     r.c_in_dev = _ptr(trace["c_in"], torch.float32).value
     r.count_dev = _ptr(trace["count"], torch.int32).value
-    r.k_max = int(trace["k_max"])
+    r.entry_capacity = int(trace["entry_capacity"])
+    r.pair_capacity = int(trace["pair_capacity"])
     return r
+
+
+def pgs_trace_entries(pair_capacity, tile_w, tile_h) -> int:
+    return int(_lib.load().pgs_trace_entries(pair_capacity, tile_w, tile_h))
 
 
 def _f3(v):

@@ -8,7 +8,7 @@
 // halo go to LDS, a horizontal then a vertical pass of the separable window
 // give mu_x, mu_y, E[x^2], E[y^2], E[xy]; the kernel writes the SSIM map's
 // partial derivatives m1 = dS/dmu_x, m2 = dS/dE[x^2], m3 = dS/dE[xy] and adds
-// the tile's SSIM and |x - y| sums to two accumulators.  Backward kernel: the
+// the tile's SSIM sum as a per-block partial.  Backward kernel: the
 // same windowed pass over (m1, m2, m3) gives
 //     dSSIM/dx_p = (1/N) (w*m1 + 2 x_p w*m2 + y_p w*m3)(p),
 // the adjoint of the zero-padded blur being the zero-padded blur.
@@ -49,13 +49,9 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
     return tot;
 }
 
-__global__ void k_zero(float* p, int n) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.f;
-}
-
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const float* __restrict__ y,
                                             size_t N, float scale, float* __restrict__ dl,
-                                            float* __restrict__ acc) {
+                                            float* __restrict__ part) {
     __shared__ float red[4];
     float s = 0.f;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
@@ -64,12 +60,12 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
         dl[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
     }
     const float tot = block_sum(s, red);
-    if (threadIdx.x == 0) unsafeAtomicAdd(&acc[0], tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y,
                                                   int W, int H, Win win, float* __restrict__ m,
-                                                  float* __restrict__ acc) {
+                                                  float* __restrict__ part) {
     __shared__ float sx[kS][kS + 1];
     __shared__ float sy[kS][kS + 1];
     __shared__ float hb[5][kS][kT + 1];
@@ -124,13 +120,13 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, c
         m[(size_t)(3 * ch + 2) * plane + pix] = m3;
     }
     const float tot = block_sum(S, red);
-    if (t == 0) unsafeAtomicAdd(&acc[1], tot);
+    if (t == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y,
                                                   int W, int H, Win win, const float* __restrict__ m,
                                                   float l1_scale, float ssim_scale,
-                                                  float* __restrict__ dl, float* __restrict__ acc) {
+                                                  float* __restrict__ dl, float* __restrict__ part) {
     __shared__ float sm[3][kS][kS + 1];
     __shared__ float hb[3][kS][kT + 1];
     __shared__ float red[4];
@@ -171,21 +167,36 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
         dl[i] = l1_scale * sgn - ssim_scale * (b[0] + 2.f * xv * b[1] + yv * b[2]);
     }
     const float tot = block_sum(l1, red);
-    if (t == 0) unsafeAtomicAdd(&acc[0], tot);
+    if (t == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-__global__ void k_loss_final(const float* __restrict__ acc, float lambda, float invN, float* __restrict__ out) {
-    if (threadIdx.x == 0) {
-        const float l1 = acc[0] * invN;
-        out[0] = lambda > 0.f ? (1.f - lambda) * l1 + lambda * (1.f - acc[1] * invN) : l1;
-    }
+// Sums the per-block partials in a fixed order (deterministic, no atomics).
+__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ part_l1, int nl,
+                                                    const float* __restrict__ part_s, int ns,
+                                                    float lambda, float invN, float* __restrict__ out) {
+    __shared__ float red[4];
+    float a = 0.f, b = 0.f;
+    for (int i = threadIdx.x; i < nl; i += 256) a += part_l1[i];
+    for (int i = threadIdx.x; i < ns; i += 256) b += part_s[i];
+    const float l1 = block_sum(a, red) * invN;
+    const float ss = block_sum(b, red) * invN;
+    if (threadIdx.x == 0) out[0] = lambda > 0.f ? (1.f - lambda) * l1 + lambda * (1.f - ss) : l1;
+}
+
+constexpr int kL1Blocks = 1024;
+
+inline int ssim_blocks(int W, int H) { return ((W + kT - 1) / kT) * ((H + kT - 1) / kT) * 3; }
+
+inline size_t part_bytes(int W, int H) {
+    const int nb = ssim_blocks(W, H) > kL1Blocks ? ssim_blocks(W, H) : kL1Blocks;
+    return (((size_t)2 * nb * sizeof(float)) + 255) & ~(size_t)255;
 }
 
 }  // namespace
 
 extern "C" size_t pgs_loss_workspace(int32_t width, int32_t height) {
     if (width <= 0 || height <= 0) return 256;
-    return 256 + (size_t)9 * width * height * sizeof(float);
+    return part_bytes(width, height) + (size_t)9 * width * height * sizeof(float);
 }
 
 extern "C" pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, int32_t width,
@@ -194,24 +205,27 @@ extern "C" pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, 
     PGS_REQUIRE(width > 0 && height > 0, "pgs_loss_l1_dssim: bad size");
     PGS_REQUIRE(lambda >= 0.f && lambda <= 1.f, "pgs_loss_l1_dssim: lambda %g", (double)lambda);
     PGS_REQUIRE(x_dev && y_dev && loss_dev && dl_dx_dev && workspace_dev, "pgs_loss_l1_dssim: null pointer");
-    const size_t need = lambda > 0.f ? pgs_loss_workspace(width, height) : 256;
+    const size_t need = lambda > 0.f ? pgs_loss_workspace(width, height) : part_bytes(width, height);
     PGS_REQUIRE(workspace_bytes >= need, "pgs_loss_l1_dssim: workspace %zu < %zu", workspace_bytes, need);
     hipStream_t s = pgs::as_stream(stream);
-    float* acc = static_cast<float*>(workspace_dev);
-    float* m = reinterpret_cast<float*>(static_cast<char*>(workspace_dev) + 256);
+    const int npart = (int)(part_bytes(width, height) / (2 * sizeof(float)));
+    float* part_l1 = static_cast<float*>(workspace_dev);
+    float* part_s = part_l1 + npart;
+    float* m = reinterpret_cast<float*>(static_cast<char*>(workspace_dev) + part_bytes(width, height));
     const size_t N = (size_t)3 * width * height;
     const float invN = (float)(1.0 / (double)N);
-    k_zero<<<1, 64, 0, s>>>(acc, 2);
+    int nl = kL1Blocks, ns = 0;
     if (lambda == 0.f) {
-        k_l1<<<1024, 256, 0, s>>>(x_dev, y_dev, N, invN, dl_dx_dev, acc);
+        k_l1<<<kL1Blocks, 256, 0, s>>>(x_dev, y_dev, N, invN, dl_dx_dev, part_l1);
     } else {
         const Win win = gaussian_window();
         const dim3 grid((width + kT - 1) / kT, (height + kT - 1) / kT, 3);
-        k_ssim_fwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, acc);
+        nl = ns = ssim_blocks(width, height);
+        k_ssim_fwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, part_s);
         k_ssim_bwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, (1.f - lambda) * invN,
-                                        lambda * invN, dl_dx_dev, acc);
+                                        lambda * invN, dl_dx_dev, part_l1);
     }
-    k_loss_final<<<1, 64, 0, s>>>(acc, lambda, invN, loss_dev);
+    k_loss_final<<<1, 256, 0, s>>>(part_l1, nl, part_s, ns, lambda, invN, loss_dev);
     PGS_CHECK_LAUNCH("pgs_loss_l1_dssim");
     return PGS_OK;
 }

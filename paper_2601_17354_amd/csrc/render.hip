@@ -3,29 +3,40 @@
 // Forward (PocketGS Sec. "Explicit Computation Graph", "Bandwidth-Efficient
 // Forward Replay Cache"): one workgroup per tile, one lane per pixel.  The
 // tile's sorted splat list is staged through LDS in batches (one splat per
-// lane per batch, 36 B of 2D attributes each); every lane composites the
-// batch front to back.  A barrier with a live-lane count ends the tile once
-// every pixel has terminated.  In cached mode each contributing splat appends
-// {id, alpha, c} to the pixel's trace slot count(u); after the pass the lane
-// walks its own entries back to front and overwrites c with C_in, the colour
-// behind the splat (the over-recursion C_out = C_in (1 - alpha) + alpha c run
-// from the background), so the backward reads C_in directly.
+// lane per batch, 36 B of 2D attributes each) and every wave steps through
+// the batch in lockstep, each lane compositing its pixel front to back.  A
+// barrier with a live-lane count ends the tile once every pixel terminated.
+//
+// Replay trace.  S = {id, C_in, alpha} is recorded per wave of 64 pixels as
+// groups, one per sorted splat id that at least one of the wave's pixels
+// composited: a 64-bit ballot mask of those pixels (stored at the id's slot)
+// followed by their entries, appended contiguously in lane order to the
+// wave's entry region.  The id of an entry is thus the slot of its group,
+// its pixel the lane of its mask bit, and a pixel's entries in group order
+// are its contributors front to back.  Entry regions have the exact worst
+// case size (64 entries per wave and listed splat), so nothing overflows;
+// a per-wave step counter bounds the valid groups, so masks of earlier
+// iterations are never read and nothing is cleared between iterations.
+// Entries are written as one coalesced run per group.  After the front to
+// back pass the kernel walks each wave's groups back to front with the
+// splat colours re-staged in LDS and replaces alpha-only entries by
+// (C_in, alpha): C_in is the colour of everything behind the splat, the
+// over-recursion C_out = C_in (1 - alpha) + alpha c run from the background.
 //
 // Backward (equation "backward_chain"), two variants:
-//   cached     walks each pixel's trace front to back.  The workgroup steps
-//              through the tile's list in lockstep; a lane consumes its next
-//              trace entry when the entry's id equals the current list
-//              position, so all lanes of a wave work on the same splat and
-//              the wave reduces its nine 2D gradients with DPP before LDS
-//              accumulation and one float atomic per field and tile.
-//              dL/dC_out starts at dL/dC and is multiplied by (1 - alpha)
-//              after every entry (dL/dC_in = dL/dC_out (1 - alpha)).
+//   cached     steps through each wave's groups front to back, visiting only
+//              non-empty masks; a lane with a bit set reads its entry, takes
+//              dL/dC_out (starts at dL/dC, times (1 - alpha) after each own
+//              entry), dL/dalpha = <dL/dC_out, c - C_in> and dL/dc =
+//              alpha dL/dC_out, chains them to the nine 2D parameters, and the
+//              wave reduces them with DPP (a lone lane writes directly).
 //   recompute  walks the list back to front from n_contrib, re-evaluates
 //              alpha with the forward's exact arithmetic, recovers
 //              T_k = T_{k+1} / (1 - alpha_k) from T_final and accumulates the
-//              colour behind as it goes.
-// Gradients are scattered to the canonical index values[j] (index-mapping
-// equation).
+//              colour behind as it goes (the 3D Gaussian Splatting backward).
+// Per-wave partial sums meet in LDS and leave with one float atomic per
+// field and (tile, splat), scattered to the canonical index values[id]
+// (index-mapping equation).
 #include "common.hpp"
 
 namespace {
@@ -66,13 +77,24 @@ __device__ __forceinline__ Splat load_splat(const float4* sa, const float4* sb, 
     return Splat{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, sc[k]};
 }
 
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 struct Trace {
-    uint32_t* id;
-    float* alpha;
-    float* c_in;
-    uint32_t* count;
-    int k_max;
-    size_t slots;
+    uint64_t* mask;    // [pair_cap][NW]
+    uint32_t* steps;   // [n_tiles][NW]
+    float* alpha;      // [entry_cap]
+    float* c_in;       // [3][entry_cap]
+    uint32_t* count;   // [H*W]
+    size_t entry_cap;
+    uint32_t pair_cap;
 };
 
 template <int TW, int TH, bool CACHED>
@@ -82,82 +104,153 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
     float bg2, float* __restrict__ image, float* __restrict__ t_final,
     uint32_t* __restrict__ n_contrib, Trace tr, uint32_t* __restrict__ flags) {
     constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64;
     __shared__ float4 s_a[NT];
     __shared__ float4 s_b[NT];
     __shared__ float s_c[NT];
+    __shared__ uint32_t s_steps;
     const int tile = blockIdx.x;
     const int tx = tile % TX, ty = tile / TX;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = tx * TW + (t % TW), py = ty * TH + (t / TW);
     const bool inside = px < W && py < H;
     const int gt = tile_offset + tile;
     const uint32_t start = ranges[gt], end = ranges[n_tiles_total + gt];
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
 
+    // the trace is recorded only if this tile's pairs fit the trace buffers
+    const bool rec = CACHED && end <= tr.pair_cap;
+    if (CACHED && !rec && t == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
+    const size_t ebase = (size_t)NT * start + (size_t)64 * (end - start) * wv;
+    uint32_t cursor = 0, steps = 0, cnt = 0;
+
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     bool done = !inside;
-    uint32_t last = 0, cnt = 0;
-    const size_t tbase = (size_t)gt * (size_t)(CACHED ? tr.k_max : 0);
+    uint32_t last = 0;
 
     for (uint32_t base = start; base < end; base += NT) {
         if (__syncthreads_count(!done) == 0) break;
         if (base + t < end) stage_splat(proj, n, values[base + t], s_a, s_b, s_c, t);
         __syncthreads();
         const int nb = (int)min((uint32_t)NT, end - base);
-        for (int k = 0; k < nb && !done; ++k) {
-            const Splat s = load_splat(s_a, s_b, s_c, k);
-            float alpha, gauss, dx, dy;
-            if (!splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy)) continue;
-            const float test_T = T * (1.f - alpha);
-            if (test_T < kTMin) {
-                done = true;
-                break;
-            }
-            const float w = alpha * T;
-            C0 += w * s.r;
-            C1 += w * s.g;
-            C2 += w * s.b;
-            if (CACHED) {
-                if (cnt < (uint32_t)tr.k_max) {
-                    const size_t e = (tbase + cnt) * NT + t;
-                    tr.id[e] = base + k;
-                    tr.alpha[e] = alpha;
-                    tr.c_in[e] = s.r;
-                    tr.c_in[tr.slots + e] = s.g;
-                    tr.c_in[2 * tr.slots + e] = s.b;
+        for (int k = 0; k < nb; ++k) {
+            if (__ballot(!done) == 0) break;  // the whole wave has terminated
+            bool contrib = false;
+            float alpha = 0.f;
+            if (!done) {
+                const Splat s = load_splat(s_a, s_b, s_c, k);
+                float gauss, dx, dy;
+                if (splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy)) {
+                    const float test_T = T * (1.f - alpha);
+                    if (test_T < kTMin) {
+                        done = true;
+                    } else {
+                        contrib = true;
+                        const float w = alpha * T;
+                        C0 += w * s.r;
+                        C1 += w * s.g;
+                        C2 += w * s.b;
+                        T = test_T;
+                        last = base + k - start + 1;
+                    }
                 }
-                ++cnt;
             }
-            T = test_T;
-            last = base + k - start + 1;
+            if (rec) {
+                const uint64_t m = __ballot(contrib);
+                if (lane == 0) tr.mask[(size_t)(base + k) * NW + wv] = m;
+                if (contrib) tr.alpha[ebase + cursor + lane_rank(m)] = alpha;
+                cursor += __popcll(m);
+                cnt += contrib ? 1u : 0u;
+                steps = base + k - start + 1;
+            }
         }
     }
-    if (!inside) return;
-    const size_t pix = (size_t)py * W + px, plane = (size_t)W * H;
-    image[pix] = C0 + T * bg0;
-    image[plane + pix] = C1 + T * bg1;
-    image[2 * plane + pix] = C2 + T * bg2;
-    t_final[pix] = T;
-    n_contrib[pix] = last;
-    if (CACHED) {
-        uint32_t kept = cnt;
-        if (cnt > (uint32_t)tr.k_max) {
-            kept = (uint32_t)tr.k_max;
-            atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
+    if (inside) {
+        const size_t pix = (size_t)py * W + px, plane = (size_t)W * H;
+        image[pix] = C0 + T * bg0;
+        image[plane + pix] = C1 + T * bg1;
+        image[2 * plane + pix] = C2 + T * bg2;
+        t_final[pix] = T;
+        n_contrib[pix] = last;
+        if (CACHED) tr.count[pix] = rec ? cnt : 0u;
+    }
+    if (!rec) return;  // uniform for the block
+    if (lane == 0) tr.steps[(size_t)gt * NW + wv] = steps;
+
+    // C_in fill: back to front over each wave's groups, splat colours staged
+    // in LDS batch by batch (the forward batches in reverse).
+    if (t == 0) s_steps = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_steps, steps);
+    __syncthreads();
+    const uint32_t smax = s_steps;
+    float a0 = bg0, a1 = bg1, a2 = bg2;
+    uint32_t cur = cursor;
+    if (smax == 0) return;
+    const int64_t top = (int64_t)((smax - 1) / NT) * NT;  // first position of the last batch
+    for (int64_t lo = top; lo >= 0; lo -= NT) {
+        const uint32_t hi = min((uint32_t)lo + NT, smax);
+        __syncthreads();
+        if ((uint32_t)lo + t < hi) {
+            const uint32_t g = values[start + lo + t];
+            s_a[t] = make_float4(proj[(size_t)PGS_PROJ_R * n + g], proj[(size_t)PGS_PROJ_G * n + g],
+                                 proj[(size_t)PGS_PROJ_BLUE * n + g], 0.f);
         }
-        tr.count[pix] = kept;
-        // C_in of each entry: everything behind it, from the background forward
-        float a0 = bg0, a1 = bg1, a2 = bg2;
-        for (int k = (int)kept - 1; k >= 0; --k) {
-            const size_t e = (tbase + k) * NT + t;
-            const float al = tr.alpha[e];
-            const float r = tr.c_in[e], g = tr.c_in[tr.slots + e], b = tr.c_in[2 * tr.slots + e];
-            tr.c_in[e] = a0;
-            tr.c_in[tr.slots + e] = a1;
-            tr.c_in[2 * tr.slots + e] = a2;
-            a0 = al * r + (1.f - al) * a0;
-            a1 = al * g + (1.f - al) * a1;
-            a2 = al * b + (1.f - al) * a2;
+        __syncthreads();
+        const uint32_t whi = min(hi, steps);
+        if (whi <= (uint32_t)lo) continue;
+        // chunks of 64 steps, last chunk first; one vector load fetches a
+        // chunk's masks, then the non-empty ones are visited last to first
+        for (int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64; c0 >= lo; c0 -= 64) {
+            const uint32_t cn = min(64u, whi - (uint32_t)c0);
+            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
+            uint64_t any = __ballot(mv != 0ull);
+            while (any) {
+                // up to kG groups (last first), all alpha loads issued first
+                constexpr int kG = 4;
+                int gi[kG];
+                uint64_t gm[kG];
+                uint32_t gc[kG];
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    gi[q] = 0;
+                    gm[q] = 0ull;
+                    gc[q] = cur;
+                    if (any) {
+                        const int i = 63 - __clzll(any);
+                        any &= ~(1ull << i);
+                        gi[q] = i;
+                        gm[q] = read_lane64(mv, i);
+                        cur -= __popcll(gm[q]);
+                        gc[q] = cur;
+                    }
+                }
+                float al[kG];
+                size_t ge[kG];
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    al[q] = 0.f;
+                    ge[q] = 0;
+                    if ((gm[q] >> lane) & 1ull) {
+                        ge[q] = ebase + gc[q] + lane_rank(gm[q]);
+                        al[q] = tr.alpha[ge[q]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    if ((gm[q] >> lane) & 1ull) {
+                        const size_t e = ge[q];
+                        const float a = al[q];
+                        const float4 col = s_a[c0 + gi[q] - lo];
+                        tr.c_in[e] = a0;
+                        tr.c_in[tr.entry_cap + e] = a1;
+                        tr.c_in[2 * tr.entry_cap + e] = a2;
+                        a0 = a * col.x + (1.f - a) * a0;
+                        a1 = a * col.y + (1.f - a) * a1;
+                        a2 = a * col.z + (1.f - a) * a2;
+                    }
+                }
+            }
         }
     }
 }
@@ -182,25 +275,41 @@ __device__ __forceinline__ void chain_2d(const Splat& s, float dx, float dy, flo
     v[8] = dc2;
 }
 
-template <int NW, int BG>
-__device__ __forceinline__ void reduce_to_lds(float* v, float (*acc)[9][BG], int wv, int lane, int jj) {
+// Adds one wave's nine gradients of splat jj into the workgroup's LDS
+// accumulator: a lone contributing lane adds its own values, otherwise the
+// wave sums with DPP and lane 63 adds (LDS float atomics, ds_add_f32).
+template <int BG>
+__device__ __forceinline__ void accumulate(const float* v, float (*acc)[BG], int lane, int jj, bool lone,
+                                           bool mine) {
+    if (lone) {
+        if (mine) {
+#pragma unroll
+            for (int f = 0; f < 9; ++f) atomicAdd(&acc[f][jj], v[f]);
+        }
+        return;
+    }
 #pragma unroll
     for (int f = 0; f < 9; ++f) {
         const float sum = wave_sum_to_lane63(v[f]);
-        if (lane == 63) acc[wv][f][jj] = sum;
+        if (lane == 63) atomicAdd(&acc[f][jj], sum);
     }
 }
 
-template <int NW, int BG>
-__device__ __forceinline__ void flush_batch(float (*acc)[9][BG], const uint32_t* gid, int nb, int n,
+// One float atomic per field and splat of the batch into the canonical
+// 2D-gradient rows (index map values[id]).
+template <int BG>
+__device__ __forceinline__ void flush_batch(float (*acc)[BG], const uint32_t* gid, int nb, int n,
                                             float* __restrict__ grad2d, int t, int NT) {
     for (int idx = t; idx < nb * 9; idx += NT) {
         const int f = idx / nb, jj = idx - f * nb;
-        float s = 0.f;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) s += acc[w][f][jj];
+        const float s = acc[f][jj];
         if (s != 0.f) unsafeAtomicAdd(&grad2d[(size_t)f * n + gid[jj]], s);
     }
+}
+
+template <int BG>
+__device__ __forceinline__ void zero_acc(float (*acc)[BG], int t, int NT) {
+    for (int idx = t; idx < 9 * BG; idx += NT) (&acc[0][0])[idx] = 0.f;
 }
 
 template <int TW, int TH>
@@ -215,85 +324,110 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
     __shared__ float4 s_b[BG];
     __shared__ float s_c[BG];
     __shared__ uint32_t s_g[BG];
-    __shared__ float s_acc[NW][9][BG];
-    __shared__ uint32_t s_end;
+    __shared__ float s_acc[9][BG];
+    __shared__ uint32_t s_steps;
     const int tile = blockIdx.x;
     const int tx = tile % TX, ty = tile / TX;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = tx * TW + (t % TW), py = ty * TH + (t / TW);
     const bool inside = px < W && py < H;
     const int gt = tile_offset + tile;
-    const uint32_t start = ranges[gt];
+    const uint32_t start = ranges[gt], end = ranges[n_tiles_total + gt];
+    if (end > tr.pair_cap) return;  // no trace was recorded for this tile
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-    const size_t tbase = (size_t)gt * (size_t)tr.k_max;
     const size_t pix = (size_t)py * W + px, plane = (size_t)W * H;
+    const size_t ebase = (size_t)NT * start + (size_t)64 * (end - start) * wv;
 
-    uint32_t cnt = 0;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;  // dL/dC_out of this pixel's next entry
     if (inside) {
-        cnt = tr.count[pix];
         g0 = dl_dimage[pix];
         g1 = dl_dimage[plane + pix];
         g2 = dl_dimage[2 * plane + pix];
     }
-    // current entry in registers
-    uint32_t k = 0, cur_id = 0xffffffffu;
-    float cur_a = 0.f, cur_c0 = 0.f, cur_c1 = 0.f, cur_c2 = 0.f;
-    auto fetch = [&](uint32_t kk) {
-        if (kk < cnt) {
-            const size_t e = (tbase + kk) * NT + t;
-            cur_id = tr.id[e];
-            cur_a = tr.alpha[e];
-            cur_c0 = tr.c_in[e];
-            cur_c1 = tr.c_in[tr.slots + e];
-            cur_c2 = tr.c_in[2 * tr.slots + e];
-        } else {
-            cur_id = 0xffffffffu;
-        }
-    };
-    if (t == 0) s_end = 0;
-    uint32_t my_end = 0;
-    if (cnt > 0) my_end = tr.id[(tbase + cnt - 1) * NT + t] + 1;
-    fetch(0);
+    const uint32_t steps = tr.steps[(size_t)gt * NW + wv];
+    if (t == 0) s_steps = 0;
     __syncthreads();
-    if (my_end) atomicMax(&s_end, my_end);
+    if (lane == 0) atomicMax(&s_steps, steps);
     __syncthreads();
-    const uint32_t end = s_end;
+    const uint32_t smax = s_steps;
+    uint32_t cursor = 0;
 
-    for (uint32_t base = start; base < end; base += BG) {
-        const int nb = (int)min((uint32_t)BG, end - base);
+    for (uint32_t base = 0; base < smax; base += BG) {
+        const int nb = (int)min((uint32_t)BG, smax - base);
         if (t < nb) {
-            const uint32_t g = values[base + t];
+            const uint32_t g = values[start + base + t];
             s_g[t] = g;
             stage_splat(proj, n, g, s_a, s_b, s_c, t);
         }
-        for (int idx = t; idx < NW * 9 * BG; idx += NT) (&s_acc[0][0][0])[idx] = 0.f;
+        zero_acc<BG>(s_acc, t, NT);
         __syncthreads();
-        for (int jj = 0; jj < nb; ++jj) {
-            const bool match = cur_id == base + jj;
-            if (__ballot(match) == 0) continue;
-            float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            if (match) {
-                const Splat s = load_splat(s_a, s_b, s_c, jj);
-                const float dx = s.u - fpx, dy = s.v - fpy;
-                const float al = cur_a;
-                // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
-                const float dla = g0 * (s.r - cur_c0) + g1 * (s.g - cur_c1) + g2 * (s.b - cur_c2);
-                const bool clamped = al >= kAlphaMax;
-                chain_2d(s, dx, dy, al, clamped ? 0.f : al / s.o, clamped, dla, al * g0, al * g1,
-                         al * g2, v);
-                // dL/dC_in = dL/dC_out (1 - alpha) is the next entry's dL/dC_out
-                const float om = 1.f - al;
-                g0 *= om;
-                g1 *= om;
-                g2 *= om;
-                ++k;
-                fetch(k);
+        const uint32_t whi = min(base + (uint32_t)nb, steps);
+        for (uint32_t c0 = base; c0 < whi; c0 += 64) {
+            const uint32_t cn = min(64u, whi - c0);
+            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
+            uint64_t any = __ballot(mv != 0ull);
+            while (any) {
+                // take up to kG groups and issue all their trace loads before
+                // any of them is consumed (memory-level parallelism per wave)
+                constexpr int kG = 4;
+                int gi[kG];
+                uint64_t gm[kG];
+                uint32_t gc[kG];
+                uint32_t cur = cursor;
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    gi[q] = 0;
+                    gm[q] = 0ull;
+                    gc[q] = cur;
+                    if (any) {
+                        const int i = __ffsll((unsigned long long)any) - 1;
+                        any &= any - 1;
+                        gi[q] = i;
+                        gm[q] = read_lane64(mv, i);
+                        cur += __popcll(gm[q]);
+                    }
+                }
+                float al[kG], ci0[kG], ci1[kG], ci2[kG];
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    al[q] = ci0[q] = ci1[q] = ci2[q] = 0.f;
+                    if ((gm[q] >> lane) & 1ull) {
+                        const size_t e = ebase + gc[q] + lane_rank(gm[q]);
+                        al[q] = tr.alpha[e];
+                        ci0[q] = tr.c_in[e];
+                        ci1[q] = tr.c_in[tr.entry_cap + e];
+                        ci2[q] = tr.c_in[2 * tr.entry_cap + e];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    const uint64_t m = gm[q];
+                    if (m == 0ull) continue;  // uniform: fewer than kG groups left
+                    const int jj = (int)(c0 - base) + gi[q];
+                    const bool mine = (m >> lane) & 1ull;
+                    float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    if (mine) {
+                        const Splat s = load_splat(s_a, s_b, s_c, jj);
+                        const float dx = s.u - fpx, dy = s.v - fpy;
+                        const float a = al[q];
+                        // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
+                        const float dla = g0 * (s.r - ci0[q]) + g1 * (s.g - ci1[q]) + g2 * (s.b - ci2[q]);
+                        const bool clamped = a >= kAlphaMax;
+                        chain_2d(s, dx, dy, a, clamped ? 0.f : a / s.o, clamped, dla, a * g0, a * g1,
+                                 a * g2, v);
+                        // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
+                        const float om = 1.f - a;
+                        g0 *= om;
+                        g1 *= om;
+                        g2 *= om;
+                    }
+                    accumulate<BG>(v, s_acc, lane, jj, __popcll(m) == 1, mine);
+                }
+                cursor = cur;
             }
-            reduce_to_lds<NW, BG>(v, s_acc, wv, lane, jj);
         }
         __syncthreads();
-        flush_batch<NW, BG>(s_acc, s_g, nb, n, grad2d, t, NT);
+        flush_batch<BG>(s_acc, s_g, nb, n, grad2d, t, NT);
         __syncthreads();
     }
 }
@@ -311,7 +445,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
     __shared__ float4 s_b[BG];
     __shared__ float s_c[BG];
     __shared__ uint32_t s_g[BG];
-    __shared__ float s_acc[NW][9][BG];
+    __shared__ float s_acc[9][BG];
     __shared__ uint32_t s_last;
     const int tile = blockIdx.x;
     const int tx = tile % TX, ty = tile / TX;
@@ -347,18 +481,19 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
             s_g[t] = g;
             stage_splat(proj, n, g, s_a, s_b, s_c, t);
         }
-        for (int idx = t; idx < NW * 9 * BG; idx += NT) (&s_acc[0][0][0])[idx] = 0.f;
+        zero_acc<BG>(s_acc, t, NT);
         __syncthreads();
         for (int jj = nb - 1; jj >= 0; --jj) {
             const uint32_t jrel = lo + jj;
             bool ok = false;
             float alpha = 0.f, gauss = 0.f, dx = 0.f, dy = 0.f;
-            Splat s;
+            Splat s{};
             if (jrel < last) {
                 s = load_splat(s_a, s_b, s_c, jj);
                 ok = splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy);
             }
-            if (__ballot(ok) == 0) continue;
+            const uint64_t m = __ballot(ok);
+            if (m == 0) continue;
             float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             if (ok) {
                 const float Tk = T / (1.f - alpha);
@@ -372,10 +507,10 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
                 a2 = alpha * s.b + (1.f - alpha) * a2;
                 T = Tk;
             }
-            reduce_to_lds<NW, BG>(v, s_acc, wv, lane, jj);
+            accumulate<BG>(v, s_acc, lane, jj, __popcll(m) == 1, ok);
         }
         __syncthreads();
-        flush_batch<NW, BG>(s_acc, s_g, nb, n, grad2d, t, NT);
+        flush_batch<BG>(s_acc, s_g, nb, n, grad2d, t, NT);
         __syncthreads();
         hi = lo;
     }
@@ -384,6 +519,21 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
 bool tile_ok(int tw, int th) { return tw == 16 && th == 16; }
 
 }  // namespace
+
+extern "C" size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int32_t tile_h) {
+    return (size_t)pair_capacity * (size_t)(tile_w > 0 ? tile_w : 0) * (size_t)(tile_h > 0 ? tile_h : 0);
+}
+
+static pgs_status make_trace(const pgs_replay* c, int tile_w, int tile_h, Trace& tr, const char* who) {
+    PGS_REQUIRE(c->mask_dev && c->steps_dev && c->alpha_dev && c->c_in_dev && c->count_dev,
+                "%s: null trace pointer", who);
+    PGS_REQUIRE(c->entry_capacity >= pgs_trace_entries(c->pair_capacity, tile_w, tile_h),
+                "%s: trace entry capacity %llu below %u pairs x %d pixels", who,
+                (unsigned long long)c->entry_capacity, c->pair_capacity, tile_w * tile_h);
+    tr = Trace{c->mask_dev, c->steps_dev, c->alpha_dev, c->c_in_dev, c->count_dev,
+               (size_t)c->entry_capacity, c->pair_capacity};
+    return PGS_OK;
+}
 
 extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
                                      const float* proj_dev, int32_t n, const uint32_t* values_dev,
@@ -400,10 +550,9 @@ extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile
     const int n_tiles_total = view_tile_offset + TX * TY;
     Trace tr{};
     if (cache) {
-        PGS_REQUIRE(cache->id_dev && cache->alpha_dev && cache->c_in_dev && cache->count_dev &&
-                        cache->k_max > 0 && flags_dev, "pgs_render_fwd: bad trace");
-        tr = Trace{cache->id_dev, cache->alpha_dev, cache->c_in_dev, cache->count_dev, cache->k_max,
-                   (size_t)n_tiles_total * cache->k_max * tile_w * tile_h};
+        PGS_REQUIRE(flags_dev != nullptr, "pgs_render_fwd: a trace needs the flags word");
+        pgs_status st = make_trace(cache, tile_w, tile_h, tr, "pgs_render_fwd");
+        if (st != PGS_OK) return st;
     }
     hipStream_t s = pgs::as_stream(stream);
     const dim3 grid(TX * TY), block(256);
@@ -437,10 +586,9 @@ extern "C" pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile
     hipStream_t s = pgs::as_stream(stream);
     const dim3 grid(TX * TY), block(256);
     if (cache) {
-        PGS_REQUIRE(cache->id_dev && cache->alpha_dev && cache->c_in_dev && cache->count_dev &&
-                        cache->k_max > 0, "pgs_render_bwd: bad trace");
-        Trace tr{cache->id_dev, cache->alpha_dev, cache->c_in_dev, cache->count_dev, cache->k_max,
-                 (size_t)n_tiles_total * cache->k_max * tile_w * tile_h};
+        Trace tr{};
+        pgs_status st = make_trace(cache, tile_w, tile_h, tr, "pgs_render_bwd");
+        if (st != PGS_OK) return st;
         k_render_bwd_cached<16, 16><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, n_tiles_total,
                                                            proj_dev, n, values_dev, ranges_dev, tr,
                                                            dl_dimage_dev, grad2d_dev);

@@ -5,7 +5,7 @@ forward:  pgs_project -> pgs_bin_sort -> pgs_render_fwd (optionally recording
 backward: pgs_render_bwd (trace replay, or recompute-T) -> pgs_project_bwd
 
 Buffers are allocated with PyTorch once and reused; the pair capacity and the
-trace depth k_max grow when the device flags report an overflow (the caller
+replay trace grow when the device flags report an overflow (the caller
 runs `forward_checked`, which synchronises once to read the flags).
 """
 
@@ -25,7 +25,7 @@ def param_rows(sh_degree: int) -> int:
 
 class Rasterizer:
     def __init__(self, n: int, sh_degree: int, width: int, height: int, tile=(16, 16),
-                 cached: bool = True, k_max: int = 64, capacity: int | None = None,
+                 cached: bool = True, capacity: int | None = None,
                  device="cuda"):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
@@ -50,45 +50,42 @@ class Rasterizer:
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
         self.grad2d = torch.zeros((GRAD2D_FIELDS, n), dtype=torch.float32, device=d)
         self.capacity = 0
-        self.k_max = 0
         self.trace = None
+        self.nw = self.tw * self.th // 64
         self._alloc_pairs(capacity if capacity is not None else max(1024, 4 * self.n))
-        if cached:
-            self._alloc_trace(k_max)
 
     # -- buffers ---------------------------------------------------------
     def _alloc_pairs(self, capacity: int):
+        """Pair buffers, sort workspace and (cached mode) the replay trace,
+        whose worst-case size is tied to the pair capacity."""
         capacity = int(capacity)
         d = self.device
         self.capacity = capacity
+        self.keys = self.values = self.workspace = self.trace = None
         self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=d)
         self.values = torch.empty(max(capacity, 1), dtype=torch.int32, device=d)
         ws = B.pgs_bin_sort_workspace(self.n, capacity)
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=d)
-
-    def _alloc_trace(self, k_max: int):
-        self.k_max = int(k_max)
-        slots = self.n_tiles * self.k_max * self.tw * self.th
-        d = self.device
-        self.trace = dict(
-            id=torch.empty(slots, dtype=torch.int32, device=d),
-            alpha=torch.empty(slots, dtype=torch.float32, device=d),
-            c_in=torch.empty(3 * slots, dtype=torch.float32, device=d),
-            count=torch.empty(self.H * self.W, dtype=torch.int32, device=d),
-            k_max=self.k_max,
-        )
-
-    def reserve(self, pair_factor: float = 2.0, k_factor: int = 2):
-        """Enlarge the pair capacity and trace depth ahead of training, whose
-        Gaussians grow and so touch more tiles and pixels over time."""
-        self._alloc_pairs(int(self.capacity * pair_factor))
         if self.cached:
-            self._alloc_trace(self.k_max * k_factor)
+            ents = B.pgs_trace_entries(capacity, self.tw, self.th)
+            self.trace = dict(
+                mask=torch.empty((max(capacity, 1), self.nw), dtype=torch.int64, device=d),
+                steps=torch.empty((self.n_tiles, self.nw), dtype=torch.int32, device=d),
+                alpha=torch.empty(max(ents, 1), dtype=torch.float32, device=d),
+                c_in=torch.empty(3 * max(ents, 1), dtype=torch.float32, device=d),
+                count=torch.empty(self.H * self.W, dtype=torch.int32, device=d),
+                entry_capacity=max(ents, 1), pair_capacity=capacity,
+            )
+
+    def reserve(self, pair_factor: float = 2.0):
+        """Enlarge the pair capacity (and the trace with it) ahead of
+        training, whose Gaussians grow and touch more tiles over time."""
+        self._alloc_pairs(int(self.capacity * pair_factor))
 
     def trace_bytes(self) -> int:
         if self.trace is None:
             return 0
-        return sum(v.numel() * v.element_size() for k, v in self.trace.items() if k != "k_max")
+        return sum(v.numel() * v.element_size() for v in self.trace.values() if isinstance(v, torch.Tensor))
 
     # -- passes ----------------------------------------------------------
     def forward(self, params: torch.Tensor, cam: dict, bg=(0.0, 0.0, 0.0)):
@@ -116,12 +113,9 @@ class Rasterizer:
             f = self.read_flags()
             if f == 0:
                 return self.image
-            if f & PGS_FLAG_PAIR_OVERFLOW:
+            if f & (PGS_FLAG_PAIR_OVERFLOW | PGS_FLAG_CACHE_OVERFLOW):
                 need = int(self.num_pairs.item())
-                self._alloc_pairs(int(math.ceil(need * headroom)) + 1024)
-            if f & PGS_FLAG_CACHE_OVERFLOW:
-                # counts are clamped at k_max, so the true depth is unknown
-                self._alloc_trace(self.k_max * 4)
+                self._alloc_pairs(int(math.ceil(max(need, self.capacity) * headroom)) + 1024)
         raise RuntimeError("rasterizer buffers kept overflowing")
 
     def backward(self, params, cam, dl_dimage, grads, bg=(0.0, 0.0, 0.0), zero_grad2d=True):

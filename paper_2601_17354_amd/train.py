@@ -51,7 +51,7 @@ class Trainer:
     """Canonical parameters, Adam moments and one rasterizer per resolution."""
 
     def __init__(self, params: torch.Tensor, sh_degree: int, width: int, height: int,
-                 cached: bool = True, lam: float = 0.2, extent: float = 1.0, k_max: int = 64,
+                 cached: bool = True, lam: float = 0.2, extent: float = 1.0,
                  tile=(16, 16)):
         self.params = params.contiguous()
         self.sh_degree = sh_degree
@@ -63,7 +63,7 @@ class Trainer:
         self.lr = learning_rates(sh_degree, extent)
         self.lam = lam
         self.W, self.H = width, height
-        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached, k_max=k_max)
+        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached)
         self.dl = torch.empty((3, height, width), dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = torch.empty(B.pgs_loss_workspace(width, height), dtype=torch.uint8, device=dev)

@@ -51,7 +51,7 @@ def max_rel(got, want, floor_frac=1e-3):
     return float((np.abs(got - want)[big] / np.abs(want)[big]).max())
 
 
-def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None, k_max=64,
+def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None,
             capacity=None, tile=(16, 16)):
     """One view through the HIP path; returns numpy copies of every output."""
     from paper_2601_17354_amd.raster import Rasterizer
@@ -59,7 +59,7 @@ def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None, 
     n = P.shape[1]
     params = torch.as_tensor(np.ascontiguousarray(P, np.float32), device=dev)
     R = Rasterizer(n, sh_degree, cam["width"], cam["height"], tile=tile, cached=cached,
-                   k_max=k_max, capacity=capacity)
+                   capacity=capacity)
     R.forward_checked(params, cam, bg)
     torch.cuda.synchronize()
     out = dict(
@@ -85,16 +85,28 @@ def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None, 
 
 
 def trace_entries(out, cam, x, y, tile=(16, 16)):
-    """Replay-trace entries (id, alpha, C_in) of pixel (x, y) read back from the GPU."""
+    """Replay-trace entries (id, alpha, C_in) of pixel (x, y), decoded from the
+    per-wave groups of the GPU trace (layout documented at pgs_replay)."""
     R = out["rast"]
     tw, th = tile
+    nt = tw * th
     TX = (cam["width"] + tw - 1) // tw
     t = (y // th) * TX + (x // tw)
     p = (y % th) * tw + (x % tw)
-    cnt = int(out["count"][y, x])
-    slots = R.trace["alpha"].numel()
-    e = (t * R.k_max + torch.arange(cnt, device=R.device)) * tw * th + p
-    ids = R.trace["id"][e].cpu().numpy().astype(np.int64)
+    w, lane = p // 64, p % 64
+    start, end = (int(v) for v in out["ranges"][:, t])
+    steps = int(R.trace["steps"][t, w].item())
+    masks = R.trace["mask"][start:start + steps, w].cpu().numpy().view(np.uint64)
+    cap = R.trace["entry_capacity"]
+    ebase = nt * start + 64 * (end - start) * w
+    cursor, ents = 0, []
+    for j, m in enumerate(masks):
+        m = int(m)
+        if (m >> lane) & 1:
+            ents.append((start + j, ebase + cursor + bin(m & ((1 << lane) - 1)).count("1")))
+        cursor += bin(m).count("1")
+    assert len(ents) == int(out["count"][y, x])
+    e = torch.as_tensor([q for _, q in ents], dtype=torch.int64, device=R.device)
     al = R.trace["alpha"][e].cpu().numpy()
-    cin = torch.stack([R.trace["c_in"][c * slots + e] for c in range(3)], 1).cpu().numpy()
-    return ids, al, cin
+    cin = torch.stack([R.trace["c_in"][c * cap + e] for c in range(3)], 1).cpu().numpy()
+    return np.asarray([i for i, _ in ents], np.int64), al, cin

@@ -149,28 +149,38 @@ def test_pca_seed_matches_oracle():
 
 
 def test_trace_poison_counter_reset_is_exact():
-    # Stale entries beyond count(u) are never read: a trace full of NaN and
-    # one full of zeros give bit-identical gradients (replay-cache subsection).
+    # Trace contents beyond the per-wave step counters are never read
+    # (replay-cache subsection): a trace pre-filled with NaN entries and
+    # all-ones masks, one pre-filled with zeros, and one left holding a
+    # different scene's trace from a previous iteration give the same
+    # gradients (up to atomic-order noise) and the same image bits.
     P, cam, _ = synth.cfg1_inputs(0)
+    P_other, _, _ = synth.cfg1_inputs(5)
     from paper_2601_17354_amd.raster import Rasterizer
     params = torch.as_tensor(P, device=DEV)
     dl = torch.as_tensor(np.random.default_rng(1).normal(size=(3, 128, 128)).astype(np.float32), device=DEV)
-    outs = []
-    for fill in (float("nan"), 0.0):
-        R = Rasterizer(P.shape[1], 0, 128, 128, cached=True, k_max=64)
-        for k in ("alpha", "c_in"):
-            R.trace[k].fill_(fill)
-        R.trace["id"].fill_(-1 if math.isnan(fill) else 0)
+    outs, imgs = [], []
+    for mode in ("nan", "zero", "stale"):
+        R = Rasterizer(P.shape[1], 0, 128, 128, cached=True, capacity=40000)
+        if mode == "stale":
+            R.forward_checked(torch.as_tensor(P_other, device=DEV), cam)
+        else:
+            fill = float("nan") if mode == "nan" else 0.0
+            R.trace["alpha"].fill_(fill)
+            R.trace["c_in"].fill_(fill)
+            R.trace["mask"].fill_(-1 if mode == "nan" else 0)
         R.forward_checked(params, cam)
+        assert R.capacity == 40000          # no reallocation wiped the poison
         grads = torch.zeros_like(params)
-        # accumulate in a fixed order: one tile per launch is not needed; the
-        # check is on finiteness and equality within atomic-order noise
         R.backward(params, cam, dl, grads)
         torch.cuda.synchronize()
         outs.append(grads.cpu().numpy())
+        imgs.append(R.image.cpu().numpy())
     assert np.isfinite(outs[0]).all()
-    for r in range(outs[0].shape[0]):
-        assert_block_close(outs[0][r], outs[1][r], 1e-6, what=f"row {r}")
+    for o, im in zip(outs[1:], imgs[1:]):
+        np.testing.assert_array_equal(im, imgs[0])
+        for r in range(outs[0].shape[0]):
+            assert_block_close(o[r], outs[0][r], 1e-6, what=f"row {r}")
 
 
 def test_index_map_permutation_equivariance():
@@ -191,15 +201,20 @@ def test_overflow_flags_and_recovery():
     from paper_2601_17354_amd._lib import PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW
     from paper_2601_17354_amd.raster import Rasterizer
     params = torch.as_tensor(P, device=DEV)
-    R = Rasterizer(P.shape[1], 0, 128, 128, cached=True, k_max=2, capacity=100)
+    R = Rasterizer(P.shape[1], 0, 128, 128, cached=True, capacity=100)
     R.flags.zero_()
     R.forward(params, cam)
-    f = R.read_flags()
-    assert f & PGS_FLAG_PAIR_OVERFLOW and f & PGS_FLAG_CACHE_OVERFLOW
+    assert R.read_flags() & PGS_FLAG_PAIR_OVERFLOW
     R.forward_checked(params, cam)
     assert R.read_flags() == 0 and R.capacity >= int(R.num_pairs.item())
     ref = run_gpu(P, cam, 0)
     np.testing.assert_array_equal(R.image.cpu().numpy(), ref["image"])
+    # a trace declared for fewer pairs than the list holds: the tiles beyond it
+    # are not recorded and the device says so
+    R.trace["pair_capacity"] = 1000
+    R.flags.zero_()
+    R.forward(params, cam)
+    assert R.read_flags() == PGS_FLAG_CACHE_OVERFLOW
 
 
 @pytest.mark.parametrize("kind", ["empty", "all-culled", "single", "huge", "flat-edge-on"])
