@@ -88,9 +88,9 @@ typedef struct pgs_camera {
  *   steps_dev  [n_tiles][TW*TH/64] uint32: per wave, the number of list
  *              positions (from the tile's start) whose masks are valid; the
  *              per-iteration counter that replaces a cache clear
- *   alpha_dev  [entry_capacity] float32 clamped alpha of each entry
- *   c_in_dev   [3][entry_capacity] float32 colour of everything behind the
- *              splat at that pixel (plane stride entry_capacity)
+ *   entry_dev  [entry_capacity][4] float32, 16-byte aligned: per entry
+ *              (C_in r, g, b, alpha) - C_in the colour of everything behind
+ *              the splat at that pixel, alpha the clamped alpha it had there
  *   count_dev  [H*W] uint32 entries per pixel, count(u)
  * Entries of wave w of the tile whose pairs are [start, end) live at
  * TW*TH*start + 64*(end-start)*w + cursor, where cursor counts the wave's
@@ -101,8 +101,7 @@ typedef struct pgs_camera {
 typedef struct pgs_replay {
     uint64_t* mask_dev;
     uint32_t* steps_dev;
-    float* alpha_dev;
-    float* c_in_dev;
+    float* entry_dev;
     uint32_t* count_dev;
     uint64_t entry_capacity;
     uint32_t pair_capacity;
@@ -206,7 +205,19 @@ pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile_w, int32_t
                           const uint32_t* ranges_dev, int32_t view_tile_offset,
                           const float* bg_host, float* image_dev, float* t_final_dev,
                           uint32_t* n_contrib_dev, const pgs_replay* cache,
-                          uint32_t* flags_dev, void* stream);
+                          uint32_t* flags_dev, const uint32_t* tile_order_dev, void* stream);
+
+/*
+ * pgs_tile_order - a launch order for the render kernels (scheduling only,
+ * results do not depend on it): the view's tiles sorted by list length,
+ * longest first, in 8-pair buckets, so long tiles do not form a tail.
+ *   ranges_dev      from pgs_bin_sort ([2][n_tiles])
+ *   order_dev       out [tiles_in_view] local tile indices; pass it as
+ *                   tile_order_dev to pgs_render_fwd / pgs_render_bwd
+ *                   (NULL there means natural order)
+ */
+pgs_status pgs_tile_order(const uint32_t* ranges_dev, int32_t tiles_in_view, int32_t view_tile_offset,
+                          int32_t n_tiles, uint32_t* order_dev, void* stream);
 
 /*
  * pgs_render_bwd - backward of the compositing recursion (equation
@@ -227,7 +238,8 @@ pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile_w, int32_t
                           const uint32_t* ranges_dev, int32_t view_tile_offset,
                           const float* bg_host, const float* t_final_dev,
                           const uint32_t* n_contrib_dev, const pgs_replay* cache,
-                          const float* dl_dimage_dev, float* grad2d_dev, void* stream);
+                          const float* dl_dimage_dev, float* grad2d_dev,
+                          const uint32_t* tile_order_dev, void* stream);
 
 /*
  * pgs_project_bwd - chain the 2D gradients of one view back to the canonical
@@ -298,6 +310,15 @@ pgs_status pgs_knn(const float* points_dev, int32_t m, int32_t k, int32_t* nbr_d
 pgs_status pgs_pca_seed(const float* points_dev, const float* colours_dev, int32_t m,
                         const int32_t* nbr_dev, const double* d2_dev, int32_t k,
                         float r_normal, float* params_dev, void* stream);
+
+/*
+ * pgs_stream_copy - plain streaming copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned) from src_dev to dst_dev.  A measurement aid, not
+ * part of the method: it defines the achievable HBM bandwidth the kernels are
+ * compared with and calibrates hardware traffic counters (it reads and
+ * writes exactly `bytes`).
+ */
+pgs_status pgs_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

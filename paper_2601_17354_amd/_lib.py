@@ -28,9 +28,8 @@ class PgsCamera(ctypes.Structure):
 
 
 class PgsReplay(ctypes.Structure):
-    _fields_ = [("mask_dev", c_void_p), ("steps_dev", c_void_p), ("alpha_dev", c_void_p),
-                ("c_in_dev", c_void_p), ("count_dev", c_void_p), ("entry_capacity", c_uint64),
-                ("pair_capacity", c_uint32)]
+    _fields_ = [("mask_dev", c_void_p), ("steps_dev", c_void_p), ("entry_dev", c_void_p),
+                ("count_dev", c_void_p), ("entry_capacity", c_uint64), ("pair_capacity", c_uint32)]
 
 
 # name -> (restype, argtypes)
@@ -49,10 +48,11 @@ SIGNATURES = {
     "pgs_trace_entries": (c_size_t, [c_uint32, c_int32, c_int32]),
     "pgs_render_fwd": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                  c_void_p, c_int32, POINTER(c_float), c_void_p, c_void_p, c_void_p,
-                                 POINTER(PgsReplay), c_void_p, c_void_p]),
+                                 POINTER(PgsReplay), c_void_p, c_void_p, c_void_p]),
+    "pgs_tile_order": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "pgs_render_bwd": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                  c_void_p, c_int32, POINTER(c_float), c_void_p, c_void_p,
-                                 POINTER(PgsReplay), c_void_p, c_void_p, c_void_p]),
+                                 POINTER(PgsReplay), c_void_p, c_void_p, c_void_p, c_void_p]),
     "pgs_project_bwd": (c_int32, [c_void_p, c_int32, c_int32, POINTER(PgsCamera), c_void_p,
                                   c_void_p, c_void_p, c_void_p]),
     "pgs_loss_workspace": (c_size_t, [c_int32, c_int32]),
@@ -63,6 +63,7 @@ SIGNATURES = {
     "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pgs_pca_seed": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float,
                                c_void_p, c_void_p]),
+    "pgs_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 _lib = None

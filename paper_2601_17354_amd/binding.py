@@ -53,8 +53,7 @@ def replay_struct(trace) -> PgsReplay | None:
     r = PgsReplay()
     r.mask_dev = _ptr(trace["mask"], torch.int64).value
     r.steps_dev = _ptr(trace["steps"], torch.int32).value
-    r.alpha_dev = _ptr(trace["alpha"], torch.float32).value
-    r.c_in_dev = _ptr(trace["c_in"], torch.float32).value
+    r.entry_dev = _ptr(trace["entry"], torch.float32).value
     r.count_dev = _ptr(trace["count"], torch.int32).value
     r.entry_capacity = int(trace["entry_capacity"])
     r.pair_capacity = int(trace["pair_capacity"])
@@ -109,26 +108,32 @@ def pgs_sort_pairs(keys, values, count, capacity, key_bits, workspace, stream=No
           "pgs_sort_pairs")
 
 
+def pgs_tile_order(ranges, tiles_in_view, view_tile_offset, n_tiles, order, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_tile_order(_ptr(ranges, I32), tiles_in_view, view_tile_offset, n_tiles,
+                             _ptr(order, I32), _stream(stream)), "pgs_tile_order")
+
+
 def pgs_render_fwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_tile_offset, bg,
-                   image, t_final, n_contrib, trace, flags, stream=None):
+                   image, t_final, n_contrib, trace, flags, tile_order=None, stream=None):
     lib = _lib.load()
     r = replay_struct(trace)
     check(lib.pgs_render_fwd(width, height, tile_w, tile_h, _ptr(proj, F32), n, _ptr(values, I32),
                              _ptr(ranges, I32), view_tile_offset, _f3(bg), _ptr(image, F32),
                              _ptr(t_final, F32), _ptr(n_contrib, I32),
                              ctypes.byref(r) if r is not None else None, _ptr(flags, I32),
-                             _stream(stream)), "pgs_render_fwd")
+                             _ptr(tile_order, I32), _stream(stream)), "pgs_render_fwd")
 
 
 def pgs_render_bwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_tile_offset, bg,
-                   t_final, n_contrib, trace, dl_dimage, grad2d, stream=None):
+                   t_final, n_contrib, trace, dl_dimage, grad2d, tile_order=None, stream=None):
     lib = _lib.load()
     r = replay_struct(trace)
     check(lib.pgs_render_bwd(width, height, tile_w, tile_h, _ptr(proj, F32), n, _ptr(values, I32),
                              _ptr(ranges, I32), view_tile_offset, _f3(bg), _ptr(t_final, F32),
                              _ptr(n_contrib, I32), ctypes.byref(r) if r is not None else None,
-                             _ptr(dl_dimage, F32), _ptr(grad2d, F32), _stream(stream)),
-          "pgs_render_bwd")
+                             _ptr(dl_dimage, F32), _ptr(grad2d, F32), _ptr(tile_order, I32),
+                             _stream(stream)), "pgs_render_bwd")
 
 
 def pgs_project_bwd(params, n, sh_degree, cam, radius, grad2d, grads, stream=None):
@@ -161,6 +166,11 @@ def pgs_knn(points, m, k, nbr, d2, stream=None):
     lib = _lib.load()
     check(lib.pgs_knn(_ptr(points, F32), m, k, _ptr(nbr, I32), _ptr(d2, torch.float64), _stream(stream)),
           "pgs_knn")
+
+
+def pgs_stream_copy(src, dst, nbytes, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "pgs_stream_copy")
 
 
 def pgs_pca_seed(points, colours, m, nbr, d2, k, r_normal, params, stream=None):

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpocketgs.so")
 
-SOURCES = ["api.hip", "project.hip", "binning.hip", "render.hip", "loss.hip", "adam.hip", "seed.hip"]
+SOURCES = ["api.hip", "project.hip", "binning.hip", "render.hip", "loss.hip", "adam.hip", "seed.hip",
+           "probe.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

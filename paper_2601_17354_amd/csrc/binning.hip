@@ -252,6 +252,44 @@ __global__ void k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __re
     }
 }
 
+// Heavy-first tile order: a one-workgroup counting sort of the view's tiles
+// by list length in 8-pair buckets, longest first, so the longest tiles start
+// first and the launch has no long tail.  Order inside a bucket is arbitrary;
+// it only changes scheduling, never a result.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 256;
+
+__device__ __forceinline__ uint32_t order_bucket(const uint32_t* ranges, uint32_t n_tiles_total, uint32_t gt) {
+    const uint32_t len = ranges[n_tiles_total + gt] - ranges[gt];
+    const uint32_t b = len >> 3;
+    return (kOrderBuckets - 1) - (b < (uint32_t)(kOrderBuckets - 1) ? b : (uint32_t)(kOrderBuckets - 1));
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges,
+                                                              uint32_t n_view, uint32_t offset,
+                                                              uint32_t n_tiles_total,
+                                                              uint32_t* __restrict__ order) {
+    __shared__ uint32_t hist[kOrderBuckets];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderThreads) hist[b] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_view; i += kOrderThreads)
+        atomicAdd(&hist[order_bucket(ranges, n_tiles_total, offset + i)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < kOrderBuckets; ++b) {
+            const uint32_t c = hist[b];
+            hist[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_view; i += kOrderThreads) {
+        const uint32_t pos = atomicAdd(&hist[order_bucket(ranges, n_tiles_total, offset + i)], 1u);
+        order[pos] = i;
+    }
+}
+
 struct SortWs {
     uint64_t* keys_alt;
     uint32_t* vals_alt;
@@ -308,6 +346,19 @@ int bits_for(uint32_t v) {  // number of bits needed for values < v
 }  // namespace
 
 extern "C" size_t pgs_sort_workspace(uint32_t capacity) { return sort_layout(nullptr, capacity).bytes; }
+
+extern "C" pgs_status pgs_tile_order(const uint32_t* ranges_dev, int32_t tiles_in_view,
+                                     int32_t view_tile_offset, int32_t n_tiles, uint32_t* order_dev,
+                                     void* stream) {
+    PGS_REQUIRE(tiles_in_view > 0 && view_tile_offset >= 0 && view_tile_offset + tiles_in_view <= n_tiles,
+                "pgs_tile_order: bad tile counts");
+    PGS_REQUIRE(ranges_dev && order_dev, "pgs_tile_order: null pointer");
+    k_tile_order<<<1, kOrderThreads, 0, pgs::as_stream(stream)>>>(ranges_dev, (uint32_t)tiles_in_view,
+                                                                 (uint32_t)view_tile_offset, (uint32_t)n_tiles,
+                                                                 order_dev);
+    PGS_CHECK_LAUNCH("pgs_tile_order");
+    return PGS_OK;
+}
 
 extern "C" pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, const uint32_t* count_dev,
                                      uint32_t capacity, int32_t key_bits, void* workspace_dev,

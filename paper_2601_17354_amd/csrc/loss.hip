@@ -170,16 +170,41 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, c
     if (t == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-// Sums the per-block partials in a fixed order (deterministic, no atomics).
-__global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ part_l1, int nl,
-                                                    const float* __restrict__ part_s, int ns,
-                                                    float lambda, float invN, float* __restrict__ out) {
-    __shared__ float red[4];
-    float a = 0.f, b = 0.f;
-    for (int i = threadIdx.x; i < nl; i += 256) a += part_l1[i];
-    for (int i = threadIdx.x; i < ns; i += 256) b += part_s[i];
-    const float l1 = block_sum(a, red) * invN;
-    const float ss = block_sum(b, red) * invN;
+// Sums the per-block partials in a fixed order (deterministic, no atomics):
+// 1024 lanes, eight independent accumulators each so the loads overlap.
+constexpr int kFinalThreads = 1024;
+
+__device__ __forceinline__ float strided_sum(const float* __restrict__ p, int n) {
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int base = threadIdx.x; base < n; base += 8 * kFinalThreads) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * kFinalThreads;
+            if (i < n) acc[u] += p[i];
+        }
+    }
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+__device__ __forceinline__ float block_sum_1024(float v, float* red) {
+    const float w = wave_sum_to_lane63(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 63) red[wv] = w;
+    __syncthreads();
+    float tot = 0.f;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kFinalThreads / 64; ++k) tot += red[k];
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(kFinalThreads) void k_loss_final(const float* __restrict__ part_l1, int nl,
+                                                              const float* __restrict__ part_s, int ns,
+                                                              float lambda, float invN,
+                                                              float* __restrict__ out) {
+    __shared__ float red[kFinalThreads / 64];
+    const float l1 = block_sum_1024(strided_sum(part_l1, nl), red) * invN;
+    const float ss = block_sum_1024(strided_sum(part_s, ns), red) * invN;
     if (threadIdx.x == 0) out[0] = lambda > 0.f ? (1.f - lambda) * l1 + lambda * (1.f - ss) : l1;
 }
 
@@ -225,7 +250,7 @@ extern "C" pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, 
         k_ssim_bwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, (1.f - lambda) * invN,
                                         lambda * invN, dl_dx_dev, part_l1);
     }
-    k_loss_final<<<1, 256, 0, s>>>(part_l1, nl, part_s, ns, lambda, invN, loss_dev);
+    k_loss_final<<<1, kFinalThreads, 0, s>>>(part_l1, nl, part_s, ns, lambda, invN, loss_dev);
     PGS_CHECK_LAUNCH("pgs_loss_l1_dssim");
     return PGS_OK;
 }

@@ -39,6 +39,11 @@
 // (index-mapping equation).
 #include "common.hpp"
 
+// Trace groups whose entries a wave loads before consuming the first one.
+#ifndef PGS_TRACE_GROUPS
+#define PGS_TRACE_GROUPS 4
+#endif
+
 namespace {
 
 using pgs::kAlphaMax;
@@ -90,8 +95,7 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
 struct Trace {
     uint64_t* mask;    // [pair_cap][NW]
     uint32_t* steps;   // [n_tiles][NW]
-    float* alpha;      // [entry_cap]
-    float* c_in;       // [3][entry_cap]
+    float4* entry;     // [entry_cap] (C_in r, g, b, alpha)
     uint32_t* count;   // [H*W]
     size_t entry_cap;
     uint32_t pair_cap;
@@ -102,14 +106,15 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
     int W, int H, int TX, int tile_offset, int n_tiles_total, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, float bg0, float bg1,
     float bg2, float* __restrict__ image, float* __restrict__ t_final,
-    uint32_t* __restrict__ n_contrib, Trace tr, uint32_t* __restrict__ flags) {
+    uint32_t* __restrict__ n_contrib, Trace tr, uint32_t* __restrict__ flags,
+    const uint32_t* __restrict__ order) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
     __shared__ float4 s_a[NT];
     __shared__ float4 s_b[NT];
     __shared__ float s_c[NT];
     __shared__ uint32_t s_steps;
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile % TX, ty = tile / TX;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = tx * TW + (t % TW), py = ty * TH + (t / TW);
@@ -158,7 +163,6 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
             if (rec) {
                 const uint64_t m = __ballot(contrib);
                 if (lane == 0) tr.mask[(size_t)(base + k) * NW + wv] = m;
-                if (contrib) tr.alpha[ebase + cursor + lane_rank(m)] = alpha;
                 cursor += __popcll(m);
                 cnt += contrib ? 1u : 0u;
                 steps = base + k - start + 1;
@@ -177,8 +181,11 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
     if (!rec) return;  // uniform for the block
     if (lane == 0) tr.steps[(size_t)gt * NW + wv] = steps;
 
-    // C_in fill: back to front over each wave's groups, splat colours staged
-    // in LDS batch by batch (the forward batches in reverse).
+    // Entry pass: back to front over each wave's groups with the splats
+    // re-staged in LDS batch by batch (the forward batches in reverse).  Each
+    // set lane re-evaluates alpha with the same arithmetic as above (same
+    // bits) and writes its entry (C_in, alpha) once, C_in being the colour
+    // accumulated behind the splat so far.
     if (t == 0) s_steps = 0;
     __syncthreads();
     if (lane == 0) atomicMax(&s_steps, steps);
@@ -191,11 +198,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
     for (int64_t lo = top; lo >= 0; lo -= NT) {
         const uint32_t hi = min((uint32_t)lo + NT, smax);
         __syncthreads();
-        if ((uint32_t)lo + t < hi) {
-            const uint32_t g = values[start + lo + t];
-            s_a[t] = make_float4(proj[(size_t)PGS_PROJ_R * n + g], proj[(size_t)PGS_PROJ_G * n + g],
-                                 proj[(size_t)PGS_PROJ_BLUE * n + g], 0.f);
-        }
+        if ((uint32_t)lo + t < hi) stage_splat(proj, n, values[start + lo + t], s_a, s_b, s_c, t);
         __syncthreads();
         const uint32_t whi = min(hi, steps);
         if (whi <= (uint32_t)lo) continue;
@@ -206,49 +209,18 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
             const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
             uint64_t any = __ballot(mv != 0ull);
             while (any) {
-                // up to kG groups (last first), all alpha loads issued first
-                constexpr int kG = 4;
-                int gi[kG];
-                uint64_t gm[kG];
-                uint32_t gc[kG];
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    gi[q] = 0;
-                    gm[q] = 0ull;
-                    gc[q] = cur;
-                    if (any) {
-                        const int i = 63 - __clzll(any);
-                        any &= ~(1ull << i);
-                        gi[q] = i;
-                        gm[q] = read_lane64(mv, i);
-                        cur -= __popcll(gm[q]);
-                        gc[q] = cur;
-                    }
-                }
-                float al[kG];
-                size_t ge[kG];
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    al[q] = 0.f;
-                    ge[q] = 0;
-                    if ((gm[q] >> lane) & 1ull) {
-                        ge[q] = ebase + gc[q] + lane_rank(gm[q]);
-                        al[q] = tr.alpha[ge[q]];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    if ((gm[q] >> lane) & 1ull) {
-                        const size_t e = ge[q];
-                        const float a = al[q];
-                        const float4 col = s_a[c0 + gi[q] - lo];
-                        tr.c_in[e] = a0;
-                        tr.c_in[tr.entry_cap + e] = a1;
-                        tr.c_in[2 * tr.entry_cap + e] = a2;
-                        a0 = a * col.x + (1.f - a) * a0;
-                        a1 = a * col.y + (1.f - a) * a1;
-                        a2 = a * col.z + (1.f - a) * a2;
-                    }
+                const int i = 63 - __clzll(any);
+                any &= ~(1ull << i);
+                const uint64_t m = read_lane64(mv, i);
+                cur -= __popcll(m);
+                if ((m >> lane) & 1ull) {
+                    const Splat s = load_splat(s_a, s_b, s_c, (int)(c0 + i - lo));
+                    float a = 0.f, gauss, dx, dy;
+                    splat_alpha(s, fpx, fpy, a, gauss, dx, dy);
+                    tr.entry[ebase + cur + lane_rank(m)] = make_float4(a0, a1, a2, a);
+                    a0 = a * s.r + (1.f - a) * a0;
+                    a1 = a * s.g + (1.f - a) * a1;
+                    a2 = a * s.b + (1.f - a) * a2;
                 }
             }
         }
@@ -316,7 +288,7 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
     int W, int H, int TX, int tile_offset, int n_tiles_total, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, Trace tr,
-    const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
+    const float* __restrict__ dl_dimage, float* __restrict__ grad2d, const uint32_t* __restrict__ order) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
     constexpr int BG = NT;
@@ -326,7 +298,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
     __shared__ uint32_t s_g[BG];
     __shared__ float s_acc[9][BG];
     __shared__ uint32_t s_steps;
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile % TX, ty = tile / TX;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = tx * TW + (t % TW), py = ty * TH + (t / TW);
@@ -369,7 +341,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
             while (any) {
                 // take up to kG groups and issue all their trace loads before
                 // any of them is consumed (memory-level parallelism per wave)
-                constexpr int kG = 4;
+                constexpr int kG = PGS_TRACE_GROUPS;
                 int gi[kG];
                 uint64_t gm[kG];
                 uint32_t gc[kG];
@@ -387,17 +359,11 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
                         cur += __popcll(gm[q]);
                     }
                 }
-                float al[kG], ci0[kG], ci1[kG], ci2[kG];
+                float4 ent[kG];
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
-                    al[q] = ci0[q] = ci1[q] = ci2[q] = 0.f;
-                    if ((gm[q] >> lane) & 1ull) {
-                        const size_t e = ebase + gc[q] + lane_rank(gm[q]);
-                        al[q] = tr.alpha[e];
-                        ci0[q] = tr.c_in[e];
-                        ci1[q] = tr.c_in[tr.entry_cap + e];
-                        ci2[q] = tr.c_in[2 * tr.entry_cap + e];
-                    }
+                    ent[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if ((gm[q] >> lane) & 1ull) ent[q] = tr.entry[ebase + gc[q] + lane_rank(gm[q])];
                 }
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
@@ -409,9 +375,10 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
                     if (mine) {
                         const Splat s = load_splat(s_a, s_b, s_c, jj);
                         const float dx = s.u - fpx, dy = s.v - fpy;
-                        const float a = al[q];
+                        const float a = ent[q].w;
                         // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
-                        const float dla = g0 * (s.r - ci0[q]) + g1 * (s.g - ci1[q]) + g2 * (s.b - ci2[q]);
+                        const float dla =
+                            g0 * (s.r - ent[q].x) + g1 * (s.g - ent[q].y) + g2 * (s.b - ent[q].z);
                         const bool clamped = a >= kAlphaMax;
                         chain_2d(s, dx, dy, a, clamped ? 0.f : a / s.o, clamped, dla, a * g0, a * g1,
                                  a * g2, v);
@@ -437,7 +404,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
     int W, int H, int TX, int tile_offset, int n_tiles_total, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, float bg0, float bg1,
     float bg2, const float* __restrict__ t_final, const uint32_t* __restrict__ n_contrib,
-    const float* __restrict__ dl_dimage, float* __restrict__ grad2d) {
+    const float* __restrict__ dl_dimage, float* __restrict__ grad2d, const uint32_t* __restrict__ order) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
     constexpr int BG = NT;
@@ -447,7 +414,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
     __shared__ uint32_t s_g[BG];
     __shared__ float s_acc[9][BG];
     __shared__ uint32_t s_last;
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile % TX, ty = tile / TX;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = tx * TW + (t % TW), py = ty * TH + (t / TW);
@@ -525,12 +492,12 @@ extern "C" size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int3
 }
 
 static pgs_status make_trace(const pgs_replay* c, int tile_w, int tile_h, Trace& tr, const char* who) {
-    PGS_REQUIRE(c->mask_dev && c->steps_dev && c->alpha_dev && c->c_in_dev && c->count_dev,
-                "%s: null trace pointer", who);
+    PGS_REQUIRE(c->mask_dev && c->steps_dev && c->entry_dev && c->count_dev, "%s: null trace pointer", who);
+    PGS_REQUIRE(((uintptr_t)c->entry_dev % 16) == 0, "%s: trace entries must be 16-byte aligned", who);
     PGS_REQUIRE(c->entry_capacity >= pgs_trace_entries(c->pair_capacity, tile_w, tile_h),
                 "%s: trace entry capacity %llu below %u pairs x %d pixels", who,
                 (unsigned long long)c->entry_capacity, c->pair_capacity, tile_w * tile_h);
-    tr = Trace{c->mask_dev, c->steps_dev, c->alpha_dev, c->c_in_dev, c->count_dev,
+    tr = Trace{c->mask_dev, c->steps_dev, reinterpret_cast<float4*>(c->entry_dev), c->count_dev,
                (size_t)c->entry_capacity, c->pair_capacity};
     return PGS_OK;
 }
@@ -540,7 +507,7 @@ extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile
                                      const uint32_t* ranges_dev, int32_t view_tile_offset,
                                      const float* bg_host, float* image_dev, float* t_final_dev,
                                      uint32_t* n_contrib_dev, const pgs_replay* cache,
-                                     uint32_t* flags_dev, void* stream) {
+                                     uint32_t* flags_dev, const uint32_t* tile_order_dev, void* stream) {
     PGS_REQUIRE(width > 0 && height > 0 && n >= 0 && view_tile_offset >= 0, "pgs_render_fwd: bad sizes");
     PGS_REQUIRE(tile_ok(tile_w, tile_h), "pgs_render_fwd: unsupported tile %dx%d", tile_w, tile_h);
     PGS_REQUIRE(bg_host && ranges_dev && image_dev && t_final_dev && n_contrib_dev,
@@ -560,12 +527,12 @@ extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile
         k_render_fwd<16, 16, true><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, n_tiles_total,
                                                           proj_dev, n, values_dev, ranges_dev, bg_host[0],
                                                           bg_host[1], bg_host[2], image_dev, t_final_dev,
-                                                          n_contrib_dev, tr, flags_dev);
+                                                          n_contrib_dev, tr, flags_dev, tile_order_dev);
     else
         k_render_fwd<16, 16, false><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, n_tiles_total,
                                                            proj_dev, n, values_dev, ranges_dev, bg_host[0],
                                                            bg_host[1], bg_host[2], image_dev, t_final_dev,
-                                                           n_contrib_dev, tr, flags_dev);
+                                                           n_contrib_dev, tr, flags_dev, tile_order_dev);
     PGS_CHECK_LAUNCH("pgs_render_fwd");
     return PGS_OK;
 }
@@ -575,7 +542,8 @@ extern "C" pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile
                                      const uint32_t* ranges_dev, int32_t view_tile_offset,
                                      const float* bg_host, const float* t_final_dev,
                                      const uint32_t* n_contrib_dev, const pgs_replay* cache,
-                                     const float* dl_dimage_dev, float* grad2d_dev, void* stream) {
+                                     const float* dl_dimage_dev, float* grad2d_dev,
+                                     const uint32_t* tile_order_dev, void* stream) {
     PGS_REQUIRE(width > 0 && height > 0 && n >= 0 && view_tile_offset >= 0, "pgs_render_bwd: bad sizes");
     PGS_REQUIRE(tile_ok(tile_w, tile_h), "pgs_render_bwd: unsupported tile %dx%d", tile_w, tile_h);
     PGS_REQUIRE(bg_host && ranges_dev && dl_dimage_dev, "pgs_render_bwd: null pointer");
@@ -591,14 +559,14 @@ extern "C" pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile
         if (st != PGS_OK) return st;
         k_render_bwd_cached<16, 16><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, n_tiles_total,
                                                            proj_dev, n, values_dev, ranges_dev, tr,
-                                                           dl_dimage_dev, grad2d_dev);
+                                                           dl_dimage_dev, grad2d_dev, tile_order_dev);
     } else {
         PGS_REQUIRE(t_final_dev && n_contrib_dev, "pgs_render_bwd: null pointer");
         k_render_bwd_recompute<16, 16><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset,
                                                               n_tiles_total, proj_dev, n, values_dev,
                                                               ranges_dev, bg_host[0], bg_host[1], bg_host[2],
                                                               t_final_dev, n_contrib_dev, dl_dimage_dev,
-                                                              grad2d_dev);
+                                                              grad2d_dev, tile_order_dev);
     }
     PGS_CHECK_LAUNCH("pgs_render_bwd");
     return PGS_OK;

@@ -26,7 +26,7 @@ def param_rows(sh_degree: int) -> int:
 class Rasterizer:
     def __init__(self, n: int, sh_degree: int, width: int, height: int, tile=(16, 16),
                  cached: bool = True, capacity: int | None = None,
-                 device="cuda"):
+                 device="cuda", ordered: bool = True):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.W, self.H = int(width), int(height)
@@ -49,6 +49,8 @@ class Rasterizer:
         self.t_final = torch.empty((self.H, self.W), dtype=torch.float32, device=d)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
         self.grad2d = torch.zeros((GRAD2D_FIELDS, n), dtype=torch.float32, device=d)
+        # heavy-first launch order of the tiles (scheduling only)
+        self.tile_order = torch.empty(self.n_tiles, dtype=torch.int32, device=d) if ordered else None
         self.capacity = 0
         self.trace = None
         self.nw = self.tw * self.th // 64
@@ -71,8 +73,7 @@ class Rasterizer:
             self.trace = dict(
                 mask=torch.empty((max(capacity, 1), self.nw), dtype=torch.int64, device=d),
                 steps=torch.empty((self.n_tiles, self.nw), dtype=torch.int32, device=d),
-                alpha=torch.empty(max(ents, 1), dtype=torch.float32, device=d),
-                c_in=torch.empty(3 * max(ents, 1), dtype=torch.float32, device=d),
+                entry=torch.empty((max(ents, 1), 4), dtype=torch.float32, device=d),
                 count=torch.empty(self.H * self.W, dtype=torch.int32, device=d),
                 entry_capacity=max(ents, 1), pair_capacity=capacity,
             )
@@ -93,13 +94,18 @@ class Rasterizer:
         n = self.n
         B.pgs_project(params, n, self.sh_degree, cam, self.tw, self.th, self.proj, self.radius,
                       self.rect, self.touched)
-        B.pgs_bin_sort(n, self.proj, self.rect, self.touched, self.TX, self.n_tiles, 0,
-                       self.capacity, self.keys, self.values, self.ranges, self.num_pairs,
-                       self.flags, self.workspace)
+        self.bin_sort()
         B.pgs_render_fwd(self.W, self.H, self.tw, self.th, self.proj, n, self.values, self.ranges,
                          0, bg, self.image, self.t_final, self.n_contrib,
-                         self.trace if self.cached else None, self.flags)
+                         self.trace if self.cached else None, self.flags, self.tile_order)
         return self.image
+
+    def bin_sort(self):
+        B.pgs_bin_sort(self.n, self.proj, self.rect, self.touched, self.TX, self.n_tiles, 0,
+                       self.capacity, self.keys, self.values, self.ranges, self.num_pairs,
+                       self.flags, self.workspace)
+        if self.tile_order is not None:
+            B.pgs_tile_order(self.ranges, self.n_tiles, 0, self.n_tiles, self.tile_order)
 
     def read_flags(self) -> int:
         return int(self.flags.item())
@@ -125,6 +131,6 @@ class Rasterizer:
             self.grad2d.zero_()
         B.pgs_render_bwd(self.W, self.H, self.tw, self.th, self.proj, self.n, self.values,
                          self.ranges, 0, bg, self.t_final, self.n_contrib,
-                         self.trace if self.cached else None, dl_dimage, self.grad2d)
+                         self.trace if self.cached else None, dl_dimage, self.grad2d, self.tile_order)
         B.pgs_project_bwd(params, self.n, self.sh_degree, cam, self.radius, self.grad2d, grads)
         return grads

@@ -52,7 +52,7 @@ class Trainer:
 
     def __init__(self, params: torch.Tensor, sh_degree: int, width: int, height: int,
                  cached: bool = True, lam: float = 0.2, extent: float = 1.0,
-                 tile=(16, 16)):
+                 tile=(16, 16), ordered: bool = True):
         self.params = params.contiguous()
         self.sh_degree = sh_degree
         self.F, self.n = self.params.shape
@@ -63,7 +63,7 @@ class Trainer:
         self.lr = learning_rates(sh_degree, extent)
         self.lam = lam
         self.W, self.H = width, height
-        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached)
+        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached, ordered=ordered)
         self.dl = torch.empty((3, height, width), dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = torch.empty(B.pgs_loss_workspace(width, height), dtype=torch.uint8, device=dev)
@@ -87,11 +87,10 @@ class Trainer:
         self._mark("start")
         B.pgs_project(self.params, n, self.sh_degree, cam, r.tw, r.th, r.proj, r.radius, r.rect, r.touched)
         self._mark("project")
-        B.pgs_bin_sort(n, r.proj, r.rect, r.touched, r.TX, r.n_tiles, 0, r.capacity, r.keys, r.values,
-                       r.ranges, r.num_pairs, r.flags, r.workspace)
+        r.bin_sort()
         self._mark("bin_sort")
         B.pgs_render_fwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.image, r.t_final,
-                         r.n_contrib, r.trace if r.cached else None, r.flags)
+                         r.n_contrib, r.trace if r.cached else None, r.flags, r.tile_order)
         self._mark("render_fwd")
         B.pgs_loss_l1_dssim(r.image, target, r.W, r.H, self.lam, self.loss, self.dl, self.loss_ws)
         self._mark("loss")
@@ -99,7 +98,7 @@ class Trainer:
         r.grad2d.zero_()
         self._mark("zero")
         B.pgs_render_bwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.t_final,
-                         r.n_contrib, r.trace if r.cached else None, self.dl, r.grad2d)
+                         r.n_contrib, r.trace if r.cached else None, self.dl, r.grad2d, r.tile_order)
         self._mark("render_bwd")
         B.pgs_project_bwd(self.params, n, self.sh_degree, cam, r.radius, r.grad2d, self.grads)
         self._mark("project_bwd")

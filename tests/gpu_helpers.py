@@ -97,7 +97,6 @@ def trace_entries(out, cam, x, y, tile=(16, 16)):
     start, end = (int(v) for v in out["ranges"][:, t])
     steps = int(R.trace["steps"][t, w].item())
     masks = R.trace["mask"][start:start + steps, w].cpu().numpy().view(np.uint64)
-    cap = R.trace["entry_capacity"]
     ebase = nt * start + 64 * (end - start) * w
     cursor, ents = 0, []
     for j, m in enumerate(masks):
@@ -107,6 +106,5 @@ def trace_entries(out, cam, x, y, tile=(16, 16)):
         cursor += bin(m).count("1")
     assert len(ents) == int(out["count"][y, x])
     e = torch.as_tensor([q for _, q in ents], dtype=torch.int64, device=R.device)
-    al = R.trace["alpha"][e].cpu().numpy()
-    cin = torch.stack([R.trace["c_in"][c * cap + e] for c in range(3)], 1).cpu().numpy()
-    return np.asarray([i for i, _ in ents], np.int64), al, cin
+    rec = R.trace["entry"][e].cpu().numpy().reshape(-1, 4)
+    return np.asarray([i for i, _ in ents], np.int64), rec[:, 3], rec[:, :3]

@@ -52,7 +52,8 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert lib.pgs_adam_step(None, None, None, None, 65, 10, lr, 1, 0.9, 0.999, 1e-15, None) == \
         _lib.PGS_ERR_INVALID_ARG
     bg = (ctypes.c_float * 3)(0, 0, 0)
-    st = lib.pgs_render_fwd(64, 48, 8, 8, None, 0, None, None, 0, bg, None, None, None, None, None, None)
+    st = lib.pgs_render_fwd(64, 48, 8, 8, None, 0, None, None, 0, bg, None, None, None, None, None, None,
+                            None)
     assert st == _lib.PGS_ERR_INVALID_ARG and b"unsupported tile" in lib.pgs_last_error()
 
 

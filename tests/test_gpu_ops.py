@@ -166,8 +166,7 @@ def test_trace_poison_counter_reset_is_exact():
             R.forward_checked(torch.as_tensor(P_other, device=DEV), cam)
         else:
             fill = float("nan") if mode == "nan" else 0.0
-            R.trace["alpha"].fill_(fill)
-            R.trace["c_in"].fill_(fill)
+            R.trace["entry"].fill_(fill)
             R.trace["mask"].fill_(-1 if mode == "nan" else 0)
         R.forward_checked(params, cam)
         assert R.capacity == 40000          # no reallocation wiped the poison
