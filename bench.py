@@ -37,12 +37,13 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1440)
     ap.add_argument("--views", type=int, default=0, help="training views to render targets for (0: all 52)")
+    ap.add_argument("--no-psnr", action="store_true", help="skip the 500-step PSNR runs")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 4 views, 4 steps, one 1 GiB stream copy")
     args = ap.parse_args()
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
-        args.no_compare = args.no_cpu_baseline = True
+        args.no_compare = args.no_cpu_baseline = args.no_psnr = True
     return args
 
 
@@ -125,6 +126,24 @@ def render_fwd_bytes(st, cached):
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def psnr_runs(wl, order, iters=500, at=(0, 100, 500)):
+    """Held-out PSNR after `iters` training steps (the same step as timed
+    above, cached backward) from each available initialisation."""
+    import torch
+    from paper_2601_17354_amd.train import Trainer, seed_pca, train
+    inits = {"plain_pca": wl["params0"]}
+    pts, col = wl["cloud"]
+    inits["isotropic"] = seed_pca(pts, col, r_normal=1.0)
+    out = {}
+    for name, p0 in inits.items():
+        tr = Trainer(p0.clone(), 0, wl["width"], wl["height"], cached=True, lam=0.2, extent=4.5)
+        hist = train(tr, wl["cams"], wl["targets"], order, iters, eval_ids=wl["test_ids"], eval_at=at)
+        out[name] = {str(k): round(v, 3) for k, v in hist.items()}
+        del tr
+        torch.cuda.empty_cache()
+    return out
 
 
 def achievable_bandwidth(nbytes=1 << 30, reps=10):
@@ -215,8 +234,10 @@ def main():
     order = [int(i) for i in rng.permutation(train_ids)]
     if args.views:
         order = order[:args.views]
+        args.no_psnr = True
+    test_ids = [i for i in range(n_cams) if i % 8 == 0]
     wl = training_workload(n_train=args.gaussians, width=args.width, height=args.height,
-                           target_cams=sorted(order))
+                           target_cams=sorted(order) + ([] if args.no_psnr else test_ids))
     log(f"workload ready in {time.perf_counter() - t:.1f} s")
     cached = args.backward == "cached"
     res = run_variant(wl, cached, args.steps, args.warmup, order)
@@ -267,6 +288,10 @@ def main():
         out["other_backward"] = {"backward": "recompute" if cached else "cached",
                                  "ms_per_step": other["ms"], "iters_per_s": 1000.0 / other["ms"],
                                  "kernels_ms": other["kernels"], "trace_gb": other["stats"]["trace_gb"]}
+    if not args.no_psnr:
+        log("held-out PSNR after 500 training steps per initialisation")
+        out["psnr_held_out"] = psnr_runs(wl, order)
+        log(f"psnr {out['psnr_held_out']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.width, args.height, args.gaussians)

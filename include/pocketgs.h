@@ -272,6 +272,15 @@ pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, int32_t wid
                              void* stream);
 
 /*
+ * pgs_psnr - evaluation metric (Sec. Experiments, "Datasets and metrics"):
+ * both images clamped to [0, 1], MSE over 3HW, PSNR = 10 log10(1 / MSE).
+ *   out_dev        out, two floats: MSE, PSNR (+inf when MSE = 0)
+ *   workspace_dev  >= 4096 bytes (pgs_loss_workspace also suffices)
+ */
+pgs_status pgs_psnr(const float* x_dev, const float* y_dev, int32_t width, int32_t height,
+                    float* out_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/*
  * pgs_adam_step - Adam (Kingma & Ba) on the canonical layout, moments aligned
  * with their parameters (index-mapping subsection):
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

@@ -58,6 +58,7 @@ SIGNATURES = {
     "pgs_loss_workspace": (c_size_t, [c_int32, c_int32]),
     "pgs_loss_l1_dssim": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_float, c_void_p,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pgs_psnr": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "pgs_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                 POINTER(c_float), c_int32, c_float, c_float, c_float, c_void_p]),
     "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),

@@ -154,6 +154,12 @@ def pgs_loss_l1_dssim(x, y, width, height, lam, loss, dl_dx, workspace, stream=N
                                 _stream(stream)), "pgs_loss_l1_dssim")
 
 
+def pgs_psnr(x, y, width, height, out, workspace, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_psnr(_ptr(x, F32), _ptr(y, F32), width, height, _ptr(out, F32),
+                       _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)), "pgs_psnr")
+
+
 def pgs_adam_step(params, grads, m, v, rows, n, lr, step, beta1, beta2, eps, stream=None):
     lib = _lib.load()
     lr_arr = (ctypes.c_float * rows)(*[float(x) for x in lr])

@@ -210,6 +210,31 @@ __global__ __launch_bounds__(kFinalThreads) void k_loss_final(const float* __res
 
 constexpr int kL1Blocks = 1024;
 
+// Squared error of the two images clamped to [0, 1], per-block partials.
+__global__ __launch_bounds__(256) void k_sq_err(const float* __restrict__ x, const float* __restrict__ y,
+                                                size_t N, float* __restrict__ part) {
+    __shared__ float red[4];
+    float s = 0.f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const float d = fminf(fmaxf(x[i], 0.f), 1.f) - fminf(fmaxf(y[i], 0.f), 1.f);
+        s += d * d;
+    }
+    const float tot = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// out[0] = MSE, out[1] = 10 log10(1 / MSE) (infinite for identical images).
+__global__ __launch_bounds__(kFinalThreads) void k_psnr_final(const float* __restrict__ part, int np,
+                                                              double invN, float* __restrict__ out) {
+    __shared__ float red[kFinalThreads / 64];
+    const float sse = block_sum_1024(strided_sum(part, np), red);
+    if (threadIdx.x == 0) {
+        const double mse = (double)sse * invN;
+        out[0] = (float)mse;
+        out[1] = mse > 0.0 ? (float)(10.0 * log10(1.0 / mse)) : INFINITY;
+    }
+}
+
 inline int ssim_blocks(int W, int H) { return ((W + kT - 1) / kT) * ((H + kT - 1) / kT) * 3; }
 
 inline size_t part_bytes(int W, int H) {
@@ -218,6 +243,20 @@ inline size_t part_bytes(int W, int H) {
 }
 
 }  // namespace
+
+extern "C" pgs_status pgs_psnr(const float* x_dev, const float* y_dev, int32_t width, int32_t height,
+                               float* out_dev, void* workspace_dev, size_t workspace_bytes, void* stream) {
+    PGS_REQUIRE(width > 0 && height > 0, "pgs_psnr: bad size");
+    PGS_REQUIRE(x_dev && y_dev && out_dev && workspace_dev, "pgs_psnr: null pointer");
+    PGS_REQUIRE(workspace_bytes >= kL1Blocks * sizeof(float), "pgs_psnr: workspace too small");
+    hipStream_t s = pgs::as_stream(stream);
+    const size_t N = (size_t)3 * width * height;
+    float* part = static_cast<float*>(workspace_dev);
+    k_sq_err<<<kL1Blocks, 256, 0, s>>>(x_dev, y_dev, N, part);
+    k_psnr_final<<<1, kFinalThreads, 0, s>>>(part, kL1Blocks, 1.0 / (double)N, out_dev);
+    PGS_CHECK_LAUNCH("pgs_psnr");
+    return PGS_OK;
+}
 
 extern "C" size_t pgs_loss_workspace(int32_t width, int32_t height) {
     if (width <= 0 || height <= 0) return 256;

@@ -81,7 +81,11 @@ class Trainer:
             ev.record()
             self.events.append((name, ev))
 
-    def step(self, cam: dict, target: torch.Tensor, bg=(0.0, 0.0, 0.0), adam: bool = True):
+    def step(self, cam: dict, target: torch.Tensor, bg=(0.0, 0.0, 0.0), adam: bool = True,
+             check: bool = False):
+        """One training step.  check=True reads the device flags after the
+        forward (one synchronisation) and, on an overflow, grows the buffers
+        and redoes the forward before anything is updated."""
         r = self.rast
         n = self.n
         self._mark("start")
@@ -92,6 +96,8 @@ class Trainer:
         B.pgs_render_fwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.image, r.t_final,
                          r.n_contrib, r.trace if r.cached else None, r.flags, r.tile_order)
         self._mark("render_fwd")
+        if check and r.read_flags():
+            r.forward_checked(self.params, cam, bg)
         B.pgs_loss_l1_dssim(r.image, target, r.W, r.H, self.lam, self.loss, self.dl, self.loss_ws)
         self._mark("loss")
         self.grads.zero_()
@@ -108,3 +114,40 @@ class Trainer:
                             BETA1, BETA2, EPS)
             self._mark("adam")
         return self.loss
+
+
+class Evaluator:
+    """PSNR of rendered views against targets (evaluation row of the method's
+    experiments), through pgs_render_fwd and pgs_psnr."""
+
+    def __init__(self, n: int, sh_degree: int, width: int, height: int, device="cuda"):
+        self.rast = Rasterizer(n, sh_degree, width, height, cached=False, device=device)
+        self.out = torch.zeros(2, dtype=torch.float32, device=device)
+        self.ws = torch.empty(B.pgs_loss_workspace(width, height), dtype=torch.uint8, device=device)
+
+    def psnr(self, params: torch.Tensor, cam: dict, target: torch.Tensor, bg=(0.0, 0.0, 0.0)) -> float:
+        self.rast.forward_checked(params, cam, bg)
+        B.pgs_psnr(self.rast.image, target, self.rast.W, self.rast.H, self.out, self.ws)
+        return float(self.out[1].item())
+
+    def mean_psnr(self, params, cams, targets, ids, bg=(0.0, 0.0, 0.0)) -> float:
+        return float(np.mean([self.psnr(params, cams[i], targets[i], bg) for i in ids]))
+
+
+def train(trainer: Trainer, cams, targets, order, iters: int, eval_ids=(), eval_at=(),
+          bg=(0.0, 0.0, 0.0), log=None):
+    """Runs `iters` steps cycling the training views in `order` (checking the
+    overflow flags every step) and returns {iteration: mean held-out PSNR}
+    for every iteration listed in eval_at (0 = before training)."""
+    ev = Evaluator(trainer.n, trainer.sh_degree, trainer.W, trainer.H, device=trainer.params.device)
+    hist = {}
+    if 0 in eval_at:
+        hist[0] = ev.mean_psnr(trainer.params, cams, targets, eval_ids, bg)
+    for it in range(1, iters + 1):
+        cid = order[(it - 1) % len(order)]
+        trainer.step(cams[cid], targets[cid], bg, check=True)
+        if it in eval_at:
+            hist[it] = ev.mean_psnr(trainer.params, cams, targets, eval_ids, bg)
+            if log:
+                log(f"iter {it}: held-out PSNR {hist[it]:.3f} dB, loss {float(trainer.loss.item()):.5f}")
+    return hist

@@ -49,4 +49,4 @@ def training_workload(n_train=300_000, n_gt=500_000, width=1920, height=1440, sc
     params0 = seed_pca(P, C)
     torch.cuda.synchronize()
     return dict(params0=params0, cams=cams, train_ids=train_ids, test_ids=test_ids,
-                targets=targets, scene=scene, width=width, height=height)
+                targets=targets, scene=scene, width=width, height=height, cloud=(P, C))
