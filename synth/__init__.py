@@ -37,4 +37,5 @@ from .gen import (  # noqa: F401
     surface_gaussians,
     noisy_cloud,
     random_image,
+    random_normal,
 )

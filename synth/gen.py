@@ -63,6 +63,13 @@ def random_image(seed, height, width, lo=0.0, hi=1.0) -> np.ndarray:
     return rng.uniform(lo, hi, (3, height, width)).astype(np.float32)
 
 
+def random_normal(seed, shape, std=1.0) -> np.ndarray:
+    """float32 array of the given shape, entries N(0, std^2) drawn in C order
+    (network weights, feature rows and output gradients of tests)."""
+    rng = np.random.default_rng(seed)
+    return (std * rng.standard_normal(shape)).astype(np.float32)
+
+
 def cfg1_inputs(seed=0, n=1000, width=128, height=128, focal=128.0):
     """Small parity workload.
 
