@@ -321,6 +321,101 @@ pgs_status pgs_pca_seed(const float* points_dev, const float* colours_dev, int32
                         float r_normal, float* params_dev, void* stream);
 
 /*
+ * Learned seeding network.  Not part of PocketGS: a network that corrects
+ * the disc-like seed of pgs_pca_seed (Sec. "Disc-Like Covariance Seeding")
+ * from the point's neighbourhood.  Layers 64 -> 64 -> 64 -> 64 -> 8 with
+ * exact-erf GELU after each hidden layer; every product multiplies bfloat16
+ * operands (float32 values rounded to nearest, ties to even) and
+ * accumulates in float32.  Weights: one float32 vector of
+ * pgs_mlp_weight_count() = 13000 values, [W1 (64 x 64, row = output), b1,
+ * W2, b2, W3, b3, W4 (8 x 64), b4].  Outputs per row: (d log-scale x3,
+ * q_out (w, x, y, z), d logit).
+ */
+int32_t pgs_mlp_weight_count(void);
+
+/*
+ * pgs_mlp_features - network inputs and base seed of every point.  Frame
+ * R = [e1 e2 e3] (columns): eigenvectors of C_i for its largest and middle
+ * eigenvalue, each signed so that sum_k ((p_k - p_i) . e)^3 >= 0 over the
+ * 16 neighbours, e3 = e1 x e2.
+ *   points_dev  [3][m] float32; nbr_dev/d2_dev pgs_knn output with k >= 16
+ *   x_dev       out [m][64] float32: (p_k - p_i) in the frame / s_t for the
+ *               16 neighbours (neighbour-major), R^T C_i R / s_t^2
+ *               (row-major), 7 zeros
+ *   base_dev    out [m][16] float32: R row-major (9), log-scales
+ *               (log s_t, log s_t, log(r_normal s_t)) (3), quaternion of R
+ *               (w, x, y, z) (4)
+ */
+pgs_status pgs_mlp_features(const float* points_dev, int32_t m, const int32_t* nbr_dev,
+                            const double* d2_dev, int32_t k, float r_normal, float* x_dev,
+                            float* base_dev, void* stream);
+
+/*
+ * pgs_mlp_forward - y = network(x) for m >= 0 rows.
+ *   weights_dev  [13000] float32
+ *   x_dev        [m][64] float32, 16-byte aligned
+ *   y_dev        out [m][8] float32, 16-byte aligned
+ */
+pgs_status pgs_mlp_forward(const float* weights_dev, const float* x_dev, int32_t m, float* y_dev,
+                           void* stream);
+
+/*
+ * pgs_mlp_backward - dweights = d(sum(dy * network(x)))/dweights, the
+ * forward recomputed inside.  Weight gradients multiply the bfloat16-rounded
+ * output gradient and activation; bias gradients sum the float32 output
+ * gradient.  Deterministic for a given m.  dweights_dev is overwritten
+ * (zeros for m = 0).
+ *   dy_dev        [m][8] float32
+ *   workspace     >= pgs_mlp_backward_workspace(m) bytes (per-block partial
+ *                 gradients, at most 256 x 13000 floats)
+ */
+size_t pgs_mlp_backward_workspace(int32_t m);
+pgs_status pgs_mlp_backward(const float* weights_dev, const float* x_dev, int32_t m,
+                            const float* dy_dev, float* dweights_dev, void* workspace_dev,
+                            size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_seed_targets - training targets from trained canonical parameters
+ * [F][n] (rows 3..5 log-scales, 6..9 quaternion, 10 opacity logit):
+ * log S = R diag(2 s) R^T, the matrix logarithm of the covariance.
+ *   targets_dev  out [n][8]: logS00, logS11, logS22, logS01, logS02, logS12,
+ *                logit, 0
+ */
+pgs_status pgs_seed_targets(const float* params_dev, int32_t n, float* targets_dev, void* stream);
+
+/*
+ * pgs_seed_loss - scale * sum over rows of ||log S_hat - log S*||_F^2 +
+ * (logit(0.1) + y[7] - logit*)^2 with q = y[3:7]/|y[3:7]|,
+ * R_hat = R_base R(q), log S_hat = R_hat diag(2 (base log-scales + y[0:3]))
+ * R_hat^T; float64 inside.  scale = 1/m gives the mean.
+ *   y_dev [m][8], base_dev [m][16] (pgs_mlp_features), target_dev [m][8]
+ *   loss_dev   out [1] float32
+ *   dy_dev     out [m][8] float32 gradient of the scaled loss, or NULL
+ *   workspace  >= pgs_seed_loss_workspace(m) bytes
+ */
+size_t pgs_seed_loss_workspace(int32_t m);
+pgs_status pgs_seed_loss(const float* y_dev, const float* base_dev, const float* target_dev,
+                         int32_t m, float scale, float* loss_dev, float* dy_dev, void* workspace_dev,
+                         size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_seed_apply - canonical SH-degree-0 parameters from network outputs:
+ * log-scales = base + y[0:3], quaternion = q_base (x) y[3:7]/|y[3:7]|
+ * (Hamilton product), logit = logit(0.1) + y[7]; means and colours from
+ * pca_params_dev.  A row falls back to its pca_params_dev column when y is
+ * not finite, |y[3:7]| < 1e-6, some |y[k]| > 2 (k < 3), or the axis of the
+ * smallest predicted scale is more than 60 degrees from e3.
+ *   pca_params_dev  [14][m] (pgs_pca_seed output); params_dev out [14][m],
+ *                   may equal pca_params_dev
+ *   fallback_dev    out [m] uint8 (1 = fell back), or NULL
+ *   fallback_count_dev  device counter incremented by the number of
+ *                   fallbacks (the caller clears it), or NULL
+ */
+pgs_status pgs_seed_apply(const float* y_dev, const float* base_dev, const float* pca_params_dev,
+                          int32_t m, float* params_dev, uint8_t* fallback_dev,
+                          uint32_t* fallback_count_dev, void* stream);
+
+/*
  * pgs_stream_copy - plain streaming copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) from src_dev to dst_dev.  A measurement aid, not
  * part of the method: it defines the achievable HBM bandwidth the kernels are

@@ -64,6 +64,19 @@ SIGNATURES = {
     "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pgs_pca_seed": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float,
                                c_void_p, c_void_p]),
+    "pgs_mlp_weight_count": (c_int32, []),
+    "pgs_mlp_features": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float, c_void_p,
+                                   c_void_p, c_void_p]),
+    "pgs_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "pgs_mlp_backward_workspace": (c_size_t, [c_int32]),
+    "pgs_mlp_backward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                                   c_void_p]),
+    "pgs_seed_targets": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "pgs_seed_loss_workspace": (c_size_t, [c_int32]),
+    "pgs_seed_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_float, c_void_p, c_void_p,
+                                c_void_p, c_size_t, c_void_p]),
+    "pgs_seed_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                 c_void_p]),
     "pgs_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 

@@ -184,3 +184,87 @@ def pgs_pca_seed(points, colours, m, nbr, d2, k, r_normal, params, stream=None):
     check(lib.pgs_pca_seed(_ptr(points, F32), _ptr(colours, F32), m, _ptr(nbr, I32),
                            _ptr(d2, torch.float64), k, float(r_normal), _ptr(params, F32),
                            _stream(stream)), "pgs_pca_seed")
+
+
+def _need(t, count, what):
+    if t is not None and t.numel() < count:
+        raise ValueError(f"{what}: {t.numel()} elements, need {count}")
+
+
+N_MLP_WEIGHTS = 13000
+
+
+def pgs_mlp_weight_count():
+    return int(_lib.load().pgs_mlp_weight_count())
+
+
+def pgs_mlp_features(points, m, nbr, d2, k, r_normal, x, base, stream=None):
+    lib = _lib.load()
+    _need(points, 3 * m, "points")
+    _need(nbr, k * m, "nbr")
+    _need(d2, k * m, "d2")
+    _need(x, 64 * m, "x")
+    _need(base, 16 * m, "base")
+    check(lib.pgs_mlp_features(_ptr(points, F32), m, _ptr(nbr, I32), _ptr(d2, torch.float64), k,
+                               float(r_normal), _ptr(x, F32), _ptr(base, F32), _stream(stream)),
+          "pgs_mlp_features")
+
+
+def pgs_mlp_forward(weights, x, m, y, stream=None):
+    lib = _lib.load()
+    _need(weights, N_MLP_WEIGHTS, "weights")
+    _need(x, 64 * m, "x")
+    _need(y, 8 * m, "y")
+    check(lib.pgs_mlp_forward(_ptr(weights, F32), _ptr(x, F32), m, _ptr(y, F32), _stream(stream)),
+          "pgs_mlp_forward")
+
+
+def pgs_mlp_backward_workspace(m):
+    return int(_lib.load().pgs_mlp_backward_workspace(m))
+
+
+def pgs_mlp_backward(weights, x, m, dy, dweights, workspace, stream=None):
+    lib = _lib.load()
+    _need(weights, N_MLP_WEIGHTS, "weights")
+    _need(dweights, N_MLP_WEIGHTS, "dweights")
+    _need(x, 64 * m, "x")
+    _need(dy, 8 * m, "dy")
+    check(lib.pgs_mlp_backward(_ptr(weights, F32), _ptr(x, F32), m, _ptr(dy, F32), _ptr(dweights, F32),
+                               _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)),
+          "pgs_mlp_backward")
+
+
+def pgs_seed_targets(params, n, targets, stream=None):
+    lib = _lib.load()
+    _need(params, 11 * n, "params")
+    _need(targets, 8 * n, "targets")
+    check(lib.pgs_seed_targets(_ptr(params, F32), n, _ptr(targets, F32), _stream(stream)), "pgs_seed_targets")
+
+
+def pgs_seed_loss_workspace(m):
+    return int(_lib.load().pgs_seed_loss_workspace(m))
+
+
+def pgs_seed_loss(y, base, target, m, scale, loss, dy, workspace, stream=None):
+    lib = _lib.load()
+    _need(y, 8 * m, "y")
+    _need(base, 16 * m, "base")
+    _need(target, 8 * m, "target")
+    _need(dy, 8 * m, "dy")
+    _need(loss, 1, "loss")
+    check(lib.pgs_seed_loss(_ptr(y, F32), _ptr(base, F32), _ptr(target, F32), m, float(scale),
+                            _ptr(loss, F32), _ptr(dy, F32), _ptr(workspace, torch.uint8), workspace.numel(),
+                            _stream(stream)), "pgs_seed_loss")
+
+
+def pgs_seed_apply(y, base, pca_params, m, params, fallback=None, fallback_count=None, stream=None):
+    lib = _lib.load()
+    _need(y, 8 * m, "y")
+    _need(base, 16 * m, "base")
+    _need(pca_params, 14 * m, "pca_params")
+    _need(params, 14 * m, "params")
+    _need(fallback, m, "fallback")
+    _need(fallback_count, 1, "fallback_count")
+    check(lib.pgs_seed_apply(_ptr(y, F32), _ptr(base, F32), _ptr(pca_params, F32), m, _ptr(params, F32),
+                             _ptr(fallback, torch.uint8), _ptr(fallback_count, I32), _stream(stream)),
+          "pgs_seed_apply")

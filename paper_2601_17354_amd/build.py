@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpocketgs.so")
 
 SOURCES = ["api.hip", "project.hip", "binning.hip", "render.hip", "loss.hip", "adam.hip", "seed.hip",
-           "probe.hip"]
+           "mlp.hip", "probe.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

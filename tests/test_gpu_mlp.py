@@ -1,0 +1,308 @@
+"""GPU parity of the learned-seeding kernels (features, bfloat16 network
+forward/backward, targets, seed loss, seed application) against the oracle.
+
+Network tolerance.  Both sides round the same operands to bfloat16 at the
+same points; they differ by float32 versus float64 accumulation (about
+1e-7 relative) and by the rare operand that lies so close to a bfloat16
+rounding boundary that this difference flips it, which moves one term of
+one sum by one bfloat16 ulp, 2^-8 of the term.  Checks:
+  * every element: |x - y| <= 2^-8 (|y| + max|y|) per block;
+  * the relative RMS difference ||x - y|| / ||y|| <= 2.5e-4: flips of a
+    fraction p of the operands give about sqrt(p) 2^-8 (p < 1e-3 gives
+    < 1.3e-4), while a rounding step missing or added on one side perturbs
+    every term by up to 2^-9 and gives about 2^-9/sqrt(3) = 1.1e-3;
+  * network outputs (few roundings per output): at least 99% also within
+    the float32 bound 1e-5 (the same rounding decisions)."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_helpers import assert_block_close, say
+from oracle import mlp
+from oracle import seed as o_seed
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+MLP_TOL = 2.0 ** -8
+MLP_CLOSE = 1e-5
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+MLP_RMS = 2.5e-4
+
+
+def _compare_net(got, want, what, outputs=False):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    assert_block_close(got, want, MLP_TOL, what=what)
+    scale = np.abs(want).max()
+    close = np.abs(got - want) <= MLP_CLOSE * (np.abs(want) + scale)
+    frac = close.mean()
+    rms = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    say(f"  {what}: max |d|/scale {np.abs(got - want).max() / max(scale, 1e-300):.2e}, "
+        f"rel rms {rms:.2e}, {100 * frac:.3f}% within {MLP_CLOSE}")
+    assert rms <= MLP_RMS, what
+    if outputs:
+        assert frac >= 0.99, what
+
+
+def _gpu_forward(w, X):
+    from paper_2601_17354_amd import binding as B
+    y = torch.full((max(1, X.shape[0]), 8), float("nan"), device=DEV)
+    B.pgs_mlp_forward(_dev(w), _dev(X), X.shape[0], y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()[:X.shape[0]]
+
+
+def _gpu_backward(w, X, dY):
+    from paper_2601_17354_amd import binding as B
+    m = X.shape[0]
+    g = torch.full((mlp.N_WEIGHTS,), 7.0, device=DEV)
+    ws = torch.empty(max(8, B.pgs_mlp_backward_workspace(m)), dtype=torch.uint8, device=DEV)
+    B.pgs_mlp_backward(_dev(w), _dev(X.reshape(-1, 64)), m, _dev(dY.reshape(-1, 8)), g, ws)
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
+
+
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 1000])
+def test_mlp_forward_matches_oracle(m):
+    say(f"mlp forward m={m}")
+    w = synth.random_normal(30, mlp.N_WEIGHTS, 0.2)
+    X = synth.random_normal(31 + m, (m, 64))
+    got = _gpu_forward(w, X)
+    want, _ = mlp.forward(w, X, emulate=True)
+    _compare_net(got, want, f"y m={m}", outputs=True)
+
+
+def test_mlp_forward_full_size_sampled_rows():
+    # 200k rows (the point count of the learned-seeding workload) in the
+    # launch used for seeding; rows are independent, so sampled rows are
+    # checked one by one
+    m = 200_000
+    say(f"mlp forward m={m} sampled")
+    w = synth.random_normal(32, mlp.N_WEIGHTS, 0.2)
+    X = synth.random_normal(33, (m, 64))
+    got = _gpu_forward(w, X)
+    rows = np.unique(np.concatenate([np.random.default_rng(34).integers(0, m, 600), [0, m - 1]]))
+    want, _ = mlp.forward(w, X[rows], emulate=True)
+    _compare_net(got[rows], want, "y sampled", outputs=True)
+
+
+def _split(g):
+    out, off = [], 0
+    for s in mlp.SHAPES:
+        k = int(np.prod(s))
+        out.append(g[off:off + k])
+        off += k
+    return out
+
+
+@pytest.mark.parametrize("m", [1, 65, 1000, 20000])
+def test_mlp_backward_matches_oracle(m):
+    say(f"mlp backward m={m}")
+    w = synth.random_normal(40, mlp.N_WEIGHTS, 0.2)
+    X = synth.random_normal(41 + m, (m, 64))
+    dY = synth.random_normal(42 + m, (m, 8))
+    got = _gpu_backward(w, X, dY)
+    _, cache = mlp.forward(w, X, emulate=True)
+    want = mlp.backward(w, cache, dY, emulate=True)
+    for k, (a, b) in enumerate(zip(_split(got), _split(want))):
+        _compare_net(a, b, f"grad block {k} m={m}")
+
+
+def test_mlp_backward_empty_and_deterministic():
+    from paper_2601_17354_amd import binding as B
+    w = synth.random_normal(43, mlp.N_WEIGHTS, 0.2)
+    g = torch.full((mlp.N_WEIGHTS,), 7.0, device=DEV)
+    x = torch.zeros((1, 64), device=DEV)
+    ws = torch.empty(8, dtype=torch.uint8, device=DEV)
+    B.pgs_mlp_backward(_dev(w), x, 0, torch.zeros((1, 8), device=DEV), g, ws)
+    torch.cuda.synchronize()
+    assert (g.cpu().numpy() == 0).all()
+    X = synth.random_normal(44, (5000, 64))
+    dY = synth.random_normal(45, (5000, 8))
+    a = _gpu_backward(w, X, dY)
+    b = _gpu_backward(w, X, dY)
+    np.testing.assert_array_equal(a, b)
+
+
+def _cloud(seed, n):
+    scene = synth.spheres_planes_scene(seed)
+    pts, col = synth.noisy_cloud(scene, n, seed=seed + 7)
+    return pts, col
+
+
+def _gpu_features(pts):
+    from paper_2601_17354_amd import seed_mlp
+    P = _dev(pts.T)
+    nbr, d2 = seed_mlp.neighbourhoods(P)
+    x, base = seed_mlp.features(P, nbr, d2)
+    torch.cuda.synchronize()
+    return P, nbr, d2, x, base
+
+
+def test_features_match_oracle():
+    pts, _ = _cloud(3, 6000)
+    say("features m=6000")
+    _, _, _, x, base = _gpu_features(pts)
+    x, base = x.cpu().numpy(), base.cpu().numpy()
+    q = np.unique(np.concatenate([np.random.default_rng(50).integers(0, len(pts), 150), [0, len(pts) - 1]]))
+    nbr, d2 = o_seed.knn(pts, q)
+    X, R, qb, logs, mg = mlp.features(pts, q, nbr, d2)
+    ok = np.array([g["gap12"] > 1e-5 and g["gap01"] > 1e-5 and g["m3"] > 1e-6 for g in mg])
+    say(f"  {ok.sum()} of {len(q)} rows away from eigen/sign ties")
+    assert ok.mean() > 0.9
+    assert_block_close(x[q][ok][:, :48], X[ok][:, :48], 1e-5, what="offsets")
+    assert_block_close(x[q][ok][:, 48:57], X[ok][:, 48:57], 1e-5, what="frame covariance")
+    assert (x[:, 57:] == 0).all()
+    assert_block_close(base[q][ok][:, :9], R[ok].reshape(-1, 9), 1e-5, what="frame")
+    assert_block_close(base[q][ok][:, 9:12], logs[ok], 1e-6, what="log-scales")
+    for j in np.flatnonzero(ok):
+        np.testing.assert_allclose(mlp.rot_of_quat(base[q[j], 12:16]), R[j], atol=1e-5)
+
+
+def test_seed_targets_match_oracle():
+    from paper_2601_17354_amd import binding as B
+    rng = np.random.default_rng(51)
+    n = 3000
+    P = np.zeros((14, n), np.float32)
+    P[3:6] = rng.normal(size=(3, n)) - 3
+    P[6:10] = rng.normal(size=(4, n))
+    P[10] = rng.normal(size=n)
+    out = torch.zeros((n, 8), device=DEV)
+    B.pgs_seed_targets(_dev(P), n, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    M, lg = mlp.targets(P, range(n))
+    want = np.stack([M[:, 0, 0], M[:, 1, 1], M[:, 2, 2], M[:, 0, 1], M[:, 0, 2], M[:, 1, 2], lg], 1)
+    assert_block_close(got[:, :7], want, 1e-6, what="targets")
+
+
+def _loss_inputs(seed, m):
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(seed)
+    R = Rotation.random(m, random_state=seed).as_matrix()
+    base = np.zeros((m, 16), np.float32)
+    base[:, :9] = R.reshape(m, 9)
+    base[:, 9:12] = rng.normal(size=(m, 3)) - 3
+    y = (rng.normal(size=(m, 8)) * 0.3).astype(np.float32)
+    y[:, 3] += 1
+    tgt = np.zeros((m, 8), np.float32)
+    tgt[:, :6] = rng.normal(size=(m, 6)) * 2 - 4
+    tgt[:, 6] = rng.normal(size=m)
+    return base, y, tgt
+
+
+@pytest.mark.parametrize("m", [1, 300, 5000])
+def test_seed_loss_matches_oracle(m):
+    from paper_2601_17354_amd import binding as B
+    say(f"seed loss m={m}")
+    base, y, tgt = _loss_inputs(52 + m, m)
+    loss = torch.zeros(1, device=DEV)
+    dy = torch.zeros((m, 8), device=DEV)
+    ws = torch.empty(B.pgs_seed_loss_workspace(m), dtype=torch.uint8, device=DEV)
+    B.pgs_seed_loss(_dev(y), _dev(base), _dev(tgt), m, 1.0 / m, loss, dy, ws)
+    torch.cuda.synchronize()
+    Rb = base[:, :9].astype(np.float64).reshape(m, 3, 3)
+    M = np.zeros((m, 3, 3))
+    for a, b, k in ((0, 0, 0), (1, 1, 1), (2, 2, 2), (0, 1, 3), (0, 2, 4), (1, 2, 5)):
+        M[:, a, b] = M[:, b, a] = tgt[:, k]
+    _, want, gwant = mlp.seed_loss(y, Rb, base[:, 9:12], M, tgt[:, 6])
+    assert abs(loss.item() - want) <= 1e-6 * abs(want)
+    assert_block_close(dy.cpu().numpy(), gwant, 1e-5, what="dloss/dy")
+
+
+def test_seed_apply_matches_oracle():
+    from paper_2601_17354_amd import binding as B
+    pts, _ = _cloud(5, 5000)
+    m = len(pts)
+    say(f"seed apply m={m}")
+    _, _, _, x, base = _gpu_features(pts)
+    rng = np.random.default_rng(53)
+    y = (rng.normal(size=(m, 8)) * np.array([0.7, 0.7, 0.7, 0.25, 0.25, 0.25, 0.25, 1.0])).astype(np.float32)
+    y[:, 3] += 1
+    y[0, 2] = np.nan
+    y[1, 3:7] = 1e-8
+    y[2, 0] = 2.5
+    y[3, 3:7] = [math.cos(math.radians(35)), math.sin(math.radians(35)), 0, 0]   # e3 tilted 70 degrees
+    pca = rng.normal(size=(14, m)).astype(np.float32)
+    out = torch.zeros((14, m), device=DEV)
+    flags = torch.zeros(m, dtype=torch.uint8, device=DEV)
+    count = torch.zeros(1, dtype=torch.int32, device=DEV)
+    B.pgs_seed_apply(_dev(y), base, _dev(pca), m, out, flags, count)
+    torch.cuda.synchronize()
+    got, gf = out.cpu().numpy(), flags.cpu().numpy().astype(bool)
+    assert int(count.item()) == int(gf.sum())
+    assert gf[:4].all()
+    q = np.unique(np.concatenate([np.arange(8), rng.integers(0, m, 300)]))
+    nbr, d2 = o_seed.knn(pts, q)
+    _, R, qb, logs, mg = mlp.features(pts, q, nbr, d2)
+    want, wf, am = mlp.apply(y[q], R, qb, logs, pca.T[q])
+    safe = np.array([g["gap12"] > 1e-5 and g["gap01"] > 1e-5 and g["m3"] > 1e-6 and
+                     a["dlog"] > 1e-5 and a["cos"] > 1e-5 and a["scale_gap"] > 1e-5 for g, a in zip(mg, am)])
+    safe[:4] = True
+    say(f"  {safe.sum()} of {len(q)} rows away from decision margins, {wf.sum()} fall back")
+    np.testing.assert_array_equal(gf[q][safe], wf[safe])
+    for j in np.flatnonzero(safe):
+        i = q[j]
+        if wf[j]:
+            np.testing.assert_array_equal(got[:, i], pca[:, i])
+            continue
+        np.testing.assert_array_equal(got[[0, 1, 2, 11, 12, 13], i], pca[[0, 1, 2, 11, 12, 13], i])
+        np.testing.assert_allclose(got[3:6, i], want[j, 3:6], rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(mlp.rot_of_quat(got[6:10, i]), mlp.rot_of_quat(want[j, 6:10]), atol=1e-5)
+        assert abs(got[10, i] - want[j, 10]) < 1e-5
+
+
+def test_untrained_network_reproduces_plain_seed():
+    from paper_2601_17354_amd import seed_mlp
+    pts, col = _cloud(6, 4000)
+    w = torch.as_tensor(seed_mlp.init_weights(0), device=DEV)
+    P, C = _dev(pts.T), _dev(col.T)
+    learned, nfb = seed_mlp.seed_learned(P, C, w)
+    plain = torch.empty_like(learned)
+    nbr, d2 = seed_mlp.neighbourhoods(P)
+    from paper_2601_17354_amd import binding as B
+    B.pgs_pca_seed(P, C, P.shape[1], nbr, d2, 16, 0.1, plain)
+    torch.cuda.synchronize()
+    assert nfb == 0
+    a, b = learned.cpu().numpy(), plain.cpu().numpy()
+    np.testing.assert_array_equal(a[[0, 1, 2, 10, 11, 12, 13]], b[[0, 1, 2, 10, 11, 12, 13]])
+    np.testing.assert_allclose(a[3:6], b[3:6], rtol=0, atol=1e-6)
+    for i in np.random.default_rng(54).integers(0, P.shape[1], 200):
+        Sa = o_seed.sigma_from_params(a[3:6, i], a[6:10, i])
+        Sb = o_seed.sigma_from_params(b[3:6, i], b[6:10, i])
+        np.testing.assert_allclose(Sa, Sb, rtol=0, atol=1e-5 * np.abs(Sb).max())
+
+
+def test_training_step_lowers_seed_loss():
+    # Targets = the seed that constant outputs y* produce (log-scales moved by
+    # (0.3, -0.2, 0.5), opacity logit 1): reachable through the output biases.
+    from paper_2601_17354_amd import binding as B
+    from paper_2601_17354_amd import seed_mlp
+    pts, col = _cloud(7, 8000)
+    m = len(pts)
+    P, nbr, d2, x, base = _gpu_features(pts)
+    pca = torch.empty((14, m), device=DEV)
+    B.pgs_pca_seed(P, _dev(col.T), m, nbr, d2, 16, 0.1, pca)
+    ystar = torch.tensor([0.3, -0.2, 0.5, 1.0, 0.0, 0.0, 0.0, 1.0 - mlp.LOGIT0], device=DEV).repeat(m, 1)
+    params = torch.empty_like(pca)
+    B.pgs_seed_apply(ystar.contiguous(), base, pca, m, params)
+    T = torch.empty((m, 8), device=DEV)
+    B.pgs_seed_targets(params, m, T)
+    tr = seed_mlp.SeedNetTrainer(torch.as_tensor(seed_mlp.init_weights(1), device=DEV), lr=3e-3,
+                                 max_rows=4096)
+    first = tr.evaluate(x, base, T)
+    for it in range(300):
+        s = (it * 4096) % (m - 4096)
+        tr.step(x[s:s + 4096], base[s:s + 4096], T[s:s + 4096])
+    last = tr.evaluate(x, base, T)
+    say(f"  seed loss {first:.4f} -> {last:.4f}")
+    assert np.isfinite(last) and last < 0.1 * first
