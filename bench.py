@@ -130,11 +130,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 
 def psnr_runs(wl, order, iters=500, at=(0, 100, 500)):
     """Held-out PSNR after `iters` training steps (the same step as timed
-    above, cached backward) from each available initialisation."""
+    above, cached backward) from each initialisation: the plain seed, the
+    learned seed (committed network weights, plain-seed fall back) and an
+    isotropic seed (r_normal = 1) for context."""
     import torch
+    from paper_2601_17354_amd.seed_mlp import load_weights, seed_learned
     from paper_2601_17354_amd.train import Trainer, seed_pca, train
     inits = {"plain_pca": wl["params0"]}
     pts, col = wl["cloud"]
+    inits["learned"], nfb = seed_learned(pts, col, load_weights())
+    log(f"learned seed: {nfb} of {pts.shape[1]} points fell back to the plain seed")
     inits["isotropic"] = seed_pca(pts, col, r_normal=1.0)
     out = {}
     for name, p0 in inits.items():
@@ -292,6 +297,12 @@ def main():
         log("held-out PSNR after 500 training steps per initialisation")
         out["psnr_held_out"] = psnr_runs(wl, order)
         log(f"psnr {out['psnr_held_out']}")
+        del wl
+        torch.cuda.empty_cache()
+        from paper_2601_17354_amd.seed_mlp import load_weights
+        from paper_2601_17354_amd.workloads import compare_inits
+        log("learned vs plain seeding on three fresh scenes (200k points, 1024x768)")
+        out["seeding_fresh_scenes"] = compare_inits(load_weights(), log=log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.width, args.height, args.gaussians)

@@ -110,6 +110,35 @@ typedef struct pgs_replay {
 /* Entry capacity a trace needs for `pair_capacity` pairs and the tile shape. */
 size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int32_t tile_h);
 
+/* A batch of views rendered by one launch (not in PocketGS, which renders one
+ * view at a time).  Tiles of all views share one numbering: view v's tiles
+ * are tile_offset[v] + row-major local index, with tile_offset[0] = 0 and
+ * tile_offset[v+1] = tile_offset[v] + ceil(W_v/tile_w) * ceil(H_v/tile_h).
+ * Per-pixel arrays (image planes, t_final, n_contrib, count, dL/dimage) are
+ * the views' own arrays concatenated: view v starts at pixel_offset[v] =
+ * sum of W_u H_u over u < v, and a 3-channel array holds view v's planar
+ * [3][H_v][W_v] block at 3 * pixel_offset[v].  Per-Gaussian arrays are
+ * stacked per view: proj [n_views][PGS_PROJ_FIELDS][n], rect
+ * [n_views][2][n], touched [n_views][n], 2D gradients
+ * [n_views][PGS_GRAD2D_FIELDS][n].
+ *   cams     host array [n_views]
+ *   tile_w/h one of 16x16, 8x8, 16x8, 32x8, 8x32 (compositing kernels)
+ *   batch    splats staged per LDS batch: 32, 64, 128 or 256
+ *   blocks   workgroups of the persistent compositing launches; 0 = as many
+ *            as the device keeps resident */
+#define PGS_MAX_VIEWS 16
+typedef struct pgs_view_batch {
+    int32_t n_views;
+    const pgs_camera* cams;
+    int32_t tile_w, tile_h;
+    int32_t batch;
+    int32_t blocks;
+} pgs_view_batch;
+
+/* Tile offsets [n_views+1] and pixel offsets [n_views+1] (host arrays, may
+ * be NULL) of a batch; returns the total tile count, or -1 on a bad batch. */
+int32_t pgs_views_layout(const pgs_view_batch* views, int32_t* tile_offsets, int64_t* pixel_offsets);
+
 /* Library version string (static storage). */
 const char* pgs_version(void);
 
@@ -291,6 +320,64 @@ pgs_status pgs_psnr(const float* x_dev, const float* y_dev, int32_t width, int32
 pgs_status pgs_adam_step(float* params_dev, const float* grads_dev, float* m_dev,
                          float* v_dev, int32_t rows, int32_t n, const float* lr_host,
                          int32_t step, float beta1, float beta2, float eps, void* stream);
+
+/*
+ * pgs_bin_sort_views - pgs_bin_sort over every view of a batch with one key
+ * sort: the pairs of view v carry key (tile_offset[v] + local tile) * 2^32 +
+ * bits(float32 depth_v) and value = canonical id, emitted view by view in
+ * canonical order, so the sorted list is the per-view lists one after the
+ * other and ranges index the global tiles.
+ *   proj_all_dev [n_views][PGS_PROJ_FIELDS][n]; rect_all_dev [n_views][2][n];
+ *   touched_all_dev [n_views][n] (pgs_project of each view with the batch's
+ *   tile shape); ranges_dev out [2][total tiles];
+ *   workspace >= pgs_bin_sort_workspace(n_views * n, capacity).
+ * Other arguments and the overflow protocol as pgs_bin_sort.
+ */
+pgs_status pgs_bin_sort_views(const pgs_view_batch* views, int32_t n, const float* proj_all_dev,
+                              const uint32_t* rect_all_dev, const uint32_t* touched_all_dev,
+                              uint32_t capacity, uint64_t* keys_dev, uint32_t* values_dev,
+                              uint32_t* ranges_dev, uint32_t* num_pairs_dev, uint32_t* flags_dev,
+                              void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_render_fwd_views - pgs_render_fwd of every view of a batch as one
+ * persistent launch: workgroups take global tiles from queue_dev (a device
+ * uint32 the call resets) in the order tile_order_dev gives (NULL = tile
+ * index order; pgs_tile_order over all tiles gives heavy-first order) until
+ * all are done.  Outputs as pgs_render_fwd, concatenated per the batch
+ * layout; the trace (optional) is shared by all views: its steps_dev is
+ * [total tiles][TW*TH/64] and count_dev [total pixels].
+ */
+pgs_status pgs_render_fwd_views(const pgs_view_batch* views, const float* proj_all_dev, int32_t n,
+                                const uint32_t* values_dev, const uint32_t* ranges_dev,
+                                const float* bg_host, float* image_all_dev, float* t_final_all_dev,
+                                uint32_t* n_contrib_all_dev, const pgs_replay* cache, uint32_t* flags_dev,
+                                const uint32_t* tile_order_dev, uint32_t* queue_dev, void* stream);
+
+/*
+ * pgs_render_bwd_views - pgs_render_bwd of every view of a batch as one
+ * persistent launch (same queue protocol as pgs_render_fwd_views).  View v's
+ * 2D gradients are accumulated (+=) into grad2d_all_dev[v].
+ *   dl_all_dev  [3 * total pixels] dL/dimage, concatenated per the layout
+ */
+pgs_status pgs_render_bwd_views(const pgs_view_batch* views, const float* proj_all_dev, int32_t n,
+                                const uint32_t* values_dev, const uint32_t* ranges_dev,
+                                const float* bg_host, const float* t_final_all_dev,
+                                const uint32_t* n_contrib_all_dev, const pgs_replay* cache,
+                                const float* dl_all_dev, float* grad2d_all_dev,
+                                const uint32_t* tile_order_dev, uint32_t* queue_dev, void* stream);
+
+/*
+ * pgs_adam_step_dev - pgs_adam_step with the step counter on the device, for
+ * callers that capture the step in a graph and replay it: the call first
+ * advances state_dev[0] (uint32 step count, 0 before the first step) and
+ * stores 1 - beta1^step, 1 - beta2^step as float32 bits in state_dev[1..2],
+ * then updates every element with them.
+ *   state_dev  [4] uint32 device words, owned by the caller
+ */
+pgs_status pgs_adam_step_dev(float* params_dev, const float* grads_dev, float* m_dev, float* v_dev,
+                             int32_t rows, int32_t n, const float* lr_host, uint32_t* state_dev,
+                             float beta1, float beta2, float eps, void* stream);
 
 /*
  * pgs_knn - exact k nearest neighbours (Sec. "Local Surface Statistics

@@ -32,6 +32,11 @@ class PgsReplay(ctypes.Structure):
                 ("count_dev", c_void_p), ("entry_capacity", c_uint64), ("pair_capacity", c_uint32)]
 
 
+class PgsViewBatch(ctypes.Structure):
+    _fields_ = [("n_views", c_int32), ("cams", POINTER(PgsCamera)), ("tile_w", c_int32), ("tile_h", c_int32),
+                ("batch", c_int32), ("blocks", c_int32)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pgs_version": (c_char_p, []),
@@ -64,6 +69,18 @@ SIGNATURES = {
     "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pgs_pca_seed": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float,
                                c_void_p, c_void_p]),
+    "pgs_views_layout": (c_int32, [POINTER(PgsViewBatch), POINTER(c_int32), POINTER(ctypes.c_int64)]),
+    "pgs_bin_sort_views": (c_int32, [POINTER(PgsViewBatch), c_int32, c_void_p, c_void_p, c_void_p, c_uint32,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                     c_void_p]),
+    "pgs_render_fwd_views": (c_int32, [POINTER(PgsViewBatch), c_void_p, c_int32, c_void_p, c_void_p,
+                                       POINTER(c_float), c_void_p, c_void_p, c_void_p, POINTER(PgsReplay),
+                                       c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pgs_render_bwd_views": (c_int32, [POINTER(PgsViewBatch), c_void_p, c_int32, c_void_p, c_void_p,
+                                       POINTER(c_float), c_void_p, c_void_p, POINTER(PgsReplay), c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pgs_adam_step_dev": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, POINTER(c_float),
+                                    c_void_p, c_float, c_float, c_float, c_void_p]),
     "pgs_mlp_weight_count": (c_int32, []),
     "pgs_mlp_features": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float, c_void_p,
                                    c_void_p, c_void_p]),

@@ -1,0 +1,213 @@
+"""Batched multi-view training step, captured as a HIP graph.
+
+Several views of uneven resolution advance one step together:
+projection per view (pgs_project) -> one bin/sort over all views
+(pgs_bin_sort_views) -> heavy-first order of all tiles (pgs_tile_order) ->
+one persistent compositing launch over every (view, tile) (pgs_render_fwd_views)
+-> loss per view -> one persistent backward launch (pgs_render_bwd_views) ->
+projection backward per view into the canonical gradient -> Adam with the
+step counter on the device (pgs_adam_step_dev).  Nothing in a step reads
+back to the host, so the whole step can be captured once
+(torch.cuda.CUDAGraph records the library's launches on the capture stream)
+and replayed; buffers are allocated beforehand and the overflow flags are
+read between replays.  Tile shape, LDS batch size and the persistent grid
+are parameters, chosen by `autotune`.
+"""
+
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import binding as B
+from ._lib import GRAD2D_FIELDS, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_FIELDS
+from .raster import param_rows
+from .train import BETA1, BETA2, EPS, learning_rates
+
+
+class BatchedStep:
+    def __init__(self, params: torch.Tensor, sh_degree: int, cams: list, targets: list, tile=(16, 16),
+                 batch: int = 256, blocks: int = 0, cached: bool = True, lam: float = 0.2, extent: float = 1.0,
+                 capacity: int | None = None, bg=(0.0, 0.0, 0.0), ordered: bool = True):
+        self.params = params.contiguous()
+        self.sh_degree = int(sh_degree)
+        self.F, self.n = self.params.shape
+        assert self.F == param_rows(self.sh_degree)
+        d = self.device = self.params.device
+        self.views = B.ViewBatch(cams, tile, batch, blocks)
+        self.cams = list(cams)
+        self.V = len(cams)
+        self.cached, self.lam, self.bg = cached, lam, tuple(float(x) for x in bg)
+        n, V = self.n, self.V
+        self.tw, self.th = self.views.tile_w, self.views.tile_h
+        self.nt = self.views.n_tiles
+        self.npx = self.views.n_pixels
+        self.proj = torch.empty((V, PROJ_FIELDS, n), dtype=torch.float32, device=d)
+        self.radius = torch.empty((V, n), dtype=torch.int32, device=d)
+        self.rect = torch.empty((V, 2, n), dtype=torch.int32, device=d)
+        self.touched = torch.empty((V, n), dtype=torch.int32, device=d)
+        self.ranges = torch.empty((2, self.nt), dtype=torch.int32, device=d)
+        self.order = torch.empty(self.nt, dtype=torch.int32, device=d) if ordered else None
+        self.queue = torch.zeros(4, dtype=torch.int32, device=d)
+        self.num_pairs = torch.zeros(1, dtype=torch.int32, device=d)
+        self.flags = torch.zeros(1, dtype=torch.int32, device=d)
+        self.image = torch.empty(3 * self.npx, dtype=torch.float32, device=d)
+        self.t_final = torch.empty(self.npx, dtype=torch.float32, device=d)
+        self.n_contrib = torch.empty(self.npx, dtype=torch.int32, device=d)
+        self.dl = torch.zeros(3 * self.npx, dtype=torch.float32, device=d)
+        self.target = torch.empty(3 * self.npx, dtype=torch.float32, device=d)
+        for v, t in enumerate(targets):
+            self.view_slice(self.target, v).copy_(t.reshape(3, self.cams[v]["height"], self.cams[v]["width"]))
+        self.grad2d = torch.zeros((V, GRAD2D_FIELDS, n), dtype=torch.float32, device=d)
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.adam_state = torch.zeros(4, dtype=torch.int32, device=d)
+        self.lr = learning_rates(self.sh_degree, extent)
+        self.losses = torch.zeros(V, dtype=torch.float32, device=d)
+        ws = max(B.pgs_loss_workspace(c["width"], c["height"]) for c in self.cams)
+        self.loss_ws = torch.empty(ws, dtype=torch.uint8, device=d)
+        self.capacity = 0
+        self.graph = None
+        self._alloc_pairs(capacity if capacity is not None else max(4096, 4 * n * V))
+
+    # -- layout ----------------------------------------------------------
+    def view_slice(self, buf: torch.Tensor, v: int, channels: int = 3) -> torch.Tensor:
+        p0, p1 = self.views.pixel_offsets[v], self.views.pixel_offsets[v + 1]
+        W, H = self.cams[v]["width"], self.cams[v]["height"]
+        if channels == 3:
+            return buf[3 * p0:3 * p1].view(3, H, W)
+        return buf[p0:p1].view(H, W)
+
+    def _alloc_pairs(self, capacity: int):
+        capacity = int(capacity)
+        d = self.device
+        self.graph = None
+        self.keys = self.values = self.workspace = self.trace = None
+        self.capacity = capacity
+        self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=d)
+        self.values = torch.empty(max(capacity, 1), dtype=torch.int32, device=d)
+        self.workspace = torch.empty(B.pgs_bin_sort_workspace(self.n * self.V, capacity), dtype=torch.uint8,
+                                     device=d)
+        if self.cached:
+            nw = self.tw * self.th // 64
+            ents = B.pgs_trace_entries(capacity, self.tw, self.th)
+            self.trace = dict(
+                mask=torch.empty((max(capacity, 1), nw), dtype=torch.int64, device=d),
+                steps=torch.empty((self.nt, nw), dtype=torch.int32, device=d),
+                entry=torch.empty((max(ents, 1), 4), dtype=torch.float32, device=d),
+                count=torch.empty(self.npx, dtype=torch.int32, device=d),
+                entry_capacity=max(ents, 1), pair_capacity=capacity)
+
+    def memory_bytes(self) -> int:
+        tot = 0
+        for t in list(vars(self).values()) + (list(self.trace.values()) if self.trace else []):
+            if isinstance(t, torch.Tensor):
+                tot += t.numel() * t.element_size()
+        return tot
+
+    # -- the step ----------------------------------------------------------
+    def forward(self):
+        n = self.n
+        for v, cam in enumerate(self.cams):
+            B.pgs_project(self.params, n, self.sh_degree, cam, self.tw, self.th, self.proj[v], self.radius[v],
+                          self.rect[v], self.touched[v])
+        B.pgs_bin_sort_views(self.views, n, self.proj, self.rect, self.touched, self.capacity, self.keys,
+                             self.values, self.ranges, self.num_pairs, self.flags, self.workspace)
+        if self.order is not None:
+            B.pgs_tile_order(self.ranges, self.nt, 0, self.nt, self.order)
+        B.pgs_render_fwd_views(self.views, self.proj, n, self.values, self.ranges, self.bg, self.image,
+                               self.t_final, self.n_contrib, self.trace if self.cached else None, self.flags,
+                               self.order, self.queue)
+
+    def backward_from(self, dl=None):
+        """Render and projection backward from dL/dimage (default: self.dl);
+        accumulates into self.grads (the caller zeroes it)."""
+        n = self.n
+        self.grad2d.zero_()
+        B.pgs_render_bwd_views(self.views, self.proj, n, self.values, self.ranges, self.bg, self.t_final,
+                               self.n_contrib, self.trace if self.cached else None,
+                               self.dl if dl is None else dl, self.grad2d, self.order, self.queue)
+        for v, cam in enumerate(self.cams):
+            B.pgs_project_bwd(self.params, n, self.sh_degree, cam, self.radius[v], self.grad2d[v], self.grads)
+
+    def step(self):
+        """One full training step over every view (no host synchronisation)."""
+        self.forward()
+        for v, cam in enumerate(self.cams):
+            B.pgs_loss_l1_dssim(self.view_slice(self.image, v), self.view_slice(self.target, v), cam["width"],
+                                cam["height"], self.lam, self.losses[v:v + 1], self.view_slice(self.dl, v),
+                                self.loss_ws)
+        self.grads.zero_()
+        self.backward_from()
+        B.pgs_adam_step_dev(self.params, self.grads, self.m, self.v, self.F, self.n, self.lr, self.adam_state,
+                            BETA1, BETA2, EPS)
+
+    # -- overflow protocol -------------------------------------------------
+    def read_flags(self) -> int:
+        return int(self.flags.item())
+
+    def prepare(self, max_retries=8, headroom=1.5):
+        """Forward until the pair buffers fit (synchronises); drops any graph."""
+        for _ in range(max_retries + 1):
+            self.flags.zero_()
+            self.forward()
+            if self.read_flags() & (PGS_FLAG_PAIR_OVERFLOW | PGS_FLAG_CACHE_OVERFLOW) == 0:
+                return
+            need = int(self.num_pairs.item())
+            self._alloc_pairs(int(math.ceil(max(need, self.capacity) * headroom)) + 4096)
+        raise RuntimeError("batched step buffers kept overflowing")
+
+    # -- graph -------------------------------------------------------------
+    def capture(self):
+        """Records one step as a graph (after a warm-up step on a side stream,
+        which advances the Adam state like any step)."""
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.step()
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def stats(self) -> dict:
+        return dict(views=self.V, gaussians=self.n, pixels=self.npx, tiles=self.nt,
+                    pairs=int(self.num_pairs.item()), tile=f"{self.tw}x{self.th}", batch=self.views.batch,
+                    trace_gb=round(sum(t.numel() * t.element_size() for t in self.trace.values()
+                                       if isinstance(t, torch.Tensor)) / 1e9, 3) if self.trace else 0.0)
+
+
+def mixed_views(n_views=8, scene_radius=4.5, sizes=((640, 480), (800, 600), (1024, 768), (1280, 960),
+                                                     (1440, 1080), (1600, 1200), (1920, 1440), (1024, 768))):
+    """Ring cameras of uneven resolution (one size per view, cycled)."""
+    import synth
+    cams = []
+    for i in range(n_views):
+        W, H = sizes[i % len(sizes)]
+        cams.append(synth.ring_cameras(n_views, W, H, radius=scene_radius)[i])
+    return cams
+
+
+def time_steps(step_fn, steps: int, warmup: int) -> float:
+    """Average ms per call of step_fn with HIP events on the current stream."""
+    for _ in range(warmup):
+        step_fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step_fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+

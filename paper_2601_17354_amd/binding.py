@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PgsCamera, PgsReplay, check
+from ._lib import PgsCamera, PgsReplay, PgsViewBatch, check
 
 
 def _ptr(t, dtype=None):
@@ -268,3 +268,85 @@ def pgs_seed_apply(y, base, pca_params, m, params, fallback=None, fallback_count
     check(lib.pgs_seed_apply(_ptr(y, F32), _ptr(base, F32), _ptr(pca_params, F32), m, _ptr(params, F32),
                              _ptr(fallback, torch.uint8), _ptr(fallback_count, I32), _stream(stream)),
           "pgs_seed_apply")
+
+
+class ViewBatch:
+    """A pgs_view_batch and the camera array it points to (kept alive here),
+    with the batch layout: tile_offsets / pixel_offsets [n_views + 1]."""
+
+    def __init__(self, cams, tile=(16, 16), batch=256, blocks=0):
+        self.cams = list(cams)
+        self.tile_w, self.tile_h = int(tile[0]), int(tile[1])
+        self.batch, self.blocks = int(batch), int(blocks)
+        v = len(self.cams)
+        self._arr = (PgsCamera * v)(*[camera_struct(c) for c in self.cams])
+        self.struct = PgsViewBatch(v, ctypes.cast(self._arr, ctypes.POINTER(PgsCamera)), self.tile_w,
+                                   self.tile_h, self.batch, self.blocks)
+        to = (ctypes.c_int32 * (v + 1))()
+        po = (ctypes.c_int64 * (v + 1))()
+        total = _lib.load().pgs_views_layout(ctypes.byref(self.struct), to, po)
+        if total < 0:
+            raise ValueError(_lib.load().pgs_last_error().decode())
+        self.tile_offsets = list(to)
+        self.pixel_offsets = list(po)
+        self.n_tiles = int(total)
+        self.n_pixels = int(po[v])
+
+    @property
+    def n_views(self):
+        return len(self.cams)
+
+
+def pgs_bin_sort_views(views, n, proj_all, rect_all, touched_all, capacity, keys, values, ranges, num_pairs,
+                       flags, workspace, stream=None):
+    lib = _lib.load()
+    _need(ranges, 2 * views.n_tiles, "ranges")
+    _need(proj_all, views.n_views * 10 * n, "proj_all")
+    _need(keys, capacity, "keys")
+    _need(values, capacity, "values")
+    check(lib.pgs_bin_sort_views(ctypes.byref(views.struct), n, _ptr(proj_all, F32), _ptr(rect_all, I32),
+                                 _ptr(touched_all, I32), int(capacity), _ptr(keys, I64), _ptr(values, I32),
+                                 _ptr(ranges, I32), _ptr(num_pairs, I32), _ptr(flags, I32),
+                                 _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)),
+          "pgs_bin_sort_views")
+
+
+def pgs_render_fwd_views(views, proj_all, n, values, ranges, bg, image_all, t_final_all, n_contrib_all, trace,
+                         flags, tile_order, queue, stream=None):
+    lib = _lib.load()
+    _need(image_all, 3 * views.n_pixels, "image_all")
+    _need(t_final_all, views.n_pixels, "t_final_all")
+    _need(n_contrib_all, views.n_pixels, "n_contrib_all")
+    _need(tile_order, views.n_tiles, "tile_order")
+    bg_arr = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    rep = replay_struct(trace)
+    check(lib.pgs_render_fwd_views(ctypes.byref(views.struct), _ptr(proj_all, F32), n, _ptr(values, I32),
+                                   _ptr(ranges, I32), bg_arr, _ptr(image_all, F32), _ptr(t_final_all, F32),
+                                   _ptr(n_contrib_all, I32), ctypes.byref(rep) if rep is not None else None,
+                                   _ptr(flags, I32), _ptr(tile_order, I32), _ptr(queue, I32), _stream(stream)),
+          "pgs_render_fwd_views")
+
+
+def pgs_render_bwd_views(views, proj_all, n, values, ranges, bg, t_final_all, n_contrib_all, trace, dl_all,
+                         grad2d_all, tile_order, queue, stream=None):
+    lib = _lib.load()
+    _need(dl_all, 3 * views.n_pixels, "dl_all")
+    _need(grad2d_all, views.n_views * 9 * n, "grad2d_all")
+    _need(tile_order, views.n_tiles, "tile_order")
+    bg_arr = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    rep = replay_struct(trace)
+    check(lib.pgs_render_bwd_views(ctypes.byref(views.struct), _ptr(proj_all, F32), n, _ptr(values, I32),
+                                   _ptr(ranges, I32), bg_arr, _ptr(t_final_all, F32), _ptr(n_contrib_all, I32),
+                                   ctypes.byref(rep) if rep is not None else None, _ptr(dl_all, F32),
+                                   _ptr(grad2d_all, F32), _ptr(tile_order, I32), _ptr(queue, I32),
+                                   _stream(stream)),
+          "pgs_render_bwd_views")
+
+
+def pgs_adam_step_dev(params, grads, m, v, rows, n, lr, state, beta1, beta2, eps, stream=None):
+    lib = _lib.load()
+    _need(state, 4, "state")
+    lr_arr = (ctypes.c_float * rows)(*[float(x) for x in lr])
+    check(lib.pgs_adam_step_dev(_ptr(params, F32), _ptr(grads, F32), _ptr(m, F32), _ptr(v, F32), rows, n,
+                                lr_arr, _ptr(state, I32), float(beta1), float(beta2), float(eps),
+                                _stream(stream)), "pgs_adam_step_dev")

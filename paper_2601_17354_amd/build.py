@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpocketgs.so")
 
-SOURCES = ["api.hip", "project.hip", "binning.hip", "render.hip", "loss.hip", "adam.hip", "seed.hip",
+SOURCES = ["api.hip", "project.hip", "binning.hip", "render.hip", "render_views.hip", "loss.hip", "adam.hip", "seed.hip",
            "mlp.hip", "probe.hip"]
 
 ARCH = "gfx950"

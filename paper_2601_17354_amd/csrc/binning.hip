@@ -147,6 +147,48 @@ __global__ __launch_bounds__(256) void k_emit(int n, const float* __restrict__ d
         }
 }
 
+// Pairs of several views: item i = v * n + g is Gaussian g in view v, keyed
+// with view v's global tile numbers; values hold the canonical id g.
+struct EmitViews {
+    int n_views;
+    int TX[PGS_MAX_VIEWS];
+    int tile_off[PGS_MAX_VIEWS];
+};
+
+__global__ __launch_bounds__(256) void k_emit_views(int n, EmitViews ev, const float* __restrict__ proj_all,
+                                                    const uint32_t* __restrict__ rect_all,
+                                                    const uint32_t* __restrict__ touched_all,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    const uint32_t* __restrict__ num_pairs, uint32_t capacity,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ values,
+                                                    uint32_t* __restrict__ flags) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && *num_pairs > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
+    if (i >= (size_t)ev.n_views * n) return;
+    const uint32_t cnt = touched_all[i];
+    if (cnt == 0) return;
+    const int v = (int)(i / (size_t)n), g = (int)(i - (size_t)v * n);
+    int TX = ev.TX[0], off = ev.tile_off[0];
+    for (int u = 1; u < ev.n_views; ++u)
+        if (u == v) {
+            TX = ev.TX[u];
+            off = ev.tile_off[u];
+        }
+    uint32_t idx = offsets[i];
+    const uint32_t* rect = rect_all + (size_t)v * 2 * n;
+    const uint32_t r0 = rect[g], r1 = rect[(size_t)n + g];
+    const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff, y1 = r1 >> 16;
+    const uint64_t dbits =
+        (uint64_t)__float_as_uint(proj_all[(size_t)v * PGS_PROJ_FIELDS * n + (size_t)PGS_PROJ_DEPTH * n + g]);
+    for (uint32_t ty = y0; ty <= y1; ++ty)
+        for (uint32_t tx = x0; tx <= x1; ++tx, ++idx) {
+            if (idx >= capacity) return;
+            const uint64_t tile = (uint64_t)(off + ty * (uint32_t)TX + tx);
+            keys[idx] = (tile << 32) | dbits;
+            values[idx] = (uint32_t)g;
+        }
+}
+
 __device__ __forceinline__ uint32_t clamp_count(const uint32_t* num, uint32_t capacity) {
     const uint32_t c = *num;
     return c < capacity ? c : capacity;
@@ -415,5 +457,56 @@ extern "C" pgs_status pgs_bin_sort(int32_t n, const float* proj_dev, const uint3
     const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
     k_ranges<<<grid, 256, 0, s>>>(keys_dev, num_pairs_dev, capacity, (uint32_t)n_tiles, ranges_dev);
     PGS_CHECK_LAUNCH("pgs_bin_sort ranges");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_bin_sort_views(const pgs_view_batch* views, int32_t n, const float* proj_all_dev,
+                                         const uint32_t* rect_all_dev, const uint32_t* touched_all_dev,
+                                         uint32_t capacity, uint64_t* keys_dev, uint32_t* values_dev,
+                                         uint32_t* ranges_dev, uint32_t* num_pairs_dev, uint32_t* flags_dev,
+                                         void* workspace_dev, size_t workspace_bytes, void* stream) {
+    pgs_status st = pgs::check_views(views, "pgs_bin_sort_views");
+    if (st != PGS_OK) return st;
+    PGS_REQUIRE(n >= 0 && (int64_t)n * views->n_views < (1ll << 31), "pgs_bin_sort_views: bad n");
+    PGS_REQUIRE(ranges_dev && num_pairs_dev && flags_dev, "pgs_bin_sort_views: null pointer");
+    PGS_REQUIRE(n == 0 || (proj_all_dev && rect_all_dev && touched_all_dev), "pgs_bin_sort_views: null pointer");
+    PGS_REQUIRE(capacity == 0 || (keys_dev && values_dev), "pgs_bin_sort_views: null pointer");
+    const int32_t items = n * views->n_views;
+    const size_t need = pgs_bin_sort_workspace(items, capacity);
+    PGS_REQUIRE(workspace_dev && workspace_bytes >= need, "pgs_bin_sort_views: workspace %zu < %zu",
+                workspace_bytes, need);
+    const pgs::ViewsLayout lay = pgs::views_layout(*views);
+    const int n_tiles = lay.tile_off[views->n_views];
+    EmitViews ev{};
+    ev.n_views = views->n_views;
+    for (int v = 0; v < views->n_views; ++v) {
+        ev.TX[v] = lay.TX[v];
+        ev.tile_off[v] = lay.tile_off[v];
+    }
+    hipStream_t s = pgs::as_stream(stream);
+    char* p = static_cast<char*>(workspace_dev);
+    uint32_t* offsets = reinterpret_cast<uint32_t*>(p);
+    p += align_up((size_t)items * 4);
+    uint32_t* partial = reinterpret_cast<uint32_t*>(p);
+    p += scan_workspace((uint32_t)items);
+    SortWs w = sort_layout(p, capacity);
+
+    k_clear_u32<<<256, 256, 0, s>>>(ranges_dev, 2u * (uint32_t)n_tiles);
+    k_clear_u32<<<1, 64, 0, s>>>(num_pairs_dev, 1u);
+    PGS_CHECK_LAUNCH("pgs_bin_sort_views clear");
+    if (items == 0) return PGS_OK;
+    st = scan_u32(touched_all_dev, offsets, (uint32_t)items, num_pairs_dev, partial, s);
+    if (st != PGS_OK) return st;
+    k_emit_views<<<div_up((uint32_t)items, 256), 256, 0, s>>>(n, ev, proj_all_dev, rect_all_dev, touched_all_dev,
+                                                             offsets, num_pairs_dev, capacity, keys_dev,
+                                                             values_dev, flags_dev);
+    PGS_CHECK_LAUNCH("pgs_bin_sort_views emit");
+    if (capacity == 0) return PGS_OK;
+    const int key_bits = 32 + bits_for((uint32_t)n_tiles);
+    st = radix_sort(keys_dev, values_dev, num_pairs_dev, capacity, key_bits, w, s);
+    if (st != PGS_OK) return st;
+    const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
+    k_ranges<<<grid, 256, 0, s>>>(keys_dev, num_pairs_dev, capacity, (uint32_t)n_tiles, ranges_dev);
+    PGS_CHECK_LAUNCH("pgs_bin_sort_views ranges");
     return PGS_OK;
 }

@@ -48,6 +48,29 @@ inline CamD make_cam(const pgs_camera& c) {
     return d;
 }
 
+// Tile and pixel offsets of a batch of views (tiles numbered view by view,
+// row-major inside a view; pixel arrays concatenated view by view).
+struct ViewsLayout {
+    int TX[PGS_MAX_VIEWS];
+    int tile_off[PGS_MAX_VIEWS + 1];
+    long long pix_off[PGS_MAX_VIEWS + 1];
+};
+
+inline ViewsLayout views_layout(const pgs_view_batch& vb) {
+    ViewsLayout l{};
+    for (int v = 0; v < vb.n_views; ++v) {
+        const int W = vb.cams[v].width, H = vb.cams[v].height;
+        l.TX[v] = (W + vb.tile_w - 1) / vb.tile_w;
+        const int TY = (H + vb.tile_h - 1) / vb.tile_h;
+        l.tile_off[v + 1] = l.tile_off[v] + l.TX[v] * TY;
+        l.pix_off[v + 1] = l.pix_off[v] + (long long)W * H;
+    }
+    return l;
+}
+
+// Validates the view list of a batch (shape checks are the caller's).
+pgs_status check_views(const pgs_view_batch* vb, const char* who);
+
 }  // namespace pgs
 
 #define PGS_REQUIRE(cond, ...)                 \

@@ -1,0 +1,506 @@
+// Per-tile compositing forward and backward, shared by the single-view
+// kernels (one workgroup per tile) and the multi-view persistent kernels
+// (workgroups pull (view, tile) items from a queue).
+//
+// Forward (PocketGS Sec. "Explicit Computation Graph", "Bandwidth-Efficient
+// Forward Replay Cache"): one lane per pixel of a TW x TH tile.  The tile's
+// sorted splat list is staged through LDS in batches of BG splats (36 B of
+// 2D attributes each) and every wave steps through the batch in lockstep,
+// each lane compositing its pixel front to back.  A barrier with a live-lane
+// count ends the tile once every pixel terminated.
+//
+// Replay trace.  S = {id, C_in, alpha} is recorded per wave of 64 pixels as
+// groups, one per sorted splat id that at least one of the wave's pixels
+// composited: a 64-bit ballot mask of those pixels (stored at the id's slot)
+// followed by their entries, appended contiguously in lane order to the
+// wave's entry region.  The id of an entry is thus the slot of its group,
+// its pixel the lane of its mask bit, and a pixel's entries in group order
+// are its contributors front to back.  Entry regions have the exact worst
+// case size (64 entries per wave and listed splat), so nothing overflows;
+// a per-wave step counter bounds the valid groups, so masks of earlier
+// iterations are never read and nothing is cleared between iterations.
+// Entries are written as one coalesced run per group.  After the front to
+// back pass the tile's groups are walked back to front with the splat
+// colours re-staged in LDS, and each entry is written once as (C_in, alpha):
+// C_in is the colour of everything behind the splat, the over-recursion
+// C_out = C_in (1 - alpha) + alpha c run from the background.
+//
+// Backward (equation "backward_chain"), two variants:
+//   cached     steps through each wave's groups front to back, visiting only
+//              non-empty masks; a lane with a bit set reads its entry, takes
+//              dL/dC_out (starts at dL/dC, times (1 - alpha) after each own
+//              entry), dL/dalpha = <dL/dC_out, c - C_in> and dL/dc =
+//              alpha dL/dC_out, chains them to the nine 2D parameters, and the
+//              wave reduces them with DPP (a lone lane writes directly).
+//   recompute  walks the list back to front from n_contrib, re-evaluates
+//              alpha with the forward's exact arithmetic, recovers
+//              T_k = T_{k+1} / (1 - alpha_k) from T_final and accumulates the
+//              colour behind as it goes (the 3D Gaussian Splatting backward).
+// Per-wave partial sums meet in LDS and leave with one float atomic per
+// field and (tile, splat), scattered to the canonical index values[id]
+// (index-mapping equation).
+#pragma once
+
+#include "common.hpp"
+
+// Trace groups whose entries a wave loads before consuming the first one.
+#ifndef PGS_TRACE_GROUPS
+#define PGS_TRACE_GROUPS 4
+#endif
+
+namespace pgs {
+
+struct Splat {
+    float u, v, A, B, C, o, r, g, b;
+};
+
+// Alpha of a splat at pixel centre (px, py).  Evaluated with contraction off
+// so that the forward and the recompute backward produce identical bits.
+__device__ __forceinline__ bool splat_alpha(const Splat& s, float px, float py, float& alpha,
+                                            float& gauss, float& dx, float& dy) {
+#pragma clang fp contract(off)
+    dx = s.u - px;
+    dy = s.v - py;
+    const float power = -0.5f * (s.A * dx * dx + s.C * dy * dy) - s.B * dx * dy;
+    if (power > 0.f) return false;
+    gauss = __expf(power);
+    alpha = fminf(kAlphaMax, s.o * gauss);
+    return alpha >= kAlphaMin;
+}
+
+__device__ __forceinline__ void stage_splat(const float* __restrict__ proj, int n, uint32_t g,
+                                            float4* sa, float4* sb, float* sc, int slot) {
+    sa[slot] = make_float4(proj[(size_t)PGS_PROJ_U * n + g], proj[(size_t)PGS_PROJ_V * n + g],
+                           proj[(size_t)PGS_PROJ_A * n + g], proj[(size_t)PGS_PROJ_B * n + g]);
+    sb[slot] = make_float4(proj[(size_t)PGS_PROJ_C * n + g], proj[(size_t)PGS_PROJ_OPACITY * n + g],
+                           proj[(size_t)PGS_PROJ_R * n + g], proj[(size_t)PGS_PROJ_G * n + g]);
+    sc[slot] = proj[(size_t)PGS_PROJ_BLUE * n + g];
+}
+
+__device__ __forceinline__ Splat load_splat(const float4* sa, const float4* sb, const float* sc, int k) {
+    const float4 a = sa[k], b = sb[k];
+    return Splat{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, sc[k]};
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+struct Trace {
+    uint64_t* mask;    // [pair_cap][NW]
+    uint32_t* steps;   // [n_tiles][NW]
+    float4* entry;     // [entry_cap] (C_in r, g, b, alpha)
+    uint32_t* count;   // [pixels]
+    size_t entry_cap;
+    uint32_t pair_cap;
+};
+
+// One tile of one view.  Pixel arrays (image planes, t_final, n_contrib,
+// count) are the view's own; gt is the tile's global index in the ranges.
+struct TileJob {
+    int W, H, tx, ty, gt;
+    const float* proj;
+    float* image;
+    float* t_final;
+    uint32_t* n_contrib;
+    uint32_t* count;
+};
+
+// LDS of a tile pass: one batch of BG staged splats (forward), plus their
+// canonical ids and the gradient accumulator (backward); declared by each
+// kernel and handed to the tile functions.
+template <int BG>
+struct FwdLds {
+    float4 a[BG];
+    float4 b[BG];
+    float c[BG];
+    uint32_t steps;
+};
+
+template <int BG>
+struct TileLds {
+    float4 a[BG];
+    float4 b[BG];
+    float c[BG];
+    uint32_t g[BG];
+    float acc[9][BG];
+    uint32_t steps;
+};
+
+// Stages splats base .. base+nb-1 of the sorted list into LDS slots 0..nb-1.
+template <int NT, bool KEEP_IDS, class Lds>
+__device__ __forceinline__ void stage_batch(Lds& L, const float* __restrict__ proj, int n,
+                                            const uint32_t* __restrict__ values, uint32_t base, int nb,
+                                            int t) {
+    for (int q = t; q < nb; q += NT) {
+        const uint32_t g = values[base + q];
+        if constexpr (KEEP_IDS) L.g[q] = g;
+        stage_splat(proj, n, g, L.a, L.b, L.c, q);
+    }
+}
+
+template <int TW, int TH, int BG, bool CACHED>
+__device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, int n,
+                                         const uint32_t* __restrict__ values,
+                                         const uint32_t* __restrict__ ranges, float bg0, float bg1,
+                                         float bg2, const Trace& tr, uint32_t* __restrict__ flags,
+                                         FwdLds<BG>& L) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
+    const bool inside = px < j.W && py < j.H;
+    const uint32_t start = ranges[j.gt], end = ranges[n_tiles_total + j.gt];
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+
+    // the trace is recorded only if this tile's pairs fit the trace buffers
+    const bool rec = CACHED && end <= tr.pair_cap;
+    if (CACHED && !rec && t == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
+    const size_t ebase = (size_t)NT * start + (size_t)64 * (end - start) * wv;
+    uint32_t cursor = 0, steps = 0, cnt = 0;
+
+    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    bool done = !inside;
+    uint32_t last = 0;
+
+    for (uint32_t base = start; base < end; base += BG) {
+        if (__syncthreads_count(!done) == 0) break;
+        const int nb = (int)min((uint32_t)BG, end - base);
+        stage_batch<NT, false>(L, j.proj, n, values, base, nb, t);
+        __syncthreads();
+        for (int k = 0; k < nb; ++k) {
+            if (__ballot(!done) == 0) break;  // the whole wave has terminated
+            bool contrib = false;
+            float alpha = 0.f;
+            if (!done) {
+                const Splat s = load_splat(L.a, L.b, L.c, k);
+                float gauss, dx, dy;
+                if (splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy)) {
+                    const float test_T = T * (1.f - alpha);
+                    if (test_T < kTMin) {
+                        done = true;
+                    } else {
+                        contrib = true;
+                        const float w = alpha * T;
+                        C0 += w * s.r;
+                        C1 += w * s.g;
+                        C2 += w * s.b;
+                        T = test_T;
+                        last = base + k - start + 1;
+                    }
+                }
+            }
+            if (rec) {
+                const uint64_t m = __ballot(contrib);
+                if (lane == 0) tr.mask[(size_t)(base + k) * NW + wv] = m;
+                cursor += __popcll(m);
+                cnt += contrib ? 1u : 0u;
+                steps = base + k - start + 1;
+            }
+        }
+    }
+    if (inside) {
+        const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
+        j.image[pix] = C0 + T * bg0;
+        j.image[plane + pix] = C1 + T * bg1;
+        j.image[2 * plane + pix] = C2 + T * bg2;
+        j.t_final[pix] = T;
+        j.n_contrib[pix] = last;
+        if (CACHED) j.count[pix] = rec ? cnt : 0u;
+    }
+    if (!rec) return;  // uniform for the block
+    if (lane == 0) tr.steps[(size_t)j.gt * NW + wv] = steps;
+
+    // Entry pass: back to front over each wave's groups with the splats
+    // re-staged in LDS batch by batch (the forward batches in reverse).  Each
+    // set lane re-evaluates alpha with the same arithmetic as above (same
+    // bits) and writes its entry (C_in, alpha) once, C_in being the colour
+    // accumulated behind the splat so far.
+    __syncthreads();
+    if (t == 0) L.steps = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&L.steps, steps);
+    __syncthreads();
+    const uint32_t smax = L.steps;
+    float a0 = bg0, a1 = bg1, a2 = bg2;
+    uint32_t cur = cursor;
+    if (smax == 0) return;
+    const int64_t top = (int64_t)((smax - 1) / BG) * BG;  // first position of the last batch
+    for (int64_t lo = top; lo >= 0; lo -= BG) {
+        const uint32_t hi = min((uint32_t)lo + BG, smax);
+        __syncthreads();
+        stage_batch<NT, false>(L, j.proj, n, values, start + (uint32_t)lo, (int)(hi - (uint32_t)lo), t);
+        __syncthreads();
+        const uint32_t whi = min(hi, steps);
+        if (whi <= (uint32_t)lo) continue;
+        // chunks of 64 steps, last chunk first; one vector load fetches a
+        // chunk's masks, then the non-empty ones are visited last to first
+        for (int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64; c0 >= lo; c0 -= 64) {
+            const uint32_t cn = min(64u, whi - (uint32_t)c0);
+            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
+            uint64_t any = __ballot(mv != 0ull);
+            while (any) {
+                const int i = 63 - __clzll(any);
+                any &= ~(1ull << i);
+                const uint64_t m = read_lane64(mv, i);
+                cur -= __popcll(m);
+                if ((m >> lane) & 1ull) {
+                    const Splat s = load_splat(L.a, L.b, L.c, (int)(c0 + i - lo));
+                    float a = 0.f, gauss, dx, dy;
+                    splat_alpha(s, fpx, fpy, a, gauss, dx, dy);
+                    tr.entry[ebase + cur + lane_rank(m)] = make_float4(a0, a1, a2, a);
+                    a0 = a * s.r + (1.f - a) * a0;
+                    a1 = a * s.g + (1.f - a) * a1;
+                    a2 = a * s.b + (1.f - a) * a2;
+                }
+            }
+        }
+    }
+}
+
+// Nine 2D gradients of one splat at one pixel from dL/dalpha and dL/dc.
+__device__ __forceinline__ void chain_2d(const Splat& s, float dx, float dy, float alpha,
+                                         float dgauss_do, bool clamped, float dl_dalpha,
+                                         float dc0, float dc1, float dc2, float* v) {
+    float dpow = 0.f, d_o = 0.f;
+    if (!clamped) {
+        dpow = alpha * dl_dalpha;
+        d_o = dgauss_do * dl_dalpha;
+    }
+    v[0] = -(s.A * dx + s.B * dy) * dpow;
+    v[1] = -(s.B * dx + s.C * dy) * dpow;
+    v[2] = -0.5f * dx * dx * dpow;
+    v[3] = -dx * dy * dpow;
+    v[4] = -0.5f * dy * dy * dpow;
+    v[5] = d_o;
+    v[6] = dc0;
+    v[7] = dc1;
+    v[8] = dc2;
+}
+
+// Adds one wave's nine gradients of splat jj into the workgroup's LDS
+// accumulator: a lone contributing lane adds its own values, otherwise the
+// wave sums with DPP and lane 63 adds (LDS float atomics, ds_add_f32).
+template <int BG>
+__device__ __forceinline__ void accumulate(const float* v, float (*acc)[BG], int lane, int jj, bool lone,
+                                           bool mine) {
+    if (lone) {
+        if (mine) {
+#pragma unroll
+            for (int f = 0; f < 9; ++f) atomicAdd(&acc[f][jj], v[f]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int f = 0; f < 9; ++f) {
+        const float sum = wave_sum_to_lane63(v[f]);
+        if (lane == 63) atomicAdd(&acc[f][jj], sum);
+    }
+}
+
+// One float atomic per field and splat of the batch into the canonical
+// 2D-gradient rows (index map values[id]).
+template <int BG>
+__device__ __forceinline__ void flush_batch(float (*acc)[BG], const uint32_t* gid, int nb, int n,
+                                            float* __restrict__ grad2d, int t, int NT) {
+    for (int idx = t; idx < nb * 9; idx += NT) {
+        const int f = idx / nb, jj = idx - f * nb;
+        const float s = acc[f][jj];
+        if (s != 0.f) unsafeAtomicAdd(&grad2d[(size_t)f * n + gid[jj]], s);
+    }
+}
+
+template <int BG>
+__device__ __forceinline__ void zero_acc(float (*acc)[BG], int t, int NT) {
+    for (int idx = t; idx < 9 * BG; idx += NT) (&acc[0][0])[idx] = 0.f;
+}
+
+template <int TW, int TH, int BG>
+__device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_total, int n,
+                                                const uint32_t* __restrict__ values,
+                                                const uint32_t* __restrict__ ranges, const Trace& tr,
+                                                const float* __restrict__ dl_dimage,
+                                                float* __restrict__ grad2d, TileLds<BG>& L) {
+    constexpr int NT = TW * TH;
+    constexpr int NW = NT / 64;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
+    const bool inside = px < j.W && py < j.H;
+    const uint32_t start = ranges[j.gt], end = ranges[n_tiles_total + j.gt];
+    if (end > tr.pair_cap) return;  // no trace was recorded for this tile (uniform)
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
+    const size_t ebase = (size_t)NT * start + (size_t)64 * (end - start) * wv;
+
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;  // dL/dC_out of this pixel's next entry
+    if (inside) {
+        g0 = dl_dimage[pix];
+        g1 = dl_dimage[plane + pix];
+        g2 = dl_dimage[2 * plane + pix];
+    }
+    const uint32_t steps = tr.steps[(size_t)j.gt * NW + wv];
+    __syncthreads();
+    if (t == 0) L.steps = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&L.steps, steps);
+    __syncthreads();
+    const uint32_t smax = L.steps;
+    uint32_t cursor = 0;
+
+    for (uint32_t base = 0; base < smax; base += BG) {
+        const int nb = (int)min((uint32_t)BG, smax - base);
+        stage_batch<NT, true>(L, j.proj, n, values, start + base, nb, t);
+        zero_acc<BG>(L.acc, t, NT);
+        __syncthreads();
+        const uint32_t whi = min(base + (uint32_t)nb, steps);
+        for (uint32_t c0 = base; c0 < whi; c0 += 64) {
+            const uint32_t cn = min(64u, whi - c0);
+            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
+            uint64_t any = __ballot(mv != 0ull);
+            while (any) {
+                // take up to kG groups and issue all their trace loads before
+                // any of them is consumed (memory-level parallelism per wave)
+                constexpr int kG = PGS_TRACE_GROUPS;
+                int gi[kG];
+                uint64_t gm[kG];
+                uint32_t gc[kG];
+                uint32_t cur = cursor;
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    gi[q] = 0;
+                    gm[q] = 0ull;
+                    gc[q] = cur;
+                    if (any) {
+                        const int i = __ffsll((unsigned long long)any) - 1;
+                        any &= any - 1;
+                        gi[q] = i;
+                        gm[q] = read_lane64(mv, i);
+                        cur += __popcll(gm[q]);
+                    }
+                }
+                float4 ent[kG];
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    ent[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if ((gm[q] >> lane) & 1ull) ent[q] = tr.entry[ebase + gc[q] + lane_rank(gm[q])];
+                }
+#pragma unroll
+                for (int q = 0; q < kG; ++q) {
+                    const uint64_t m = gm[q];
+                    if (m == 0ull) continue;  // uniform: fewer than kG groups left
+                    const int jj = (int)(c0 - base) + gi[q];
+                    const bool mine = (m >> lane) & 1ull;
+                    float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    if (mine) {
+                        const Splat s = load_splat(L.a, L.b, L.c, jj);
+                        const float dx = s.u - fpx, dy = s.v - fpy;
+                        const float a = ent[q].w;
+                        // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
+                        const float dla =
+                            g0 * (s.r - ent[q].x) + g1 * (s.g - ent[q].y) + g2 * (s.b - ent[q].z);
+                        const bool clamped = a >= kAlphaMax;
+                        chain_2d(s, dx, dy, a, clamped ? 0.f : a / s.o, clamped, dla, a * g0, a * g1,
+                                 a * g2, v);
+                        // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
+                        const float om = 1.f - a;
+                        g0 *= om;
+                        g1 *= om;
+                        g2 *= om;
+                    }
+                    accumulate<BG>(v, L.acc, lane, jj, __popcll(m) == 1, mine);
+                }
+                cursor = cur;
+            }
+        }
+        __syncthreads();
+        flush_batch<BG>(L.acc, L.g, nb, n, grad2d, t, NT);
+        __syncthreads();
+    }
+}
+
+template <int TW, int TH, int BG>
+__device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
+                                                   const uint32_t* __restrict__ values,
+                                                   const uint32_t* __restrict__ ranges, float bg0,
+                                                   float bg1, float bg2, const float* __restrict__ dl_dimage,
+                                                   float* __restrict__ grad2d, TileLds<BG>& L) {
+    constexpr int NT = TW * TH;
+    const int t = threadIdx.x, lane = t & 63;
+    const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
+    const bool inside = px < j.W && py < j.H;
+    const uint32_t start = ranges[j.gt];
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
+
+    uint32_t last = 0;
+    float T = 1.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
+    if (inside) {
+        last = j.n_contrib[pix];
+        T = j.t_final[pix];
+        G0 = dl_dimage[pix];
+        G1 = dl_dimage[plane + pix];
+        G2 = dl_dimage[2 * plane + pix];
+    }
+    float a0 = bg0, a1 = bg1, a2 = bg2;  // colour behind the current splat
+    __syncthreads();
+    if (t == 0) L.steps = 0;
+    __syncthreads();
+    if (last) atomicMax(&L.steps, last);
+    __syncthreads();
+    const uint32_t top = L.steps;
+
+    for (uint32_t hi = top; hi > 0;) {
+        const uint32_t lo = hi > (uint32_t)BG ? hi - BG : 0u;
+        const int nb = (int)(hi - lo);
+        stage_batch<NT, true>(L, j.proj, n, values, start + lo, nb, t);
+        zero_acc<BG>(L.acc, t, NT);
+        __syncthreads();
+        for (int jj = nb - 1; jj >= 0; --jj) {
+            const uint32_t jrel = lo + jj;
+            bool ok = false;
+            float alpha = 0.f, gauss = 0.f, dx = 0.f, dy = 0.f;
+            Splat s{};
+            if (jrel < last) {
+                s = load_splat(L.a, L.b, L.c, jj);
+                ok = splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy);
+            }
+            const uint64_t m = __ballot(ok);
+            if (m == 0) continue;
+            float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (ok) {
+                const float Tk = T / (1.f - alpha);
+                const float q0 = Tk * G0, q1 = Tk * G1, q2 = Tk * G2;
+                const float dla = q0 * (s.r - a0) + q1 * (s.g - a1) + q2 * (s.b - a2);
+                const bool clamped = s.o * gauss > kAlphaMax;
+                chain_2d(s, dx, dy, alpha, gauss, clamped, dla, alpha * q0, alpha * q1,
+                         alpha * q2, v);
+                a0 = alpha * s.r + (1.f - alpha) * a0;
+                a1 = alpha * s.g + (1.f - alpha) * a1;
+                a2 = alpha * s.b + (1.f - alpha) * a2;
+                T = Tk;
+            }
+            accumulate<BG>(v, L.acc, lane, jj, __popcll(m) == 1, ok);
+        }
+        __syncthreads();
+        flush_batch<BG>(L.acc, L.g, nb, n, grad2d, t, NT);
+        __syncthreads();
+        hi = lo;
+    }
+}
+
+// Checks a replay-trace descriptor against the tile shape and wraps it.
+pgs_status make_trace(const pgs_replay* c, int tile_w, int tile_h, Trace& tr, const char* who);
+
+// Tile shapes the kernels are built for (one lane per pixel, whole waves).
+inline bool tile_shape_ok(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) ||
+           (tw == 32 && th == 8) || (tw == 8 && th == 32);
+}
+
+}  // namespace pgs

@@ -29,9 +29,12 @@ def render_targets(params: torch.Tensor, sh_degree: int, cams: list, width: int,
     return out
 
 
-def training_workload(n_train=300_000, n_gt=500_000, width=1920, height=1440, scene_seed=0,
-                      n_cams=60, target_cams=None, device="cuda"):
-    """Returns dict(params0 [14][n], cams, train_ids, test_ids, targets{idx: image})."""
+def scene_views(scene_seed, n_points, n_gt=500_000, width=1920, height=1440, n_cams=60, target_cams=None,
+                device="cuda"):
+    """Seeded spheres-and-planes scene: ground truth = n_gt flat opaque
+    Gaussians on its surfaces (seed 1000 + scene_seed), targets = the ground
+    truth rendered at n_cams ring cameras (every 8th held out), and a noisy
+    n_points cloud of the same surfaces (seed 2000 + scene_seed)."""
     dev = torch.device(device)
     scene = synth.spheres_planes_scene(scene_seed)
     gt = synth.surface_gaussians(scene, n_gt, seed=1000 + scene_seed, sh_degree=0, opacity=0.95)
@@ -43,10 +46,53 @@ def training_workload(n_train=300_000, n_gt=500_000, width=1920, height=1440, sc
     imgs = render_targets(gt_t, 0, [cams[i] for i in want], width, height)
     targets = dict(zip(want, imgs))
     del gt_t
-    pts, col = synth.noisy_cloud(scene, n_train, seed=2000 + scene_seed)
+    pts, col = synth.noisy_cloud(scene, n_points, seed=2000 + scene_seed)
     P = torch.as_tensor(np.ascontiguousarray(pts.T), device=dev)
     C = torch.as_tensor(np.ascontiguousarray(col.T), device=dev)
-    params0 = seed_pca(P, C)
+    return dict(cams=cams, train_ids=train_ids, test_ids=test_ids, targets=targets, scene=scene,
+                width=width, height=height, cloud=(P, C))
+
+
+def training_workload(n_train=300_000, n_gt=500_000, width=1920, height=1440, scene_seed=0,
+                      n_cams=60, target_cams=None, device="cuda"):
+    """Returns dict(params0 [14][n], cams, train_ids, test_ids, targets{idx: image})."""
+    wl = scene_views(scene_seed, n_train, n_gt, width, height, n_cams, target_cams, device)
+    P, C = wl["cloud"]
+    wl["params0"] = seed_pca(P, C)
     torch.cuda.synchronize()
-    return dict(params0=params0, cams=cams, train_ids=train_ids, test_ids=test_ids,
-                targets=targets, scene=scene, width=width, height=height, cloud=(P, C))
+    return wl
+
+
+def compare_inits(weights, scene_seeds=(200, 201, 202), n_points=200_000, n_gt=400_000, width=1024,
+                  height=768, iters=500, eval_at=(0, 100, 500), isotropic=True, log=None):
+    """Held-out PSNR after training from the plain seed, the learned seed
+    (network `weights`, plain-seed fall back) and, for context, an isotropic
+    seed (r_normal = 1), on fresh scenes.  Returns per-scene histories, the
+    mean over scenes and the learned seed's fall-back counts."""
+    from .seed_mlp import seed_learned
+    from .train import Trainer, train
+    rng = np.random.default_rng(0)
+    per_scene, fallbacks = {}, {}
+    for s in scene_seeds:
+        wl = scene_views(s, n_points, n_gt, width, height)
+        P, C = wl["cloud"]
+        order = [int(i) for i in rng.permutation(wl["train_ids"])]
+        inits = {"plain_pca": seed_pca(P, C)}
+        inits["learned"], fallbacks[str(s)] = seed_learned(P, C, weights)
+        if isotropic:
+            inits["isotropic"] = seed_pca(P, C, r_normal=1.0)
+        res = {}
+        for name, p0 in inits.items():
+            tr = Trainer(p0.clone(), 0, width, height, cached=True, lam=0.2, extent=4.5)
+            hist = train(tr, wl["cams"], wl["targets"], order, iters, eval_ids=wl["test_ids"], eval_at=eval_at)
+            res[name] = {str(k): round(v, 3) for k, v in hist.items()}
+            del tr
+            if log:
+                log(f"scene {s} {name}: {res[name]}")
+        per_scene[str(s)] = res
+        del wl, inits
+        torch.cuda.empty_cache()
+    names = list(next(iter(per_scene.values())).keys())
+    mean = {n: {str(k): round(float(np.mean([per_scene[sc][n][str(k)] for sc in per_scene])), 3)
+                for k in eval_at} for n in names}
+    return dict(per_scene=per_scene, mean=mean, fallbacks=fallbacks)

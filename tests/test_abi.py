@@ -52,9 +52,23 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert lib.pgs_adam_step(None, None, None, None, 65, 10, lr, 1, 0.9, 0.999, 1e-15, None) == \
         _lib.PGS_ERR_INVALID_ARG
     bg = (ctypes.c_float * 3)(0, 0, 0)
-    st = lib.pgs_render_fwd(64, 48, 8, 8, None, 0, None, None, 0, bg, None, None, None, None, None, None,
+    st = lib.pgs_render_fwd(64, 48, 12, 8, None, 0, None, None, 0, bg, None, None, None, None, None, None,
                             None)
     assert st == _lib.PGS_ERR_INVALID_ARG and b"unsupported tile" in lib.pgs_last_error()
+    cams = (_lib.PgsCamera * 2)()
+    for c in cams:
+        c.width, c.height = 64, 48
+    vb = _lib.PgsViewBatch(2, ctypes.cast(cams, ctypes.POINTER(_lib.PgsCamera)), 16, 16, 100, 0)
+    st = lib.pgs_render_fwd_views(ctypes.byref(vb), None, 0, None, None, bg, None, None, None, None, None, None,
+                                  None, None)
+    assert st == _lib.PGS_ERR_INVALID_ARG and b"batch 100" in lib.pgs_last_error()
+    vb.batch, vb.n_views = 64, 17
+    assert lib.pgs_views_layout(ctypes.byref(vb), None, None) == -1
+    vb.n_views = 2
+    to = (ctypes.c_int32 * 3)()
+    po = (ctypes.c_int64 * 3)()
+    assert lib.pgs_views_layout(ctypes.byref(vb), to, po) == 24 and list(to) == [0, 12, 24]
+    assert list(po) == [0, 64 * 48, 2 * 64 * 48]
 
 
 def test_workspace_queries_grow_with_size():

@@ -1,0 +1,176 @@
+"""GPU parity of the batched multi-view path (one bin/sort over every view,
+persistent compositing forward and backward over the (view, tile) queue)
+against the oracle run view by view, for every tile shape and several LDS
+batch sizes; the device-counter Adam against the host-counter one; and
+graph replays of the whole step against eager steps."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_helpers import GRAD_TOL, IMG_TOL, assert_block_close, say
+from oracle import pipeline
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+
+
+def _views():
+    # one cloud of 1000 Gaussians (the small parity workload) seen by three
+    # cameras of uneven size at the same pose
+    P, _, _ = synth.cfg1_inputs(0)
+    cams = [synth.make_camera(128, 128, 128.0, 128.0, 64.0, 64.0, np.eye(3), np.zeros(3)),
+            synth.make_camera(100, 75, 90.0, 90.0, 50.0, 37.5, np.eye(3), np.zeros(3)),
+            synth.make_camera(72, 40, 60.0, 60.0, 36.0, 20.0, np.eye(3), np.zeros(3))]
+    return P, cams
+
+
+def _oracle(P, cams, tile, bg, dls):
+    out = []
+    for cam, dl in zip(cams, dls):
+        proj, bins, fwd = pipeline.forward(P, cam, tile[0], tile[1], bg)
+        og, og2d, taint = pipeline.backward(P, cam, proj, bins, fwd, dl, "cached")
+        out.append(dict(proj=proj, bins=bins, fwd=fwd, grads=og, g2d=og2d, taint=taint))
+    return out
+
+
+CONFIGS = [((16, 16), 256, True), ((8, 8), 32, True), ((16, 8), 128, True), ((32, 8), 64, True),
+           ((8, 32), 256, True), ((16, 16), 32, True), ((16, 16), 128, False), ((8, 8), 64, False)]
+
+
+@pytest.mark.parametrize("tile,batch,cached", CONFIGS, ids=[f"{t[0]}x{t[1]}-b{b}-{'c' if c else 'r'}"
+                                                            for t, b, c in CONFIGS])
+def test_views_match_oracle_per_view(tile, batch, cached):
+    from paper_2601_17354_amd.batch import BatchedStep
+    P, cams = _views()
+    bg = (0.1, 0.2, 0.3)
+    rng = np.random.default_rng(11)
+    dls = [rng.normal(size=(3, c["height"], c["width"])).astype(np.float32) for c in cams]
+    say(f"[views] tile {tile} batch {batch} cached {cached}")
+    targets = [torch.zeros((3, c["height"], c["width"]), device=DEV) for c in cams]
+    st = BatchedStep(torch.as_tensor(P, device=DEV), 0, cams, targets, tile=tile, batch=batch, cached=cached,
+                     bg=bg)
+    st.prepare()
+    for v in range(len(cams)):
+        st.view_slice(st.dl, v).copy_(torch.as_tensor(dls[v], device=DEV))
+    st.grads.zero_()
+    st.backward_from()
+    torch.cuda.synchronize()
+    assert st.read_flags() == 0
+    ref = _oracle(P, cams, tile, bg, dls)
+
+    # one sorted list = the per-view lists one after the other, tiles offset
+    npairs = int(st.num_pairs.item())
+    keys = st.keys[:npairs].cpu().numpy().view(np.uint64)
+    vals = st.values[:npairs].cpu().numpy().astype(np.int64)
+    offs = st.views.tile_offsets
+    want_k = np.concatenate([r["bins"]["keys"] + (np.uint64(off) << np.uint64(32)) for r, off in zip(ref, offs)])
+    want_v = np.concatenate([r["bins"]["values"] for r in ref]).astype(np.int64)
+    n_marg = sum(int(r["proj"]["marginal"].sum()) for r in ref)
+    say(f"  pairs {npairs}, marginal gaussians {n_marg}")
+    if n_marg == 0:
+        np.testing.assert_array_equal(keys, want_k)
+        np.testing.assert_array_equal(vals, want_v)
+        ranges = st.ranges.cpu().numpy().astype(np.int64)
+        base = 0
+        for r, t0, t1 in zip(ref, offs[:-1], offs[1:]):
+            rr = r["bins"]["ranges"]
+            want = np.where((rr[:, 1] > rr[:, 0])[:, None], rr + base, 0)   # empty tiles stay (0, 0)
+            np.testing.assert_array_equal(ranges[:, t0:t1].T, want)
+            base += r["bins"]["num_pairs"]
+    else:
+        # drop the pairs of Gaussians whose decisions are marginal in the
+        # view the pair belongs to (view from the global tile of the key)
+        def keep(k, v):
+            view = np.searchsorted(np.asarray(offs[1:]), (k >> np.uint64(32)).astype(np.int64), side="right")
+            marg = np.stack([r["proj"]["marginal"] for r in ref])
+            return ~marg[view, v]
+        kg, kw = keep(keys, vals), keep(want_k, want_v)
+        np.testing.assert_array_equal(keys[kg], want_k[kw])
+        np.testing.assert_array_equal(vals[kg], want_v[kw])
+
+    grads_want = np.zeros_like(P, dtype=np.float64)
+    taint_any = np.zeros(P.shape[1], bool)
+    for v, r in enumerate(ref):
+        ok = ~r["fwd"]["marginal"]
+        img = st.view_slice(st.image, v).cpu().numpy()
+        for c in range(3):
+            assert_block_close(img[c], r["fwd"]["image"][c], IMG_TOL, mask=ok, what=f"view {v} image[{c}]")
+        nc = st.view_slice(st.n_contrib, v, channels=1).cpu().numpy()
+        assert (nc[ok] == r["fwd"]["n_contrib"][ok]).all()
+        if cached:
+            cnt = st.view_slice(st.trace["count"], v, channels=1).cpu().numpy()
+            assert (cnt[ok] == r["fwd"]["count"][ok]).all()
+        g2 = st.grad2d[v].cpu().numpy()
+        for f in range(9):
+            assert_block_close(g2[f], r["g2d"][f], GRAD_TOL, mask=~r["taint"], what=f"view {v} grad2d[{f}]")
+        grads_want += r["grads"]
+        taint_any |= r["taint"]
+    g = st.grads.cpu().numpy()
+    for row in range(g.shape[0]):
+        assert_block_close(g[row], grads_want[row], GRAD_TOL, mask=~taint_any, what=f"canonical row {row}")
+
+
+def test_adam_step_dev_matches_host_counter():
+    from paper_2601_17354_amd import binding as B
+    rng = np.random.default_rng(12)
+    rows, n = 14, 3001
+    p0 = rng.normal(size=(rows, n)).astype(np.float32)
+    lr = rng.uniform(1e-4, 1e-2, rows)
+    a = [torch.as_tensor(p0, device=DEV)] + [torch.zeros((rows, n), device=DEV) for _ in range(2)]
+    b = [torch.as_tensor(p0, device=DEV)] + [torch.zeros((rows, n), device=DEV) for _ in range(2)]
+    state = torch.zeros(4, dtype=torch.int32, device=DEV)
+    for step in (1, 2, 3):
+        g = torch.as_tensor(rng.normal(size=(rows, n)).astype(np.float32), device=DEV)
+        B.pgs_adam_step(a[0], g, a[1], a[2], rows, n, lr, step, 0.9, 0.999, 1e-15)
+        B.pgs_adam_step_dev(b[0], g, b[1], b[2], rows, n, lr, state, 0.9, 0.999, 1e-15)
+    torch.cuda.synchronize()
+    assert int(state[0].item()) == 3
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+def _scene_views(n=20000):
+    scene = synth.spheres_planes_scene(4)
+    P = synth.surface_gaussians(scene, n, seed=60, sh_degree=3, logit_sigma=0.5)
+    sizes = [(320, 240), (256, 192), (160, 120)]
+    cams = [synth.ring_cameras(12, W, H)[i * 4] for i, (W, H) in enumerate(sizes)]
+    return P, cams
+
+
+def test_graph_replay_matches_eager_steps():
+    # Replays of the captured step, with unrelated eager work and host
+    # synchronisations in between, against the same steps run eagerly.
+    from paper_2601_17354_amd.batch import BatchedStep
+    P, cams = _scene_views()
+    rng = np.random.default_rng(13)
+    targets = [torch.as_tensor(rng.uniform(size=(3, c["height"], c["width"])).astype(np.float32), device=DEV)
+               for c in cams]
+    say("[views] graph replay vs eager")
+    ga = BatchedStep(torch.as_tensor(P, device=DEV), 3, cams, targets, tile=(16, 8), batch=128, extent=4.5)
+    eb = BatchedStep(torch.as_tensor(P, device=DEV), 3, cams, targets, tile=(16, 8), batch=128, extent=4.5)
+    ga.prepare()
+    eb.prepare()
+    cap = max(ga.capacity, eb.capacity) * 2
+    ga._alloc_pairs(cap)
+    eb._alloc_pairs(cap)
+    ga.capture()          # runs one eager warm-up step, then records one
+    eb.step()
+    for k in range(4):
+        ga.replay()
+        eb.step()
+        scratch = torch.randn(1 << 20, device=DEV)
+        scratch.mul_(2.0).sum().item()
+        torch.cuda.synchronize()
+        assert ga.read_flags() == 0 and eb.read_flags() == 0
+        la, lb = ga.losses.cpu().numpy(), eb.losses.cpu().numpy()
+        say(f"  step {k + 2}: losses graph {la} eager {lb}")
+        np.testing.assert_allclose(la, lb, rtol=1e-4)
+        pa, pb = ga.params.cpu().numpy(), eb.params.cpu().numpy()
+        diff = np.abs(pa - pb)
+        # float atomics may order the gradient sums differently; Adam's
+        # normalised step bounds what that can move per step
+        assert diff.max() <= 2.0 * (k + 2) * 2.5e-2, diff.max()
+        assert (diff <= 1e-5).mean() > 0.99
+    assert int(ga.adam_state[0].item()) == 5 and int(eb.adam_state[0].item()) == 5
