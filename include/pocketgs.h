@@ -88,26 +88,33 @@ typedef struct pgs_camera {
  *   steps_dev  [n_tiles][TW*TH/64] uint32: per wave, the number of list
  *              positions (from the tile's start) whose masks are valid; the
  *              per-iteration counter that replaces a cache clear
+ *   base_dev   [n_tiles][TW*TH/64] uint32: first entry of the wave's region
+ *   used_dev   [1] uint64 device counter of entries handed out; reset by the
+ *              forward, which leaves the total demand of the pass in it
  *   entry_dev  [entry_capacity][4] float32, 16-byte aligned: per entry
  *              (C_in r, g, b, alpha) - C_in the colour of everything behind
  *              the splat at that pixel, alpha the clamped alpha it had there
  *   count_dev  [H*W] uint32 entries per pixel, count(u)
- * Entries of wave w of the tile whose pairs are [start, end) live at
- * TW*TH*start + 64*(end-start)*w + cursor, where cursor counts the wave's
- * entries of earlier groups and a group's entries follow in lane order.  So
- * entry_capacity >= TW*TH * pair_capacity (pgs_trace_entries) bounds every
- * iteration and the trace never overflows; only tiles whose pairs exceed
- * pair_capacity go unrecorded (flagged PGS_FLAG_CACHE_OVERFLOW). */
+ * A wave's entries are base + cursor, where cursor counts the wave's entries
+ * of earlier groups and a group's entries follow in lane order; each wave
+ * takes a region of exactly its entry count.  entry_capacity <= 2^32 - 1.
+ * A wave whose region does not fit, and every tile whose pairs exceed
+ * pair_capacity, goes unrecorded (steps 0, count 0) and the forward raises
+ * PGS_FLAG_CACHE_OVERFLOW; used_dev then tells how many entries the pass
+ * needed.  pgs_trace_entries gives a capacity that can never overflow. */
 typedef struct pgs_replay {
     uint64_t* mask_dev;
     uint32_t* steps_dev;
+    uint32_t* base_dev;
+    uint64_t* used_dev;
     float* entry_dev;
     uint32_t* count_dev;
     uint64_t entry_capacity;
     uint32_t pair_capacity;
 } pgs_replay;
 
-/* Entry capacity a trace needs for `pair_capacity` pairs and the tile shape. */
+/* Entry capacity that no pass with at most `pair_capacity` pairs can exceed
+ * (64 entries per wave and listed splat: TW*TH*pair_capacity). */
 size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int32_t tile_h);
 
 /* A batch of views rendered by one launch (not in PocketGS, which renders one

@@ -28,8 +28,9 @@ class PgsCamera(ctypes.Structure):
 
 
 class PgsReplay(ctypes.Structure):
-    _fields_ = [("mask_dev", c_void_p), ("steps_dev", c_void_p), ("entry_dev", c_void_p),
-                ("count_dev", c_void_p), ("entry_capacity", c_uint64), ("pair_capacity", c_uint32)]
+    _fields_ = [("mask_dev", c_void_p), ("steps_dev", c_void_p), ("base_dev", c_void_p), ("used_dev", c_void_p),
+                ("entry_dev", c_void_p), ("count_dev", c_void_p), ("entry_capacity", c_uint64),
+                ("pair_capacity", c_uint32)]
 
 
 class PgsViewBatch(ctypes.Structure):

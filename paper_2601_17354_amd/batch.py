@@ -22,14 +22,15 @@ import torch
 
 from . import binding as B
 from ._lib import GRAD2D_FIELDS, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_FIELDS
-from .raster import param_rows
+from .raster import MAX_ENTRIES, new_trace, param_rows
 from .train import BETA1, BETA2, EPS, learning_rates
 
 
 class BatchedStep:
     def __init__(self, params: torch.Tensor, sh_degree: int, cams: list, targets: list, tile=(16, 16),
                  batch: int = 256, blocks: int = 0, cached: bool = True, lam: float = 0.2, extent: float = 1.0,
-                 capacity: int | None = None, bg=(0.0, 0.0, 0.0), ordered: bool = True):
+                 capacity: int | None = None, bg=(0.0, 0.0, 0.0), ordered: bool = True,
+                 entries: int | None = None):
         self.params = params.contiguous()
         self.sh_degree = int(sh_degree)
         self.F, self.n = self.params.shape
@@ -70,6 +71,7 @@ class BatchedStep:
         self.loss_ws = torch.empty(ws, dtype=torch.uint8, device=d)
         self.capacity = 0
         self.graph = None
+        self.entry_capacity = int(entries) if entries is not None else max(1 << 20, 32 * self.npx)
         self._alloc_pairs(capacity if capacity is not None else max(4096, 4 * n * V))
 
     # -- layout ----------------------------------------------------------
@@ -80,8 +82,10 @@ class BatchedStep:
             return buf[3 * p0:3 * p1].view(3, H, W)
         return buf[p0:p1].view(H, W)
 
-    def _alloc_pairs(self, capacity: int):
+    def _alloc_pairs(self, capacity: int, entries: int | None = None):
         capacity = int(capacity)
+        if entries is not None:
+            self.entry_capacity = min(int(entries), MAX_ENTRIES)
         d = self.device
         self.graph = None
         self.keys = self.values = self.workspace = self.trace = None
@@ -91,14 +95,7 @@ class BatchedStep:
         self.workspace = torch.empty(B.pgs_bin_sort_workspace(self.n * self.V, capacity), dtype=torch.uint8,
                                      device=d)
         if self.cached:
-            nw = self.tw * self.th // 64
-            ents = B.pgs_trace_entries(capacity, self.tw, self.th)
-            self.trace = dict(
-                mask=torch.empty((max(capacity, 1), nw), dtype=torch.int64, device=d),
-                steps=torch.empty((self.nt, nw), dtype=torch.int32, device=d),
-                entry=torch.empty((max(ents, 1), 4), dtype=torch.float32, device=d),
-                count=torch.empty(self.npx, dtype=torch.int32, device=d),
-                entry_capacity=max(ents, 1), pair_capacity=capacity)
+            self.trace = new_trace(capacity, self.tw * self.th // 64, self.nt, self.npx, self.entry_capacity, d)
 
     def memory_bytes(self) -> int:
         tot = 0
@@ -156,7 +153,10 @@ class BatchedStep:
             if self.read_flags() & (PGS_FLAG_PAIR_OVERFLOW | PGS_FLAG_CACHE_OVERFLOW) == 0:
                 return
             need = int(self.num_pairs.item())
-            self._alloc_pairs(int(math.ceil(max(need, self.capacity) * headroom)) + 4096)
+            cap = self.capacity if need <= self.capacity else int(math.ceil(need * headroom)) + 4096
+            used = int(self.trace["used"].item()) if self.trace is not None else 0
+            ents = self.entry_capacity if used <= self.entry_capacity else int(math.ceil(used * headroom)) + 4096
+            self._alloc_pairs(cap, ents)
         raise RuntimeError("batched step buffers kept overflowing")
 
     # -- graph -------------------------------------------------------------
@@ -186,15 +186,16 @@ class BatchedStep:
                                        if isinstance(t, torch.Tensor)) / 1e9, 3) if self.trace else 0.0)
 
 
-def mixed_views(n_views=8, scene_radius=4.5, sizes=((640, 480), (800, 600), (1024, 768), (1280, 960),
-                                                     (1440, 1080), (1600, 1200), (1920, 1440), (1024, 768))):
+# Eight view sizes from 640x480 to 1920x1440: 9,733,632 pixels, 38,092
+# tiles of 16x16 in total.
+MIXED_SIZES = ((640, 480), (800, 600), (960, 720), (1024, 768), (1280, 960), (1440, 1080), (1600, 1200),
+               (1920, 1440))
+
+
+def mixed_views(n_views=8, radius=4.5, sizes=MIXED_SIZES):
     """Ring cameras of uneven resolution (one size per view, cycled)."""
     import synth
-    cams = []
-    for i in range(n_views):
-        W, H = sizes[i % len(sizes)]
-        cams.append(synth.ring_cameras(n_views, W, H, radius=scene_radius)[i])
-    return cams
+    return [synth.ring_cameras(n_views, *sizes[i % len(sizes)], radius=radius)[i] for i in range(n_views)]
 
 
 def time_steps(step_fn, steps: int, warmup: int) -> float:

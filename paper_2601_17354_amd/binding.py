@@ -53,7 +53,12 @@ def replay_struct(trace) -> PgsReplay | None:
     r = PgsReplay()
     r.mask_dev = _ptr(trace["mask"], torch.int64).value
     r.steps_dev = _ptr(trace["steps"], torch.int32).value
+    r.base_dev = _ptr(trace["base"], torch.int32).value
+    r.used_dev = _ptr(trace["used"], torch.int64).value
     r.entry_dev = _ptr(trace["entry"], torch.float32).value
+    _need(trace["steps"], trace["base"].numel(), "trace base")
+    _need(trace["entry"], 4 * int(trace["entry_capacity"]), "trace entries")
+    _need(trace["mask"], int(trace["pair_capacity"]), "trace masks")
     r.count_dev = _ptr(trace["count"], torch.int32).value
     r.entry_capacity = int(trace["entry_capacity"])
     r.pair_capacity = int(trace["pair_capacity"])

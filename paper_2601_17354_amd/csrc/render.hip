@@ -67,16 +67,25 @@ extern "C" size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int3
     return (size_t)pair_capacity * (size_t)(tile_w > 0 ? tile_w : 0) * (size_t)(tile_h > 0 ? tile_h : 0);
 }
 
-pgs_status pgs::make_trace(const pgs_replay* c, int tile_w, int tile_h, Trace& tr, const char* who) {
-    PGS_REQUIRE(c->mask_dev && c->steps_dev && c->entry_dev && c->count_dev, "%s: null trace pointer", who);
+namespace {
+__global__ void k_clear_u64(unsigned long long* p) {
+    if (threadIdx.x == 0) *p = 0ull;
+}
+}  // namespace
+
+pgs_status pgs::make_trace(const pgs_replay* c, Trace& tr, const char* who) {
+    PGS_REQUIRE(c->mask_dev && c->steps_dev && c->base_dev && c->used_dev && c->entry_dev && c->count_dev,
+                "%s: null trace pointer", who);
     PGS_REQUIRE(((uintptr_t)c->entry_dev % 16) == 0, "%s: trace entries must be 16-byte aligned", who);
-    PGS_REQUIRE(c->entry_capacity >= pgs_trace_entries(c->pair_capacity, tile_w, tile_h),
-                "%s: trace entry capacity %llu below %u pairs x %d pixels", who,
-                (unsigned long long)c->entry_capacity, c->pair_capacity, tile_w * tile_h);
-    tr = Trace{c->mask_dev, c->steps_dev, reinterpret_cast<float4*>(c->entry_dev), c->count_dev,
-               (size_t)c->entry_capacity, c->pair_capacity};
+    PGS_REQUIRE(c->entry_capacity <= 0xffffffffull, "%s: entry capacity %llu above 2^32 - 1", who,
+                (unsigned long long)c->entry_capacity);
+    tr = Trace{c->mask_dev, c->steps_dev, c->base_dev, reinterpret_cast<unsigned long long*>(c->used_dev),
+               reinterpret_cast<float4*>(c->entry_dev), c->count_dev, (size_t)c->entry_capacity,
+               c->pair_capacity};
     return PGS_OK;
 }
+
+void pgs::reset_trace_counter(const Trace& tr, hipStream_t s) { k_clear_u64<<<1, 64, 0, s>>>(tr.used); }
 
 extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
                                      const float* proj_dev, int32_t n, const uint32_t* values_dev,
@@ -94,10 +103,11 @@ extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile
     Trace tr{};
     if (cache) {
         PGS_REQUIRE(flags_dev != nullptr, "pgs_render_fwd: a trace needs the flags word");
-        pgs_status st = pgs::make_trace(cache, tile_w, tile_h, tr, "pgs_render_fwd");
+        pgs_status st = pgs::make_trace(cache, tr, "pgs_render_fwd");
         if (st != PGS_OK) return st;
     }
     hipStream_t s = pgs::as_stream(stream);
+    if (cache) pgs::reset_trace_counter(tr, s);
     with_tile(tile_w, tile_h, [&](auto TWc, auto THc) {
         constexpr int TW = decltype(TWc)::value, TH = decltype(THc)::value;
         const dim3 grid(TX * TY), block(TW * TH);
@@ -134,7 +144,7 @@ extern "C" pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile
     hipStream_t s = pgs::as_stream(stream);
     Trace tr{};
     if (cache) {
-        pgs_status st = pgs::make_trace(cache, tile_w, tile_h, tr, "pgs_render_bwd");
+        pgs_status st = pgs::make_trace(cache, tr, "pgs_render_bwd");
         if (st != PGS_OK) return st;
     } else {
         PGS_REQUIRE(t_final_dev && n_contrib_dev, "pgs_render_bwd: null pointer");

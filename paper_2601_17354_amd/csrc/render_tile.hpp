@@ -12,17 +12,19 @@
 // Replay trace.  S = {id, C_in, alpha} is recorded per wave of 64 pixels as
 // groups, one per sorted splat id that at least one of the wave's pixels
 // composited: a 64-bit ballot mask of those pixels (stored at the id's slot)
-// followed by their entries, appended contiguously in lane order to the
-// wave's entry region.  The id of an entry is thus the slot of its group,
-// its pixel the lane of its mask bit, and a pixel's entries in group order
-// are its contributors front to back.  Entry regions have the exact worst
-// case size (64 entries per wave and listed splat), so nothing overflows;
-// a per-wave step counter bounds the valid groups, so masks of earlier
-// iterations are never read and nothing is cleared between iterations.
-// Entries are written as one coalesced run per group.  After the front to
-// back pass the tile's groups are walked back to front with the splat
-// colours re-staged in LDS, and each entry is written once as (C_in, alpha):
-// C_in is the colour of everything behind the splat, the over-recursion
+// followed by their entries in lane order.  The id of an entry is thus the
+// slot of its group, its pixel the lane of its mask bit, and a pixel's
+// entries in group order are its contributors front to back.  After the
+// front to back pass each wave knows how many entries it recorded and takes
+// a region of exactly that size from a device-wide bump counter (one 64-bit
+// atomic per wave); a wave whose region does not fit the entry capacity is
+// left unrecorded and the overflow flag is raised, the counter then holding
+// the demand the caller needs.  A per-wave step counter bounds the valid
+// groups, so masks of earlier iterations are never read and nothing is
+// cleared between iterations.  The tile's groups are then walked back to
+// front with the splat colours re-staged in LDS, and each entry is written
+// once as (C_in, alpha), one coalesced run per group: C_in is the colour of
+// everything behind the splat, the over-recursion
 // C_out = C_in (1 - alpha) + alpha c run from the background.
 //
 // Backward (equation "backward_chain"), two variants:
@@ -93,10 +95,12 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
 }
 
 struct Trace {
-    uint64_t* mask;    // [pair_cap][NW]
-    uint32_t* steps;   // [n_tiles][NW]
-    float4* entry;     // [entry_cap] (C_in r, g, b, alpha)
-    uint32_t* count;   // [pixels]
+    uint64_t* mask;             // [pair_cap][NW]
+    uint32_t* steps;            // [n_tiles][NW]
+    uint32_t* base;             // [n_tiles][NW] first entry of the wave's region
+    unsigned long long* used;   // entries handed out in this forward
+    float4* entry;              // [entry_cap] (C_in r, g, b, alpha)
+    uint32_t* count;            // [pixels]
     size_t entry_cap;
     uint32_t pair_cap;
 };
@@ -162,7 +166,6 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     // the trace is recorded only if this tile's pairs fit the trace buffers
     const bool rec = CACHED && end <= tr.pair_cap;
     if (CACHED && !rec && t == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
-    const size_t ebase = (size_t)NT * start + (size_t)64 * (end - start) * wv;
     uint32_t cursor = 0, steps = 0, cnt = 0;
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -205,6 +208,21 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
             }
         }
     }
+    // the wave's entry region: `cursor` entries from the bump counter
+    size_t ebase = 0;
+    bool wrec = rec;
+    if (rec) {
+        unsigned long long b = 0;
+        if (lane == 0 && cursor) b = atomicAdd(tr.used, (unsigned long long)cursor);
+        b = read_lane64(b, 0);
+        wrec = b + cursor <= tr.entry_cap;
+        if (!wrec) {
+            if (lane == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
+            steps = 0;   // the backward reads nothing of this wave
+        } else {
+            ebase = (size_t)b;
+        }
+    }
     if (inside) {
         const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
         j.image[pix] = C0 + T * bg0;
@@ -212,10 +230,13 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
         j.image[2 * plane + pix] = C2 + T * bg2;
         j.t_final[pix] = T;
         j.n_contrib[pix] = last;
-        if (CACHED) j.count[pix] = rec ? cnt : 0u;
+        if (CACHED) j.count[pix] = wrec ? cnt : 0u;
     }
     if (!rec) return;  // uniform for the block
-    if (lane == 0) tr.steps[(size_t)j.gt * NW + wv] = steps;
+    if (lane == 0) {
+        tr.steps[(size_t)j.gt * NW + wv] = steps;
+        tr.base[(size_t)j.gt * NW + wv] = (uint32_t)ebase;
+    }
 
     // Entry pass: back to front over each wave's groups with the splats
     // re-staged in LDS batch by batch (the forward batches in reverse).  Each
@@ -336,7 +357,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
     if (end > tr.pair_cap) return;  // no trace was recorded for this tile (uniform)
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
-    const size_t ebase = (size_t)NT * start + (size_t)64 * (end - start) * wv;
+    const size_t ebase = tr.base[(size_t)j.gt * NW + wv];
 
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;  // dL/dC_out of this pixel's next entry
     if (inside) {
@@ -494,8 +515,12 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
     }
 }
 
-// Checks a replay-trace descriptor against the tile shape and wraps it.
-pgs_status make_trace(const pgs_replay* c, int tile_w, int tile_h, Trace& tr, const char* who);
+// Checks a replay-trace descriptor and wraps it.
+pgs_status make_trace(const pgs_replay* c, Trace& tr, const char* who);
+
+// Zeroes the trace's entry counter ahead of a forward (a kernel, so that the
+// call can be captured in a graph).
+void reset_trace_counter(const Trace& tr, hipStream_t s);
 
 // Tile shapes the kernels are built for (one lane per pixel, whole waves).
 inline bool tile_shape_ok(int tw, int th) {

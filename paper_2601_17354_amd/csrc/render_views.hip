@@ -198,11 +198,12 @@ extern "C" pgs_status pgs_render_fwd_views(const pgs_view_batch* vb, const float
     Trace tr{};
     if (cache) {
         PGS_REQUIRE(flags_dev != nullptr, "pgs_render_fwd_views: a trace needs the flags word");
-        st = pgs::make_trace(cache, vb->tile_w, vb->tile_h, tr, "pgs_render_fwd_views");
+        st = pgs::make_trace(cache, tr, "pgs_render_fwd_views");
         if (st != PGS_OK) return st;
     }
     hipStream_t s = pgs::as_stream(stream);
     k_clear_queue<<<1, 64, 0, s>>>(queue_dev);
+    if (cache) pgs::reset_trace_counter(tr, s);
     with_config(vb->tile_w, vb->tile_h, vb->batch, [&](auto TWc, auto THc, auto BGc) {
         constexpr int TW = decltype(TWc)::value, TH = decltype(THc)::value, BG = decltype(BGc)::value;
         if (cache) {
@@ -239,7 +240,7 @@ extern "C" pgs_status pgs_render_bwd_views(const pgs_view_batch* vb, const float
     const int total = vt.tile_off[vb->n_views];
     Trace tr{};
     if (cache) {
-        st = pgs::make_trace(cache, vb->tile_w, vb->tile_h, tr, "pgs_render_bwd_views");
+        st = pgs::make_trace(cache, tr, "pgs_render_bwd_views");
         if (st != PGS_OK) return st;
     } else {
         PGS_REQUIRE(t_final_all_dev && n_contrib_all_dev, "pgs_render_bwd_views: null pointer");

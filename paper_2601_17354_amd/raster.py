@@ -23,10 +23,29 @@ def param_rows(sh_degree: int) -> int:
     return 11 + 3 * (sh_degree + 1) ** 2
 
 
+MAX_ENTRIES = (1 << 32) - 1
+
+
+def new_trace(pair_capacity: int, nw: int, n_tiles: int, pixels: int, entries: int, device) -> dict:
+    """Replay-trace buffers (layout of pgs_replay): masks per pair slot and
+    wave, per-wave step counters and entry offsets, the entry counter,
+    `entries` 16-byte entries and per-pixel counts."""
+    entries = max(1, min(int(entries), MAX_ENTRIES))
+    return dict(
+        mask=torch.empty((max(pair_capacity, 1), nw), dtype=torch.int64, device=device),
+        steps=torch.empty((n_tiles, nw), dtype=torch.int32, device=device),
+        base=torch.empty((n_tiles, nw), dtype=torch.int32, device=device),
+        used=torch.zeros(1, dtype=torch.int64, device=device),
+        entry=torch.empty((entries, 4), dtype=torch.float32, device=device),
+        count=torch.empty(pixels, dtype=torch.int32, device=device),
+        entry_capacity=entries, pair_capacity=int(pair_capacity),
+    )
+
+
 class Rasterizer:
     def __init__(self, n: int, sh_degree: int, width: int, height: int, tile=(16, 16),
                  cached: bool = True, capacity: int | None = None,
-                 device="cuda", ordered: bool = True):
+                 device="cuda", ordered: bool = True, entries: int | None = None):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.W, self.H = int(width), int(height)
@@ -54,13 +73,16 @@ class Rasterizer:
         self.capacity = 0
         self.trace = None
         self.nw = self.tw * self.th // 64
+        self.entry_capacity = int(entries) if entries is not None else max(1 << 20, 32 * self.W * self.H)
         self._alloc_pairs(capacity if capacity is not None else max(1024, 4 * self.n))
 
     # -- buffers ---------------------------------------------------------
-    def _alloc_pairs(self, capacity: int):
-        """Pair buffers, sort workspace and (cached mode) the replay trace,
-        whose worst-case size is tied to the pair capacity."""
+    def _alloc_pairs(self, capacity: int, entries: int | None = None):
+        """Pair buffers, sort workspace and (cached mode) the replay trace:
+        masks per pair slot and `entries` trace entries (default: keep)."""
         capacity = int(capacity)
+        if entries is not None:
+            self.entry_capacity = min(int(entries), MAX_ENTRIES)
         d = self.device
         self.capacity = capacity
         self.keys = self.values = self.workspace = self.trace = None
@@ -69,19 +91,12 @@ class Rasterizer:
         ws = B.pgs_bin_sort_workspace(self.n, capacity)
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=d)
         if self.cached:
-            ents = B.pgs_trace_entries(capacity, self.tw, self.th)
-            self.trace = dict(
-                mask=torch.empty((max(capacity, 1), self.nw), dtype=torch.int64, device=d),
-                steps=torch.empty((self.n_tiles, self.nw), dtype=torch.int32, device=d),
-                entry=torch.empty((max(ents, 1), 4), dtype=torch.float32, device=d),
-                count=torch.empty(self.H * self.W, dtype=torch.int32, device=d),
-                entry_capacity=max(ents, 1), pair_capacity=capacity,
-            )
+            self.trace = new_trace(capacity, self.nw, self.n_tiles, self.H * self.W, self.entry_capacity, d)
 
     def reserve(self, pair_factor: float = 2.0):
-        """Enlarge the pair capacity (and the trace with it) ahead of
-        training, whose Gaussians grow and touch more tiles over time."""
-        self._alloc_pairs(int(self.capacity * pair_factor))
+        """Enlarge the pair capacity and the trace entries ahead of training,
+        whose Gaussians grow and touch more tiles over time."""
+        self._alloc_pairs(int(self.capacity * pair_factor), int(self.entry_capacity * pair_factor))
 
     def trace_bytes(self) -> int:
         if self.trace is None:
@@ -121,7 +136,14 @@ class Rasterizer:
                 return self.image
             if f & (PGS_FLAG_PAIR_OVERFLOW | PGS_FLAG_CACHE_OVERFLOW):
                 need = int(self.num_pairs.item())
-                self._alloc_pairs(int(math.ceil(max(need, self.capacity) * headroom)) + 1024)
+                cap = self.capacity
+                if need > cap:
+                    cap = int(math.ceil(need * headroom)) + 1024
+                ents = self.entry_capacity
+                used = int(self.trace["used"].item()) if self.trace is not None else 0
+                if used > ents:
+                    ents = int(math.ceil(used * headroom)) + 4096
+                self._alloc_pairs(cap, ents)
         raise RuntimeError("rasterizer buffers kept overflowing")
 
     def backward(self, params, cam, dl_dimage, grads, bg=(0.0, 0.0, 0.0), zero_grad2d=True):

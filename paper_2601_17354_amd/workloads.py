@@ -96,3 +96,27 @@ def compare_inits(weights, scene_seeds=(200, 201, 202), n_points=200_000, n_gt=4
     mean = {n: {str(k): round(float(np.mean([per_scene[sc][n][str(k)] for sc in per_scene])), 3)
                 for k in eval_at} for n in names}
     return dict(per_scene=per_scene, mean=mean, fallbacks=fallbacks)
+
+
+def batched_workload(n=1_000_000, sh_degree=3, n_gt=500_000, scene_seed=0, device="cuda"):
+    """Eight ring views of uneven resolution (640x480 .. 1920x1440) of the
+    spheres-and-planes scene; the trained set = plain seed of an n-point
+    noisy cloud with SH coefficients up to sh_degree (higher ones zero);
+    targets = the ground truth rendered at each view."""
+    from .batch import mixed_views
+    from .raster import param_rows
+    dev = torch.device(device)
+    scene = synth.spheres_planes_scene(scene_seed)
+    cams = mixed_views()
+    gt = torch.as_tensor(synth.surface_gaussians(scene, n_gt, seed=1000 + scene_seed, sh_degree=0, opacity=0.95),
+                         device=dev)
+    targets = [render_targets(gt, 0, [c], c["width"], c["height"])[0] for c in cams]
+    del gt
+    pts, col = synth.noisy_cloud(scene, n, seed=3000 + scene_seed)
+    P = torch.as_tensor(np.ascontiguousarray(pts.T), device=dev)
+    C = torch.as_tensor(np.ascontiguousarray(col.T), device=dev)
+    p14 = seed_pca(P, C)
+    params = torch.zeros((param_rows(sh_degree), n), dtype=torch.float32, device=dev)
+    params[:14] = p14
+    torch.cuda.synchronize()
+    return dict(params0=params, cams=cams, targets=targets, sh_degree=sh_degree)

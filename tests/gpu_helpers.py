@@ -97,7 +97,7 @@ def trace_entries(out, cam, x, y, tile=(16, 16)):
     start, end = (int(v) for v in out["ranges"][:, t])
     steps = int(R.trace["steps"][t, w].item())
     masks = R.trace["mask"][start:start + steps, w].cpu().numpy().view(np.uint64)
-    ebase = nt * start + 64 * (end - start) * w
+    ebase = int(R.trace["base"][t, w].item()) & 0xFFFFFFFF
     cursor, ents = 0, []
     for j, m in enumerate(masks):
         m = int(m)

@@ -161,7 +161,7 @@ def test_trace_poison_counter_reset_is_exact():
     dl = torch.as_tensor(np.random.default_rng(1).normal(size=(3, 128, 128)).astype(np.float32), device=DEV)
     outs, imgs = [], []
     for mode in ("nan", "zero", "stale"):
-        R = Rasterizer(P.shape[1], 0, 128, 128, cached=True, capacity=40000)
+        R = Rasterizer(P.shape[1], 0, 128, 128, cached=True, capacity=40000, entries=1 << 20)
         if mode == "stale":
             R.forward_checked(torch.as_tensor(P_other, device=DEV), cam)
         else:
@@ -169,7 +169,7 @@ def test_trace_poison_counter_reset_is_exact():
             R.trace["entry"].fill_(fill)
             R.trace["mask"].fill_(-1 if mode == "nan" else 0)
         R.forward_checked(params, cam)
-        assert R.capacity == 40000          # no reallocation wiped the poison
+        assert R.capacity == 40000 and R.entry_capacity == 1 << 20   # no reallocation wiped the poison
         grads = torch.zeros_like(params)
         R.backward(params, cam, dl, grads)
         torch.cuda.synchronize()
@@ -214,6 +214,18 @@ def test_overflow_flags_and_recovery():
     R.flags.zero_()
     R.forward(params, cam)
     assert R.read_flags() == PGS_FLAG_CACHE_OVERFLOW
+    # too few trace entries: the waves that do not fit are left unrecorded,
+    # the counter reports the demand and a checked forward recovers
+    R2 = Rasterizer(P.shape[1], 0, 128, 128, cached=True, capacity=R.capacity, entries=500)
+    R2.flags.zero_()
+    R2.forward(params, cam)
+    assert R2.read_flags() == PGS_FLAG_CACHE_OVERFLOW
+    need = int(R2.trace["used"].item())
+    assert need > 500
+    R2.forward_checked(params, cam)
+    assert R2.read_flags() == 0 and R2.entry_capacity >= need
+    np.testing.assert_array_equal(R2.image.cpu().numpy(), ref["image"])
+    assert int(R2.trace["count"].sum().item()) == need
 
 
 @pytest.mark.parametrize("kind", ["empty", "all-culled", "single", "huge", "flat-edge-on"])
