@@ -38,12 +38,15 @@ def parse():
     ap.add_argument("--height", type=int, default=1440)
     ap.add_argument("--views", type=int, default=0, help="training views to render targets for (0: all 52)")
     ap.add_argument("--no-psnr", action="store_true", help="skip the 500-step PSNR runs")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched multi-view step (1M Gaussians, 8 views, SH 3, tuned)")
+    ap.add_argument("--batched-gaussians", type=int, default=1_000_000)
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 4 views, 4 steps, one 1 GiB stream copy")
     args = ap.parse_args()
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
-        args.no_compare = args.no_cpu_baseline = args.no_psnr = True
+        args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = True
     return args
 
 
@@ -149,6 +152,69 @@ def psnr_runs(wl, order, iters=500, at=(0, 100, 500)):
         del tr
         torch.cuda.empty_cache()
     return out
+
+
+def batched_runs(n, steps=20, warmup=3):
+    """The batched multi-view step: 8 views of uneven resolution (9.73M
+    pixels), n Gaussians at SH degree 3, tuned tile shape and LDS batch,
+    captured as a graph; beside it the same eight views stepped one view at
+    a time with the single-view kernels (eager), for the batching gain."""
+    import torch
+    from paper_2601_17354_amd import binding as B
+    from paper_2601_17354_amd.autotune import tune
+    from paper_2601_17354_amd.batch import BatchedStep, time_steps
+    from paper_2601_17354_amd.raster import Rasterizer
+    from paper_2601_17354_amd.train import BETA1, BETA2, EPS, learning_rates
+    from paper_2601_17354_amd.workloads import batched_workload
+    wl = batched_workload(n=n)
+    cams, targets, sh = wl["cams"], wl["targets"], wl["sh_degree"]
+    log(f"batched workload ready: {n} Gaussians, {len(cams)} views")
+    tuned = tune(wl["params0"], sh, cams, targets, cached=True, use_cache=False, log=log, extent=4.5)
+    log(f"tuned: tile {tuned['tile']} batch {tuned['batch']} ({tuned['seconds']} s)")
+    st = BatchedStep(wl["params0"].clone(), sh, cams, targets, tile=tuple(tuned["tile"]), batch=tuned["batch"],
+                     extent=4.5)
+    st.prepare()
+    st._alloc_pairs(int(st.capacity * 1.25), int(st.entry_capacity * 1.25))
+    ms_eager = time_steps(st.step, max(5, steps // 4), 2)
+    st.capture()
+    ms_graph = time_steps(st.replay, steps, warmup)
+    assert st.read_flags() == 0, "batched step overflowed during timing"
+    stats = st.stats()
+    del st
+    torch.cuda.empty_cache()
+    # one view at a time, single-view kernels, one Adam step per eight views
+    params = wl["params0"].clone()
+    grads, m, v = torch.zeros_like(params), torch.zeros_like(params), torch.zeros_like(params)
+    lr = learning_rates(sh, 4.5)
+    rasts = [Rasterizer(n, sh, c["width"], c["height"], cached=True) for c in cams]
+    dls = [torch.empty_like(t) for t in targets]
+    loss = torch.zeros(1, device=params.device)
+    ws = torch.empty(max(B.pgs_loss_workspace(c["width"], c["height"]) for c in cams), dtype=torch.uint8,
+                     device=params.device)
+    for r, c in zip(rasts, cams):
+        r.forward_checked(params, c)
+        r.reserve(1.25)
+    count = [0]
+
+    def per_view_step():
+        grads.zero_()
+        for r, c, t, dl in zip(rasts, cams, targets, dls):
+            r.forward(params, c)
+            B.pgs_loss_l1_dssim(r.image, t, c["width"], c["height"], 0.2, loss, dl, ws)
+            r.backward(params, c, dl, grads)
+        count[0] += 1
+        B.pgs_adam_step(params, grads, m, v, params.shape[0], n, lr, count[0], BETA1, BETA2, EPS)
+
+    ms_views = time_steps(per_view_step, max(5, steps // 4), 2)
+    flags = sum(r.read_flags() for r in rasts)
+    del rasts
+    torch.cuda.empty_cache()
+    return {"workload": f"{n} Gaussians, SH 3, 8 views of uneven size (640x480 .. 1920x1440, "
+                        f"{sum(c['width'] * c['height'] for c in cams)} pixels), cached backward, Adam",
+            "tile": tuned["tile"], "batch": tuned["batch"], "ms_per_step_graph": ms_graph,
+            "ms_per_step_eager": ms_eager, "iters_per_s": 1000.0 / ms_graph,
+            "views_per_s": len(cams) * 1000.0 / ms_graph, "ms_per_step_one_view_at_a_time": ms_views,
+            "one_view_at_a_time_flags": flags, "stats": stats, "tuning": tuned["table"]}
 
 
 def achievable_bandwidth(nbytes=1 << 30, reps=10):
@@ -303,6 +369,12 @@ def main():
         from paper_2601_17354_amd.workloads import compare_inits
         log("learned vs plain seeding on three fresh scenes (200k points, 1024x768)")
         out["seeding_fresh_scenes"] = compare_inits(load_weights(), log=log)
+    if not args.no_batched:
+        log("batched multi-view step")
+        out["batched_views"] = batched_runs(args.batched_gaussians)
+        b = out["batched_views"]
+        log(f"batched: {b['ms_per_step_graph']:.2f} ms/step graph, {b['ms_per_step_eager']:.2f} eager, "
+            f"{b['ms_per_step_one_view_at_a_time']:.2f} one view at a time")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.width, args.height, args.gaussians)
