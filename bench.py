@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched multi-view step (1M Gaussians, 8 views, SH 3, tuned)")
     ap.add_argument("--batched-gaussians", type=int, default=1_000_000)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched multi-view step, untuned 16x16 tiles / batch 256, 6 replays "
+                         "(for rocprofv3)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 4 views, 4 steps, one 1 GiB stream copy")
     args = ap.parse_args()
@@ -154,7 +157,7 @@ def psnr_runs(wl, order, iters=500, at=(0, 100, 500)):
     return out
 
 
-def batched_runs(n, steps=20, warmup=3):
+def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
     """The batched multi-view step: 8 views of uneven resolution (9.73M
     pixels), n Gaussians at SH degree 3, tuned tile shape and LDS batch,
     captured as a graph; beside it the same eight views stepped one view at
@@ -169,8 +172,9 @@ def batched_runs(n, steps=20, warmup=3):
     wl = batched_workload(n=n)
     cams, targets, sh = wl["cams"], wl["targets"], wl["sh_degree"]
     log(f"batched workload ready: {n} Gaussians, {len(cams)} views")
-    tuned = tune(wl["params0"], sh, cams, targets, cached=True, use_cache=False, log=log, extent=4.5)
-    log(f"tuned: tile {tuned['tile']} batch {tuned['batch']} ({tuned['seconds']} s)")
+    if tuned is None:
+        tuned = tune(wl["params0"], sh, cams, targets, cached=True, use_cache=False, log=log, extent=4.5)
+        log(f"tuned: tile {tuned['tile']} batch {tuned['batch']} ({tuned['seconds']} s)")
     st = BatchedStep(wl["params0"].clone(), sh, cams, targets, tile=tuple(tuned["tile"]), batch=tuned["batch"],
                      extent=4.5)
     st.prepare()
@@ -182,6 +186,9 @@ def batched_runs(n, steps=20, warmup=3):
     stats = st.stats()
     del st
     torch.cuda.empty_cache()
+    if not compare:
+        return {"tile": tuned["tile"], "batch": tuned["batch"], "ms_per_step_graph": ms_graph,
+                "ms_per_step_eager": ms_eager, "stats": stats}
     # one view at a time, single-view kernels, one Adam step per eight views
     params = wl["params0"].clone()
     grads, m, v = torch.zeros_like(params), torch.zeros_like(params), torch.zeros_like(params)
@@ -241,7 +248,8 @@ def roofline(kernel, avg_ms, nbytes, achievable, backward):
     from paper_2601_17354_amd.profiling import read_traffic
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     summary = os.path.join(ROOT, "profiles", f"{kernel}_{backward}_300k_1920x1440_pmc.txt")
-    traffic = read_traffic(summary, os.path.join(ROOT, "paper_2601_17354_amd", "csrc", "render.hip"))
+    csrc = os.path.join(ROOT, "paper_2601_17354_amd", "csrc")
+    traffic = read_traffic(summary, os.path.join(csrc, "render.hip") + "," + os.path.join(csrc, "render_tile.hpp"))
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": nbytes,
             "avg_ms": avg_ms, "achievable": achievable, "frac_of_achievable": achieved / achievable}
@@ -296,6 +304,11 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
+    if args.batched_only:
+        r = batched_runs(args.batched_gaussians, steps=6, warmup=2, tuned={"tile": [16, 16], "batch": 256,
+                                                                           "table": []}, compare=False)
+        print(json.dumps({"batched_views": r}))
+        return
     from paper_2601_17354_amd.workloads import training_workload
     torch.manual_seed(0)
     rng = np.random.default_rng(0)

@@ -56,7 +56,9 @@ typedef enum pgs_status {
 #define PGS_FLAG_PAIR_OVERFLOW 1u  /* more (tile, Gaussian) pairs than capacity */
 #define PGS_FLAG_CACHE_OVERFLOW 2u /* a tile's pairs exceed the trace's pair capacity */
 
-/* Projected-Gaussian fields, rows of a float32 [PGS_PROJ_FIELDS][n] buffer. */
+/* Projected Gaussians: one 64-byte record per Gaussian, float32
+ * [n][PGS_PROJ_STRIDE] with the fields below at these slots (slots 10..15
+ * are written as zero), so that staging one splat reads one cache line. */
 #define PGS_PROJ_U 0       /* pixel-space mean x */
 #define PGS_PROJ_V 1       /* pixel-space mean y */
 #define PGS_PROJ_DEPTH 2   /* camera-space z, the depth of the sort key */
@@ -68,9 +70,14 @@ typedef enum pgs_status {
 #define PGS_PROJ_G 8
 #define PGS_PROJ_BLUE 9
 #define PGS_PROJ_FIELDS 10
+#define PGS_PROJ_STRIDE 16
 
-/* Rows of the float32 [PGS_GRAD2D_FIELDS][n] 2D-gradient buffer. */
-#define PGS_GRAD2D_FIELDS 9 /* dL/d(u, v, A, B, C, opacity, r, g, b) */
+/* 2D gradients: one 64-byte record per Gaussian, float32
+ * [n][PGS_GRAD2D_STRIDE] with dL/d(u, v, A, B, C, opacity, r, g, b) at
+ * slots 0..8 (slots 9..15 are never written), so that the nine atomic adds
+ * of one splat meet one cache line. */
+#define PGS_GRAD2D_FIELDS 9
+#define PGS_GRAD2D_STRIDE 16
 
 typedef struct pgs_camera {
     int32_t width, height;
@@ -125,9 +132,9 @@ size_t pgs_trace_entries(uint32_t pair_capacity, int32_t tile_w, int32_t tile_h)
  * the views' own arrays concatenated: view v starts at pixel_offset[v] =
  * sum of W_u H_u over u < v, and a 3-channel array holds view v's planar
  * [3][H_v][W_v] block at 3 * pixel_offset[v].  Per-Gaussian arrays are
- * stacked per view: proj [n_views][PGS_PROJ_FIELDS][n], rect
+ * stacked per view: proj [n_views][n][PGS_PROJ_STRIDE], rect
  * [n_views][2][n], touched [n_views][n], 2D gradients
- * [n_views][PGS_GRAD2D_FIELDS][n].
+ * [n_views][n][PGS_GRAD2D_STRIDE].
  *   cams     host array [n_views]
  *   tile_w/h one of 16x16, 8x8, 16x8, 32x8, 8x32 (compositing kernels)
  *   batch    splats staged per LDS batch: 32, 64, 128 or 256
@@ -160,7 +167,7 @@ const char* pgs_last_error(void);
  *   params_dev   [F][n] canonical parameters, F = 11 + 3 (sh_degree+1)^2
  *   cam_host     camera; near plane 0.2, dilation 0.3, J clamp 1.3 x half-FOV
  *   tile_w/h     tile shape used for the rectangle
- *   proj_dev     out [PGS_PROJ_FIELDS][n]
+ *   proj_dev     out [n][PGS_PROJ_STRIDE]
  *   radius_dev   out [n] int32 ceil(3 sqrt(lambda_max)), 0 if culled
  *   rect_dev     out [2][n] uint32 inclusive tile rectangle, packed
  *                (x0 | y0 << 16) then (x1 | y1 << 16); 0 if culled
@@ -266,7 +273,7 @@ pgs_status pgs_tile_order(const uint32_t* ranges_dev, int32_t tiles_in_view, int
  *   cache == NULL  recomputes alpha and T back to front from t_final and
  *                  n_contrib (the recompute-based backward of 3DGS).
  *   dl_dimage_dev  [3][H][W]
- *   grad2d_dev     [PGS_GRAD2D_FIELDS][n], ACCUMULATED (+=) with float atomics;
+ *   grad2d_dev     [n][PGS_GRAD2D_STRIDE], ACCUMULATED (+=) with float atomics;
  *                  the caller zeroes it.
  */
 pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
@@ -281,7 +288,7 @@ pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile_w, int32_t
  * pgs_project_bwd - chain the 2D gradients of one view back to the canonical
  * parameters (exact derivative of pgs_project with culling and clamps frozen:
  * no gradient through a clamped colour channel or a clamped J entry).
- *   grad2d_dev  [PGS_GRAD2D_FIELDS][n] from pgs_render_bwd
+ *   grad2d_dev  [n][PGS_GRAD2D_STRIDE] from pgs_render_bwd
  *   radius_dev  from pgs_project (culled Gaussians get no gradient)
  *   grads_dev   [F][n] ACCUMULATED (+=); one thread per Gaussian, no atomics,
  *               so views must be enqueued one after another on one stream.
@@ -334,7 +341,7 @@ pgs_status pgs_adam_step(float* params_dev, const float* grads_dev, float* m_dev
  * bits(float32 depth_v) and value = canonical id, emitted view by view in
  * canonical order, so the sorted list is the per-view lists one after the
  * other and ranges index the global tiles.
- *   proj_all_dev [n_views][PGS_PROJ_FIELDS][n]; rect_all_dev [n_views][2][n];
+ *   proj_all_dev [n_views][n][PGS_PROJ_STRIDE]; rect_all_dev [n_views][2][n];
  *   touched_all_dev [n_views][n] (pgs_project of each view with the batch's
  *   tile shape); ranges_dev out [2][total tiles];
  *   workspace >= pgs_bin_sort_workspace(n_views * n, capacity).

@@ -21,7 +21,7 @@ import math
 import torch
 
 from . import binding as B
-from ._lib import GRAD2D_FIELDS, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_FIELDS
+from ._lib import GRAD2D_STRIDE, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_STRIDE
 from .raster import MAX_ENTRIES, new_trace, param_rows
 from .train import BETA1, BETA2, EPS, learning_rates
 
@@ -44,7 +44,7 @@ class BatchedStep:
         self.tw, self.th = self.views.tile_w, self.views.tile_h
         self.nt = self.views.n_tiles
         self.npx = self.views.n_pixels
-        self.proj = torch.empty((V, PROJ_FIELDS, n), dtype=torch.float32, device=d)
+        self.proj = torch.empty((V, n, PROJ_STRIDE), dtype=torch.float32, device=d)
         self.radius = torch.empty((V, n), dtype=torch.int32, device=d)
         self.rect = torch.empty((V, 2, n), dtype=torch.int32, device=d)
         self.touched = torch.empty((V, n), dtype=torch.int32, device=d)
@@ -60,7 +60,7 @@ class BatchedStep:
         self.target = torch.empty(3 * self.npx, dtype=torch.float32, device=d)
         for v, t in enumerate(targets):
             self.view_slice(self.target, v).copy_(t.reshape(3, self.cams[v]["height"], self.cams[v]["width"]))
-        self.grad2d = torch.zeros((V, GRAD2D_FIELDS, n), dtype=torch.float32, device=d)
+        self.grad2d = torch.zeros((V, n, GRAD2D_STRIDE), dtype=torch.float32, device=d)
         self.grads = torch.zeros_like(self.params)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)

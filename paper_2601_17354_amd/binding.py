@@ -83,6 +83,11 @@ def pgs_version() -> str:
 def pgs_project(params, n, sh_degree, cam, tile_w, tile_h, proj, radius, rect, touched, stream=None):
     lib = _lib.load()
     c = camera_struct(cam)
+    _need(params, (11 + 3 * (sh_degree + 1) ** 2) * n, "params")
+    _need(proj, 16 * n, "proj")
+    _need(radius, n, "radius")
+    _need(rect, 2 * n, "rect")
+    _need(touched, n, "touched")
     check(lib.pgs_project(_ptr(params, F32), n, sh_degree, ctypes.byref(c), tile_w, tile_h,
                           _ptr(proj, F32), _ptr(radius, I32), _ptr(rect, I32), _ptr(touched, I32),
                           _stream(stream)), "pgs_project")
@@ -95,6 +100,8 @@ def pgs_bin_sort_workspace(n, capacity) -> int:
 def pgs_bin_sort(n, proj, rect, touched, tiles_x, n_tiles, view_tile_offset, capacity, keys, values,
                  ranges, num_pairs, flags, workspace, stream=None):
     lib = _lib.load()
+    _need(proj, 16 * n, "proj")
+    _need(ranges, 2 * n_tiles, "ranges")
     check(lib.pgs_bin_sort(n, _ptr(proj, F32), _ptr(rect, I32), _ptr(touched, I32), tiles_x, n_tiles,
                            view_tile_offset, capacity, _ptr(keys, I64), _ptr(values, I32),
                            _ptr(ranges, I32), _ptr(num_pairs, I32), _ptr(flags, I32),
@@ -122,6 +129,10 @@ def pgs_tile_order(ranges, tiles_in_view, view_tile_offset, n_tiles, order, stre
 def pgs_render_fwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_tile_offset, bg,
                    image, t_final, n_contrib, trace, flags, tile_order=None, stream=None):
     lib = _lib.load()
+    _need(proj, 16 * n, "proj")
+    _need(image, 3 * width * height, "image")
+    _need(t_final, width * height, "t_final")
+    _need(n_contrib, width * height, "n_contrib")
     r = replay_struct(trace)
     check(lib.pgs_render_fwd(width, height, tile_w, tile_h, _ptr(proj, F32), n, _ptr(values, I32),
                              _ptr(ranges, I32), view_tile_offset, _f3(bg), _ptr(image, F32),
@@ -133,6 +144,9 @@ def pgs_render_fwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_
 def pgs_render_bwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_tile_offset, bg,
                    t_final, n_contrib, trace, dl_dimage, grad2d, tile_order=None, stream=None):
     lib = _lib.load()
+    _need(proj, 16 * n, "proj")
+    _need(grad2d, 16 * n, "grad2d")
+    _need(dl_dimage, 3 * width * height, "dl_dimage")
     r = replay_struct(trace)
     check(lib.pgs_render_bwd(width, height, tile_w, tile_h, _ptr(proj, F32), n, _ptr(values, I32),
                              _ptr(ranges, I32), view_tile_offset, _f3(bg), _ptr(t_final, F32),
@@ -144,6 +158,8 @@ def pgs_render_bwd(width, height, tile_w, tile_h, proj, n, values, ranges, view_
 def pgs_project_bwd(params, n, sh_degree, cam, radius, grad2d, grads, stream=None):
     lib = _lib.load()
     c = camera_struct(cam)
+    _need(grad2d, 16 * n, "grad2d")
+    _need(grads, (11 + 3 * (sh_degree + 1) ** 2) * n, "grads")
     check(lib.pgs_project_bwd(_ptr(params, F32), n, sh_degree, ctypes.byref(c), _ptr(radius, I32),
                               _ptr(grad2d, F32), _ptr(grads, F32), _stream(stream)), "pgs_project_bwd")
 
@@ -306,7 +322,7 @@ def pgs_bin_sort_views(views, n, proj_all, rect_all, touched_all, capacity, keys
                        flags, workspace, stream=None):
     lib = _lib.load()
     _need(ranges, 2 * views.n_tiles, "ranges")
-    _need(proj_all, views.n_views * 10 * n, "proj_all")
+    _need(proj_all, views.n_views * 16 * n, "proj_all")
     _need(keys, capacity, "keys")
     _need(values, capacity, "values")
     check(lib.pgs_bin_sort_views(ctypes.byref(views.struct), n, _ptr(proj_all, F32), _ptr(rect_all, I32),
@@ -336,7 +352,7 @@ def pgs_render_bwd_views(views, proj_all, n, values, ranges, bg, t_final_all, n_
                          grad2d_all, tile_order, queue, stream=None):
     lib = _lib.load()
     _need(dl_all, 3 * views.n_pixels, "dl_all")
-    _need(grad2d_all, views.n_views * 9 * n, "grad2d_all")
+    _need(grad2d_all, views.n_views * 16 * n, "grad2d_all")
     _need(tile_order, views.n_tiles, "tile_order")
     bg_arr = (ctypes.c_float * 3)(*[float(x) for x in bg])
     rep = replay_struct(trace)

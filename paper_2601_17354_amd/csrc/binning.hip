@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_emit(int n, const float* __restrict__ d
     uint32_t idx = offsets[i];
     const uint32_t r0 = rect[i], r1 = rect[(size_t)n + i];
     const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff, y1 = r1 >> 16;
-    const uint64_t dbits = (uint64_t)__float_as_uint(depth[i]);
+    const uint64_t dbits = (uint64_t)__float_as_uint(depth[(size_t)i * PGS_PROJ_STRIDE]);
     for (uint32_t ty = y0; ty <= y1; ++ty)
         for (uint32_t tx = x0; tx <= x1; ++tx, ++idx) {
             if (idx >= capacity) return;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_emit_views(int n, EmitViews ev, const f
     const uint32_t r0 = rect[g], r1 = rect[(size_t)n + g];
     const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff, y1 = r1 >> 16;
     const uint64_t dbits =
-        (uint64_t)__float_as_uint(proj_all[(size_t)v * PGS_PROJ_FIELDS * n + (size_t)PGS_PROJ_DEPTH * n + g]);
+        (uint64_t)__float_as_uint(proj_all[((size_t)v * n + g) * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
     for (uint32_t ty = y0; ty <= y1; ++ty)
         for (uint32_t tx = x0; tx <= x1; ++tx, ++idx) {
             if (idx >= capacity) return;
@@ -446,7 +446,7 @@ extern "C" pgs_status pgs_bin_sort(int32_t n, const float* proj_dev, const uint3
     if (n == 0) return PGS_OK;
     pgs_status st = scan_u32(touched_dev, offsets, (uint32_t)n, num_pairs_dev, partial, s);
     if (st != PGS_OK) return st;
-    k_emit<<<(n + 255) / 256, 256, 0, s>>>(n, proj_dev + (size_t)PGS_PROJ_DEPTH * n, rect_dev,
+    k_emit<<<(n + 255) / 256, 256, 0, s>>>(n, proj_dev + PGS_PROJ_DEPTH, rect_dev,
                                             touched_dev, offsets, num_pairs_dev, tiles_x,
                                             view_tile_offset, capacity, keys_dev, values_dev, flags_dev);
     PGS_CHECK_LAUNCH("pgs_bin_sort emit");

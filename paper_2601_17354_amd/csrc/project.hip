@@ -193,7 +193,12 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, in
         ok = isfinite(u) && isfinite(v) && x0 <= x1 && y0 <= y1;
     }
     if (!ok) {
-        for (int f = 0; f < PGS_PROJ_FIELDS; ++f) out[(size_t)f * n + i] = 0.f;
+        float4* rec = reinterpret_cast<float4*>(out + (size_t)i * PGS_PROJ_STRIDE);
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec[0] = z;
+        rec[1] = z;
+        rec[2] = z;
+        rec[3] = z;
         radius[i] = 0;
         rect[i] = 0;
         rect[(size_t)n + i] = 0;
@@ -215,16 +220,15 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, in
         col[ch] = fmax(acc, 0.0);
     }
     const double o = 1.0 / (1.0 + exp(-prow(P, 10, n, i)));
-    out[(size_t)PGS_PROJ_U * n + i] = (float)u;
-    out[(size_t)PGS_PROJ_V * n + i] = (float)v;
-    out[(size_t)PGS_PROJ_DEPTH * n + i] = (float)G.z;
-    out[(size_t)PGS_PROJ_A * n + i] = (float)(G.c / G.det);
-    out[(size_t)PGS_PROJ_B * n + i] = (float)(-G.b / G.det);
-    out[(size_t)PGS_PROJ_C * n + i] = (float)(G.a / G.det);
-    out[(size_t)PGS_PROJ_OPACITY * n + i] = (float)o;
-    out[(size_t)PGS_PROJ_R * n + i] = (float)col[0];
-    out[(size_t)PGS_PROJ_G * n + i] = (float)col[1];
-    out[(size_t)PGS_PROJ_BLUE * n + i] = (float)col[2];
+    static_assert(PGS_PROJ_U == 0 && PGS_PROJ_V == 1 && PGS_PROJ_DEPTH == 2 && PGS_PROJ_A == 3 &&
+                      PGS_PROJ_B == 4 && PGS_PROJ_C == 5 && PGS_PROJ_OPACITY == 6 && PGS_PROJ_R == 7 &&
+                      PGS_PROJ_G == 8 && PGS_PROJ_BLUE == 9 && PGS_PROJ_STRIDE == 16,
+                  "record layout");
+    float4* rec = reinterpret_cast<float4*>(out + (size_t)i * PGS_PROJ_STRIDE);
+    rec[0] = make_float4((float)u, (float)v, (float)G.z, (float)(G.c / G.det));
+    rec[1] = make_float4((float)(-G.b / G.det), (float)(G.a / G.det), (float)o, (float)col[0]);
+    rec[2] = make_float4((float)col[1], (float)col[2], 0.f, 0.f);
+    rec[3] = make_float4(0.f, 0.f, 0.f, 0.f);
     radius[i] = (int)r;
     const uint32_t ix0 = (uint32_t)x0, ix1 = (uint32_t)x1, iy0 = (uint32_t)y0, iy1 = (uint32_t)y1;
     rect[i] = ix0 | (iy0 << 16);
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P
     constexpr int K = (D + 1) * (D + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || radius[i] == 0) return;
-    auto gin = [&](int f) { return (double)g2d[(size_t)f * n + i]; };
+    auto gin = [&](int f) { return (double)g2d[(size_t)i * PGS_GRAD2D_STRIDE + f]; };
     const double gu = gin(0), gv = gin(1), gA = gin(2), gB = gin(3), gC = gin(4), go = gin(5);
     const double gcol[3] = {gin(6), gin(7), gin(8)};
 

@@ -70,13 +70,16 @@ __device__ __forceinline__ bool splat_alpha(const Splat& s, float px, float py, 
     return alpha >= kAlphaMin;
 }
 
+// One splat's record (u, v, depth, A | B, C, o, r | g, b, -, -) is one
+// 64-byte line: three 16-byte loads.
 __device__ __forceinline__ void stage_splat(const float* __restrict__ proj, int n, uint32_t g,
                                             float4* sa, float4* sb, float* sc, int slot) {
-    sa[slot] = make_float4(proj[(size_t)PGS_PROJ_U * n + g], proj[(size_t)PGS_PROJ_V * n + g],
-                           proj[(size_t)PGS_PROJ_A * n + g], proj[(size_t)PGS_PROJ_B * n + g]);
-    sb[slot] = make_float4(proj[(size_t)PGS_PROJ_C * n + g], proj[(size_t)PGS_PROJ_OPACITY * n + g],
-                           proj[(size_t)PGS_PROJ_R * n + g], proj[(size_t)PGS_PROJ_G * n + g]);
-    sc[slot] = proj[(size_t)PGS_PROJ_BLUE * n + g];
+    (void)n;
+    const float4* rec = reinterpret_cast<const float4*>(proj + (size_t)g * PGS_PROJ_STRIDE);
+    const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+    sa[slot] = make_float4(r0.x, r0.y, r0.w, r1.x);   // u, v, A, B
+    sb[slot] = make_float4(r1.y, r1.z, r1.w, r2.x);   // C, o, r, g
+    sc[slot] = r2.y;                                  // b
 }
 
 __device__ __forceinline__ Splat load_splat(const float4* sa, const float4* sb, const float* sc, int k) {
@@ -326,14 +329,16 @@ __device__ __forceinline__ void accumulate(const float* v, float (*acc)[BG], int
 }
 
 // One float atomic per field and splat of the batch into the canonical
-// 2D-gradient rows (index map values[id]).
+// 2D-gradient records (index map values[id]); the nine fields of a splat
+// share one 64-byte record, so consecutive lanes hit the same line.
 template <int BG>
 __device__ __forceinline__ void flush_batch(float (*acc)[BG], const uint32_t* gid, int nb, int n,
                                             float* __restrict__ grad2d, int t, int NT) {
+    (void)n;
     for (int idx = t; idx < nb * 9; idx += NT) {
-        const int f = idx / nb, jj = idx - f * nb;
+        const int jj = idx / 9, f = idx - jj * 9;
         const float s = acc[f][jj];
-        if (s != 0.f) unsafeAtomicAdd(&grad2d[(size_t)f * n + gid[jj]], s);
+        if (s != 0.f) unsafeAtomicAdd(&grad2d[(size_t)gid[jj] * PGS_GRAD2D_STRIDE + f], s);
     }
 }
 

@@ -49,7 +49,7 @@ __device__ __forceinline__ TileJob job_of(const ViewTable& vt, int gt, const flo
     const int tile = gt - vt.tile_off[v];
     const size_t p0 = (size_t)vt.pix_off[v];
     return TileJob{vt.W[v], vt.H[v], tile % vt.TX[v], tile / vt.TX[v], gt,
-                   proj_all + (size_t)v * PGS_PROJ_FIELDS * n,
+                   proj_all + (size_t)v * PGS_PROJ_STRIDE * n,
                    image_all ? image_all + 3 * p0 : nullptr, t_final_all ? t_final_all + p0 : nullptr,
                    n_contrib_all ? n_contrib_all + p0 : nullptr, count_all ? count_all + p0 : nullptr};
 }
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_views(
         const TileJob j = job_of(vt, gt, proj_all, n, nullptr, const_cast<float*>(t_final_all),
                                  const_cast<uint32_t*>(n_contrib_all), nullptr, v);
         const float* dl = dl_all + 3 * (size_t)vt.pix_off[v];
-        float* g2 = grad2d_all + (size_t)v * PGS_GRAD2D_FIELDS * n;
+        float* g2 = grad2d_all + (size_t)v * PGS_GRAD2D_STRIDE * n;
         if constexpr (CACHED)
             pgs::bwd_cached_tile<TW, TH, BG>(j, n_tiles_total, n, values, ranges, tr, dl, g2, L);
         else

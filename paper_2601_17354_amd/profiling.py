@@ -2,7 +2,7 @@
 
     python -m paper_2601_17354_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
     python -m paper_2601_17354_amd.profiling pmc <fetch_dir> <write_dir> <kernel substring>
-           <copy_bytes> <source file> <out.txt> "<command>"
+           <copy_bytes> <source file[,file...]> <out.txt> "<command>"
 
 The PMC summary scales each kernel's FETCH_SIZE / WRITE_SIZE (KiB per
 dispatch) by the ratio known-bytes / counter-reading of the plain copy kernel
@@ -20,8 +20,17 @@ import os
 import sys
 
 
-def source_sha(path: str) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_sha(paths: str) -> str:
+    """SHA-256 (first 16 hex digits) of one source file, or of several
+    comma-separated files concatenated in order."""
+    h = hashlib.sha256()
+    for p in paths.split(","):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _names(paths: str) -> str:
+    return "+".join(os.path.basename(p) for p in paths.split(","))
 
 
 def _short(name: str) -> str:
@@ -73,7 +82,7 @@ def summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes, source, out_txt, com
     lines = [
         f"command: {command}",
         f"kernel: {_short(name)}",
-        f"source: {os.path.basename(source)} sha256[:16]={source_sha(source)}",
+        f"source: {_names(source)} sha256[:16]={source_sha(source)}",
         f"dispatches: fetch {nf}, write {nw}",
         f"FETCH_SIZE_KiB_per_dispatch: {fk:.1f}",
         f"WRITE_SIZE_KiB_per_dispatch: {wk:.1f}",

@@ -16,7 +16,7 @@ import math
 import torch
 
 from . import binding as B
-from ._lib import GRAD2D_FIELDS, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_FIELDS
+from ._lib import GRAD2D_STRIDE, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_STRIDE
 
 
 def param_rows(sh_degree: int) -> int:
@@ -57,7 +57,7 @@ class Rasterizer:
         self.device = torch.device(device)
         d = self.device
         n = max(self.n, 1)
-        self.proj = torch.empty((PROJ_FIELDS, n), dtype=torch.float32, device=d)
+        self.proj = torch.empty((n, PROJ_STRIDE), dtype=torch.float32, device=d)
         self.radius = torch.empty(n, dtype=torch.int32, device=d)
         self.rect = torch.empty((2, n), dtype=torch.int32, device=d)
         self.touched = torch.empty(n, dtype=torch.int32, device=d)
@@ -67,7 +67,7 @@ class Rasterizer:
         self.image = torch.empty((3, self.H, self.W), dtype=torch.float32, device=d)
         self.t_final = torch.empty((self.H, self.W), dtype=torch.float32, device=d)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
-        self.grad2d = torch.zeros((GRAD2D_FIELDS, n), dtype=torch.float32, device=d)
+        self.grad2d = torch.zeros((n, GRAD2D_STRIDE), dtype=torch.float32, device=d)
         # heavy-first launch order of the tiles (scheduling only)
         self.tile_order = torch.empty(self.n_tiles, dtype=torch.int32, device=d) if ordered else None
         self.capacity = 0

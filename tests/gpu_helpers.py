@@ -63,7 +63,7 @@ def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None,
     R.forward_checked(params, cam, bg)
     torch.cuda.synchronize()
     out = dict(
-        proj=R.proj.cpu().numpy()[:, :n], radius=R.radius.cpu().numpy()[:n],
+        proj=R.proj.cpu().numpy()[:n].T, radius=R.radius.cpu().numpy()[:n],
         rect=R.rect.cpu().numpy()[:, :n].view(np.uint32), touched=R.touched.cpu().numpy()[:n],
         num_pairs=int(R.num_pairs.item()), image=R.image.cpu().numpy(),
         t_final=R.t_final.cpu().numpy(), n_contrib=R.n_contrib.cpu().numpy(),
@@ -79,7 +79,7 @@ def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None,
         dl = torch.as_tensor(np.ascontiguousarray(dl_dimage, np.float32), device=dev)
         R.backward(params, cam, dl, grads, bg)
         torch.cuda.synchronize()
-        out["grad2d"] = R.grad2d.cpu().numpy()[:, :n]
+        out["grad2d"] = R.grad2d.cpu().numpy()[:n, :9].T
         out["grads"] = grads.cpu().numpy()
     return out
 
