@@ -57,7 +57,7 @@ typedef enum pgs_status {
 #define PGS_FLAG_CACHE_OVERFLOW 2u /* a tile's pairs exceed the trace's pair capacity */
 
 /* Projected Gaussians: one 64-byte record per Gaussian, float32
- * [n][PGS_PROJ_STRIDE] with the fields below at these slots (slots 10..15
+ * [n][PGS_PROJ_STRIDE] with the fields below at these slots (slots 12..15
  * are written as zero), so that staging one splat reads one cache line. */
 #define PGS_PROJ_U 0       /* pixel-space mean x */
 #define PGS_PROJ_V 1       /* pixel-space mean y */
@@ -69,7 +69,9 @@ typedef enum pgs_status {
 #define PGS_PROJ_R 7       /* view-dependent colour */
 #define PGS_PROJ_G 8
 #define PGS_PROJ_BLUE 9
-#define PGS_PROJ_FIELDS 10
+#define PGS_PROJ_EXTENT_X 10 /* half-extents of the pixels where alpha can reach */
+#define PGS_PROJ_EXTENT_Y 11 /* 1/255 (conservative; -1 = nowhere, inf = unknown) */
+#define PGS_PROJ_FIELDS 12
 #define PGS_PROJ_STRIDE 16
 
 /* 2D gradients: one 64-byte record per Gaussian, float32
@@ -88,8 +90,10 @@ typedef struct pgs_camera {
 /* Forward replay trace S = {id, C_in, alpha} (replay-cache subsection),
  * stored per wave of 64 pixels (lanes = row-major pixels of the tile, wave w
  * holds pixels 64w .. 64w+63) as groups, one group per sorted splat id:
- *   mask_dev   [pair_capacity][TW*TH/64] uint64: bit l of mask[id][w] is set
- *              when pixel (lane l of wave w) recorded an entry for splat id
+ *   mask_dev   [TW*TH/64][pair_capacity] uint64 (wave-major, so that a wave
+ *              writes and reads 64 consecutive masks as one run): bit l of
+ *              mask[w][id] is set when pixel (lane l of wave w) recorded an
+ *              entry for splat id
  *              (id = index in the sorted pair list; values[id] is the
  *              canonical index, the permutation pi of the index map)
  *   steps_dev  [n_tiles][TW*TH/64] uint32: per wave, the number of list

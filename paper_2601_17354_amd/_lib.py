@@ -18,7 +18,7 @@ PGS_ERR_INVALID_ARG = 1
 PGS_ERR_HIP = 2
 PGS_FLAG_PAIR_OVERFLOW = 1
 PGS_FLAG_CACHE_OVERFLOW = 2
-PROJ_FIELDS = 10
+PROJ_FIELDS = 12
 PROJ_STRIDE = 16
 GRAD2D_FIELDS = 9
 GRAD2D_STRIDE = 16

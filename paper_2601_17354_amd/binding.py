@@ -58,7 +58,7 @@ def replay_struct(trace) -> PgsReplay | None:
     r.entry_dev = _ptr(trace["entry"], torch.float32).value
     _need(trace["steps"], trace["base"].numel(), "trace base")
     _need(trace["entry"], 4 * int(trace["entry_capacity"]), "trace entries")
-    _need(trace["mask"], int(trace["pair_capacity"]), "trace masks")
+    _need(trace["mask"], int(trace["pair_capacity"]) * trace["steps"].shape[-1], "trace masks")
     r.count_dev = _ptr(trace["count"], torch.int32).value
     r.entry_capacity = int(trace["entry_capacity"])
     r.pair_capacity = int(trace["pair_capacity"])

@@ -167,6 +167,34 @@ __device__ __forceinline__ void geometry(const float* __restrict__ P, int n, int
     G.det = G.a * G.c - G.b * G.b;
 }
 
+// Half-extents (x, y) of the pixel region where the compositing kernels can
+// find alpha >= 1/255 for a splat with the float32 conic (A, B, C) and
+// opacity o that they read.  The region is the ellipse
+// A dx^2 + 2B dx dy + C dy^2 <= tau, tau = 2 ln(255 o), enlarged so that it
+// also covers the float32 evaluation of the quadratic form (relative error
+// below 20 * 2^-24 / (1 - rho), rho = |B| / sqrt(AC)) and of exp (1e-3 added
+// to tau).  (-1, -1) when o is below the threshold (no pixel qualifies);
+// (inf, inf) when the conic is too close to degenerate (1 - rho < 1e-3) for
+// the bound, so that nothing is skipped.
+__device__ void alpha_extent(float A, float B, float C, float o, float& hx, float& hy) {
+    if (o < pgs::kAlphaMin * (1.0f - 1e-6f)) {
+        hx = hy = -1.f;
+        return;
+    }
+    const double a = A, b = B, c = C;
+    const double det = a * c - b * b;
+    const double one_m_rho = 1.0 - fabs(b) / sqrt(a * c);
+    if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0) || !(one_m_rho >= 1e-3)) {
+        hx = hy = INFINITY;
+        return;
+    }
+    const double tau = 2.0 * log(255.0 * fmax((double)o, 1.0 / 255.0));
+    const double eta = 20.0 * 0x1p-24 / one_m_rho;
+    const double t = (tau + 1e-3) / (1.0 - eta);
+    hx = (float)(sqrt(t * c / det) * (1.0 + 1e-5) + 1e-2);
+    hy = (float)(sqrt(t * a / det) * (1.0 + 1e-5) + 1e-2);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, int n, CamD cam,
                                                  int tw, int th, int TX, int TY,
@@ -225,9 +253,13 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, in
                       PGS_PROJ_G == 8 && PGS_PROJ_BLUE == 9 && PGS_PROJ_STRIDE == 16,
                   "record layout");
     float4* rec = reinterpret_cast<float4*>(out + (size_t)i * PGS_PROJ_STRIDE);
-    rec[0] = make_float4((float)u, (float)v, (float)G.z, (float)(G.c / G.det));
-    rec[1] = make_float4((float)(-G.b / G.det), (float)(G.a / G.det), (float)o, (float)col[0]);
-    rec[2] = make_float4((float)col[1], (float)col[2], 0.f, 0.f);
+    const float A32 = (float)(G.c / G.det), B32 = (float)(-G.b / G.det), C32 = (float)(G.a / G.det);
+    const float o32 = (float)o;
+    float hx, hy;
+    alpha_extent(A32, B32, C32, o32, hx, hy);
+    rec[0] = make_float4((float)u, (float)v, (float)G.z, A32);
+    rec[1] = make_float4(B32, C32, o32, (float)col[0]);
+    rec[2] = make_float4((float)col[1], (float)col[2], hx, hy);
     rec[3] = make_float4(0.f, 0.f, 0.f, 0.f);
     radius[i] = (int)r;
     const uint32_t ix0 = (uint32_t)x0, ix1 = (uint32_t)x1, iy0 = (uint32_t)y0, iy1 = (uint32_t)y1;

@@ -70,17 +70,41 @@ __device__ __forceinline__ bool splat_alpha(const Splat& s, float px, float py, 
     return alpha >= kAlphaMin;
 }
 
-// One splat's record (u, v, depth, A | B, C, o, r | g, b, -, -) is one
-// 64-byte line: three 16-byte loads.
+// One splat's record (u, v, depth, A | B, C, o, r | g, b, ex, ey) is one
+// 64-byte line: three 16-byte loads.  (ex, ey) are the half-extents of the
+// pixels where its alpha can reach 1/255 (conservative, from the FP64
+// projection); the recompute backward skips a splat for a whole wave with
+// them.  (In the forward the test costs more than the alpha it saves.)
 __device__ __forceinline__ void stage_splat(const float* __restrict__ proj, int n, uint32_t g,
-                                            float4* sa, float4* sb, float* sc, int slot) {
+                                            float4* sa, float4* sb, float* sc, float2* se, int slot) {
     (void)n;
     const float4* rec = reinterpret_cast<const float4*>(proj + (size_t)g * PGS_PROJ_STRIDE);
     const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
     sa[slot] = make_float4(r0.x, r0.y, r0.w, r1.x);   // u, v, A, B
     sb[slot] = make_float4(r1.y, r1.z, r1.w, r2.x);   // C, o, r, g
     sc[slot] = r2.y;                                  // b
+    se[slot] = make_float2(r2.z, r2.w);               // extents
 }
+
+// Pixel-centre rectangle of one wave of a TW x TH tile (64 consecutive
+// row-major lanes).
+template <int TW>
+struct WaveRect {
+    float x0, x1, y0, y1;
+    __device__ __forceinline__ WaveRect(int tx, int ty, int TH, int wv) {
+        x0 = (float)(tx * TW) + 0.5f;
+        x1 = x0 + (float)(TW - 1);
+        y0 = (float)(ty * TH + (64 * wv) / TW) + 0.5f;
+        y1 = (float)(ty * TH + (64 * wv + 63) / TW) + 0.5f;
+    }
+    // whether a splat centred at (u, v) with extents e can reach a pixel of
+    // the wave; the same answer in every lane (LDS broadcast operands), made
+    // scalar so that the skip is a uniform branch
+    __device__ __forceinline__ bool hit(float u, float v, float2 e) const {
+        const float dx = u - fminf(fmaxf(u, x0), x1), dy = v - fminf(fmaxf(v, y0), y1);
+        return __builtin_amdgcn_readfirstlane((int)(fabsf(dx) <= e.x && fabsf(dy) <= e.y)) != 0;
+    }
+};
 
 __device__ __forceinline__ Splat load_splat(const float4* sa, const float4* sb, const float* sc, int k) {
     const float4 a = sa[k], b = sb[k];
@@ -98,7 +122,7 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
 }
 
 struct Trace {
-    uint64_t* mask;             // [pair_cap][NW]
+    uint64_t* mask;             // [NW][pair_cap]
     uint32_t* steps;            // [n_tiles][NW]
     uint32_t* base;             // [n_tiles][NW] first entry of the wave's region
     unsigned long long* used;   // entries handed out in this forward
@@ -127,6 +151,7 @@ struct FwdLds {
     float4 a[BG];
     float4 b[BG];
     float c[BG];
+    float2 e[BG];
     uint32_t steps;
 };
 
@@ -135,6 +160,7 @@ struct TileLds {
     float4 a[BG];
     float4 b[BG];
     float c[BG];
+    float2 e[BG];
     uint32_t g[BG];
     float acc[9][BG];
     uint32_t steps;
@@ -148,7 +174,7 @@ __device__ __forceinline__ void stage_batch(Lds& L, const float* __restrict__ pr
     for (int q = t; q < nb; q += NT) {
         const uint32_t g = values[base + q];
         if constexpr (KEEP_IDS) L.g[q] = g;
-        stage_splat(proj, n, g, L.a, L.b, L.c, q);
+        stage_splat(proj, n, g, L.a, L.b, L.c, L.e, q);
     }
 }
 
@@ -170,6 +196,10 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     const bool rec = CACHED && end <= tr.pair_cap;
     if (CACHED && !rec && t == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
     uint32_t cursor = 0, steps = 0, cnt = 0;
+    // masks of the current 64-step chunk, lane i holding step i; written
+    // as one coalesced 512-byte run per chunk (wave-major mask layout)
+    uint64_t* wmask = tr.mask + (size_t)wv * tr.pair_cap + start;
+    uint64_t mreg = 0ull;
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     bool done = !inside;
@@ -204,13 +234,16 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
             }
             if (rec) {
                 const uint64_t m = __ballot(contrib);
-                if (lane == 0) tr.mask[(size_t)(base + k) * NW + wv] = m;
+                const uint32_t rel = base + k - start;
+                if ((uint32_t)lane == (rel & 63u)) mreg = m;
+                if ((rel & 63u) == 63u) wmask[rel - 63u + lane] = mreg;
                 cursor += __popcll(m);
                 cnt += contrib ? 1u : 0u;
-                steps = base + k - start + 1;
+                steps = rel + 1;
             }
         }
     }
+    if (rec && (steps & 63u) && (uint32_t)lane < (steps & 63u)) wmask[(steps & ~63u) + lane] = mreg;
     // the wave's entry region: `cursor` entries from the bump counter
     size_t ebase = 0;
     bool wrec = rec;
@@ -267,7 +300,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
         // chunk's masks, then the non-empty ones are visited last to first
         for (int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64; c0 >= lo; c0 -= 64) {
             const uint32_t cn = min(64u, whi - (uint32_t)c0);
-            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
+            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)wv * tr.pair_cap + start + c0 + lane] : 0ull;
             uint64_t any = __ballot(mv != 0ull);
             while (any) {
                 const int i = 63 - __clzll(any);
@@ -387,7 +420,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
         const uint32_t whi = min(base + (uint32_t)nb, steps);
         for (uint32_t c0 = base; c0 < whi; c0 += 64) {
             const uint32_t cn = min(64u, whi - c0);
-            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)(start + c0 + lane) * NW + wv] : 0ull;
+            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)wv * tr.pair_cap + start + c0 + lane] : 0ull;
             uint64_t any = __ballot(mv != 0ull);
             while (any) {
                 // take up to kG groups and issue all their trace loads before
@@ -480,6 +513,7 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
     if (last) atomicMax(&L.steps, last);
     __syncthreads();
     const uint32_t top = L.steps;
+    const WaveRect<TW> wr(j.tx, j.ty, TH, t >> 6);
 
     for (uint32_t hi = top; hi > 0;) {
         const uint32_t lo = hi > (uint32_t)BG ? hi - BG : 0u;
@@ -488,6 +522,7 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
         zero_acc<BG>(L.acc, t, NT);
         __syncthreads();
         for (int jj = nb - 1; jj >= 0; --jj) {
+            if (!wr.hit(L.a[jj].x, L.a[jj].y, L.e[jj])) continue;  // uniform: no lane can use it
             const uint32_t jrel = lo + jj;
             bool ok = false;
             float alpha = 0.f, gauss = 0.f, dx = 0.f, dy = 0.f;

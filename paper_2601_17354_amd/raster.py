@@ -32,7 +32,7 @@ def new_trace(pair_capacity: int, nw: int, n_tiles: int, pixels: int, entries: i
     `entries` 16-byte entries and per-pixel counts."""
     entries = max(1, min(int(entries), MAX_ENTRIES))
     return dict(
-        mask=torch.empty((max(pair_capacity, 1), nw), dtype=torch.int64, device=device),
+        mask=torch.empty((nw, max(pair_capacity, 1)), dtype=torch.int64, device=device),
         steps=torch.empty((n_tiles, nw), dtype=torch.int32, device=device),
         base=torch.empty((n_tiles, nw), dtype=torch.int32, device=device),
         used=torch.zeros(1, dtype=torch.int64, device=device),

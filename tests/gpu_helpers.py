@@ -96,7 +96,7 @@ def trace_entries(out, cam, x, y, tile=(16, 16)):
     w, lane = p // 64, p % 64
     start, end = (int(v) for v in out["ranges"][:, t])
     steps = int(R.trace["steps"][t, w].item())
-    masks = R.trace["mask"][start:start + steps, w].cpu().numpy().view(np.uint64)
+    masks = R.trace["mask"][w, start:start + steps].cpu().numpy().view(np.uint64)
     ebase = int(R.trace["base"][t, w].item()) & 0xFFFFFFFF
     cursor, ents = 0, []
     for j, m in enumerate(masks):
