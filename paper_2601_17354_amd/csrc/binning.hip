@@ -1,17 +1,26 @@
 // Tile binning and the (tile, depth) key sort that yields the permutation pi
 // of PocketGS's index-mapping subsection.
 //
-//   scan     exclusive prefix sum of tiles_touched -> pair offsets + count
+// The pairs are ordered by (tile, depth bits, canonical id).  Instead of
+// sorting all 46 significant key bits of every pair, the Gaussians are
+// sorted once by depth and the pairs emitted in that order, so that a stable
+// sort on the tile bits alone finishes the order:
+//   depth    stable LSD sort of the (depth bits, item) of every Gaussian of
+//            every view (4 passes over n items instead of 4 over the pairs)
+//   scan     exclusive prefix sum of tiles_touched in depth order -> pair
+//            offsets + count
 //   emit     one (key, canonical id) pair per Gaussian x rectangle tile,
-//            key = tile << 32 | bits(float32 depth)
-//   sort     stable LSD radix sort, 8-bit digits, only the significant key
-//            bits (32 + ceil(log2 n_tiles)); every pass is histogram ->
-//            device scan of the digit-major histogram -> stable scatter
+//            key = tile << 32 | bits(float32 depth), one thread per pair
+//            (binary search over the offsets), so large Gaussians do not
+//            serialise
+//   sort     stable LSD radix sort on the tile bits only, 8-bit digits;
+//            every pass is histogram -> device scan of the digit-major
+//            histogram -> stable scatter
 //   ranges   per-tile [start, end)
 //
-// Every kernel reads the pair count from device memory and is launched on a
-// grid sized for the capacity, so nothing travels to the host and the whole
-// sequence can be captured in a HIP graph.
+// Every kernel reads the item and pair counts from device memory and is
+// launched on a grid sized for the capacity, so nothing travels to the host
+// and the whole sequence can be captured in a HIP graph.
 #include "common.hpp"
 
 namespace {
@@ -120,73 +129,81 @@ pgs_status scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tot
     return PGS_OK;
 }
 
-__global__ __launch_bounds__(256) void k_emit(int n, const float* __restrict__ depth,
-                                              const uint32_t* __restrict__ rect,
-                                              const uint32_t* __restrict__ touched,
-                                              const uint32_t* __restrict__ offsets,
-                                              const uint32_t* __restrict__ num_pairs, int TX,
-                                              int tile_offset, uint32_t capacity,
-                                              uint64_t* __restrict__ keys,
-                                              uint32_t* __restrict__ values,
-                                              uint32_t* __restrict__ flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && *num_pairs > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
-    if (i >= n) return;
-    const uint32_t cnt = touched[i];
-    if (cnt == 0) return;
-    uint32_t idx = offsets[i];
-    const uint32_t r0 = rect[i], r1 = rect[(size_t)n + i];
-    const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff, y1 = r1 >> 16;
-    const uint64_t dbits = (uint64_t)__float_as_uint(depth[(size_t)i * PGS_PROJ_STRIDE]);
-    for (uint32_t ty = y0; ty <= y1; ++ty)
-        for (uint32_t tx = x0; tx <= x1; ++tx, ++idx) {
-            if (idx >= capacity) return;
-            const uint64_t tile = (uint64_t)(tile_offset + ty * (uint32_t)TX + tx);
-            keys[idx] = (tile << 32) | dbits;
-            values[idx] = (uint32_t)i;
-        }
-}
-
-// Pairs of several views: item i = v * n + g is Gaussian g in view v, keyed
-// with view v's global tile numbers; values hold the canonical id g.
+// Items of a bin/sort: item i = v * n + g is Gaussian g in view v (one view:
+// v = 0), keyed with view v's global tile numbers; values hold the id g.
 struct EmitViews {
     int n_views;
     int TX[PGS_MAX_VIEWS];
     int tile_off[PGS_MAX_VIEWS];
 };
 
-__global__ __launch_bounds__(256) void k_emit_views(int n, EmitViews ev, const float* __restrict__ proj_all,
-                                                    const uint32_t* __restrict__ rect_all,
-                                                    const uint32_t* __restrict__ touched_all,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const uint32_t* __restrict__ num_pairs, uint32_t capacity,
-                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ values,
-                                                    uint32_t* __restrict__ flags) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && *num_pairs > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
-    if (i >= (size_t)ev.n_views * n) return;
-    const uint32_t cnt = touched_all[i];
-    if (cnt == 0) return;
-    const int v = (int)(i / (size_t)n), g = (int)(i - (size_t)v * n);
-    int TX = ev.TX[0], off = ev.tile_off[0];
+__device__ __forceinline__ void view_tiles(const EmitViews& ev, int v, int& TX, int& off) {
+    TX = ev.TX[0];
+    off = ev.tile_off[0];
     for (int u = 1; u < ev.n_views; ++u)
         if (u == v) {
             TX = ev.TX[u];
             off = ev.tile_off[u];
         }
-    uint32_t idx = offsets[i];
-    const uint32_t* rect = rect_all + (size_t)v * 2 * n;
-    const uint32_t r0 = rect[g], r1 = rect[(size_t)n + g];
-    const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff, y1 = r1 >> 16;
-    const uint64_t dbits =
-        (uint64_t)__float_as_uint(proj_all[((size_t)v * n + g) * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
-    for (uint32_t ty = y0; ty <= y1; ++ty)
-        for (uint32_t tx = x0; tx <= x1; ++tx, ++idx) {
-            if (idx >= capacity) return;
-            const uint64_t tile = (uint64_t)(off + ty * (uint32_t)TX + tx);
-            keys[idx] = (tile << 32) | dbits;
-            values[idx] = (uint32_t)g;
+}
+
+// Depth keys of every item (float32 depth bits; culled items sort last),
+// values = item index, and the item count for the depth sort.
+__global__ __launch_bounds__(256) void k_depth_keys(uint32_t items, int n, const float* __restrict__ proj_all,
+                                                    const uint32_t* __restrict__ touched_all,
+                                                    uint64_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
+                                                    uint32_t* __restrict__ count) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *count = items;
+    if (i >= items) return;
+    const uint32_t bits = __float_as_uint(proj_all[(size_t)i * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
+    dkeys[i] = touched_all[i] ? (uint64_t)bits : 0xffffffffull;
+    dvals[i] = i;
+}
+
+// tiles_touched in depth order (scanned in place afterwards).
+__global__ __launch_bounds__(256) void k_gather_touched(uint32_t items, const uint32_t* __restrict__ dvals,
+                                                        const uint32_t* __restrict__ touched_all,
+                                                        uint32_t* __restrict__ cnt) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < items) cnt[i] = touched_all[dvals[i]];
+}
+
+// Pairs of the items in depth order, one thread per pair: the pair's item is
+// the last one whose offset is <= the pair index (binary search over the
+// scanned counts; empty items share their successor's offset and are never
+// chosen), so the work is even however unevenly the rectangles are sized.
+__global__ __launch_bounds__(256) void k_emit_sorted(uint32_t items, int n, EmitViews ev,
+                                                     const float* __restrict__ proj_all,
+                                                     const uint32_t* __restrict__ rect_all,
+                                                     const uint32_t* __restrict__ dvals,
+                                                     const uint32_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ num_pairs, uint32_t capacity,
+                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ values,
+                                                     uint32_t* __restrict__ flags) {
+    const uint32_t total = *num_pairs;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
+    const uint32_t count = min(total, capacity);
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < count; p += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = items - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= p) lo = mid;
+            else hi = mid - 1;
         }
+        const uint32_t item = dvals[lo], local = p - off[lo];
+        const uint32_t v = item / (uint32_t)n, g = item - v * (uint32_t)n;
+        int TX, toff;
+        view_tiles(ev, (int)v, TX, toff);
+        const uint32_t r0 = rect_all[(size_t)v * 2 * n + g], r1 = rect_all[(size_t)v * 2 * n + n + g];
+        const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff;
+        const uint32_t w = x1 - x0 + 1;
+        const uint32_t ty = y0 + local / w, tx = x0 + local % w;
+        const uint64_t tile = (uint64_t)((uint32_t)toff + ty * (uint32_t)TX + tx);
+        const uint32_t dbits = __float_as_uint(proj_all[(size_t)item * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
+        keys[p] = (tile << 32) | (uint64_t)dbits;
+        values[p] = g;
+    }
 }
 
 __device__ __forceinline__ uint32_t clamp_count(const uint32_t* num, uint32_t capacity) {
@@ -355,14 +372,15 @@ SortWs sort_layout(void* base, uint32_t capacity) {
     return w;
 }
 
+// Sorts key bits [start_bit, start_bit + key_bits) (stable).
 pgs_status radix_sort(uint64_t* keys, uint32_t* vals, const uint32_t* num, uint32_t capacity,
-                      int key_bits, const SortWs& w, hipStream_t s) {
+                      int key_bits, const SortWs& w, hipStream_t s, int start_bit = 0) {
     if (capacity == 0) return PGS_OK;
     const int passes = (key_bits + 7) / 8;
     uint64_t* kin = keys; uint32_t* vin = vals;
     uint64_t* kout = w.keys_alt; uint32_t* vout = w.vals_alt;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = start_bit + 8 * p;
         k_radix_hist<<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
         pgs_status st = scan_u32(w.hist, w.hist, w.nb * kRadix, nullptr, w.partial, s);
         if (st != PGS_OK) return st;
@@ -413,9 +431,70 @@ extern "C" pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, c
     return radix_sort(keys_dev, values_dev, count_dev, capacity, key_bits, w, pgs::as_stream(stream));
 }
 
+namespace {
+
+// Workspace of a bin/sort over `items` Gaussians (all views) and `capacity`
+// pairs: depth keys and item ids, pair offsets, scan partials, the item
+// count word, and the two sorts' ping-pong buffers.
+struct BinWs {
+    uint64_t* dkeys;
+    uint32_t* dvals;
+    uint32_t* off;
+    uint32_t* partial;
+    uint32_t* count;
+    SortWs items_ws;
+    SortWs pairs_ws;
+    size_t bytes;
+};
+
+BinWs bin_layout(void* base, uint32_t items, uint32_t capacity) {
+    BinWs w{};
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    w.dkeys = reinterpret_cast<uint64_t*>(p + off); off += align_up((size_t)items * 8);
+    w.dvals = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)items * 4);
+    w.off = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)items * 4);
+    w.partial = reinterpret_cast<uint32_t*>(p + off); off += scan_workspace(items);
+    w.count = reinterpret_cast<uint32_t*>(p + off); off += align_up(4);
+    w.items_ws = sort_layout(p ? p + off : nullptr, items); off += w.items_ws.bytes;
+    w.pairs_ws = sort_layout(p ? p + off : nullptr, capacity); off += w.pairs_ws.bytes;
+    w.bytes = off;
+    return w;
+}
+
+pgs_status bin_sort_items(uint32_t items, int n, const EmitViews& ev, int n_tiles, const float* proj_all,
+                          const uint32_t* rect_all, const uint32_t* touched_all, uint32_t capacity,
+                          uint64_t* keys, uint32_t* values, uint32_t* ranges, uint32_t* num_pairs,
+                          uint32_t* flags, const BinWs& w, hipStream_t s, const char* who) {
+    k_clear_u32<<<256, 256, 0, s>>>(ranges, 2u * (uint32_t)n_tiles);
+    k_clear_u32<<<1, 64, 0, s>>>(num_pairs, 1u);
+    PGS_CHECK_LAUNCH(who);
+    if (items == 0) return PGS_OK;
+    const uint32_t g = div_up(items, 256);
+    k_depth_keys<<<g, 256, 0, s>>>(items, n, proj_all, touched_all, w.dkeys, w.dvals, w.count);
+    PGS_CHECK_LAUNCH(who);
+    pgs_status st = radix_sort(w.dkeys, w.dvals, w.count, items, 32, w.items_ws, s);
+    if (st != PGS_OK) return st;
+    k_gather_touched<<<g, 256, 0, s>>>(items, w.dvals, touched_all, w.off);
+    st = scan_u32(w.off, w.off, items, num_pairs, w.partial, s);
+    if (st != PGS_OK) return st;
+    const uint32_t ge = div_up(capacity, 256) < 16384 ? div_up(capacity, 256) : 16384;
+    k_emit_sorted<<<ge > 0 ? ge : 1, 256, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals, w.off, num_pairs,
+                                                  capacity, keys, values, flags);
+    PGS_CHECK_LAUNCH(who);
+    if (capacity == 0) return PGS_OK;
+    st = radix_sort(keys, values, num_pairs, capacity, bits_for((uint32_t)n_tiles), w.pairs_ws, s, 32);
+    if (st != PGS_OK) return st;
+    const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
+    k_ranges<<<grid, 256, 0, s>>>(keys, num_pairs, capacity, (uint32_t)n_tiles, ranges);
+    PGS_CHECK_LAUNCH(who);
+    return PGS_OK;
+}
+
+}  // namespace
+
 extern "C" size_t pgs_bin_sort_workspace(int32_t n, uint32_t capacity) {
-    const uint32_t nn = n > 0 ? (uint32_t)n : 0u;
-    return align_up((size_t)nn * 4) + scan_workspace(nn) + sort_layout(nullptr, capacity).bytes;
+    return bin_layout(nullptr, n > 0 ? (uint32_t)n : 0u, capacity).bytes;
 }
 
 extern "C" pgs_status pgs_bin_sort(int32_t n, const float* proj_dev, const uint32_t* rect_dev,
@@ -432,32 +511,14 @@ extern "C" pgs_status pgs_bin_sort(int32_t n, const float* proj_dev, const uint3
     const size_t need = pgs_bin_sort_workspace(n, capacity);
     PGS_REQUIRE(workspace_dev && workspace_bytes >= need, "pgs_bin_sort: workspace %zu < %zu",
                 workspace_bytes, need);
-    hipStream_t s = pgs::as_stream(stream);
-    char* p = static_cast<char*>(workspace_dev);
-    uint32_t* offsets = reinterpret_cast<uint32_t*>(p);
-    p += align_up((size_t)n * 4);
-    uint32_t* partial = reinterpret_cast<uint32_t*>(p);
-    p += scan_workspace((uint32_t)n);
-    SortWs w = sort_layout(p, capacity);
-
-    k_clear_u32<<<256, 256, 0, s>>>(ranges_dev, 2u * (uint32_t)n_tiles);
-    k_clear_u32<<<1, 64, 0, s>>>(num_pairs_dev, 1u);
-    PGS_CHECK_LAUNCH("pgs_bin_sort clear");
-    if (n == 0) return PGS_OK;
-    pgs_status st = scan_u32(touched_dev, offsets, (uint32_t)n, num_pairs_dev, partial, s);
-    if (st != PGS_OK) return st;
-    k_emit<<<(n + 255) / 256, 256, 0, s>>>(n, proj_dev + PGS_PROJ_DEPTH, rect_dev,
-                                            touched_dev, offsets, num_pairs_dev, tiles_x,
-                                            view_tile_offset, capacity, keys_dev, values_dev, flags_dev);
-    PGS_CHECK_LAUNCH("pgs_bin_sort emit");
-    if (capacity == 0) return PGS_OK;
-    const int key_bits = 32 + bits_for((uint32_t)n_tiles);
-    st = radix_sort(keys_dev, values_dev, num_pairs_dev, capacity, key_bits, w, s);
-    if (st != PGS_OK) return st;
-    const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
-    k_ranges<<<grid, 256, 0, s>>>(keys_dev, num_pairs_dev, capacity, (uint32_t)n_tiles, ranges_dev);
-    PGS_CHECK_LAUNCH("pgs_bin_sort ranges");
-    return PGS_OK;
+    EmitViews ev{};
+    ev.n_views = 1;
+    ev.TX[0] = tiles_x;
+    ev.tile_off[0] = view_tile_offset;
+    const BinWs w = bin_layout(workspace_dev, (uint32_t)n, capacity);
+    return bin_sort_items((uint32_t)n, n > 0 ? n : 1, ev, n_tiles, proj_dev, rect_dev, touched_dev, capacity,
+                          keys_dev, values_dev, ranges_dev, num_pairs_dev, flags_dev, w, pgs::as_stream(stream),
+                          "pgs_bin_sort");
 }
 
 extern "C" pgs_status pgs_bin_sort_views(const pgs_view_batch* views, int32_t n, const float* proj_all_dev,
@@ -476,37 +537,14 @@ extern "C" pgs_status pgs_bin_sort_views(const pgs_view_batch* views, int32_t n,
     PGS_REQUIRE(workspace_dev && workspace_bytes >= need, "pgs_bin_sort_views: workspace %zu < %zu",
                 workspace_bytes, need);
     const pgs::ViewsLayout lay = pgs::views_layout(*views);
-    const int n_tiles = lay.tile_off[views->n_views];
     EmitViews ev{};
     ev.n_views = views->n_views;
     for (int v = 0; v < views->n_views; ++v) {
         ev.TX[v] = lay.TX[v];
         ev.tile_off[v] = lay.tile_off[v];
     }
-    hipStream_t s = pgs::as_stream(stream);
-    char* p = static_cast<char*>(workspace_dev);
-    uint32_t* offsets = reinterpret_cast<uint32_t*>(p);
-    p += align_up((size_t)items * 4);
-    uint32_t* partial = reinterpret_cast<uint32_t*>(p);
-    p += scan_workspace((uint32_t)items);
-    SortWs w = sort_layout(p, capacity);
-
-    k_clear_u32<<<256, 256, 0, s>>>(ranges_dev, 2u * (uint32_t)n_tiles);
-    k_clear_u32<<<1, 64, 0, s>>>(num_pairs_dev, 1u);
-    PGS_CHECK_LAUNCH("pgs_bin_sort_views clear");
-    if (items == 0) return PGS_OK;
-    st = scan_u32(touched_all_dev, offsets, (uint32_t)items, num_pairs_dev, partial, s);
-    if (st != PGS_OK) return st;
-    k_emit_views<<<div_up((uint32_t)items, 256), 256, 0, s>>>(n, ev, proj_all_dev, rect_all_dev, touched_all_dev,
-                                                             offsets, num_pairs_dev, capacity, keys_dev,
-                                                             values_dev, flags_dev);
-    PGS_CHECK_LAUNCH("pgs_bin_sort_views emit");
-    if (capacity == 0) return PGS_OK;
-    const int key_bits = 32 + bits_for((uint32_t)n_tiles);
-    st = radix_sort(keys_dev, values_dev, num_pairs_dev, capacity, key_bits, w, s);
-    if (st != PGS_OK) return st;
-    const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
-    k_ranges<<<grid, 256, 0, s>>>(keys_dev, num_pairs_dev, capacity, (uint32_t)n_tiles, ranges_dev);
-    PGS_CHECK_LAUNCH("pgs_bin_sort_views ranges");
-    return PGS_OK;
+    const BinWs w = bin_layout(workspace_dev, (uint32_t)items, capacity);
+    return bin_sort_items((uint32_t)items, n > 0 ? n : 1, ev, lay.tile_off[views->n_views], proj_all_dev,
+                          rect_all_dev, touched_all_dev, capacity, keys_dev, values_dev, ranges_dev, num_pairs_dev,
+                          flags_dev, w, pgs::as_stream(stream), "pgs_bin_sort_views");
 }
