@@ -4,12 +4,14 @@
 // SSIM (Wang et al. 2004): 11x11 Gaussian window (sigma 1.5), C1 = 1e-4,
 // C2 = 9e-4, zero padding, mean over pixels and channels.
 //
-// Forward kernel, per 16x16 output tile and channel: x and y with a 5-pixel
-// halo go to LDS, a horizontal then a vertical pass of the separable window
-// give mu_x, mu_y, E[x^2], E[y^2], E[xy]; the kernel writes the SSIM map's
-// partial derivatives m1 = dS/dmu_x, m2 = dS/dE[x^2], m3 = dS/dE[xy] and adds
-// the tile's SSIM sum as a per-block partial.  Backward kernel: the
-// same windowed pass over (m1, m2, m3) gives
+// Both SSIM kernels walk a strip of 64 output columns (one lane each) down
+// 32 rows per workgroup of one wave.  Each input row (with a 5-column halo)
+// is loaded once, prefetched one row ahead into registers, placed in LDS and
+// blurred horizontally; the horizontal results of the last 11 rows sit in a
+// register ring, from which the vertical pass forms the 11x11 window sums.
+// Forward: mu_x, mu_y, E[x^2], E[y^2], E[xy] -> the SSIM map's partial
+// derivatives m1 = dS/dmu_x, m2 = dS/dE[x^2], m3 = dS/dE[xy] and the strip's
+// SSIM sum.  Backward: the same windowed pass over (m1, m2, m3) gives
 //     dSSIM/dx_p = (1/N) (w*m1 + 2 x_p w*m2 + y_p w*m3)(p),
 // the adjoint of the zero-padded blur being the zero-padded blur.
 #include <math.h>
@@ -18,7 +20,10 @@
 
 namespace {
 
-constexpr int kT = 16, kHalo = 5, kS = kT + 2 * kHalo;  // 26
+constexpr int kHalo = 5;
+constexpr int kSW = 64;                    // output columns per strip (one lane each)
+constexpr int kRH = 32;                    // output rows per workgroup
+constexpr int kRowW = kSW + 2 * kHalo;     // 74 input columns per row
 constexpr float kC1 = 1e-4f, kC2 = 9e-4f;
 
 struct Win {
@@ -63,111 +68,151 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ x, const f
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y,
-                                                  int W, int H, Win win, float* __restrict__ m,
-                                                  float* __restrict__ part) {
-    __shared__ float sx[kS][kS + 1];
-    __shared__ float sy[kS][kS + 1];
-    __shared__ float hb[5][kS][kT + 1];
-    __shared__ float red[4];
-    const int ch = blockIdx.z, ox = blockIdx.x * kT, oy = blockIdx.y * kT, t = threadIdx.x;
-    const size_t plane = (size_t)W * H;
-    const float* xc = x + ch * plane;
-    const float* yc = y + ch * plane;
-    for (int idx = t; idx < kS * kS; idx += 256) {
-        const int r = idx / kS, c = idx % kS;
-        const int gx = ox + c - kHalo, gy = oy + r - kHalo;
-        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        sx[r][c] = in ? xc[(size_t)gy * W + gx] : 0.f;
-        sy[r][c] = in ? yc[(size_t)gy * W + gx] : 0.f;
+// Row ii of a strip (input row r0 - 5 + ii) of up to NQ planes, loaded by
+// the 64 lanes: lane l takes columns l and (for l < 10) l + 64.
+template <int NQ>
+struct RowLoad {
+    float v[NQ][2];
+    __device__ __forceinline__ void load(const float* const* planes, int W, int H, int c0, int gy, int l) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = l + 64 * h, gx = c0 - kHalo + q;
+            const bool in = q < kRowW && gy >= 0 && gy < H && gx >= 0 && gx < W;
+#pragma unroll
+            for (int f = 0; f < NQ; ++f) v[f][h] = in ? planes[f][(size_t)gy * W + gx] : 0.f;
+        }
     }
-    __syncthreads();
-    for (int idx = t; idx < kS * kT; idx += 256) {
-        const int r = idx / kT, c = idx % kT;
-        float a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+    __device__ __forceinline__ void store(float (*lds)[kRowW + 2], int l) const {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = l + 64 * h;
+            if (q < kRowW) {
+#pragma unroll
+                for (int f = 0; f < NQ; ++f) lds[f][q] = v[f][h];
+            }
+        }
+    }
+};
+
+__global__ __launch_bounds__(64) void k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y,
+                                                 int W, int H, Win win, float* __restrict__ m,
+                                                 float* __restrict__ part) {
+    __shared__ float rows[2][2][kRowW + 2];
+    const int l = threadIdx.x, ch = blockIdx.z, c0 = blockIdx.x * kSW, r0 = blockIdx.y * kRH;
+    const size_t plane = (size_t)W * H;
+    const float* planes[2] = {x + ch * plane, y + ch * plane};
+    const int col = c0 + l;
+    const int rows_in = min(kRH, H - r0) + 2 * kHalo;
+    float ring[11][5];
+    float ssum = 0.f;
+    RowLoad<2> next;
+    next.load(planes, W, H, c0, r0 - kHalo, l);
+    for (int base = 0; base < rows_in; base += 11) {
 #pragma unroll
         for (int k = 0; k < 11; ++k) {
-            const float w = win.w[k], xv = sx[r][c + k], yv = sy[r][c + k];
-            a0 += w * xv;
-            a1 += w * yv;
-            a2 += w * xv * xv;
-            a3 += w * yv * yv;
-            a4 += w * xv * yv;
+            const int ii = base + k;
+            if (ii < rows_in) {
+            const int buf = ii & 1;
+            next.store(rows[buf], l);
+            if (ii + 1 < rows_in) next.load(planes, W, H, c0, r0 - kHalo + ii + 1, l);
+            __syncthreads();
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+            for (int t = 0; t < 11; ++t) {
+                const float w = win.w[t], xv = rows[buf][0][l + t], yv = rows[buf][1][l + t];
+                a0 += w * xv;
+                a1 += w * yv;
+                a2 += w * xv * xv;
+                a3 += w * yv * yv;
+                a4 += w * xv * yv;
+            }
+            ring[k][0] = a0;
+            ring[k][1] = a1;
+            ring[k][2] = a2;
+            ring[k][3] = a3;
+            ring[k][4] = a4;
+            if (ii >= 2 * kHalo) {
+                const int o = r0 + ii - 2 * kHalo;   // output row
+                float q[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < 11; ++t)
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) q[f] += win.w[t] * ring[(k + 1 + t) % 11][f];
+                if (col < W && o < H) {
+                    const float mx = q[0], my = q[1];
+                    const float vx = q[2] - mx * mx, vy = q[3] - my * my, cxy = q[4] - mx * my;
+                    const float N1 = 2.f * mx * my + kC1, N2 = 2.f * cxy + kC2;
+                    const float D1 = mx * mx + my * my + kC1, D2 = vx + vy + kC2;
+                    const float inv = 1.f / (D1 * D2);
+                    const float S = N1 * N2 * inv;
+                    const float m1 = (2.f * my * N2 - 2.f * my * N1) * inv - S * (2.f * mx / D1 - 2.f * mx / D2);
+                    const float m2 = -S / D2;
+                    const float m3 = 2.f * N1 * inv;
+                    const size_t pix = (size_t)o * W + col;
+                    m[(size_t)(3 * ch + 0) * plane + pix] = m1;
+                    m[(size_t)(3 * ch + 1) * plane + pix] = m2;
+                    m[(size_t)(3 * ch + 2) * plane + pix] = m3;
+                    ssum += S;
+                }
+            }
+            }
         }
-        hb[0][r][c] = a0; hb[1][r][c] = a1; hb[2][r][c] = a2; hb[3][r][c] = a3; hb[4][r][c] = a4;
     }
-    __syncthreads();
-    const int lx = t % kT, ly = t / kT, gx = ox + lx, gy = oy + ly;
-    float q[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 11; ++k)
-#pragma unroll
-        for (int f = 0; f < 5; ++f) q[f] += win.w[k] * hb[f][ly + k][lx];
-    float S = 0.f;
-    if (gx < W && gy < H) {
-        const float mx = q[0], my = q[1];
-        const float vx = q[2] - mx * mx, vy = q[3] - my * my, cxy = q[4] - mx * my;
-        const float N1 = 2.f * mx * my + kC1, N2 = 2.f * cxy + kC2;
-        const float D1 = mx * mx + my * my + kC1, D2 = vx + vy + kC2;
-        const float inv = 1.f / (D1 * D2);
-        S = N1 * N2 * inv;
-        const float m1 = (2.f * my * N2 - 2.f * my * N1) * inv - S * (2.f * mx / D1 - 2.f * mx / D2);
-        const float m2 = -S / D2;
-        const float m3 = 2.f * N1 * inv;
-        const size_t pix = (size_t)gy * W + gx;
-        m[(size_t)(3 * ch + 0) * plane + pix] = m1;
-        m[(size_t)(3 * ch + 1) * plane + pix] = m2;
-        m[(size_t)(3 * ch + 2) * plane + pix] = m3;
-    }
-    const float tot = block_sum(S, red);
-    if (t == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+    const float tot = wave_sum_to_lane63(ssum);
+    if (l == 63) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y,
-                                                  int W, int H, Win win, const float* __restrict__ m,
-                                                  float l1_scale, float ssim_scale,
-                                                  float* __restrict__ dl, float* __restrict__ part) {
-    __shared__ float sm[3][kS][kS + 1];
-    __shared__ float hb[3][kS][kT + 1];
-    __shared__ float red[4];
-    const int ch = blockIdx.z, ox = blockIdx.x * kT, oy = blockIdx.y * kT, t = threadIdx.x;
+__global__ __launch_bounds__(64) void k_ssim_bwd(const float* __restrict__ x, const float* __restrict__ y,
+                                                 int W, int H, Win win, const float* __restrict__ m,
+                                                 float l1_scale, float ssim_scale,
+                                                 float* __restrict__ dl, float* __restrict__ part) {
+    __shared__ float rows[2][3][kRowW + 2];
+    const int l = threadIdx.x, ch = blockIdx.z, c0 = blockIdx.x * kSW, r0 = blockIdx.y * kRH;
     const size_t plane = (size_t)W * H;
-    for (int idx = t; idx < kS * kS; idx += 256) {
-        const int r = idx / kS, c = idx % kS;
-        const int gx = ox + c - kHalo, gy = oy + r - kHalo;
-        const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        const size_t pix = (size_t)gy * W + gx;
+    const float* planes[3] = {m + (size_t)(3 * ch) * plane, m + (size_t)(3 * ch + 1) * plane,
+                              m + (size_t)(3 * ch + 2) * plane};
+    const int col = c0 + l;
+    const int rows_in = min(kRH, H - r0) + 2 * kHalo;
+    float ring[11][3];
+    float l1sum = 0.f;
+    RowLoad<3> next;
+    next.load(planes, W, H, c0, r0 - kHalo, l);
+    for (int base = 0; base < rows_in; base += 11) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) sm[f][r][c] = in ? m[(size_t)(3 * ch + f) * plane + pix] : 0.f;
+        for (int k = 0; k < 11; ++k) {
+            const int ii = base + k;
+            if (ii < rows_in) {
+            const int buf = ii & 1;
+            next.store(rows[buf], l);
+            if (ii + 1 < rows_in) next.load(planes, W, H, c0, r0 - kHalo + ii + 1, l);
+            __syncthreads();
+            float a[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 11; ++t)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) a[f] += win.w[t] * rows[buf][f][l + t];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) ring[k][f] = a[f];
+            if (ii >= 2 * kHalo) {
+                const int o = r0 + ii - 2 * kHalo;
+                float b[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < 11; ++t)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) b[f] += win.w[t] * ring[(k + 1 + t) % 11][f];
+                if (col < W && o < H) {
+                    const size_t i = ch * plane + (size_t)o * W + col;
+                    const float xv = x[i], yv = y[i], d = xv - yv;
+                    l1sum += fabsf(d);
+                    const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+                    dl[i] = l1_scale * sgn - ssim_scale * (b[0] + 2.f * xv * b[1] + yv * b[2]);
+                }
+            }
+            }
+        }
     }
-    __syncthreads();
-    for (int idx = t; idx < kS * kT; idx += 256) {
-        const int r = idx / kT, c = idx % kT;
-        float a[3] = {0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < 11; ++k)
-#pragma unroll
-            for (int f = 0; f < 3; ++f) a[f] += win.w[k] * sm[f][r][c + k];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) hb[f][r][c] = a[f];
-    }
-    __syncthreads();
-    const int lx = t % kT, ly = t / kT, gx = ox + lx, gy = oy + ly;
-    float b[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 11; ++k)
-#pragma unroll
-        for (int f = 0; f < 3; ++f) b[f] += win.w[k] * hb[f][ly + k][lx];
-    float l1 = 0.f;
-    if (gx < W && gy < H) {
-        const size_t i = ch * plane + (size_t)gy * W + gx;
-        const float xv = x[i], yv = y[i], d = xv - yv;
-        l1 = fabsf(d);
-        const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        dl[i] = l1_scale * sgn - ssim_scale * (b[0] + 2.f * xv * b[1] + yv * b[2]);
-    }
-    const float tot = block_sum(l1, red);
-    if (t == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+    const float tot = wave_sum_to_lane63(l1sum);
+    if (l == 63) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
 // Sums the per-block partials in a fixed order (deterministic, no atomics):
@@ -235,7 +280,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_psnr_final(const float* __res
     }
 }
 
-inline int ssim_blocks(int W, int H) { return ((W + kT - 1) / kT) * ((H + kT - 1) / kT) * 3; }
+inline int ssim_blocks(int W, int H) { return ((W + kSW - 1) / kSW) * ((H + kRH - 1) / kRH) * 3; }
 
 inline size_t part_bytes(int W, int H) {
     const int nb = ssim_blocks(W, H) > kL1Blocks ? ssim_blocks(W, H) : kL1Blocks;
@@ -283,11 +328,11 @@ extern "C" pgs_status pgs_loss_l1_dssim(const float* x_dev, const float* y_dev, 
         k_l1<<<kL1Blocks, 256, 0, s>>>(x_dev, y_dev, N, invN, dl_dx_dev, part_l1);
     } else {
         const Win win = gaussian_window();
-        const dim3 grid((width + kT - 1) / kT, (height + kT - 1) / kT, 3);
+        const dim3 grid((width + kSW - 1) / kSW, (height + kRH - 1) / kRH, 3);
         nl = ns = ssim_blocks(width, height);
-        k_ssim_fwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, part_s);
-        k_ssim_bwd<<<grid, 256, 0, s>>>(x_dev, y_dev, width, height, win, m, (1.f - lambda) * invN,
-                                        lambda * invN, dl_dx_dev, part_l1);
+        k_ssim_fwd<<<grid, 64, 0, s>>>(x_dev, y_dev, width, height, win, m, part_s);
+        k_ssim_bwd<<<grid, 64, 0, s>>>(x_dev, y_dev, width, height, win, m, (1.f - lambda) * invN,
+                                       lambda * invN, dl_dx_dev, part_l1);
     }
     k_loss_final<<<1, kFinalThreads, 0, s>>>(part_l1, nl, part_s, ns, lambda, invN, loss_dev);
     PGS_CHECK_LAUNCH("pgs_loss_l1_dssim");
