@@ -49,6 +49,10 @@
 #ifndef PGS_TRACE_GROUPS
 #define PGS_TRACE_GROUPS 4
 #endif
+// Splats a wave composites between two termination checks.
+#ifndef FWD_UNROLL
+#define FWD_UNROLL 4
+#endif
 
 namespace pgs {
 
@@ -210,36 +214,44 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
         const int nb = (int)min((uint32_t)BG, end - base);
         stage_batch<NT, false>(L, j.proj, n, values, base, nb, t);
         __syncthreads();
-        for (int k = 0; k < nb; ++k) {
+        // the wave checks for termination once per FWD_UNROLL splats, so
+        // that the splat loads and alpha evaluations of a group overlap
+        for (int k0 = 0; k0 < nb; k0 += FWD_UNROLL) {
             if (__ballot(!done) == 0) break;  // the whole wave has terminated
-            bool contrib = false;
-            float alpha = 0.f;
-            if (!done) {
-                const Splat s = load_splat(L.a, L.b, L.c, k);
-                float gauss, dx, dy;
-                if (splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy)) {
-                    const float test_T = T * (1.f - alpha);
-                    if (test_T < kTMin) {
-                        done = true;
-                    } else {
-                        contrib = true;
-                        const float w = alpha * T;
-                        C0 += w * s.r;
-                        C1 += w * s.g;
-                        C2 += w * s.b;
-                        T = test_T;
-                        last = base + k - start + 1;
+#pragma unroll
+            for (int u = 0; u < FWD_UNROLL; ++u) {
+                const int k = k0 + u;
+                if (k < nb) {
+                    bool contrib = false;
+                    float alpha = 0.f;
+                    if (!done) {
+                        const Splat s = load_splat(L.a, L.b, L.c, k);
+                        float gauss, dx, dy;
+                        if (splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy)) {
+                            const float test_T = T * (1.f - alpha);
+                            if (test_T < kTMin) {
+                                done = true;
+                            } else {
+                                contrib = true;
+                                const float w = alpha * T;
+                                C0 += w * s.r;
+                                C1 += w * s.g;
+                                C2 += w * s.b;
+                                T = test_T;
+                                last = base + k - start + 1;
+                            }
+                        }
+                    }
+                    if (rec) {
+                        const uint64_t m = __ballot(contrib);
+                        const uint32_t rel = base + k - start;
+                        if ((uint32_t)lane == (rel & 63u)) mreg = m;
+                        if ((rel & 63u) == 63u) wmask[rel - 63u + lane] = mreg;
+                        cursor += __popcll(m);
+                        cnt += contrib ? 1u : 0u;
+                        steps = rel + 1;
                     }
                 }
-            }
-            if (rec) {
-                const uint64_t m = __ballot(contrib);
-                const uint32_t rel = base + k - start;
-                if ((uint32_t)lane == (rel & 63u)) mreg = m;
-                if ((rel & 63u) == 63u) wmask[rel - 63u + lane] = mreg;
-                cursor += __popcll(m);
-                cnt += contrib ? 1u : 0u;
-                steps = rel + 1;
             }
         }
     }
