@@ -51,7 +51,7 @@
 #endif
 // Splats a wave composites between two termination checks.
 #ifndef FWD_UNROLL
-#define FWD_UNROLL 4
+#define FWD_UNROLL 8
 #endif
 
 namespace pgs {
