@@ -373,6 +373,58 @@ __device__ __forceinline__ void accumulate(const float* v, float (*acc)[BG], int
     }
 }
 
+// Sums 36 per-lane values over the wave with two swap-and-add stages
+// (v_permlane32_swap: lanes 0-31 of one register meet lanes 32-63 of
+// another; v_permlane16_swap: the same between 16-lane rows) and a DPP
+// scan inside each row.  Afterwards lane 16r + 15 holds in t[j] the total of
+// value 4j + c, c = (0, 2, 1, 3)[r].
+__device__ __forceinline__ void wave_reduce36(const float* v, float* t) {
+    float s[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]),
+                                                        false, false);
+        s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * j]), __float_as_uint(s[2 * j + 1]),
+                                                        false, false);
+        float x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        int xi = __float_as_int(x);
+        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x111, 0xf, 0xf, false));
+        xi = __float_as_int(x);
+        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x112, 0xf, 0xf, false));
+        xi = __float_as_int(x);
+        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x114, 0xf, 0xf, false));
+        xi = __float_as_int(x);
+        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x118, 0xf, 0xf, false));
+        t[j] = x;
+    }
+}
+
+// Adds the wave's nine gradients of each of KG = 4 groups (splat slots
+// slot0 + gi[q]; a group with an empty mask adds nothing) into the LDS
+// accumulator: one combined reduction, then the four row leaders add.
+template <int BG, int KG>
+__device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[BG], int lane, uint32_t slot0,
+                                                  const int* gi, const uint64_t* gm) {
+    static_assert(KG * 9 == 36, "the combined reduction takes four groups");
+    float t[9];
+    wave_reduce36(v, t);
+    if ((lane & 15) == 15) {
+        const int r = lane >> 4;
+        const int c = r == 0 ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int idx = 4 * j + c, q = idx / 9, f = idx - 9 * q;
+            const int slot = (int)slot0 + (q == 0 ? gi[0] : q == 1 ? gi[1] : q == 2 ? gi[2] : gi[3]);
+            const uint64_t m = q == 0 ? gm[0] : q == 1 ? gm[1] : q == 2 ? gm[2] : gm[3];
+            if (m != 0ull) atomicAdd(&acc[f][slot], t[j]);
+        }
+    }
+}
+
 // One float atomic per field and splat of the batch into the canonical
 // 2D-gradient records (index map values[id]); the nine fields of a splat
 // share one 64-byte record, so consecutive lanes hit the same line.
@@ -461,14 +513,15 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
                     ent[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                     if ((gm[q] >> lane) & 1ull) ent[q] = tr.entry[ebase + gc[q] + lane_rank(gm[q])];
                 }
+                // the gradients of the kG groups, reduced over the wave together
+                float v[kG * 9];
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
                     const uint64_t m = gm[q];
-                    if (m == 0ull) continue;  // uniform: fewer than kG groups left
                     const int jj = (int)(c0 - base) + gi[q];
-                    const bool mine = (m >> lane) & 1ull;
-                    float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-                    if (mine) {
+#pragma unroll
+                    for (int f = 0; f < 9; ++f) v[q * 9 + f] = 0.f;
+                    if ((m >> lane) & 1ull) {
                         const Splat s = load_splat(L.a, L.b, L.c, jj);
                         const float dx = s.u - fpx, dy = s.v - fpy;
                         const float a = ent[q].w;
@@ -477,15 +530,15 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
                             g0 * (s.r - ent[q].x) + g1 * (s.g - ent[q].y) + g2 * (s.b - ent[q].z);
                         const bool clamped = a >= kAlphaMax;
                         chain_2d(s, dx, dy, a, clamped ? 0.f : a / s.o, clamped, dla, a * g0, a * g1,
-                                 a * g2, v);
+                                 a * g2, &v[q * 9]);
                         // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
                         const float om = 1.f - a;
                         g0 *= om;
                         g1 *= om;
                         g2 *= om;
                     }
-                    accumulate<BG>(v, L.acc, lane, jj, __popcll(m) == 1, mine);
                 }
+                accumulate_groups<BG, kG>(v, L.acc, lane, c0 - base, gi, gm);
                 cursor = cur;
             }
         }
