@@ -353,26 +353,6 @@ __device__ __forceinline__ void chain_2d(const Splat& s, float dx, float dy, flo
     v[8] = dc2;
 }
 
-// Adds one wave's nine gradients of splat jj into the workgroup's LDS
-// accumulator: a lone contributing lane adds its own values, otherwise the
-// wave sums with DPP and lane 63 adds (LDS float atomics, ds_add_f32).
-template <int BG>
-__device__ __forceinline__ void accumulate(const float* v, float (*acc)[BG], int lane, int jj, bool lone,
-                                           bool mine) {
-    if (lone) {
-        if (mine) {
-#pragma unroll
-            for (int f = 0; f < 9; ++f) atomicAdd(&acc[f][jj], v[f]);
-        }
-        return;
-    }
-#pragma unroll
-    for (int f = 0; f < 9; ++f) {
-        const float sum = wave_sum_to_lane63(v[f]);
-        if (lane == 63) atomicAdd(&acc[f][jj], sum);
-    }
-}
-
 // Sums 36 per-lane values over the wave with two swap-and-add stages
 // (v_permlane32_swap: lanes 0-31 of one register meet lanes 32-63 of
 // another; v_permlane16_swap: the same between 16-lane rows) and a DPP
@@ -586,32 +566,49 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
         stage_batch<NT, true>(L, j.proj, n, values, start + lo, nb, t);
         zero_acc<BG>(L.acc, t, NT);
         __syncthreads();
-        for (int jj = nb - 1; jj >= 0; --jj) {
-            if (!wr.hit(L.a[jj].x, L.a[jj].y, L.e[jj])) continue;  // uniform: no lane can use it
-            const uint32_t jrel = lo + jj;
-            bool ok = false;
-            float alpha = 0.f, gauss = 0.f, dx = 0.f, dy = 0.f;
-            Splat s{};
-            if (jrel < last) {
-                s = load_splat(L.a, L.b, L.c, jj);
-                ok = splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy);
+        // back to front; the gradients of four splats that some lane of
+        // the wave uses are reduced over the wave together
+        int jj = nb - 1;
+        while (jj >= 0) {
+            float v[36];
+            int gi[4];
+            uint64_t gm[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                gi[q] = 0;
+                gm[q] = 0ull;
+#pragma unroll
+                for (int f = 0; f < 9; ++f) v[q * 9 + f] = 0.f;
+                while (jj >= 0) {
+                    const int k = jj--;
+                    if (!wr.hit(L.a[k].x, L.a[k].y, L.e[k])) continue;  // uniform: no lane can use it
+                    bool ok = false;
+                    float alpha = 0.f, gauss = 0.f, dx = 0.f, dy = 0.f;
+                    Splat s{};
+                    if (lo + (uint32_t)k < last) {
+                        s = load_splat(L.a, L.b, L.c, k);
+                        ok = splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy);
+                    }
+                    const uint64_t m = __ballot(ok);
+                    if (m == 0) continue;
+                    if (ok) {
+                        const float Tk = T / (1.f - alpha);
+                        const float q0 = Tk * G0, q1 = Tk * G1, q2 = Tk * G2;
+                        const float dla = q0 * (s.r - a0) + q1 * (s.g - a1) + q2 * (s.b - a2);
+                        const bool clamped = s.o * gauss > kAlphaMax;
+                        chain_2d(s, dx, dy, alpha, gauss, clamped, dla, alpha * q0, alpha * q1, alpha * q2,
+                                 &v[q * 9]);
+                        a0 = alpha * s.r + (1.f - alpha) * a0;
+                        a1 = alpha * s.g + (1.f - alpha) * a1;
+                        a2 = alpha * s.b + (1.f - alpha) * a2;
+                        T = Tk;
+                    }
+                    gi[q] = k;
+                    gm[q] = m;
+                    break;
+                }
             }
-            const uint64_t m = __ballot(ok);
-            if (m == 0) continue;
-            float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            if (ok) {
-                const float Tk = T / (1.f - alpha);
-                const float q0 = Tk * G0, q1 = Tk * G1, q2 = Tk * G2;
-                const float dla = q0 * (s.r - a0) + q1 * (s.g - a1) + q2 * (s.b - a2);
-                const bool clamped = s.o * gauss > kAlphaMax;
-                chain_2d(s, dx, dy, alpha, gauss, clamped, dla, alpha * q0, alpha * q1,
-                         alpha * q2, v);
-                a0 = alpha * s.r + (1.f - alpha) * a0;
-                a1 = alpha * s.g + (1.f - alpha) * a1;
-                a2 = alpha * s.b + (1.f - alpha) * a2;
-                T = Tk;
-            }
-            accumulate<BG>(v, L.acc, lane, jj, __popcll(m) == 1, ok);
+            accumulate_groups<BG, 4>(v, L.acc, lane, 0u, gi, gm);
         }
         __syncthreads();
         flush_batch<BG>(L.acc, L.g, nb, n, grad2d, t, NT);
