@@ -88,17 +88,18 @@ def run_variant(wl, cached, steps, warmup, order):
         tr.step(wl["cams"][cid], targets[cid])
     torch.cuda.synchronize()
     tr.rast.flags.zero_()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
+    evs[0].record()
     for k in range(steps):
         cid = order[(warmup + k) % len(order)]
         tr.step(wl["cams"][cid], targets[cid])
-    end.record()
+        evs[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end) / steps
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    per_step = np.array([a.elapsed_time(b) for a, b in zip(evs[:-1], evs[1:])])
     flags = tr.rast.read_flags()
     if flags:
         raise RuntimeError(f"buffer overflow during the timed region (flags={flags})")
@@ -111,24 +112,59 @@ def run_variant(wl, cached, steps, warmup, order):
     stats = dict(pairs=P, entries=E, visible=visible, pixels=r.W * r.H, n=tr.n,
                  trace_gb=r.trace_bytes() / 1e9, capacity=r.capacity,
                  loss=float(tr.loss.item()))
-    return dict(ms=ms, wall_s=wall, kernels=per, stats=stats, trainer=tr)
+    pct = {f"p{q}": float(np.percentile(per_step, q)) for q in (10, 50, 90)}
+    return dict(ms=ms, wall_s=wall, kernels=per, stats=stats, trainer=tr, pct=pct)
+
+
+def render_fps(wl, params, order, frames=50):
+    """Render-only frames per second at the workload's resolution (projection,
+    bin/sort, compositing without the trace) on the trained parameters: the
+    deployment path that follows training."""
+    import torch
+    from paper_2601_17354_amd.raster import Rasterizer
+    r = Rasterizer(params.shape[1], 0, wl["width"], wl["height"], cached=False)
+    for cid in order[:8]:
+        r.forward_checked(params, wl["cams"][cid])
+    r.reserve(1.5)
+    for k in range(5):
+        r.forward(params, wl["cams"][order[k % len(order)]])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for k in range(frames):
+        r.forward(params, wl["cams"][order[k % len(order)]])
+    b.record()
+    torch.cuda.synchronize()
+    if r.read_flags():
+        raise RuntimeError("render-only pass overflowed")
+    return 1000.0 * frames / a.elapsed_time(b)
+
+
+# Bytes one launch must move at least, per unit of work (16x16 tiles, four
+# waves of 64 pixels per tile):
+#   per (tile, Gaussian) pair: the sorted id 4 B, the splat's record 48 B
+#     (u, v, A, B, C, o, rgb and extents), the trace's ballot mask of each
+#     wave 4 x 8 B (written forward, read backward), and backward the nine
+#     gradient fields 36 B accumulated into the canonical record;
+#   per trace entry: (C_in, alpha) 16 B, written once forward, read once
+#     backward;
+#   per pixel: forward image 12 B + T_final 4 B + n_contrib 4 B + count 4 B,
+#     backward dL/dimage 12 B (recompute also T_final and n_contrib, 8 B).
+PAIR_FWD, PAIR_BWD, MASKS, ENTRY = 4 + 48, 4 + 48 + 36, 4 * 8, 16
 
 
 def render_bwd_bytes(st, cached):
-    """Algorithmic HBM bytes of one render_bwd launch: trace entries 20 B
-    (cached) + per pixel 28 B + per (tile, Gaussian) pair 40 B gather and
-    36 B atomic payload."""
-    b = 28 * st["pixels"] + (40 + 36) * st["pairs"]
+    """Algorithmic HBM bytes of one render_bwd launch (see above)."""
     if cached:
-        b += 20 * st["entries"]
-    return b
+        return 12 * st["pixels"] + (PAIR_BWD + MASKS) * st["pairs"] + ENTRY * st["entries"]
+    return 20 * st["pixels"] + PAIR_BWD * st["pairs"]
 
 
 def render_fwd_bytes(st, cached):
-    b = 20 * st["pixels"] + 40 * st["pairs"]
+    """Algorithmic HBM bytes of one render_fwd launch (see above)."""
     if cached:
-        b += 28 * st["entries"]
-    return b
+        return 24 * st["pixels"] + (PAIR_FWD + MASKS) * st["pairs"] + ENTRY * st["entries"]
+    return 20 * st["pixels"] + PAIR_FWD * st["pairs"]
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -326,6 +362,8 @@ def main():
     cached = args.backward == "cached"
     res = run_variant(wl, cached, args.steps, args.warmup, order)
     log(f"{args.backward}: {res['ms']:.3f} ms/step, kernels {res['kernels']}, stats {res['stats']}")
+    fps = render_fps(wl, res["trainer"].params, order)
+    log(f"render-only: {fps:.1f} frames/s")
     other = None
     if not args.no_compare:
         del res["trainer"]
@@ -352,6 +390,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": res["ms"],
+        "ms_per_step_percentiles": res["pct"],
+        "ms_fwd_bwd": res["ms"] - res["kernels"].get("adam", 0.0),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -368,9 +408,11 @@ def main():
         "kernels_ms": kern,
         "work": st,
     }
+    out["render_only_fps"] = fps
     if other is not None:
         out["other_backward"] = {"backward": "recompute" if cached else "cached",
                                  "ms_per_step": other["ms"], "iters_per_s": 1000.0 / other["ms"],
+                                 "ms_per_step_percentiles": other["pct"],
                                  "kernels_ms": other["kernels"], "trace_gb": other["stats"]["trace_gb"]}
     if not args.no_psnr:
         log("held-out PSNR after 500 training steps per initialisation")
