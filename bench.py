@@ -215,9 +215,13 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
                      extent=4.5)
     st.prepare()
     st._alloc_pairs(int(st.capacity * 1.25), int(st.entry_capacity * 1.25))
-    ms_eager = time_steps(st.step, max(5, steps // 4), 2)
     st.capture()
+    # eager steps and graph replays from the same optimiser state, so that
+    # both time the same work (training changes the pair and entry counts)
+    snap = st.snapshot()
     ms_graph = time_steps(st.replay, steps, warmup)
+    st.restore(snap)
+    ms_eager = time_steps(st.step, steps, warmup)
     assert st.read_flags() == 0, "batched step overflowed during timing"
     stats = st.stats()
     del st

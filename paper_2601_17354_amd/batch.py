@@ -159,6 +159,17 @@ class BatchedStep:
             self._alloc_pairs(cap, ents)
         raise RuntimeError("batched step buffers kept overflowing")
 
+    # -- optimiser state -----------------------------------------------------
+    def snapshot(self):
+        """Copies of the parameters, Adam moments and step counter."""
+        return [t.clone() for t in (self.params, self.m, self.v, self.adam_state)]
+
+    def restore(self, snap):
+        """Puts a snapshot back in place (same buffers, so a captured graph
+        keeps working)."""
+        for dst, src in zip((self.params, self.m, self.v, self.adam_state), snap):
+            dst.copy_(src)
+
     # -- graph -------------------------------------------------------------
     def capture(self):
         """Records one step as a graph (after a warm-up step on a side stream,

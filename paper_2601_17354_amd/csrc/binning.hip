@@ -10,9 +10,9 @@
 //   scan     exclusive prefix sum of tiles_touched in depth order -> pair
 //            offsets + count
 //   emit     one (key, canonical id) pair per Gaussian x rectangle tile,
-//            key = tile << 32 | bits(float32 depth), one thread per pair
-//            (binary search over the offsets), so large Gaussians do not
-//            serialise
+//            key = tile << 32 | bits(float32 depth), each workgroup filling
+//            an equal range of pairs (binary search over the offsets), so
+//            large Gaussians do not serialise
 //   sort     stable LSD radix sort on the tile bits only, 8-bit digits;
 //            every pass is histogram -> device scan of the digit-major
 //            histogram -> stable scatter
@@ -169,10 +169,25 @@ __global__ __launch_bounds__(256) void k_gather_touched(uint32_t items, const ui
     if (i < items) cnt[i] = touched_all[dvals[i]];
 }
 
-// Pairs of the items in depth order, one thread per pair: the pair's item is
-// the last one whose offset is <= the pair index (binary search over the
-// scanned counts; empty items share their successor's offset and are never
-// chosen), so the work is even however unevenly the rectangles are sized.
+// Pairs of the items in depth order.  Workgroup b fills pairs
+// [1024 b, 1024 b + 1024): one binary search over the scanned counts finds
+// the item of its first pair; every item of the range has at least one pair
+// (empty items share their successor's offset), so the range spans at most
+// 1024 items, whose offsets go to LDS; each thread then finds its pairs'
+// items there.  The work per workgroup is even however unevenly the
+// rectangles are sized.
+constexpr int kEmitPairs = 1024;
+
+__device__ __forceinline__ uint32_t last_le(const uint32_t* off, uint32_t n, uint32_t p) {
+    uint32_t lo = 0, hi = n - 1;  // last j with off[j] <= p (off[0] <= p)
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(256) void k_emit_sorted(uint32_t items, int n, EmitViews ev,
                                                      const float* __restrict__ proj_all,
                                                      const uint32_t* __restrict__ rect_all,
@@ -181,17 +196,23 @@ __global__ __launch_bounds__(256) void k_emit_sorted(uint32_t items, int n, Emit
                                                      const uint32_t* __restrict__ num_pairs, uint32_t capacity,
                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ values,
                                                      uint32_t* __restrict__ flags) {
+    __shared__ uint32_t s_off[kEmitPairs + 1];
+    __shared__ uint32_t s_first;
     const uint32_t total = *num_pairs;
     if (blockIdx.x == 0 && threadIdx.x == 0 && total > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
     const uint32_t count = min(total, capacity);
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < count; p += gridDim.x * blockDim.x) {
-        uint32_t lo = 0, hi = items - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        const uint32_t item = dvals[lo], local = p - off[lo];
+    const uint32_t p0 = blockIdx.x * (uint32_t)kEmitPairs;
+    if (p0 >= count) return;  // uniform for the block
+    const uint32_t p1 = min(p0 + (uint32_t)kEmitPairs, count);
+    if (threadIdx.x == 0) s_first = last_le(off, items, p0);
+    __syncthreads();
+    const uint32_t i0 = s_first;
+    const uint32_t span = min((uint32_t)kEmitPairs + 1, items - i0);
+    for (uint32_t q = threadIdx.x; q < span; q += blockDim.x) s_off[q] = off[i0 + q];
+    __syncthreads();
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const uint32_t j = last_le(s_off, span, p);
+        const uint32_t item = dvals[i0 + j], local = p - s_off[j];
         const uint32_t v = item / (uint32_t)n, g = item - v * (uint32_t)n;
         int TX, toff;
         view_tiles(ev, (int)v, TX, toff);
@@ -478,7 +499,7 @@ pgs_status bin_sort_items(uint32_t items, int n, const EmitViews& ev, int n_tile
     k_gather_touched<<<g, 256, 0, s>>>(items, w.dvals, touched_all, w.off);
     st = scan_u32(w.off, w.off, items, num_pairs, w.partial, s);
     if (st != PGS_OK) return st;
-    const uint32_t ge = div_up(capacity, 256) < 16384 ? div_up(capacity, 256) : 16384;
+    const uint32_t ge = div_up(capacity, kEmitPairs);
     k_emit_sorted<<<ge > 0 ? ge : 1, 256, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals, w.off, num_pairs,
                                                   capacity, keys, values, flags);
     PGS_CHECK_LAUNCH(who);
