@@ -174,3 +174,19 @@ def test_graph_replay_matches_eager_steps():
         assert diff.max() <= 2.0 * (k + 2) * 2.5e-2, diff.max()
         assert (diff <= 1e-5).mean() > 0.99
     assert int(ga.adam_state[0].item()) == 5 and int(eb.adam_state[0].item()) == 5
+
+
+def test_tuner_times_candidates_and_caches_the_choice(tmp_path, monkeypatch):
+    from paper_2601_17354_amd.autotune import tune
+    monkeypatch.setenv("PGS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    P, cams = _views()
+    targets = [torch.zeros((3, c["height"], c["width"]), device=DEV) for c in cams]
+    params = torch.as_tensor(P, device=DEV)
+    cands = [((16, 16), 256), ((8, 8), 64)]
+    first = tune(params, 0, cams, targets, steps=2, warmup=1, cands=cands)
+    say(f"  tuning table {first['table']}")
+    assert not first["cached"] and len(first["table"]) == 2 and all(r["ok"] for r in first["table"])
+    assert (tuple(first["tile"]), first["batch"]) in cands
+    assert first["ms"] == min(r["ms"] for r in first["table"])
+    second = tune(params, 0, cams, targets, steps=2, warmup=1, cands=cands)
+    assert second["cached"] and second["tile"] == first["tile"] and second["batch"] == first["batch"]
