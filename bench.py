@@ -264,6 +264,53 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
             "one_view_at_a_time_flags": flags, "stats": stats, "tuning": tuned["table"]}
 
 
+def mlp_runs(rows=200_000, batch=16384, reps=20):
+    """The seeding network on its own: inference over `rows` feature rows
+    and one training step (forward, seed loss, backward, Adam) on a batch,
+    timed with HIP events; matrix-core throughput against the bf16 dense
+    peak (products only: 2 x 12,800 multiply-adds per row forward, twice
+    that more backward, where the first layer's input gradient is skipped)."""
+    import torch
+    from paper_2601_17354_amd import binding as B
+    from paper_2601_17354_amd.seed_mlp import SeedNetTrainer, load_weights
+    dev = torch.device("cuda")
+    g = torch.Generator(device=dev).manual_seed(0)
+    w = load_weights()
+    x = torch.randn((rows, 64), generator=g, device=dev)
+    y = torch.empty((rows, 8), device=dev)
+    for _ in range(3):
+        B.pgs_mlp_forward(w, x, rows, y)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        B.pgs_mlp_forward(w, x, rows, y)
+    b.record()
+    torch.cuda.synchronize()
+    ms_inf = a.elapsed_time(b) / reps
+    base = torch.zeros((batch, 16), device=dev)
+    base[:, 0] = base[:, 4] = base[:, 8] = 1.0
+    base[:, 9:12] = -3.0
+    base[:, 12] = 1.0
+    tgt = torch.zeros((batch, 8), device=dev)
+    tr = SeedNetTrainer(w, max_rows=batch)
+    xb = x[:batch].contiguous()
+    for _ in range(3):
+        tr.step(xb, base, tgt)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        tr.step(xb, base, tgt)
+    b.record()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / reps
+    fwd_flop = 2.0 * (3 * 64 * 64 + 64 * 8)
+    return {"inference_rows": rows, "inference_ms": ms_inf, "inference_rows_per_s": rows / (ms_inf * 1e-3),
+            "inference_tflops": rows * fwd_flop / (ms_inf * 1e-3) / 1e12,
+            "train_batch": batch, "train_step_ms": ms_step,
+            "train_tflops": batch * fwd_flop * 3 / (ms_step * 1e-3) / 1e12, "bf16_dense_peak_tflops": 2500.0}
+
+
 def achievable_bandwidth(nbytes=1 << 30, reps=10):
     """GB/s of the library's plain streaming copy (reads and writes nbytes)."""
     import torch
@@ -434,6 +481,9 @@ def main():
         b = out["batched_views"]
         log(f"batched: {b['ms_per_step_graph']:.2f} ms/step graph, {b['ms_per_step_eager']:.2f} eager, "
             f"{b['ms_per_step_one_view_at_a_time']:.2f} one view at a time")
+    log("seeding network alone")
+    out["seed_network"] = mlp_runs()
+    log(f"seed network: {out['seed_network']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.width, args.height, args.gaussians)

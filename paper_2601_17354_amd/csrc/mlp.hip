@@ -469,7 +469,7 @@ extern "C" pgs_status pgs_mlp_forward(const float* weights_dev, const float* x_d
     PGS_REQUIRE(weights_dev && x_dev && y_dev, "pgs_mlp_forward: null pointer");
     PGS_REQUIRE(aligned16(x_dev) && aligned16(y_dev), "pgs_mlp_forward: x and y must be 16-byte aligned");
     const int tiles = (m + kRows - 1) / kRows;
-    const int grid = tiles < 2048 ? tiles : 2048;
+    const int grid = tiles < 512 ? tiles : 512;   // persistent: each block converts the weights once
     k_mlp_forward<<<grid, kThreads, 0, pgs::as_stream(stream)>>>(weights_dev, x_dev, m, y_dev);
     PGS_CHECK_LAUNCH("pgs_mlp_forward");
     return PGS_OK;
