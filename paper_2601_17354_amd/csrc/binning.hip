@@ -245,44 +245,70 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
     __syncthreads();
     const uint32_t base = blockIdx.x * kSortItems;
     if (base < count) {
+        uint32_t d[kSortRounds];  // every load in flight before the first atomic
+#pragma unroll
         for (int r = 0; r < kSortRounds; ++r) {
             const uint32_t idx = base + r * kSortThreads + threadIdx.x;
-            if (idx < count) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 0xffu], 1u);
+            d[r] = idx < count ? (uint32_t)(keys[idx] >> shift) & 0xffu : kRadix;
         }
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r)
+            if (d[r] < kRadix) atomicAdd(&h[d[r]], 1u);
     }
     __syncthreads();
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter.  Each round handles 256 consecutive keys; a key's rank is
-// (keys of its digit already placed by this block) + (same digit in lower
-// waves of this round) + (same digit in lower lanes of its wave), the last
-// found by matching the 8 digit bits with wave ballots.
+// Stable scatter through LDS.  The block's digit counts are the differences
+// of consecutive entries of the scanned digit-major histogram (the last
+// entry's successor is the key count).  Each round handles 256 consecutive
+// keys; a key's position inside the block is (the digit's start in the
+// block) + (keys of its digit already placed) + (same digit in lower waves
+// of this round) + (same digit in lower lanes of its wave), the last found
+// by matching the 8 digit bits with wave ballots.  The keys go to LDS in
+// that order and leave as one contiguous run per digit, so the global
+// writes coalesce.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ num,
     uint32_t capacity, int shift, uint32_t nb, const uint32_t* __restrict__ offs) {
     constexpr int NW = kSortThreads / 64;
-    __shared__ uint32_t s_base[kRadix];
-    __shared__ uint32_t s_wcnt[NW][kRadix];
+    __shared__ uint64_t s_key[kSortItems];
+    __shared__ uint32_t s_val[kSortItems];
+    __shared__ uint32_t s_run[kRadix];     // next local position per digit
+    __shared__ uint32_t s_lbase[kRadix];   // digit start inside the block
+    __shared__ uint32_t s_gbase[kRadix];   // digit start in the output
+    __shared__ uint32_t s_wcnt[2][NW][kRadix];  // per-wave digit counts, two rounds in flight
+    __shared__ uint32_t s_scan[kSortThreads];
     const uint32_t count = clamp_count(num, capacity);
     const uint32_t base = blockIdx.x * kSortItems;
     if (base >= count) return;  // uniform for the block
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    s_base[t] = offs[(size_t)t * nb + blockIdx.x];
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const size_t e = (size_t)t * nb + blockIdx.x;
+    const uint32_t g0 = offs[e];
+    const uint32_t g1 = (e + 1 < (size_t)kRadix * nb) ? offs[e + 1] : count;
+    s_gbase[t] = g0;
+    for (int w = 0; w < NW; ++w) s_wcnt[0][w][t] = s_wcnt[1][w][t] = 0;
+    uint32_t total;
+    const uint32_t lb = block_exclusive_scan(g1 - g0, s_scan, total);
+    s_lbase[t] = lb;
+    s_run[t] = lb;
+    // All of the block's loads are issued before the first round, so the
+    // rounds wait on LDS only.
+    uint64_t kreg[kSortRounds];
+    uint32_t vreg[kSortRounds];
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        for (int w = 0; w < NW; ++w) s_wcnt[w][t] = 0;
-        __syncthreads();
         const uint32_t idx = base + r * kSortThreads + t;
-        const bool valid = idx < count;
-        uint64_t key = 0;
-        uint32_t val = 0, digit = 0;
-        if (valid) {
-            key = kin[idx];
-            val = vin[idx];
-            digit = (uint32_t)(key >> shift) & 0xffu;
-        }
+        kreg[r] = idx < count ? kin[idx] : 0ull;
+        vreg[r] = idx < count ? vin[idx] : 0u;
+    }
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        uint32_t (*cnt)[kRadix] = s_wcnt[r & 1];
+        const bool valid = base + r * kSortThreads + t < count;
+        const uint32_t digit = (uint32_t)(kreg[r] >> shift) & 0xffu;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -291,19 +317,29 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) s_wcnt[wv][digit] = __popcll(peers);
+        if (valid && rank == 0) cnt[wv][digit] = __popcll(peers);
         __syncthreads();
+        // The other buffer was last read before this barrier; clear it for
+        // the next round, whose writes come after the next barrier.
+        for (int w = 0; w < NW; ++w) s_wcnt[(r + 1) & 1][w][t] = 0;
         if (valid) {
-            uint32_t pos = s_base[digit] + rank;
-            for (int w = 0; w < wv; ++w) pos += s_wcnt[w][digit];
-            kout[pos] = key;
-            vout[pos] = val;
+            uint32_t pos = s_run[digit] + rank;
+            for (int w = 0; w < wv; ++w) pos += cnt[w][digit];
+            s_key[pos] = kreg[r];
+            s_val[pos] = vreg[r];
         }
         __syncthreads();
         uint32_t add = 0;
-        for (int w = 0; w < NW; ++w) add += s_wcnt[w][t];
-        s_base[t] += add;
-        __syncthreads();  // counts read; the next round may clear them
+        for (int w = 0; w < NW; ++w) add += cnt[w][t];
+        s_run[t] += add;
+    }
+    const uint32_t here = min((uint32_t)kSortItems, count - base);
+    for (uint32_t i = t; i < here; i += kSortThreads) {
+        const uint64_t key = s_key[i];
+        const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+        const uint32_t pos = s_gbase[d] + (i - s_lbase[d]);
+        kout[pos] = key;
+        vout[pos] = s_val[i];
     }
 }
 
