@@ -56,8 +56,11 @@
 
 namespace pgs {
 
+// A splat as staged in LDS: mean (u, v), the conic (A, B, C) held as
+// hA = -A/2, nB = -B, hC = -C/2 (scalings by powers of two and a sign, so
+// exact), opacity and colour.
 struct Splat {
-    float u, v, A, B, C, o, r, g, b;
+    float u, v, hA, nB, hC, o, r, g, b;
 };
 
 // Alpha of a splat at pixel centre (px, py).  Evaluated with contraction off
@@ -67,11 +70,11 @@ __device__ __forceinline__ bool splat_alpha(const Splat& s, float px, float py, 
 #pragma clang fp contract(off)
     dx = s.u - px;
     dy = s.v - py;
-    const float power = -0.5f * (s.A * dx * dx + s.C * dy * dy) - s.B * dx * dy;
-    if (power > 0.f) return false;
+    // power = -(A dx^2 + 2 B dx dy + C dy^2) / 2 = (hA dx + nB dy) dx + hC dy^2
+    const float power = __builtin_fmaf(__builtin_fmaf(s.hA, dx, s.nB * dy), dx, s.hC * dy * dy);
     gauss = __expf(power);
     alpha = fminf(kAlphaMax, s.o * gauss);
-    return alpha >= kAlphaMin;
+    return !(power > 0.f) && alpha >= kAlphaMin;
 }
 
 // One splat's record (u, v, depth, A | B, C, o, r | g, b, ex, ey) is one
@@ -84,8 +87,8 @@ __device__ __forceinline__ void stage_splat(const float* __restrict__ proj, int 
     (void)n;
     const float4* rec = reinterpret_cast<const float4*>(proj + (size_t)g * PGS_PROJ_STRIDE);
     const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-    sa[slot] = make_float4(r0.x, r0.y, r0.w, r1.x);   // u, v, A, B
-    sb[slot] = make_float4(r1.y, r1.z, r1.w, r2.x);   // C, o, r, g
+    sa[slot] = make_float4(r0.x, r0.y, -0.5f * r0.w, -r1.x);   // u, v, hA, nB
+    sb[slot] = make_float4(-0.5f * r1.y, r1.z, r1.w, r2.x);    // hC, o, r, g
     sc[slot] = r2.y;                                  // b
     se[slot] = make_float2(r2.z, r2.w);               // extents
 }
@@ -115,6 +118,13 @@ __device__ __forceinline__ Splat load_splat(const float4* sa, const float4* sb, 
     return Splat{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, sc[k]};
 }
 
+// Mean, conic and opacity of a staged splat (colour left zero).
+__device__ __forceinline__ Splat load_shape(const float4* sa, const float4* sb, int k) {
+    const float4 a = sa[k];
+    const float2 b = *reinterpret_cast<const float2*>(&sb[k]);
+    return Splat{a.x, a.y, a.z, a.w, b.x, b.y, 0.f, 0.f, 0.f};
+}
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -123,6 +133,31 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// Transposes the 64 x 64 bit matrix whose row r is lane r's h: afterwards
+// lane s holds bit s of every lane's h, bit r from lane r.  Six block-swap
+// stages; stage j exchanges the j x j blocks between lanes r and r ^ j.
+__device__ __forceinline__ uint64_t transpose64(uint64_t h, int lane) {
+    constexpr uint64_t kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                   0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const int j = 32 >> l;
+        const uint32_t plo = (uint32_t)__shfl_xor((int)(uint32_t)h, j);
+        const uint32_t phi = (uint32_t)__shfl_xor((int)(uint32_t)(h >> 32), j);
+        const uint64_t p = ((uint64_t)phi << 32) | plo;
+        const bool low = (lane & j) == 0;
+        const uint64_t d = low ? (((h >> j) ^ p) & kMask[l]) : (((p >> j) ^ h) & kMask[l]);
+        h ^= low ? (d << j) : d;
+    }
+    return h;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) v += (uint32_t)__shfl_xor((int)v, j);
+    return v;
 }
 
 struct Trace {
@@ -190,6 +225,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
                                          FwdLds<BG>& L) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
+    static_assert((BG & (BG - 1)) == 0 && BG % FWD_UNROLL == 0, "batch: a power of two, whole groups");
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
     const bool inside = px < j.W && py < j.H;
@@ -199,63 +235,82 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     // the trace is recorded only if this tile's pairs fit the trace buffers
     const bool rec = CACHED && end <= tr.pair_cap;
     if (CACHED && !rec && t == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
-    uint32_t cursor = 0, steps = 0, cnt = 0;
-    // masks of the current 64-step chunk, lane i holding step i; written
-    // as one coalesced 512-byte run per chunk (wave-major mask layout)
+    // Each lane keeps the composited bits of the current 64-step chunk
+    // (bit s: this pixel took step s); a full chunk is transposed over the
+    // wave into the chunk's 64 step masks and written as one coalesced
+    // 512-byte run (wave-major mask layout).  The lane's entry count and
+    // last contributing step come from the same bits.
     uint64_t* wmask = tr.mask + (size_t)wv * tr.pair_cap + start;
-    uint64_t mreg = 0ull;
+    uint64_t hist = 0ull;
+    uint32_t steps = 0, cnt = 0, last = 0;
+    auto flush_chunk = [&](uint32_t c0, uint32_t cn) {
+        cnt += (uint32_t)__popcll(hist);
+        if (hist) last = c0 + 64u - (uint32_t)__clzll(hist);
+        if (rec) {
+            const uint64_t m = transpose64(hist, lane);
+            if ((uint32_t)lane < cn) wmask[c0 + lane] = m;
+        }
+        hist = 0ull;
+    };
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
     bool done = !inside;
-    uint32_t last = 0;
 
     for (uint32_t base = start; base < end; base += BG) {
         if (__syncthreads_count(!done) == 0) break;
         const int nb = (int)min((uint32_t)BG, end - base);
         stage_batch<NT, false>(L, j.proj, n, values, base, nb, t);
         __syncthreads();
-        // the wave checks for termination once per FWD_UNROLL splats, so
-        // that the splat loads and alpha evaluations of a group overlap
+        // The wave takes FWD_UNROLL splats at a time: all their LDS loads
+        // and alphas first, straight-line (slots past the batch hold stale,
+        // in-bounds data that the valid flag discards), then the steps in
+        // order, with a termination check per group.
         for (int k0 = 0; k0 < nb; k0 += FWD_UNROLL) {
             if (__ballot(!done) == 0) break;  // the whole wave has terminated
+            // geometry and opacity only; the colours are read by the steps
+            // that composite
+            Splat sp[FWD_UNROLL];
+#pragma unroll
+            for (int u = 0; u < FWD_UNROLL; ++u) sp[u] = load_shape(L.a, L.b, (k0 + u) & (BG - 1));
+            float al[FWD_UNROLL];
+            bool hit[FWD_UNROLL];
 #pragma unroll
             for (int u = 0; u < FWD_UNROLL; ++u) {
-                const int k = k0 + u;
-                if (k < nb) {
-                    bool contrib = false;
-                    float alpha = 0.f;
-                    if (!done) {
-                        const Splat s = load_splat(L.a, L.b, L.c, k);
-                        float gauss, dx, dy;
-                        if (splat_alpha(s, fpx, fpy, alpha, gauss, dx, dy)) {
-                            const float test_T = T * (1.f - alpha);
-                            if (test_T < kTMin) {
-                                done = true;
-                            } else {
-                                contrib = true;
-                                const float w = alpha * T;
-                                C0 += w * s.r;
-                                C1 += w * s.g;
-                                C2 += w * s.b;
-                                T = test_T;
-                                last = base + k - start + 1;
-                            }
-                        }
-                    }
-                    if (rec) {
-                        const uint64_t m = __ballot(contrib);
-                        const uint32_t rel = base + k - start;
-                        if ((uint32_t)lane == (rel & 63u)) mreg = m;
-                        if ((rel & 63u) == 63u) wmask[rel - 63u + lane] = mreg;
-                        cursor += __popcll(m);
-                        cnt += contrib ? 1u : 0u;
-                        steps = rel + 1;
+                float gauss, dx, dy;
+                hit[u] = splat_alpha(sp[u], fpx, fpy, al[u], gauss, dx, dy) && k0 + u < nb;
+            }
+            uint32_t bits = 0;
+#pragma unroll
+            for (int u = 0; u < FWD_UNROLL; ++u) {
+                // exec-masked: a step none of the wave's pixels takes is
+                // skipped by the whole wave
+                if (hit[u] && !done) {
+                    const float alpha = al[u];
+                    const float test_T = T * (1.f - alpha);
+                    if (test_T < kTMin) {
+                        done = true;
+                    } else {
+                        const int k = (k0 + u) & (BG - 1);
+                        const float2 rg = *reinterpret_cast<const float2*>(&L.b[k].z);
+                        const float w = alpha * T;
+                        C0 += w * rg.x;
+                        C1 += w * rg.y;
+                        C2 += w * L.c[k];
+                        T = test_T;
+                        bits |= 1u << u;
                     }
                 }
             }
+            const uint32_t rel0 = base + (uint32_t)k0 - start;
+            const uint32_t nv = (uint32_t)min(FWD_UNROLL, nb - k0);
+            steps = rel0 + nv;
+            hist |= (uint64_t)bits << (rel0 & 63u);
+            if (((rel0 + FWD_UNROLL) & 63u) == 0u && nv == FWD_UNROLL) flush_chunk(rel0 + FWD_UNROLL - 64u, 64u);
         }
     }
-    if (rec && (steps & 63u) && (uint32_t)lane < (steps & 63u)) wmask[(steps & ~63u) + lane] = mreg;
+    if (steps & 63u) flush_chunk(steps & ~63u, steps & 63u);
+    uint32_t cursor = 0;
+    if (rec) cursor = wave_sum_u32(cnt);
     // the wave's entry region: `cursor` entries from the bump counter
     size_t ebase = 0;
     bool wrec = rec;
@@ -308,27 +363,54 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
         __syncthreads();
         const uint32_t whi = min(hi, steps);
         if (whi <= (uint32_t)lo) continue;
-        // chunks of 64 steps, last chunk first; one vector load fetches a
-        // chunk's masks, then the non-empty ones are visited last to first
-        for (int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64; c0 >= lo; c0 -= 64) {
-            const uint32_t cn = min(64u, whi - (uint32_t)c0);
-            const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)wv * tr.pair_cap + start + c0 + lane] : 0ull;
+        // windows of 64 steps, last first; one vector load fetches a
+        // window's masks (the next window's is in flight meanwhile), then the
+        // non-empty ones are taken last to first, four at a time: their
+        // splats' loads and alphas first, then each set lane writes its
+        // entries in order
+        const uint64_t* wm = tr.mask + (size_t)wv * tr.pair_cap + start;
+        int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64;
+        uint64_t mv = (uint32_t)lane < min(64u, whi - (uint32_t)c0) ? wm[c0 + lane] : 0ull;
+        for (; c0 >= lo; c0 -= 64) {
+            const uint64_t mnext = c0 - 64 >= lo ? wm[c0 - 64 + lane] : 0ull;  // a full window
             uint64_t any = __ballot(mv != 0ull);
             while (any) {
-                const int i = 63 - __clzll(any);
-                any &= ~(1ull << i);
-                const uint64_t m = read_lane64(mv, i);
-                cur -= __popcll(m);
-                if ((m >> lane) & 1ull) {
-                    const Splat s = load_splat(L.a, L.b, L.c, (int)(c0 + i - lo));
-                    float a = 0.f, gauss, dx, dy;
-                    splat_alpha(s, fpx, fpy, a, gauss, dx, dy);
-                    tr.entry[ebase + cur + lane_rank(m)] = make_float4(a0, a1, a2, a);
-                    a0 = a * s.r + (1.f - a) * a0;
-                    a1 = a * s.g + (1.f - a) * a1;
-                    a2 = a * s.b + (1.f - a) * a2;
+                int gi[4];
+                uint64_t gm[4];
+                uint32_t gc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    gi[q] = 0;
+                    gm[q] = 0ull;
+                    if (any) {
+                        const int i = 63 - __clzll(any);
+                        any &= ~(1ull << i);
+                        gi[q] = i;
+                        gm[q] = read_lane64(mv, i);
+                        cur -= __popcll(gm[q]);
+                    }
+                    gc[q] = cur;
+                }
+                Splat sq[4];
+                float al[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sq[q] = load_splat(L.a, L.b, L.c, (int)(c0 - lo) + gi[q]);
+                    float gauss, dx, dy;
+                    splat_alpha(sq[q], fpx, fpy, al[q], gauss, dx, dy);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if ((gm[q] >> lane) & 1ull) {
+                        const float a = al[q];
+                        tr.entry[ebase + gc[q] + lane_rank(gm[q])] = make_float4(a0, a1, a2, a);
+                        a0 = a * sq[q].r + (1.f - a) * a0;
+                        a1 = a * sq[q].g + (1.f - a) * a1;
+                        a2 = a * sq[q].b + (1.f - a) * a2;
+                    }
                 }
             }
+            mv = mnext;
         }
     }
 }
@@ -342,8 +424,9 @@ __device__ __forceinline__ void chain_2d(const Splat& s, float dx, float dy, flo
         dpow = alpha * dl_dalpha;
         d_o = dgauss_do * dl_dalpha;
     }
-    v[0] = -(s.A * dx + s.B * dy) * dpow;
-    v[1] = -(s.B * dx + s.C * dy) * dpow;
+    // -(A dx + B dy) and -(B dx + C dy) from the staged halves
+    v[0] = (2.f * s.hA * dx + s.nB * dy) * dpow;
+    v[1] = (s.nB * dx + 2.f * s.hC * dy) * dpow;
     v[2] = -0.5f * dx * dx * dpow;
     v[3] = -dx * dy * dpow;
     v[4] = -0.5f * dy * dy * dpow;
