@@ -201,6 +201,7 @@ struct TileLds {
     float c[BG];
     float2 e[BG];
     uint32_t g[BG];
+    float io[BG];  // 1 / opacity
     float acc[9][BG];
     uint32_t steps;
 };
@@ -212,8 +213,11 @@ __device__ __forceinline__ void stage_batch(Lds& L, const float* __restrict__ pr
                                             int t) {
     for (int q = t; q < nb; q += NT) {
         const uint32_t g = values[base + q];
-        if constexpr (KEEP_IDS) L.g[q] = g;
         stage_splat(proj, n, g, L.a, L.b, L.c, L.e, q);
+        if constexpr (KEEP_IDS) {
+            L.g[q] = g;
+            L.io[q] = 1.f / L.b[q].y;
+        }
     }
 }
 
@@ -419,17 +423,15 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
 __device__ __forceinline__ void chain_2d(const Splat& s, float dx, float dy, float alpha,
                                          float dgauss_do, bool clamped, float dl_dalpha,
                                          float dc0, float dc1, float dc2, float* v) {
-    float dpow = 0.f, d_o = 0.f;
-    if (!clamped) {
-        dpow = alpha * dl_dalpha;
-        d_o = dgauss_do * dl_dalpha;
-    }
-    // -(A dx + B dy) and -(B dx + C dy) from the staged halves
-    v[0] = (2.f * s.hA * dx + s.nB * dy) * dpow;
-    v[1] = (s.nB * dx + 2.f * s.hC * dy) * dpow;
-    v[2] = -0.5f * dx * dx * dpow;
-    v[3] = -dx * dy * dpow;
-    v[4] = -0.5f * dy * dy * dpow;
+    const float dpow = clamped ? 0.f : alpha * dl_dalpha;
+    const float d_o = clamped ? 0.f : dgauss_do * dl_dalpha;
+    const float px = dpow * dx, py = dpow * dy;
+    // -(A dx + B dy) dpow and -(B dx + C dy) dpow from the staged halves
+    v[0] = __builtin_fmaf(s.hA, px, __builtin_fmaf(s.hA, px, s.nB * py));
+    v[1] = __builtin_fmaf(s.hC, py, __builtin_fmaf(s.hC, py, s.nB * px));
+    v[2] = -0.5f * dx * px;
+    v[3] = -dy * px;
+    v[4] = -0.5f * dy * py;
     v[5] = d_o;
     v[6] = dc0;
     v[7] = dc1;
@@ -576,30 +578,26 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
                     ent[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                     if ((gm[q] >> lane) & 1ull) ent[q] = tr.entry[ebase + gc[q] + lane_rank(gm[q])];
                 }
-                // the gradients of the kG groups, reduced over the wave together
+                // the gradients of the kG groups, reduced over the wave
+                // together; every lane computes them, a lane without an entry
+                // in a group holding alpha = 0 there, which makes its nine
+                // values and its change of dL/dC_out exactly zero
                 float v[kG * 9];
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
-                    const uint64_t m = gm[q];
                     const int jj = (int)(c0 - base) + gi[q];
-#pragma unroll
-                    for (int f = 0; f < 9; ++f) v[q * 9 + f] = 0.f;
-                    if ((m >> lane) & 1ull) {
-                        const Splat s = load_splat(L.a, L.b, L.c, jj);
-                        const float dx = s.u - fpx, dy = s.v - fpy;
-                        const float a = ent[q].w;
-                        // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
-                        const float dla =
-                            g0 * (s.r - ent[q].x) + g1 * (s.g - ent[q].y) + g2 * (s.b - ent[q].z);
-                        const bool clamped = a >= kAlphaMax;
-                        chain_2d(s, dx, dy, a, clamped ? 0.f : a / s.o, clamped, dla, a * g0, a * g1,
-                                 a * g2, &v[q * 9]);
-                        // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
-                        const float om = 1.f - a;
-                        g0 *= om;
-                        g1 *= om;
-                        g2 *= om;
-                    }
+                    const Splat s = load_splat(L.a, L.b, L.c, jj);
+                    const float dx = s.u - fpx, dy = s.v - fpy;
+                    const float a = ent[q].w;
+                    // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
+                    const float dla = g0 * (s.r - ent[q].x) + g1 * (s.g - ent[q].y) + g2 * (s.b - ent[q].z);
+                    const bool clamped = a >= kAlphaMax;
+                    chain_2d(s, dx, dy, a, a * L.io[jj], clamped, dla, a * g0, a * g1, a * g2, &v[q * 9]);
+                    // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
+                    const float om = 1.f - a;
+                    g0 *= om;
+                    g1 *= om;
+                    g2 *= om;
                 }
                 accumulate_groups<BG, kG>(v, L.acc, lane, c0 - base, gi, gm);
                 cursor = cur;
