@@ -129,6 +129,15 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// base + (set bits of m below this lane): a lane's entry in a group of m.
+__device__ __forceinline__ uint32_t entry_slot(uint64_t m, uint32_t base) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
+}
+
+// Whether this lane's bit is set in the wave-uniform mask m (the mask
+// becomes the execution mask directly).
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 __device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
@@ -373,6 +382,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
         // splats' loads and alphas first, then each set lane writes its
         // entries in order
         const uint64_t* wm = tr.mask + (size_t)wv * tr.pair_cap + start;
+        float4* went = tr.entry + ebase;  // the wave's entry region
         int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64;
         uint64_t mv = (uint32_t)lane < min(64u, whi - (uint32_t)c0) ? wm[c0 + lane] : 0ull;
         for (; c0 >= lo; c0 -= 64) {
@@ -405,9 +415,9 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if ((gm[q] >> lane) & 1ull) {
+                    if (lane_in(gm[q])) {
                         const float a = al[q];
-                        tr.entry[ebase + gc[q] + lane_rank(gm[q])] = make_float4(a0, a1, a2, a);
+                        went[entry_slot(gm[q], gc[q])] = make_float4(a0, a1, a2, a);
                         a0 = a * sq[q].r + (1.f - a) * a0;
                         a1 = a * sq[q].g + (1.f - a) * a1;
                         a2 = a * sq[q].b + (1.f - a) * a2;
@@ -525,6 +535,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
     const size_t ebase = tr.base[(size_t)j.gt * NW + wv];
+    const float4* went = tr.entry + ebase;  // the wave's entry region
 
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;  // dL/dC_out of this pixel's next entry
     if (inside) {
@@ -576,7 +587,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
 #pragma unroll
                 for (int q = 0; q < kG; ++q) {
                     ent[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if ((gm[q] >> lane) & 1ull) ent[q] = tr.entry[ebase + gc[q] + lane_rank(gm[q])];
+                    if (lane_in(gm[q])) ent[q] = went[entry_slot(gm[q], gc[q])];
                 }
                 // the gradients of the kG groups, reduced over the wave
                 // together; every lane computes them, a lane without an entry
