@@ -369,24 +369,33 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     uint32_t cur = cursor;
     if (smax == 0) return;
     const int64_t top = (int64_t)((smax - 1) / BG) * BG;  // first position of the last batch
+    // Windows of 64 steps per batch.  A batch's masks are loaded together
+    // with its splats: a wait on a vector load also waits for the entry
+    // stores issued before it, so this costs one such wait per batch rather
+    // than one per window.
+    constexpr int kWin = BG >= 64 ? BG / 64 : 1;
+    const uint64_t* wm = tr.mask + (size_t)wv * tr.pair_cap + start;
+    float4* went = tr.entry + ebase;  // the wave's entry region
     for (int64_t lo = top; lo >= 0; lo -= BG) {
         const uint32_t hi = min((uint32_t)lo + BG, smax);
         __syncthreads();
         stage_batch<NT, false>(L, j.proj, n, values, start + (uint32_t)lo, (int)(hi - (uint32_t)lo), t);
-        __syncthreads();
         const uint32_t whi = min(hi, steps);
-        if (whi <= (uint32_t)lo) continue;
-        // windows of 64 steps, last first; one vector load fetches a
-        // window's masks (the next window's is in flight meanwhile), then the
-        // non-empty ones are taken last to first, four at a time: their
-        // splats' loads and alphas first, then each set lane writes its
-        // entries in order
-        const uint64_t* wm = tr.mask + (size_t)wv * tr.pair_cap + start;
-        float4* went = tr.entry + ebase;  // the wave's entry region
-        int64_t c0 = lo + (int64_t)((whi - 1 - lo) / 64) * 64;
-        uint64_t mv = (uint32_t)lane < min(64u, whi - (uint32_t)c0) ? wm[c0 + lane] : 0ull;
-        for (; c0 >= lo; c0 -= 64) {
-            const uint64_t mnext = c0 - 64 >= lo ? wm[c0 - 64 + lane] : 0ull;  // a full window
+        uint64_t mw[kWin];
+#pragma unroll
+        for (int w = 0; w < kWin; ++w) {
+            const uint32_t c0 = (uint32_t)lo + 64u * w;
+            mw[w] = c0 + (uint32_t)lane < whi ? wm[c0 + lane] : 0ull;
+        }
+        __syncthreads();
+        // windows last to first; the non-empty groups of a window are taken
+        // last to first, four at a time: their splats' loads and alphas
+        // first, then each set lane writes its entries in order
+#pragma unroll
+        for (int w = kWin - 1; w >= 0; --w) {
+            const uint32_t c0 = (uint32_t)lo + 64u * w;
+            if (c0 >= whi) continue;  // uniform
+            const uint64_t mv = mw[w];
             uint64_t any = __ballot(mv != 0ull);
             while (any) {
                 int gi[4];
@@ -409,7 +418,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
                 float al[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    sq[q] = load_splat(L.a, L.b, L.c, (int)(c0 - lo) + gi[q]);
+                    sq[q] = load_splat(L.a, L.b, L.c, 64 * w + gi[q]);
                     float gauss, dx, dy;
                     splat_alpha(sq[q], fpx, fpy, al[q], gauss, dx, dy);
                 }
@@ -424,7 +433,6 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
                     }
                 }
             }
-            mv = mnext;
         }
     }
 }
