@@ -201,6 +201,9 @@ struct FwdLds {
     float c[BG];
     float2 e[BG];
     uint32_t steps;
+    // per wave of the tile: entries, steps, fit flag and region start
+    uint32_t wcur[4], wsteps[4], wfit[4];
+    unsigned long long wbase[4];
 };
 
 template <int BG>
@@ -239,6 +242,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
     static_assert((BG & (BG - 1)) == 0 && BG % FWD_UNROLL == 0, "batch: a power of two, whole groups");
+    static_assert(NW <= 4, "at most four waves per tile");
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
     const bool inside = px < j.W && py < j.H;
@@ -324,20 +328,43 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     if (steps & 63u) flush_chunk(steps & ~63u, steps & 63u);
     uint32_t cursor = 0;
     if (rec) cursor = wave_sum_u32(cnt);
-    // the wave's entry region: `cursor` entries from the bump counter
+    // Entry regions: one bump-counter atomic per tile (a single device-wide
+    // address, so per-wave atomics would queue there), split among the
+    // waves in order.  A wave whose region does not fit the entry capacity
+    // is left unrecorded (its step count becomes 0, so the backward reads
+    // nothing of it) and the overflow flag is raised; the counter keeps the
+    // demand either way.
     size_t ebase = 0;
     bool wrec = rec;
-    if (rec) {
-        unsigned long long b = 0;
-        if (lane == 0 && cursor) b = atomicAdd(tr.used, (unsigned long long)cursor);
-        b = read_lane64(b, 0);
-        wrec = b + cursor <= tr.entry_cap;
-        if (!wrec) {
-            if (lane == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
-            steps = 0;   // the backward reads nothing of this wave
-        } else {
-            ebase = (size_t)b;
+    uint32_t smax = 0;
+    if (rec) {  // uniform for the block
+        if (lane == 0) {
+            L.wcur[wv] = cursor;
+            L.wsteps[wv] = steps;
         }
+        __syncthreads();
+        if (t == 0) {
+            unsigned long long total = 0;
+            for (int w = 0; w < NW; ++w) total += L.wcur[w];
+            unsigned long long b = total ? atomicAdd(tr.used, total) : 0ull;
+            uint32_t sm = 0;
+            bool lost = false;
+            for (int w = 0; w < NW; ++w) {
+                const bool fit = L.wcur[w] == 0 || b + L.wcur[w] <= tr.entry_cap;
+                L.wfit[w] = fit;
+                L.wbase[w] = fit ? b : 0ull;
+                if (fit) sm = max(sm, L.wsteps[w]);
+                lost |= !fit;
+                b += L.wcur[w];
+            }
+            if (lost) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
+            L.steps = sm;
+        }
+        __syncthreads();
+        wrec = L.wfit[wv] != 0;
+        ebase = (size_t)L.wbase[wv];
+        smax = L.steps;
+        if (!wrec) steps = 0;
     }
     if (inside) {
         const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
@@ -359,12 +386,6 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     // set lane re-evaluates alpha with the same arithmetic as above (same
     // bits) and writes its entry (C_in, alpha) once, C_in being the colour
     // accumulated behind the splat so far.
-    __syncthreads();
-    if (t == 0) L.steps = 0;
-    __syncthreads();
-    if (lane == 0) atomicMax(&L.steps, steps);
-    __syncthreads();
-    const uint32_t smax = L.steps;
     float a0 = bg0, a1 = bg1, a2 = bg2;
     uint32_t cur = cursor;
     if (smax == 0) return;
