@@ -29,11 +29,13 @@
 //
 // Backward (equation "backward_chain"), two variants:
 //   cached     steps through each wave's groups front to back, visiting only
-//              non-empty masks; a lane with a bit set reads its entry, takes
+//              non-empty masks, four groups at a time with the next four's
+//              entries in flight; a lane with a bit set reads its entry, takes
 //              dL/dC_out (starts at dL/dC, times (1 - alpha) after each own
 //              entry), dL/dalpha = <dL/dC_out, c - C_in> and dL/dc =
 //              alpha dL/dC_out, chains them to the nine 2D parameters, and the
-//              wave reduces them with DPP (a lone lane writes directly).
+//              wave reduces the four groups' values together (lane swaps and
+//              DPP).
 //   recompute  walks the list back to front from n_contrib, re-evaluates
 //              alpha with the forward's exact arithmetic, recovers
 //              T_k = T_{k+1} / (1 - alpha_k) from T_final and accumulates the
@@ -45,10 +47,6 @@
 
 #include "common.hpp"
 
-// Trace groups whose entries a wave loads before consuming the first one.
-#ifndef PGS_TRACE_GROUPS
-#define PGS_TRACE_GROUPS 4
-#endif
 // Splats a wave composites between two termination checks.
 #ifndef FWD_UNROLL
 #define FWD_UNROLL 8
@@ -548,6 +546,65 @@ __device__ __forceinline__ void zero_acc(float (*acc)[BG], int t, int NT) {
     for (int idx = t; idx < 9 * BG; idx += NT) (&acc[0][0])[idx] = 0.f;
 }
 
+// Up to four non-empty groups of a 64-step window, front to back: the
+// step within the window, the lane mask and the first entry (relative to the
+// wave's region) of each; an unused slot has an empty mask.
+struct TraceGroups {
+    int gi[4];
+    uint64_t gm[4];
+    uint32_t gc[4];
+};
+
+__device__ __forceinline__ void take_groups(uint64_t& any, uint64_t mv, uint32_t& cursor, TraceGroups& g) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        g.gi[q] = 0;
+        g.gm[q] = 0ull;
+        g.gc[q] = cursor;
+        if (any) {
+            const int i = __ffsll((unsigned long long)any) - 1;
+            any &= any - 1;
+            g.gi[q] = i;
+            g.gm[q] = read_lane64(mv, i);
+            cursor += __popcll(g.gm[q]);
+        }
+    }
+}
+
+// Every lane loads: its own entry where it has one, else the wave's first
+// entry (the region is not empty when a group exists); alpha is taken as 0
+// for the latter in bwd_groups.
+__device__ __forceinline__ void load_groups(const float4* went, const TraceGroups& g, float4* e) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) e[q] = went[lane_in(g.gm[q]) ? entry_slot(g.gm[q], g.gc[q]) : 0u];
+}
+
+// Gradients of four groups at this lane's pixel, reduced over the wave into
+// the batch accumulator; a lane without an entry in a group contributes
+// exact zeros there and keeps its dL/dC_out.
+template <int BG, class Lds>
+__device__ __forceinline__ void bwd_groups(const TraceGroups& g, const float4* e, Lds& L, uint32_t slot0, float fpx,
+                                           float fpy, int lane, float& g0, float& g1, float& g2) {
+    float v[36];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int jj = (int)slot0 + g.gi[q];
+        const Splat s = load_splat(L.a, L.b, L.c, jj);
+        const float dx = s.u - fpx, dy = s.v - fpy;
+        const float a = lane_in(g.gm[q]) ? e[q].w : 0.f;
+        // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
+        const float dla = g0 * (s.r - e[q].x) + g1 * (s.g - e[q].y) + g2 * (s.b - e[q].z);
+        const bool clamped = a >= kAlphaMax;
+        chain_2d(s, dx, dy, a, a * L.io[jj], clamped, dla, a * g0, a * g1, a * g2, &v[q * 9]);
+        // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
+        const float om = 1.f - a;
+        g0 *= om;
+        g1 *= om;
+        g2 *= om;
+    }
+    accumulate_groups<BG, 4>(v, L.acc, lane, slot0, g.gi, g.gm);
+}
+
 template <int TW, int TH, int BG>
 __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_total, int n,
                                                 const uint32_t* __restrict__ values,
@@ -591,56 +648,32 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
             const uint32_t cn = min(64u, whi - c0);
             const uint64_t mv = (uint32_t)lane < cn ? tr.mask[(size_t)wv * tr.pair_cap + start + c0 + lane] : 0ull;
             uint64_t any = __ballot(mv != 0ull);
-            while (any) {
-                // take up to kG groups and issue all their trace loads before
-                // any of them is consumed (memory-level parallelism per wave)
-                constexpr int kG = PGS_TRACE_GROUPS;
-                int gi[kG];
-                uint64_t gm[kG];
-                uint32_t gc[kG];
-                uint32_t cur = cursor;
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    gi[q] = 0;
-                    gm[q] = 0ull;
-                    gc[q] = cur;
-                    if (any) {
-                        const int i = __ffsll((unsigned long long)any) - 1;
-                        any &= any - 1;
-                        gi[q] = i;
-                        gm[q] = read_lane64(mv, i);
-                        cur += __popcll(gm[q]);
-                    }
+            if (!any) continue;  // uniform
+            // Groups are taken four at a time and software-pipelined: the
+            // next four groups' trace entries are loaded while the current
+            // four are reduced.  Every lane loads (a lane without an entry in
+            // a group reads the wave's first entry and takes alpha = 0 there),
+            // so the count of loads in flight is fixed and the wait for the
+            // current four leaves the next four outstanding.
+            TraceGroups ga, gb;
+            float4 ea[4], eb[4];
+            take_groups(any, mv, cursor, ga);
+            load_groups(went, ga, ea);
+            for (;;) {
+                if (!any) {
+                    bwd_groups<BG>(ga, ea, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                    break;
                 }
-                float4 ent[kG];
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    ent[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (lane_in(gm[q])) ent[q] = went[entry_slot(gm[q], gc[q])];
+                take_groups(any, mv, cursor, gb);
+                load_groups(went, gb, eb);
+                bwd_groups<BG>(ga, ea, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                if (!any) {
+                    bwd_groups<BG>(gb, eb, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                    break;
                 }
-                // the gradients of the kG groups, reduced over the wave
-                // together; every lane computes them, a lane without an entry
-                // in a group holding alpha = 0 there, which makes its nine
-                // values and its change of dL/dC_out exactly zero
-                float v[kG * 9];
-#pragma unroll
-                for (int q = 0; q < kG; ++q) {
-                    const int jj = (int)(c0 - base) + gi[q];
-                    const Splat s = load_splat(L.a, L.b, L.c, jj);
-                    const float dx = s.u - fpx, dy = s.v - fpy;
-                    const float a = ent[q].w;
-                    // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
-                    const float dla = g0 * (s.r - ent[q].x) + g1 * (s.g - ent[q].y) + g2 * (s.b - ent[q].z);
-                    const bool clamped = a >= kAlphaMax;
-                    chain_2d(s, dx, dy, a, a * L.io[jj], clamped, dla, a * g0, a * g1, a * g2, &v[q * 9]);
-                    // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
-                    const float om = 1.f - a;
-                    g0 *= om;
-                    g1 *= om;
-                    g2 *= om;
-                }
-                accumulate_groups<BG, kG>(v, L.acc, lane, c0 - base, gi, gm);
-                cursor = cur;
+                take_groups(any, mv, cursor, ga);
+                load_groups(went, ga, ea);
+                bwd_groups<BG>(gb, eb, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
             }
         }
         __syncthreads();
