@@ -29,9 +29,13 @@ constexpr int kScanThreads = 256;
 constexpr int kScanIpt = 8;
 constexpr int kScanItems = kScanThreads * kScanIpt;  // 2048 per block
 
-constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 16;                       // 256 keys per round
-constexpr int kSortItems = kSortThreads * kSortRounds; // 4096 keys per block
+constexpr int kSortThreads = 256;  // 256 keys per round
+// Rounds per workgroup: 16 (4096 keys) for large sorts; 4 (1024 keys) for
+// sorts of at most kSmallSort keys, which would otherwise run on too few
+// workgroups to fill the chip.
+constexpr int kSortRoundsLarge = 16;
+constexpr int kSortRoundsSmall = 4;
+constexpr uint32_t kSmallSort = 1u << 20;
 constexpr int kRadix = 256;
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -232,9 +236,10 @@ __device__ __forceinline__ uint32_t clamp_count(const uint32_t* num, uint32_t ca
     return c < capacity ? c : capacity;
 }
 
-// Digit histogram of each block's 4096-key chunk, stored digit-major
+// Digit histogram of each block's chunk of 256 R keys, stored digit-major
 // hist[d * nb + block] so that one exclusive scan yields every block's
 // output offset for every digit.
+template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ num,
                                                              uint32_t capacity, int shift, uint32_t nb,
@@ -243,16 +248,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
     const uint32_t count = clamp_count(num, capacity);
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * kSortItems;
+    const uint32_t base = blockIdx.x * kSortThreads * R;
     if (base < count) {
-        uint32_t d[kSortRounds];  // every load in flight before the first atomic
+        uint32_t d[R];  // every load in flight before the first atomic
 #pragma unroll
-        for (int r = 0; r < kSortRounds; ++r) {
+        for (int r = 0; r < R; ++r) {
             const uint32_t idx = base + r * kSortThreads + threadIdx.x;
             d[r] = idx < count ? (uint32_t)(keys[idx] >> shift) & 0xffu : kRadix;
         }
 #pragma unroll
-        for (int r = 0; r < kSortRounds; ++r)
+        for (int r = 0; r < R; ++r)
             if (d[r] < kRadix) atomicAdd(&h[d[r]], 1u);
     }
     __syncthreads();
@@ -268,20 +273,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
 // by matching the 8 digit bits with wave ballots.  The keys go to LDS in
 // that order and leave as one contiguous run per digit, so the global
 // writes coalesce.
+template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ num,
     uint32_t capacity, int shift, uint32_t nb, const uint32_t* __restrict__ offs) {
     constexpr int NW = kSortThreads / 64;
-    __shared__ uint64_t s_key[kSortItems];
-    __shared__ uint32_t s_val[kSortItems];
+    __shared__ uint64_t s_key[kSortThreads * R];
+    __shared__ uint32_t s_val[kSortThreads * R];
     __shared__ uint32_t s_run[kRadix];     // next local position per digit
     __shared__ uint32_t s_lbase[kRadix];   // digit start inside the block
     __shared__ uint32_t s_gbase[kRadix];   // digit start in the output
     __shared__ uint32_t s_wcnt[2][NW][kRadix];  // per-wave digit counts, two rounds in flight
     __shared__ uint32_t s_scan[kSortThreads];
     const uint32_t count = clamp_count(num, capacity);
-    const uint32_t base = blockIdx.x * kSortItems;
+    const uint32_t base = blockIdx.x * kSortThreads * R;
     if (base >= count) return;  // uniform for the block
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const size_t e = (size_t)t * nb + blockIdx.x;
@@ -295,17 +301,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     s_run[t] = lb;
     // All of the block's loads are issued before the first round, so the
     // rounds wait on LDS only.
-    uint64_t kreg[kSortRounds];
-    uint32_t vreg[kSortRounds];
+    uint64_t kreg[R];
+    uint32_t vreg[R];
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
         const uint32_t idx = base + r * kSortThreads + t;
         kreg[r] = idx < count ? kin[idx] : 0ull;
         vreg[r] = idx < count ? vin[idx] : 0u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
         uint32_t (*cnt)[kRadix] = s_wcnt[r & 1];
         const bool valid = base + r * kSortThreads + t < count;
         const uint32_t digit = (uint32_t)(kreg[r] >> shift) & 0xffu;
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         for (int w = 0; w < NW; ++w) add += cnt[w][t];
         s_run[t] += add;
     }
-    const uint32_t here = min((uint32_t)kSortItems, count - base);
+    const uint32_t here = min((uint32_t)kSortThreads * R, count - base);
     for (uint32_t i = t; i < here; i += kSortThreads) {
         const uint64_t key = s_key[i];
         const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
@@ -412,12 +418,14 @@ struct SortWs {
     uint32_t* hist;
     uint32_t* partial;
     uint32_t nb;
+    int rounds;
     size_t bytes;
 };
 
 SortWs sort_layout(void* base, uint32_t capacity) {
     SortWs w{};
-    const uint32_t nb = div_up(capacity, kSortItems);
+    const int rounds = capacity <= kSmallSort ? kSortRoundsSmall : kSortRoundsLarge;
+    const uint32_t nb = div_up(capacity, (uint64_t)kSortThreads * rounds);
     size_t off = 0;
     char* p = static_cast<char*>(base);
     w.keys_alt = reinterpret_cast<uint64_t*>(p + off); off += align_up((size_t)capacity * 8);
@@ -425,6 +433,7 @@ SortWs sort_layout(void* base, uint32_t capacity) {
     w.hist = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)nb * kRadix * 4);
     w.partial = reinterpret_cast<uint32_t*>(p + off); off += scan_workspace(nb * kRadix);
     w.nb = nb;
+    w.rounds = rounds;
     w.bytes = off;
     return w;
 }
@@ -438,11 +447,18 @@ pgs_status radix_sort(uint64_t* keys, uint32_t* vals, const uint32_t* num, uint3
     uint64_t* kout = w.keys_alt; uint32_t* vout = w.vals_alt;
     for (int p = 0; p < passes; ++p) {
         const int shift = start_bit + 8 * p;
-        k_radix_hist<<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
+        if (w.rounds == kSortRoundsSmall)
+            k_radix_hist<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
+        else
+            k_radix_hist<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
         pgs_status st = scan_u32(w.hist, w.hist, w.nb * kRadix, nullptr, w.partial, s);
         if (st != PGS_OK) return st;
-        k_radix_scatter<<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity, shift,
-                                                      w.nb, w.hist);
+        if (w.rounds == kSortRoundsSmall)
+            k_radix_scatter<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
+                                                                            shift, w.nb, w.hist);
+        else
+            k_radix_scatter<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
+                                                                            shift, w.nb, w.hist);
         PGS_CHECK_LAUNCH("radix pass");
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
