@@ -30,10 +30,10 @@ constexpr int kScanIpt = 8;
 constexpr int kScanItems = kScanThreads * kScanIpt;  // 2048 per block
 
 constexpr int kSortThreads = 256;  // 256 keys per round
-// Rounds per workgroup: 16 (4096 keys) for large sorts; 4 (1024 keys) for
+// Rounds per workgroup: 8 (2048 keys) for large sorts; 4 (1024 keys) for
 // sorts of at most kSmallSort keys, which would otherwise run on too few
 // workgroups to fill the chip.
-constexpr int kSortRoundsLarge = 16;
+constexpr int kSortRoundsLarge = 8;
 constexpr int kSortRoundsSmall = 4;
 constexpr uint32_t kSmallSort = 1u << 20;
 constexpr int kRadix = 256;
