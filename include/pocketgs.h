@@ -340,6 +340,36 @@ pgs_status pgs_adam_step(float* params_dev, const float* grads_dev, float* m_dev
                          int32_t step, float beta1, float beta2, float eps, void* stream);
 
 /*
+ * pgs_project_views - pgs_project of every view of a batch in one pass over
+ * the Gaussians (the projection inherited from 3D Gaussian Splatting; the
+ * view-independent part, rotation, scales and 3D covariance, is computed
+ * once per Gaussian and the parameters are read once).  Outputs per view,
+ * identical in layout to pgs_project's with the batch's tile shape:
+ *   proj_all_dev [n_views][n][PGS_PROJ_STRIDE]; radius_all_dev [n_views][n];
+ *   rect_all_dev [n_views][2][n]; touched_all_dev [n_views][n].
+ * Views are taken eight per launch.  Errors: PGS_ERR_INVALID_ARG for a bad batch,
+ * degree or null pointer (nothing is enqueued).
+ */
+pgs_status pgs_project_views(const pgs_view_batch* views, const float* params_dev, int32_t n,
+                             int32_t sh_degree, float* proj_all_dev, int32_t* radius_all_dev,
+                             uint32_t* rect_all_dev, uint32_t* touched_all_dev, void* stream);
+
+/*
+ * pgs_project_bwd_views - pgs_project_bwd of every view of a batch in one
+ * pass: each Gaussian's canonical rows are read once, every view's
+ * contribution is added in float64 and rounded to float32 in view order
+ * (as enqueuing pgs_project_bwd view by view does), and the rows are written
+ * once; views in which the Gaussian was culled add nothing.
+ *   radius_all_dev [n_views][n] and grad2d_all_dev [n_views][n][PGS_GRAD2D_STRIDE]
+ *   (per view, from pgs_project_views and pgs_render_bwd_views);
+ *   grads_dev [F][n] ACCUMULATED (+=).
+ * Views are taken eight per launch.  Errors as pgs_project_views.
+ */
+pgs_status pgs_project_bwd_views(const pgs_view_batch* views, const float* params_dev, int32_t n,
+                                 int32_t sh_degree, const int32_t* radius_all_dev,
+                                 const float* grad2d_all_dev, float* grads_dev, void* stream);
+
+/*
  * pgs_bin_sort_views - pgs_bin_sort over every view of a batch with one key
  * sort: the pairs of view v carry key (tile_offset[v] + local tile) * 2^32 +
  * bits(float32 depth_v) and value = canonical id, emitted view by view in

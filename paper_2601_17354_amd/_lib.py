@@ -73,6 +73,10 @@ SIGNATURES = {
     "pgs_pca_seed": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float,
                                c_void_p, c_void_p]),
     "pgs_views_layout": (c_int32, [POINTER(PgsViewBatch), POINTER(c_int32), POINTER(ctypes.c_int64)]),
+    "pgs_project_views": (c_int32, [POINTER(PgsViewBatch), c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p]),
+    "pgs_project_bwd_views": (c_int32, [POINTER(PgsViewBatch), c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                                        c_void_p, c_void_p]),
     "pgs_bin_sort_views": (c_int32, [POINTER(PgsViewBatch), c_int32, c_void_p, c_void_p, c_void_p, c_uint32,
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                      c_void_p]),

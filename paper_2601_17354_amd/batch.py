@@ -1,11 +1,13 @@
 """Batched multi-view training step, captured as a HIP graph.
 
 Several views of uneven resolution advance one step together:
-projection per view (pgs_project) -> one bin/sort over all views
+projection of every view in one pass over the Gaussians (pgs_project_views)
+-> one bin/sort over all views
 (pgs_bin_sort_views) -> heavy-first order of all tiles (pgs_tile_order) ->
 one persistent compositing launch over every (view, tile) (pgs_render_fwd_views)
 -> loss per view -> one persistent backward launch (pgs_render_bwd_views) ->
-projection backward per view into the canonical gradient -> Adam with the
+projection backward of every view in one pass into the canonical gradient
+(pgs_project_bwd_views) -> Adam with the
 step counter on the device (pgs_adam_step_dev).  Nothing in a step reads
 back to the host, so the whole step can be captured once
 (torch.cuda.CUDAGraph records the library's launches on the capture stream)
@@ -107,9 +109,8 @@ class BatchedStep:
     # -- the step ----------------------------------------------------------
     def forward(self):
         n = self.n
-        for v, cam in enumerate(self.cams):
-            B.pgs_project(self.params, n, self.sh_degree, cam, self.tw, self.th, self.proj[v], self.radius[v],
-                          self.rect[v], self.touched[v])
+        B.pgs_project_views(self.views, self.params, n, self.sh_degree, self.proj, self.radius, self.rect,
+                            self.touched)
         B.pgs_bin_sort_views(self.views, n, self.proj, self.rect, self.touched, self.capacity, self.keys,
                              self.values, self.ranges, self.num_pairs, self.flags, self.workspace)
         if self.order is not None:
@@ -126,8 +127,7 @@ class BatchedStep:
         B.pgs_render_bwd_views(self.views, self.proj, n, self.values, self.ranges, self.bg, self.t_final,
                                self.n_contrib, self.trace if self.cached else None,
                                self.dl if dl is None else dl, self.grad2d, self.order, self.queue)
-        for v, cam in enumerate(self.cams):
-            B.pgs_project_bwd(self.params, n, self.sh_degree, cam, self.radius[v], self.grad2d[v], self.grads)
+        B.pgs_project_bwd_views(self.views, self.params, n, self.sh_degree, self.radius, self.grad2d, self.grads)
 
     def step(self):
         """One full training step over every view (no host synchronisation)."""

@@ -318,6 +318,31 @@ class ViewBatch:
         return len(self.cams)
 
 
+def pgs_project_views(views, params, n, sh_degree, proj_all, radius_all, rect_all, touched_all, stream=None):
+    lib = _lib.load()
+    V = views.n_views
+    _need(params, (11 + 3 * (sh_degree + 1) ** 2) * n, "params")
+    _need(proj_all, V * 16 * n, "proj_all")
+    _need(radius_all, V * n, "radius_all")
+    _need(rect_all, V * 2 * n, "rect_all")
+    _need(touched_all, V * n, "touched_all")
+    check(lib.pgs_project_views(ctypes.byref(views.struct), _ptr(params, F32), n, sh_degree, _ptr(proj_all, F32),
+                                _ptr(radius_all, I32), _ptr(rect_all, I32), _ptr(touched_all, I32),
+                                _stream(stream)), "pgs_project_views")
+
+
+def pgs_project_bwd_views(views, params, n, sh_degree, radius_all, grad2d_all, grads, stream=None):
+    lib = _lib.load()
+    V = views.n_views
+    _need(params, (11 + 3 * (sh_degree + 1) ** 2) * n, "params")
+    _need(radius_all, V * n, "radius_all")
+    _need(grad2d_all, V * 16 * n, "grad2d_all")
+    _need(grads, (11 + 3 * (sh_degree + 1) ** 2) * n, "grads")
+    check(lib.pgs_project_bwd_views(ctypes.byref(views.struct), _ptr(params, F32), n, sh_degree,
+                                    _ptr(radius_all, I32), _ptr(grad2d_all, F32), _ptr(grads, F32),
+                                    _stream(stream)), "pgs_project_bwd_views")
+
+
 def pgs_bin_sort_views(views, n, proj_all, rect_all, touched_all, capacity, keys, values, ranges, num_pairs,
                        flags, workspace, stream=None):
     lib = _lib.load()

@@ -60,56 +60,43 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y)
     }
 }
 
-// Gradient of each polynomial Y[k] with respect to (x, y, z) (any extension
-// off the sphere works: the chain through normalisation removes the radial
-// part).
-template <int D>
-__device__ __forceinline__ void sh_grad(double x, double y, double z, double (*dY)[3]) {
-    dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
-    if (D >= 1) {
-        dY[1][0] = 0.0;   dY[1][1] = -kY1; dY[1][2] = 0.0;
-        dY[2][0] = 0.0;   dY[2][1] = 0.0;  dY[2][2] = kY1;
-        dY[3][0] = -kY1;  dY[3][1] = 0.0;  dY[3][2] = 0.0;
-    }
-    if (D >= 2) {
-        dY[4][0] = kY2a * y;        dY[4][1] = kY2a * x;         dY[4][2] = 0.0;
-        dY[5][0] = 0.0;             dY[5][1] = -kY2a * z;        dY[5][2] = -kY2a * y;
-        dY[6][0] = 0.0;             dY[6][1] = 0.0;              dY[6][2] = 6.0 * kY2b * z;
-        dY[7][0] = -kY2a * z;       dY[7][1] = 0.0;              dY[7][2] = -kY2a * x;
-        dY[8][0] = 2.0 * kY2c * x;  dY[8][1] = -2.0 * kY2c * y;  dY[8][2] = 0.0;
-    }
-    if (D >= 3) {
-        dY[9][0] = -6.0 * kY3a * x * y;
-        dY[9][1] = -3.0 * kY3a * (x * x - y * y);
-        dY[9][2] = 0.0;
-        dY[10][0] = kY3b * y * z;
-        dY[10][1] = kY3b * x * z;
-        dY[10][2] = kY3b * x * y;
-        dY[11][0] = 0.0;
-        dY[11][1] = -kY3c * (5.0 * z * z - 1.0);
-        dY[11][2] = -10.0 * kY3c * y * z;
-        dY[12][0] = 0.0;
-        dY[12][1] = 0.0;
-        dY[12][2] = kY3d * (15.0 * z * z - 3.0);
-        dY[13][0] = -kY3c * (5.0 * z * z - 1.0);
-        dY[13][1] = 0.0;
-        dY[13][2] = -10.0 * kY3c * x * z;
-        dY[14][0] = 2.0 * kY3e * x * z;
-        dY[14][1] = -2.0 * kY3e * y * z;
-        dY[14][2] = kY3e * (x * x - y * y);
-        dY[15][0] = -3.0 * kY3a * (x * x - y * y);
-        dY[15][1] = 6.0 * kY3a * x * y;
-        dY[15][2] = 0.0;
+// Gradient of polynomial Y[k] with respect to (x, y, z) (any extension off
+// the sphere works: the chain through normalisation removes the radial
+// part); k is a constant wherever this is called, so the switch folds away.
+__device__ __forceinline__ void sh_grad_k(int k, double x, double y, double z, double& gx, double& gy,
+                                          double& gz) {
+    switch (k) {
+        case 1: gx = 0.0; gy = -kY1; gz = 0.0; break;
+        case 2: gx = 0.0; gy = 0.0; gz = kY1; break;
+        case 3: gx = -kY1; gy = 0.0; gz = 0.0; break;
+        case 4: gx = kY2a * y; gy = kY2a * x; gz = 0.0; break;
+        case 5: gx = 0.0; gy = -kY2a * z; gz = -kY2a * y; break;
+        case 6: gx = 0.0; gy = 0.0; gz = 6.0 * kY2b * z; break;
+        case 7: gx = -kY2a * z; gy = 0.0; gz = -kY2a * x; break;
+        case 8: gx = 2.0 * kY2c * x; gy = -2.0 * kY2c * y; gz = 0.0; break;
+        case 9: gx = -6.0 * kY3a * x * y; gy = -3.0 * kY3a * (x * x - y * y); gz = 0.0; break;
+        case 10: gx = kY3b * y * z; gy = kY3b * x * z; gz = kY3b * x * y; break;
+        case 11: gx = 0.0; gy = -kY3c * (5.0 * z * z - 1.0); gz = -10.0 * kY3c * y * z; break;
+        case 12: gx = 0.0; gy = 0.0; gz = kY3d * (15.0 * z * z - 3.0); break;
+        case 13: gx = -kY3c * (5.0 * z * z - 1.0); gy = 0.0; gz = -10.0 * kY3c * x * z; break;
+        case 14: gx = 2.0 * kY3e * x * z; gy = -2.0 * kY3e * y * z; gz = kY3e * (x * x - y * y); break;
+        case 15: gx = -3.0 * kY3a * (x * x - y * y); gy = 6.0 * kY3a * x * y; gz = 0.0; break;
+        default: gx = gy = gz = 0.0; break;
     }
 }
 
-// Geometry shared by the forward and the backward kernels.
-struct Geo {
-    double x, y, z;          // camera-space mean
+// Geometry shared by the forward and the backward kernels: the part that
+// does not depend on the view (rotation, scales, 3D covariance) and the
+// per-view part (camera-space mean, Jacobian, 2D covariance).
+struct Shape {
     double qn[4], qlen;      // normalised quaternion and |q|
     double R[9];             // rotation of the Gaussian
     double s[3];             // exp(log-scale)
     double Sig[6];           // 3D covariance xx, xy, xz, yy, yz, zz
+};
+
+struct Geo {
+    double x, y, z;          // camera-space mean
     double tx, ty;           // clamped x/z, y/z
     bool clx, cly;           // J clamp active
     double T0[3], T1[3];     // rows of J W
@@ -120,29 +107,30 @@ __device__ __forceinline__ double prow(const float* P, int r, int n, int i) {
     return (double)P[(size_t)r * n + i];
 }
 
-__device__ __forceinline__ void geometry(const float* __restrict__ P, int n, int i,
-                                         const CamD& cam, Geo& G) {
+__device__ __forceinline__ void shape_of(const float* __restrict__ P, int n, int i, Shape& S3) {
+    const double qw = prow(P, 6, n, i), qx = prow(P, 7, n, i), qy = prow(P, 8, n, i),
+                 qz = prow(P, 9, n, i);
+    S3.qlen = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw / S3.qlen, x = qx / S3.qlen, y = qy / S3.qlen, z = qz / S3.qlen;
+    S3.qn[0] = w; S3.qn[1] = x; S3.qn[2] = y; S3.qn[3] = z;
+    double* R = S3.R;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+    for (int k = 0; k < 3; ++k) S3.s[k] = exp(prow(P, 3 + k, n, i));
+    // Sigma = R diag(s^2) R^T
+    const double s0 = S3.s[0] * S3.s[0], s1 = S3.s[1] * S3.s[1], s2 = S3.s[2] * S3.s[2];
+    auto sig = [&](int r, int c) { return R[3 * r] * R[3 * c] * s0 + R[3 * r + 1] * R[3 * c + 1] * s1 + R[3 * r + 2] * R[3 * c + 2] * s2; };
+    S3.Sig[0] = sig(0, 0); S3.Sig[1] = sig(0, 1); S3.Sig[2] = sig(0, 2);
+    S3.Sig[3] = sig(1, 1); S3.Sig[4] = sig(1, 2); S3.Sig[5] = sig(2, 2);
+}
+
+__device__ __forceinline__ void view_geometry(const float* __restrict__ P, int n, int i, const Shape& S3,
+                                              const CamD& cam, Geo& G) {
     const double mx = prow(P, 0, n, i), my = prow(P, 1, n, i), mz = prow(P, 2, n, i);
     G.x = cam.R[0] * mx + cam.R[1] * my + cam.R[2] * mz + cam.t[0];
     G.y = cam.R[3] * mx + cam.R[4] * my + cam.R[5] * mz + cam.t[1];
     G.z = cam.R[6] * mx + cam.R[7] * my + cam.R[8] * mz + cam.t[2];
-
-    const double qw = prow(P, 6, n, i), qx = prow(P, 7, n, i), qy = prow(P, 8, n, i),
-                 qz = prow(P, 9, n, i);
-    G.qlen = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    const double w = qw / G.qlen, x = qx / G.qlen, y = qy / G.qlen, z = qz / G.qlen;
-    G.qn[0] = w; G.qn[1] = x; G.qn[2] = y; G.qn[3] = z;
-    double* R = G.R;
-    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
-    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
-    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
-    for (int k = 0; k < 3; ++k) G.s[k] = exp(prow(P, 3 + k, n, i));
-    // Sigma = R diag(s^2) R^T
-    const double s0 = G.s[0] * G.s[0], s1 = G.s[1] * G.s[1], s2 = G.s[2] * G.s[2];
-    auto sig = [&](int r, int c) { return R[3 * r] * R[3 * c] * s0 + R[3 * r + 1] * R[3 * c + 1] * s1 + R[3 * r + 2] * R[3 * c + 2] * s2; };
-    G.Sig[0] = sig(0, 0); G.Sig[1] = sig(0, 1); G.Sig[2] = sig(0, 2);
-    G.Sig[3] = sig(1, 1); G.Sig[4] = sig(1, 2); G.Sig[5] = sig(2, 2);
-
     const double xz = G.x / G.z, yz = G.y / G.z;
     G.clx = (xz < -cam.lim_x) || (xz > cam.lim_x);
     G.cly = (yz < -cam.lim_y) || (yz > cam.lim_y);
@@ -154,7 +142,7 @@ __device__ __forceinline__ void geometry(const float* __restrict__ P, int n, int
         G.T0[k] = j00 * cam.R[k] + j02 * cam.R[6 + k];
         G.T1[k] = j11 * cam.R[3 + k] + j12 * cam.R[6 + k];
     }
-    const double* S = G.Sig;
+    const double* S = S3.Sig;
     const double U0 = S[0] * G.T0[0] + S[1] * G.T0[1] + S[2] * G.T0[2];
     const double U1 = S[1] * G.T0[0] + S[3] * G.T0[1] + S[4] * G.T0[2];
     const double U2 = S[2] * G.T0[0] + S[4] * G.T0[1] + S[5] * G.T0[2];
@@ -195,17 +183,16 @@ __device__ void alpha_extent(float A, float B, float C, float o, float& hx, floa
     hy = (float)(sqrt(t * a / det) * (1.0 + 1e-5) + 1e-2);
 }
 
+// Projection of Gaussian i into one view (record, radius, rectangle and
+// tile count at index i of that view's arrays).
 template <int D>
-__global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, int n, CamD cam,
-                                                 int tw, int th, int TX, int TY,
-                                                 float* __restrict__ out, int* __restrict__ radius,
-                                                 uint32_t* __restrict__ rect,
-                                                 uint32_t* __restrict__ touched) {
+__device__ __forceinline__ void project_view(const float* __restrict__ P, int n, int i, const Shape& S3,
+                                             const CamD& cam, int tw, int th, int TX, int TY,
+                                             float* __restrict__ out, int* __restrict__ radius,
+                                             uint32_t* __restrict__ rect, uint32_t* __restrict__ touched) {
     constexpr int K = (D + 1) * (D + 1);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     Geo G;
-    geometry(P, n, i, cam, G);
+    view_geometry(P, n, i, S3, cam, G);
     bool ok = G.z > 0.2 && G.det > 0.0;
     double u = 0, v = 0, r = 0, x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     if (ok) {
@@ -268,23 +255,62 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, in
     touched[i] = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ P, int n, CamD cam,
+                                                 int tw, int th, int TX, int TY,
+                                                 float* __restrict__ out, int* __restrict__ radius,
+                                                 uint32_t* __restrict__ rect,
+                                                 uint32_t* __restrict__ touched) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Shape S3;
+    shape_of(P, n, i, S3);
+    project_view<D>(P, n, i, S3, cam, tw, th, TX, TY, out, radius, rect, touched);
+}
+
+// Up to kLaunchViews views per multi-view launch, cameras by value.
+constexpr int kLaunchViews = 8;
+struct LaunchViews {
+    int nv, v0;  // views in this launch, index of the first
+    CamD cam[kLaunchViews];
+    int TX[kLaunchViews], TY[kLaunchViews];
+};
+
+// Every view of a launch for one Gaussian: the view-independent shape once,
+// the parameters read once from HBM (the views re-read them from cache).
+template <int D>
+__global__ __launch_bounds__(256) void k_project_views(const float* __restrict__ P, int n, LaunchViews lv,
+                                                       int tw, int th, float* __restrict__ out_all,
+                                                       int* __restrict__ radius_all,
+                                                       uint32_t* __restrict__ rect_all,
+                                                       uint32_t* __restrict__ touched_all) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Shape S3;
+    shape_of(P, n, i, S3);
+    for (int k = 0; k < lv.nv; ++k) {
+        const size_t v = (size_t)(lv.v0 + k);
+        project_view<D>(P, n, i, S3, lv.cam[k], tw, th, lv.TX[k], lv.TY[k], out_all + v * n * PGS_PROJ_STRIDE,
+                        radius_all + v * n, rect_all + 2 * v * n, touched_all + v * n);
+    }
+}
+
 // Backward: exact derivative of k_project's outputs (u, v, A, B, C, o, rgb)
 // with every discrete decision frozen, accumulated into the canonical
 // gradient rows.
-template <int D>
-__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P, int n, CamD cam,
-                                                     const int* __restrict__ radius,
-                                                     const float* __restrict__ g2d,
-                                                     float* __restrict__ grads) {
+// The gradient contributions of one view to Gaussian i's canonical rows,
+// handed to acc(row, value) (float64).
+template <int D, class Acc>
+__device__ __forceinline__ void project_bwd_view(const float* __restrict__ P, int n, int i, const Shape& S3,
+                                                 const CamD& cam, const float* __restrict__ g2d_row, Acc&& acc) {
     constexpr int K = (D + 1) * (D + 1);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || radius[i] == 0) return;
-    auto gin = [&](int f) { return (double)g2d[(size_t)i * PGS_GRAD2D_STRIDE + f]; };
+    auto gin = [&](int f) { return (double)g2d_row[f]; };
     const double gu = gin(0), gv = gin(1), gA = gin(2), gB = gin(3), gC = gin(4), go = gin(5);
     const double gcol[3] = {gin(6), gin(7), gin(8)};
 
+    double gmu[3], glog[3], gqraw[4];
     Geo G;
-    geometry(P, n, i, cam, G);
+    view_geometry(P, n, i, S3, cam, G);
     const double a = G.a, b = G.b, c = G.c, det2 = G.det * G.det;
     // conic (A, B, C) = (c, -b, a) / det  ->  Sigma2D entries
     const double ga = (-c * c * gA + b * c * gB - b * b * gC) / det2;
@@ -292,7 +318,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P
     const double gc = (-b * b * gA + a * b * gB - a * a * gC) / det2;
     // symmetric 2x2 gradient of Sigma2D
     const double G00 = ga, G01 = 0.5 * gb, G11 = gc;
-    const double* S = G.Sig;
+    const double* S = S3.Sig;
     double Sm[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
     // dL/dSigma = T^T G2 T (3x3 symmetric)
     double GS[3][3];
@@ -335,26 +361,25 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P
     gy += gv * cam.fy / z;
     gz += -gu * cam.fx * G.x / z2 - gv * cam.fy * G.y / z2;
     // x_c = W mu + t
-    double gmu[3];
     for (int k = 0; k < 3; ++k) gmu[k] = W[k] * gx + W[3 + k] * gy + W[6 + k] * gz;
 
     // Sigma = M M^T, M = R diag(s): dL/dM = 2 dL/dSigma M
     double M[3][3], gM[3][3];
     for (int r = 0; r < 3; ++r)
-        for (int q = 0; q < 3; ++q) M[r][q] = G.R[3 * r + q] * G.s[q];
+        for (int q = 0; q < 3; ++q) M[r][q] = S3.R[3 * r + q] * S3.s[q];
     for (int r = 0; r < 3; ++r)
         for (int q = 0; q < 3; ++q)
             gM[r][q] = 2.0 * (GS[r][0] * M[0][q] + GS[r][1] * M[1][q] + GS[r][2] * M[2][q]);
-    double glog[3], gR[9];
+    double gR[9];
     for (int q = 0; q < 3; ++q) {
-        double acc = 0.0;
+        double a_ = 0.0;
         for (int r = 0; r < 3; ++r) {
-            acc += gM[r][q] * G.R[3 * r + q];
-            gR[3 * r + q] = gM[r][q] * G.s[q];
+            a_ += gM[r][q] * S3.R[3 * r + q];
+            gR[3 * r + q] = gM[r][q] * S3.s[q];
         }
-        glog[q] = acc * G.s[q];
+        glog[q] = a_ * S3.s[q];
     }
-    const double w = G.qn[0], x = G.qn[1], y = G.qn[2], zq = G.qn[3];
+    const double w = S3.qn[0], x = S3.qn[1], y = S3.qn[2], zq = S3.qn[3];
     double gq[4];
     gq[0] = 2.0 * (-zq * gR[1] + y * gR[2] + zq * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
     gq[1] = 2.0 * (y * gR[1] + zq * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] +
@@ -364,9 +389,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P
     gq[3] = 2.0 * (-2.0 * zq * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * zq * gR[4] +
                    y * gR[5] + x * gR[6] + y * gR[7]);
     const double dotq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * zq;
-    double gqraw[4];
-    for (int k = 0; k < 4; ++k) gqraw[k] = (gq[k] - G.qn[k] * dotq) / G.qlen;
-
+    for (int k = 0; k < 4; ++k) gqraw[k] = (gq[k] - S3.qn[k] * dotq) / S3.qlen;
     // colour: c = max(0, sum_k Y_k(d) f_k + 1/2), d = unit(mu - campos)
     double d0 = prow(P, 0, n, i) - cam.campos[0];
     double d1 = prow(P, 1, n, i) - cam.campos[1];
@@ -377,24 +400,26 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P
     sh_eval<D>(d0, d1, d2, Y);
     double graw[3];
     for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.5;
-        for (int k = 0; k < K; ++k) acc += Y[k] * prow(P, 11 + 3 * k + ch, n, i);
-        graw[ch] = acc >= 0.0 ? gcol[ch] : 0.0;
+        double c_ = 0.5;
+        for (int k = 0; k < K; ++k) c_ += Y[k] * prow(P, 11 + 3 * k + ch, n, i);
+        graw[ch] = c_ >= 0.0 ? gcol[ch] : 0.0;
     }
+#pragma unroll
     for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) {
-            float* dst = &grads[(size_t)(11 + 3 * k + ch) * n + i];
-            *dst = (float)((double)*dst + Y[k] * graw[ch]);
-        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) acc(11 + 3 * k + ch, Y[k] * graw[ch]);
     if (D >= 1) {
-        double dY[K][3];
-        sh_grad<D>(d0, d1, d2, dY);
         double gd[3] = {0, 0, 0};
+#pragma unroll
         for (int k = 1; k < K; ++k) {
             const double gy_k = prow(P, 11 + 3 * k, n, i) * graw[0] +
                                 prow(P, 12 + 3 * k, n, i) * graw[1] +
                                 prow(P, 13 + 3 * k, n, i) * graw[2];
-            for (int q = 0; q < 3; ++q) gd[q] += gy_k * dY[k][q];
+            double dx, dy, dz;
+            sh_grad_k(k, d0, d1, d2, dx, dy, dz);
+            gd[0] += gy_k * dx;
+            gd[1] += gy_k * dy;
+            gd[2] += gy_k * dz;
         }
         const double dd = gd[0] * d0 + gd[1] * d1 + gd[2] * d2;
         gmu[0] += (gd[0] - d0 * dd) / dl;
@@ -402,14 +427,58 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P
         gmu[2] += (gd[2] - d2 * dd) / dl;
     }
     const double o = 1.0 / (1.0 + exp(-prow(P, 10, n, i)));
-    auto acc_row = [&](int r, double g) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc(k, gmu[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc(3 + k, glog[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc(6 + k, gqraw[k]);
+    acc(10, go * o * (1.0 - o));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ P, int n, CamD cam,
+                                                     const int* __restrict__ radius,
+                                                     const float* __restrict__ g2d,
+                                                     float* __restrict__ grads) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || radius[i] == 0) return;
+    Shape S3;
+    shape_of(P, n, i, S3);
+    project_bwd_view<D>(P, n, i, S3, cam, g2d + (size_t)i * PGS_GRAD2D_STRIDE, [&](int r, double g) {
         float* dst = &grads[(size_t)r * n + i];
         *dst = (float)((double)*dst + g);
-    };
-    for (int k = 0; k < 3; ++k) acc_row(k, gmu[k]);
-    for (int k = 0; k < 3; ++k) acc_row(3 + k, glog[k]);
-    for (int k = 0; k < 4; ++k) acc_row(6 + k, gqraw[k]);
-    acc_row(10, go * o * (1.0 - o));
+    });
+}
+
+// Every view of a launch for one Gaussian, its canonical rows accumulated
+// in registers: each view adds in float64 and rounds to float32, in view
+// order, as launching the one-view kernel per view would; the rows are read
+// and written once.
+template <int D>
+__global__ __launch_bounds__(256) void k_project_bwd_views(const float* __restrict__ P, int n, LaunchViews lv,
+                                                           const int* __restrict__ radius_all,
+                                                           const float* __restrict__ g2d_all,
+                                                           float* __restrict__ grads) {
+    constexpr int F = 11 + 3 * (D + 1) * (D + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool any = false;
+    for (int k = 0; k < lv.nv; ++k) any |= radius_all[(size_t)(lv.v0 + k) * n + i] != 0;
+    if (!any) return;
+    float acc[F];
+#pragma unroll
+    for (int r = 0; r < F; ++r) acc[r] = grads[(size_t)r * n + i];
+    Shape S3;
+    shape_of(P, n, i, S3);
+    for (int k = 0; k < lv.nv; ++k) {
+        const size_t v = (size_t)(lv.v0 + k);
+        if (radius_all[v * n + i] == 0) continue;
+        project_bwd_view<D>(P, n, i, S3, lv.cam[k], g2d_all + (v * n + i) * PGS_GRAD2D_STRIDE,
+                            [&](int r, double g) { acc[r] = (float)((double)acc[r] + g); });
+    }
+#pragma unroll
+    for (int r = 0; r < F; ++r) grads[(size_t)r * n + i] = acc[r];
 }
 
 }  // namespace
@@ -460,5 +529,71 @@ extern "C" pgs_status pgs_project_bwd(const float* params_dev, int32_t n, int32_
         default: k_project_bwd<3><<<grid, block, 0, s>>>(params_dev, n, cam, radius_dev, grad2d_dev, grads_dev); break;
     }
     PGS_CHECK_LAUNCH("pgs_project_bwd");
+    return PGS_OK;
+}
+
+namespace {
+
+// Cameras of views [v0, v0 + nv) of a batch, for one multi-view launch.
+LaunchViews launch_views(const pgs_view_batch& vb, int v0, int nv) {
+    LaunchViews lv{};
+    lv.nv = nv;
+    lv.v0 = v0;
+    for (int k = 0; k < nv; ++k) {
+        const pgs_camera& c = vb.cams[v0 + k];
+        lv.cam[k] = pgs::make_cam(c);
+        lv.TX[k] = (c.width + vb.tile_w - 1) / vb.tile_w;
+        lv.TY[k] = (c.height + vb.tile_h - 1) / vb.tile_h;
+    }
+    return lv;
+}
+
+}  // namespace
+
+extern "C" pgs_status pgs_project_views(const pgs_view_batch* views, const float* params_dev, int32_t n,
+                                        int32_t sh_degree, float* proj_all_dev, int32_t* radius_all_dev,
+                                        uint32_t* rect_all_dev, uint32_t* touched_all_dev, void* stream) {
+    if (pgs_status st = pgs::check_views(views, "pgs_project_views")) return st;
+    PGS_REQUIRE(n >= 0, "pgs_project_views: n < 0");
+    PGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "pgs_project_views: sh_degree %d", sh_degree);
+    if (n == 0) return PGS_OK;
+    PGS_REQUIRE(params_dev && proj_all_dev && radius_all_dev && rect_all_dev && touched_all_dev,
+                "pgs_project_views: null pointer");
+    const dim3 grid((n + 255) / 256), block(256);
+    hipStream_t s = pgs::as_stream(stream);
+    const int tw = views->tile_w, th = views->tile_h;
+    for (int v0 = 0; v0 < views->n_views; v0 += kLaunchViews) {
+        const LaunchViews lv = launch_views(*views, v0, min(kLaunchViews, views->n_views - v0));
+        switch (sh_degree) {
+            case 0: k_project_views<0><<<grid, block, 0, s>>>(params_dev, n, lv, tw, th, proj_all_dev, radius_all_dev, rect_all_dev, touched_all_dev); break;
+            case 1: k_project_views<1><<<grid, block, 0, s>>>(params_dev, n, lv, tw, th, proj_all_dev, radius_all_dev, rect_all_dev, touched_all_dev); break;
+            case 2: k_project_views<2><<<grid, block, 0, s>>>(params_dev, n, lv, tw, th, proj_all_dev, radius_all_dev, rect_all_dev, touched_all_dev); break;
+            default: k_project_views<3><<<grid, block, 0, s>>>(params_dev, n, lv, tw, th, proj_all_dev, radius_all_dev, rect_all_dev, touched_all_dev); break;
+        }
+    }
+    PGS_CHECK_LAUNCH("pgs_project_views");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_project_bwd_views(const pgs_view_batch* views, const float* params_dev, int32_t n,
+                                            int32_t sh_degree, const int32_t* radius_all_dev,
+                                            const float* grad2d_all_dev, float* grads_dev, void* stream) {
+    if (pgs_status st = pgs::check_views(views, "pgs_project_bwd_views")) return st;
+    PGS_REQUIRE(n >= 0, "pgs_project_bwd_views: n < 0");
+    PGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "pgs_project_bwd_views: sh_degree %d", sh_degree);
+    if (n == 0) return PGS_OK;
+    PGS_REQUIRE(params_dev && radius_all_dev && grad2d_all_dev && grads_dev, "pgs_project_bwd_views: null pointer");
+    const dim3 grid((n + 255) / 256), block(256);
+    hipStream_t s = pgs::as_stream(stream);
+    for (int v0 = 0; v0 < views->n_views; v0 += kLaunchViews) {
+        const LaunchViews lv = launch_views(*views, v0, min(kLaunchViews, views->n_views - v0));
+        switch (sh_degree) {
+            case 0: k_project_bwd_views<0><<<grid, block, 0, s>>>(params_dev, n, lv, radius_all_dev, grad2d_all_dev, grads_dev); break;
+            case 1: k_project_bwd_views<1><<<grid, block, 0, s>>>(params_dev, n, lv, radius_all_dev, grad2d_all_dev, grads_dev); break;
+            case 2: k_project_bwd_views<2><<<grid, block, 0, s>>>(params_dev, n, lv, radius_all_dev, grad2d_all_dev, grads_dev); break;
+            default: k_project_bwd_views<3><<<grid, block, 0, s>>>(params_dev, n, lv, radius_all_dev, grad2d_all_dev, grads_dev); break;
+        }
+    }
+    PGS_CHECK_LAUNCH("pgs_project_bwd_views");
     return PGS_OK;
 }

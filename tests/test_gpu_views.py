@@ -112,6 +112,52 @@ def test_views_match_oracle_per_view(tile, batch, cached):
         assert_block_close(g[row], grads_want[row], GRAD_TOL, mask=~taint_any, what=f"canonical row {row}")
 
 
+@pytest.mark.parametrize("deg", [0, 3])
+def test_project_views_match_per_view_calls(deg):
+    # The multi-view projection and its backward run the per-view code once
+    # per view in view order, so they reproduce pgs_project / pgs_project_bwd
+    # enqueued view by view bit for bit (ten views: two launches of at most
+    # eight).
+    from paper_2601_17354_amd import binding as B
+    scene = synth.spheres_planes_scene(2)
+    P = synth.surface_gaussians(scene, 5003, seed=31, sh_degree=deg, logit_sigma=0.5)
+    sizes = [(320, 240), (256, 192), (160, 120), (200, 150), (96, 64)]
+    ring = synth.ring_cameras(10, 320, 240)
+    cams = []
+    for i in range(10):
+        W, H = sizes[i % len(sizes)]
+        c = dict(ring[i])
+        c.update(width=W, height=H, cx=W / 2.0, cy=H / 2.0)
+        cams.append(c)
+    n, V, F = P.shape[1], len(cams), P.shape[0]
+    say(f"[views] project_views: n={n} views={V} sh={deg}")
+    views = B.ViewBatch(cams, (16, 16))
+    params = torch.as_tensor(P, device=DEV)
+    proj = torch.zeros((V, n, 16), device=DEV)
+    radius = torch.zeros((V, n), dtype=torch.int32, device=DEV)
+    rect = torch.zeros((V, 2, n), dtype=torch.int32, device=DEV)
+    touched = torch.zeros((V, n), dtype=torch.int32, device=DEV)
+    proj1, radius1, rect1, touched1 = (torch.zeros_like(t) for t in (proj, radius, rect, touched))
+    B.pgs_project_views(views, params, n, deg, proj, radius, rect, touched)
+    for v, cam in enumerate(cams):
+        B.pgs_project(params, n, deg, cam, 16, 16, proj1[v], radius1[v], rect1[v], touched1[v])
+    torch.cuda.synchronize()
+    for a, b in ((proj, proj1), (radius, radius1), (rect, rect1), (touched, touched1)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    vis = (radius > 0).sum().item()
+    assert 0 < vis < V * n   # some culled, some visible
+    rng = np.random.default_rng(deg + 40)
+    g2d = torch.as_tensor(rng.normal(size=(V, n, 16)).astype(np.float32), device=DEV)
+    g0 = rng.normal(size=(F, n)).astype(np.float32)
+    grads = torch.as_tensor(g0, device=DEV)
+    grads1 = torch.as_tensor(g0, device=DEV)
+    B.pgs_project_bwd_views(views, params, n, deg, radius, g2d, grads)
+    for v, cam in enumerate(cams):
+        B.pgs_project_bwd(params, n, deg, cam, radius[v], g2d[v], grads1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(grads.cpu().numpy(), grads1.cpu().numpy())
+
+
 def test_adam_step_dev_matches_host_counter():
     from paper_2601_17354_amd import binding as B
     rng = np.random.default_rng(12)
