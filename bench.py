@@ -44,12 +44,14 @@ def parse():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched multi-view step, untuned 16x16 tiles / batch 256, 6 replays "
                          "(for rocprofv3)")
+    ap.add_argument("--no-cfg2", action="store_true",
+                    help="skip the 100k / SH 3 / 1024x768 cached-vs-recompute comparison")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 4 views, 4 steps, one 1 GiB stream copy")
     args = ap.parse_args()
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
-        args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = True
+        args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = args.no_cfg2 = True
     return args
 
 
@@ -114,6 +116,79 @@ def run_variant(wl, cached, steps, warmup, order):
                  loss=float(tr.loss.item()))
     pct = {f"p{q}": float(np.percentile(per_step, q)) for q in (10, 50, 90)}
     return dict(ms=ms, wall_s=wall, kernels=per, stats=stats, trainer=tr, pct=pct)
+
+
+def trace_clear_ablation(tr, reps=5):
+    """The replay-cache ablation: clearing the whole trace (entries and
+    masks) before each iteration against the counter reset this design uses
+    (the bump counter; the step counters and per-pixel counts are rewritten
+    by every forward)."""
+    import torch
+    trace = tr.rast.trace
+    full = [trace["entry"], trace["mask"]]
+    nbytes = sum(t.numel() * t.element_size() for t in full)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_full = timed(lambda: [t.zero_() for t in full])
+    ms_reset = timed(lambda: trace["used"].zero_())
+    return {"full_clear_ms": ms_full, "full_clear_bytes": nbytes, "counter_reset_ms": ms_reset,
+            "counter_reset_bytes": trace["used"].numel() * trace["used"].element_size()}
+
+
+def cfg2_runs(steps=50, warmup=5):
+    """100k Gaussians with SH degree 3 on the scene (logit ~ N(0, 0.5^2),
+    higher SH ~ N(0, 0.05^2)), ring camera 0 at 1024x768, L1 to the
+    ground-truth render of that view; the cached and the recompute backward
+    compared on step time, trace size and peak device memory."""
+    import torch
+    import synth
+    from paper_2601_17354_amd.train import Trainer
+    from paper_2601_17354_amd.workloads import render_targets
+    W, H = 1024, 768
+    scene = synth.spheres_planes_scene(0)
+    cam = synth.ring_cameras(60, W, H)[0]
+    gt = torch.as_tensor(synth.surface_gaussians(scene, 500_000, seed=1000, sh_degree=0, opacity=0.95),
+                         device="cuda")
+    target = render_targets(gt, 0, [cam], W, H)[0]
+    del gt
+    P = torch.as_tensor(synth.surface_gaussians(scene, 100_000, seed=300, sh_degree=3, logit_sigma=0.5),
+                        device="cuda")
+    out = {"workload": "100k Gaussians, SH 3, one 1024x768 view, L1 to the ground-truth render"}
+    for cached in (True, False):
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        tr = Trainer(P.clone(), 3, W, H, cached=cached, lam=0.0, extent=4.5)
+        tr.prepare(cam)
+        tr.rast.reserve(1.5)
+        for _ in range(warmup):
+            tr.step(cam, target)
+        torch.cuda.synchronize()
+        tr.rast.flags.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            tr.step(cam, target)
+        b.record()
+        torch.cuda.synchronize()
+        if tr.rast.read_flags():
+            raise RuntimeError("config-2 run overflowed its buffers")
+        out["cached" if cached else "recompute"] = {
+            "ms_per_step": a.elapsed_time(b) / steps, "trace_gb": tr.rast.trace_bytes() / 1e9,
+            "peak_device_gb": torch.cuda.max_memory_allocated() / 1e9,
+            "pairs": int(tr.rast.num_pairs.item()),
+            "entries": int(tr.rast.trace["count"].sum().item()) if cached else 0}
+        del tr
+    return out
 
 
 def render_fps(wl, params, order, frames=50):
@@ -415,6 +490,9 @@ def main():
     log(f"{args.backward}: {res['ms']:.3f} ms/step, kernels {res['kernels']}, stats {res['stats']}")
     fps = render_fps(wl, res["trainer"].params, order)
     log(f"render-only: {fps:.1f} frames/s")
+    ablation = trace_clear_ablation(res["trainer"]) if cached else None
+    if ablation:
+        log(f"trace clear vs counter reset: {ablation}")
     other = None
     if not args.no_compare:
         del res["trainer"]
@@ -460,6 +538,8 @@ def main():
         "work": st,
     }
     out["render_only_fps"] = fps
+    if ablation:
+        out["ablation_trace_clear"] = ablation
     if other is not None:
         out["other_backward"] = {"backward": "recompute" if cached else "cached",
                                  "ms_per_step": other["ms"], "iters_per_s": 1000.0 / other["ms"],
@@ -481,6 +561,10 @@ def main():
         b = out["batched_views"]
         log(f"batched: {b['ms_per_step_graph']:.2f} ms/step graph, {b['ms_per_step_eager']:.2f} eager, "
             f"{b['ms_per_step_one_view_at_a_time']:.2f} one view at a time")
+    if not args.no_cfg2:
+        log("config 2: 100k Gaussians, SH 3, 1024x768, cached vs recompute backward")
+        out["cfg2_backward_variants"] = cfg2_runs()
+        log(f"config 2: {out['cfg2_backward_variants']}")
     log("seeding network alone")
     out["seed_network"] = mlp_runs()
     log(f"seed network: {out['seed_network']}")

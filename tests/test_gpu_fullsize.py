@@ -1,5 +1,7 @@
-"""GPU parity at the benchmark's size: 300k Gaussians, one 1920x1440 view,
-16x16 tiles, the launch configuration the training step uses.
+"""GPU parity at full size, in the launch configuration of the training step
+(16x16 tiles): the benchmark workload (300k Gaussians, SH degree 0, one
+1920x1440 view) and the SH degree 3 configuration (100k Gaussians, one
+1024x768 view).
 
 The oracle cannot composite every pixel of that view in a test, so:
   * projection, binning and the (tile, depth) sort are compared in full
@@ -11,7 +13,7 @@ The oracle cannot composite every pixel of that view in a test, so:
     tiles, so the oracle's gradients over the sampled tiles are the exact
     gradients of every Gaussian and are compared for all of them.
 Inputs: flat Gaussians on the seeded spheres-and-planes scene (the shapes and
-size mix of the training workload), camera 7 of the 60-view ring.
+size mix of the training workload); ring cameras 7 and 0.
 """
 
 import numpy as np
@@ -25,15 +27,21 @@ from oracle.render import render_backward, render_forward, replay_entries
 
 pytestmark = pytest.mark.gpu
 
-N, W, H, TILE = 300_000, 1920, 1440, 16
+TILE = 16
+# name: (Gaussians, SH degree, width, height, ring camera, generator keywords)
+CONFIGS = {
+    "300k-sh0-1920x1440": (300_000, 0, 1920, 1440, 7, dict(size=1.2)),
+    "100k-sh3-1024x768": (100_000, 3, 1024, 768, 0, dict(logit_sigma=0.5)),
+}
 
 
-@pytest.fixture(scope="module")
-def full():
+@pytest.fixture(scope="module", params=list(CONFIGS))
+def full(request):
+    N, deg, W, H, ci, kw = CONFIGS[request.param]
     scene = synth.spheres_planes_scene(0)
-    P = synth.surface_gaussians(scene, N, seed=77, sh_degree=0, size=1.2)
-    cam = synth.ring_cameras(60, W, H)[7]
-    say(f"[fullsize] n={N} {W}x{H}: oracle projection and sort")
+    P = synth.surface_gaussians(scene, N, seed=77, sh_degree=deg, **kw)
+    cam = synth.ring_cameras(60, W, H)[ci]
+    say(f"[fullsize] {request.param}: oracle projection and sort")
     proj = project(P, cam)
     bins = bin_and_sort(proj)
     r = bins["ranges"]
@@ -53,8 +61,8 @@ def full():
     g2d, tainted = render_backward(proj, bins, fwd, dl, "cached")
     grads = project_vjp(P, cam, g2d, proj["visible"])
     say("[fullsize] HIP path, cached and recompute")
-    gc = run_gpu(P, cam, 0, cached=True, dl_dimage=dl)
-    gr = run_gpu(P, cam, 0, cached=False, dl_dimage=dl)
+    gc = run_gpu(P, cam, deg, cached=True, dl_dimage=dl)
+    gr = run_gpu(P, cam, deg, cached=False, dl_dimage=dl)
     return dict(P=P, cam=cam, proj=proj, bins=bins, tiles=tiles, on=on, fwd=fwd, g2d=g2d, tainted=tainted,
                 grads=grads, gc=gc, gr=gr)
 
