@@ -1,9 +1,12 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
 
 This module holds only input generation: Gaussian parameter sets, cameras,
-surface point clouds and target images.  It holds none of the splatting
-arithmetic (no projection, binning, compositing, gradients or seeding); both
-the oracle and the HIP path consume what it produces.
+surface point clouds, target images and bundle-adjustment tracks.  It holds
+none of the splatting arithmetic (no projection, binning, compositing,
+gradients or seeding) and none of the bundle adjustment's (the tracks'
+measurements come from a pinhole projection written in the generator for
+that purpose alone); both the oracle and the HIP path consume what it
+produces.
 
 Canonical parameter layout (one float32 row per scalar field, N columns):
 
@@ -38,4 +41,5 @@ from .gen import (  # noqa: F401
     noisy_cloud,
     random_image,
     random_normal,
+    ba_tracks,
 )

@@ -279,3 +279,83 @@ def noisy_cloud(scene: Scene, n: int, seed: int, noise=0.01):
     rng = np.random.default_rng(seed + 7)
     pts = pts + rng.normal(0.0, noise, pts.shape)
     return pts.astype(np.float32), col.astype(np.float32)
+
+
+def ba_tracks(seed, n_cams=60, n_points=2000, width=1920, height=1440, max_views=8, noise_px=0.5,
+              outlier_frac=0.01, rot_noise_deg=0.5, centre_noise=0.02, point_noise=0.02):
+    """Synthetic bundle-adjustment problem on the spheres-and-planes scene.
+
+    Ground truth: the ring cameras (rotation R_i, centre c_i) and n_points
+    surface samples P_j.  A point is observed by a camera when it lies
+    0.2 or more in front of it and projects inside the image (no occlusion
+    test; sparse tracks), by at most max_views of those cameras chosen at
+    random; points seen fewer than twice are dropped.  The measurements are
+    made here, for input generation only, by the pinhole projection
+    u = fx x/z + cx, v = fy y/z + cy of x = R (P - c), plus N(0, noise_px^2)
+    pixel noise; a fraction outlier_frac of them is replaced by a uniform
+    random pixel.  Initial state: rotations perturbed by exp([w]x) with
+    w ~ N(0, rot_noise^2 I3) (radians from degrees), centres by
+    N(0, centre_noise^2 I3), points by N(0, point_noise^2 I3); camera 0 keeps
+    its true pose and camera 1 its true centre coordinate along the axis of
+    its largest baseline component to camera 0 (the fixed gauge).
+
+    Draw order (default_rng(seed)): scene (spheres_planes_scene(seed)),
+    points (sample_surface(scene, n_points, seed + 1)), then from
+    default_rng(seed + 2): per point a permutation of its visible cameras,
+    noise (n_obs, 2), outlier mask (n_obs,), outlier pixels (n_out, 2),
+    rotation noise (n_cams, 3), centre noise (n_cams, 3), point noise (m, 3).
+    Observations are ordered by point, then camera.
+    """
+    scene = spheres_planes_scene(seed)
+    pts = sample_surface(scene, n_points, seed + 1)[0]
+    cams = ring_cameras(n_cams, width, height)
+    R = np.stack([np.asarray(c["viewmat"][:, :3], np.float64) for c in cams])
+    t = np.stack([np.asarray(c["viewmat"][:, 3], np.float64) for c in cams])
+    # orthonormalise the float32-stored rotations so that the truth is exact
+    U, _, Vt = np.linalg.svd(R)
+    R = U @ Vt
+    centre = -np.einsum("cji,cj->ci", R, t)
+    fx, fy, cx, cy = (float(cams[0][k]) for k in ("fx", "fy", "cx", "cy"))
+    xc = np.einsum("cij,mcj->mci", R, pts[:, None, :] - centre[None, :, :])
+    z = xc[..., 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = fx * xc[..., 0] / z + cx
+        v = fy * xc[..., 1] / z + cy
+    vis = (z > 0.2) & (u >= 0) & (u < width) & (v >= 0) & (v < height)
+    rng = np.random.default_rng(seed + 2)
+    keep, obs_cam, obs_pt = [], [], []
+    for j in range(pts.shape[0]):
+        cs = np.nonzero(vis[j])[0]
+        if cs.size < 2:
+            continue
+        cs = np.sort(rng.permutation(cs)[:max_views])
+        m = len(keep)
+        keep.append(j)
+        obs_cam.append(cs)
+        obs_pt.append(np.full(cs.size, m))
+    keep = np.asarray(keep)
+    obs_cam = np.concatenate(obs_cam).astype(np.uint32)
+    obs_pt = np.concatenate(obs_pt).astype(np.uint32)
+    P = pts[keep]
+    uv = np.stack([u[keep[obs_pt], obs_cam], v[keep[obs_pt], obs_cam]], 1)
+    uv = uv + rng.normal(0.0, noise_px, uv.shape)
+    out = rng.uniform(0.0, 1.0, obs_cam.size) < outlier_frac
+    uv[out] = rng.uniform(0.0, 1.0, (int(out.sum()), 2)) * np.array([width, height])
+
+    def rodrigues(w):
+        th = np.linalg.norm(w, axis=1)[:, None, None]
+        K = np.zeros((w.shape[0], 3, 3))
+        K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -w[:, 2], w[:, 1], -w[:, 0]
+        K[:, 1, 0], K[:, 2, 0], K[:, 2, 1] = w[:, 2], -w[:, 1], w[:, 0]
+        th = np.where(th == 0, 1e-300, th)
+        return np.eye(3) + np.sin(th) / th * K + (1 - np.cos(th)) / th ** 2 * (K @ K)
+
+    wn = rng.normal(0.0, math.radians(rot_noise_deg), (n_cams, 3))
+    R0 = R @ rodrigues(wn)
+    c0 = centre + rng.normal(0.0, centre_noise, centre.shape)
+    P0 = P + rng.normal(0.0, point_noise, P.shape)
+    axis = int(np.argmax(np.abs(centre[1] - centre[0])))
+    R0[0], c0[0] = R[0], centre[0]
+    c0[1, axis] = centre[1, axis]
+    return dict(fx=fx, fy=fy, cx=cx, cy=cy, width=width, height=height, R_true=R, c_true=centre, P_true=P,
+                obs_cam=obs_cam, obs_pt=obs_pt, obs_uv=uv, outlier=out, R0=R0, c0=c0, P0=P0, gauge_axis=axis)
