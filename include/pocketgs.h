@@ -551,6 +551,75 @@ pgs_status pgs_seed_apply(const float* y_dev, const float* base_dev, const float
                           uint32_t* fallback_count_dev, void* stream);
 
 /*
+ * Bundle adjustment (subsection "GPU-Native Global BA as Mobile MAP
+ * Refinement"): the robustified reprojection objective of equation ba_obj,
+ * sum over observations (i, j) of rho(|pi(T_i, P_j) - p_ij|^2) with the Huber
+ * loss rho (unit information W_ij), scale-aware gauge fixing and the normal
+ * equation solved through the reduced camera system (Schur complement over
+ * the block-diagonal 3x3 point blocks).  Everything is float64.
+ *
+ * Camera i: rotation R_i (world to camera, 3x3 row-major) and centre c_i,
+ * x = R_i (P - c_i), pixel (fx x0/x2 + cx, fy x1/x2 + cy).  A step is
+ * dpose_i = (dphi, dc) and dP_j: R_i <- R_i exp([dphi]x), c_i <- c_i + dc,
+ * P_j <- P_j + dP.  Gauge: camera 0's six parameters and camera 1's centre
+ * coordinate gauge_axis are fixed (their step entries are 0).
+ *
+ * Observations are ordered by point: point j's are [point_start[j],
+ * point_start[j+1]); obs_cam / obs_pt give each one's camera and point;
+ * cam_obs lists the observation ids of each camera,
+ * [cam_start[i], cam_start[i+1]).  All arrays are device memory owned by
+ * the caller.
+ */
+#define PGS_BA_MAX_CAMS 200
+
+typedef struct pgs_ba_problem {
+    int32_t n_cams, n_points, n_obs;
+    int32_t gauge_axis;             /* 0..2 */
+    double fx, fy, cx, cy;
+    double huber_delta;             /* pixels, > 0 */
+    const uint32_t* obs_cam_dev;    /* [n_obs] */
+    const uint32_t* obs_pt_dev;     /* [n_obs] */
+    const double* obs_uv_dev;       /* [n_obs][2] measured pixels */
+    const uint32_t* point_start_dev;/* [n_points + 1] */
+    const uint32_t* cam_obs_dev;    /* [n_obs] */
+    const uint32_t* cam_start_dev;  /* [n_cams + 1] */
+} pgs_ba_problem;
+
+/* Workspace bytes of pgs_ba_cost / pgs_ba_step for a problem of this size. */
+size_t pgs_ba_workspace(int32_t n_cams, int32_t n_points, int32_t n_obs);
+
+/*
+ * pgs_ba_cost - robust cost sum rho(|r|^2) of the state (rot_dev [n_cams][9],
+ * centre_dev [n_cams][3], points_dev [n_points][3]) into *cost_dev (one
+ * double), summed in a fixed order.  Errors: PGS_ERR_INVALID_ARG for a bad
+ * problem (2 <= n_cams <= PGS_BA_MAX_CAMS, non-empty, gauge_axis 0..2,
+ * huber_delta > 0, no null pointer) or a small workspace.
+ */
+pgs_status pgs_ba_cost(const pgs_ba_problem* problem, const double* rot_dev, const double* centre_dev,
+                       const double* points_dev, double* cost_dev, void* workspace_dev,
+                       size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_ba_step - one Levenberg-Marquardt step of the iteratively reweighted
+ * Gauss-Newton normal equations, (H + lambda diag(H)) Delta = b over the
+ * free parameters (H = sum w J^T J, b = -sum w J^T r, w the Huber weight
+ * min(1, delta/|r|)), through the reduced camera system: dpose_dev
+ * [n_cams][6] (fixed entries 0) and dpoint_dev [n_points][3], overwritten.
+ * Errors as pgs_ba_cost, and lambda < 0.
+ */
+pgs_status pgs_ba_step(const pgs_ba_problem* problem, const double* rot_dev, const double* centre_dev,
+                       const double* points_dev, double lambda, double* dpose_dev, double* dpoint_dev,
+                       void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_ba_apply - the state after a step: rot_out = R exp([dphi]x),
+ * centre_out = c + dc, points_out = P + dP (outputs may not alias inputs).
+ */
+pgs_status pgs_ba_apply(int32_t n_cams, int32_t n_points, const double* rot_dev, const double* centre_dev,
+                        const double* points_dev, const double* dpose_dev, const double* dpoint_dev,
+                        double* rot_out_dev, double* centre_out_dev, double* points_out_dev, void* stream);
+
+/*
  * pgs_stream_copy - plain streaming copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) from src_dev to dst_dev.  A measurement aid, not
  * part of the method: it defines the achievable HBM bandwidth the kernels are

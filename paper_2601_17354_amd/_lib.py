@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpocketgs.so")
@@ -38,6 +38,13 @@ class PgsReplay(ctypes.Structure):
 class PgsViewBatch(ctypes.Structure):
     _fields_ = [("n_views", c_int32), ("cams", POINTER(PgsCamera)), ("tile_w", c_int32), ("tile_h", c_int32),
                 ("batch", c_int32), ("blocks", c_int32)]
+
+
+class PgsBaProblem(ctypes.Structure):
+    _fields_ = [("n_cams", c_int32), ("n_points", c_int32), ("n_obs", c_int32), ("gauge_axis", c_int32),
+                ("fx", c_double), ("fy", c_double), ("cx", c_double), ("cy", c_double), ("huber_delta", c_double),
+                ("obs_cam_dev", c_void_p), ("obs_pt_dev", c_void_p), ("obs_uv_dev", c_void_p),
+                ("point_start_dev", c_void_p), ("cam_obs_dev", c_void_p), ("cam_start_dev", c_void_p)]
 
 
 # name -> (restype, argtypes)
@@ -102,6 +109,13 @@ SIGNATURES = {
     "pgs_seed_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                  c_void_p]),
     "pgs_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pgs_ba_workspace": (c_size_t, [c_int32, c_int32, c_int32]),
+    "pgs_ba_cost": (c_int32, [POINTER(PgsBaProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                              c_void_p]),
+    "pgs_ba_step": (c_int32, [POINTER(PgsBaProblem), c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
+                              c_void_p, c_size_t, c_void_p]),
+    "pgs_ba_apply": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None

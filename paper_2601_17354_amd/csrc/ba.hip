@@ -1,0 +1,446 @@
+// Robust bundle adjustment with the reduced camera system (PocketGS
+// subsection "GPU-Native Global BA as Mobile MAP Refinement": the robustified
+// reprojection objective of equation ba_obj, scale-aware gauge fixing, and
+// the Schur complement over the block-diagonal point blocks).
+//
+// Everything is float64.  One Levenberg-Marquardt step (pgs_ba_step):
+//   k_ba_points   one thread per point, over its observations: residual,
+//                 Huber weight, Jacobians; the point block H_pp + lambda
+//                 diag(H_pp) inverted in place (3x3, adjugate), v = H_pp^-1 b_p,
+//                 and per observation the pose-point block H_tp (6x3) and the
+//                 observation's pose block and gradient (21 + 6 values);
+//   k_ba_cameras  one workgroup per camera: its pose block and gradient
+//                 summed over its observations in a fixed order (damped),
+//                 then its row block of the reduced system
+//                 S = H_tt - H_tp H_pp^-1 H_pt and g = b_t - H_tp v
+//                 accumulated in LDS over every pair of observations that
+//                 share a point (float64 LDS atomics), written to HBM;
+//   k_ba_solve    one workgroup: the gauge-free rows and columns of S
+//                 (camera 0's six parameters and camera 1's centre coordinate
+//                 along the gauge axis removed), Cholesky in place, forward
+//                 and back substitution -> the pose step;
+//   k_ba_backsub  one thread per point: dP = v - H_pp^-1 sum H_tp^T dt.
+// The cost (sum of Huber terms) is reduced per block in a fixed order.
+#include <math.h>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kCamThreads = 256;
+constexpr int kSolveThreads = 1024;
+constexpr int kCostThreads = 256;
+
+// Per-observation record in the workspace: H_tp (6x3 row-major), then the
+// observation's pose block (upper triangle of 6x6, row-major, 21 values)
+// and its gradient contribution (6).
+constexpr int kObsRec = 18 + 21 + 6;
+// Per-point record: damped H_pp^-1 (3x3 row-major) and v (3).
+constexpr int kPtRec = 12;
+
+struct Obs {
+    double r[2];        // residual
+    double w;           // Huber weight
+    double Jt[2][6];    // d r / d(dphi, dc)
+    double Jp[2][3];    // d r / dP
+};
+
+__device__ __forceinline__ void observe(const pgs_ba_problem& pb, const double* __restrict__ rot,
+                                        const double* __restrict__ centre, const double* __restrict__ pts,
+                                        int o, int j, Obs& ob) {
+    const int i = (int)pb.obs_cam_dev[o];
+    const double* R = rot + 9 * (size_t)i;
+    const double d0 = pts[3 * (size_t)j] - centre[3 * i], d1 = pts[3 * (size_t)j + 1] - centre[3 * i + 1],
+                 d2 = pts[3 * (size_t)j + 2] - centre[3 * i + 2];
+    const double x0 = R[0] * d0 + R[1] * d1 + R[2] * d2;
+    const double x1 = R[3] * d0 + R[4] * d1 + R[5] * d2;
+    const double x2 = R[6] * d0 + R[7] * d1 + R[8] * d2;
+    const double iz = 1.0 / x2;
+    ob.r[0] = pb.fx * x0 * iz + pb.cx - pb.obs_uv_dev[2 * (size_t)o];
+    ob.r[1] = pb.fy * x1 * iz + pb.cy - pb.obs_uv_dev[2 * (size_t)o + 1];
+    const double s = ob.r[0] * ob.r[0] + ob.r[1] * ob.r[1];
+    const double nrm = sqrt(s);
+    ob.w = nrm <= pb.huber_delta ? 1.0 : pb.huber_delta / nrm;
+    // d pi / d x
+    const double a00 = pb.fx * iz, a02 = -pb.fx * x0 * iz * iz;
+    const double a11 = pb.fy * iz, a12 = -pb.fy * x1 * iz * iz;
+    // A R (2x3): d r / dP; d r / dc = -A R; d r / ddphi = -A R [d]x
+    double AR[2][3];
+    for (int k = 0; k < 3; ++k) {
+        AR[0][k] = a00 * R[k] + a02 * R[6 + k];
+        AR[1][k] = a11 * R[3 + k] + a12 * R[6 + k];
+    }
+    for (int r = 0; r < 2; ++r) {
+        // (A R) [d]x with [d]x = [[0,-d2,d1],[d2,0,-d0],[-d1,d0,0]]
+        const double m0 = AR[r][1] * d2 - AR[r][2] * d1;
+        const double m1 = -AR[r][0] * d2 + AR[r][2] * d0;
+        const double m2 = AR[r][0] * d1 - AR[r][1] * d0;
+        ob.Jt[r][0] = -m0;
+        ob.Jt[r][1] = -m1;
+        ob.Jt[r][2] = -m2;
+        for (int k = 0; k < 3; ++k) {
+            ob.Jt[r][3 + k] = -AR[r][k];
+            ob.Jp[r][k] = AR[r][k];
+        }
+    }
+}
+
+__device__ __forceinline__ int tri6(int a, int b) {  // index of (a, b), a <= b, in the 6x6 upper triangle
+    return a * 6 - a * (a - 1) / 2 + (b - a);
+}
+
+__global__ __launch_bounds__(256) void k_ba_points(pgs_ba_problem pb, const double* __restrict__ rot,
+                                                   const double* __restrict__ centre,
+                                                   const double* __restrict__ pts, double lam,
+                                                   double* __restrict__ obs_rec, double* __restrict__ pt_rec) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= pb.n_points) return;
+    double Hp[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, bp[3] = {0, 0, 0};
+    const uint32_t o0 = pb.point_start_dev[j], o1 = pb.point_start_dev[j + 1];
+    for (uint32_t o = o0; o < o1; ++o) {
+        Obs ob;
+        observe(pb, rot, centre, pts, (int)o, j, ob);
+        double* rec = obs_rec + (size_t)o * kObsRec;
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) Hp[a][b] += ob.w * (ob.Jp[0][a] * ob.Jp[0][b] + ob.Jp[1][a] * ob.Jp[1][b]);
+            bp[a] -= ob.w * (ob.Jp[0][a] * ob.r[0] + ob.Jp[1][a] * ob.r[1]);
+        }
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 3; ++b)
+                rec[3 * a + b] = ob.w * (ob.Jt[0][a] * ob.Jp[0][b] + ob.Jt[1][a] * ob.Jp[1][b]);
+        for (int a = 0; a < 6; ++a) {
+            for (int b = a; b < 6; ++b)
+                rec[18 + tri6(a, b)] = ob.w * (ob.Jt[0][a] * ob.Jt[0][b] + ob.Jt[1][a] * ob.Jt[1][b]);
+            rec[39 + a] = -ob.w * (ob.Jt[0][a] * ob.r[0] + ob.Jt[1][a] * ob.r[1]);
+        }
+    }
+    // damped point block and its inverse (adjugate / determinant)
+    for (int a = 0; a < 3; ++a) Hp[a][a] += lam * Hp[a][a];
+    const double c00 = Hp[1][1] * Hp[2][2] - Hp[1][2] * Hp[2][1];
+    const double c01 = Hp[1][2] * Hp[2][0] - Hp[1][0] * Hp[2][2];
+    const double c02 = Hp[1][0] * Hp[2][1] - Hp[1][1] * Hp[2][0];
+    const double det = Hp[0][0] * c00 + Hp[0][1] * c01 + Hp[0][2] * c02;
+    const double id = 1.0 / det;
+    double Ai[3][3];
+    Ai[0][0] = c00 * id;
+    Ai[1][0] = c01 * id;
+    Ai[2][0] = c02 * id;
+    Ai[0][1] = (Hp[0][2] * Hp[2][1] - Hp[0][1] * Hp[2][2]) * id;
+    Ai[1][1] = (Hp[0][0] * Hp[2][2] - Hp[0][2] * Hp[2][0]) * id;
+    Ai[2][1] = (Hp[0][1] * Hp[2][0] - Hp[0][0] * Hp[2][1]) * id;
+    Ai[0][2] = (Hp[0][1] * Hp[1][2] - Hp[0][2] * Hp[1][1]) * id;
+    Ai[1][2] = (Hp[0][2] * Hp[1][0] - Hp[0][0] * Hp[1][2]) * id;
+    Ai[2][2] = (Hp[0][0] * Hp[1][1] - Hp[0][1] * Hp[1][0]) * id;
+    double* pr = pt_rec + (size_t)j * kPtRec;
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) pr[3 * a + b] = Ai[a][b];
+        pr[9 + a] = Ai[a][0] * bp[0] + Ai[a][1] * bp[1] + Ai[a][2] * bp[2];
+    }
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int k = 32; k > 0; k >>= 1) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __shfl_xor((int)(b & 0xffffffffll), k), hi = __shfl_xor((int)(b >> 32), k);
+        v += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+    return v;
+}
+
+// One workgroup per camera i: row block i of the reduced system.
+__global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, double lam,
+                                                            const double* __restrict__ obs_rec,
+                                                            const double* __restrict__ pt_rec,
+                                                            double* __restrict__ S, double* __restrict__ g) {
+    extern __shared__ double lds[];
+    constexpr int NW = kCamThreads / 64;
+    const int i = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int n6 = 6 * pb.n_cams;
+    double* row = lds;                 // [6][n6]
+    double* wsum = row + 6 * n6;       // [NW][27] per-wave pose block sums
+    double* gi = wsum + NW * 27;       // [6]
+    const uint32_t c0 = pb.cam_start_dev[i], c1 = pb.cam_start_dev[i + 1];
+    // pose block and gradient of camera i: per-lane sums over its
+    // observations, then wave sums and the waves' totals in a fixed order
+    double acc[27];
+    for (int k = 0; k < 27; ++k) acc[k] = 0.0;
+    for (uint32_t q = c0 + t; q < c1; q += kCamThreads) {
+        const double* rec = obs_rec + (size_t)pb.cam_obs_dev[q] * kObsRec + 18;
+        for (int k = 0; k < 27; ++k) acc[k] += rec[k];
+    }
+    for (int k = 0; k < 27; ++k) {
+        const double v = wave_sum_f64(acc[k]);
+        if (lane == 0) wsum[wv * 27 + k] = v;
+    }
+    for (int e = t; e < 6 * n6; e += kCamThreads) row[e] = 0.0;
+    __syncthreads();
+    if (t < 36) {
+        const int a = t / 6, b = t % 6, k = a <= b ? tri6(a, b) : tri6(b, a);
+        double h = 0.0;
+        for (int w = 0; w < NW; ++w) h += wsum[w * 27 + k];
+        if (a == b) h += lam * h;
+        row[a * n6 + 6 * i + b] = h;
+    }
+    if (t < 6) {
+        double h = 0.0;
+        for (int w = 0; w < NW; ++w) h += wsum[w * 27 + 21 + t];
+        gi[t] = h;
+    }
+    __syncthreads();
+    // - H_tp H_pp^-1 H_pt and - H_tp v over the observations of camera i
+    for (uint32_t q = c0 + t; q < c1; q += kCamThreads) {
+        const uint32_t o = pb.cam_obs_dev[q];
+        const uint32_t j = pb.obs_pt_dev[o];
+        const double* Htp = obs_rec + (size_t)o * kObsRec;
+        const double* pr = pt_rec + (size_t)j * kPtRec;
+        double T[6][3];  // H_tp(i, j) H_pp(j)^-1
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 3; ++b)
+                T[a][b] = Htp[3 * a] * pr[b] + Htp[3 * a + 1] * pr[3 + b] + Htp[3 * a + 2] * pr[6 + b];
+        for (int a = 0; a < 6; ++a)
+            atomicAdd(&gi[a], -(Htp[3 * a] * pr[9] + Htp[3 * a + 1] * pr[10] + Htp[3 * a + 2] * pr[11]));
+        for (uint32_t o2 = pb.point_start_dev[j]; o2 < pb.point_start_dev[j + 1]; ++o2) {
+            const int k = (int)pb.obs_cam_dev[o2];
+            const double* H2 = obs_rec + (size_t)o2 * kObsRec;
+            for (int a = 0; a < 6; ++a)
+                for (int b = 0; b < 6; ++b)
+                    atomicAdd(&row[a * n6 + 6 * k + b],
+                              -(T[a][0] * H2[3 * b] + T[a][1] * H2[3 * b + 1] + T[a][2] * H2[3 * b + 2]));
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < 6 * n6; e += kCamThreads) S[(size_t)(6 * i) * n6 + e] = row[e];
+    if (t < 6) g[6 * i + t] = gi[t];
+}
+
+// Free (moving) pose parameter k of nf: skips camera 0's six and camera 1's
+// centre coordinate along the gauge axis.
+__device__ __forceinline__ int free_param(int k, int gauge_axis) {
+    const int p = k + 6;                        // past camera 0
+    return p >= 9 + gauge_axis ? p + 1 : p;     // past camera 1's fixed centre coordinate
+}
+
+// One workgroup: gather the gauge-free system into A (nf x nf, row-major),
+// Cholesky A = L L^T in place (lower), solve L y = g, L^T x = y, scatter.
+__global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gauge_axis,
+                                                            const double* __restrict__ S,
+                                                            const double* __restrict__ g, double* __restrict__ A,
+                                                            double* __restrict__ y, double* __restrict__ dpose) {
+    const int n6 = 6 * n_cams, nf = n6 - 7, t = threadIdx.x;
+    for (int e = t; e < nf * nf; e += kSolveThreads) {
+        const int r = e / nf, c = e - r * nf;
+        A[e] = S[(size_t)free_param(r, gauge_axis) * n6 + free_param(c, gauge_axis)];
+    }
+    for (int r = t; r < nf; r += kSolveThreads) y[r] = g[free_param(r, gauge_axis)];
+    __syncthreads();
+    for (int k = 0; k < nf; ++k) {
+        if (t == 0) A[(size_t)k * nf + k] = sqrt(A[(size_t)k * nf + k]);
+        __syncthreads();
+        const double dkk = A[(size_t)k * nf + k];
+        for (int r = k + 1 + t; r < nf; r += kSolveThreads) A[(size_t)r * nf + k] /= dkk;
+        __syncthreads();
+        const int m = nf - k - 1;  // trailing (m x m) lower triangle
+        for (int e = t; e < m * m; e += kSolveThreads) {
+            const int r = k + 1 + e / m, c = k + 1 + e % m;
+            if (c <= r) A[(size_t)r * nf + c] -= A[(size_t)r * nf + k] * A[(size_t)c * nf + k];
+        }
+        __syncthreads();
+    }
+    // L y = g (column-oriented: y_k final, then subtract its column)
+    for (int k = 0; k < nf; ++k) {
+        if (t == 0) y[k] /= A[(size_t)k * nf + k];
+        __syncthreads();
+        const double yk = y[k];
+        for (int r = k + 1 + t; r < nf; r += kSolveThreads) y[r] -= A[(size_t)r * nf + k] * yk;
+        __syncthreads();
+    }
+    // L^T x = y (row k of L^T is column k of L)
+    for (int k = nf - 1; k >= 0; --k) {
+        if (t == 0) y[k] /= A[(size_t)k * nf + k];
+        __syncthreads();
+        const double xk = y[k];
+        for (int r = t; r < k; r += kSolveThreads) y[r] -= A[(size_t)k * nf + r] * xk;
+        __syncthreads();
+    }
+    for (int e = t; e < n6; e += kSolveThreads) dpose[e] = 0.0;
+    __syncthreads();
+    for (int r = t; r < nf; r += kSolveThreads) dpose[free_param(r, gauge_axis)] = y[r];
+}
+
+__global__ __launch_bounds__(256) void k_ba_backsub(pgs_ba_problem pb, const double* __restrict__ obs_rec,
+                                                    const double* __restrict__ pt_rec,
+                                                    const double* __restrict__ dpose,
+                                                    double* __restrict__ dpoint) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= pb.n_points) return;
+    double s[3] = {0, 0, 0};
+    for (uint32_t o = pb.point_start_dev[j]; o < pb.point_start_dev[j + 1]; ++o) {
+        const double* Htp = obs_rec + (size_t)o * kObsRec;
+        const double* dt = dpose + 6 * (size_t)pb.obs_cam_dev[o];
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 6; ++a) s[b] += Htp[3 * a + b] * dt[a];
+    }
+    const double* pr = pt_rec + (size_t)j * kPtRec;
+    for (int a = 0; a < 3; ++a)
+        dpoint[3 * (size_t)j + a] = pr[9 + a] - (pr[3 * a] * s[0] + pr[3 * a + 1] * s[1] + pr[3 * a + 2] * s[2]);
+}
+
+// Robust cost: per-block partial sums of rho over the observations.
+__global__ __launch_bounds__(kCostThreads) void k_ba_cost(pgs_ba_problem pb, const double* __restrict__ rot,
+                                                          const double* __restrict__ centre,
+                                                          const double* __restrict__ pts,
+                                                          double* __restrict__ part) {
+    __shared__ double s[kCostThreads];
+    double acc = 0.0;
+    for (int j = blockIdx.x * kCostThreads + threadIdx.x; j < pb.n_points; j += gridDim.x * kCostThreads) {
+        for (uint32_t o = pb.point_start_dev[j]; o < pb.point_start_dev[j + 1]; ++o) {
+            Obs ob;
+            observe(pb, rot, centre, pts, (int)o, j, ob);
+            const double q = ob.r[0] * ob.r[0] + ob.r[1] * ob.r[1];
+            const double n = sqrt(q);
+            acc += n <= pb.huber_delta ? q : 2.0 * pb.huber_delta * n - pb.huber_delta * pb.huber_delta;
+        }
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kCostThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_ba_cost_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += part[k];
+        *out = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ba_apply(int n_cams, int n_points, const double* __restrict__ rot,
+                                                  const double* __restrict__ centre,
+                                                  const double* __restrict__ pts, const double* __restrict__ dpose,
+                                                  const double* __restrict__ dpoint, double* __restrict__ rot_out,
+                                                  double* __restrict__ centre_out, double* __restrict__ pts_out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_points)
+        for (int a = 0; a < 3; ++a) pts_out[3 * (size_t)k + a] = pts[3 * (size_t)k + a] + dpoint[3 * (size_t)k + a];
+    if (k < n_cams) {
+        const double* w = dpose + 6 * k;
+        const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        // exp([w]x) = I + a [w]x + b [w]x^2 (Rodrigues; series below 1e-8)
+        const double a = th < 1e-8 ? 1.0 - th * th / 6.0 : sin(th) / th;
+        const double b = th < 1e-8 ? 0.5 - th * th / 24.0 : (1.0 - cos(th)) / (th * th);
+        const double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+        double E[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double kk = 0.0;
+                for (int m = 0; m < 3; ++m) kk += K[3 * r + m] * K[3 * m + c];
+                E[3 * r + c] = (r == c ? 1.0 : 0.0) + a * K[3 * r + c] + b * kk;
+            }
+        const double* R = rot + 9 * k;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                rot_out[9 * k + 3 * r + c] = R[3 * r] * E[c] + R[3 * r + 1] * E[3 + c] + R[3 * r + 2] * E[6 + c];
+        for (int a2 = 0; a2 < 3; ++a2) centre_out[3 * k + a2] = centre[3 * k + a2] + w[3 + a2];
+    }
+}
+
+// Workspace layout of one problem size.
+struct BaWs {
+    double *obs_rec, *pt_rec, *S, *g, *A, *y, *part;
+    size_t bytes;
+};
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr int kCostBlocks = 1024;
+
+BaWs ba_layout(void* base, int C, int M, int O) {
+    BaWs w{};
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    const size_t n6 = 6 * (size_t)C, nf = n6 > 7 ? n6 - 7 : 0;
+    auto take = [&](size_t n) { double* q = reinterpret_cast<double*>(p + off); off += al(n * 8); return q; };
+    w.obs_rec = take((size_t)O * kObsRec);
+    w.pt_rec = take((size_t)M * kPtRec);
+    w.S = take(n6 * n6);
+    w.g = take(n6);
+    w.A = take(nf * nf);
+    w.y = take(nf);
+    w.part = take(kCostBlocks);
+    w.bytes = off;
+    return w;
+}
+
+pgs_status check_problem(const pgs_ba_problem* pb, const char* who) {
+    PGS_REQUIRE(pb != nullptr, "%s: null problem", who);
+    PGS_REQUIRE(pb->n_cams >= 2 && pb->n_cams <= PGS_BA_MAX_CAMS, "%s: n_cams %d not in 2..%d", who, pb->n_cams,
+                PGS_BA_MAX_CAMS);
+    PGS_REQUIRE(pb->n_points >= 1 && pb->n_obs >= 1, "%s: empty problem", who);
+    PGS_REQUIRE(pb->gauge_axis >= 0 && pb->gauge_axis <= 2, "%s: gauge_axis %d", who, pb->gauge_axis);
+    PGS_REQUIRE(pb->huber_delta > 0.0, "%s: huber_delta must be > 0", who);
+    PGS_REQUIRE(pb->obs_cam_dev && pb->obs_pt_dev && pb->obs_uv_dev && pb->point_start_dev && pb->cam_obs_dev &&
+                    pb->cam_start_dev, "%s: null pointer in the problem", who);
+    return PGS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t pgs_ba_workspace(int32_t n_cams, int32_t n_points, int32_t n_obs) {
+    if (n_cams < 0 || n_points < 0 || n_obs < 0) return 0;
+    return ba_layout(nullptr, n_cams, n_points, n_obs).bytes;
+}
+
+extern "C" pgs_status pgs_ba_cost(const pgs_ba_problem* problem, const double* rot_dev, const double* centre_dev,
+                                  const double* points_dev, double* cost_dev, void* workspace_dev,
+                                  size_t workspace_bytes, void* stream) {
+    if (pgs_status st = check_problem(problem, "pgs_ba_cost")) return st;
+    PGS_REQUIRE(rot_dev && centre_dev && points_dev && cost_dev && workspace_dev, "pgs_ba_cost: null pointer");
+    const BaWs w = ba_layout(workspace_dev, problem->n_cams, problem->n_points, problem->n_obs);
+    PGS_REQUIRE(workspace_bytes >= w.bytes, "pgs_ba_cost: workspace %zu < %zu", workspace_bytes, w.bytes);
+    hipStream_t s = pgs::as_stream(stream);
+    const int blocks = min(kCostBlocks, (problem->n_points + kCostThreads - 1) / kCostThreads);
+    k_ba_cost<<<blocks, kCostThreads, 0, s>>>(*problem, rot_dev, centre_dev, points_dev, w.part);
+    k_ba_cost_final<<<1, 64, 0, s>>>(w.part, blocks, cost_dev);
+    PGS_CHECK_LAUNCH("pgs_ba_cost");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_ba_step(const pgs_ba_problem* problem, const double* rot_dev, const double* centre_dev,
+                                  const double* points_dev, double lambda, double* dpose_dev, double* dpoint_dev,
+                                  void* workspace_dev, size_t workspace_bytes, void* stream) {
+    if (pgs_status st = check_problem(problem, "pgs_ba_step")) return st;
+    PGS_REQUIRE(lambda >= 0.0, "pgs_ba_step: lambda < 0");
+    PGS_REQUIRE(rot_dev && centre_dev && points_dev && dpose_dev && dpoint_dev && workspace_dev,
+                "pgs_ba_step: null pointer");
+    const int C = problem->n_cams, M = problem->n_points;
+    const BaWs w = ba_layout(workspace_dev, C, M, problem->n_obs);
+    PGS_REQUIRE(workspace_bytes >= w.bytes, "pgs_ba_step: workspace %zu < %zu", workspace_bytes, w.bytes);
+    hipStream_t s = pgs::as_stream(stream);
+    k_ba_points<<<(M + 255) / 256, 256, 0, s>>>(*problem, rot_dev, centre_dev, points_dev, lambda, w.obs_rec,
+                                                w.pt_rec);
+    const size_t lds = (size_t)(6 * 6 * C + (kCamThreads / 64) * 27 + 6) * sizeof(double);
+    k_ba_cameras<<<C, kCamThreads, lds, s>>>(*problem, lambda, w.obs_rec, w.pt_rec, w.S, w.g);
+    k_ba_solve<<<1, kSolveThreads, 0, s>>>(C, problem->gauge_axis, w.S, w.g, w.A, w.y, dpose_dev);
+    k_ba_backsub<<<(M + 255) / 256, 256, 0, s>>>(*problem, w.obs_rec, w.pt_rec, dpose_dev, dpoint_dev);
+    PGS_CHECK_LAUNCH("pgs_ba_step");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_ba_apply(int32_t n_cams, int32_t n_points, const double* rot_dev,
+                                   const double* centre_dev, const double* points_dev, const double* dpose_dev,
+                                   const double* dpoint_dev, double* rot_out_dev, double* centre_out_dev,
+                                   double* points_out_dev, void* stream) {
+    PGS_REQUIRE(n_cams >= 0 && n_points >= 0, "pgs_ba_apply: negative size");
+    PGS_REQUIRE(rot_dev && centre_dev && points_dev && dpose_dev && dpoint_dev && rot_out_dev && centre_out_dev &&
+                    points_out_dev, "pgs_ba_apply: null pointer");
+    const int n = max(n_cams, n_points);
+    if (n == 0) return PGS_OK;
+    k_ba_apply<<<(n + 255) / 256, 256, 0, pgs::as_stream(stream)>>>(n_cams, n_points, rot_dev, centre_dev,
+                                                                   points_dev, dpose_dev, dpoint_dev, rot_out_dev,
+                                                                   centre_out_dev, points_out_dev);
+    PGS_CHECK_LAUNCH("pgs_ba_apply");
+    return PGS_OK;
+}

@@ -86,3 +86,23 @@ def test_missing_library_fails_loudly(tmp_path):
             _lib.load(str(tmp_path / "nope.so"))
     finally:
         _lib._lib = saved
+
+
+def test_ba_rejects_bad_problems_before_any_launch():
+    import ctypes
+    from paper_2601_17354_amd import _lib
+    lib = _lib.load()
+    pb = _lib.PgsBaProblem()
+    pb.n_cams, pb.n_points, pb.n_obs, pb.gauge_axis, pb.huber_delta = 1, 10, 20, 0, 2.0
+    st = lib.pgs_ba_cost(ctypes.byref(pb), None, None, None, None, None, 0, None)
+    assert st == _lib.PGS_ERR_INVALID_ARG and b"n_cams" in lib.pgs_last_error()
+    pb.n_cams = 4
+    pb.gauge_axis = 3
+    assert lib.pgs_ba_step(ctypes.byref(pb), None, None, None, 1e-3, None, None, None, 0, None) == \
+        _lib.PGS_ERR_INVALID_ARG
+    pb.gauge_axis, pb.huber_delta = 0, 0.0
+    assert lib.pgs_ba_cost(ctypes.byref(pb), None, None, None, None, None, 0, None) == _lib.PGS_ERR_INVALID_ARG
+    pb.huber_delta = 2.0
+    assert lib.pgs_ba_step(ctypes.byref(pb), None, None, None, -1.0, None, None, None, 0, None) == \
+        _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_ba_workspace(60, 1000, 5000) > 0
