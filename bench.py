@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched multi-view step, untuned 16x16 tiles / batch 256, 6 replays "
                          "(for rocprofv3)")
+    ap.add_argument("--no-ba", action="store_true", help="skip the bundle-adjustment measurement")
+    ap.add_argument("--ba-only", action="store_true", help="only the bundle-adjustment measurement")
     ap.add_argument("--no-cfg2", action="store_true",
                     help="skip the 100k / SH 3 / 1024x768 cached-vs-recompute comparison")
     ap.add_argument("--profile", action="store_true",
@@ -52,6 +54,7 @@ def parse():
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
         args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = args.no_cfg2 = True
+        args.no_ba = True
     return args
 
 
@@ -189,6 +192,68 @@ def cfg2_runs(steps=50, warmup=5):
             "entries": int(tr.rast.trace["count"].sum().item()) if cached else 0}
         del tr
     return out
+
+
+def ba_runs(n_cams=60, n_points=100_000, iters=15, cpu_points=3_000):
+    """Bundle adjustment of synthetic tracks (ring cameras, scene points,
+    0.5 px noise, 1% outliers, perturbed poses and points): per-kernel time of
+    one Levenberg-Marquardt iteration (step = linearise + reduced camera
+    system + solve + back-substitution, apply, cost) with HIP events, a full
+    run's convergence against the truth, and the oracle's step (sparse
+    normal equations + sparse direct solve) on a smaller problem."""
+    import torch
+    import synth
+    from paper_2601_17354_amd import ba
+    tr = synth.ba_tracks(6, n_cams=n_cams, n_points=n_points)
+    pb = ba.BAProblem.from_tracks(tr)
+    st = ba.state(tr["R0"], tr["c0"], tr["P0"])
+    dpose = torch.empty((pb.n_cams, 6), dtype=torch.float64, device="cuda")
+    dpoint = torch.empty((pb.n_points, 3), dtype=torch.float64, device="cuda")
+    out = tuple(torch.empty_like(t) for t in st)
+    cst = torch.empty(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        ba.step(pb, st, 1e-3, dpose, dpoint)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t = {"step": 0.0, "apply": 0.0, "cost": 0.0}
+    for _ in range(iters):
+        ev[0].record()
+        ba.step(pb, st, 1e-3, dpose, dpoint)
+        ev[1].record()
+        ba.apply(pb, st, dpose, dpoint, out)
+        ev[2].record()
+        ba.cost(pb, out, cst)
+        ev[3].record()
+        torch.cuda.synchronize()
+        t["step"] += ev[0].elapsed_time(ev[1]) / iters
+        t["apply"] += ev[1].elapsed_time(ev[2]) / iters
+        t["cost"] += ev[2].elapsed_time(ev[3]) / iters
+    final, hist, acc = ba.lm(pb, st, lam=1e-3, iters=20)
+    R, c, P = (x.cpu().numpy() for x in final)
+    R = R.reshape(-1, 3, 3)
+    rot_err = np.degrees(np.arccos(np.clip((np.einsum("cij,cij->c", R, tr["R_true"]) - 1) / 2, -1, 1)))
+    res = {"workload": f"{pb.n_cams} ring cameras, {pb.n_points} points, {pb.n_obs} observations "
+                       "(0.5 px noise, 1% outliers), Huber delta 2 px",
+           "ms_per_iteration": sum(t.values()), "ms": t, "iterations": len(hist) - 1,
+           "accepted": int(sum(acc)), "cost_first": hist[0], "cost_last": hist[-1],
+           "median_rotation_error_deg": float(np.median(rot_err)),
+           "median_centre_error": float(np.median(np.linalg.norm(c - tr["c_true"], axis=1))),
+           "median_point_error": float(np.median(np.linalg.norm(P - tr["P_true"], axis=1)))}
+    # the oracle's step on a smaller problem: sparse normal equations + direct solve
+    import time as _t
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spl
+    from oracle import ba as oba
+    trs = synth.ba_tracks(6, n_cams=n_cams, n_points=cpu_points)
+    t0 = _t.perf_counter()
+    H, b = oba.normal_equations_sparse(trs, trs["R0"], trs["c0"], trs["P0"], 2.0)
+    free = np.r_[oba.free_pose_params(n_cams, trs["gauge_axis"]), 6 * n_cams + np.arange(trs["P0"].size)]
+    A = H[free][:, free]
+    A = (A + 1e-3 * sps.diags(A.diagonal())).tocsc()
+    spl.spsolve(A, b[free])
+    res["cpu_oracle_step_s"] = _t.perf_counter() - t0
+    res["cpu_oracle_problem"] = f"{n_cams} cameras, {trs['P0'].shape[0]} points, 1 thread"
+    return res
 
 
 def render_fps(wl, params, order, frames=50):
@@ -466,6 +531,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
+    if args.ba_only:
+        print(json.dumps({"bundle_adjustment": ba_runs()}))
+        return
     if args.batched_only:
         r = batched_runs(args.batched_gaussians, steps=6, warmup=2, tuned={"tile": [16, 16], "batch": 256,
                                                                            "table": []}, compare=False)
@@ -565,6 +633,10 @@ def main():
         log("config 2: 100k Gaussians, SH 3, 1024x768, cached vs recompute backward")
         out["cfg2_backward_variants"] = cfg2_runs()
         log(f"config 2: {out['cfg2_backward_variants']}")
+    if not args.no_ba:
+        log("bundle adjustment: 60 cameras, 100k points")
+        out["bundle_adjustment"] = ba_runs()
+        log(f"bundle adjustment: {out['bundle_adjustment']}")
     log("seeding network alone")
     out["seed_network"] = mlp_runs()
     log(f"seed network: {out['seed_network']}")

@@ -568,9 +568,10 @@ pgs_status pgs_seed_apply(const float* y_dev, const float* base_dev, const float
  * point_start[j+1]); obs_cam / obs_pt give each one's camera and point;
  * cam_obs lists the observation ids of each camera,
  * [cam_start[i], cam_start[i+1]).  All arrays are device memory owned by
- * the caller.
+ * the caller.  At most PGS_BA_MAX_CAMS cameras (keyframes): the reduced
+ * camera system is factored by one workgroup with its panels in LDS.
  */
-#define PGS_BA_MAX_CAMS 200
+#define PGS_BA_MAX_CAMS 128
 
 typedef struct pgs_ba_problem {
     int32_t n_cams, n_points, n_obs;

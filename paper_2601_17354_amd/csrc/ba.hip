@@ -9,16 +9,19 @@
 //                 diag(H_pp) inverted in place (3x3, adjugate), v = H_pp^-1 b_p,
 //                 and per observation the pose-point block H_tp (6x3) and the
 //                 observation's pose block and gradient (21 + 6 values);
-//   k_ba_cameras  one workgroup per camera: its pose block and gradient
-//                 summed over its observations in a fixed order (damped),
-//                 then its row block of the reduced system
+//   k_ba_cameras  16 workgroups per camera, each over a slice of its
+//                 observations: partial row blocks of the reduced system
 //                 S = H_tt - H_tp H_pp^-1 H_pt and g = b_t - H_tp v
 //                 accumulated in LDS over every pair of observations that
-//                 share a point (float64 LDS atomics), written to HBM;
+//                 share a point (float64 LDS atomics); the first slice adds
+//                 the camera's damped pose block and gradient, summed over
+//                 its observations in a fixed order; k_ba_rows sums the
+//                 slices in order;
 //   k_ba_solve    one workgroup: the gauge-free rows and columns of S
 //                 (camera 0's six parameters and camera 1's centre coordinate
-//                 along the gauge axis removed), Cholesky in place, forward
-//                 and back substitution -> the pose step;
+//                 along the gauge axis removed), a panel-blocked Cholesky
+//                 (panels factored in LDS) with the forward substitution
+//                 folded in, and the back substitution -> the pose step;
 //   k_ba_backsub  one thread per point: dP = v - H_pp^-1 sum H_tp^T dt.
 // The cost (sum of Huber terms) is reduced per block in a fixed order.
 #include <math.h>
@@ -147,48 +150,59 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-// One workgroup per camera i: row block i of the reduced system.
+// Workgroup (i, s): split s of camera i's observations.  Partial row block
+// i of the reduced system over those observations (pair products of
+// observations that share a point, float64 LDS atomics); split 0 also adds
+// the camera's damped pose block and gradient, summed over all its
+// observations in a fixed order.  Partials go to part[i][s][6 n6 + 6].
+constexpr int kCamSplit = 16;
+
 __global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, double lam,
                                                             const double* __restrict__ obs_rec,
                                                             const double* __restrict__ pt_rec,
-                                                            double* __restrict__ S, double* __restrict__ g) {
+                                                            double* __restrict__ part) {
     extern __shared__ double lds[];
     constexpr int NW = kCamThreads / 64;
-    const int i = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int i = blockIdx.x, split = blockIdx.y, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int n6 = 6 * pb.n_cams;
     double* row = lds;                 // [6][n6]
     double* wsum = row + 6 * n6;       // [NW][27] per-wave pose block sums
     double* gi = wsum + NW * 27;       // [6]
     const uint32_t c0 = pb.cam_start_dev[i], c1 = pb.cam_start_dev[i + 1];
-    // pose block and gradient of camera i: per-lane sums over its
-    // observations, then wave sums and the waves' totals in a fixed order
-    double acc[27];
-    for (int k = 0; k < 27; ++k) acc[k] = 0.0;
-    for (uint32_t q = c0 + t; q < c1; q += kCamThreads) {
-        const double* rec = obs_rec + (size_t)pb.cam_obs_dev[q] * kObsRec + 18;
-        for (int k = 0; k < 27; ++k) acc[k] += rec[k];
-    }
-    for (int k = 0; k < 27; ++k) {
-        const double v = wave_sum_f64(acc[k]);
-        if (lane == 0) wsum[wv * 27 + k] = v;
-    }
     for (int e = t; e < 6 * n6; e += kCamThreads) row[e] = 0.0;
-    __syncthreads();
-    if (t < 36) {
-        const int a = t / 6, b = t % 6, k = a <= b ? tri6(a, b) : tri6(b, a);
-        double h = 0.0;
-        for (int w = 0; w < NW; ++w) h += wsum[w * 27 + k];
-        if (a == b) h += lam * h;
-        row[a * n6 + 6 * i + b] = h;
+    if (t < 6) gi[t] = 0.0;
+    if (split == 0) {
+        // pose block and gradient of camera i: per-lane sums over its
+        // observations, then wave sums and the waves' totals in a fixed order
+        double acc[27];
+        for (int k = 0; k < 27; ++k) acc[k] = 0.0;
+        for (uint32_t q = c0 + t; q < c1; q += kCamThreads) {
+            const double* rec = obs_rec + (size_t)pb.cam_obs_dev[q] * kObsRec + 18;
+            for (int k = 0; k < 27; ++k) acc[k] += rec[k];
+        }
+        for (int k = 0; k < 27; ++k) {
+            const double v = wave_sum_f64(acc[k]);
+            if (lane == 0) wsum[wv * 27 + k] = v;
+        }
+        __syncthreads();
+        if (t < 36) {
+            const int a = t / 6, b = t % 6, k = a <= b ? tri6(a, b) : tri6(b, a);
+            double h = 0.0;
+            for (int w = 0; w < NW; ++w) h += wsum[w * 27 + k];
+            if (a == b) h += lam * h;
+            row[a * n6 + 6 * i + b] = h;
+        }
+        if (t < 6) {
+            double h = 0.0;
+            for (int w = 0; w < NW; ++w) h += wsum[w * 27 + 21 + t];
+            gi[t] = h;
+        }
     }
-    if (t < 6) {
-        double h = 0.0;
-        for (int w = 0; w < NW; ++w) h += wsum[w * 27 + 21 + t];
-        gi[t] = h;
-    }
     __syncthreads();
-    // - H_tp H_pp^-1 H_pt and - H_tp v over the observations of camera i
-    for (uint32_t q = c0 + t; q < c1; q += kCamThreads) {
+    // - H_tp H_pp^-1 H_pt and - H_tp v over this split of camera i's observations
+    const uint32_t chunk = (c1 - c0 + kCamSplit - 1) / kCamSplit;
+    const uint32_t q0 = c0 + split * chunk, q1 = min(c1, q0 + chunk);
+    for (uint32_t q = q0 + t; q < q1; q += kCamThreads) {
         const uint32_t o = pb.cam_obs_dev[q];
         const uint32_t j = pb.obs_pt_dev[o];
         const double* Htp = obs_rec + (size_t)o * kObsRec;
@@ -209,8 +223,22 @@ __global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, d
         }
     }
     __syncthreads();
-    for (int e = t; e < 6 * n6; e += kCamThreads) S[(size_t)(6 * i) * n6 + e] = row[e];
-    if (t < 6) g[6 * i + t] = gi[t];
+    double* out = part + ((size_t)i * kCamSplit + split) * (6 * n6 + 6);
+    for (int e = t; e < 6 * n6; e += kCamThreads) out[e] = row[e];
+    if (t < 6) out[6 * n6 + t] = gi[t];
+}
+
+// Row blocks of S and g: the camera splits' partials summed in split order.
+__global__ __launch_bounds__(256) void k_ba_rows(int n_cams, const double* __restrict__ part,
+                                                 double* __restrict__ S, double* __restrict__ g) {
+    const int n6 = 6 * n_cams, per = 6 * n6 + 6;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)n_cams * per) return;
+    const int i = (int)(e / per), k = (int)(e - (size_t)i * per);
+    double acc = 0.0;
+    for (int sp = 0; sp < kCamSplit; ++sp) acc += part[((size_t)i * kCamSplit + sp) * per + k];
+    if (k < 6 * n6) S[(size_t)(6 * i) * n6 + k] = acc;
+    else g[6 * i + (k - 6 * n6)] = acc;
 }
 
 // Free (moving) pose parameter k of nf: skips camera 0's six and camera 1's
@@ -221,50 +249,92 @@ __device__ __forceinline__ int free_param(int k, int gauge_axis) {
 }
 
 // One workgroup: gather the gauge-free system into A (nf x nf, row-major),
-// Cholesky A = L L^T in place (lower), solve L y = g, L^T x = y, scatter.
-__global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gauge_axis,
+// then a right-looking Cholesky A = L L^T in panels of pw columns: the panel
+// (rows k0..nf-1) is factored in LDS, written back, and the trailing matrix
+// updated once per panel (dot products of length pw from LDS), with the
+// forward substitution L y = g folded in panel by panel; then L^T x = y
+// panel by panel from the last.  The step is scattered to the free entries.
+__global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gauge_axis, int pw,
                                                             const double* __restrict__ S,
                                                             const double* __restrict__ g, double* __restrict__ A,
                                                             double* __restrict__ y, double* __restrict__ dpose) {
-    const int n6 = 6 * n_cams, nf = n6 - 7, t = threadIdx.x;
-    for (int e = t; e < nf * nf; e += kSolveThreads) {
+    extern __shared__ double P[];  // [nf][pw + 1] the panel's rows (padded), then [pw] scratch
+    const int n6 = 6 * n_cams, nf = n6 - 7, t = threadIdx.x, ps = pw + 1;
+    constexpr int T = kSolveThreads;
+    for (int e = t; e < nf * nf; e += T) {
         const int r = e / nf, c = e - r * nf;
         A[e] = S[(size_t)free_param(r, gauge_axis) * n6 + free_param(c, gauge_axis)];
     }
-    for (int r = t; r < nf; r += kSolveThreads) y[r] = g[free_param(r, gauge_axis)];
+    for (int r = t; r < nf; r += T) y[r] = g[free_param(r, gauge_axis)];
     __syncthreads();
-    for (int k = 0; k < nf; ++k) {
-        if (t == 0) A[(size_t)k * nf + k] = sqrt(A[(size_t)k * nf + k]);
+    for (int k0 = 0; k0 < nf; k0 += pw) {
+        const int nb = min(pw, nf - k0), m = nf - k0, mt = m - nb;
+        for (int e = t; e < m * nb; e += T) {
+            const int r = e / nb, c = e - r * nb;
+            P[r * ps + c] = A[(size_t)(k0 + r) * nf + k0 + c];
+        }
         __syncthreads();
-        const double dkk = A[(size_t)k * nf + k];
-        for (int r = k + 1 + t; r < nf; r += kSolveThreads) A[(size_t)r * nf + k] /= dkk;
+        for (int p = 0; p < nb; ++p) {
+            if (t == 0) P[p * ps + p] = sqrt(P[p * ps + p]);
+            __syncthreads();
+            const double d = P[p * ps + p];
+            for (int r = p + 1 + t; r < m; r += T) P[r * ps + p] /= d;
+            __syncthreads();
+            const int w = nb - p - 1;
+            if (w > 0) {
+                for (int e = t; e < (m - p - 1) * w; e += T) {
+                    const int r = p + 1 + e / w, c = p + 1 + e % w;
+                    if (c <= r) P[r * ps + c] -= P[r * ps + p] * P[c * ps + p];
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < m * nb; e += T) {
+            const int r = e / nb, c = e - r * nb;
+            if (c <= r) A[(size_t)(k0 + r) * nf + k0 + c] = P[r * ps + c];
+        }
+        if (t == 0)
+            for (int p = 0; p < nb; ++p) {
+                double v = y[k0 + p];
+                for (int q = 0; q < p; ++q) v -= P[p * ps + q] * y[k0 + q];
+                y[k0 + p] = v / P[p * ps + p];
+            }
         __syncthreads();
-        const int m = nf - k - 1;  // trailing (m x m) lower triangle
-        for (int e = t; e < m * m; e += kSolveThreads) {
-            const int r = k + 1 + e / m, c = k + 1 + e % m;
-            if (c <= r) A[(size_t)r * nf + c] -= A[(size_t)r * nf + k] * A[(size_t)c * nf + k];
+        for (int r = nb + t; r < m; r += T) {
+            double v = 0.0;
+            for (int p = 0; p < nb; ++p) v += P[r * ps + p] * y[k0 + p];
+            y[k0 + r] -= v;
+        }
+        for (int e = t; e < mt * mt; e += T) {
+            const int ii = e / mt, jj = e - ii * mt;
+            if (jj <= ii) {
+                double v = 0.0;
+                for (int p = 0; p < nb; ++p) v += P[(nb + ii) * ps + p] * P[(nb + jj) * ps + p];
+                A[(size_t)(k0 + nb + ii) * nf + k0 + nb + jj] -= v;
+            }
         }
         __syncthreads();
     }
-    // L y = g (column-oriented: y_k final, then subtract its column)
-    for (int k = 0; k < nf; ++k) {
-        if (t == 0) y[k] /= A[(size_t)k * nf + k];
+    double* red = P + (size_t)nf * ps;  // [pw]
+    for (int k0 = ((nf - 1) / pw) * pw; k0 >= 0; k0 -= pw) {
+        const int nb = min(pw, nf - k0);
+        if (t < nb) {
+            double v = 0.0;
+            for (int r = k0 + nb; r < nf; ++r) v += A[(size_t)r * nf + k0 + t] * y[r];
+            red[t] = v;
+        }
         __syncthreads();
-        const double yk = y[k];
-        for (int r = k + 1 + t; r < nf; r += kSolveThreads) y[r] -= A[(size_t)r * nf + k] * yk;
+        if (t == 0)
+            for (int p = nb - 1; p >= 0; --p) {
+                double v = y[k0 + p] - red[p];
+                for (int q = p + 1; q < nb; ++q) v -= A[(size_t)(k0 + q) * nf + k0 + p] * y[k0 + q];
+                y[k0 + p] = v / A[(size_t)(k0 + p) * nf + k0 + p];
+            }
         __syncthreads();
     }
-    // L^T x = y (row k of L^T is column k of L)
-    for (int k = nf - 1; k >= 0; --k) {
-        if (t == 0) y[k] /= A[(size_t)k * nf + k];
-        __syncthreads();
-        const double xk = y[k];
-        for (int r = t; r < k; r += kSolveThreads) y[r] -= A[(size_t)k * nf + r] * xk;
-        __syncthreads();
-    }
-    for (int e = t; e < n6; e += kSolveThreads) dpose[e] = 0.0;
+    for (int e = t; e < n6; e += T) dpose[e] = 0.0;
     __syncthreads();
-    for (int r = t; r < nf; r += kSolveThreads) dpose[free_param(r, gauge_axis)] = y[r];
+    for (int r = t; r < nf; r += T) dpose[free_param(r, gauge_axis)] = y[r];
 }
 
 __global__ __launch_bounds__(256) void k_ba_backsub(pgs_ba_problem pb, const double* __restrict__ obs_rec,
@@ -350,7 +420,7 @@ __global__ __launch_bounds__(256) void k_ba_apply(int n_cams, int n_points, cons
 
 // Workspace layout of one problem size.
 struct BaWs {
-    double *obs_rec, *pt_rec, *S, *g, *A, *y, *part;
+    double *obs_rec, *pt_rec, *cam_part, *S, *g, *A, *y, *part;
     size_t bytes;
 };
 
@@ -365,6 +435,7 @@ BaWs ba_layout(void* base, int C, int M, int O) {
     auto take = [&](size_t n) { double* q = reinterpret_cast<double*>(p + off); off += al(n * 8); return q; };
     w.obs_rec = take((size_t)O * kObsRec);
     w.pt_rec = take((size_t)M * kPtRec);
+    w.cam_part = take((size_t)C * kCamSplit * (6 * n6 + 6));
     w.S = take(n6 * n6);
     w.g = take(n6);
     w.A = take(nf * nf);
@@ -372,6 +443,15 @@ BaWs ba_layout(void* base, int C, int M, int O) {
     w.part = take(kCostBlocks);
     w.bytes = off;
     return w;
+}
+
+// Panel width of the solve: 32 columns while the padded panel fits 127 KB
+// of LDS (nf <= 480), else 16 (nf <= 6 PGS_BA_MAX_CAMS - 7: about 104 KB).
+inline int solve_panel(int nf) { return nf <= 480 ? 32 : 16; }
+inline size_t solve_lds(int nf, int pw) { return ((size_t)nf * (pw + 1) + pw) * sizeof(double); }
+inline size_t solve_lds_max() {
+    const size_t a = solve_lds(480, 32), b = solve_lds(6 * PGS_BA_MAX_CAMS - 7, 16);
+    return a > b ? a : b;
 }
 
 pgs_status check_problem(const pgs_ba_problem* pb, const char* who) {
@@ -422,8 +502,16 @@ extern "C" pgs_status pgs_ba_step(const pgs_ba_problem* problem, const double* r
     k_ba_points<<<(M + 255) / 256, 256, 0, s>>>(*problem, rot_dev, centre_dev, points_dev, lambda, w.obs_rec,
                                                 w.pt_rec);
     const size_t lds = (size_t)(6 * 6 * C + (kCamThreads / 64) * 27 + 6) * sizeof(double);
-    k_ba_cameras<<<C, kCamThreads, lds, s>>>(*problem, lambda, w.obs_rec, w.pt_rec, w.S, w.g);
-    k_ba_solve<<<1, kSolveThreads, 0, s>>>(C, problem->gauge_axis, w.S, w.g, w.A, w.y, dpose_dev);
+    k_ba_cameras<<<dim3(C, kCamSplit), kCamThreads, lds, s>>>(*problem, lambda, w.obs_rec, w.pt_rec, w.cam_part);
+    const size_t rows = (size_t)C * (36 * C + 6);
+    k_ba_rows<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(C, w.cam_part, w.S, w.g);
+    const int nf = 6 * C - 7, pw = solve_panel(nf);
+    const size_t slds = solve_lds(nf, pw);
+    static bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ba_solve),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)solve_lds_max()) == hipSuccess;
+    PGS_REQUIRE(lds_ok, "pgs_ba_step: cannot reserve %zu bytes of LDS for the solve", solve_lds_max());
+    k_ba_solve<<<1, kSolveThreads, slds, s>>>(C, problem->gauge_axis, pw, w.S, w.g, w.A, w.y, dpose_dev);
     k_ba_backsub<<<(M + 255) / 256, 256, 0, s>>>(*problem, w.obs_rec, w.pt_rec, dpose_dev, dpoint_dev);
     PGS_CHECK_LAUNCH("pgs_ba_step");
     return PGS_OK;
