@@ -20,8 +20,9 @@
 //   k_ba_solve    one workgroup: the gauge-free rows and columns of S
 //                 (camera 0's six parameters and camera 1's centre coordinate
 //                 along the gauge axis removed), a panel-blocked Cholesky
-//                 (panels factored in LDS) with the forward substitution
-//                 folded in, and the back substitution -> the pose step;
+//                 (panels in LDS, the right-hand side carried as an extra
+//                 row so the forward substitution comes with the factor),
+//                 and the blocked back substitution -> the pose step;
 //   k_ba_backsub  one thread per point: dP = v - H_pp^-1 sum H_tp^T dt.
 // The cost (sum of Huber terms) is reduced per block in a fixed order.
 #include <math.h>
@@ -248,93 +249,167 @@ __device__ __forceinline__ int free_param(int k, int gauge_axis) {
     return p >= 9 + gauge_axis ? p + 1 : p;     // past camera 1's fixed centre coordinate
 }
 
-// One workgroup: gather the gauge-free system into A (nf x nf, row-major),
-// then a right-looking Cholesky A = L L^T in panels of pw columns: the panel
-// (rows k0..nf-1) is factored in LDS, written back, and the trailing matrix
-// updated once per panel (dot products of length pw from LDS), with the
-// forward substitution L y = g folded in panel by panel; then L^T x = y
-// panel by panel from the last.  The step is scattered to the free entries.
-__global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gauge_axis, int pw,
+// Broadcast of a double from lane `src` of the wave.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __shfl((int)(b & 0xffffffffll), src), hi = __shfl((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One workgroup solves the gauge-free reduced camera system.  A holds nf + 1
+// rows of nf: the system's rows, then the right-hand side as an extra row,
+// so that the Cholesky factorisation A = L L^T of the rows computes the
+// forward substitution L y = g as that row's entries of L.  Right-looking,
+// in panels of PW columns: the panel's rows (from the panel's diagonal down,
+// right-hand side included) are staged in LDS; the PW x PW diagonal block is
+// factored with one thread per entry; the rows below are the triangular
+// solves x L11^T = a, one thread per row; the trailing lower triangle is
+// updated in 4 x 4 register blocks from the panel in LDS.  Back substitution
+// L^T x = y then runs panel by panel from the last: the products with the
+// solved entries below a panel are summed over 1024 / PW row slices in a
+// fixed order, and one wave solves the PW x PW triangle with lane broadcasts.
+// The step is scattered to the free pose entries; the fixed ones are 0.
+template <int PW>
+__global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gauge_axis,
                                                             const double* __restrict__ S,
                                                             const double* __restrict__ g, double* __restrict__ A,
-                                                            double* __restrict__ y, double* __restrict__ dpose) {
-    extern __shared__ double P[];  // [nf][pw + 1] the panel's rows (padded), then [pw] scratch
-    const int n6 = 6 * n_cams, nf = n6 - 7, t = threadIdx.x, ps = pw + 1;
-    constexpr int T = kSolveThreads;
+                                                            double* __restrict__ dpose) {
+    extern __shared__ double lds[];
+    constexpr int T = kSolveThreads, PS = PW + 1, NS = T / PW;
+    const int n6 = 6 * n_cams, nf = n6 - 7, t = threadIdx.x;
+    double* col = lds;                  // [PW] the column being eliminated
+    double* inv = col + PW;             // [PW] 1 / L_pp of the panel
+    double* dd = inv + PW;              // [1]  the pivot
+    double* P = dd + 2;                 // panel [nf + 1][PS]; later red [NS][PW], L11 [PW][PS], x [nf]
     for (int e = t; e < nf * nf; e += T) {
         const int r = e / nf, c = e - r * nf;
-        A[e] = S[(size_t)free_param(r, gauge_axis) * n6 + free_param(c, gauge_axis)];
+        if (c <= r) A[e] = S[(size_t)free_param(r, gauge_axis) * n6 + free_param(c, gauge_axis)];
     }
-    for (int r = t; r < nf; r += T) y[r] = g[free_param(r, gauge_axis)];
+    for (int c = t; c < nf; c += T) A[(size_t)nf * nf + c] = g[free_param(c, gauge_axis)];
     __syncthreads();
-    for (int k0 = 0; k0 < nf; k0 += pw) {
-        const int nb = min(pw, nf - k0), m = nf - k0, mt = m - nb;
+    for (int k0 = 0; k0 < nf; k0 += PW) {
+        const int nb = min(PW, nf - k0), m = nf + 1 - k0;  // panel rows, the right-hand side last
         for (int e = t; e < m * nb; e += T) {
             const int r = e / nb, c = e - r * nb;
-            P[r * ps + c] = A[(size_t)(k0 + r) * nf + k0 + c];
+            P[r * PS + c] = (r >= nb || c <= r) ? A[(size_t)(k0 + r) * nf + k0 + c] : 0.0;
         }
         __syncthreads();
+        // diagonal block: thread (r, c), c <= r < nb, keeps its entry in a register
+        const int dr = t / PW, dc = t % PW;
+        const bool own = t < PW * PW && dr < nb && dc <= dr;
+        double a = own ? P[dr * PS + dc] : 0.0;
         for (int p = 0; p < nb; ++p) {
-            if (t == 0) P[p * ps + p] = sqrt(P[p * ps + p]);
+            if (own && dr == p && dc == p) dd[0] = a;
             __syncthreads();
-            const double d = P[p * ps + p];
-            for (int r = p + 1 + t; r < m; r += T) P[r * ps + p] /= d;
+            if (own && dc == p) {
+                const double d = sqrt(dd[0]);
+                a = dr == p ? d : a / d;
+                col[dr] = a;
+                if (dr == p) inv[p] = 1.0 / d;
+            }
             __syncthreads();
-            const int w = nb - p - 1;
-            if (w > 0) {
-                for (int e = t; e < (m - p - 1) * w; e += T) {
-                    const int r = p + 1 + e / w, c = p + 1 + e % w;
-                    if (c <= r) P[r * ps + c] -= P[r * ps + p] * P[c * ps + p];
+            if (own && dc > p) a -= col[dr] * col[dc];
+        }
+        if (own) P[dr * PS + dc] = a;
+        __syncthreads();
+        // rows below the block: x L11^T = a, x_p = (a_p - sum_{q<p} x_q L_pq) / L_pp
+        for (int r = nb + t; r < m; r += T) {
+            double x[PW];
+#pragma unroll
+            for (int p = 0; p < PW; ++p) x[p] = p < nb ? P[r * PS + p] : 0.0;
+#pragma unroll
+            for (int p = 0; p < PW; ++p) {
+                if (p < nb) {
+                    double v = x[p];
+#pragma unroll
+                    for (int q = 0; q < p; ++q) v -= x[q] * P[p * PS + q];
+                    x[p] = v * inv[p];
                 }
             }
-            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < PW; ++p)
+                if (p < nb) P[r * PS + p] = x[p];
         }
+        __syncthreads();
         for (int e = t; e < m * nb; e += T) {
             const int r = e / nb, c = e - r * nb;
-            if (c <= r) A[(size_t)(k0 + r) * nf + k0 + c] = P[r * ps + c];
+            if (r >= nb || c <= r) A[(size_t)(k0 + r) * nf + k0 + c] = P[r * PS + c];
         }
-        if (t == 0)
-            for (int p = 0; p < nb; ++p) {
-                double v = y[k0 + p];
-                for (int q = 0; q < p; ++q) v -= P[p * ps + q] * y[k0 + q];
-                y[k0 + p] = v / P[p * ps + p];
+        // trailing update of rows nb..m-1 (right-hand side last), columns
+        // nb..nf-k0-1, lower triangle: A_ij -= sum_p L_ip L_jp
+        const int mt = m - nb, mc = mt - 1, bi_n = (mt + 3) >> 2, bj_n = (mc + 3) >> 2;
+        for (int e = t; e < bi_n * bj_n; e += T) {
+            const int bi = e / bj_n, bj = e - bi * bj_n;
+            if (bj > bi) continue;
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+            int ri[4], rj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ri[u] = nb + min(4 * bi + u, mt - 1);
+                rj[u] = nb + min(4 * bj + u, mc - 1);
             }
-        __syncthreads();
-        for (int r = nb + t; r < m; r += T) {
-            double v = 0.0;
-            for (int p = 0; p < nb; ++p) v += P[r * ps + p] * y[k0 + p];
-            y[k0 + r] -= v;
-        }
-        for (int e = t; e < mt * mt; e += T) {
-            const int ii = e / mt, jj = e - ii * mt;
-            if (jj <= ii) {
-                double v = 0.0;
-                for (int p = 0; p < nb; ++p) v += P[(nb + ii) * ps + p] * P[(nb + jj) * ps + p];
-                A[(size_t)(k0 + nb + ii) * nf + k0 + nb + jj] -= v;
+            for (int p = 0; p < nb; ++p) {
+                double li[4], lj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    li[u] = P[ri[u] * PS + p];
+                    lj[u] = P[rj[u] * PS + p];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] = fma(li[u], lj[v], acc[u][v]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ii = 4 * bi + u;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int jj = 4 * bj + v;
+                    if (ii < mt && jj < mc && jj <= ii) A[(size_t)(k0 + nb + ii) * nf + k0 + nb + jj] -= acc[u][v];
+                }
             }
         }
         __syncthreads();
     }
-    double* red = P + (size_t)nf * ps;  // [pw]
-    for (int k0 = ((nf - 1) / pw) * pw; k0 >= 0; k0 -= pw) {
-        const int nb = min(pw, nf - k0);
-        if (t < nb) {
-            double v = 0.0;
-            for (int r = k0 + nb; r < nf; ++r) v += A[(size_t)r * nf + k0 + t] * y[r];
-            red[t] = v;
+    // back substitution L^T x = y, y = row nf of A
+    double* red = P;                    // [NS][PW]
+    double* L11 = red + NS * PW;        // [PW][PS]
+    double* xs = L11 + PW * PS;         // [nf]
+    const int lane = t & 63;
+    for (int k0 = ((nf - 1) / PW) * PW; k0 >= 0; k0 -= PW) {
+        const int nb = min(PW, nf - k0), cc = t % PW, sl = t / PW;
+        double v = 0.0;
+        if (cc < nb)
+            for (int r = k0 + nb + sl; r < nf; r += NS) v += A[(size_t)r * nf + k0 + cc] * xs[r];
+        red[sl * PW + cc] = v;
+        for (int e = t; e < nb * nb; e += T) {
+            const int r = e / nb, c = e - r * nb;
+            if (c <= r) L11[r * PS + c] = A[(size_t)(k0 + r) * nf + k0 + c];
         }
         __syncthreads();
-        if (t == 0)
-            for (int p = nb - 1; p >= 0; --p) {
-                double v = y[k0 + p] - red[p];
-                for (int q = p + 1; q < nb; ++q) v -= A[(size_t)(k0 + q) * nf + k0 + p] * y[k0 + q];
-                y[k0 + p] = v / A[(size_t)(k0 + p) * nf + k0 + p];
+        if (t < 64) {
+            double w = 0.0;
+            if (lane < nb) {
+                w = A[(size_t)nf * nf + k0 + lane];
+                for (int q = 0; q < NS; ++q) w -= red[q * PW + lane];
             }
+            for (int q = nb - 1; q >= 0; --q) {
+                const double xq = lane_bcast(w / L11[q * PS + q], q);
+                if (lane == q) w = xq;
+                else if (lane < q) w -= L11[q * PS + lane] * xq;
+            }
+            if (lane < nb) xs[k0 + lane] = w;
+        }
         __syncthreads();
     }
     for (int e = t; e < n6; e += T) dpose[e] = 0.0;
     __syncthreads();
-    for (int r = t; r < nf; r += T) dpose[free_param(r, gauge_axis)] = y[r];
+    for (int r = t; r < nf; r += T) dpose[free_param(r, gauge_axis)] = xs[r];
 }
 
 __global__ __launch_bounds__(256) void k_ba_backsub(pgs_ba_problem pb, const double* __restrict__ obs_rec,
@@ -420,7 +495,7 @@ __global__ __launch_bounds__(256) void k_ba_apply(int n_cams, int n_points, cons
 
 // Workspace layout of one problem size.
 struct BaWs {
-    double *obs_rec, *pt_rec, *cam_part, *S, *g, *A, *y, *part;
+    double *obs_rec, *pt_rec, *cam_part, *S, *g, *A, *part;
     size_t bytes;
 };
 
@@ -438,20 +513,28 @@ BaWs ba_layout(void* base, int C, int M, int O) {
     w.cam_part = take((size_t)C * kCamSplit * (6 * n6 + 6));
     w.S = take(n6 * n6);
     w.g = take(n6);
-    w.A = take(nf * nf);
-    w.y = take(nf);
+    w.A = take((nf + 1) * nf);
     w.part = take(kCostBlocks);
     w.bytes = off;
     return w;
 }
 
-// Panel width of the solve: 32 columns while the padded panel fits 127 KB
-// of LDS (nf <= 480), else 16 (nf <= 6 PGS_BA_MAX_CAMS - 7: about 104 KB).
-inline int solve_panel(int nf) { return nf <= 480 ? 32 : 16; }
-inline size_t solve_lds(int nf, int pw) { return ((size_t)nf * (pw + 1) + pw) * sizeof(double); }
-inline size_t solve_lds_max() {
-    const size_t a = solve_lds(480, 32), b = solve_lds(6 * PGS_BA_MAX_CAMS - 7, 16);
-    return a > b ? a : b;
+// Panel width of the solve and its LDS: the panel's nf + 1 rows padded to
+// PW + 1 doubles (32 columns up to nf = 400: at most 106 KB; 16 beyond, up
+// to nf = 6 PGS_BA_MAX_CAMS - 7: about 104 KB).
+constexpr int kSolveWide = 400;
+template <int PW>
+inline size_t solve_lds(int nf) {
+    const size_t panel = (size_t)(nf + 1) * (PW + 1), back = (size_t)kSolveThreads + PW * (PW + 1) + nf;
+    return (2 * PW + 2 + (panel > back ? panel : back)) * sizeof(double);
+}
+template <int PW>
+bool solve_lds_reserved(int nf) {
+    static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ba_solve<PW>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)solve_lds<PW>(PW == 32 ? kSolveWide : 6 * PGS_BA_MAX_CAMS - 7)) ==
+                           hipSuccess;
+    return ok && solve_lds<PW>(nf) <= solve_lds<PW>(PW == 32 ? kSolveWide : 6 * PGS_BA_MAX_CAMS - 7);
 }
 
 pgs_status check_problem(const pgs_ba_problem* pb, const char* who) {
@@ -505,13 +588,14 @@ extern "C" pgs_status pgs_ba_step(const pgs_ba_problem* problem, const double* r
     k_ba_cameras<<<dim3(C, kCamSplit), kCamThreads, lds, s>>>(*problem, lambda, w.obs_rec, w.pt_rec, w.cam_part);
     const size_t rows = (size_t)C * (36 * C + 6);
     k_ba_rows<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(C, w.cam_part, w.S, w.g);
-    const int nf = 6 * C - 7, pw = solve_panel(nf);
-    const size_t slds = solve_lds(nf, pw);
-    static bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ba_solve),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)solve_lds_max()) == hipSuccess;
-    PGS_REQUIRE(lds_ok, "pgs_ba_step: cannot reserve %zu bytes of LDS for the solve", solve_lds_max());
-    k_ba_solve<<<1, kSolveThreads, slds, s>>>(C, problem->gauge_axis, pw, w.S, w.g, w.A, w.y, dpose_dev);
+    const int nf = 6 * C - 7;
+    if (nf <= kSolveWide) {
+        PGS_REQUIRE(solve_lds_reserved<32>(nf), "pgs_ba_step: cannot reserve LDS for the solve");
+        k_ba_solve<32><<<1, kSolveThreads, solve_lds<32>(nf), s>>>(C, problem->gauge_axis, w.S, w.g, w.A, dpose_dev);
+    } else {
+        PGS_REQUIRE(solve_lds_reserved<16>(nf), "pgs_ba_step: cannot reserve LDS for the solve");
+        k_ba_solve<16><<<1, kSolveThreads, solve_lds<16>(nf), s>>>(C, problem->gauge_axis, w.S, w.g, w.A, dpose_dev);
+    }
     k_ba_backsub<<<(M + 255) / 256, 256, 0, s>>>(*problem, w.obs_rec, w.pt_rec, dpose_dev, dpoint_dev);
     PGS_CHECK_LAUNCH("pgs_ba_step");
     return PGS_OK;
