@@ -25,6 +25,13 @@ conventions that section inherits):
   seed.py        KNN local statistics and disc-like covariance seeding (Sec.
                  "Prior-Conditioned Gaussian Parameterization").
   sh.py          real spherical-harmonic basis used for colour.
+  mlp.py         the learned seeding network (bfloat16 products, float32
+                 accumulation emulated) and its loss and targets.
+  ba.py          robust bundle adjustment (Sec. "GPU-Native Global BA"):
+                 Huber reprojection objective, gauge, damped normal equations.
+  mvs.py         single-reference Census / plane-sweep / SGM stereo with the
+                 depth range, reference score, confidence filter and fusion
+                 (Sec. "Single-Reference Cost-Volume MVS").
 
 Everything is float64.  Decisions that turn floating point into integers
 (culling, radius, tile rectangle, depth key, alpha skip, termination) are

@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
 
 This module holds only input generation: Gaussian parameter sets, cameras,
-surface point clouds, target images and bundle-adjustment tracks.  It holds
+surface point clouds, target images, bundle-adjustment tracks and ray-cast
+greyscale views with exact depth (multi-view stereo inputs).  It holds
 none of the splatting arithmetic (no projection, binning, compositing,
 gradients or seeding) and none of the bundle adjustment's (the tracks'
 measurements come from a pinhole projection written in the generator for
@@ -42,4 +43,5 @@ from .gen import (  # noqa: F401
     random_image,
     random_normal,
     ba_tracks,
+    textured_views,
 )

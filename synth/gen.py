@@ -359,3 +359,92 @@ def ba_tracks(seed, n_cams=60, n_points=2000, width=1920, height=1440, max_views
     c0[1, axis] = centre[1, axis]
     return dict(fx=fx, fy=fy, cx=cx, cy=cy, width=width, height=height, R_true=R, c_true=centre, P_true=P,
                 obs_cam=obs_cam, obs_pt=obs_pt, obs_uv=uv, outlier=out, R0=R0, c0=c0, P0=P0, gauge_axis=axis)
+
+
+def _value_noise(table: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """Trilinear interpolation of a periodic random lattice (table (n, n, n))
+    at points p (m, 3) given in lattice units."""
+    n = table.shape[0]
+    f = np.floor(p)
+    w = p - f
+    i = f.astype(np.int64) % n
+    out = np.zeros(p.shape[0])
+    for dx in (0, 1):
+        wx = w[:, 0] if dx else 1.0 - w[:, 0]
+        for dy in (0, 1):
+            wy = w[:, 1] if dy else 1.0 - w[:, 1]
+            for dz in (0, 1):
+                wz = w[:, 2] if dz else 1.0 - w[:, 2]
+                out += wx * wy * wz * table[(i[:, 0] + dx) % n, (i[:, 1] + dy) % n, (i[:, 2] + dz) % n]
+    return out
+
+
+def textured_views(scene: Scene, cams: list, seed: int = 0, speckle=((0.012, 0.12), (0.04, 0.08)),
+                   near=0.2):
+    """Ray-cast greyscale views of the spheres-and-planes scene with their
+    exact depth maps (multi-view stereo inputs).
+
+    Pixel (x, y) of a camera (the float32-stored intrinsics and [R|t], taken
+    as float64) casts the ray X(z) = R^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t);
+    its depth is the smallest camera z >= near at which it meets a sphere or
+    a plane rectangle, 0 where it meets nothing.  Intensity = luma
+    (0.299, 0.587, 0.114) of the scene's procedural colour at the hit plus
+    solid value noise: for each (cell, amplitude) of `speckle`, amplitude x
+    a trilinearly interpolated 64^3 lattice of U[-1, 1] values at the hit
+    point divided by cell; clipped to [0, 1] and stored as uint8
+    floor(255 v + 0.5).  Background pixels are 0.
+
+    Draw order (default_rng(seed)): one 64^3 lattice per speckle octave.
+    Returns (grey uint8 (V, H, W), depth float32 (V, H, W)).
+    """
+    rng = np.random.default_rng(seed)
+    tables = [rng.uniform(-1.0, 1.0, (64, 64, 64)) for _ in speckle]
+    S = len(scene.radii)
+    greys, depths = [], []
+    for cam in cams:
+        W, H = cam["width"], cam["height"]
+        vm = np.asarray(cam["viewmat"], np.float64)
+        R, t = vm[:, :3], vm[:, 3]
+        o = -R.T @ t
+        ys, xs = np.mgrid[0:H, 0:W]
+        dc = np.stack([(xs.ravel() - cam["cx"]) / cam["fx"], (ys.ravel() - cam["cy"]) / cam["fy"],
+                       np.ones(W * H)], 1)
+        d = dc @ R                      # world direction per unit camera depth
+        best = np.full(W * H, np.inf)
+        sid = np.full(W * H, -1, np.int64)
+        for s in range(S):
+            oc = o - scene.centres[s]
+            a = (d * d).sum(1)
+            b = 2.0 * (d @ oc)
+            c = oc @ oc - scene.radii[s] ** 2
+            disc = b * b - 4.0 * a * c
+            ok = disc >= 0
+            sq = np.sqrt(np.where(ok, disc, 0.0))
+            z0 = (-b - sq) / (2.0 * a)
+            z1 = (-b + sq) / (2.0 * a)
+            z = np.where(z0 >= near, z0, z1)
+            hit = ok & (z >= near) & (z < best)
+            best = np.where(hit, z, best)
+            sid = np.where(hit, s, sid)
+        for k, (po, ua, va, nn, ul, vl) in enumerate(scene.planes):
+            den = d @ nn
+            with np.errstate(divide="ignore", invalid="ignore"):
+                z = ((po - o) @ nn) / den
+                q = o + z[:, None] * d - po
+                u, v = q @ ua, q @ va
+            hit = (np.abs(den) > 1e-12) & (z >= near) & (z < best) & (u >= 0) & (u <= ul) & (v >= 0) & (v <= vl)
+            best = np.where(hit, z, best)
+            sid = np.where(hit, S + k, sid)
+        hitm = sid >= 0
+        p = o + best[hitm, None] * d[hitm]
+        col = _texture(scene, sid[hitm], p)
+        g = col @ np.array([0.299, 0.587, 0.114])
+        for (cell, amp), tab in zip(speckle, tables):
+            g = g + amp * _value_noise(tab, p / cell)
+        grey = np.zeros(W * H)
+        grey[hitm] = np.clip(g, 0.0, 1.0)
+        greys.append(np.floor(255.0 * grey + 0.5).astype(np.uint8).reshape(H, W))
+        dep = np.zeros(W * H)
+        dep[hitm] = best[hitm]
+        depths.append(dep.astype(np.float32).reshape(H, W))
+    return np.stack(greys), np.stack(depths)
