@@ -620,6 +620,110 @@ pgs_status pgs_ba_apply(int32_t n_cams, int32_t n_points, const double* rot_dev,
                         const double* points_dev, const double* dpose_dev, const double* dpoint_dev,
                         double* rot_out_dev, double* centre_out_dev, double* points_out_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Single-reference cost-volume multi-view stereo (subsection
+ * "Single-Reference Cost-Volume MVS").  All views share one image size
+ * width x height (the cameras' own width/height fields are not read); the
+ * cameras are a device array cams_dev[n_views] of pgs_camera, read as
+ * float64.  Images are 8-bit greyscale [n_views][height][width].
+ * ------------------------------------------------------------------------ */
+typedef struct pgs_mvs_params {
+    int32_t n_planes;   /* depth hypotheses: 64, 128, 192 or 256 */
+    int32_t p1, p2;     /* SGM penalties for a one-plane / a larger jump, 0..1000 */
+    double conf_min;    /* confidence filter, 0.4 in the paper */
+    double b_target;    /* preferred baseline (scene units), reference score */
+    double sigma_b;     /* > 0, width of the baseline term */
+    double alpha_min;   /* > 0 radians, angle scale of the reference score */
+} pgs_mvs_params;
+
+/*
+ * pgs_mvs_census - 7 x 7 Census transform (matching-cost paragraph): 48
+ * bits per pixel, bit b (row-major over the window, centre skipped) set when
+ * the neighbour is darker than the centre; neighbours outside the image take
+ * the nearest border pixel.  grey_dev [n_views][height][width] uint8 ->
+ * census_dev [n_views][height][width] uint64.
+ */
+pgs_status pgs_mvs_census(const uint8_t* grey_dev, int32_t n_views, int32_t width, int32_t height,
+                          uint64_t* census_dev, void* stream);
+
+/* Workspace bytes of pgs_mvs_depth_range. */
+size_t pgs_mvs_range_workspace(int32_t n_views, int32_t n_points);
+
+/*
+ * pgs_mvs_depth_range - probabilistic depth range (paragraph "Probabilistic
+ * Depth Range Estimation"): per view, the camera depths z > 0 of the sparse
+ * points points_dev [n_points][3] (float64, world) whose pixel lies in
+ * [-0.5, width - 0.5) x [-0.5, height - 0.5); with their sorted depths z_i
+ * and q(p) = z_i + (z_{i+1} - z_i)(h - i), h = (n - 1) p, i = floor(h):
+ * range_dev [n_views][2] = (0.5 q(0.05), 1.5 q(0.95)), (0, 0) when no point
+ * projects into the view.  Every product and sum is an unfused float64
+ * operation in a fixed order, so the result is reproducible bit for bit.
+ */
+pgs_status pgs_mvs_depth_range(const pgs_camera* cams_dev, int32_t n_views, int32_t width, int32_t height,
+                               const double* points_dev, int32_t n_points, double* range_dev,
+                               void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/*
+ * pgs_mvs_select_ref - single-reference selection (equation S_ref): for
+ * each view, among all other views the one maximising
+ * exp(-(b - b_target)^2 / (2 sigma_b^2)) * max(alpha / alpha_min, 1), b the
+ * distance between the camera centres, alpha the angle between the optical
+ * axes; ref_dev [n_views] int32 (smallest index on ties; -1 with one view).
+ */
+pgs_status pgs_mvs_select_ref(const pgs_camera* cams_dev, int32_t n_views, const pgs_mvs_params* params,
+                              int32_t* ref_dev, void* stream);
+
+/*
+ * pgs_mvs_cost - plane-sweep Census cost volume (matching-cost paragraph)
+ * for the target views targets_dev [n_targets] against their references
+ * ref_dev[view]: n_planes fronto-parallel planes uniform in inverse depth
+ * over range_dev[view] (plane 0 the farthest,
+ * 1/d_k = 1/d_max + k (1/d_min - 1/d_max)/(n_planes - 1)); target pixel
+ * (x, y) at d_k maps to X = d_k ((x - cx)/fx, (y - cy)/fy, 1), to the
+ * reference as M X + m (M = R_r R_t^T, m = t_r - M t_t) and to its nearest
+ * pixel floor(fx x/z + cx + 0.5), likewise y (unfused float64 in a fixed
+ * order); cost = Hamming distance of the Census strings, 48 where z <= 0,
+ * the pixel is outside the image or the range is empty.
+ * cost_dev [n_targets][height][width][n_planes] uint8.
+ */
+pgs_status pgs_mvs_cost(const pgs_camera* cams_dev, int32_t width, int32_t height, const uint64_t* census_dev,
+                        const int32_t* targets_dev, int32_t n_targets, const int32_t* ref_dev,
+                        const double* range_dev, const pgs_mvs_params* params, uint8_t* cost_dev, void* stream);
+
+/* Workspace bytes of pgs_mvs_sgm (the path-cost sum, uint16). */
+size_t pgs_mvs_sgm_workspace(int32_t n_targets, int32_t width, int32_t height, int32_t n_planes);
+
+/*
+ * pgs_mvs_sgm - SGM aggregation over 4 paths (left-right, right-left,
+ * top-bottom, bottom-top), L_r(p,k) = C(p,k) + min(L_r(p-r,k),
+ * L_r(p-r,k+-1) + p1, min_i L_r(p-r,i) + p2) - min_i L_r(p-r,i), then per
+ * pixel the winner k* (smallest sum S, smallest plane on ties), S2 = min S
+ * over |k - k*| >= 2 and the confidence filter: kept when 0 < k* < n_planes-1,
+ * S2 > 0 and S(k*) <= (1 - conf_min) S2, with the parabola-refined depth
+ * 1/d = 1/d_max + (k* + delta) h.  depth_dev [n_targets][height][width]
+ * float32 (0 where rejected), conf_dev the same shape (1 - S(k*)/S2).
+ * agg_out_dev (optional, [n_targets][height][width][n_planes] uint16)
+ * receives S; without it the sum lives in the workspace.
+ */
+pgs_status pgs_mvs_sgm(const uint8_t* cost_dev, int32_t width, int32_t height, const int32_t* targets_dev,
+                       int32_t n_targets, const double* range_dev, const pgs_mvs_params* params, float* depth_dev,
+                       float* conf_dev, uint16_t* agg_out_dev, void* workspace_dev, size_t workspace_bytes,
+                       void* stream);
+
+/* Workspace bytes of pgs_mvs_fuse. */
+size_t pgs_mvs_fuse_workspace(int32_t n_targets, int32_t height);
+
+/*
+ * pgs_mvs_fuse - fusion into the dense cloud P: the kept pixels (depth > 0)
+ * of each target view, in target order and row-major pixel order,
+ * back-projected to the world, R^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t),
+ * into points_dev [capacity][3] float32; *count_dev = the number of kept
+ * pixels (points beyond capacity are not written).
+ */
+pgs_status pgs_mvs_fuse(const pgs_camera* cams_dev, const int32_t* targets_dev, int32_t n_targets, int32_t width,
+                        int32_t height, const float* depth_dev, float* points_dev, uint32_t capacity,
+                        uint32_t* count_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+
 /*
  * pgs_stream_copy - plain streaming copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) from src_dev to dst_dev.  A measurement aid, not

@@ -40,6 +40,11 @@ class PgsViewBatch(ctypes.Structure):
                 ("batch", c_int32), ("blocks", c_int32)]
 
 
+class PgsMvsParams(ctypes.Structure):
+    _fields_ = [("n_planes", c_int32), ("p1", c_int32), ("p2", c_int32), ("conf_min", c_double),
+                ("b_target", c_double), ("sigma_b", c_double), ("alpha_min", c_double)]
+
+
 class PgsBaProblem(ctypes.Structure):
     _fields_ = [("n_cams", c_int32), ("n_points", c_int32), ("n_obs", c_int32), ("gauge_axis", c_int32),
                 ("fx", c_double), ("fy", c_double), ("cx", c_double), ("cy", c_double), ("huber_delta", c_double),
@@ -116,6 +121,19 @@ SIGNATURES = {
                               c_void_p, c_size_t, c_void_p]),
     "pgs_ba_apply": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p]),
+    "pgs_mvs_census": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "pgs_mvs_range_workspace": (c_size_t, [c_int32, c_int32]),
+    "pgs_mvs_depth_range": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
+                                      c_size_t, c_void_p]),
+    "pgs_mvs_select_ref": (c_int32, [c_void_p, c_int32, POINTER(PgsMvsParams), c_void_p, c_void_p]),
+    "pgs_mvs_cost": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                               POINTER(PgsMvsParams), c_void_p, c_void_p]),
+    "pgs_mvs_sgm_workspace": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
+    "pgs_mvs_sgm": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_void_p, POINTER(PgsMvsParams),
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pgs_mvs_fuse_workspace": (c_size_t, [c_int32, c_int32]),
+    "pgs_mvs_fuse": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_uint32,
+                               c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 _lib = None

@@ -1,0 +1,690 @@
+// Single-reference cost-volume multi-view stereo on gfx950 (subsection
+// "Single-Reference Cost-Volume MVS": probabilistic depth range, reference
+// score S_ref, Census plane-sweep cost, SGM aggregation, confidence filter,
+// fusion into the dense cloud).
+//
+// Kernels:
+//   k_mvs_depths / k_mvs_range  camera depths of the sparse points that
+//       project into each view, appended per view (wave-aggregated atomics),
+//       then per view (one workgroup) the ranks that define the 5% and 95%
+//       quantiles found by radix selection over the float64 bit patterns;
+//       range = [0.5 q_.05, 1.5 q_.95];
+//   k_mvs_ref     per target view the candidate maximising
+//       exp(-(b - b_target)^2 / (2 sigma_b^2)) max(alpha / alpha_min, 1);
+//   k_census      7 x 7 Census (48 bits) from a 22 x 22 LDS tile;
+//   k_cost<D>     one thread per (pixel, plane): the plane-sweep pixel in the
+//       reference view from float64 arithmetic in a fixed order without
+//       contraction (the nearest-pixel decision is reproducible), Hamming
+//       distance of the Census strings; cost volume [y][x][plane] bytes;
+//   k_sgm<KPL, MODE>  one wave per image line and direction: lane l holds
+//       planes l, l + 64, ... ; per step the previous costs' minimum is a
+//       wave reduction and the neighbouring planes come from lane shuffles;
+//       the first pass writes the path cost, the middle ones add to it, the
+//       last adds its own and takes the winner, the confidence and the
+//       refined depth for each pixel without storing the sum;
+//   k_fuse_*      per-row counts, one scan over rows and the back-projection
+//       of the kept pixels in row-major order.
+
+#include <math.h>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kCensusR = 3;
+constexpr int kCensusBits = (2 * kCensusR + 1) * (2 * kCensusR + 1) - 1;  // 48
+constexpr int kCostOut = kCensusBits;
+constexpr int kTile = 16;
+constexpr int kHalo = kTile + 2 * kCensusR;
+
+struct Cam64 {
+    double fx, fy, cx, cy, R[9], t[3];
+};
+
+__device__ __forceinline__ Cam64 cam64(const pgs_camera& c) {
+    Cam64 d;
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) d.R[3 * r + k] = c.viewmat[4 * r + k];
+        d.t[r] = c.viewmat[4 * r + 3];
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------- census
+
+__global__ __launch_bounds__(256) void k_census(const uint8_t* __restrict__ grey, int W, int H,
+                                                uint64_t* __restrict__ out) {
+    __shared__ int tile[kHalo][kHalo];
+    const size_t off = (size_t)blockIdx.z * W * H;
+    const int x0 = blockIdx.x * kTile - kCensusR, y0 = blockIdx.y * kTile - kCensusR;
+    for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
+        const int ty = e / kHalo, tx = e - ty * kHalo;
+        const int gx = min(max(x0 + tx, 0), W - 1), gy = min(max(y0 + ty, 0), H - 1);
+        tile[ty][tx] = grey[off + (size_t)gy * W + gx];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
+    const int x = blockIdx.x * kTile + lx, y = blockIdx.y * kTile + ly;
+    if (x >= W || y >= H) return;
+    const int c = tile[ly + kCensusR][lx + kCensusR];
+    uint64_t v = 0;
+    int b = 0;
+#pragma unroll
+    for (int dy = -kCensusR; dy <= kCensusR; ++dy)
+#pragma unroll
+        for (int dx = -kCensusR; dx <= kCensusR; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            v |= (uint64_t)(tile[ly + kCensusR + dy][lx + kCensusR + dx] < c) << b;
+            ++b;
+        }
+    out[off + (size_t)y * W + x] = v;
+}
+
+// ---------------------------------------------------------------- range
+
+__global__ __launch_bounds__(256) void k_mvs_clear(uint32_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_mvs_depths(const pgs_camera* __restrict__ cams, int W, int H,
+                                                    const double* __restrict__ pts, int M,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ cnt) {
+#pragma clang fp contract(off)
+    const int v = blockIdx.y, j = blockIdx.x * 256 + threadIdx.x, lane = threadIdx.x & 63;
+    bool in = false;
+    double z = 0.0;
+    if (j < M) {
+        const Cam64 c = cam64(cams[v]);
+        const double P0 = pts[3 * (size_t)j], P1 = pts[3 * (size_t)j + 1], P2 = pts[3 * (size_t)j + 2];
+        const double x = c.R[0] * P0 + c.R[1] * P1 + c.R[2] * P2 + c.t[0];
+        const double y = c.R[3] * P0 + c.R[4] * P1 + c.R[5] * P2 + c.t[1];
+        z = c.R[6] * P0 + c.R[7] * P1 + c.R[8] * P2 + c.t[2];
+        const double u = c.fx * (x / z) + c.cx, w = c.fy * (y / z) + c.cy;
+        in = z > 0.0 && u >= -0.5 && u < (double)W - 0.5 && w >= -0.5 && w < (double)H - 0.5;
+    }
+    const uint64_t b = __ballot(in);
+    if (b == 0) return;
+    const int leader = __ffsll((long long)b) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[v], (uint32_t)__popcll(b));
+    base = __shfl(base, leader);
+    if (in) {
+        const uint64_t below = b & ((1ull << lane) - 1ull);
+        keys[(size_t)v * M + base + __popcll(below)] = (uint64_t)__double_as_longlong(z);
+    }
+}
+
+// The rank-th smallest of n keys (one workgroup), by radix selection over
+// 8-bit digits from the most significant.
+__device__ uint64_t select_rank(const uint64_t* __restrict__ keys, uint32_t n, uint32_t rank, uint32_t* hist,
+                                uint64_t* s_prefix, uint32_t* s_rank) {
+    const int t = threadIdx.x;
+    uint64_t prefix = 0, mask = 0;
+    uint32_t r = rank;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        if (t < 256) hist[t] = 0u;
+        __syncthreads();
+        for (uint32_t i = t; i < n; i += blockDim.x) {
+            const uint64_t k = keys[i];
+            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t acc = 0, d = 255;
+            for (uint32_t q = 0; q < 256; ++q) {
+                if (acc + hist[q] > r) {
+                    d = q;
+                    break;
+                }
+                acc += hist[q];
+            }
+            *s_prefix = prefix | ((uint64_t)d << shift);
+            *s_rank = r - acc;
+        }
+        __syncthreads();
+        prefix = *s_prefix;
+        r = *s_rank;
+        mask |= 255ull << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+__device__ double quantile_of(const uint64_t* keys, uint32_t n, double p, uint32_t* hist, uint64_t* s_prefix,
+                              uint32_t* s_rank) {
+#pragma clang fp contract(off)
+    const double h = (double)(n - 1) * p;
+    const uint32_t i = (uint32_t)floor(h);
+    const double zi = __longlong_as_double((long long)select_rank(keys, n, i, hist, s_prefix, s_rank));
+    if (i + 1 >= n) return zi;
+    const double zj = __longlong_as_double((long long)select_rank(keys, n, i + 1, hist, s_prefix, s_rank));
+    return zi + (zj - zi) * (h - (double)i);
+}
+
+__global__ __launch_bounds__(1024) void k_mvs_range(int M, const uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ cnt, double* __restrict__ range) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t s_prefix;
+    __shared__ uint32_t s_rank;
+    const int v = blockIdx.x;
+    const uint32_t n = cnt[v];
+    double lo = 0.0, hi = 0.0;
+    if (n > 0) {
+        const uint64_t* k = keys + (size_t)v * M;
+        lo = 0.5 * quantile_of(k, n, 0.05, hist, &s_prefix, &s_rank);
+        hi = 1.5 * quantile_of(k, n, 0.95, hist, &s_prefix, &s_rank);
+    }
+    if (threadIdx.x == 0) {
+        range[2 * v] = lo;
+        range[2 * v + 1] = hi;
+    }
+}
+
+// ---------------------------------------------------------------- reference
+
+__global__ __launch_bounds__(64) void k_mvs_ref(const pgs_camera* __restrict__ cams, int V, double b_target,
+                                                double sigma_b, double alpha_min, int32_t* __restrict__ ref) {
+    const int tv = blockIdx.x * 64 + threadIdx.x;
+    if (tv >= V) return;
+    const Cam64 a = cam64(cams[tv]);
+    double ca[3];
+    for (int k = 0; k < 3; ++k) ca[k] = -(a.R[k] * a.t[0] + a.R[3 + k] * a.t[1] + a.R[6 + k] * a.t[2]);
+    double best = -1.0;
+    int arg = -1;
+    for (int c = 0; c < V; ++c) {
+        if (c == tv) continue;
+        const Cam64 b = cam64(cams[c]);
+        double d2 = 0.0, dot = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double cb = -(b.R[k] * b.t[0] + b.R[3 + k] * b.t[1] + b.R[6 + k] * b.t[2]);
+            d2 += (cb - ca[k]) * (cb - ca[k]);
+            dot += a.R[6 + k] * b.R[6 + k];
+        }
+        const double base = sqrt(d2), alpha = acos(fmin(1.0, fmax(-1.0, dot)));
+        const double s = exp(-(base - b_target) * (base - b_target) / (2.0 * sigma_b * sigma_b)) *
+                         fmax(alpha / alpha_min, 1.0);
+        if (arg < 0 || s > best) {
+            best = s;
+            arg = c;
+        }
+    }
+    ref[tv] = arg;
+}
+
+// ---------------------------------------------------------------- cost volume
+
+template <int D>
+__global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cams, int W, int H,
+                                              const uint64_t* __restrict__ census,
+                                              const int32_t* __restrict__ targets, const int32_t* __restrict__ refs,
+                                              const double* __restrict__ range, uint8_t* __restrict__ cost) {
+#pragma clang fp contract(off)
+    constexpr int PPB = 256 / D > 0 ? 256 / D : 1;  // pixels per block
+    __shared__ double s_pose[12 + 8];                 // M, m, then the two cameras' intrinsics, 1/d_max, h
+    const int ti = blockIdx.y, tv = targets[ti], rv = refs[tv];
+    const double d_min = range[2 * tv], d_max = range[2 * tv + 1];
+    if (threadIdx.x == 0) {
+        const Cam64 ct = cam64(cams[tv]), cr = cam64(cams[rv]);
+        double M[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                M[3 * i + j] = cr.R[3 * i] * ct.R[3 * j] + cr.R[3 * i + 1] * ct.R[3 * j + 1] +
+                               cr.R[3 * i + 2] * ct.R[3 * j + 2];
+        for (int i = 0; i < 9; ++i) s_pose[i] = M[i];
+        for (int i = 0; i < 3; ++i)
+            s_pose[9 + i] = cr.t[i] - (M[3 * i] * ct.t[0] + M[3 * i + 1] * ct.t[1] + M[3 * i + 2] * ct.t[2]);
+        s_pose[12] = ct.fx;
+        s_pose[13] = ct.fy;
+        s_pose[14] = ct.cx;
+        s_pose[15] = ct.cy;
+        s_pose[16] = cr.fx;
+        s_pose[17] = cr.fy;
+        s_pose[18] = cr.cx;
+        s_pose[19] = cr.cy;
+    }
+    __syncthreads();
+    const int k = threadIdx.x % D;
+    const long long pix = (long long)blockIdx.x * PPB + threadIdx.x / D;
+    if (pix >= (long long)W * H) return;
+    const int y = (int)(pix / W), x = (int)(pix - (long long)y * W);
+    const size_t npix = (size_t)W * H;
+    int c = kCostOut;
+    if (d_min > 0.0 && d_max > d_min) {
+        const double inv_far = 1.0 / d_max;
+        const double h = (1.0 / d_min - inv_far) / (double)(D - 1);
+        const double d = 1.0 / (inv_far + (double)k * h);
+        const double a = ((double)x - s_pose[14]) / s_pose[12], b = ((double)y - s_pose[15]) / s_pose[13];
+        const double X = d * a, Y = d * b, Z = d;
+        const double* M = s_pose;
+        const double xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
+        const double yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
+        const double zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
+        const double u = floor(s_pose[16] * (xr / zr) + s_pose[18] + 0.5);
+        const double v = floor(s_pose[17] * (yr / zr) + s_pose[19] + 0.5);
+        if (zr > 0.0 && u >= 0.0 && u <= (double)(W - 1) && v >= 0.0 && v <= (double)(H - 1)) {
+            const uint64_t ref = census[(size_t)rv * npix + (size_t)v * W + (size_t)u];
+            c = __popcll(census[(size_t)tv * npix + pix] ^ ref);
+        }
+    }
+    cost[((size_t)ti * npix + pix) * D + k] = (uint8_t)c;
+}
+
+// ---------------------------------------------------------------- SGM
+
+enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2 };
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+struct SgmArgs {
+    const uint8_t* cost;
+    uint16_t* agg;       // path-cost sum [T][H][W][D]
+    bool agg_total;      // the last pass also stores the full sum
+    const int32_t* targets;
+    const double* range;
+    float* depth;        // [T][H][W]
+    float* conf;
+    int W, H, dir, p1, p2, lines;
+    double keep_ratio;   // 1 - confidence threshold
+};
+
+// dir 0: left to right along rows, 1: right to left, 2: top to bottom along
+// columns, 3: bottom to top.
+template <int KPL, int MODE>
+__global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
+#pragma clang fp contract(off)
+    constexpr int D = 64 * KPL;
+    constexpr int kBig = 1 << 28;
+    const int lane = threadIdx.x & 63;
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6), ti = blockIdx.y;
+    if (line >= a.lines) return;
+    const bool rows = a.dir < 2, rev = (a.dir & 1) != 0;
+    const int n = rows ? a.W : a.H;
+    const size_t npix = (size_t)a.W * a.H;
+    // pixel of step s: element offset (pixel * D)
+    const long long p0 = rows ? (long long)line * a.W + (rev ? a.W - 1 : 0)
+                              : (long long)(rev ? a.H - 1 : 0) * a.W + line;
+    const long long dp = rows ? (rev ? -1 : 1) : (rev ? -(long long)a.W : (long long)a.W);
+    const uint8_t* cbase = a.cost + (size_t)ti * npix * D;
+    uint16_t* abase = a.agg + (size_t)ti * npix * D;
+    double inv_far = 0.0, h = 0.0;
+    if (MODE == kLast) {
+        const int tv = a.targets[ti];
+        const double d_min = a.range[2 * tv], d_max = a.range[2 * tv + 1];
+        inv_far = 1.0 / d_max;
+        h = (1.0 / d_min - inv_far) / (double)(D - 1);
+    }
+    int L[KPL];
+    constexpr int PF = 4;
+    uint8_t cn[PF][KPL];
+    uint16_t an[PF][KPL];
+    auto load = [&](int s, uint8_t (&c)[KPL], uint16_t (&g)[KPL]) {
+        if (s < n) {
+            const size_t e = (size_t)(p0 + dp * s) * D + lane;
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                c[j] = cbase[e + 64 * j];
+                if (MODE != kFirst) g[j] = abase[e + 64 * j];
+            }
+        }
+    };
+    uint8_t cc[PF][KPL];
+    uint16_t ac[PF][KPL];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) load(q, cc[q], ac[q]);
+    for (int s0 = 0; s0 < n; s0 += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) load(s0 + PF + q, cn[q], an[q]);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int s = s0 + q;
+            if (s >= n) break;
+            if (s == 0) {
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) L[j] = cc[q][j];
+            } else {
+                int m = L[0];
+#pragma unroll
+                for (int j = 1; j < KPL; ++j) m = min(m, L[j]);
+                m = wave_min_i32(m);
+                int dn[KPL], up[KPL];
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) {
+                    dn[j] = __shfl(L[j], (lane + 63) & 63);
+                    up[j] = __shfl(L[j], (lane + 1) & 63);
+                }
+                int Ln[KPL];
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) {
+                    const int km1 = lane > 0 ? dn[j] : (j > 0 ? dn[j - 1] : kBig);
+                    const int kp1 = lane < 63 ? up[j] : (j + 1 < KPL ? up[j + 1] : kBig);
+                    const int best = min(min(L[j], km1 + a.p1), min(kp1 + a.p1, m + a.p2));
+                    Ln[j] = (int)cc[q][j] + best - m;
+                }
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) L[j] = Ln[j];
+            }
+            const long long pix = p0 + dp * s;
+            const size_t e = (size_t)pix * D + lane;
+            if (MODE == kFirst) {
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) abase[e + 64 * j] = (uint16_t)L[j];
+            } else if (MODE == kMiddle) {
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) abase[e + 64 * j] = (uint16_t)(ac[q][j] + L[j]);
+            } else {
+                int S[KPL];
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) S[j] = (int)ac[q][j] + L[j];
+                if (a.agg_total) {
+#pragma unroll
+                    for (int j = 0; j < KPL; ++j) abase[e + 64 * j] = (uint16_t)S[j];
+                }
+                // winner: smallest sum, then smallest plane
+                int key = (S[0] << 8) | lane;
+#pragma unroll
+                for (int j = 1; j < KPL; ++j) key = min(key, (S[j] << 8) | (64 * j + lane));
+                key = wave_min_i32(key);
+                const int s1 = key >> 8, kw = key & 255;
+                int s2 = kBig;
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) {
+                    const int kk = 64 * j + lane;
+                    if (kk - kw >= 2 || kw - kk >= 2) s2 = min(s2, S[j]);
+                }
+                s2 = wave_min_i32(s2);
+                // S(k* - 1) and S(k* + 1) from their lanes
+                const int km = max(kw - 1, 0), kq = min(kw + 1, D - 1);
+                int vm = S[0], vq = S[0];
+#pragma unroll
+                for (int j = 1; j < KPL; ++j) {
+                    if ((km >> 6) == j) vm = S[j];
+                    if ((kq >> 6) == j) vq = S[j];
+                }
+                vm = __shfl(vm, km & 63);
+                vq = __shfl(vq, kq & 63);
+                if (lane == 0) {
+                    const bool keep = kw > 0 && kw < D - 1 && s2 > 0 && (double)s1 <= a.keep_ratio * (double)s2;
+                    float dout = 0.0f;
+                    if (keep) {
+                        const int den = vm - 2 * s1 + vq;
+                        const double delta = den > 0 ? (double)(vm - vq) / (2.0 * (double)den) : 0.0;
+                        dout = (float)(1.0 / (inv_far + ((double)kw + delta) * h));
+                    }
+                    const size_t o = (size_t)ti * npix + (size_t)pix;
+                    a.depth[o] = dout;
+                    a.conf[o] = s2 > 0 ? (float)(1.0 - (double)s1 / (double)s2) : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                cc[q][j] = cn[q][j];
+                ac[q][j] = an[q][j];
+            }
+    }
+}
+
+// ---------------------------------------------------------------- fusion
+
+__global__ __launch_bounds__(256) void k_fuse_count(const float* __restrict__ depth, int W,
+                                                    uint32_t* __restrict__ rowcnt) {
+    const size_t row = blockIdx.x;
+    const float* d = depth + row * W;
+    int c = 0;
+    for (int x = threadIdx.x; x < W; x += 256) c += d[x] > 0.0f;
+    __shared__ int s[256];
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rowcnt[row] = (uint32_t)s[0];
+}
+
+// Exclusive scan of the row counts (one workgroup); total to *total.
+__global__ __launch_bounds__(1024) void k_fuse_scan(uint32_t* __restrict__ rows, int n, uint32_t* __restrict__ total) {
+    __shared__ uint32_t s[1024];
+    uint32_t carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < n ? rows[i] : 0u;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) rows[i] = carry + s[threadIdx.x] - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_fuse_write(const pgs_camera* __restrict__ cams,
+                                                    const int32_t* __restrict__ targets, int W, int H,
+                                                    const float* __restrict__ depth,
+                                                    const uint32_t* __restrict__ rowoff, float* __restrict__ out,
+                                                    uint32_t capacity) {
+    __shared__ uint32_t wcnt[4];
+    const size_t row = blockIdx.x;
+    const int ti = (int)(row / H), y = (int)(row - (size_t)ti * H);
+    const Cam64 c = cam64(cams[targets[ti]]);
+    const float* d = depth + row * W;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t base = rowoff[row];
+    for (int x0 = 0; x0 < W; x0 += 256) {
+        const int x = x0 + threadIdx.x;
+        const float z = x < W ? d[x] : 0.0f;
+        const bool keep = z > 0.0f;
+        const uint64_t b = __ballot(keep);
+        if (lane == 0) wcnt[wv] = (uint32_t)__popcll(b);
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int w = 0; w < 4; ++w) {
+            before += w < wv ? wcnt[w] : 0u;
+            all += wcnt[w];
+        }
+        const uint32_t idx = base + before + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+        if (keep && idx < capacity) {
+            const double zz = z;
+            const double X = zz * (((double)x - c.cx) / c.fx) - c.t[0];
+            const double Y = zz * (((double)y - c.cy) / c.fy) - c.t[1];
+            const double Z = zz - c.t[2];
+            for (int k = 0; k < 3; ++k) out[3 * (size_t)idx + k] = (float)(c.R[k] * X + c.R[3 + k] * Y + c.R[6 + k] * Z);
+        }
+        base += all;
+        __syncthreads();
+    }
+}
+
+inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+pgs_status check_params(const pgs_mvs_params* p, const char* who) {
+    PGS_REQUIRE(p, "%s: null params", who);
+    PGS_REQUIRE(p->n_planes == 64 || p->n_planes == 128 || p->n_planes == 192 || p->n_planes == 256,
+                "%s: n_planes %d not 64, 128, 192 or 256", who, p->n_planes);
+    PGS_REQUIRE(p->p1 >= 0 && p->p2 >= 0 && p->p1 <= 1000 && p->p2 <= 1000, "%s: penalties %d, %d not in 0..1000",
+                who, p->p1, p->p2);
+    PGS_REQUIRE(p->conf_min >= 0.0 && p->conf_min <= 1.0, "%s: conf_min not in [0, 1]", who);
+    return PGS_OK;
+}
+
+template <int KPL>
+pgs_status launch_sgm(SgmArgs a, int n_targets, hipStream_t s) {
+    for (int dir = 0; dir < 4; ++dir) {
+        a.dir = dir;
+        a.lines = dir < 2 ? a.H : a.W;
+        const dim3 grid((a.lines + 3) / 4, n_targets);
+        if (dir == 0) k_sgm<KPL, kFirst><<<grid, 256, 0, s>>>(a);
+        else if (dir < 3) k_sgm<KPL, kMiddle><<<grid, 256, 0, s>>>(a);
+        else k_sgm<KPL, kLast><<<grid, 256, 0, s>>>(a);
+    }
+    PGS_CHECK_LAUNCH("pgs_mvs_sgm");
+    return PGS_OK;
+}
+
+}  // namespace
+
+extern "C" pgs_status pgs_mvs_census(const uint8_t* grey_dev, int32_t n_views, int32_t width, int32_t height,
+                                     uint64_t* census_dev, void* stream) {
+    PGS_REQUIRE(n_views >= 0 && width >= 0 && height >= 0, "pgs_mvs_census: negative size");
+    if (n_views == 0 || width == 0 || height == 0) return PGS_OK;
+    PGS_REQUIRE(grey_dev && census_dev, "pgs_mvs_census: null pointer");
+    PGS_REQUIRE(n_views <= 65535, "pgs_mvs_census: more than 65535 views");
+    const dim3 grid((width + kTile - 1) / kTile, (height + kTile - 1) / kTile, n_views);
+    k_census<<<grid, 256, 0, pgs::as_stream(stream)>>>(grey_dev, width, height, census_dev);
+    PGS_CHECK_LAUNCH("pgs_mvs_census");
+    return PGS_OK;
+}
+
+extern "C" size_t pgs_mvs_range_workspace(int32_t n_views, int32_t n_points) {
+    if (n_views <= 0 || n_points < 0) return 0;
+    return al256((size_t)n_views * n_points * 8) + al256((size_t)n_views * 4);
+}
+
+extern "C" pgs_status pgs_mvs_depth_range(const pgs_camera* cams_dev, int32_t n_views, int32_t width, int32_t height,
+                                          const double* points_dev, int32_t n_points, double* range_dev,
+                                          void* workspace_dev, size_t workspace_bytes, void* stream) {
+    PGS_REQUIRE(n_views >= 0 && n_points >= 0 && width > 0 && height > 0, "pgs_mvs_depth_range: bad size");
+    if (n_views == 0) return PGS_OK;
+    PGS_REQUIRE(n_views <= 65535, "pgs_mvs_depth_range: more than 65535 views");
+    PGS_REQUIRE(cams_dev && range_dev && (points_dev || n_points == 0) && workspace_dev,
+                "pgs_mvs_depth_range: null pointer");
+    PGS_REQUIRE(workspace_bytes >= pgs_mvs_range_workspace(n_views, n_points),
+                "pgs_mvs_depth_range: workspace %zu < %zu", workspace_bytes,
+                pgs_mvs_range_workspace(n_views, n_points));
+    hipStream_t s = pgs::as_stream(stream);
+    uint64_t* keys = static_cast<uint64_t*>(workspace_dev);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace_dev) +
+                                                al256((size_t)n_views * n_points * 8));
+    k_mvs_clear<<<(n_views + 255) / 256, 256, 0, s>>>(cnt, n_views);
+    if (n_points > 0)
+        k_mvs_depths<<<dim3((n_points + 255) / 256, n_views), 256, 0, s>>>(cams_dev, width, height, points_dev,
+                                                                           n_points, keys, cnt);
+    k_mvs_range<<<n_views, 1024, 0, s>>>(n_points, keys, cnt, range_dev);
+    PGS_CHECK_LAUNCH("pgs_mvs_depth_range");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_mvs_select_ref(const pgs_camera* cams_dev, int32_t n_views, const pgs_mvs_params* params,
+                                         int32_t* ref_dev, void* stream) {
+    PGS_REQUIRE(n_views >= 0, "pgs_mvs_select_ref: negative size");
+    if (n_views == 0) return PGS_OK;
+    PGS_REQUIRE(cams_dev && ref_dev && params, "pgs_mvs_select_ref: null pointer");
+    PGS_REQUIRE(params->sigma_b > 0.0 && params->alpha_min > 0.0, "pgs_mvs_select_ref: sigma_b, alpha_min must be > 0");
+    k_mvs_ref<<<(n_views + 63) / 64, 64, 0, pgs::as_stream(stream)>>>(cams_dev, n_views, params->b_target,
+                                                                      params->sigma_b, params->alpha_min, ref_dev);
+    PGS_CHECK_LAUNCH("pgs_mvs_select_ref");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_mvs_cost(const pgs_camera* cams_dev, int32_t width, int32_t height,
+                                   const uint64_t* census_dev, const int32_t* targets_dev, int32_t n_targets,
+                                   const int32_t* ref_dev, const double* range_dev, const pgs_mvs_params* params,
+                                   uint8_t* cost_dev, void* stream) {
+    if (pgs_status st = check_params(params, "pgs_mvs_cost")) return st;
+    PGS_REQUIRE(n_targets >= 0 && width > 0 && height > 0, "pgs_mvs_cost: bad size");
+    if (n_targets == 0) return PGS_OK;
+    PGS_REQUIRE(n_targets <= 65535, "pgs_mvs_cost: more than 65535 targets");
+    PGS_REQUIRE(cams_dev && census_dev && targets_dev && ref_dev && range_dev && cost_dev, "pgs_mvs_cost: null pointer");
+    const int D = params->n_planes;
+    const long long npix = (long long)width * height;
+    const long long blocks = (npix * D + 255) / 256;
+    PGS_REQUIRE(blocks < (1ll << 31), "pgs_mvs_cost: image too large");
+    hipStream_t s = pgs::as_stream(stream);
+    const dim3 grid((unsigned)blocks, n_targets);
+    switch (D) {
+        case 64: k_cost<64><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
+        case 128: k_cost<128><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
+        case 192: k_cost<192><<<dim3((unsigned)npix, n_targets), 192, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
+        default: k_cost<256><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
+    }
+    PGS_CHECK_LAUNCH("pgs_mvs_cost");
+    return PGS_OK;
+}
+
+extern "C" size_t pgs_mvs_sgm_workspace(int32_t n_targets, int32_t width, int32_t height, int32_t n_planes) {
+    if (n_targets <= 0 || width <= 0 || height <= 0 || n_planes <= 0) return 0;
+    return al256((size_t)n_targets * width * height * n_planes * 2);
+}
+
+extern "C" pgs_status pgs_mvs_sgm(const uint8_t* cost_dev, int32_t width, int32_t height, const int32_t* targets_dev,
+                                  int32_t n_targets, const double* range_dev, const pgs_mvs_params* params,
+                                  float* depth_dev, float* conf_dev, uint16_t* agg_out_dev, void* workspace_dev,
+                                  size_t workspace_bytes, void* stream) {
+    if (pgs_status st = check_params(params, "pgs_mvs_sgm")) return st;
+    PGS_REQUIRE(n_targets >= 0 && width > 0 && height > 0, "pgs_mvs_sgm: bad size");
+    if (n_targets == 0) return PGS_OK;
+    PGS_REQUIRE(n_targets <= 65535, "pgs_mvs_sgm: more than 65535 targets");
+    PGS_REQUIRE(cost_dev && targets_dev && range_dev && depth_dev && conf_dev, "pgs_mvs_sgm: null pointer");
+    PGS_REQUIRE(agg_out_dev || (workspace_dev && workspace_bytes >= pgs_mvs_sgm_workspace(n_targets, width, height,
+                                                                                        params->n_planes)),
+                "pgs_mvs_sgm: workspace too small");
+    SgmArgs a{};
+    a.cost = cost_dev;
+    a.agg = agg_out_dev ? agg_out_dev : static_cast<uint16_t*>(workspace_dev);
+    a.agg_total = agg_out_dev != nullptr;
+    a.targets = targets_dev;
+    a.range = range_dev;
+    a.depth = depth_dev;
+    a.conf = conf_dev;
+    a.W = width;
+    a.H = height;
+    a.p1 = params->p1;
+    a.p2 = params->p2;
+    a.keep_ratio = 1.0 - params->conf_min;
+    hipStream_t s = pgs::as_stream(stream);
+    switch (params->n_planes) {
+        case 64: return launch_sgm<1>(a, n_targets, s);
+        case 128: return launch_sgm<2>(a, n_targets, s);
+        case 192: return launch_sgm<3>(a, n_targets, s);
+        default: return launch_sgm<4>(a, n_targets, s);
+    }
+}
+
+extern "C" size_t pgs_mvs_fuse_workspace(int32_t n_targets, int32_t height) {
+    if (n_targets <= 0 || height <= 0) return 0;
+    return al256((size_t)n_targets * height * 4);
+}
+
+extern "C" pgs_status pgs_mvs_fuse(const pgs_camera* cams_dev, const int32_t* targets_dev, int32_t n_targets,
+                                   int32_t width, int32_t height, const float* depth_dev, float* points_dev,
+                                   uint32_t capacity, uint32_t* count_dev, void* workspace_dev,
+                                   size_t workspace_bytes, void* stream) {
+    PGS_REQUIRE(n_targets >= 0 && width > 0 && height > 0, "pgs_mvs_fuse: bad size");
+    PGS_REQUIRE(count_dev, "pgs_mvs_fuse: null count");
+    hipStream_t s = pgs::as_stream(stream);
+    if (n_targets == 0) {
+        k_mvs_clear<<<1, 256, 0, s>>>(count_dev, 1);
+        PGS_CHECK_LAUNCH("pgs_mvs_fuse");
+        return PGS_OK;
+    }
+    PGS_REQUIRE(cams_dev && targets_dev && depth_dev && (points_dev || capacity == 0) && workspace_dev,
+                "pgs_mvs_fuse: null pointer");
+    PGS_REQUIRE(workspace_bytes >= pgs_mvs_fuse_workspace(n_targets, height), "pgs_mvs_fuse: workspace too small");
+    const long long rows = (long long)n_targets * height;
+    PGS_REQUIRE(rows < (1ll << 31), "pgs_mvs_fuse: too many rows");
+    uint32_t* rowcnt = static_cast<uint32_t*>(workspace_dev);
+    k_fuse_count<<<(unsigned)rows, 256, 0, s>>>(depth_dev, width, rowcnt);
+    k_fuse_scan<<<1, 1024, 0, s>>>(rowcnt, (int)rows, count_dev);
+    k_fuse_write<<<(unsigned)rows, 256, 0, s>>>(cams_dev, targets_dev, width, height, depth_dev, rowcnt, points_dev,
+                                                capacity);
+    PGS_CHECK_LAUNCH("pgs_mvs_fuse");
+    return PGS_OK;
+}

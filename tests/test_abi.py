@@ -106,3 +106,25 @@ def test_ba_rejects_bad_problems_before_any_launch():
     assert lib.pgs_ba_step(ctypes.byref(pb), None, None, None, -1.0, None, None, None, 0, None) == \
         _lib.PGS_ERR_INVALID_ARG
     assert lib.pgs_ba_workspace(60, 1000, 5000) > 0
+
+
+def test_mvs_rejects_bad_arguments_before_any_launch():
+    lib = _lib.load()
+    p = _lib.PgsMvsParams(100, 4, 32, 0.4, 0.5, 0.25, 0.1)
+    assert lib.pgs_mvs_cost(None, 64, 48, None, None, 1, None, None, ctypes.byref(p), None,
+                            None) == _lib.PGS_ERR_INVALID_ARG
+    assert b"n_planes" in lib.pgs_last_error()
+    p.n_planes, p.p2 = 64, 5000
+    assert lib.pgs_mvs_sgm(None, 64, 48, None, 1, None, ctypes.byref(p), None, None, None, None, 0,
+                           None) == _lib.PGS_ERR_INVALID_ARG
+    assert b"penalties" in lib.pgs_last_error()
+    p.p2 = 32
+    assert lib.pgs_mvs_sgm(None, 64, 48, None, 1, None, ctypes.byref(p), None, None, None, None, 0,
+                           None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_mvs_census(None, 1, 64, 48, None, None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_mvs_depth_range(None, 2, 0, 48, None, 0, None, None, 0, None) == _lib.PGS_ERR_INVALID_ARG
+    p.sigma_b = 0.0
+    assert lib.pgs_mvs_select_ref(ctypes.c_void_p(8), 3, ctypes.byref(p), ctypes.c_void_p(8),
+                                  None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_mvs_range_workspace(3, 10) >= 3 * 10 * 8 + 12
+    assert lib.pgs_mvs_sgm_workspace(2, 8, 4, 64) >= 2 * 8 * 4 * 64 * 2

@@ -1,0 +1,211 @@
+"""GPU parity of the multi-view stereo path (pgs_mvs_* through the C ABI)
+against the FP64 oracle, on ray-cast views of the seeded scene.
+
+Integer results are compared bit for bit: Census strings, the depth range
+(float64 from unfused operations in the same order, so equal to the last
+bit), the cost volume, the SGM sums, the winner and the kept mask.  Float
+outputs of float64 arithmetic rounded to float32 (depth, confidence, fused
+points) are compared at 1e-6 relative.  The reference choice is compared
+where it is unique: the GPU's choice must reach the oracle's best score
+(within 1e-12), and equal the oracle's when the runner-up is more than 1e-9
+behind (on a ring the two neighbours tie up to rounding).  Inputs the GPU
+path consumes downstream of a choice (ranges, references, depth maps for
+fusion) are the oracle's."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_helpers import say
+from oracle import mvs as omvs
+
+pytestmark = pytest.mark.gpu
+
+
+def _views(W, H, idx, seed=5, n=60):
+    scene = synth.spheres_planes_scene(0)
+    cams = synth.ring_cameras(n, W, H)
+    g, dep = synth.textured_views(scene, [cams[i] for i in idx], seed=seed)
+    pts = synth.sample_surface(scene, 5000, 1)[0]
+    return scene, cams, g, dep, pts
+
+
+def _params(D=64, **kw):
+    from paper_2601_17354_amd.mvs import MVSParams
+    return MVSParams(n_planes=D, **kw)
+
+
+def test_census_bit_exact():
+    from paper_2601_17354_amd import mvs
+    _, _, g, _, _ = _views(160, 120, [0, 1])
+    rnd = np.random.default_rng(0).integers(0, 256, (1, 23, 37)).astype(np.uint8)
+    rnd[0, 5:9, 4:20] = 91
+    for imgs in (g, rnd):
+        V, H, W = imgs.shape
+        out = torch.empty((V, H, W), dtype=torch.int64, device="cuda")
+        mvs.pgs_mvs_census(torch.as_tensor(imgs, device="cuda"), out)
+        got = out.cpu().numpy().view(np.uint64)
+        for v in range(V):
+            np.testing.assert_array_equal(got[v], omvs.census(imgs[v]))
+
+
+def test_depth_range_bit_exact():
+    from paper_2601_17354_amd import mvs
+    W, H = 320, 240
+    cams = synth.ring_cameras(60, W, H)
+    pts = synth.sample_surface(synth.spheres_planes_scene(0), 20000, 1)[0]
+    cd = mvs.cameras_tensor(cams)
+    rng = torch.empty((60, 2), dtype=torch.float64, device="cuda")
+    mvs.pgs_mvs_depth_range(cd, 60, W, H, torch.as_tensor(pts, device="cuda"), rng)
+    got = rng.cpu().numpy()
+    for v in range(60):
+        want = omvs.depth_range(cams[v], pts)
+        assert tuple(got[v]) == want, (v, got[v], want)
+    # no point in view: (0, 0); a single point: both quantiles are its depth
+    far = np.array([[0.0, 0.8, 40.0], [0.0, 0.8, -40.0]])
+    one = np.array([[0.0, 0.3, 0.0]])
+    for P in (far, one):
+        mvs.pgs_mvs_depth_range(cd, 60, W, H, torch.as_tensor(P, device="cuda"), rng)
+        got = rng.cpu().numpy()
+        for v in (0, 17):
+            assert tuple(got[v]) == omvs.depth_range(cams[v], P)
+
+
+def test_reference_choice():
+    from paper_2601_17354_amd import mvs
+    for n, pr in [(60, _params(b_target=0.5, sigma_b=0.25)), (24, _params(b_target=2.0, sigma_b=0.3)),
+                  (60, _params(b_target=0.0, sigma_b=1e3, alpha_min=np.radians(1.0)))]:
+        cams = synth.ring_cameras(n, 64, 48)
+        ref = torch.empty(n, dtype=torch.int32, device="cuda")
+        mvs.pgs_mvs_select_ref(mvs.cameras_tensor(cams), n, pr, ref)
+        got = ref.cpu().numpy()
+        for t in range(n):
+            want, sc = omvs.select_reference(cams, t, pr.b_target, pr.sigma_b, pr.alpha_min)
+            best = sc[want]
+            assert sc[got[t]] >= best * (1 - 1e-12), (t, got[t], want)
+            second = np.sort(sc)[-2]
+            if best - second > 1e-9 * best:
+                assert got[t] == want
+
+
+def _gpu_depth(cams, g, targets, refs, ranges, pr, want_agg=True):
+    from paper_2601_17354_amd import mvs
+    V, H, W = g.shape
+    cd = mvs.cameras_tensor(cams)
+    cen = torch.empty((V, H, W), dtype=torch.int64, device="cuda")
+    mvs.pgs_mvs_census(torch.as_tensor(g, device="cuda"), cen)
+    tg = torch.as_tensor(np.asarray(targets, np.int32), device="cuda")
+    rf = torch.as_tensor(np.asarray(refs, np.int32), device="cuda")
+    rg = torch.as_tensor(np.asarray(ranges, np.float64), device="cuda")
+    T, D = len(targets), pr.n_planes
+    cost = torch.empty((T, H, W, D), dtype=torch.uint8, device="cuda")
+    mvs.pgs_mvs_cost(cd, W, H, cen, tg, rf, rg, pr, cost)
+    depth = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    conf = torch.empty_like(depth)
+    agg = torch.empty((T, H, W, D), dtype=torch.int16, device="cuda") if want_agg else None
+    mvs.pgs_mvs_sgm(cost, tg, rg, pr, depth, conf, agg_out=agg)
+    torch.cuda.synchronize()
+    return (cost.cpu().numpy(), agg.cpu().numpy().view(np.uint16) if want_agg else None, depth.cpu().numpy(),
+            conf.cpu().numpy())
+
+
+@pytest.mark.parametrize("W,H,D", [(160, 120, 64), (101, 77, 128), (96, 70, 192), (64, 40, 256)])
+def test_cost_sgm_depth_bit_exact(W, H, D):
+    say(f"[mvs] {W}x{H} planes {D}")
+    _, cams, g, dep, pts = _views(W, H, [0, 1, 2, 3])
+    cams = cams[:4]
+    pr = _params(D, p1=4, p2=32)
+    targets = [2, 0]
+    refs = [0] * len(cams)
+    refs[2], refs[0] = 3, 1
+    ranges = np.zeros((len(cams), 2))
+    for t in targets:
+        ranges[t] = omvs.depth_range(cams[t], pts)
+    cost, agg, depth, conf = _gpu_depth(cams, g, targets, refs, ranges, pr)
+    for i, t in enumerate(targets):
+        r = refs[t]
+        C = omvs.cost_volume(omvs.census(g[t]), omvs.census(g[r]), cams[t], cams[r], ranges[t][0], ranges[t][1], D)
+        np.testing.assert_array_equal(cost[i], C)
+        S = omvs.sgm(C, pr.p1, pr.p2)
+        np.testing.assert_array_equal(agg[i].astype(np.int64), S)
+        d, c, k = omvs.winner(S, ranges[t][0], ranges[t][1], pr.conf_min)
+        np.testing.assert_array_equal(depth[i] > 0, d > 0)
+        np.testing.assert_allclose(depth[i], d, rtol=1e-6, atol=0)
+        np.testing.assert_allclose(conf[i], c, rtol=1e-6, atol=1e-7)
+        say(f"[mvs] target {t}: kept {(d > 0).mean():.3f}")
+
+
+def test_empty_range_and_penalty_free_sgm():
+    _, cams, g, _, pts = _views(64, 48, [0, 1])
+    cams = cams[:2]
+    pr = _params(64, p1=0, p2=0)
+    ranges = np.zeros((2, 2))
+    ranges[1] = omvs.depth_range(cams[1], pts)
+    cost, agg, depth, _ = _gpu_depth(cams, g, [0, 1], [1, 0], ranges, pr)
+    assert (cost[0] == omvs.COST_OUT).all() and not (depth[0] > 0).any()
+    np.testing.assert_array_equal(agg[1].astype(np.int64), 4 * cost[1].astype(np.int64))
+
+
+def test_fuse_matches_oracle():
+    from paper_2601_17354_amd import mvs
+    W, H = 96, 72
+    scene = synth.spheres_planes_scene(0)
+    cams = synth.ring_cameras(60, W, H)
+    _, dep = synth.textured_views(scene, [cams[4], cams[9]], seed=1)
+    dep[0][::3] = 0.0                                          # holes
+    targets = [4, 9]
+    cd = mvs.cameras_tensor(cams)
+    want = np.concatenate([omvs.fuse(cams[4], dep[0]), omvs.fuse(cams[9], dep[1])])
+    for cap in (want.shape[0] + 5, want.shape[0] // 2):
+        pts = torch.full((cap, 3), -7.0, dtype=torch.float32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mvs.pgs_mvs_fuse(cd, torch.as_tensor(np.int32(targets), device="cuda"),
+                         torch.as_tensor(dep, device="cuda"), pts, cnt)
+        assert int(cnt.item()) == want.shape[0]
+        got = pts.cpu().numpy()
+        n = min(cap, want.shape[0])
+        np.testing.assert_allclose(got[:n], want[:n], rtol=1e-6, atol=1e-6)
+        assert (got[n:] == -7.0).all()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_pipeline():
+    """The bench workload's shape: 960x720 views, 128 planes, the references
+    and ranges the pipeline chooses, cost volume and SGM sums bit-exact over
+    the whole image and the depth maps against the oracle."""
+    from paper_2601_17354_amd import mvs
+    W, H, D = 960, 720, 128
+    scene = synth.spheres_planes_scene(0)
+    cams = synth.ring_cameras(60, W, H)
+    pr = _params(D, p1=4, p2=32)
+    targets = [0, 31]
+    refs = {}
+    for t in targets:
+        refs[t], _ = omvs.select_reference(cams, t, pr.b_target, pr.sigma_b, pr.alpha_min)
+    idx = sorted(set(targets) | set(refs.values()))
+    say(f"[mvs full] ray casting views {idx}")
+    g_sub, _ = synth.textured_views(scene, [cams[i] for i in idx], seed=5)
+    g = np.zeros((60, H, W), np.uint8)
+    g[idx] = g_sub
+    pts = synth.sample_surface(scene, 100_000, 1)[0]
+    ranges = np.zeros((60, 2))
+    for t in targets:
+        ranges[t] = omvs.depth_range(cams[t], pts)
+    ref_all = np.zeros(60, np.int32)
+    for t in targets:
+        ref_all[t] = refs[t]
+    say("[mvs full] GPU")
+    cost, agg, depth, conf = _gpu_depth(cams, g, targets, ref_all, ranges, pr)
+    for i, t in enumerate(targets):
+        say(f"[mvs full] oracle target {t} ref {refs[t]}")
+        ct, cr = omvs.census(g[t]), omvs.census(g[refs[t]])
+        C = np.concatenate([omvs.cost_volume(ct, cr, cams[t], cams[refs[t]], ranges[t][0], ranges[t][1], D,
+                                             rows=np.arange(y0, min(y0 + 90, H))) for y0 in range(0, H, 90)])
+        np.testing.assert_array_equal(cost[i], C)
+        S = omvs.sgm(C, pr.p1, pr.p2)
+        np.testing.assert_array_equal(agg[i].astype(np.int64), S)
+        d, c, _ = omvs.winner(S, ranges[t][0], ranges[t][1], pr.conf_min)
+        np.testing.assert_array_equal(depth[i] > 0, d > 0)
+        np.testing.assert_allclose(depth[i], d, rtol=1e-6, atol=0)
+        say(f"[mvs full] target {t}: kept {(d > 0).mean():.3f}")
