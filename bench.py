@@ -46,6 +46,8 @@ def parse():
                          "(for rocprofv3)")
     ap.add_argument("--no-ba", action="store_true", help="skip the bundle-adjustment measurement")
     ap.add_argument("--ba-only", action="store_true", help="only the bundle-adjustment measurement")
+    ap.add_argument("--no-mvs", action="store_true", help="skip the multi-view stereo measurement")
+    ap.add_argument("--mvs-only", action="store_true", help="only the multi-view stereo measurement")
     ap.add_argument("--no-cfg2", action="store_true",
                     help="skip the 100k / SH 3 / 1024x768 cached-vs-recompute comparison")
     ap.add_argument("--profile", action="store_true",
@@ -54,7 +56,7 @@ def parse():
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
         args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = args.no_cfg2 = True
-        args.no_ba = True
+        args.no_ba = args.no_mvs = True
     return args
 
 
@@ -253,6 +255,101 @@ def ba_runs(n_cams=60, n_points=100_000, iters=15, cpu_points=3_000):
     spl.spsolve(A, b[free])
     res["cpu_oracle_step_s"] = _t.perf_counter() - t0
     res["cpu_oracle_problem"] = f"{n_cams} cameras, {trs['P0'].shape[0]} points, 1 thread"
+    return res
+
+
+def mvs_runs(width=960, height=720, n_targets=8, iters=5):
+    """Single-reference MVS on ray-cast views of the seeded scene (60 ring
+    cameras at width x height, 128 planes, 100k scene points standing in for
+    the refined sparse cloud): per-stage time with HIP events (Census of all
+    60 views, depth ranges, reference choice, then cost volume, SGM and
+    fusion for n_targets target views), the depth maps' accuracy against the
+    exact ray-cast depth, and the oracle's per-view chain on a smaller view
+    scaled by pixels x planes."""
+    import torch
+    import synth
+    from paper_2601_17354_amd import mvs
+    scene = synth.spheres_planes_scene(0)
+    cams = synth.ring_cameras(60, width, height)
+    pr = mvs.MVSParams()
+    m = mvs.MVS(cams, width, height, pr, max_targets=n_targets)
+    pts = torch.as_tensor(synth.sample_surface(scene, 100_000, 1)[0], device="cuda")
+    ref = torch.empty(60, dtype=torch.int32, device="cuda")
+    mvs.pgs_mvs_select_ref(m.cams_dev, 60, pr, ref)
+    refs = ref.cpu().numpy()
+    targets = [int(round(i * 60 / n_targets)) % 60 for i in range(n_targets)]
+    need = sorted(set(targets) | {int(refs[t]) for t in targets})
+    g_sub, d_sub = synth.textured_views(scene, [cams[i] for i in need], seed=5)
+    grey = np.zeros((60, height, width), np.uint8)
+    grey[need] = g_sub
+    gt = {v: d_sub[i] for i, v in enumerate(need)}
+    grey_d = torch.as_tensor(grey, device="cuda")
+    tg = torch.as_tensor(np.int32(targets), device="cuda")
+    cap = n_targets * width * height
+    cloud = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+    from paper_2601_17354_amd import _lib
+    rng_ws = torch.empty(_lib.load().pgs_mvs_range_workspace(60, pts.shape[0]), dtype=torch.uint8, device="cuda")
+    stages = ["census", "range", "reference", "cost", "sgm", "fuse"]
+
+    def run(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        mvs.pgs_mvs_census(grey_d, m.census)
+        mark(1)
+        mvs.pgs_mvs_depth_range(m.cams_dev, 60, width, height, pts, m.range, rng_ws)
+        mark(2)
+        mvs.pgs_mvs_select_ref(m.cams_dev, 60, pr, m.ref)
+        mark(3)
+        mvs.pgs_mvs_cost(m.cams_dev, width, height, m.census, tg, m.ref, m.range, pr, m.cost[:n_targets])
+        mark(4)
+        mvs.pgs_mvs_sgm(m.cost[:n_targets], tg, m.range, pr, m.depth[:n_targets], m.conf[:n_targets],
+                        workspace=m.sgm_ws)
+        mark(5)
+        m.fuse(tg, cloud)
+        mark(6)
+
+    for _ in range(2):
+        run()
+    torch.cuda.synchronize()
+    t = {k: 0.0 for k in stages}
+    for _ in range(iters):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        run(ev)
+        torch.cuda.synchronize()
+        for i, k in enumerate(stages):
+            t[k] += ev[i].elapsed_time(ev[i + 1]) / iters
+    depth = m.depth[:n_targets].cpu().numpy()
+    kept, rel = [], []
+    for i, v in enumerate(targets):
+        ok = (depth[i] > 0) & (gt[v] > 0)
+        kept.append(float((depth[i] > 0).mean()))
+        rel.append(np.abs(depth[i][ok] - gt[v][ok]) / gt[v][ok])
+    rel = np.concatenate(rel)
+    npix, D = width * height, pr.n_planes
+    cost_bytes = n_targets * (npix * D + 16 * npix)
+    sgm_bytes = n_targets * (16 * npix * D + 8 * npix)
+    per_view = (t["cost"] + t["sgm"] + t["fuse"]) / n_targets + (t["census"] + t["range"] + t["reference"]) / 60
+    res = {"workload": f"60 ring views {width}x{height} (ray-cast, textured), {D} planes, Census 7x7, SGM 4 paths "
+                       f"P1={pr.p1} P2={pr.p2}, {n_targets} target views, 100k sparse points",
+           "ms_per_target_view": per_view, "views_per_s": 1e3 / per_view, "ms": t,
+           "cost_GBps": cost_bytes / (t["cost"] * 1e-3) / 1e9, "sgm_GBps": sgm_bytes / (t["sgm"] * 1e-3) / 1e9,
+           "algorithmic_bytes": {"cost": cost_bytes, "sgm": sgm_bytes},
+           "references": {str(v): int(refs[v]) for v in targets},
+           "kept_fraction": float(np.mean(kept)), "median_rel_depth_error": float(np.median(rel)),
+           "within_1pct": float((rel < 0.01).mean()), "fused_points": int(m.count.item())}
+    # the oracle's chain (Census, cost volume, SGM, winner) on a 320x240 view
+    import time as _t
+    from oracle import mvs as omvs
+    cs = synth.ring_cameras(60, 320, 240)
+    gs, _ = synth.textured_views(scene, [cs[0], cs[1]], seed=5)
+    lo, hi = omvs.depth_range(cs[0], pts.cpu().numpy())
+    t0 = _t.perf_counter()
+    omvs.depth_map(gs[0], gs[1], cs[0], cs[1], lo, hi, D, pr.p1, pr.p2)
+    dt = _t.perf_counter() - t0
+    res["cpu_oracle_s_per_view"] = dt * npix / (320 * 240)
+    res["cpu_oracle_sample"] = f"one 320x240 view, {D} planes ({dt:.1f} s), scaled by pixels to {width}x{height}"
     return res
 
 
@@ -534,6 +631,9 @@ def main():
     if args.ba_only:
         print(json.dumps({"bundle_adjustment": ba_runs()}))
         return
+    if args.mvs_only:
+        print(json.dumps({"multi_view_stereo": mvs_runs()}))
+        return
     if args.batched_only:
         r = batched_runs(args.batched_gaussians, steps=6, warmup=2, tuned={"tile": [16, 16], "batch": 256,
                                                                            "table": []}, compare=False)
@@ -637,6 +737,10 @@ def main():
         log("bundle adjustment: 60 cameras, 100k points")
         out["bundle_adjustment"] = ba_runs()
         log(f"bundle adjustment: {out['bundle_adjustment']}")
+    if not args.no_mvs:
+        log("multi-view stereo: 60 views 960x720, 128 planes, 8 targets")
+        out["multi_view_stereo"] = mvs_runs()
+        log(f"multi-view stereo: {out['multi_view_stereo']}")
     log("seeding network alone")
     out["seed_network"] = mlp_runs()
     log(f"seed network: {out['seed_network']}")

@@ -5,10 +5,10 @@
 //
 // Kernels:
 //   k_mvs_depths / k_mvs_range  camera depths of the sparse points that
-//       project into each view, appended per view (wave-aggregated atomics),
-//       then per view (one workgroup) the ranks that define the 5% and 95%
-//       quantiles found by radix selection over the float64 bit patterns;
-//       range = [0.5 q_.05, 1.5 q_.95];
+//       project into each view as float64 bit patterns (all ones for the
+//       others), then per view (one workgroup) the ranks that define the 5%
+//       and 95% quantiles found by radix selection; range =
+//       [0.5 q_.05, 1.5 q_.95];
 //   k_mvs_ref     per target view the candidate maximising
 //       exp(-(b - b_target)^2 / (2 sigma_b^2)) max(alpha / alpha_min, 1);
 //   k_census      7 x 7 Census (48 bits) from a 22 x 22 LDS tile;
@@ -17,11 +17,13 @@
 //       contraction (the nearest-pixel decision is reproducible), Hamming
 //       distance of the Census strings; cost volume [y][x][plane] bytes;
 //   k_sgm<KPL, MODE>  one wave per image line and direction: lane l holds
-//       planes l, l + 64, ... ; per step the previous costs' minimum is a
-//       wave reduction and the neighbouring planes come from lane shuffles;
-//       the first pass writes the path cost, the middle ones add to it, the
-//       last adds its own and takes the winner, the confidence and the
-//       refined depth for each pixel without storing the sum;
+//       the KPL consecutive planes KPL l .. (one load of its costs and sums
+//       per step, prefetched 8 steps ahead); per step the previous costs'
+//       minimum is a DPP wave reduction and the neighbouring planes come
+//       from DPP wave shifts; the first pass writes the path cost, the middle
+//       ones add to it, the last adds its own and takes the winner and the
+//       confidence-test sums per pixel (lane = step mod 64), turned into
+//       refined depths 64 pixels at a time, without storing the sum;
 //   k_fuse_*      per-row counts, one scan over rows and the back-projection
 //       of the kept pixels in row-major order.
 
@@ -91,94 +93,142 @@ __global__ __launch_bounds__(256) void k_mvs_clear(uint32_t* __restrict__ p, int
     if (i < n) p[i] = 0u;
 }
 
+// Key of point j in view v: the float64 bit pattern of its camera depth when
+// it projects into the view (positive, so the patterns order like the
+// values), all ones otherwise (after every valid key).
 __global__ __launch_bounds__(256) void k_mvs_depths(const pgs_camera* __restrict__ cams, int W, int H,
                                                     const double* __restrict__ pts, int M,
-                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ cnt) {
+                                                    uint64_t* __restrict__ keys) {
 #pragma clang fp contract(off)
-    const int v = blockIdx.y, j = blockIdx.x * 256 + threadIdx.x, lane = threadIdx.x & 63;
-    bool in = false;
-    double z = 0.0;
-    if (j < M) {
-        const Cam64 c = cam64(cams[v]);
-        const double P0 = pts[3 * (size_t)j], P1 = pts[3 * (size_t)j + 1], P2 = pts[3 * (size_t)j + 2];
-        const double x = c.R[0] * P0 + c.R[1] * P1 + c.R[2] * P2 + c.t[0];
-        const double y = c.R[3] * P0 + c.R[4] * P1 + c.R[5] * P2 + c.t[1];
-        z = c.R[6] * P0 + c.R[7] * P1 + c.R[8] * P2 + c.t[2];
-        const double u = c.fx * (x / z) + c.cx, w = c.fy * (y / z) + c.cy;
-        in = z > 0.0 && u >= -0.5 && u < (double)W - 0.5 && w >= -0.5 && w < (double)H - 0.5;
-    }
-    const uint64_t b = __ballot(in);
-    if (b == 0) return;
-    const int leader = __ffsll((long long)b) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&cnt[v], (uint32_t)__popcll(b));
-    base = __shfl(base, leader);
-    if (in) {
-        const uint64_t below = b & ((1ull << lane) - 1ull);
-        keys[(size_t)v * M + base + __popcll(below)] = (uint64_t)__double_as_longlong(z);
-    }
+    const int v = blockIdx.y, j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= M) return;
+    const Cam64 c = cam64(cams[v]);
+    const double P0 = pts[3 * (size_t)j], P1 = pts[3 * (size_t)j + 1], P2 = pts[3 * (size_t)j + 2];
+    const double x = c.R[0] * P0 + c.R[1] * P1 + c.R[2] * P2 + c.t[0];
+    const double y = c.R[3] * P0 + c.R[4] * P1 + c.R[5] * P2 + c.t[1];
+    const double z = c.R[6] * P0 + c.R[7] * P1 + c.R[8] * P2 + c.t[2];
+    const double u = c.fx * (x / z) + c.cx, w = c.fy * (y / z) + c.cy;
+    const bool in = z > 0.0 && u >= -0.5 && u < (double)W - 0.5 && w >= -0.5 && w < (double)H - 0.5;
+    keys[(size_t)v * M + j] = in ? (uint64_t)__double_as_longlong(z) : ~0ull;
 }
 
-// The rank-th smallest of n keys (one workgroup), by radix selection over
-// 8-bit digits from the most significant.
-__device__ uint64_t select_rank(const uint64_t* __restrict__ keys, uint32_t n, uint32_t rank, uint32_t* hist,
-                                uint64_t* s_prefix, uint32_t* s_rank) {
-    const int t = threadIdx.x;
+struct RangeLds {
+    uint32_t hist[256];
+    uint32_t wsum[16];
+    uint64_t wmin[16];
+    uint64_t prefix;
+    uint32_t rank;
+};
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, RangeLds& L) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) L.wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += L.wsum[w];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ uint64_t block_min_u64(uint64_t v, RangeLds& L) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t u = ((uint64_t)(uint32_t)__shfl_xor((int)(v >> 32), o) << 32) |
+                           (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+        v = u < v ? u : v;
+    }
+    if ((threadIdx.x & 63) == 0) L.wmin[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint64_t m = ~0ull;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = L.wmin[w] < m ? L.wmin[w] : m;
+    __syncthreads();
+    return m;
+}
+
+// The rank-th smallest of the keys (one workgroup), by radix selection over
+// 8-bit digits from the most significant; the digit is found by one wave
+// (four bins per lane, a lane prefix sum and a ballot).
+__device__ uint64_t select_rank(const uint64_t* __restrict__ keys, uint32_t n, uint32_t rank, RangeLds& L) {
+    const int t = threadIdx.x, lane = t & 63;
     uint64_t prefix = 0, mask = 0;
     uint32_t r = rank;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        if (t < 256) hist[t] = 0u;
+        if (t < 256) L.hist[t] = 0u;
         __syncthreads();
         for (uint32_t i = t; i < n; i += blockDim.x) {
             const uint64_t k = keys[i];
-            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+            if ((k & mask) == prefix) atomicAdd(&L.hist[(k >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (t == 0) {
-            uint32_t acc = 0, d = 255;
-            for (uint32_t q = 0; q < 256; ++q) {
-                if (acc + hist[q] > r) {
-                    d = q;
-                    break;
-                }
-                acc += hist[q];
+        if (t < 64) {
+            const uint32_t h0 = L.hist[4 * lane], h1 = L.hist[4 * lane + 1], h2 = L.hist[4 * lane + 2],
+                           h3 = L.hist[4 * lane + 3];
+            const uint32_t own = h0 + h1 + h2 + h3;
+            uint32_t inc = own;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(inc, o);
+                if (lane >= o) inc += u;
             }
-            *s_prefix = prefix | ((uint64_t)d << shift);
-            *s_rank = r - acc;
+            const uint32_t exc = inc - own;
+            const uint64_t hit = __ballot(inc > r);
+            const int q = __ffsll((long long)hit) - 1;  // first lane whose bins reach past r
+            if (lane == q) {
+                uint32_t acc = exc, d = 4 * lane + 3;
+                const uint32_t hs[4] = {h0, h1, h2, h3};
+                for (int e = 0; e < 4; ++e) {
+                    if (acc + hs[e] > r) {
+                        d = 4 * lane + e;
+                        break;
+                    }
+                    acc += hs[e];
+                }
+                L.prefix = prefix | ((uint64_t)d << shift);
+                L.rank = r - acc;
+            }
         }
         __syncthreads();
-        prefix = *s_prefix;
-        r = *s_rank;
+        prefix = L.prefix;
+        r = L.rank;
         mask |= 255ull << shift;
         __syncthreads();
     }
     return prefix;
 }
 
-__device__ double quantile_of(const uint64_t* keys, uint32_t n, double p, uint32_t* hist, uint64_t* s_prefix,
-                              uint32_t* s_rank) {
+// q(p) = z_i + (z_{i+1} - z_i)(h - i), h = (n - 1) p: z_i by selection, z_{i+1}
+// is z_i when more than i + 1 keys are <= z_i, else the smallest key above.
+__device__ double quantile_of(const uint64_t* keys, uint32_t M, uint32_t n, double p, RangeLds& L) {
 #pragma clang fp contract(off)
     const double h = (double)(n - 1) * p;
     const uint32_t i = (uint32_t)floor(h);
-    const double zi = __longlong_as_double((long long)select_rank(keys, n, i, hist, s_prefix, s_rank));
+    const uint64_t ki = select_rank(keys, M, i, L);
+    const double zi = __longlong_as_double((long long)ki);
     if (i + 1 >= n) return zi;
-    const double zj = __longlong_as_double((long long)select_rank(keys, n, i + 1, hist, s_prefix, s_rank));
+    uint32_t le = 0;
+    uint64_t above = ~0ull;
+    for (uint32_t e = threadIdx.x; e < M; e += blockDim.x) {
+        const uint64_t k = keys[e];
+        le += k <= ki;
+        if (k > ki && k < above) above = k;
+    }
+    le = block_sum_u32(le, L);
+    above = block_min_u64(above, L);
+    const double zj = le >= i + 2 ? zi : __longlong_as_double((long long)above);
     return zi + (zj - zi) * (h - (double)i);
 }
 
 __global__ __launch_bounds__(1024) void k_mvs_range(int M, const uint64_t* __restrict__ keys,
-                                                    const uint32_t* __restrict__ cnt, double* __restrict__ range) {
+                                                    double* __restrict__ range) {
 #pragma clang fp contract(off)
-    __shared__ uint32_t hist[256];
-    __shared__ uint64_t s_prefix;
-    __shared__ uint32_t s_rank;
+    __shared__ RangeLds L;
     const int v = blockIdx.x;
-    const uint32_t n = cnt[v];
+    const uint64_t* k = keys + (size_t)v * M;
+    uint32_t c = 0;
+    for (int e = threadIdx.x; e < M; e += blockDim.x) c += k[e] != ~0ull;
+    const uint32_t n = block_sum_u32(c, L);
     double lo = 0.0, hi = 0.0;
     if (n > 0) {
-        const uint64_t* k = keys + (size_t)v * M;
-        lo = 0.5 * quantile_of(k, n, 0.05, hist, &s_prefix, &s_rank);
-        hi = 1.5 * quantile_of(k, n, 0.95, hist, &s_prefix, &s_rank);
+        lo = 0.5 * quantile_of(k, M, n, 0.05, L);
+        hi = 1.5 * quantile_of(k, M, n, 0.95, L);
     }
     if (threadIdx.x == 0) {
         range[2 * v] = lo;
@@ -219,17 +269,25 @@ __global__ __launch_bounds__(64) void k_mvs_ref(const pgs_camera* __restrict__ c
 
 // ---------------------------------------------------------------- cost volume
 
+constexpr int kCostPix = 32;  // pixels per cost workgroup
+
+// Workgroup: kCostPix consecutive pixels of one target, all D planes; thread
+// (slot, k) handles plane k for pixels slot, slot + 256/D, ...  The plane
+// depth d_k is computed once per thread, the pixel rays ((x - cx)/fx,
+// (y - cy)/fy) once per pixel in LDS.
 template <int D>
 __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cams, int W, int H,
                                               const uint64_t* __restrict__ census,
                                               const int32_t* __restrict__ targets, const int32_t* __restrict__ refs,
                                               const double* __restrict__ range, uint8_t* __restrict__ cost) {
 #pragma clang fp contract(off)
-    constexpr int PPB = 256 / D > 0 ? 256 / D : 1;  // pixels per block
-    __shared__ double s_pose[12 + 8];                 // M, m, then the two cameras' intrinsics, 1/d_max, h
-    const int ti = blockIdx.y, tv = targets[ti], rv = refs[tv];
-    const double d_min = range[2 * tv], d_max = range[2 * tv + 1];
-    if (threadIdx.x == 0) {
+    constexpr int SL = 256 / D > 0 ? 256 / D : 1;  // pixel slots per pass
+    __shared__ double s_pose[20];  // M, m, the reference intrinsics
+    __shared__ double s_a[kCostPix], s_b[kCostPix];
+    __shared__ uint64_t s_cen[kCostPix];
+    const int t = threadIdx.x, ti = blockIdx.y, tv = targets[ti], rv = refs[tv];
+    const uint32_t npix = (uint32_t)W * (uint32_t)H, base = blockIdx.x * kCostPix;
+    if (t == 0) {
         const Cam64 ct = cam64(cams[tv]), cr = cam64(cams[rv]);
         double M[9];
         for (int i = 0; i < 3; ++i)
@@ -239,50 +297,76 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
         for (int i = 0; i < 9; ++i) s_pose[i] = M[i];
         for (int i = 0; i < 3; ++i)
             s_pose[9 + i] = cr.t[i] - (M[3 * i] * ct.t[0] + M[3 * i + 1] * ct.t[1] + M[3 * i + 2] * ct.t[2]);
-        s_pose[12] = ct.fx;
-        s_pose[13] = ct.fy;
-        s_pose[14] = ct.cx;
-        s_pose[15] = ct.cy;
-        s_pose[16] = cr.fx;
-        s_pose[17] = cr.fy;
-        s_pose[18] = cr.cx;
-        s_pose[19] = cr.cy;
+        s_pose[12] = cr.fx;
+        s_pose[13] = cr.fy;
+        s_pose[14] = cr.cx;
+        s_pose[15] = cr.cy;
+    }
+    if (t < kCostPix && base + t < npix) {
+        const pgs_camera& c = cams[tv];
+        const uint32_t pix = base + t, y = pix / (uint32_t)W, x = pix - y * (uint32_t)W;
+        s_a[t] = ((double)x - (double)c.cx) / (double)c.fx;
+        s_b[t] = ((double)y - (double)c.cy) / (double)c.fy;
+        s_cen[t] = census[(size_t)tv * npix + pix];
     }
     __syncthreads();
-    const int k = threadIdx.x % D;
-    const long long pix = (long long)blockIdx.x * PPB + threadIdx.x / D;
-    if (pix >= (long long)W * H) return;
-    const int y = (int)(pix / W), x = (int)(pix - (long long)y * W);
-    const size_t npix = (size_t)W * H;
-    int c = kCostOut;
-    if (d_min > 0.0 && d_max > d_min) {
+    if (t >= SL * D) return;
+    const int k = t % D, slot = t / D;
+    const double d_min = range[2 * tv], d_max = range[2 * tv + 1];
+    const bool ranged = d_min > 0.0 && d_max > d_min;
+    double d = 0.0;
+    if (ranged) {
         const double inv_far = 1.0 / d_max;
         const double h = (1.0 / d_min - inv_far) / (double)(D - 1);
-        const double d = 1.0 / (inv_far + (double)k * h);
-        const double a = ((double)x - s_pose[14]) / s_pose[12], b = ((double)y - s_pose[15]) / s_pose[13];
-        const double X = d * a, Y = d * b, Z = d;
-        const double* M = s_pose;
-        const double xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
-        const double yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
-        const double zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
-        const double u = floor(s_pose[16] * (xr / zr) + s_pose[18] + 0.5);
-        const double v = floor(s_pose[17] * (yr / zr) + s_pose[19] + 0.5);
-        if (zr > 0.0 && u >= 0.0 && u <= (double)(W - 1) && v >= 0.0 && v <= (double)(H - 1)) {
-            const uint64_t ref = census[(size_t)rv * npix + (size_t)v * W + (size_t)u];
-            c = __popcll(census[(size_t)tv * npix + pix] ^ ref);
-        }
+        d = 1.0 / (inv_far + (double)k * h);
     }
-    cost[((size_t)ti * npix + pix) * D + k] = (uint8_t)c;
+    const double* M = s_pose;
+    const uint64_t* rc = census + (size_t)rv * npix;
+    uint8_t* out = cost + ((size_t)ti * npix + base) * D + k;
+    for (int i = slot; i < kCostPix; i += SL) {
+        if (base + i >= npix) break;
+        int c = kCostOut;
+        if (ranged) {
+            const double X = d * s_a[i], Y = d * s_b[i], Z = d;
+            const double xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
+            const double yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
+            const double zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
+            const double u = floor(M[12] * (xr / zr) + M[14] + 0.5);
+            const double v = floor(M[13] * (yr / zr) + M[15] + 0.5);
+            if (zr > 0.0 && u >= 0.0 && u <= (double)(W - 1) && v >= 0.0 && v <= (double)(H - 1))
+                c = __popcll(s_cen[i] ^ rc[(size_t)v * W + (size_t)u]);
+        }
+        out[(size_t)i * D] = (uint8_t)c;
+    }
 }
 
 // ---------------------------------------------------------------- SGM
 
 enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2 };
 
-__device__ __forceinline__ int wave_min_i32(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
+constexpr int kIntMax = 0x7fffffff;
+
+// Minimum over the wave, returned to every lane: an inclusive min-scan
+// inside each row of 16 lanes (DPP row shifts), folded across rows with
+// row broadcasts (lane 63 ends with the total), then read from lane 63.
+__device__ __forceinline__ int wave_min_all(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(kIntMax, v, 0x111, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(kIntMax, v, 0x112, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(kIntMax, v, 0x114, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(kIntMax, v, 0x118, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(kIntMax, v, 0x142, 0xa, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(kIntMax, v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Value of lane l - 1 (wave shift right by one), `edge` in lane 0.
+__device__ __forceinline__ int from_lower_lane(int v, int edge) {
+    return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);
+}
+
+// Value of lane l + 1 (wave shift left by one), `edge` in lane 63.
+__device__ __forceinline__ int from_upper_lane(int v, int edge) {
+    return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);
 }
 
 struct SgmArgs {
@@ -297,25 +381,69 @@ struct SgmArgs {
     double keep_ratio;   // 1 - confidence threshold
 };
 
+// Lane l holds planes KPL l .. KPL l + KPL - 1 of a pixel: its costs are KPL
+// consecutive bytes and its sums KPL consecutive uint16, loaded as one word
+// where KPL allows and kept packed until used.
+template <int KPL> struct SumWord { typedef uint64_t type; };
+template <> struct SumWord<1> { typedef uint32_t type; };
+template <> struct SumWord<2> { typedef uint32_t type; };
+
+template <int KPL>
+struct LanePack {
+    typedef typename SumWord<KPL>::type G;
+    __device__ static void load(const uint8_t* c, const uint16_t* g, bool with_g, uint32_t& cw, G& gw) {
+        if (KPL == 2) {
+            cw = *reinterpret_cast<const uint16_t*>(c);
+            gw = with_g ? *reinterpret_cast<const uint32_t*>(g) : 0u;
+        } else if (KPL == 4) {
+            cw = *reinterpret_cast<const uint32_t*>(c);
+            gw = with_g ? (G)*reinterpret_cast<const uint64_t*>(g) : (G)0;
+        } else {
+            cw = 0;
+            gw = 0;
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                cw |= (uint32_t)c[j] << (8 * j);
+                if (with_g) gw |= (G)g[j] << (16 * j);
+            }
+        }
+    }
+    __device__ static int cost(uint32_t cw, int j) { return (int)((cw >> (8 * j)) & 255u); }
+    __device__ static int sum(G gw, int j) { return (int)((gw >> (16 * j)) & 0xffffu); }
+    __device__ static void store(uint16_t* g, const int (&v)[KPL]) {
+        if (KPL == 2) {
+            *reinterpret_cast<uint32_t*>(g) = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        } else if (KPL == 4) {
+            *reinterpret_cast<uint64_t*>(g) = (uint64_t)(uint32_t)v[0] | ((uint64_t)(uint32_t)v[1] << 16) |
+                                              ((uint64_t)(uint32_t)v[2] << 32) | ((uint64_t)(uint32_t)v[3] << 48);
+        } else {
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) g[j] = (uint16_t)v[j];
+        }
+    }
+};
+
 // dir 0: left to right along rows, 1: right to left, 2: top to bottom along
-// columns, 3: bottom to top.
+// columns, 3: bottom to top.  The last pass records per step the winner,
+// the two sums of the confidence test and the winner's neighbours in lane
+// (step mod 64) and turns 64 steps at a time into depths, one per lane.
 template <int KPL, int MODE>
 __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
 #pragma clang fp contract(off)
     constexpr int D = 64 * KPL;
     constexpr int kBig = 1 << 28;
+    constexpr int PF = 8;
     const int lane = threadIdx.x & 63;
     const int line = blockIdx.x * 4 + (threadIdx.x >> 6), ti = blockIdx.y;
     if (line >= a.lines) return;
     const bool rows = a.dir < 2, rev = (a.dir & 1) != 0;
     const int n = rows ? a.W : a.H;
     const size_t npix = (size_t)a.W * a.H;
-    // pixel of step s: element offset (pixel * D)
     const long long p0 = rows ? (long long)line * a.W + (rev ? a.W - 1 : 0)
                               : (long long)(rev ? a.H - 1 : 0) * a.W + line;
     const long long dp = rows ? (rev ? -1 : 1) : (rev ? -(long long)a.W : (long long)a.W);
-    const uint8_t* cbase = a.cost + (size_t)ti * npix * D;
-    uint16_t* abase = a.agg + (size_t)ti * npix * D;
+    const uint8_t* cbase = a.cost + (size_t)ti * npix * D + KPL * lane;
+    uint16_t* abase = a.agg + (size_t)ti * npix * D + KPL * lane;
     double inv_far = 0.0, h = 0.0;
     if (MODE == kLast) {
         const int tv = a.targets[ti];
@@ -323,22 +451,33 @@ __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
         inv_far = 1.0 / d_max;
         h = (1.0 / d_min - inv_far) / (double)(D - 1);
     }
+    typedef LanePack<KPL> LP;
+    typedef typename LP::G G;
     int L[KPL];
-    constexpr int PF = 4;
-    uint8_t cn[PF][KPL];
-    uint16_t an[PF][KPL];
-    auto load = [&](int s, uint8_t (&c)[KPL], uint16_t (&g)[KPL]) {
+    uint32_t cc[PF], cn[PF];
+    G ac[PF], an[PF];
+    auto load = [&](int s, uint32_t& c, G& g) {
         if (s < n) {
-            const size_t e = (size_t)(p0 + dp * s) * D + lane;
-#pragma unroll
-            for (int j = 0; j < KPL; ++j) {
-                c[j] = cbase[e + 64 * j];
-                if (MODE != kFirst) g[j] = abase[e + 64 * j];
-            }
+            const size_t e = (size_t)(p0 + dp * s) * D;
+            LP::load(cbase + e, abase + e, MODE != kFirst, c, g);
         }
     };
-    uint8_t cc[PF][KPL];
-    uint16_t ac[PF][KPL];
+    // winner records of the last pass: step s lives in lane s mod 64
+    int r_k = 0, r_s1 = 0, r_s2 = 0, r_m = 0, r_q = 0;
+    auto flush = [&](int s_first, int count) {
+        if (lane < count) {
+            const bool keep = r_k > 0 && r_k < D - 1 && r_s2 > 0 && (double)r_s1 <= a.keep_ratio * (double)r_s2;
+            float dout = 0.0f;
+            if (keep) {
+                const int den = r_m - 2 * r_s1 + r_q;
+                const double delta = den > 0 ? (double)(r_m - r_q) / (2.0 * (double)den) : 0.0;
+                dout = (float)(1.0 / (inv_far + ((double)r_k + delta) * h));
+            }
+            const size_t o = (size_t)ti * npix + (size_t)(p0 + dp * (s_first + lane));
+            a.depth[o] = dout;
+            a.conf[o] = r_s2 > 0 ? (float)(1.0 - (double)r_s1 / (double)r_s2) : 0.0f;
+        }
+    };
 #pragma unroll
     for (int q = 0; q < PF; ++q) load(q, cc[q], ac[q]);
     for (int s0 = 0; s0 < n; s0 += PF) {
@@ -350,89 +489,78 @@ __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
             if (s >= n) break;
             if (s == 0) {
 #pragma unroll
-                for (int j = 0; j < KPL; ++j) L[j] = cc[q][j];
+                for (int j = 0; j < KPL; ++j) L[j] = LP::cost(cc[q], j);
             } else {
                 int m = L[0];
 #pragma unroll
                 for (int j = 1; j < KPL; ++j) m = min(m, L[j]);
-                m = wave_min_i32(m);
-                int dn[KPL], up[KPL];
-#pragma unroll
-                for (int j = 0; j < KPL; ++j) {
-                    dn[j] = __shfl(L[j], (lane + 63) & 63);
-                    up[j] = __shfl(L[j], (lane + 1) & 63);
-                }
+                m = wave_min_all(m);
+                // plane k - 1 of the lane's first plane is the previous
+                // lane's last; k + 1 of its last is the next lane's first
+                const int below = from_lower_lane(L[KPL - 1], kBig);
+                const int above = from_upper_lane(L[0], kBig);
                 int Ln[KPL];
 #pragma unroll
                 for (int j = 0; j < KPL; ++j) {
-                    const int km1 = lane > 0 ? dn[j] : (j > 0 ? dn[j - 1] : kBig);
-                    const int kp1 = lane < 63 ? up[j] : (j + 1 < KPL ? up[j + 1] : kBig);
+                    const int km1 = j > 0 ? L[j - 1] : below;
+                    const int kp1 = j + 1 < KPL ? L[j + 1] : above;
                     const int best = min(min(L[j], km1 + a.p1), min(kp1 + a.p1, m + a.p2));
-                    Ln[j] = (int)cc[q][j] + best - m;
+                    Ln[j] = LP::cost(cc[q], j) + best - m;
                 }
 #pragma unroll
                 for (int j = 0; j < KPL; ++j) L[j] = Ln[j];
             }
-            const long long pix = p0 + dp * s;
-            const size_t e = (size_t)pix * D + lane;
+            const size_t e = (size_t)(p0 + dp * s) * D;
             if (MODE == kFirst) {
-#pragma unroll
-                for (int j = 0; j < KPL; ++j) abase[e + 64 * j] = (uint16_t)L[j];
+                LP::store(abase + e, L);
             } else if (MODE == kMiddle) {
+                int S[KPL];
 #pragma unroll
-                for (int j = 0; j < KPL; ++j) abase[e + 64 * j] = (uint16_t)(ac[q][j] + L[j]);
+                for (int j = 0; j < KPL; ++j) S[j] = LP::sum(ac[q], j) + L[j];
+                LP::store(abase + e, S);
             } else {
                 int S[KPL];
 #pragma unroll
-                for (int j = 0; j < KPL; ++j) S[j] = (int)ac[q][j] + L[j];
-                if (a.agg_total) {
-#pragma unroll
-                    for (int j = 0; j < KPL; ++j) abase[e + 64 * j] = (uint16_t)S[j];
-                }
+                for (int j = 0; j < KPL; ++j) S[j] = LP::sum(ac[q], j) + L[j];
+                if (a.agg_total) LP::store(abase + e, S);
                 // winner: smallest sum, then smallest plane
-                int key = (S[0] << 8) | lane;
+                int key = (S[0] << 8) | (KPL * lane);
 #pragma unroll
-                for (int j = 1; j < KPL; ++j) key = min(key, (S[j] << 8) | (64 * j + lane));
-                key = wave_min_i32(key);
+                for (int j = 1; j < KPL; ++j) key = min(key, (S[j] << 8) | (KPL * lane + j));
+                key = wave_min_all(key);
                 const int s1 = key >> 8, kw = key & 255;
                 int s2 = kBig;
 #pragma unroll
                 for (int j = 0; j < KPL; ++j) {
-                    const int kk = 64 * j + lane;
+                    const int kk = KPL * lane + j;
                     if (kk - kw >= 2 || kw - kk >= 2) s2 = min(s2, S[j]);
                 }
-                s2 = wave_min_i32(s2);
-                // S(k* - 1) and S(k* + 1) from their lanes
+                s2 = wave_min_all(s2);
                 const int km = max(kw - 1, 0), kq = min(kw + 1, D - 1);
+                const int jm = km % KPL, jq = kq % KPL;
                 int vm = S[0], vq = S[0];
 #pragma unroll
                 for (int j = 1; j < KPL; ++j) {
-                    if ((km >> 6) == j) vm = S[j];
-                    if ((kq >> 6) == j) vq = S[j];
+                    if (jm == j) vm = S[j];
+                    if (jq == j) vq = S[j];
                 }
-                vm = __shfl(vm, km & 63);
-                vq = __shfl(vq, kq & 63);
-                if (lane == 0) {
-                    const bool keep = kw > 0 && kw < D - 1 && s2 > 0 && (double)s1 <= a.keep_ratio * (double)s2;
-                    float dout = 0.0f;
-                    if (keep) {
-                        const int den = vm - 2 * s1 + vq;
-                        const double delta = den > 0 ? (double)(vm - vq) / (2.0 * (double)den) : 0.0;
-                        dout = (float)(1.0 / (inv_far + ((double)kw + delta) * h));
-                    }
-                    const size_t o = (size_t)ti * npix + (size_t)pix;
-                    a.depth[o] = dout;
-                    a.conf[o] = s2 > 0 ? (float)(1.0 - (double)s1 / (double)s2) : 0.0f;
+                vm = __builtin_amdgcn_readlane(vm, km / KPL);
+                vq = __builtin_amdgcn_readlane(vq, kq / KPL);
+                if (lane == (s & 63)) {
+                    r_k = kw;
+                    r_s1 = s1;
+                    r_s2 = s2;
+                    r_m = vm;
+                    r_q = vq;
                 }
+                if ((s & 63) == 63 || s == n - 1) flush(s & ~63, (s & 63) + 1);
             }
         }
 #pragma unroll
-        for (int q = 0; q < PF; ++q)
-#pragma unroll
-            for (int j = 0; j < KPL; ++j) {
-                cc[q][j] = cn[q][j];
-                ac[q][j] = an[q][j];
-            }
+        for (int q = 0; q < PF; ++q) {
+            cc[q] = cn[q];
+            ac[q] = an[q];
+        }
     }
 }
 
@@ -555,7 +683,7 @@ extern "C" pgs_status pgs_mvs_census(const uint8_t* grey_dev, int32_t n_views, i
 
 extern "C" size_t pgs_mvs_range_workspace(int32_t n_views, int32_t n_points) {
     if (n_views <= 0 || n_points < 0) return 0;
-    return al256((size_t)n_views * n_points * 8) + al256((size_t)n_views * 4);
+    return al256((size_t)n_views * n_points * 8);
 }
 
 extern "C" pgs_status pgs_mvs_depth_range(const pgs_camera* cams_dev, int32_t n_views, int32_t width, int32_t height,
@@ -571,13 +699,10 @@ extern "C" pgs_status pgs_mvs_depth_range(const pgs_camera* cams_dev, int32_t n_
                 pgs_mvs_range_workspace(n_views, n_points));
     hipStream_t s = pgs::as_stream(stream);
     uint64_t* keys = static_cast<uint64_t*>(workspace_dev);
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace_dev) +
-                                                al256((size_t)n_views * n_points * 8));
-    k_mvs_clear<<<(n_views + 255) / 256, 256, 0, s>>>(cnt, n_views);
     if (n_points > 0)
         k_mvs_depths<<<dim3((n_points + 255) / 256, n_views), 256, 0, s>>>(cams_dev, width, height, points_dev,
-                                                                           n_points, keys, cnt);
-    k_mvs_range<<<n_views, 1024, 0, s>>>(n_points, keys, cnt, range_dev);
+                                                                           n_points, keys);
+    k_mvs_range<<<n_views, 1024, 0, s>>>(n_points, keys, range_dev);
     PGS_CHECK_LAUNCH("pgs_mvs_depth_range");
     return PGS_OK;
 }
@@ -605,14 +730,13 @@ extern "C" pgs_status pgs_mvs_cost(const pgs_camera* cams_dev, int32_t width, in
     PGS_REQUIRE(cams_dev && census_dev && targets_dev && ref_dev && range_dev && cost_dev, "pgs_mvs_cost: null pointer");
     const int D = params->n_planes;
     const long long npix = (long long)width * height;
-    const long long blocks = (npix * D + 255) / 256;
-    PGS_REQUIRE(blocks < (1ll << 31), "pgs_mvs_cost: image too large");
+    PGS_REQUIRE(npix < (1ll << 31), "pgs_mvs_cost: image too large");
     hipStream_t s = pgs::as_stream(stream);
-    const dim3 grid((unsigned)blocks, n_targets);
+    const dim3 grid((unsigned)((npix + kCostPix - 1) / kCostPix), n_targets);
     switch (D) {
         case 64: k_cost<64><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
         case 128: k_cost<128><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
-        case 192: k_cost<192><<<dim3((unsigned)npix, n_targets), 192, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
+        case 192: k_cost<192><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
         default: k_cost<256><<<grid, 256, 0, s>>>(cams_dev, width, height, census_dev, targets_dev, ref_dev, range_dev, cost_dev); break;
     }
     PGS_CHECK_LAUNCH("pgs_mvs_cost");
