@@ -629,7 +629,8 @@ pgs_status pgs_ba_apply(int32_t n_cams, int32_t n_points, const double* rot_dev,
  * ------------------------------------------------------------------------ */
 typedef struct pgs_mvs_params {
     int32_t n_planes;   /* depth hypotheses: 64, 128, 192 or 256 */
-    int32_t p1, p2;     /* SGM penalties for a one-plane / a larger jump, 0..1000 */
+    int32_t p1, p2;     /* SGM penalties for a one-plane / a larger jump, 0..1000
+                           (pgs_mvs_sgm: p2 <= 207, path costs kept in bytes) */
     double conf_min;    /* confidence filter, 0.4 in the paper */
     double b_target;    /* preferred baseline (scene units), reference score */
     double sigma_b;     /* > 0, width of the baseline term */
@@ -690,7 +691,8 @@ pgs_status pgs_mvs_cost(const pgs_camera* cams_dev, int32_t width, int32_t heigh
                         const int32_t* targets_dev, int32_t n_targets, const int32_t* ref_dev,
                         const double* range_dev, const pgs_mvs_params* params, uint8_t* cost_dev, void* stream);
 
-/* Workspace bytes of pgs_mvs_sgm (the path-cost sum, uint16). */
+/* Workspace bytes of pgs_mvs_sgm (one direction's path costs as bytes,
+ * then the path-cost sum as uint16). */
 size_t pgs_mvs_sgm_workspace(int32_t n_targets, int32_t width, int32_t height, int32_t n_planes);
 
 /*
@@ -703,7 +705,9 @@ size_t pgs_mvs_sgm_workspace(int32_t n_targets, int32_t width, int32_t height, i
  * 1/d = 1/d_max + (k* + delta) h.  depth_dev [n_targets][height][width]
  * float32 (0 where rejected), conf_dev the same shape (1 - S(k*)/S2).
  * agg_out_dev (optional, [n_targets][height][width][n_planes] uint16)
- * receives S; without it the sum lives in the workspace.
+ * receives S; without it the partial sums live in the workspace, which is
+ * required either way.  p2 <= 207 (each path cost, <= 48 + p2, is stored in
+ * a byte between the two sweeps of a line).
  */
 pgs_status pgs_mvs_sgm(const uint8_t* cost_dev, int32_t width, int32_t height, const int32_t* targets_dev,
                        int32_t n_targets, const double* range_dev, const pgs_mvs_params* params, float* depth_dev,

@@ -16,14 +16,15 @@
 //       reference view from float64 arithmetic in a fixed order without
 //       contraction (the nearest-pixel decision is reproducible), Hamming
 //       distance of the Census strings; cost volume [y][x][plane] bytes;
-//   k_sgm<KPL, MODE>  one wave per image line and direction: lane l holds
-//       the KPL consecutive planes KPL l .. (one load of its costs and sums
-//       per step, prefetched 8 steps ahead); per step the previous costs'
-//       minimum is a DPP wave reduction and the neighbouring planes come
-//       from DPP wave shifts; the first pass writes the path cost, the middle
-//       ones add to it, the last adds its own and takes the winner and the
-//       confidence-test sums per pixel (lane = step mod 64), turned into
-//       refined depths 64 pixels at a time, without storing the sum;
+//   k_sgm<KPL, COLS>  one wave per image line sweeps it forward (path costs
+//       stored as bytes) and back: lane l holds the KPL consecutive planes
+//       KPL l .. (one load per step of each operand, prefetched 8 steps
+//       ahead); per step the previous costs' minimum is a DPP wave reduction
+//       and the neighbouring planes come from DPP wave shifts.  The row
+//       kernel writes the two row paths' sum; the column kernel adds both
+//       column paths to it and takes the winner and the confidence-test sums
+//       per pixel (lane = step mod 64), turned into refined depths 64 pixels
+//       at a time, without storing the total;
 //   k_fuse_*      per-row counts, one scan over rows and the back-projection
 //       of the kept pixels in row-major order.
 
@@ -342,8 +343,6 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
 
 // ---------------------------------------------------------------- SGM
 
-enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2 };
-
 constexpr int kIntMax = 0x7fffffff;
 
 // Minimum over the wave, returned to every lane: an inclusive min-scan
@@ -371,13 +370,14 @@ __device__ __forceinline__ int from_upper_lane(int v, int edge) {
 
 struct SgmArgs {
     const uint8_t* cost;
+    uint8_t* lbuf;       // forward path costs of the line being swept [T][H][W][D]
     uint16_t* agg;       // path-cost sum [T][H][W][D]
     bool agg_total;      // the last pass also stores the full sum
     const int32_t* targets;
     const double* range;
     float* depth;        // [T][H][W]
     float* conf;
-    int W, H, dir, p1, p2, lines;
+    int W, H, p1, p2;
     double keep_ratio;   // 1 - confidence threshold
 };
 
@@ -408,6 +408,33 @@ struct LanePack {
             }
         }
     }
+    __device__ static uint32_t load_bytes(const uint8_t* c) {
+        if (KPL == 2) return *reinterpret_cast<const uint16_t*>(c);
+        if (KPL == 4) return *reinterpret_cast<const uint32_t*>(c);
+        uint32_t w = 0;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) w |= (uint32_t)c[j] << (8 * j);
+        return w;
+    }
+    __device__ static void store_bytes(uint8_t* c, const int (&v)[KPL]) {
+        if (KPL == 2) {
+            *reinterpret_cast<uint16_t*>(c) = (uint16_t)((uint32_t)v[0] | ((uint32_t)v[1] << 8));
+        } else if (KPL == 4) {
+            *reinterpret_cast<uint32_t*>(c) =
+                (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+        } else {
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) c[j] = (uint8_t)v[j];
+        }
+    }
+    __device__ static G load_sums(const uint16_t* g) {
+        if (KPL == 2) return *reinterpret_cast<const uint32_t*>(g);
+        if (KPL == 4) return (G)*reinterpret_cast<const uint64_t*>(g);
+        G w = 0;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) w |= (G)g[j] << (16 * j);
+        return w;
+    }
     __device__ static int cost(uint32_t cw, int j) { return (int)((cw >> (8 * j)) & 255u); }
     __device__ static int sum(G gw, int j) { return (int)((gw >> (16 * j)) & 0xffffu); }
     __device__ static void store(uint16_t* g, const int (&v)[KPL]) {
@@ -423,46 +450,51 @@ struct LanePack {
     }
 };
 
-// dir 0: left to right along rows, 1: right to left, 2: top to bottom along
-// columns, 3: bottom to top.  The last pass records per step the winner,
-// the two sums of the confidence test and the winner's neighbours in lane
-// (step mod 64) and turns 64 steps at a time into depths, one per lane.
+// One sweep of a wave along its line.  kForward: path costs to lbuf (bytes,
+// every value <= 48 + p2 <= 255 is checked on the host); kRowsBack: the
+// opposite direction, the two rows' path costs summed into agg; kColsBack:
+// the opposite column direction added to the row sum and lbuf's forward
+// column costs, then per pixel the winner and the confidence-test sums
+// (recorded in lane step mod 64 and turned into refined depths 64 pixels
+// at a time).
+enum SweepMode { kForward = 0, kRowsBack = 1, kColsBack = 2 };
+
 template <int KPL, int MODE>
-__global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
+__device__ __forceinline__ void sgm_sweep(const SgmArgs& a, int line, int ti, bool rows, bool rev) {
 #pragma clang fp contract(off)
     constexpr int D = 64 * KPL;
     constexpr int kBig = 1 << 28;
     constexpr int PF = 8;
+    typedef LanePack<KPL> LP;
+    typedef typename LP::G G;
     const int lane = threadIdx.x & 63;
-    const int line = blockIdx.x * 4 + (threadIdx.x >> 6), ti = blockIdx.y;
-    if (line >= a.lines) return;
-    const bool rows = a.dir < 2, rev = (a.dir & 1) != 0;
     const int n = rows ? a.W : a.H;
     const size_t npix = (size_t)a.W * a.H;
     const long long p0 = rows ? (long long)line * a.W + (rev ? a.W - 1 : 0)
                               : (long long)(rev ? a.H - 1 : 0) * a.W + line;
     const long long dp = rows ? (rev ? -1 : 1) : (rev ? -(long long)a.W : (long long)a.W);
-    const uint8_t* cbase = a.cost + (size_t)ti * npix * D + KPL * lane;
-    uint16_t* abase = a.agg + (size_t)ti * npix * D + KPL * lane;
+    const size_t off = (size_t)ti * npix * D + KPL * lane;
+    const uint8_t* cbase = a.cost + off;
+    uint8_t* lbase = a.lbuf + off;
+    uint16_t* abase = a.agg + off;
     double inv_far = 0.0, h = 0.0;
-    if (MODE == kLast) {
+    if (MODE == kColsBack) {
         const int tv = a.targets[ti];
         const double d_min = a.range[2 * tv], d_max = a.range[2 * tv + 1];
         inv_far = 1.0 / d_max;
         h = (1.0 / d_min - inv_far) / (double)(D - 1);
     }
-    typedef LanePack<KPL> LP;
-    typedef typename LP::G G;
     int L[KPL];
-    uint32_t cc[PF], cn[PF];
+    uint32_t cc[PF], cn[PF], fc[PF], fn[PF];
     G ac[PF], an[PF];
-    auto load = [&](int s, uint32_t& c, G& g) {
+    auto load = [&](int s, uint32_t& c, uint32_t& f, G& g) {
         if (s < n) {
             const size_t e = (size_t)(p0 + dp * s) * D;
-            LP::load(cbase + e, abase + e, MODE != kFirst, c, g);
+            c = LP::load_bytes(cbase + e);
+            if (MODE != kForward) f = LP::load_bytes(lbase + e);
+            if (MODE == kColsBack) g = LP::load_sums(abase + e);
         }
     };
-    // winner records of the last pass: step s lives in lane s mod 64
     int r_k = 0, r_s1 = 0, r_s2 = 0, r_m = 0, r_q = 0;
     auto flush = [&](int s_first, int count) {
         if (lane < count) {
@@ -479,10 +511,10 @@ __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
         }
     };
 #pragma unroll
-    for (int q = 0; q < PF; ++q) load(q, cc[q], ac[q]);
+    for (int q = 0; q < PF; ++q) load(q, cc[q], fc[q], ac[q]);
     for (int s0 = 0; s0 < n; s0 += PF) {
 #pragma unroll
-        for (int q = 0; q < PF; ++q) load(s0 + PF + q, cn[q], an[q]);
+        for (int q = 0; q < PF; ++q) load(s0 + PF + q, cn[q], fn[q], an[q]);
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int s = s0 + q;
@@ -511,17 +543,17 @@ __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
                 for (int j = 0; j < KPL; ++j) L[j] = Ln[j];
             }
             const size_t e = (size_t)(p0 + dp * s) * D;
-            if (MODE == kFirst) {
-                LP::store(abase + e, L);
-            } else if (MODE == kMiddle) {
+            if (MODE == kForward) {
+                LP::store_bytes(lbase + e, L);
+            } else if (MODE == kRowsBack) {
                 int S[KPL];
 #pragma unroll
-                for (int j = 0; j < KPL; ++j) S[j] = LP::sum(ac[q], j) + L[j];
+                for (int j = 0; j < KPL; ++j) S[j] = LP::cost(fc[q], j) + L[j];
                 LP::store(abase + e, S);
             } else {
                 int S[KPL];
 #pragma unroll
-                for (int j = 0; j < KPL; ++j) S[j] = LP::sum(ac[q], j) + L[j];
+                for (int j = 0; j < KPL; ++j) S[j] = LP::sum(ac[q], j) + LP::cost(fc[q], j) + L[j];
                 if (a.agg_total) LP::store(abase + e, S);
                 // winner: smallest sum, then smallest plane
                 int key = (S[0] << 8) | (KPL * lane);
@@ -559,9 +591,23 @@ __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             cc[q] = cn[q];
+            fc[q] = fn[q];
             ac[q] = an[q];
         }
     }
+}
+
+// Rows (COLS = false): left to right into lbuf, then right to left summed
+// with it into agg.  Columns (COLS = true): top to bottom into lbuf, then
+// bottom to top with the winner.  One wave per line, four lines per
+// workgroup; the second sweep reads what the same wave stored.
+template <int KPL, bool COLS>
+__global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6), ti = blockIdx.y;
+    if (line >= (COLS ? a.W : a.H)) return;
+    sgm_sweep<KPL, kForward>(a, line, ti, !COLS, false);
+    if (COLS) sgm_sweep<KPL, kColsBack>(a, line, ti, false, true);
+    else sgm_sweep<KPL, kRowsBack>(a, line, ti, true, true);
 }
 
 // ---------------------------------------------------------------- fusion
@@ -655,14 +701,8 @@ pgs_status check_params(const pgs_mvs_params* p, const char* who) {
 
 template <int KPL>
 pgs_status launch_sgm(SgmArgs a, int n_targets, hipStream_t s) {
-    for (int dir = 0; dir < 4; ++dir) {
-        a.dir = dir;
-        a.lines = dir < 2 ? a.H : a.W;
-        const dim3 grid((a.lines + 3) / 4, n_targets);
-        if (dir == 0) k_sgm<KPL, kFirst><<<grid, 256, 0, s>>>(a);
-        else if (dir < 3) k_sgm<KPL, kMiddle><<<grid, 256, 0, s>>>(a);
-        else k_sgm<KPL, kLast><<<grid, 256, 0, s>>>(a);
-    }
+    k_sgm<KPL, false><<<dim3((a.H + 3) / 4, n_targets), 256, 0, s>>>(a);
+    k_sgm<KPL, true><<<dim3((a.W + 3) / 4, n_targets), 256, 0, s>>>(a);
     PGS_CHECK_LAUNCH("pgs_mvs_sgm");
     return PGS_OK;
 }
@@ -745,7 +785,8 @@ extern "C" pgs_status pgs_mvs_cost(const pgs_camera* cams_dev, int32_t width, in
 
 extern "C" size_t pgs_mvs_sgm_workspace(int32_t n_targets, int32_t width, int32_t height, int32_t n_planes) {
     if (n_targets <= 0 || width <= 0 || height <= 0 || n_planes <= 0) return 0;
-    return al256((size_t)n_targets * width * height * n_planes * 2);
+    const size_t e = (size_t)n_targets * width * height * n_planes;
+    return al256(e) + al256(e * 2);
 }
 
 extern "C" pgs_status pgs_mvs_sgm(const uint8_t* cost_dev, int32_t width, int32_t height, const int32_t* targets_dev,
@@ -757,12 +798,15 @@ extern "C" pgs_status pgs_mvs_sgm(const uint8_t* cost_dev, int32_t width, int32_
     if (n_targets == 0) return PGS_OK;
     PGS_REQUIRE(n_targets <= 65535, "pgs_mvs_sgm: more than 65535 targets");
     PGS_REQUIRE(cost_dev && targets_dev && range_dev && depth_dev && conf_dev, "pgs_mvs_sgm: null pointer");
-    PGS_REQUIRE(agg_out_dev || (workspace_dev && workspace_bytes >= pgs_mvs_sgm_workspace(n_targets, width, height,
-                                                                                        params->n_planes)),
+    PGS_REQUIRE(workspace_dev && workspace_bytes >= pgs_mvs_sgm_workspace(n_targets, width, height,
+                                                                           params->n_planes),
                 "pgs_mvs_sgm: workspace too small");
+    PGS_REQUIRE(48 + params->p2 <= 255, "pgs_mvs_sgm: path costs up to %d do not fit a byte", 48 + params->p2);
+    const size_t e = (size_t)n_targets * width * height * params->n_planes;
     SgmArgs a{};
     a.cost = cost_dev;
-    a.agg = agg_out_dev ? agg_out_dev : static_cast<uint16_t*>(workspace_dev);
+    a.lbuf = static_cast<uint8_t*>(workspace_dev);
+    a.agg = agg_out_dev ? agg_out_dev : reinterpret_cast<uint16_t*>(static_cast<char*>(workspace_dev) + al256(e));
     a.agg_total = agg_out_dev != nullptr;
     a.targets = targets_dev;
     a.range = range_dev;

@@ -109,12 +109,10 @@ def pgs_mvs_sgm(cost, targets, rng, params: MVSParams, depth, conf, agg_out=None
     lib = _lib.load()
     if agg_out is not None:
         assert agg_out.shape == cost.shape and agg_out.dtype == torch.int16
-        ws, nbytes = ctypes.c_void_p(0), 0
-    else:
-        need = lib.pgs_mvs_sgm_workspace(T, W, H, D)
-        if workspace is None or workspace.numel() < need:
-            workspace = torch.empty(need, dtype=torch.uint8, device=cost.device)
-        ws, nbytes = _p(workspace), workspace.numel()
+    need = lib.pgs_mvs_sgm_workspace(T, W, H, D)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=cost.device)
+    ws, nbytes = _p(workspace), workspace.numel()
     ps = params.struct()
     check(lib.pgs_mvs_sgm(_p(cost, torch.uint8), W, H, _p(targets, torch.int32), T, _p(rng, torch.float64),
                           ctypes.byref(ps), _p(depth, torch.float32), _p(conf, torch.float32),
