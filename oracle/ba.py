@@ -174,3 +174,83 @@ def normal_equations_sparse(prob, R, c, P, delta):
     b = np.zeros(n)
     np.add.at(b, cols.ravel(), -np.einsum("o,oai,oa->oi", w, J, r).ravel())
     return H, b
+
+
+# Iterative geometric refinement (subsection "GPU-Native Global BA", the
+# refinement loop): after a global update every point is re-triangulated
+# from its observations with the updated poses, points with a high
+# reprojection error or an insufficient triangulation angle are dropped and
+# observations behind their camera are discarded.  Readings: the
+# re-triangulated point is the least-squares intersection of the
+# observation rays (the point minimising the summed squared distances to
+# the rays, sum (I - d d^T) P = sum (I - d d^T) c, d the unit world ray of
+# the measured pixel); a point is kept when it has at least two
+# observations in front of their cameras (z > 0), the mean reprojection
+# error over those is at most max_err pixels and the largest angle between
+# two of their camera-to-point rays is at least min_angle (tested as the
+# smallest cosine <= cos(min_angle)); an observation is kept when its point
+# is kept and it lies in front of its camera.  A point whose normal matrix
+# has a determinant of at most 1e-12 times the cube of its trace is dropped.
+
+def observation_rays(prob, R, c):
+    """Unit world directions of the measured pixels, (n_obs, 3)."""
+    cam = prob["obs_cam"]
+    uv = prob["obs_uv"]
+    dc = np.stack([(uv[:, 0] - prob["cx"]) / prob["fx"], (uv[:, 1] - prob["cy"]) / prob["fy"],
+                   np.ones(uv.shape[0])], 1)
+    d = np.einsum("oji,oj->oi", R[cam], dc)          # R^T dc
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def retriangulate(prob, R, c, n_points):
+    """Least-squares ray intersection per point; (points, solvable mask)."""
+    d = observation_rays(prob, R, c)
+    cam, pt = prob["obs_cam"], prob["obs_pt"]
+    A = np.zeros((n_points, 3, 3))
+    b = np.zeros((n_points, 3))
+    Pm = np.eye(3)[None] - d[:, :, None] * d[:, None, :]
+    np.add.at(A, pt, Pm)
+    np.add.at(b, pt, np.einsum("oij,oj->oi", Pm, c[cam]))
+    tr = np.trace(A, axis1=1, axis2=2)
+    det = np.linalg.det(A)
+    ok = det > 1e-12 * tr ** 3
+    P = np.zeros((n_points, 3))
+    P[ok] = np.linalg.solve(A[ok], b[ok][:, :, None])[:, :, 0]
+    return P, ok
+
+
+def refine(prob, R, c, n_points, max_err=4.0, min_angle=np.radians(1.5)):
+    """Re-triangulated points, point keep mask, observation keep mask and
+    the per-point statistics (mean error, smallest ray cosine, count)."""
+    P, ok = retriangulate(prob, R, c, n_points)
+    cam, pt = prob["obs_cam"], prob["obs_pt"]
+    x, uv = project(R, c, P, prob["fx"], prob["fy"], prob["cx"], prob["cy"], cam, pt)
+    front = x[:, 2] > 0
+    err = np.linalg.norm(uv - prob["obs_uv"], axis=1)
+    cnt = np.bincount(pt, weights=front, minlength=n_points)
+    esum = np.bincount(pt, weights=np.where(front, err, 0.0), minlength=n_points)
+    mean_err = np.where(cnt > 0, esum / np.maximum(cnt, 1), np.inf)
+    ray = P[pt] - c[cam]
+    ray /= np.linalg.norm(ray, axis=1, keepdims=True)
+    min_cos = np.full(n_points, np.inf)
+    starts = np.searchsorted(pt, np.arange(n_points + 1))
+    for j in range(n_points):
+        o = np.arange(starts[j], starts[j + 1])
+        o = o[front[o]]
+        if o.size >= 2:
+            g = ray[o] @ ray[o].T
+            min_cos[j] = g[np.triu_indices(o.size, 1)].min()
+    keep_pt = ok & (cnt >= 2) & (mean_err <= max_err) & (min_cos <= np.cos(min_angle))
+    keep_obs = keep_pt[pt] & front
+    return P, keep_pt, keep_obs, dict(mean_err=mean_err, min_cos=min_cos, count=cnt, solvable=ok)
+
+
+def compact(prob, P, keep_pt, keep_obs):
+    """The problem and points restricted to the kept points and
+    observations (order preserved, points renumbered)."""
+    new_id = np.cumsum(keep_pt) - 1
+    out = {k: prob[k] for k in ("fx", "fy", "cx", "cy", "gauge_axis")}
+    out["obs_cam"] = prob["obs_cam"][keep_obs]
+    out["obs_pt"] = new_id[prob["obs_pt"][keep_obs]]
+    out["obs_uv"] = prob["obs_uv"][keep_obs]
+    return out, P[keep_pt]

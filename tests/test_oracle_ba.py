@@ -101,3 +101,81 @@ def test_huber_resists_outliers():
         (R, c, P), _, _ = ba.lm(p, p["R0"], p["c0"], p["P0"], delta=delta, iters=15)
         err[name] = np.median(np.linalg.norm(P - p["P_true"], axis=1))
     assert err["huber"] < 0.5 * err["l2"], err
+
+
+def _cam_looking_at(eye, target):
+    f = np.asarray(target, float) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, [0.0, 1.0, 0.0])
+    r /= np.linalg.norm(r)
+    return np.stack([r, np.cross(f, r), f]), np.asarray(eye, float)
+
+
+def _problem(cams, points, obs, fx=500.0, cx=320.0):
+    R = np.stack([c[0] for c in cams])
+    c = np.stack([c[1] for c in cams])
+    cam = np.array([o[0] for o in obs])
+    pt = np.array([o[1] for o in obs])
+    prob = dict(fx=fx, fy=fx, cx=cx, cy=cx, gauge_axis=0, obs_cam=cam, obs_pt=pt,
+                obs_uv=np.zeros((len(obs), 2)))
+    _, uv = ba.project(R, c, np.asarray(points, float), fx, fx, cx, cx, cam, pt)
+    prob["obs_uv"] = uv
+    return prob, R, c
+
+
+def test_retriangulation_recovers_noise_free_points_and_is_the_ray_least_squares():
+    p = synth.ba_tracks(3, n_cams=12, n_points=300, noise_px=0.0, outlier_frac=0.0)
+    M = p["P_true"].shape[0]
+    P, ok = ba.retriangulate(p, p["R_true"], p["c_true"], M)
+    assert ok.all()
+    np.testing.assert_allclose(P, p["P_true"], atol=1e-9)
+    # with noise: the same point as a library least-squares solve of the
+    # stacked ray-distance system (I - d d^T)(P - c) = 0
+    q = synth.ba_tracks(4, n_cams=12, n_points=50, noise_px=2.0)
+    P, ok = ba.retriangulate(q, q["R_true"], q["c_true"], q["P_true"].shape[0])
+    d = ba.observation_rays(q, q["R_true"], q["c_true"])
+    for j in range(5):
+        o = np.nonzero(q["obs_pt"] == j)[0]
+        A = np.concatenate([np.eye(3) - np.outer(d[k], d[k]) for k in o])
+        b = np.concatenate([(np.eye(3) - np.outer(d[k], d[k])) @ q["c_true"][q["obs_cam"][k]] for k in o])
+        np.testing.assert_allclose(P[j], np.linalg.lstsq(A, b, rcond=None)[0], atol=1e-10)
+
+
+def test_refinement_filters():
+    X = np.array([0.0, 0.0, 0.0])
+    cams = [_cam_looking_at(np.array([4.0 * np.sin(a), 0.0, 4.0 * np.cos(a)]), X)
+            for a in np.radians([0.0, 20.0, 40.0])]
+    cams.append(_cam_looking_at(np.array([0.0, 0.0, -4.0]), [0.0, 0.0, -8.0]))  # faces away from X
+    cams.append(_cam_looking_at(np.array([4.0 * np.sin(0.01), 0.0, 4.0 * np.cos(0.01)]), X))
+    pts = np.array([X, [0.3, 0.2, 0.1], [0.1, -0.2, 0.3], [-0.2, 0.1, 0.0]])
+    obs = [(0, 0), (1, 0), (2, 0), (3, 0),          # point 0: three in front, one behind its camera
+           (0, 1), (4, 1),                          # point 1: two rays 0.6 degrees apart
+           (0, 2), (1, 2), (2, 2),                  # point 2: one measurement moved 40 px
+           (0, 3), (1, 3)]                          # point 3: fine
+    prob, R, c = _problem(cams, pts, obs)
+    prob["obs_uv"][7] += [40.0, 0.0]
+    P, kp, ko, st = ba.refine(prob, R, c, 4)
+    np.testing.assert_allclose(P[0], X, atol=1e-9)
+    assert list(kp) == [True, False, False, True]
+    assert list(ko) == [True, True, True, False, False, False, False, False, False, True, True]
+    assert st["count"][0] == 3 and st["mean_err"][2] > 4.0 and np.degrees(np.arccos(st["min_cos"][1])) < 1.5
+
+
+def test_compaction_keeps_order_and_renumbers():
+    p = synth.ba_tracks(5, n_cams=8, n_points=80)
+    M = p["P_true"].shape[0]
+    P, kp, ko, _ = ba.refine(p, p["R0"], p["c0"], M)
+    q, Pc = ba.compact(p, P, kp, ko)
+    # explicit loop
+    new, cams, pts, uvs = {}, [], [], []
+    for j in range(M):
+        if kp[j]:
+            new[j] = len(new)
+    for o in range(p["obs_cam"].size):
+        if ko[o]:
+            cams.append(p["obs_cam"][o])
+            pts.append(new[p["obs_pt"][o]])
+            uvs.append(p["obs_uv"][o])
+    assert list(q["obs_cam"]) == cams and list(q["obs_pt"]) == pts
+    np.testing.assert_array_equal(q["obs_uv"], np.array(uvs))
+    np.testing.assert_array_equal(Pc, P[kp])
