@@ -620,6 +620,42 @@ pgs_status pgs_ba_apply(int32_t n_cams, int32_t n_points, const double* rot_dev,
                         const double* points_dev, const double* dpose_dev, const double* dpoint_dev,
                         double* rot_out_dev, double* centre_out_dev, double* points_out_dev, void* stream);
 
+/*
+ * pgs_ba_refine - one pass of the iterative geometric refinement around the
+ * bundle adjustment (refinement paragraph of the BA subsection): every point
+ * re-triangulated as the least-squares intersection of its observation rays
+ * (sum (I - d d^T) P = sum (I - d d^T) c_i, d the unit world ray of the
+ * measured pixel) with the poses rot_dev / centre_dev, into points_out_dev
+ * [n_points][3]; keep_point_dev [n_points] = 1 when the system is solvable
+ * (det > 1e-12 trace^3), at least two observations lie in front of their
+ * cameras, their mean reprojection error is <= max_err pixels and the
+ * largest angle between two of their camera-to-point rays is >= min_angle
+ * (radians); keep_obs_dev [n_obs] = 1 for the observations of kept points
+ * that lie in front of their camera.  Errors as pgs_ba_cost.
+ */
+pgs_status pgs_ba_refine(const pgs_ba_problem* problem, const double* rot_dev, const double* centre_dev,
+                         double max_err, double min_angle, double* points_out_dev, uint8_t* keep_point_dev,
+                         uint8_t* keep_obs_dev, void* stream);
+
+/* Workspace bytes of pgs_ba_compact. */
+size_t pgs_ba_compact_workspace(int32_t n_points, int32_t n_obs);
+
+/*
+ * pgs_ba_compact - the problem restricted to the kept points and
+ * observations (order preserved, points renumbered in order): the new
+ * observation arrays (obs_cam, obs_pt, obs_uv, by point), point_start
+ * [kept points + 1], cam_obs (the kept observations by camera, stable),
+ * cam_start [n_cams + 1] and the kept points' coordinates, written to
+ * caller-owned device arrays sized like the input problem's, and
+ * counts_out_dev [2] = (kept points, kept observations).  A camera may be
+ * left without observations.
+ */
+pgs_status pgs_ba_compact(const pgs_ba_problem* problem, const uint8_t* keep_point_dev,
+                          const uint8_t* keep_obs_dev, const double* points_dev, uint32_t* obs_cam_out_dev,
+                          uint32_t* obs_pt_out_dev, double* obs_uv_out_dev, uint32_t* point_start_out_dev,
+                          uint32_t* cam_obs_out_dev, uint32_t* cam_start_out_dev, double* points_out_dev,
+                          uint32_t* counts_out_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Single-reference cost-volume multi-view stereo (subsection
  * "Single-Reference Cost-Volume MVS").  All views share one image size

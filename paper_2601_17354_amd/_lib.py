@@ -121,6 +121,11 @@ SIGNATURES = {
                               c_void_p, c_size_t, c_void_p]),
     "pgs_ba_apply": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p]),
+    "pgs_ba_refine": (c_int32, [POINTER(PgsBaProblem), c_void_p, c_void_p, c_double, c_double, c_void_p, c_void_p,
+                                c_void_p, c_void_p]),
+    "pgs_ba_compact_workspace": (c_size_t, [c_int32, c_int32]),
+    "pgs_ba_compact": (c_int32, [POINTER(PgsBaProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "pgs_mvs_census": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "pgs_mvs_range_workspace": (c_size_t, [c_int32, c_int32]),
     "pgs_mvs_depth_range": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p,

@@ -493,6 +493,214 @@ __global__ __launch_bounds__(256) void k_ba_apply(int n_cams, int n_points, cons
     }
 }
 
+// ------------------------------------------------------------ refinement
+
+// Thread per point: the least-squares intersection of its observation rays
+// (sum (I - d d^T) P = sum (I - d d^T) c, d the unit world ray of the
+// measured pixel, solved by the adjugate when det > 1e-12 trace^3), then
+// over its observations in front of their cameras the mean reprojection
+// error and the smallest cosine between two camera-to-point rays; the point
+// is kept with >= 2 such observations, mean error <= max_err and smallest
+// cosine <= cos_min; an observation is kept when its point is and it lies
+// in front of its camera.
+__global__ __launch_bounds__(256) void k_ba_refine(pgs_ba_problem pb, const double* __restrict__ rot,
+                                                   const double* __restrict__ centre, double max_err,
+                                                   double cos_min, double* __restrict__ pts_out,
+                                                   uint8_t* __restrict__ keep_pt, uint8_t* __restrict__ keep_obs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= pb.n_points) return;
+    const uint32_t o0 = pb.point_start_dev[j], o1 = pb.point_start_dev[j + 1];
+    double A[6] = {0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};  // A00 A01 A02 A11 A12 A22
+    for (uint32_t o = o0; o < o1; ++o) {
+        const int i = (int)pb.obs_cam_dev[o];
+        const double* R = rot + 9 * (size_t)i;
+        const double* c = centre + 3 * (size_t)i;
+        const double q0 = (pb.obs_uv_dev[2 * (size_t)o] - pb.cx) / pb.fx;
+        const double q1 = (pb.obs_uv_dev[2 * (size_t)o + 1] - pb.cy) / pb.fy;
+        double d[3];
+        for (int a = 0; a < 3; ++a) d[a] = R[a] * q0 + R[3 + a] * q1 + R[6 + a];  // R^T (q0, q1, 1)
+        const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int a = 0; a < 3; ++a) d[a] *= inv;
+        const double dc = d[0] * c[0] + d[1] * c[1] + d[2] * c[2];
+        A[0] += 1.0 - d[0] * d[0];
+        A[1] -= d[0] * d[1];
+        A[2] -= d[0] * d[2];
+        A[3] += 1.0 - d[1] * d[1];
+        A[4] -= d[1] * d[2];
+        A[5] += 1.0 - d[2] * d[2];
+        for (int a = 0; a < 3; ++a) b[a] += c[a] - d[a] * dc;
+    }
+    const double c00 = A[3] * A[5] - A[4] * A[4], c01 = A[2] * A[4] - A[1] * A[5], c02 = A[1] * A[4] - A[2] * A[3];
+    const double c11 = A[0] * A[5] - A[2] * A[2], c12 = A[1] * A[2] - A[0] * A[4], c22 = A[0] * A[3] - A[1] * A[1];
+    const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    const double tr = A[0] + A[3] + A[5];
+    const bool solvable = det > 1e-12 * tr * tr * tr;
+    double P[3] = {0.0, 0.0, 0.0};
+    if (solvable) {
+        const double id = 1.0 / det;
+        P[0] = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
+        P[1] = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
+        P[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
+    }
+    int cnt = 0;
+    double esum = 0.0, mincos = 2.0;
+    for (uint32_t o = o0; o < o1 && solvable; ++o) {
+        const int i = (int)pb.obs_cam_dev[o];
+        const double* R = rot + 9 * (size_t)i;
+        const double* c = centre + 3 * (size_t)i;
+        const double v0 = P[0] - c[0], v1 = P[1] - c[1], v2 = P[2] - c[2];
+        const double x0 = R[0] * v0 + R[1] * v1 + R[2] * v2, x1 = R[3] * v0 + R[4] * v1 + R[5] * v2,
+                     x2 = R[6] * v0 + R[7] * v1 + R[8] * v2;
+        if (!(x2 > 0.0)) continue;
+        const double du = pb.fx * x0 / x2 + pb.cx - pb.obs_uv_dev[2 * (size_t)o];
+        const double dv = pb.fy * x1 / x2 + pb.cy - pb.obs_uv_dev[2 * (size_t)o + 1];
+        esum += sqrt(du * du + dv * dv);
+        ++cnt;
+        const double n0 = 1.0 / sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        for (uint32_t o2 = o + 1; o2 < o1; ++o2) {
+            const int k = (int)pb.obs_cam_dev[o2];
+            const double* R2 = rot + 9 * (size_t)k;
+            const double* c2 = centre + 3 * (size_t)k;
+            const double w0 = P[0] - c2[0], w1 = P[1] - c2[1], w2 = P[2] - c2[2];
+            if (!(R2[6] * w0 + R2[7] * w1 + R2[8] * w2 > 0.0)) continue;
+            const double cs = (v0 * w0 + v1 * w1 + v2 * w2) * n0 / sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+            mincos = fmin(mincos, cs);
+        }
+    }
+    const bool keep = solvable && cnt >= 2 && esum / (double)(cnt > 0 ? cnt : 1) <= max_err && mincos <= cos_min;
+    for (int a = 0; a < 3; ++a) pts_out[3 * (size_t)j + a] = P[a];
+    keep_pt[j] = keep ? 1 : 0;
+    for (uint32_t o = o0; o < o1; ++o) {
+        bool front = false;
+        if (keep) {
+            const int i = (int)pb.obs_cam_dev[o];
+            const double* R = rot + 9 * (size_t)i;
+            const double* c = centre + 3 * (size_t)i;
+            front = R[6] * (P[0] - c[0]) + R[7] * (P[1] - c[1]) + R[8] * (P[2] - c[2]) > 0.0;
+        }
+        keep_obs[o] = front ? 1 : 0;
+    }
+}
+
+// Exclusive scan of 0/1 flags (optionally read through a permutation) into
+// idx[0..n] (idx[n] = total): per-block sums, one workgroup over the block
+// sums, then per-block prefixes.
+constexpr int kFlagBlock = 1024;
+
+__device__ __forceinline__ uint32_t flag_at(const uint8_t* f, const uint32_t* perm, uint32_t i) {
+    return f[perm ? perm[i] : i] ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_flag_sums(const uint8_t* __restrict__ f, const uint32_t* __restrict__ perm,
+                                                   uint32_t n, uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s[4];
+    const uint32_t base = blockIdx.x * kFlagBlock;
+    uint32_t c = 0;
+    for (uint32_t i = base + threadIdx.x; i < min(n, base + kFlagBlock); i += 256) c += flag_at(f, perm, i);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(1024) void k_flag_top(uint32_t* __restrict__ bsum, uint32_t nb) {
+    __shared__ uint32_t s[1024];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < nb ? bsum[i] : 0u;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const uint32_t add = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + s[threadIdx.x] - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_flag_apply(const uint8_t* __restrict__ f, const uint32_t* __restrict__ perm,
+                                                    uint32_t n, const uint32_t* __restrict__ bsum,
+                                                    uint32_t* __restrict__ idx) {
+    __shared__ uint32_t s[4];
+    const uint32_t base = blockIdx.x * kFlagBlock;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t run = bsum[blockIdx.x];
+    for (uint32_t c0 = base; c0 < min(n, base + kFlagBlock); c0 += 256) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t v = i < n ? flag_at(f, perm, i) : 0u;
+        const uint64_t bal = __ballot(v != 0u);
+        if (lane == 0) s[wv] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int w = 0; w < 4; ++w) {
+            before += w < wv ? s[w] : 0u;
+            all += s[w];
+        }
+        if (i < n) idx[i] = run + before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        run += all;
+        __syncthreads();
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) idx[n] = run;
+}
+
+pgs_status flag_scan(const uint8_t* f, const uint32_t* perm, uint32_t n, uint32_t* idx, uint32_t* bsum,
+                     hipStream_t s) {
+    const uint32_t nb = (n + kFlagBlock - 1) / kFlagBlock;
+    if (nb == 0) return PGS_OK;
+    k_flag_sums<<<nb, 256, 0, s>>>(f, perm, n, bsum);
+    k_flag_top<<<1, 1024, 0, s>>>(bsum, nb);
+    k_flag_apply<<<nb, 256, 0, s>>>(f, perm, n, bsum, idx);
+    return PGS_OK;
+}
+
+// Points: kept ones renumbered, their first observation's new index.
+__global__ __launch_bounds__(256) void k_compact_points(int M, const uint8_t* __restrict__ keep_pt,
+                                                        const uint32_t* __restrict__ pidx,
+                                                        const uint32_t* __restrict__ oidx,
+                                                        const uint32_t* __restrict__ point_start,
+                                                        const double* __restrict__ pts, double* __restrict__ pts_out,
+                                                        uint32_t* __restrict__ point_start_out, int O,
+                                                        uint32_t* __restrict__ counts) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < M && keep_pt[j]) {
+        const uint32_t n = pidx[j];
+        for (int a = 0; a < 3; ++a) pts_out[3 * (size_t)n + a] = pts[3 * (size_t)j + a];
+        point_start_out[n] = oidx[point_start[j]];
+    }
+    if (j == 0) {
+        point_start_out[pidx[M]] = oidx[point_start[M]];
+        counts[0] = pidx[M];
+        counts[1] = oidx[O];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_compact_obs(pgs_ba_problem pb, const uint8_t* __restrict__ keep_obs,
+                                                     const uint32_t* __restrict__ oidx,
+                                                     const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ qidx,
+                                                     uint32_t* __restrict__ cam_out, uint32_t* __restrict__ pt_out,
+                                                     double* __restrict__ uv_out, uint32_t* __restrict__ cam_obs_out,
+                                                     uint32_t* __restrict__ cam_start_out) {
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < (uint32_t)pb.n_obs) {
+        if (keep_obs[o]) {
+            const uint32_t n = oidx[o];
+            cam_out[n] = pb.obs_cam_dev[o];
+            pt_out[n] = pidx[pb.obs_pt_dev[o]];
+            uv_out[2 * (size_t)n] = pb.obs_uv_dev[2 * (size_t)o];
+            uv_out[2 * (size_t)n + 1] = pb.obs_uv_dev[2 * (size_t)o + 1];
+        }
+        // o is a position in the by-camera list here
+        const uint32_t ob = pb.cam_obs_dev[o];
+        if (keep_obs[ob]) cam_obs_out[qidx[o]] = oidx[ob];
+    }
+    if (o <= (uint32_t)pb.n_cams) cam_start_out[o] = qidx[pb.cam_start_dev[o]];
+}
+
 // Workspace layout of one problem size.
 struct BaWs {
     double *obs_rec, *pt_rec, *cam_part, *S, *g, *A, *part;
@@ -614,5 +822,67 @@ extern "C" pgs_status pgs_ba_apply(int32_t n_cams, int32_t n_points, const doubl
                                                                    points_dev, dpose_dev, dpoint_dev, rot_out_dev,
                                                                    centre_out_dev, points_out_dev);
     PGS_CHECK_LAUNCH("pgs_ba_apply");
+    return PGS_OK;
+}
+
+extern "C" pgs_status pgs_ba_refine(const pgs_ba_problem* problem, const double* rot_dev, const double* centre_dev,
+                                    double max_err, double min_angle, double* points_out_dev,
+                                    uint8_t* keep_point_dev, uint8_t* keep_obs_dev, void* stream) {
+    if (pgs_status st = check_problem(problem, "pgs_ba_refine")) return st;
+    PGS_REQUIRE(rot_dev && centre_dev && points_out_dev && keep_point_dev && keep_obs_dev,
+                "pgs_ba_refine: null pointer");
+    PGS_REQUIRE(max_err >= 0.0 && min_angle >= 0.0, "pgs_ba_refine: negative threshold");
+    const int M = problem->n_points;
+    k_ba_refine<<<(M + 255) / 256, 256, 0, pgs::as_stream(stream)>>>(*problem, rot_dev, centre_dev, max_err,
+                                                                     cos(min_angle), points_out_dev, keep_point_dev,
+                                                                     keep_obs_dev);
+    PGS_CHECK_LAUNCH("pgs_ba_refine");
+    return PGS_OK;
+}
+
+extern "C" size_t pgs_ba_compact_workspace(int32_t n_points, int32_t n_obs) {
+    if (n_points < 0 || n_obs < 0) return 0;
+    const size_t nb = ((size_t)(n_points > n_obs ? n_points : n_obs) + kFlagBlock - 1) / kFlagBlock + 1;
+    return al(((size_t)n_points + 1) * 4) + 2 * al(((size_t)n_obs + 1) * 4) + 3 * al(nb * 4);
+}
+
+extern "C" pgs_status pgs_ba_compact(const pgs_ba_problem* problem, const uint8_t* keep_point_dev,
+                                     const uint8_t* keep_obs_dev, const double* points_dev,
+                                     uint32_t* obs_cam_out_dev, uint32_t* obs_pt_out_dev, double* obs_uv_out_dev,
+                                     uint32_t* point_start_out_dev, uint32_t* cam_obs_out_dev,
+                                     uint32_t* cam_start_out_dev, double* points_out_dev, uint32_t* counts_out_dev,
+                                     void* workspace_dev, size_t workspace_bytes, void* stream) {
+    if (pgs_status st = check_problem(problem, "pgs_ba_compact")) return st;
+    PGS_REQUIRE(keep_point_dev && keep_obs_dev && points_dev && obs_cam_out_dev && obs_pt_out_dev &&
+                    obs_uv_out_dev && point_start_out_dev && cam_obs_out_dev && cam_start_out_dev &&
+                    points_out_dev && counts_out_dev && workspace_dev, "pgs_ba_compact: null pointer");
+    const int M = problem->n_points, O = problem->n_obs;
+    PGS_REQUIRE(workspace_bytes >= pgs_ba_compact_workspace(M, O), "pgs_ba_compact: workspace %zu < %zu",
+                workspace_bytes, pgs_ba_compact_workspace(M, O));
+    hipStream_t s = pgs::as_stream(stream);
+    char* p = static_cast<char*>(workspace_dev);
+    const size_t nb = ((size_t)(M > O ? M : O) + kFlagBlock - 1) / kFlagBlock + 1;
+    uint32_t* pidx = reinterpret_cast<uint32_t*>(p);
+    p += al(((size_t)M + 1) * 4);
+    uint32_t* oidx = reinterpret_cast<uint32_t*>(p);
+    p += al(((size_t)O + 1) * 4);
+    uint32_t* qidx = reinterpret_cast<uint32_t*>(p);
+    p += al(((size_t)O + 1) * 4);
+    uint32_t* b0 = reinterpret_cast<uint32_t*>(p);
+    p += al(nb * 4);
+    uint32_t* b1 = reinterpret_cast<uint32_t*>(p);
+    p += al(nb * 4);
+    uint32_t* b2 = reinterpret_cast<uint32_t*>(p);
+    flag_scan(keep_point_dev, nullptr, (uint32_t)M, pidx, b0, s);
+    flag_scan(keep_obs_dev, nullptr, (uint32_t)O, oidx, b1, s);
+    flag_scan(keep_obs_dev, problem->cam_obs_dev, (uint32_t)O, qidx, b2, s);
+    k_compact_points<<<(M + 255) / 256, 256, 0, s>>>(M, keep_point_dev, pidx, oidx, problem->point_start_dev,
+                                                     points_dev, points_out_dev, point_start_out_dev, O,
+                                                     counts_out_dev);
+    const int n = (O > problem->n_cams + 1 ? O : problem->n_cams + 1);
+    k_compact_obs<<<(n + 255) / 256, 256, 0, s>>>(*problem, keep_obs_dev, oidx, pidx, qidx, obs_cam_out_dev,
+                                                  obs_pt_out_dev, obs_uv_out_dev, cam_obs_out_dev,
+                                                  cam_start_out_dev);
+    PGS_CHECK_LAUNCH("pgs_ba_compact");
     return PGS_OK;
 }
