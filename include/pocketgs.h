@@ -718,8 +718,9 @@ pgs_status pgs_mvs_select_ref(const pgs_camera* cams_dev, int32_t n_views, const
  * 1/d_k = 1/d_max + k (1/d_min - 1/d_max)/(n_planes - 1)); target pixel
  * (x, y) at d_k maps to X = d_k ((x - cx)/fx, (y - cy)/fy, 1), to the
  * reference as M X + m (M = R_r R_t^T, m = t_r - M t_t) and to its nearest
- * pixel floor(fx x/z + cx + 0.5), likewise y (unfused float64 in a fixed
- * order); cost = Hamming distance of the Census strings, 48 where z <= 0,
+ * pixel floor(fx x/z + cx + 0.5), likewise y (M, m, d_k and the rays are
+ * float64 rounded to float32; the per pixel-plane arithmetic is unfused
+ * float32 in a fixed order); cost = Hamming distance of the Census strings, 48 where z <= 0,
  * the pixel is outside the image or the range is empty.
  * cost_dev [n_targets][height][width][n_planes] uint8.
  */

@@ -26,7 +26,11 @@ count, penalties, path set or confidence measure):
     samples the reference Census at the nearest pixel
     (floor(fx_r x_r / z_r + cx_r + 0.5), likewise y); the cost is the
     Hamming distance of the two Census strings, 48 where z_r <= 0 or the
-    pixel falls outside the reference image;
+    pixel falls outside the reference image.  The paper fixes no precision
+    for the sweep: M, m, d_k and the pixel rays are float64 values rounded
+    to float32, and the per pixel-plane products, sums, quotients and the
+    rounding to the nearest pixel are float32 operations (the kernel's
+    precision for this decision);
   * SGM over 4 paths (left to right, right to left, top to bottom, bottom
     to top) with constant penalties P1, P2:
     L_r(p, k) = C(p, k) + min(L_r(p-r, k), L_r(p-r, k-1) + P1,
@@ -51,8 +55,9 @@ count, penalties, path set or confidence measure):
     pixels back-projected to the world, R_t^T (X - t_t).
 Cameras are the float32-stored intrinsics and [R|t] taken as float64.  The
 decisions that turn floating point into integers (nearest reference pixel,
-inside tests, range membership) are written as explicit float64 operations
-in a fixed order without fused multiply-adds, so that they are reproducible.
+inside tests, range membership) are written as explicit operations in a
+fixed order without fused multiply-adds (float32 for the sweep, float64
+for the range), so that they are reproducible.
 """
 
 from __future__ import annotations
@@ -124,22 +129,25 @@ def relative_pose(cam_t, cam_r):
 def sweep_pixels(cam_t, cam_r, d_min, d_max, n_planes, xs, ys):
     """Nearest reference pixel (qx, qy) and validity for target pixels
     (xs, ys) (1-D arrays) at every plane: arrays (n_planes, n)."""
+    f32 = np.float32
     fx, fy, cx, cy, _, _ = cam64(cam_t)
-    fxr, fyr, cxr, cyr, _, _ = cam64(cam_r)
+    fxr, fyr, cxr, cyr = (f32(v) for v in cam64(cam_r)[:4])
     Wr, Hr = cam_r["width"], cam_r["height"]
     M, m = relative_pose(cam_t, cam_r)
+    M, m = M.astype(f32), m.astype(f32)
     inv, _ = plane_inverse_depths(d_min, d_max, n_planes)
-    d = (1.0 / inv)[:, None]
-    a = ((np.asarray(xs, np.float64) - cx) / fx)[None, :]
-    b = ((np.asarray(ys, np.float64) - cy) / fy)[None, :]
-    X, Y, Z = d * a, d * b, d * np.ones_like(a)
+    d = (1.0 / inv).astype(f32)[:, None]
+    a = ((np.asarray(xs, np.float64) - cx) / fx).astype(f32)[None, :]
+    b = ((np.asarray(ys, np.float64) - cy) / fy).astype(f32)[None, :]
+    X, Y, Z = d * a, d * b, np.broadcast_to(d, (d.shape[0], a.shape[1]))
     xr = M[0, 0] * X + M[0, 1] * Y + M[0, 2] * Z + m[0]
     yr = M[1, 0] * X + M[1, 1] * Y + M[1, 2] * Z + m[1]
     zr = M[2, 0] * X + M[2, 1] * Y + M[2, 2] * Z + m[2]
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        u = np.floor(fxr * (xr / zr) + cxr + 0.5)
-        v = np.floor(fyr * (yr / zr) + cyr + 0.5)
-    ok = (zr > 0) & (u >= 0) & (u <= Wr - 1) & (v >= 0) & (v <= Hr - 1)
+        u = np.floor(fxr * (xr / zr) + cxr + f32(0.5))
+        v = np.floor(fyr * (yr / zr) + cyr + f32(0.5))
+    assert u.dtype == f32 and v.dtype == f32
+    ok = (zr > 0) & (u >= 0) & (u <= f32(Wr - 1)) & (v >= 0) & (v <= f32(Hr - 1))
     qx = np.where(ok, u, 0).astype(np.int64)
     qy = np.where(ok, v, 0).astype(np.int64)
     return qx, qy, ok

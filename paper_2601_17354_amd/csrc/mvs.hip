@@ -13,7 +13,7 @@
 //       exp(-(b - b_target)^2 / (2 sigma_b^2)) max(alpha / alpha_min, 1);
 //   k_census      7 x 7 Census (48 bits) from a 22 x 22 LDS tile;
 //   k_cost<D>     one thread per (pixel, plane): the plane-sweep pixel in the
-//       reference view from float64 arithmetic in a fixed order without
+//       reference view from float32 arithmetic in a fixed order without
 //       contraction (the nearest-pixel decision is reproducible), Hamming
 //       distance of the Census strings; cost volume [y][x][plane] bytes;
 //   k_sgm<KPL, COLS>  one wave per image line sweeps it forward (path costs
@@ -273,9 +273,10 @@ __global__ __launch_bounds__(64) void k_mvs_ref(const pgs_camera* __restrict__ c
 constexpr int kCostPix = 32;  // pixels per cost workgroup
 
 // Workgroup: kCostPix consecutive pixels of one target, all D planes; thread
-// (slot, k) handles plane k for pixels slot, slot + 256/D, ...  The plane
-// depth d_k is computed once per thread, the pixel rays ((x - cx)/fx,
-// (y - cy)/fy) once per pixel in LDS.
+// (slot, k) handles plane k for pixels slot, slot + 256/D, ...  The relative
+// pose, the plane depth d_k and the pixel rays are float64 values rounded
+// to float32 (d_k once per thread, the rays once per pixel in LDS); the per
+// pixel-plane sweep is unfused float32 in a fixed order.
 template <int D>
 __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cams, int W, int H,
                                               const uint64_t* __restrict__ census,
@@ -283,8 +284,8 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
                                               const double* __restrict__ range, uint8_t* __restrict__ cost) {
 #pragma clang fp contract(off)
     constexpr int SL = 256 / D > 0 ? 256 / D : 1;  // pixel slots per pass
-    __shared__ double s_pose[20];  // M, m, the reference intrinsics
-    __shared__ double s_a[kCostPix], s_b[kCostPix];
+    __shared__ float s_pose[16];  // M, m, the reference intrinsics
+    __shared__ float s_a[kCostPix], s_b[kCostPix];
     __shared__ uint64_t s_cen[kCostPix];
     const int t = threadIdx.x, ti = blockIdx.y, tv = targets[ti], rv = refs[tv];
     const uint32_t npix = (uint32_t)W * (uint32_t)H, base = blockIdx.x * kCostPix;
@@ -295,19 +296,20 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
             for (int j = 0; j < 3; ++j)
                 M[3 * i + j] = cr.R[3 * i] * ct.R[3 * j] + cr.R[3 * i + 1] * ct.R[3 * j + 1] +
                                cr.R[3 * i + 2] * ct.R[3 * j + 2];
-        for (int i = 0; i < 9; ++i) s_pose[i] = M[i];
+        for (int i = 0; i < 9; ++i) s_pose[i] = (float)M[i];
         for (int i = 0; i < 3; ++i)
-            s_pose[9 + i] = cr.t[i] - (M[3 * i] * ct.t[0] + M[3 * i + 1] * ct.t[1] + M[3 * i + 2] * ct.t[2]);
-        s_pose[12] = cr.fx;
-        s_pose[13] = cr.fy;
-        s_pose[14] = cr.cx;
-        s_pose[15] = cr.cy;
+            s_pose[9 + i] =
+                (float)(cr.t[i] - (M[3 * i] * ct.t[0] + M[3 * i + 1] * ct.t[1] + M[3 * i + 2] * ct.t[2]));
+        s_pose[12] = cams[rv].fx;
+        s_pose[13] = cams[rv].fy;
+        s_pose[14] = cams[rv].cx;
+        s_pose[15] = cams[rv].cy;
     }
     if (t < kCostPix && base + t < npix) {
         const pgs_camera& c = cams[tv];
         const uint32_t pix = base + t, y = pix / (uint32_t)W, x = pix - y * (uint32_t)W;
-        s_a[t] = ((double)x - (double)c.cx) / (double)c.fx;
-        s_b[t] = ((double)y - (double)c.cy) / (double)c.fy;
+        s_a[t] = (float)(((double)x - (double)c.cx) / (double)c.fx);
+        s_b[t] = (float)(((double)y - (double)c.cy) / (double)c.fy);
         s_cen[t] = census[(size_t)tv * npix + pix];
     }
     __syncthreads();
@@ -315,26 +317,27 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
     const int k = t % D, slot = t / D;
     const double d_min = range[2 * tv], d_max = range[2 * tv + 1];
     const bool ranged = d_min > 0.0 && d_max > d_min;
-    double d = 0.0;
+    float d = 0.0f;
     if (ranged) {
         const double inv_far = 1.0 / d_max;
         const double h = (1.0 / d_min - inv_far) / (double)(D - 1);
-        d = 1.0 / (inv_far + (double)k * h);
+        d = (float)(1.0 / (inv_far + (double)k * h));
     }
-    const double* M = s_pose;
+    const float* M = s_pose;
+    const float wmax = (float)(W - 1), hmax = (float)(H - 1);
     const uint64_t* rc = census + (size_t)rv * npix;
     uint8_t* out = cost + ((size_t)ti * npix + base) * D + k;
     for (int i = slot; i < kCostPix; i += SL) {
         if (base + i >= npix) break;
         int c = kCostOut;
         if (ranged) {
-            const double X = d * s_a[i], Y = d * s_b[i], Z = d;
-            const double xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
-            const double yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
-            const double zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
-            const double u = floor(M[12] * (xr / zr) + M[14] + 0.5);
-            const double v = floor(M[13] * (yr / zr) + M[15] + 0.5);
-            if (zr > 0.0 && u >= 0.0 && u <= (double)(W - 1) && v >= 0.0 && v <= (double)(H - 1))
+            const float X = d * s_a[i], Y = d * s_b[i], Z = d;
+            const float xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
+            const float yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
+            const float zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
+            const float u = floorf(M[12] * (xr / zr) + M[14] + 0.5f);
+            const float v = floorf(M[13] * (yr / zr) + M[15] + 0.5f);
+            if (zr > 0.0f && u >= 0.0f && u <= wmax && v >= 0.0f && v <= hmax)
                 c = __popcll(s_cen[i] ^ rc[(size_t)v * W + (size_t)u]);
         }
         out[(size_t)i * D] = (uint8_t)c;
