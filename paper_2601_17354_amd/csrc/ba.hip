@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, d
     // - H_tp H_pp^-1 H_pt and - H_tp v over this split of camera i's observations
     const uint32_t chunk = (c1 - c0 + kCamSplit - 1) / kCamSplit;
     const uint32_t q0 = c0 + split * chunk, q1 = min(c1, q0 + chunk);
+    double gl[6] = {0, 0, 0, 0, 0, 0};  // this lane's share of - H_tp v
     for (uint32_t q = q0 + t; q < q1; q += kCamThreads) {
         const uint32_t o = pb.cam_obs_dev[q];
         const uint32_t j = pb.obs_pt_dev[o];
@@ -212,9 +213,13 @@ __global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, d
         for (int a = 0; a < 6; ++a)
             for (int b = 0; b < 3; ++b)
                 T[a][b] = Htp[3 * a] * pr[b] + Htp[3 * a + 1] * pr[3 + b] + Htp[3 * a + 2] * pr[6 + b];
-        for (int a = 0; a < 6; ++a)
-            atomicAdd(&gi[a], -(Htp[3 * a] * pr[9] + Htp[3 * a + 1] * pr[10] + Htp[3 * a + 2] * pr[11]));
-        for (uint32_t o2 = pb.point_start_dev[j]; o2 < pb.point_start_dev[j + 1]; ++o2) {
+        for (int a = 0; a < 6; ++a) gl[a] -= Htp[3 * a] * pr[9] + Htp[3 * a + 1] * pr[10] + Htp[3 * a + 2] * pr[11];
+        // the track is walked from a lane-dependent start so that the lanes
+        // of a wave add into different camera blocks at the same time
+        const uint32_t s0 = pb.point_start_dev[j], nt = pb.point_start_dev[j + 1] - s0;
+        for (uint32_t r = 0; r < nt; ++r) {
+            uint32_t o2 = s0 + r + (uint32_t)lane % nt;
+            if (o2 >= s0 + nt) o2 -= nt;
             const int k = (int)pb.obs_cam_dev[o2];
             const double* H2 = obs_rec + (size_t)o2 * kObsRec;
             for (int a = 0; a < 6; ++a)
@@ -222,6 +227,10 @@ __global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, d
                     atomicAdd(&row[a * n6 + 6 * k + b],
                               -(T[a][0] * H2[3 * b] + T[a][1] * H2[3 * b + 1] + T[a][2] * H2[3 * b + 2]));
         }
+    }
+    for (int a = 0; a < 6; ++a) {
+        const double v = wave_sum_f64(gl[a]);
+        if (lane == 0) atomicAdd(&gi[a], v);
     }
     __syncthreads();
     double* out = part + ((size_t)i * kCamSplit + split) * (6 * n6 + 6);
