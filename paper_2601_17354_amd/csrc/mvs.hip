@@ -22,9 +22,9 @@
 //       ahead); per step the previous costs' minimum is a DPP wave reduction
 //       and the neighbouring planes come from DPP wave shifts.  The row
 //       kernel writes the two row paths' sum; the column kernel adds both
-//       column paths to it and takes the winner and the confidence-test sums
-//       per pixel (lane = step mod 64), turned into refined depths 64 pixels
-//       at a time, without storing the total;
+//       column paths to it, stages the totals of 64 steps in an LDS ring and
+//       lets each lane take the winner, the confidence test and the refined
+//       depth of one of those pixels, without storing the total;
 //   k_fuse_*      per-row counts, one scan over rows and the back-projection
 //       of the kept pixels in row-major order.
 
@@ -461,9 +461,11 @@ struct LanePack {
 // (recorded in lane step mod 64 and turned into refined depths 64 pixels
 // at a time).
 enum SweepMode { kForward = 0, kRowsBack = 1, kColsBack = 2 };
+constexpr int kSgmRing = 32;  // column steps staged in LDS per wave
 
 template <int KPL, int MODE>
-__device__ __forceinline__ void sgm_sweep(const SgmArgs& a, int line, int ti, bool rows, bool rev) {
+__device__ __forceinline__ void sgm_sweep(const SgmArgs& a, int line, int ti, bool rows, bool rev,
+                                          uint16_t* ring) {
 #pragma clang fp contract(off)
     constexpr int D = 64 * KPL;
     constexpr int kBig = 1 << 28;
@@ -498,20 +500,62 @@ __device__ __forceinline__ void sgm_sweep(const SgmArgs& a, int line, int ti, bo
             if (MODE == kColsBack) g = LP::load_sums(abase + e);
         }
     };
-    int r_k = 0, r_s1 = 0, r_s2 = 0, r_m = 0, r_q = 0;
+    // column back sweep: the full sums of kSgmRing consecutive steps sit in
+    // this wave's LDS ring (row = step mod kSgmRing, D + 2 uint16 per row so
+    // that the lanes' rows fall in different banks); lanes p and p + 32 then
+    // take the winner, the second minimum two planes away and the winner's
+    // neighbours of step p over one half of the planes each, combined by a
+    // lane swap, and lane p writes that pixel's depth and confidence
+    constexpr int RS = D + 2;
+    constexpr int RING = kSgmRing;
     auto flush = [&](int s_first, int count) {
-        if (lane < count) {
-            const bool keep = r_k > 0 && r_k < D - 1 && r_s2 > 0 && (double)r_s1 <= a.keep_ratio * (double)r_s2;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lanes p and p + 32 take step p, each over half of the planes
+        const int px = lane & 31, half = lane >> 5;
+        const bool act = px < count;
+        const uint32_t* r = reinterpret_cast<const uint32_t*>(ring + px * RS) + half * (D / 4);
+        const int k0 = half * (D / 2);
+        int key = kBig;  // (sum << 8) | plane, smallest first
+        if (act) {
+#pragma unroll 4
+            for (int c = 0; c < D / 4; ++c) {
+                const uint32_t w = r[c];
+                key = min(key, (int)((w & 0xffffu) << 8) | (k0 + 2 * c));
+                key = min(key, (int)((w >> 16) << 8) | (k0 + 2 * c + 1));
+            }
+        }
+        key = min(key, __shfl_xor(key, 32));
+        const int s1 = key >> 8, kw = key & 255;
+        int s2 = kBig;
+        if (act) {
+#pragma unroll 4
+            for (int c = 0; c < D / 4; ++c) {
+                const uint32_t w = r[c];
+                const int ka = k0 + 2 * c, kb = ka + 1;
+                if (ka - kw >= 2 || kw - ka >= 2) s2 = min(s2, (int)(w & 0xffffu));
+                if (kb - kw >= 2 || kw - kb >= 2) s2 = min(s2, (int)(w >> 16));
+            }
+        }
+        s2 = min(s2, __shfl_xor(s2, 32));
+        if (act && half == 0) {
+            const uint16_t* rh = ring + px * RS;
+            const int vm = rh[kw > 0 ? kw - 1 : 0], vq = rh[kw < D - 1 ? kw + 1 : D - 1];
+            const bool keep = kw > 0 && kw < D - 1 && s2 > 0 && (double)s1 <= a.keep_ratio * (double)s2;
             float dout = 0.0f;
             if (keep) {
-                const int den = r_m - 2 * r_s1 + r_q;
-                const double delta = den > 0 ? (double)(r_m - r_q) / (2.0 * (double)den) : 0.0;
-                dout = (float)(1.0 / (inv_far + ((double)r_k + delta) * h));
+                const int den = vm - 2 * s1 + vq;
+                const double delta = den > 0 ? (double)(vm - vq) / (2.0 * (double)den) : 0.0;
+                dout = (float)(1.0 / (inv_far + ((double)kw + delta) * h));
             }
-            const size_t o = (size_t)ti * npix + (size_t)(p0 + dp * (s_first + lane));
+            const size_t o = (size_t)ti * npix + (size_t)(p0 + dp * (s_first + px));
             a.depth[o] = dout;
-            a.conf[o] = r_s2 > 0 ? (float)(1.0 - (double)r_s1 / (double)r_s2) : 0.0f;
+            a.conf[o] = s2 > 0 ? (float)(1.0 - (double)s1 / (double)s2) : 0.0f;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 #pragma unroll
     for (int q = 0; q < PF; ++q) load(q, cc[q], fc[q], ac[q]);
@@ -558,37 +602,14 @@ __device__ __forceinline__ void sgm_sweep(const SgmArgs& a, int line, int ti, bo
 #pragma unroll
                 for (int j = 0; j < KPL; ++j) S[j] = LP::sum(ac[q], j) + LP::cost(fc[q], j) + L[j];
                 if (a.agg_total) LP::store(abase + e, S);
-                // winner: smallest sum, then smallest plane
-                int key = (S[0] << 8) | (KPL * lane);
+                uint16_t* rw = ring + (s & (RING - 1)) * RS + KPL * lane;
+                if (KPL == 2) {
+                    *reinterpret_cast<uint32_t*>(rw) = (uint32_t)S[0] | ((uint32_t)S[1] << 16);
+                } else {
 #pragma unroll
-                for (int j = 1; j < KPL; ++j) key = min(key, (S[j] << 8) | (KPL * lane + j));
-                key = wave_min_all(key);
-                const int s1 = key >> 8, kw = key & 255;
-                int s2 = kBig;
-#pragma unroll
-                for (int j = 0; j < KPL; ++j) {
-                    const int kk = KPL * lane + j;
-                    if (kk - kw >= 2 || kw - kk >= 2) s2 = min(s2, S[j]);
+                    for (int j = 0; j < KPL; ++j) rw[j] = (uint16_t)S[j];
                 }
-                s2 = wave_min_all(s2);
-                const int km = max(kw - 1, 0), kq = min(kw + 1, D - 1);
-                const int jm = km % KPL, jq = kq % KPL;
-                int vm = S[0], vq = S[0];
-#pragma unroll
-                for (int j = 1; j < KPL; ++j) {
-                    if (jm == j) vm = S[j];
-                    if (jq == j) vq = S[j];
-                }
-                vm = __builtin_amdgcn_readlane(vm, km / KPL);
-                vq = __builtin_amdgcn_readlane(vq, kq / KPL);
-                if (lane == (s & 63)) {
-                    r_k = kw;
-                    r_s1 = s1;
-                    r_s2 = s2;
-                    r_m = vm;
-                    r_q = vq;
-                }
-                if ((s & 63) == 63 || s == n - 1) flush(s & ~63, (s & 63) + 1);
+                if ((s & (RING - 1)) == RING - 1 || s == n - 1) flush(s & ~(RING - 1), (s & (RING - 1)) + 1);
             }
         }
 #pragma unroll
@@ -606,12 +627,17 @@ __device__ __forceinline__ void sgm_sweep(const SgmArgs& a, int line, int ti, bo
 // workgroup; the second sweep reads what the same wave stored.
 template <int KPL, bool COLS>
 __global__ __launch_bounds__(256) void k_sgm(SgmArgs a) {
+    extern __shared__ uint16_t sgm_ring[];  // columns: [4 waves][kSgmRing steps][64 KPL + 2]
     const int line = blockIdx.x * 4 + (threadIdx.x >> 6), ti = blockIdx.y;
     if (line >= (COLS ? a.W : a.H)) return;
-    sgm_sweep<KPL, kForward>(a, line, ti, !COLS, false);
-    if (COLS) sgm_sweep<KPL, kColsBack>(a, line, ti, false, true);
-    else sgm_sweep<KPL, kRowsBack>(a, line, ti, true, true);
+    uint16_t* ring = sgm_ring + (threadIdx.x >> 6) * kSgmRing * (64 * KPL + 2);
+    sgm_sweep<KPL, kForward>(a, line, ti, !COLS, false, ring);
+    if (COLS) sgm_sweep<KPL, kColsBack>(a, line, ti, false, true, ring);
+    else sgm_sweep<KPL, kRowsBack>(a, line, ti, true, true, ring);
 }
+
+template <int KPL>
+constexpr size_t sgm_ring_bytes() { return (size_t)4 * kSgmRing * (64 * KPL + 2) * sizeof(uint16_t); }
 
 // ---------------------------------------------------------------- fusion
 
@@ -704,8 +730,12 @@ pgs_status check_params(const pgs_mvs_params* p, const char* who) {
 
 template <int KPL>
 pgs_status launch_sgm(SgmArgs a, int n_targets, hipStream_t s) {
+    static const bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_sgm<KPL, true>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)sgm_ring_bytes<KPL>()) == hipSuccess;
+    PGS_REQUIRE(lds_ok, "pgs_mvs_sgm: cannot reserve %zu bytes of LDS", sgm_ring_bytes<KPL>());
     k_sgm<KPL, false><<<dim3((a.H + 3) / 4, n_targets), 256, 0, s>>>(a);
-    k_sgm<KPL, true><<<dim3((a.W + 3) / 4, n_targets), 256, 0, s>>>(a);
+    k_sgm<KPL, true><<<dim3((a.W + 3) / 4, n_targets), 256, sgm_ring_bytes<KPL>(), s>>>(a);
     PGS_CHECK_LAUNCH("pgs_mvs_sgm");
     return PGS_OK;
 }
