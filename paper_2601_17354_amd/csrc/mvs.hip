@@ -270,7 +270,7 @@ __global__ __launch_bounds__(64) void k_mvs_ref(const pgs_camera* __restrict__ c
 
 // ---------------------------------------------------------------- cost volume
 
-constexpr int kCostPix = 32;  // pixels per cost workgroup
+constexpr int kCostPix = 128;  // pixels per cost workgroup
 
 // Workgroup: kCostPix consecutive pixels of one target, all D planes; thread
 // (slot, k) handles plane k for pixels slot, slot + 256/D, ...  The relative
@@ -305,12 +305,13 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
         s_pose[14] = cams[rv].cx;
         s_pose[15] = cams[rv].cy;
     }
-    if (t < kCostPix && base + t < npix) {
+    for (int q = t; q < kCostPix; q += blockDim.x) {
+        if (base + q >= npix) break;
         const pgs_camera& c = cams[tv];
-        const uint32_t pix = base + t, y = pix / (uint32_t)W, x = pix - y * (uint32_t)W;
-        s_a[t] = (float)(((double)x - (double)c.cx) / (double)c.fx);
-        s_b[t] = (float)(((double)y - (double)c.cy) / (double)c.fy);
-        s_cen[t] = census[(size_t)tv * npix + pix];
+        const uint32_t pix = base + q, y = pix / (uint32_t)W, x = pix - y * (uint32_t)W;
+        s_a[q] = (float)(((double)x - (double)c.cx) / (double)c.fx);
+        s_b[q] = (float)(((double)y - (double)c.cy) / (double)c.fy);
+        s_cen[q] = census[(size_t)tv * npix + pix];
     }
     __syncthreads();
     if (t >= SL * D) return;
@@ -327,20 +328,34 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
     const float wmax = (float)(W - 1), hmax = (float)(H - 1);
     const uint64_t* rc = census + (size_t)rv * npix;
     uint8_t* out = cost + ((size_t)ti * npix + base) * D + k;
-    for (int i = slot; i < kCostPix; i += SL) {
-        if (base + i >= npix) break;
-        int c = kCostOut;
-        if (ranged) {
-            const float X = d * s_a[i], Y = d * s_b[i], Z = d;
-            const float xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
-            const float yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
-            const float zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
-            const float u = floorf(M[12] * (xr / zr) + M[14] + 0.5f);
-            const float v = floorf(M[13] * (yr / zr) + M[15] + 0.5f);
-            if (zr > 0.0f && u >= 0.0f && u <= wmax && v >= 0.0f && v <= hmax)
-                c = __popcll(s_cen[i] ^ rc[(size_t)v * W + (size_t)u]);
+    // four pixels per round with their gathers issued together: an invalid
+    // sample reads the reference's pixel 0 and is replaced by the out cost
+    static_assert(kCostPix % (4 * SL) == 0, "pixel rounds must tile the workgroup");
+    for (int i0 = slot; i0 < kCostPix; i0 += 4 * SL) {
+        uint64_t g[4];
+        bool ok[4];
+#pragma unroll
+        for (int u4 = 0; u4 < 4; ++u4) {
+            const int i = i0 + u4 * SL;
+            ok[u4] = false;
+            size_t idx = 0;
+            if (ranged && base + i < npix) {
+                const float X = d * s_a[i], Y = d * s_b[i], Z = d;
+                const float xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
+                const float yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
+                const float zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
+                const float u = floorf(M[12] * (xr / zr) + M[14] + 0.5f);
+                const float v = floorf(M[13] * (yr / zr) + M[15] + 0.5f);
+                ok[u4] = zr > 0.0f && u >= 0.0f && u <= wmax && v >= 0.0f && v <= hmax;
+                if (ok[u4]) idx = (size_t)v * W + (size_t)u;
+            }
+            g[u4] = rc[idx];
         }
-        out[(size_t)i * D] = (uint8_t)c;
+#pragma unroll
+        for (int u4 = 0; u4 < 4; ++u4) {
+            const int i = i0 + u4 * SL;
+            if (base + i < npix) out[(size_t)i * D] = (uint8_t)(ok[u4] ? __popcll(s_cen[i] ^ g[u4]) : kCostOut);
+        }
     }
 }
 
