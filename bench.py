@@ -309,7 +309,7 @@ def mvs_runs(width=960, height=720, n_targets=8, iters=5):
     grey_d = torch.as_tensor(grey, device="cuda")
     tg = torch.as_tensor(np.int32(targets), device="cuda")
     cap = n_targets * width * height
-    cloud = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+    cloud = torch.empty((3, cap), dtype=torch.float32, device="cuda")
     from paper_2601_17354_amd import _lib
     rng_ws = torch.empty(_lib.load().pgs_mvs_range_workspace(60, pts.shape[0]), dtype=torch.uint8, device="cuda")
     stages = ["census", "range", "reference", "cost", "sgm", "fuse"]

@@ -756,14 +756,19 @@ size_t pgs_mvs_fuse_workspace(int32_t n_targets, int32_t height);
 
 /*
  * pgs_mvs_fuse - fusion into the dense cloud P: the kept pixels (depth > 0)
- * of each target view, in target order and row-major pixel order,
- * back-projected to the world, R^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t),
- * into points_dev [capacity][3] float32; *count_dev = the number of kept
- * pixels (points beyond capacity are not written).
+ * of each target view, numbered in target order and row-major pixel order,
+ * back-projected to the world, R^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t);
+ * kept pixel i becomes point i / stride when stride divides i, written to
+ * points_dev [3][capacity] float32 (the point-cloud layout of pgs_knn and
+ * pgs_pca_seed) and, when colour_dev is given, its intensity
+ * grey_dev[view][y][x] / 255 to all three rows of colour_dev [3][capacity].
+ * *count_dev = the number of kept pixels (points beyond capacity are not
+ * written).
  */
 pgs_status pgs_mvs_fuse(const pgs_camera* cams_dev, const int32_t* targets_dev, int32_t n_targets, int32_t width,
-                        int32_t height, const float* depth_dev, float* points_dev, uint32_t capacity,
-                        uint32_t* count_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
+                        int32_t height, const float* depth_dev, const uint8_t* grey_dev, uint32_t stride,
+                        float* points_dev, float* colour_dev, uint32_t capacity, uint32_t* count_dev,
+                        void* workspace_dev, size_t workspace_bytes, void* stream);
 
 /*
  * pgs_stream_copy - plain streaming copy of `bytes` (a multiple of 16, both

@@ -52,7 +52,9 @@ count, penalties, path set or confidence measure):
     wider angles, the baseline term keeps the choice near b_target);
     argmax, smallest index on ties;
   * fusion: the union, view by view in row-major pixel order, of the kept
-    pixels back-projected to the world, R_t^T (X - t_t).
+    pixels back-projected to the world, R_t^T (X - t_t), each with its
+    image intensity as colour (greyscale captures); every stride-th point
+    of that sequence is kept when the cloud is thinned for seeding.
 Cameras are the float32-stored intrinsics and [R|t] taken as float64.  The
 decisions that turn floating point into integers (nearest reference pixel,
 inside tests, range membership) are written as explicit operations in a
@@ -267,14 +269,18 @@ def select_reference(cams, target, b_target, sigma_b, alpha_min):
     return int(np.argmax(scores)), scores
 
 
-def fuse(cam, depth):
+def fuse(cam, depth, grey=None):
     """World points (float32, (n, 3)) of the kept pixels of one depth map,
-    row-major: R^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t)."""
+    row-major: R^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t); with the view's
+    grey image also their intensities / 255 (float32, (n,))."""
     fx, fy, cx, cy, R, t = cam64(cam)
     ys, xs = np.nonzero(depth > 0)
     z = depth[ys, xs].astype(np.float64)
     Xc = np.stack([z * ((xs - cx) / fx), z * ((ys - cy) / fy), z], 1) - t
-    return (Xc @ R).astype(np.float32)
+    P = (Xc @ R).astype(np.float32)
+    if grey is None:
+        return P
+    return P, (np.asarray(grey)[ys, xs].astype(np.float32) / np.float32(255.0))
 
 
 def depth_map(grey_t, grey_r, cam_t, cam_r, d_min, d_max, n_planes, p1, p2, conf_min=CONF_MIN):

@@ -138,7 +138,7 @@ SIGNATURES = {
                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "pgs_mvs_fuse_workspace": (c_size_t, [c_int32, c_int32]),
     "pgs_mvs_fuse": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_uint32,
-                               c_void_p, c_void_p, c_size_t, c_void_p]),
+                               c_void_p, c_void_p, c_uint32, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 _lib = None

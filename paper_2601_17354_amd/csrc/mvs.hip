@@ -694,11 +694,15 @@ __global__ __launch_bounds__(1024) void k_fuse_scan(uint32_t* __restrict__ rows,
     if (threadIdx.x == 0) *total = carry;
 }
 
+// Kept pixel number idx (row-major over the targets) becomes point idx / stride
+// when idx is a multiple of stride: world position into out [3][capacity]
+// and, with grey given, its intensity / 255 into colour [3][capacity].
 __global__ __launch_bounds__(256) void k_fuse_write(const pgs_camera* __restrict__ cams,
                                                     const int32_t* __restrict__ targets, int W, int H,
                                                     const float* __restrict__ depth,
-                                                    const uint32_t* __restrict__ rowoff, float* __restrict__ out,
-                                                    uint32_t capacity) {
+                                                    const uint32_t* __restrict__ rowoff, const uint8_t* __restrict__ grey,
+                                                    uint32_t stride, float* __restrict__ out,
+                                                    float* __restrict__ colour, uint32_t capacity) {
     __shared__ uint32_t wcnt[4];
     const size_t row = blockIdx.x;
     const int ti = (int)(row / H), y = (int)(row - (size_t)ti * H);
@@ -719,12 +723,18 @@ __global__ __launch_bounds__(256) void k_fuse_write(const pgs_camera* __restrict
             all += wcnt[w];
         }
         const uint32_t idx = base + before + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
-        if (keep && idx < capacity) {
+        const uint32_t o = idx / stride;
+        if (keep && idx == o * stride && o < capacity) {
             const double zz = z;
             const double X = zz * (((double)x - c.cx) / c.fx) - c.t[0];
             const double Y = zz * (((double)y - c.cy) / c.fy) - c.t[1];
             const double Z = zz - c.t[2];
-            for (int k = 0; k < 3; ++k) out[3 * (size_t)idx + k] = (float)(c.R[k] * X + c.R[3 + k] * Y + c.R[6 + k] * Z);
+            for (int k = 0; k < 3; ++k)
+                out[(size_t)k * capacity + o] = (float)(c.R[k] * X + c.R[3 + k] * Y + c.R[6 + k] * Z);
+            if (colour) {
+                const float v = (float)grey[((size_t)targets[ti] * H + y) * W + x] / 255.0f;
+                for (int k = 0; k < 3; ++k) colour[(size_t)k * capacity + o] = v;
+            }
         }
         base += all;
         __syncthreads();
@@ -880,11 +890,12 @@ extern "C" size_t pgs_mvs_fuse_workspace(int32_t n_targets, int32_t height) {
 }
 
 extern "C" pgs_status pgs_mvs_fuse(const pgs_camera* cams_dev, const int32_t* targets_dev, int32_t n_targets,
-                                   int32_t width, int32_t height, const float* depth_dev, float* points_dev,
-                                   uint32_t capacity, uint32_t* count_dev, void* workspace_dev,
-                                   size_t workspace_bytes, void* stream) {
-    PGS_REQUIRE(n_targets >= 0 && width > 0 && height > 0, "pgs_mvs_fuse: bad size");
+                                   int32_t width, int32_t height, const float* depth_dev, const uint8_t* grey_dev,
+                                   uint32_t stride, float* points_dev, float* colour_dev, uint32_t capacity,
+                                   uint32_t* count_dev, void* workspace_dev, size_t workspace_bytes, void* stream) {
+    PGS_REQUIRE(n_targets >= 0 && width > 0 && height > 0 && stride >= 1, "pgs_mvs_fuse: bad size or stride");
     PGS_REQUIRE(count_dev, "pgs_mvs_fuse: null count");
+    PGS_REQUIRE(!colour_dev || grey_dev, "pgs_mvs_fuse: colours need the grey images");
     hipStream_t s = pgs::as_stream(stream);
     if (n_targets == 0) {
         k_mvs_clear<<<1, 256, 0, s>>>(count_dev, 1);
@@ -899,8 +910,8 @@ extern "C" pgs_status pgs_mvs_fuse(const pgs_camera* cams_dev, const int32_t* ta
     uint32_t* rowcnt = static_cast<uint32_t*>(workspace_dev);
     k_fuse_count<<<(unsigned)rows, 256, 0, s>>>(depth_dev, width, rowcnt);
     k_fuse_scan<<<1, 1024, 0, s>>>(rowcnt, (int)rows, count_dev);
-    k_fuse_write<<<(unsigned)rows, 256, 0, s>>>(cams_dev, targets_dev, width, height, depth_dev, rowcnt, points_dev,
-                                                capacity);
+    k_fuse_write<<<(unsigned)rows, 256, 0, s>>>(cams_dev, targets_dev, width, height, depth_dev, rowcnt, grey_dev,
+                                                stride, points_dev, colour_dev, capacity);
     PGS_CHECK_LAUNCH("pgs_mvs_fuse");
     return PGS_OK;
 }

@@ -120,15 +120,20 @@ def pgs_mvs_sgm(cost, targets, rng, params: MVSParams, depth, conf, agg_out=None
           "pgs_mvs_sgm")
 
 
-def pgs_mvs_fuse(cams_dev, targets, depth, points, count, workspace=None):
+def pgs_mvs_fuse(cams_dev, targets, depth, points, count, workspace=None, grey=None, colours=None, stride=1):
+    """points (and colours): [3][capacity] float32; count: one int32."""
     T, H, W = depth.shape
+    cap = points.shape[1]
+    assert points.shape[0] == 3 and (colours is None or colours.shape == points.shape)
     lib = _lib.load()
     need = lib.pgs_mvs_fuse_workspace(T, H)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=depth.device)
+    nul = ctypes.c_void_p(0)
     check(lib.pgs_mvs_fuse(_p(cams_dev, torch.uint8), _p(targets, torch.int32), T, W, H, _p(depth, torch.float32),
-                           _p(points, torch.float32), points.shape[0], _p(count, torch.int32), _p(workspace),
-                           workspace.numel(), _stream()), "pgs_mvs_fuse")
+                           _p(grey, torch.uint8) if grey is not None else nul, int(stride), _p(points, torch.float32),
+                           _p(colours, torch.float32) if colours is not None else nul, cap, _p(count, torch.int32),
+                           _p(workspace), workspace.numel(), _stream()), "pgs_mvs_fuse")
 
 
 class MVS:
@@ -175,9 +180,11 @@ class MVS:
                     workspace=self.sgm_ws)
         return self.depth[:T]
 
-    def fuse(self, targets, points):
+    def fuse(self, targets, points, grey=None, colours=None, stride=1):
         """Kept pixels of the last depth maps back-projected into `points`
-        (capacity = its rows); returns the device count."""
+        ([3][capacity]; every stride-th kept pixel, with its intensity in
+        `colours` when given); returns the device count of kept pixels."""
         T = targets.numel()
-        pgs_mvs_fuse(self.cams_dev, targets, self.depth[:T], points, self.count, workspace=self.fuse_ws)
+        pgs_mvs_fuse(self.cams_dev, targets, self.depth[:T], points, self.count, workspace=self.fuse_ws, grey=grey,
+                     colours=colours, stride=stride)
         return self.count

@@ -152,21 +152,29 @@ def test_fuse_matches_oracle():
     W, H = 96, 72
     scene = synth.spheres_planes_scene(0)
     cams = synth.ring_cameras(60, W, H)
-    _, dep = synth.textured_views(scene, [cams[4], cams[9]], seed=1)
+    g, dep = synth.textured_views(scene, [cams[4], cams[9]], seed=1)
     dep[0][::3] = 0.0                                          # holes
     targets = [4, 9]
+    grey = np.zeros((60, H, W), np.uint8)
+    grey[4], grey[9] = g[0], g[1]
     cd = mvs.cameras_tensor(cams)
-    want = np.concatenate([omvs.fuse(cams[4], dep[0]), omvs.fuse(cams[9], dep[1])])
-    for cap in (want.shape[0] + 5, want.shape[0] // 2):
-        pts = torch.full((cap, 3), -7.0, dtype=torch.float32, device="cuda")
+    f0, f1 = omvs.fuse(cams[4], dep[0], g[0]), omvs.fuse(cams[9], dep[1], g[1])
+    want = np.concatenate([f0[0], f1[0]])
+    wcol = np.concatenate([f0[1], f1[1]])
+    for cap, stride in ((want.shape[0] + 5, 1), (want.shape[0] // 2, 1), (want.shape[0], 7)):
+        pts = torch.full((3, cap), -7.0, dtype=torch.float32, device="cuda")
+        col = torch.full((3, cap), -7.0, dtype=torch.float32, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
-        mvs.pgs_mvs_fuse(cd, torch.as_tensor(np.int32(targets), device="cuda"),
-                         torch.as_tensor(dep, device="cuda"), pts, cnt)
+        mvs.pgs_mvs_fuse(cd, torch.as_tensor(np.int32(targets), device="cuda"), torch.as_tensor(dep, device="cuda"),
+                         pts, cnt, grey=torch.as_tensor(grey, device="cuda"), colours=col, stride=stride)
         assert int(cnt.item()) == want.shape[0]
-        got = pts.cpu().numpy()
-        n = min(cap, want.shape[0])
-        np.testing.assert_allclose(got[:n], want[:n], rtol=1e-6, atol=1e-6)
-        assert (got[n:] == -7.0).all()
+        sel = np.arange(0, want.shape[0], stride)
+        n = min(cap, sel.size)
+        got, gc = pts.cpu().numpy(), col.cpu().numpy()
+        np.testing.assert_allclose(got[:, :n].T, want[sel[:n]], rtol=1e-6, atol=1e-6)
+        for k in range(3):
+            np.testing.assert_array_equal(gc[k, :n], wcol[sel[:n]])
+        assert (got[:, n:] == -7.0).all() and (gc[:, n:] == -7.0).all()
 
 
 @pytest.mark.timeout(900)
