@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--ba-only", action="store_true", help="only the bundle-adjustment measurement")
     ap.add_argument("--no-mvs", action="store_true", help="skip the multi-view stereo measurement")
     ap.add_argument("--mvs-only", action="store_true", help="only the multi-view stereo measurement")
+    ap.add_argument("--no-capture", action="store_true", help="skip the captures-to-model run")
+    ap.add_argument("--capture-only", action="store_true", help="only the captures-to-model run")
     ap.add_argument("--no-cfg2", action="store_true",
                     help="skip the 100k / SH 3 / 1024x768 cached-vs-recompute comparison")
     ap.add_argument("--profile", action="store_true",
@@ -56,7 +58,7 @@ def parse():
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
         args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = args.no_cfg2 = True
-        args.no_ba = args.no_mvs = True
+        args.no_ba = args.no_mvs = args.no_capture = True
     return args
 
 
@@ -376,6 +378,55 @@ def mvs_runs(width=960, height=720, n_targets=8, iters=5):
     return res
 
 
+def capture_runs(width=640, height=480, n_views=24, iters=500, stride=12):
+    """Captures to a trained model: ray-cast greyscale views of the seeded
+    scene -> MVS depth maps of every view and their fused, thinned cloud ->
+    PCA seeding -> training against the captures (every 6th view held out),
+    with the time of each stage and the held-out PSNR."""
+    import torch
+    import synth
+    from paper_2601_17354_amd import mvs, train as tr_
+    scene = synth.spheres_planes_scene(0)
+    cams = synth.ring_cameras(n_views, width, height)
+    grey_np, _ = synth.textured_views(scene, cams, seed=5)
+    grey = torch.as_tensor(grey_np, device="cuda")
+    sparse = torch.as_tensor(synth.sample_surface(scene, 20000, 1)[0], device="cuda")
+    m = mvs.MVS(cams, width, height, mvs.MVSParams(), max_targets=n_views)
+    targets = torch.arange(n_views, dtype=torch.int32, device="cuda")
+    cap = n_views * width * height // stride + 1
+    P = torch.empty((3, cap), dtype=torch.float32, device="cuda")
+    C = torch.empty_like(P)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for rep in range(2):                      # the first pass warms up
+        ev[0].record()
+        m.prepare(grey, sparse)
+        m.depth_maps(targets)
+        cnt = m.fuse(targets, P, grey=grey, colours=C, stride=stride)
+        ev[1].record()
+    kept = int(cnt.item())
+    n = (kept + stride - 1) // stride
+    P, C = P[:, :n].contiguous(), C[:, :n].contiguous()
+    ev[2].record()
+    params = tr_.seed_pca(P, C)
+    ev[3].record()
+    torch.cuda.synchronize()
+    t_mvs, t_seed = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    del m
+    tgt = {i: (grey[i].float() / 255.0).expand(3, height, width).contiguous() for i in range(n_views)}
+    test_ids = [i for i in range(n_views) if i % 6 == 0]
+    order = [i for i in range(n_views) if i % 6 != 0]
+    trainer = tr_.Trainer(params, 0, width, height)
+    trainer.prepare(cams[order[0]])
+    t0 = time.perf_counter()
+    hist = tr_.train(trainer, cams, tgt, order, iters, eval_ids=test_ids, eval_at=(0, 100, iters))
+    torch.cuda.synchronize()
+    return {"workload": f"{n_views} ray-cast ring views {width}x{height}: MVS (128 planes) of every view, "
+                        f"cloud thinned 1/{stride}, PCA seed, {iters} training steps, every 6th view held out",
+            "mvs_ms_all_views": t_mvs, "kept_pixels": kept, "cloud_points": n, "seed_ms": t_seed,
+            "train_s_incl_eval": time.perf_counter() - t0,
+            "psnr_held_out": {str(k): v for k, v in hist.items()}}
+
+
 def render_fps(wl, params, order, frames=50):
     """Render-only frames per second at the workload's resolution (projection,
     bin/sort, compositing without the trace) on the trained parameters: the
@@ -657,6 +708,9 @@ def main():
     if args.mvs_only:
         print(json.dumps({"multi_view_stereo": mvs_runs()}))
         return
+    if args.capture_only:
+        print(json.dumps({"captures_to_model": capture_runs()}))
+        return
     if args.batched_only:
         r = batched_runs(args.batched_gaussians, steps=6, warmup=2, tuned={"tile": [16, 16], "batch": 256,
                                                                            "table": []}, compare=False)
@@ -764,6 +818,10 @@ def main():
         log("multi-view stereo: 60 views 960x720, 128 planes, 8 targets")
         out["multi_view_stereo"] = mvs_runs()
         log(f"multi-view stereo: {out['multi_view_stereo']}")
+    if not args.no_capture:
+        log("captures to model: 24 views 640x480, MVS, seed, 500 steps")
+        out["captures_to_model"] = capture_runs()
+        log(f"captures to model: {out['captures_to_model']}")
     log("seeding network alone")
     out["seed_network"] = mlp_runs()
     log(f"seed network: {out['seed_network']}")
