@@ -11,7 +11,8 @@
 //                 observation's pose block and gradient (21 + 6 values);
 //   k_ba_cameras  16 workgroups per camera, each over a slice of its
 //                 observations: partial row blocks of the reduced system
-//                 S = H_tt - H_tp H_pp^-1 H_pt and g = b_t - H_tp v
+//                 S = H_tt - H_tp H_pp^-1 H_pt (its blocks (i, k), k <= i:
+//                 the solve reads the lower triangle) and g = b_t - H_tp v
 //                 accumulated in LDS over every pair of observations that
 //                 share a point (float64 LDS atomics); the first slice adds
 //                 the camera's damped pose block and gradient, summed over
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(kCamThreads) void k_ba_cameras(pgs_ba_problem pb, d
             uint32_t o2 = s0 + r + (uint32_t)lane % nt;
             if (o2 >= s0 + nt) o2 -= nt;
             const int k = (int)pb.obs_cam_dev[o2];
+            if (k > i) continue;  // the solve reads the lower triangle only
             const double* H2 = obs_rec + (size_t)o2 * kObsRec;
             for (int a = 0; a < 6; ++a)
                 for (int b = 0; b < 6; ++b)
