@@ -721,7 +721,8 @@ pgs_status pgs_mvs_select_ref(const pgs_camera* cams_dev, int32_t n_views, const
  * pixel floor(fx x/z + cx + 0.5), likewise y (M, m, d_k and the rays are
  * float64 rounded to float32; the per pixel-plane arithmetic is unfused
  * float32 in a fixed order); cost = Hamming distance of the Census strings, 48 where z <= 0,
- * the pixel is outside the image or the range is empty.
+ * the pixel is outside the image, the range is empty or the view has no
+ * reference (ref_dev[view] < 0, as pgs_mvs_select_ref gives a lone view).
  * cost_dev [n_targets][height][width][n_planes] uint8.
  */
 pgs_status pgs_mvs_cost(const pgs_camera* cams_dev, int32_t width, int32_t height, const uint64_t* census_dev,

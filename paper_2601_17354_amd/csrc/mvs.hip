@@ -12,7 +12,8 @@
 //   k_mvs_ref     per target view the candidate maximising
 //       exp(-(b - b_target)^2 / (2 sigma_b^2)) max(alpha / alpha_min, 1);
 //   k_census      7 x 7 Census (48 bits) from a 22 x 22 LDS tile;
-//   k_cost<D>     one thread per (pixel, plane): the plane-sweep pixel in the
+//   k_cost<D>     one thread per (pixel slot, plane) over 128 pixels per
+//       workgroup: the plane-sweep pixel in the
 //       reference view from float32 arithmetic in a fixed order without
 //       contraction (the nearest-pixel decision is reproducible), Hamming
 //       distance of the Census strings; cost volume [y][x][plane] bytes;
@@ -22,8 +23,8 @@
 //       ahead); per step the previous costs' minimum is a DPP wave reduction
 //       and the neighbouring planes come from DPP wave shifts.  The row
 //       kernel writes the two row paths' sum; the column kernel adds both
-//       column paths to it, stages the totals of 64 steps in an LDS ring and
-//       lets each lane take the winner, the confidence test and the refined
+//       column paths to it, stages the totals of 32 steps in an LDS ring and
+//       lets two lanes per pixel take the winner, the confidence test and the refined
 //       depth of one of those pixels, without storing the total;
 //   k_fuse_*      per-row counts, one scan over rows and the back-projection
 //       of the kept pixels in row-major order.
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
     __shared__ uint64_t s_cen[kCostPix];
     const int t = threadIdx.x, ti = blockIdx.y, tv = targets[ti], rv = refs[tv];
     const uint32_t npix = (uint32_t)W * (uint32_t)H, base = blockIdx.x * kCostPix;
-    if (t == 0) {
+    if (t == 0 && rv >= 0) {
         const Cam64 ct = cam64(cams[tv]), cr = cam64(cams[rv]);
         double M[9];
         for (int i = 0; i < 3; ++i)
@@ -317,7 +318,8 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
     if (t >= SL * D) return;
     const int k = t % D, slot = t / D;
     const double d_min = range[2 * tv], d_max = range[2 * tv + 1];
-    const bool ranged = d_min > 0.0 && d_max > d_min;
+    // no reference (a single view) or an empty range: every cost is the out cost
+    const bool ranged = rv >= 0 && d_min > 0.0 && d_max > d_min;
     float d = 0.0f;
     if (ranged) {
         const double inv_far = 1.0 / d_max;
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
     }
     const float* M = s_pose;
     const float wmax = (float)(W - 1), hmax = (float)(H - 1);
-    const uint64_t* rc = census + (size_t)rv * npix;
+    const uint64_t* rc = census + (size_t)(rv >= 0 ? rv : tv) * npix;
     uint8_t* out = cost + ((size_t)ti * npix + base) * D + k;
     // four pixels per round with their gathers issued together: an invalid
     // sample reads the reference's pixel 0 and is replaced by the out cost

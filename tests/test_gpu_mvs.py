@@ -145,6 +145,10 @@ def test_empty_range_and_penalty_free_sgm():
     cost, agg, depth, _ = _gpu_depth(cams, g, [0, 1], [1, 0], ranges, pr)
     assert (cost[0] == omvs.COST_OUT).all() and not (depth[0] > 0).any()
     np.testing.assert_array_equal(agg[1].astype(np.int64), 4 * cost[1].astype(np.int64))
+    # a view without a reference (what the selection gives a lone view)
+    ranges[0] = ranges[1]
+    cost, _, depth, _ = _gpu_depth(cams, g, [0], [-1, 0], ranges, pr)
+    assert (cost[0] == omvs.COST_OUT).all() and not (depth[0] > 0).any()
 
 
 def test_fuse_matches_oracle():
