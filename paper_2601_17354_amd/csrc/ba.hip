@@ -280,11 +280,16 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // solved entries below a panel are summed over 1024 / PW row slices in a
 // fixed order, and one wave solves the PW x PW triangle with lane broadcasts.
 // The step is scattered to the free pose entries; the fixed ones are 0.
+// `flags` and [k_begin, k_end) select the part one launch does (gather,
+// panels, in-kernel trailing updates, back substitution).
+constexpr int kSolveGather = 1, kSolveTrailing = 2, kSolveBack = 4;
+
 template <int PW>
 __global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gauge_axis,
                                                             const double* __restrict__ S,
                                                             const double* __restrict__ g, double* __restrict__ A,
-                                                            double* __restrict__ dpose) {
+                                                            double* __restrict__ dpose, int k_begin, int k_end,
+                                                            int flags) {
     extern __shared__ double lds[];
     constexpr int T = kSolveThreads, PS = PW + 1, NS = T / PW;
     const int n6 = 6 * n_cams, nf = n6 - 7, t = threadIdx.x;
@@ -292,13 +297,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gaug
     double* inv = col + PW;             // [PW] 1 / L_pp of the panel
     double* dd = inv + PW;              // [1]  the pivot
     double* P = dd + 2;                 // panel [nf + 1][PS]; later red [NS][PW], L11 [PW][PS], x [nf]
-    for (int e = t; e < nf * nf; e += T) {
-        const int r = e / nf, c = e - r * nf;
-        if (c <= r) A[e] = S[(size_t)free_param(r, gauge_axis) * n6 + free_param(c, gauge_axis)];
+    if (flags & kSolveGather) {
+        for (int e = t; e < nf * nf; e += T) {
+            const int r = e / nf, c = e - r * nf;
+            if (c <= r) A[e] = S[(size_t)free_param(r, gauge_axis) * n6 + free_param(c, gauge_axis)];
+        }
+        for (int c = t; c < nf; c += T) A[(size_t)nf * nf + c] = g[free_param(c, gauge_axis)];
+        __syncthreads();
     }
-    for (int c = t; c < nf; c += T) A[(size_t)nf * nf + c] = g[free_param(c, gauge_axis)];
-    __syncthreads();
-    for (int k0 = 0; k0 < nf; k0 += PW) {
+    for (int k0 = k_begin; k0 < nf && k0 < k_end; k0 += PW) {
         const int nb = min(PW, nf - k0), m = nf + 1 - k0;  // panel rows, the right-hand side last
         for (int e = t; e < m * nb; e += T) {
             const int r = e / nb, c = e - r * nb;
@@ -347,9 +354,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gaug
             if (r >= nb || c <= r) A[(size_t)(k0 + r) * nf + k0 + c] = P[r * PS + c];
         }
         // trailing update of rows nb..m-1 (right-hand side last), columns
-        // nb..nf-k0-1, lower triangle: A_ij -= sum_p L_ip L_jp
+        // nb..nf-k0-1, lower triangle: A_ij -= sum_p L_ip L_jp (here, or by
+        // k_ba_syrk over many workgroups)
         const int mt = m - nb, mc = mt - 1, bi_n = (mt + 3) >> 2, bj_n = (mc + 3) >> 2;
-        for (int e = t; e < bi_n * bj_n; e += T) {
+        for (int e = t; e < ((flags & kSolveTrailing) ? bi_n * bj_n : 0); e += T) {
             const int bi = e / bj_n, bj = e - bi * bj_n;
             if (bj > bi) continue;
             double acc[4][4];
@@ -387,6 +395,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gaug
         }
         __syncthreads();
     }
+    if (!(flags & kSolveBack)) return;
     // back substitution L^T x = y, y = row nf of A
     double* red = P;                    // [NS][PW]
     double* L11 = red + NS * PW;        // [PW][PS]
@@ -421,6 +430,47 @@ __global__ __launch_bounds__(kSolveThreads) void k_ba_solve(int n_cams, int gaug
     for (int e = t; e < n6; e += T) dpose[e] = 0.0;
     __syncthreads();
     for (int r = t; r < nf; r += T) dpose[free_param(r, gauge_axis)] = xs[r];
+}
+
+// Trailing update after panel k0 over many workgroups: one 32 x 32 tile of
+// the lower triangle of rows k0 + nb .. nf (the right-hand side row last)
+// and columns k0 + nb .. nf - 1 per workgroup, A_ij -= sum_p L_ip L_jp with
+// the panel's columns of both row ranges staged in LDS; each thread a 2 x 2
+// block, the sum over p in order.
+constexpr int kSyrkTile = 32;
+
+template <int PW>
+__global__ __launch_bounds__(256) void k_ba_syrk(int nf, int k0, double* __restrict__ A) {
+    __shared__ double Li[kSyrkTile][PW + 1], Lj[kSyrkTile][PW + 1];
+    const int t = threadIdx.x, nb = min(PW, nf - k0), r0 = k0 + nb;
+    const int mt = nf + 1 - r0, mc = nf - r0;
+    const int e = (int)blockIdx.x;
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= e) ++ti;
+    const int tj = e - ti * (ti + 1) / 2, i0 = ti * kSyrkTile, j0 = tj * kSyrkTile;
+    if (j0 >= mc) return;
+    for (int q = t; q < kSyrkTile * nb; q += 256) {
+        const int r = q / nb, p = q - r * nb;
+        Li[r][p] = i0 + r < mt ? A[(size_t)(r0 + i0 + r) * nf + k0 + p] : 0.0;
+        Lj[r][p] = j0 + r < mc ? A[(size_t)(r0 + j0 + r) * nf + k0 + p] : 0.0;
+    }
+    __syncthreads();
+    const int ty = t >> 4, tx = t & 15;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int p = 0; p < nb; ++p) {
+        const double a0 = Li[2 * ty][p], a1 = Li[2 * ty + 1][p], b0 = Lj[2 * tx][p], b1 = Lj[2 * tx + 1][p];
+        acc[0][0] = fma(a0, b0, acc[0][0]);
+        acc[0][1] = fma(a0, b1, acc[0][1]);
+        acc[1][0] = fma(a1, b0, acc[1][0]);
+        acc[1][1] = fma(a1, b1, acc[1][1]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int ii = i0 + 2 * ty + u, jj = j0 + 2 * tx + v;
+            if (ii < mt && jj < mc && jj <= ii) A[(size_t)(r0 + ii) * nf + r0 + jj] -= acc[u][v];
+        }
 }
 
 __global__ __launch_bounds__(256) void k_ba_backsub(pgs_ba_problem pb, const double* __restrict__ obs_rec,
@@ -756,6 +806,25 @@ bool solve_lds_reserved(int nf) {
     return ok && solve_lds<PW>(nf) <= solve_lds<PW>(PW == 32 ? kSolveWide : 6 * PGS_BA_MAX_CAMS - 7);
 }
 
+// The solve as a chain of launches: the gather and the first panel, then
+// per panel the trailing update over many workgroups and the next panel's
+// factorisation (one workgroup), then the back substitution.
+template <int PW>
+void solve_panels(int C, int gauge_axis, const BaWs& w, double* dpose, hipStream_t s) {
+    const int nf = 6 * C - 7;
+    const size_t lds = solve_lds<PW>(nf);
+    for (int k0 = 0; k0 < nf; k0 += PW) {
+        k_ba_solve<PW><<<1, kSolveThreads, lds, s>>>(C, gauge_axis, w.S, w.g, w.A, dpose, k0, k0 + PW,
+                                                     k0 == 0 ? kSolveGather : 0);
+        const int nb = min(PW, nf - k0), mt = nf + 1 - k0 - nb;
+        if (nf - k0 - nb > 0) {
+            const int tiles = (mt + kSyrkTile - 1) / kSyrkTile;
+            k_ba_syrk<PW><<<tiles * (tiles + 1) / 2, 256, 0, s>>>(nf, k0, w.A);
+        }
+    }
+    k_ba_solve<PW><<<1, kSolveThreads, lds, s>>>(C, gauge_axis, w.S, w.g, w.A, dpose, nf, nf, kSolveBack);
+}
+
 pgs_status check_problem(const pgs_ba_problem* pb, const char* who) {
     PGS_REQUIRE(pb != nullptr, "%s: null problem", who);
     PGS_REQUIRE(pb->n_cams >= 2 && pb->n_cams <= PGS_BA_MAX_CAMS, "%s: n_cams %d not in 2..%d", who, pb->n_cams,
@@ -810,10 +879,10 @@ extern "C" pgs_status pgs_ba_step(const pgs_ba_problem* problem, const double* r
     const int nf = 6 * C - 7;
     if (nf <= kSolveWide) {
         PGS_REQUIRE(solve_lds_reserved<32>(nf), "pgs_ba_step: cannot reserve LDS for the solve");
-        k_ba_solve<32><<<1, kSolveThreads, solve_lds<32>(nf), s>>>(C, problem->gauge_axis, w.S, w.g, w.A, dpose_dev);
+        solve_panels<32>(C, problem->gauge_axis, w, dpose_dev, s);
     } else {
         PGS_REQUIRE(solve_lds_reserved<16>(nf), "pgs_ba_step: cannot reserve LDS for the solve");
-        k_ba_solve<16><<<1, kSolveThreads, solve_lds<16>(nf), s>>>(C, problem->gauge_axis, w.S, w.g, w.A, dpose_dev);
+        solve_panels<16>(C, problem->gauge_axis, w, dpose_dev, s);
     }
     k_ba_backsub<<<(M + 255) / 256, 256, 0, s>>>(*problem, w.obs_rec, w.pt_rec, dpose_dev, dpoint_dev);
     PGS_CHECK_LAUNCH("pgs_ba_step");
