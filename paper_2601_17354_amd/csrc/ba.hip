@@ -18,12 +18,14 @@
 //                 the camera's damped pose block and gradient, summed over
 //                 its observations in a fixed order; k_ba_rows sums the
 //                 slices in order;
-//   k_ba_solve    one workgroup: the gauge-free rows and columns of S
-//                 (camera 0's six parameters and camera 1's centre coordinate
-//                 along the gauge axis removed), a panel-blocked Cholesky
-//                 (panels in LDS, the right-hand side carried as an extra
-//                 row so the forward substitution comes with the factor),
-//                 and the blocked back substitution -> the pose step;
+//   k_ba_solve /  the gauge-free rows and columns of S (camera 0's six
+//   k_ba_syrk     parameters and camera 1's centre coordinate along the gauge
+//                 axis removed), a panel-blocked Cholesky (each panel
+//                 factored by one workgroup in LDS, the right-hand side
+//                 carried as an extra row so the forward substitution comes
+//                 with the factor; the trailing update over many
+//                 workgroups), and the blocked back substitution -> the
+//                 pose step;
 //   k_ba_backsub  one thread per point: dP = v - H_pp^-1 sum H_tp^T dt.
 // The cost (sum of Huber terms) is reduced per block in a fixed order.
 #include <math.h>
