@@ -71,37 +71,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Exclusive scan of the per-block partial sums by one block; writes the
-// grand total to *total_out (if not null).
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partial,
-                                                                uint32_t nb, uint32_t* __restrict__ total_out) {
-    __shared__ uint32_t s[kScanThreads];
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += kScanItems) {
-        const uint32_t b0 = base + threadIdx.x * kScanIpt;
-        uint32_t loc[kScanIpt];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < kScanIpt; ++k) {
-            loc[k] = (b0 + k < nb) ? partial[b0 + k] : 0u;
-            sum += loc[k];
-        }
-        uint32_t total;
-        uint32_t run = carry + block_exclusive_scan(sum, s, total);
-#pragma unroll
-        for (int k = 0; k < kScanIpt; ++k) {
-            if (b0 + k < nb) partial[b0 + k] = run;
-            run += loc[k];
-        }
-        carry += total;
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
+// Per-block exclusive scan of `in` offset by the sum of the preceding
+// blocks' partial sums (each block adds those up itself, so the partials
+// need no scan launch of their own); the last block writes the grand total
+// to *total_out (if not null).  `out` may alias `in`.
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __restrict__ in, uint32_t n,
                                                              const uint32_t* __restrict__ partial,
-                                                             uint32_t* __restrict__ out) {
+                                                             uint32_t* __restrict__ out,
+                                                             uint32_t* __restrict__ total_out) {
     __shared__ uint32_t s[kScanThreads];
+    uint32_t before = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) before += partial[i];
+    uint32_t offset;
+    block_exclusive_scan(before, s, offset);
     const uint32_t base = blockIdx.x * kScanItems + threadIdx.x * kScanIpt;
     uint32_t loc[kScanIpt];
     uint32_t sum = 0;
@@ -111,12 +93,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __r
         sum += loc[k];
     }
     uint32_t total;
-    uint32_t run = partial[blockIdx.x] + block_exclusive_scan(sum, s, total);
+    uint32_t run = offset + block_exclusive_scan(sum, s, total);
 #pragma unroll
     for (int k = 0; k < kScanIpt; ++k) {
         if (base + k < n) out[base + k] = run;
         run += loc[k];
     }
+    if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = offset + total;
 }
 
 size_t scan_workspace(uint32_t n) { return align_up((size_t)div_up(n, kScanItems) * 4); }
@@ -127,8 +110,7 @@ pgs_status scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tot
     const uint32_t nb = div_up(n, kScanItems);
     if (nb == 0) return PGS_OK;
     k_scan_reduce<<<nb, kScanThreads, 0, s>>>(in, n, partial);
-    k_scan_partials<<<1, kScanThreads, 0, s>>>(partial, nb, total_out);
-    k_scan_apply<<<nb, kScanThreads, 0, s>>>(in, n, partial, out);
+    k_scan_apply<<<nb, kScanThreads, 0, s>>>(in, n, partial, out, total_out);
     PGS_CHECK_LAUNCH("scan");
     return PGS_OK;
 }
