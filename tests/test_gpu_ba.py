@@ -3,7 +3,8 @@ pgs_ba_apply through the C ABI) against the FP64 oracle: the robust cost,
 one damped Gauss-Newton step (reduced camera system on the GPU, the full
 damped normal equations solved directly in the oracle), the update, whole
 Levenberg-Marquardt runs, and at full size (60 cameras, ~100k points,
-~790k observations) the step's residual in the oracle's normal equations.
+~790k observations; 80 and 128 cameras, the solve's narrow-panel path up to
+the camera limit) the step's residual in the oracle's normal equations.
 
 Tolerances: the cost and the update are float64 sums and products in a
 different order (1e-12 relative).  The step solves an ill-conditioned
@@ -104,10 +105,13 @@ def test_ba_noise_free_recovers_the_truth():
     np.testing.assert_allclose(P, tr["P_true"], atol=1e-8)
 
 
-def test_ba_full_size_step_solves_the_normal_equations():
-    # 60 ring cameras, ~100k points: the oracle assembles the sparse normal
-    # equations; the GPU step's residual in them and the cost are checked
-    ba, tr, pb, st = _setup(6, n_cams=60, n_points=100_000)
+@pytest.mark.parametrize("n_cams,n_points", [(60, 100_000), (80, 20_000), (128, 20_000)])
+def test_ba_full_size_step_solves_the_normal_equations(n_cams, n_points):
+    # 60 ring cameras, ~100k points (the bench size), and 80 and 128 cameras
+    # (more than 400 free pose parameters: the solve's 16-column panels, up
+    # to the camera limit): the oracle assembles the sparse normal equations;
+    # the GPU step's residual in them and the cost are checked
+    ba, tr, pb, st = _setup(6, n_cams=n_cams, n_points=n_points)
     say(f"[ba] full size: {pb.n_cams} cameras, {pb.n_points} points, {pb.n_obs} observations")
     got = float(ba.cost(pb, st).item())
     want = oba.cost(tr, tr["R0"], tr["c0"], tr["P0"], DELTA)
