@@ -1,7 +1,6 @@
 """GPU parity of the remaining entry points and the trace / index-map
 properties the paper states."""
 
-import math
 
 import numpy as np
 import pytest

@@ -8,7 +8,6 @@ the block-relative rule of gpu_helpers.
 
 import numpy as np
 import pytest
-import torch
 
 import synth
 from gpu_helpers import GRAD_TOL, IMG_TOL, assert_block_close, max_rel, run_gpu, say, trace_entries

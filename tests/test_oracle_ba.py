@@ -5,7 +5,6 @@ Huber closed forms, scipy's rotation vector map, exact recovery of the
 truth on noise-free tracks, the gauge and robustness to outliers."""
 
 import numpy as np
-import pytest
 from scipy.spatial.transform import Rotation
 
 import synth
