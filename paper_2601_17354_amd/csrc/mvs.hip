@@ -290,6 +290,8 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
     __shared__ uint64_t s_cen[kCostPix];
     const int t = threadIdx.x, ti = blockIdx.y, tv = targets[ti], rv = refs[tv];
     const uint32_t npix = (uint32_t)W * (uint32_t)H, base = blockIdx.x * kCostPix;
+    // every lane reads the pose below, so it is defined without a reference too
+    if (rv < 0 && t < 16) s_pose[t] = 0.0f;
     if (t == 0 && rv >= 0) {
         const Cam64 ct = cam64(cams[tv]), cr = cam64(cams[rv]);
         double M[9];
@@ -307,7 +309,11 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
         s_pose[15] = cams[rv].cy;
     }
     for (int q = t; q < kCostPix; q += blockDim.x) {
-        if (base + q >= npix) break;
+        if (base + q >= npix) {  // the ragged tail's slots are masked but still read
+            s_a[q] = s_b[q] = 0.0f;
+            s_cen[q] = 0;
+            continue;
+        }
         const pgs_camera& c = cams[tv];
         const uint32_t pix = base + q, y = pix / (uint32_t)W, x = pix - y * (uint32_t)W;
         s_a[q] = (float)(((double)x - (double)c.cx) / (double)c.fx);
@@ -339,18 +345,15 @@ __global__ __launch_bounds__(256) void k_cost(const pgs_camera* __restrict__ cam
 #pragma unroll
         for (int u4 = 0; u4 < 4; ++u4) {
             const int i = i0 + u4 * SL;
-            ok[u4] = false;
-            size_t idx = 0;
-            if (ranged && base + i < npix) {
-                const float X = d * s_a[i], Y = d * s_b[i], Z = d;
-                const float xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
-                const float yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
-                const float zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
-                const float u = floorf(M[12] * (xr / zr) + M[14] + 0.5f);
-                const float v = floorf(M[13] * (yr / zr) + M[15] + 0.5f);
-                ok[u4] = zr > 0.0f && u >= 0.0f && u <= wmax && v >= 0.0f && v <= hmax;
-                if (ok[u4]) idx = (size_t)v * W + (size_t)u;
-            }
+            // evaluated everywhere and masked (no divergent branch)
+            const float X = d * s_a[i], Y = d * s_b[i], Z = d;
+            const float xr = M[0] * X + M[1] * Y + M[2] * Z + M[9];
+            const float yr = M[3] * X + M[4] * Y + M[5] * Z + M[10];
+            const float zr = M[6] * X + M[7] * Y + M[8] * Z + M[11];
+            const float u = floorf(M[12] * (xr / zr) + M[14] + 0.5f);
+            const float v = floorf(M[13] * (yr / zr) + M[15] + 0.5f);
+            ok[u4] = ranged && base + i < npix && zr > 0.0f && u >= 0.0f && u <= wmax && v >= 0.0f && v <= hmax;
+            const size_t idx = (size_t)(uint32_t)(ok[u4] ? v : 0.0f) * W + (size_t)(uint32_t)(ok[u4] ? u : 0.0f);
             g[u4] = rc[idx];
         }
 #pragma unroll
