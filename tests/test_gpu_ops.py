@@ -55,6 +55,30 @@ def test_sort_respects_device_count_and_capacity():
     np.testing.assert_array_equal(gk, np.sort(keys, kind="stable"))
 
 
+@pytest.mark.parametrize("n_tiles", [10800, 77, 1])
+def test_tile_order_is_a_heavy_first_permutation(n_tiles):
+    """The launch order only schedules, so it is checked by what it promises:
+    a permutation of the view's tiles, non-increasing in 8-pair buckets of
+    list length (lengths past the last bucket share it), read at the view's
+    tile offset."""
+    from paper_2601_17354_amd import binding as B
+    rng = np.random.default_rng(n_tiles)
+    lens = rng.integers(0, 600, n_tiles)
+    lens[rng.random(n_tiles) < 0.02] = 5000
+    off = 3
+    total = n_tiles + 2 * off
+    start = np.zeros(total, np.int64)
+    start[off:off + n_tiles] = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    end = start.copy()
+    end[off:off + n_tiles] += lens
+    ranges = torch.as_tensor(np.stack([start, end]).astype(np.int32), device=DEV)
+    order = torch.full((n_tiles,), -1, dtype=torch.int32, device=DEV)
+    B.pgs_tile_order(ranges, n_tiles, off, total, order)
+    got = order.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(np.sort(got), np.arange(n_tiles))
+    assert np.all(np.diff(np.minimum(lens[got] >> 3, 255)) <= 0)
+
+
 @pytest.mark.parametrize("W,H,lam", [(64, 48, 0.0), (70, 45, 0.2), (128, 96, 0.2)])
 def test_loss_matches_oracle(W, H, lam):
     from paper_2601_17354_amd import binding as B
