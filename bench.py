@@ -638,6 +638,13 @@ def achievable_bandwidth(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
 
 
+def traffic_sources():
+    """Files whose change invalidates the render kernels' counters: the
+    kernels and the rasterizer that chooses their launch order."""
+    pkg = os.path.join(ROOT, "paper_2601_17354_amd")
+    return ",".join(os.path.join(pkg, f) for f in ("csrc/render.hip", "csrc/render_tile.hpp", "raster.py"))
+
+
 def roofline(kernel, avg_ms, nbytes, achievable, backward):
     """Roofline entry for one kernel: algorithmic bytes over its average
     event-timed duration, against the 8 TB/s HBM peak (and the measured
@@ -646,8 +653,7 @@ def roofline(kernel, avg_ms, nbytes, achievable, backward):
     from paper_2601_17354_amd.profiling import read_traffic
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     summary = os.path.join(ROOT, "profiles", f"{kernel}_{backward}_300k_1920x1440_pmc.txt")
-    csrc = os.path.join(ROOT, "paper_2601_17354_amd", "csrc")
-    traffic = read_traffic(summary, os.path.join(csrc, "render.hip") + "," + os.path.join(csrc, "render_tile.hpp"))
+    traffic = read_traffic(summary, traffic_sources())
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": nbytes,
             "avg_ms": avg_ms, "achievable": achievable, "frac_of_achievable": achieved / achievable}

@@ -4,7 +4,8 @@ Several views of uneven resolution advance one step together:
 projection of every view in one pass over the Gaussians (pgs_project_views)
 -> one bin/sort over all views
 (pgs_bin_sort_views) -> heavy-first order of all tiles (pgs_tile_order) ->
-one persistent compositing launch over every (view, tile) (pgs_render_fwd_views)
+one persistent compositing launch over every (view, tile) (pgs_render_fwd_views;
+with the trace in natural tile order)
 -> loss per view -> one persistent backward launch (pgs_render_bwd_views) ->
 projection backward of every view in one pass into the canonical gradient
 (pgs_project_bwd_views) -> Adam with the
@@ -115,9 +116,12 @@ class BatchedStep:
                              self.values, self.ranges, self.num_pairs, self.flags, self.workspace)
         if self.order is not None:
             B.pgs_tile_order(self.ranges, self.nt, 0, self.nt, self.order)
+        # the forward that records the trace takes the tiles in natural order
+        # (neighbouring pair ranges and mask runs together), the others
+        # heavy-first, as in the single-view rasterizer
         B.pgs_render_fwd_views(self.views, self.proj, n, self.values, self.ranges, self.bg, self.image,
                                self.t_final, self.n_contrib, self.trace if self.cached else None, self.flags,
-                               self.order, self.queue)
+                               None if self.cached else self.order, self.queue)
 
     def backward_from(self, dl=None):
         """Render and projection backward from dL/dimage (default: self.dl);

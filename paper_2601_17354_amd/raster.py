@@ -68,7 +68,10 @@ class Rasterizer:
         self.t_final = torch.empty((self.H, self.W), dtype=torch.float32, device=d)
         self.n_contrib = torch.empty((self.H, self.W), dtype=torch.int32, device=d)
         self.grad2d = torch.zeros((n, GRAD2D_STRIDE), dtype=torch.float32, device=d)
-        # heavy-first launch order of the tiles (scheduling only)
+        # Heavy-first launch order of the tiles (scheduling only), used by the
+        # backward and by the forward without a trace.  The forward that
+        # records the trace launches in natural tile order instead (see
+        # fwd_order).
         self.tile_order = torch.empty(self.n_tiles, dtype=torch.int32, device=d) if ordered else None
         self.capacity = 0
         self.trace = None
@@ -112,8 +115,17 @@ class Rasterizer:
         self.bin_sort()
         B.pgs_render_fwd(self.W, self.H, self.tw, self.th, self.proj, n, self.values, self.ranges,
                          0, bg, self.image, self.t_final, self.n_contrib,
-                         self.trace if self.cached else None, self.flags, self.tile_order)
+                         self.trace if self.cached else None, self.flags, self.fwd_order)
         return self.image
+
+    @property
+    def fwd_order(self):
+        """Launch order of the forward.  With the trace, natural tile order:
+        tiles that run together then write neighbouring mask runs and read
+        neighbouring pair ranges and splats, and the write-bound entry pass
+        measured 6% faster than heavy-first; without the trace (compute
+        bound) heavy-first avoids a tail of long tiles and is faster."""
+        return None if self.cached else self.tile_order
 
     def bin_sort(self):
         B.pgs_bin_sort(self.n, self.proj, self.rect, self.touched, self.TX, self.n_tiles, 0,

@@ -94,7 +94,7 @@ class Trainer:
         r.bin_sort()
         self._mark("bin_sort")
         B.pgs_render_fwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.image, r.t_final,
-                         r.n_contrib, r.trace if r.cached else None, r.flags, r.tile_order)
+                         r.n_contrib, r.trace if r.cached else None, r.flags, r.fwd_order)
         self._mark("render_fwd")
         if check and r.read_flags():
             r.forward_checked(self.params, cam, bg)
