@@ -205,6 +205,40 @@ def test_trace_poison_counter_reset_is_exact():
             assert_block_close(o[r], outs[0][r], 1e-6, what=f"row {r}")
 
 
+def test_launch_order_changes_no_result():
+    # The traced forward launches tiles in natural order, the backward and
+    # the untraced forward heavy-first; the order only schedules.  The same
+    # traced forward in both orders gives the same image, transmittance,
+    # contributor counts and per-pixel entry counts to the bit, and the
+    # backward replaying either trace the same gradients up to float-atomic
+    # order.
+    from paper_2601_17354_amd import binding as B
+    from paper_2601_17354_amd.raster import Rasterizer
+    P, cam, _ = synth.cfg1_inputs(4, n=6000, width=256, height=192, focal=220.0)
+    params = torch.as_tensor(P, device=DEV)
+    dl = torch.as_tensor(np.random.default_rng(3).normal(size=(3, 192, 256)).astype(np.float32), device=DEV)
+    R = Rasterizer(P.shape[1], 0, 256, 192, cached=True)
+    R.forward_checked(params, cam)
+    assert R.fwd_order is None and R.tile_order is not None
+    res = []
+    for order in (None, R.tile_order):
+        R.flags.zero_()
+        B.pgs_render_fwd(R.W, R.H, R.tw, R.th, R.proj, R.n, R.values, R.ranges, 0, (0.0, 0.0, 0.0), R.image,
+                         R.t_final, R.n_contrib, R.trace, R.flags, order)
+        assert R.read_flags() == 0
+        snap = [t.cpu().numpy().copy() for t in (R.image, R.t_final, R.n_contrib, R.trace["count"])]
+        grads = torch.zeros_like(params)
+        R.backward(params, cam, dl, grads)
+        torch.cuda.synchronize()
+        res.append((snap, grads.cpu().numpy()))
+    (a, ga), (b, gb) = res
+    assert int(np.count_nonzero(a[3])) > 1000
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    for r in range(ga.shape[0]):
+        assert_block_close(gb[r], ga[r], 1e-6, what=f"row {r}")
+
+
 def test_index_map_permutation_equivariance():
     # Permuting the canonical order leaves the image unchanged and permutes
     # the gradients (index-mapping subsection).
