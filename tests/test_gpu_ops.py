@@ -171,6 +171,28 @@ def test_pca_seed_matches_oracle():
     assert checked > len(q) * 0.9
 
 
+def test_isotropic_seed_ablation():
+    # The "without the seeding" ablation seeds isotropic Gaussians: normal
+    # radius 1 instead of 0.1.  Only the normal log-scale may change, and it
+    # then equals the two in-plane ones, bit for bit.
+    from paper_2601_17354_amd import binding as B
+    scene = synth.spheres_planes_scene(0)
+    pts, col = synth.noisy_cloud(scene, 3000, seed=12)
+    P, nbr, d2 = _knn_gpu(pts)
+    colt = torch.as_tensor(np.ascontiguousarray(col.T), device=DEV)
+    outs = []
+    for r_normal in (0.1, 1.0):
+        out = torch.empty((14, len(pts)), dtype=torch.float32, device=DEV)
+        B.pgs_pca_seed(P, colt, len(pts), nbr, d2, 16, r_normal, out)
+        outs.append(out.cpu().numpy())
+    disc, iso = outs
+    keep = [r for r in range(14) if r != 5]
+    np.testing.assert_array_equal(iso[keep], disc[keep])
+    np.testing.assert_array_equal(iso[5], iso[3])
+    np.testing.assert_array_equal(iso[4], iso[3])
+    assert np.all(disc[5] < disc[3])
+
+
 def test_trace_poison_counter_reset_is_exact():
     # Trace contents beyond the per-wave step counters are never read
     # (replay-cache subsection): a trace pre-filled with NaN entries and
