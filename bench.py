@@ -7,7 +7,7 @@ loss 0.8 L1 + 0.2 (1 - SSIM), Adam, FP32.  One step = project -> bin/sort ->
 composite with replay trace -> loss -> replay backward -> projection
 backward -> Adam, on one training camera (cycling a seeded shuffle).
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the framework runs on
 one GPU.
 """
 
@@ -701,7 +701,7 @@ def cpu_baseline(width, height, n):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this framework runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
