@@ -230,6 +230,26 @@ pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, const uint32
                           size_t workspace_bytes, void* stream);
 
 /*
+ * pgs_sort_pairs_noalloc - pgs_sort_pairs for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and result, with the
+ * workspace taken from a fixed array of PGS_SORT_NOALLOC_SCRATCH_BYTES that
+ * the library holds in device memory on every GPU it runs on until the
+ * process ends.  The call allocates and frees nothing.
+ *   capacity  at most PGS_SORT_NOALLOC_MAX_PAIRS; larger capacities are
+ *             rejected with PGS_ERR_INVALID_ARG (use pgs_sort_pairs)
+ * Other arguments as pgs_sort_pairs.  The array is looked up on a device's
+ * first call (with that device current; PGS_ERR_HIP if the lookup fails).
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents: calls that overlap on one GPU (several streams, several host
+ * threads) race and must be serialised by the caller.
+ */
+#define PGS_SORT_NOALLOC_MAX_PAIRS (1u << 20)
+#define PGS_SORT_NOALLOC_SCRATCH_BYTES (16u << 20)
+pgs_status pgs_sort_pairs_noalloc(uint64_t* keys_dev, uint32_t* values_dev, const uint32_t* count_dev,
+                                  uint32_t capacity, int32_t key_bits, void* stream);
+
+/*
  * pgs_render_fwd - per-tile front-to-back compositing (compositing subsection,
  * equation C_out = C_in (1 - alpha) + alpha c, unrolled front to back):
  * per pixel and splat of its tile's sorted list, alpha = min(0.99, o e^power),

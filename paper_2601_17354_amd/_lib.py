@@ -18,6 +18,8 @@ PGS_ERR_INVALID_ARG = 1
 PGS_ERR_HIP = 2
 PGS_FLAG_PAIR_OVERFLOW = 1
 PGS_FLAG_CACHE_OVERFLOW = 2
+SORT_NOALLOC_MAX_PAIRS = 1 << 20
+SORT_NOALLOC_SCRATCH_BYTES = 16 << 20
 PROJ_FIELDS = 12
 PROJ_STRIDE = 16
 GRAD2D_FIELDS = 9
@@ -65,6 +67,7 @@ SIGNATURES = {
     "pgs_sort_workspace": (c_size_t, [c_uint32]),
     "pgs_sort_pairs": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint32, c_int32, c_void_p,
                                  c_size_t, c_void_p]),
+    "pgs_sort_pairs_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint32, c_int32, c_void_p]),
     "pgs_trace_entries": (c_size_t, [c_uint32, c_int32, c_int32]),
     "pgs_render_fwd": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                  c_void_p, c_int32, POINTER(c_float), c_void_p, c_void_p, c_void_p,

@@ -120,6 +120,12 @@ def pgs_sort_pairs(keys, values, count, capacity, key_bits, workspace, stream=No
           "pgs_sort_pairs")
 
 
+def pgs_sort_pairs_noalloc(keys, values, count, capacity, key_bits, stream=None):
+    lib = _lib.load()
+    check(lib.pgs_sort_pairs_noalloc(_ptr(keys, I64), _ptr(values, I32), _ptr(count, I32), capacity, key_bits,
+                                     _stream(stream)), "pgs_sort_pairs_noalloc")
+
+
 def pgs_tile_order(ranges, tiles_in_view, view_tile_offset, n_tiles, order, stream=None):
     lib = _lib.load()
     check(lib.pgs_tile_order(_ptr(ranges, I32), tiles_in_view, view_tile_offset, n_tiles,

@@ -21,6 +21,8 @@
 // Every kernel reads the item and pair counts from device memory and is
 // launched on a grid sized for the capacity, so nothing travels to the host
 // and the whole sequence can be captured in a HIP graph.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace {
@@ -484,6 +486,62 @@ extern "C" pgs_status pgs_sort_pairs(uint64_t* keys_dev, uint32_t* values_dev, c
     SortWs w = sort_layout(workspace_dev, capacity);
     PGS_REQUIRE(workspace_bytes >= w.bytes, "pgs_sort_pairs: workspace %zu < %zu", workspace_bytes, w.bytes);
     return radix_sort(keys_dev, values_dev, count_dev, capacity, key_bits, w, pgs::as_stream(stream));
+}
+
+// Workspace of pgs_sort_pairs_noalloc: one array per GPU, in the code
+// object, alive until the process ends.  Host code must not pass the name
+// `scratch` to a kernel (on the host it is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress gave for the device.
+static __device__ __align__(256) unsigned char scratch[PGS_SORT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+pgs_status scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        pgs::set_error("pgs_sort_pairs_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+        return PGS_ERR_HIP;
+    }
+    PGS_REQUIRE(dev >= 0 && dev < kMaxDevices, "pgs_sort_pairs_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            pgs::set_error("pgs_sort_pairs_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return PGS_ERR_HIP;
+        }
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return PGS_OK;
+}
+
+}  // namespace
+
+extern "C" pgs_status pgs_sort_pairs_noalloc(uint64_t* keys_dev, uint32_t* values_dev, const uint32_t* count_dev,
+                                             uint32_t capacity, int32_t key_bits, void* stream) {
+    PGS_REQUIRE(key_bits >= 1 && key_bits <= 64, "pgs_sort_pairs_noalloc: key_bits %d", key_bits);
+    PGS_REQUIRE(capacity <= PGS_SORT_NOALLOC_MAX_PAIRS,
+                "pgs_sort_pairs_noalloc: capacity %u exceeds the %u pairs its fixed scratch holds "
+                "(use pgs_sort_pairs with a workspace)", capacity, (unsigned)PGS_SORT_NOALLOC_MAX_PAIRS);
+    if (capacity == 0) return PGS_OK;
+    PGS_REQUIRE(keys_dev && values_dev && count_dev, "pgs_sort_pairs_noalloc: null pointer");
+    const size_t need = sort_layout(nullptr, capacity).bytes;
+    PGS_REQUIRE(need <= sizeof(scratch), "pgs_sort_pairs_noalloc: workspace %zu exceeds the scratch (%zu)", need,
+                sizeof(scratch));
+    void* ws = nullptr;
+    const pgs_status st = scratch_address(&ws);
+    if (st != PGS_OK) return st;
+    return radix_sort(keys_dev, values_dev, count_dev, capacity, key_bits, sort_layout(ws, capacity),
+                      pgs::as_stream(stream));
 }
 
 namespace {

@@ -128,3 +128,11 @@ def test_mvs_rejects_bad_arguments_before_any_launch():
                                   None) == _lib.PGS_ERR_INVALID_ARG
     assert lib.pgs_mvs_range_workspace(3, 10) >= 3 * 10 * 8 + 12
     assert lib.pgs_mvs_sgm_workspace(2, 8, 4, 64) >= 2 * 8 * 4 * 64 * 2
+
+
+def test_noalloc_sort_scratch_holds_its_largest_capacity_and_rejects_beyond():
+    lib = _lib.load()
+    assert lib.pgs_sort_workspace(_lib.SORT_NOALLOC_MAX_PAIRS) <= _lib.SORT_NOALLOC_SCRATCH_BYTES
+    st = lib.pgs_sort_pairs_noalloc(None, None, None, _lib.SORT_NOALLOC_MAX_PAIRS + 1, 40, None)
+    assert st == _lib.PGS_ERR_INVALID_ARG and b"exceeds" in lib.pgs_last_error()
+    assert lib.pgs_sort_pairs_noalloc(None, None, None, 10, 65, None) == _lib.PGS_ERR_INVALID_ARG
