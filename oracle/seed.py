@@ -64,8 +64,10 @@ def knn(points, queries=None, k=K_N):
     return np.asarray(ids, np.int64), np.asarray(d2s)
 
 
-def seed_from_neighbours(points, i, nbr_idx, nbr_d2):
-    """Local statistics and the seeded Gaussian of point i."""
+def seed_from_neighbours(points, i, nbr_idx, nbr_d2, r_normal=R_NORMAL):
+    """Local statistics and the seeded Gaussian of point i.  r_normal is the
+    normal-to-tangential scale ratio; r_normal = 1 gives the isotropic seed of
+    the ablation without the disc prior (Table 3, "w/o I")."""
     P = np.asarray(points, np.float32).astype(np.float64)
     nb = P[nbr_idx[:K_N]]
     pbar = nb.mean(0)
@@ -74,7 +76,7 @@ def seed_from_neighbours(points, i, nbr_idx, nbr_d2):
     lam, vec = np.linalg.eigh(Cov)                       # ascending
     n = vec[:, 0]
     s_t = float(np.sqrt(nbr_d2[:K_S]).mean())
-    s_n = R_NORMAL * s_t
+    s_n = r_normal * s_t
     Sigma = s_t ** 2 * (np.eye(3) - np.outer(n, n)) + s_n ** 2 * np.outer(n, n)
     gap = (lam[1] - lam[0]) / max(lam[2], 1e-300)
     return dict(cov=Cov, eig=lam, normal=n, s_t=s_t, s_n=s_n, sigma=Sigma,
@@ -82,14 +84,14 @@ def seed_from_neighbours(points, i, nbr_idx, nbr_d2):
                 logit=math.log(INIT_OPACITY / (1.0 - INIT_OPACITY)), gap=gap)
 
 
-def seed_points(points, colours, queries):
+def seed_points(points, colours, queries, r_normal=R_NORMAL):
     """Seeds for the query indices; returns a list of dicts (see above) with
     `dc` (3,) added."""
     out = []
     y00 = 1.0 / (2.0 * math.sqrt(math.pi))
     for i in queries:
         a, b = knn_one(points, int(i))
-        s = seed_from_neighbours(points, int(i), a, b)
+        s = seed_from_neighbours(points, int(i), a, b, r_normal)
         s["nbr"] = a
         s["d2"] = b
         s["dc"] = (np.asarray(colours[int(i)], np.float64) - 0.5) / y00

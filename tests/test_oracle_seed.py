@@ -72,3 +72,20 @@ def test_sigma_from_params_matches_seed_form():
     n = np.array([0.0, 0.0, 1.0])
     S = seed.sigma_from_params([math.log(0.2), math.log(0.2), math.log(0.02)], [1, 0, 0, 0])
     np.testing.assert_allclose(S, 0.04 * (np.eye(3) - np.outer(n, n)) + 0.0004 * np.outer(n, n), atol=1e-16)
+
+
+def test_isotropic_seed_is_a_ball_of_the_tangential_scale():
+    # r_normal = 1 (the ablation without the disc prior): on the same planar
+    # neighbourhood every axis gets s_t, so Sigma = s_t^2 I whatever the normal,
+    # while the default ratio keeps the disc of the test above.
+    n = np.array([1.0, 2.0, 2.0]) / 3.0
+    t1 = np.array([2.0, -1.0, 0.0]) / math.sqrt(5)
+    t2 = np.cross(n, t1)
+    g = np.arange(-3, 4) * 0.25
+    a, b = np.meshgrid(g, g)
+    pts = (a.reshape(-1, 1) * t1 + b.reshape(-1, 1) * t2).astype(np.float32)
+    iso = seed.seed_points(pts, np.zeros((len(pts), 3)), [24], r_normal=1.0)[0]
+    disc = seed.seed_points(pts, np.zeros((len(pts), 3)), [24])[0]
+    np.testing.assert_allclose(iso["sigma"], 0.25 ** 2 * np.eye(3), atol=1e-7)
+    np.testing.assert_allclose(iso["log_scales"], [math.log(0.25)] * 3, atol=1e-6)
+    assert iso["s_t"] == disc["s_t"] and iso["s_n"] == 10 * disc["s_n"]
