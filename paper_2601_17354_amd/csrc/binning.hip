@@ -77,9 +77,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 // blocks' partial sums (each block adds those up itself, so the partials
 // need no scan launch of their own); the last block writes the grand total
 // to *total_out (if not null).  `out` may alias `in`.
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __restrict__ in, uint32_t n,
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* in, uint32_t n,
                                                              const uint32_t* __restrict__ partial,
-                                                             uint32_t* __restrict__ out,
+                                                             uint32_t* out,
                                                              uint32_t* __restrict__ total_out) {
     __shared__ uint32_t s[kScanThreads];
     uint32_t before = 0;

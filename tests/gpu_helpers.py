@@ -42,6 +42,30 @@ def assert_block_close(got, want, tol, mask=None, what="", atol=0.0):
                              f"scale {scale}")
 
 
+# float32 unit roundoff
+U32 = 2.0 ** -24
+
+
+def assert_cin_close(got, want, what=""):
+    """Replay-trace C_in of one pixel's entries (K x 3, front to back) against
+    the oracle.  The kernel forms C_in_k by the over recursion
+    C_in_k = alpha_{k+1} c_{k+1} + (1 - alpha_{k+1}) C_in_{k+1} in float32,
+    starting from the background behind the last entry, so entry k carries
+    the rounding of the K - 1 - k steps behind it: each step rounds three
+    operations (<= 3u of the running value) and brings the error of its
+    alpha, o e^power evaluated in float32 with |power| <= ln 255 (<= ~8u);
+    the (1 - alpha) factor never amplifies earlier error.  Bound per entry:
+    16 u (K - k) (1 + max|C_in|), u = 2^-24, i.e. ~1e-6 for the last entry
+    and ~1e-4 for a front entry with a hundred entries behind it."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    k = np.arange(len(want))
+    bound = 16 * U32 * (len(want) - k)[:, None] * (1.0 + np.abs(want).max())
+    err = np.abs(got - want)
+    assert (err <= bound).all(), (what, float((err / bound).max()), len(want))
+    return float((err / bound).max()) if len(want) else 0.0
+
+
 def max_rel(got, want, floor_frac=1e-3):
     got = np.asarray(got, np.float64)
     want = np.asarray(want, np.float64)

@@ -118,6 +118,8 @@ def test_adam_matches_oracle():
                                       b1=float(np.float32(0.9)), b2=float(np.float32(0.999)))
     torch.cuda.synchronize()
     np.testing.assert_allclose(pt.cpu().numpy(), op, rtol=1e-5, atol=1e-6)
+    # first moment: a float32 running mean of gradients of scale 1
+    np.testing.assert_allclose(mt.cpu().numpy(), om, rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(vt.cpu().numpy(), ov, rtol=1e-5)
 
 
@@ -191,6 +193,16 @@ def test_isotropic_seed_ablation():
     np.testing.assert_array_equal(iso[5], iso[3])
     np.testing.assert_array_equal(iso[4], iso[3])
     assert np.all(disc[5] < disc[3])
+    # against the oracle's isotropic seed (r_normal = 1): Sigma = s_t^2 I, so
+    # every sampled point is compared, eigen-gap or not
+    q = list(range(0, len(pts), 23))
+    want = o_seed.seed_points(pts, col, q, r_normal=1.0)
+    for i, w in zip(q, want):
+        np.testing.assert_allclose(iso[3:6, i], w["log_scales"], rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(iso[10, i], w["logit"], rtol=1e-6)
+        np.testing.assert_allclose(iso[11:14, i], w["dc"], rtol=1e-5, atol=1e-6)
+        S = o_seed.sigma_from_params(iso[3:6, i], iso[6:10, i])
+        np.testing.assert_allclose(S, w["sigma"], rtol=1e-5, atol=1e-6 * np.abs(w["sigma"]).max())
 
 
 def test_trace_poison_counter_reset_is_exact():

@@ -39,25 +39,45 @@ CONFIGS = [((16, 16), 256, True), ((8, 8), 32, True), ((16, 8), 128, True), ((32
            ((8, 32), 256, True), ((16, 16), 32, True), ((16, 16), 128, False), ((8, 8), 64, False)]
 
 
+def _assert_queue(st, blocks):
+    """The persistent launch's queue counter after it ran: every workgroup
+    takes items until one lies past the last tile, so the counter ends at
+    tiles + workgroups.  With `blocks` workgroups over more tiles than that,
+    the workgroups walked several queue items each (one workgroup walked all
+    of them when blocks = 1)."""
+    q = int(st.queue[0].item())
+    if blocks > 0:
+        assert q == st.nt + min(blocks, st.nt), (q, st.nt, blocks)
+    else:
+        assert st.nt < q <= 2 * st.nt, (q, st.nt)
+
+
+BLOCKS = [0, 1, 3]
+
+
+@pytest.mark.parametrize("blocks", BLOCKS, ids=[f"grid{b}" for b in BLOCKS])
 @pytest.mark.parametrize("tile,batch,cached", CONFIGS, ids=[f"{t[0]}x{t[1]}-b{b}-{'c' if c else 'r'}"
                                                             for t, b, c in CONFIGS])
-def test_views_match_oracle_per_view(tile, batch, cached):
+def test_views_match_oracle_per_view(tile, batch, cached, blocks):
     from paper_2601_17354_amd.batch import BatchedStep
     P, cams = _views()
     bg = (0.1, 0.2, 0.3)
     rng = np.random.default_rng(11)
     dls = [rng.normal(size=(3, c["height"], c["width"])).astype(np.float32) for c in cams]
-    say(f"[views] tile {tile} batch {batch} cached {cached}")
+    say(f"[views] tile {tile} batch {batch} cached {cached} blocks {blocks}")
     targets = [torch.zeros((3, c["height"], c["width"]), device=DEV) for c in cams]
     st = BatchedStep(torch.as_tensor(P, device=DEV), 0, cams, targets, tile=tile, batch=batch, cached=cached,
-                     bg=bg)
+                     bg=bg, blocks=blocks)
     st.prepare()
+    torch.cuda.synchronize()
+    _assert_queue(st, blocks)
     for v in range(len(cams)):
         st.view_slice(st.dl, v).copy_(torch.as_tensor(dls[v], device=DEV))
     st.grads.zero_()
     st.backward_from()
     torch.cuda.synchronize()
     assert st.read_flags() == 0
+    _assert_queue(st, blocks)
     ref = _oracle(P, cams, tile, bg, dls)
 
     # one sorted list = the per-view lists one after the other, tiles offset
@@ -102,6 +122,106 @@ def test_views_match_oracle_per_view(tile, batch, cached):
         if cached:
             cnt = st.view_slice(st.trace["count"], v, channels=1).cpu().numpy()
             assert (cnt[ok] == r["fwd"]["count"][ok]).all()
+        g2 = st.grad2d[v].cpu().numpy()[:, :9].T
+        for f in range(9):
+            assert_block_close(g2[f], r["g2d"][f], GRAD_TOL, mask=~r["taint"], what=f"view {v} grad2d[{f}]")
+        grads_want += r["grads"]
+        taint_any |= r["taint"]
+    g = st.grads.cpu().numpy()
+    for row in range(g.shape[0]):
+        assert_block_close(g[row], grads_want[row], GRAD_TOL, mask=~taint_any, what=f"canonical row {row}")
+
+
+# SH degree 3 on the seeded scene seen by three ring cameras of uneven size
+# (6,147 tiles of 16x16): tile shape, LDS batch, backward variant and the
+# number of persistent workgroups (each walking many queue items).
+BIG = [((16, 16), 256, True, 64), ((16, 16), 256, False, 64), ((8, 32), 128, True, 3),
+       ((16, 8), 64, False, 3)]
+
+
+@pytest.mark.parametrize("tile,batch,cached,blocks", BIG,
+                         ids=[f"{t[0]}x{t[1]}-b{b}-{'c' if c else 'r'}-grid{g}" for t, b, c, g in BIG])
+def test_views_sh3_ring_sampled_tiles_match_oracle(tile, batch, cached, blocks):
+    """Every sorted pair in full; compositing, counts and T_final on sampled
+    tiles of every view (the heaviest plus seeded random ones) that the
+    oracle renders one by one; every Gaussian's 2D gradient per view and
+    canonical gradient under a dL/dimage that is non-zero only on those
+    tiles, which makes the oracle's sampled-tile backward exact."""
+    from paper_2601_17354_amd.batch import BatchedStep, mixed_views
+    from oracle.binning import bin_and_sort
+    from oracle.projection import project, project_vjp
+    from oracle.render import render_backward, render_forward
+    scene = synth.spheres_planes_scene(0)
+    P = synth.surface_gaussians(scene, 100_000, seed=81, sh_degree=3, logit_sigma=0.5)
+    cams = mixed_views(3, sizes=((640, 480), (800, 600), (1024, 768)))
+    tw, th = tile
+    rng = np.random.default_rng(19)
+    ref, dls = [], []
+    for v, cam in enumerate(cams):
+        W, H = cam["width"], cam["height"]
+        proj = project(P, cam, tw, th)
+        bins = bin_and_sort(proj)
+        lens = bins["ranges"][:, 1] - bins["ranges"][:, 0]
+        busy = np.nonzero(lens > 0)[0]
+        tiles = sorted({int(np.argmax(lens))} | {int(t) for t in rng.choice(busy, 3, replace=False)})
+        fwd = render_forward(proj, bins, cam, tw, th, (0.0, 0.0, 0.0), tiles=tiles)
+        TX = (W + tw - 1) // tw
+        on = np.zeros((H, W), bool)
+        for t in tiles:
+            ty, tx = divmod(t, TX)
+            on[ty * th:(ty + 1) * th, tx * tw:(tx + 1) * tw] = True
+        dl = np.zeros((3, H, W), np.float32)
+        dl[:, on] = rng.normal(size=(3, int(on.sum()))).astype(np.float32)
+        g2d, taint = render_backward(proj, bins, fwd, dl, "cached")
+        grads = project_vjp(P, cam, g2d, proj["visible"])
+        ref.append(dict(proj=proj, bins=bins, fwd=fwd, on=on, g2d=g2d, taint=taint, grads=grads, tiles=tiles))
+        dls.append(dl)
+    say(f"[views-sh3] tile {tile} batch {batch} cached {cached} blocks {blocks}: sampled "
+        f"{[r['tiles'] for r in ref]}")
+    targets = [torch.zeros((3, c["height"], c["width"]), device=DEV) for c in cams]
+    st = BatchedStep(torch.as_tensor(P, device=DEV), 3, cams, targets, tile=tile, batch=batch, cached=cached,
+                     blocks=blocks)
+    st.prepare()
+    torch.cuda.synchronize()
+    assert st.nt > 20 * blocks
+    _assert_queue(st, blocks)
+    for v in range(len(cams)):
+        st.view_slice(st.dl, v).copy_(torch.as_tensor(dls[v], device=DEV))
+    st.grads.zero_()
+    st.backward_from()
+    torch.cuda.synchronize()
+    assert st.read_flags() == 0
+    _assert_queue(st, blocks)
+
+    npairs = int(st.num_pairs.item())
+    keys = st.keys[:npairs].cpu().numpy().view(np.uint64)
+    vals = st.values[:npairs].cpu().numpy().astype(np.int64)
+    offs = st.views.tile_offsets
+    want_k = np.concatenate([r["bins"]["keys"] + (np.uint64(off) << np.uint64(32)) for r, off in zip(ref, offs)])
+    want_v = np.concatenate([r["bins"]["values"] for r in ref]).astype(np.int64)
+    view_g = np.searchsorted(np.asarray(offs[1:]), (keys >> np.uint64(32)).astype(np.int64), side="right")
+    view_w = np.searchsorted(np.asarray(offs[1:]), (want_k >> np.uint64(32)).astype(np.int64), side="right")
+    marg = np.stack([r["proj"]["marginal"] for r in ref])
+    kg, kw = ~marg[view_g, vals], ~marg[view_w, want_v]
+    say(f"  pairs {npairs}, marginal Gaussian-views {int(marg.sum())}")
+    np.testing.assert_array_equal(keys[kg], want_k[kw])
+    np.testing.assert_array_equal(vals[kg], want_v[kw])
+
+    grads_want = np.zeros_like(P, dtype=np.float64)
+    taint_any = np.zeros(P.shape[1], bool)
+    for v, r in enumerate(ref):
+        on, fwd = r["on"], r["fwd"]
+        ok = on & ~fwd["marginal"]
+        img = st.view_slice(st.image, v).cpu().numpy()
+        for c in range(3):
+            assert_block_close(img[c][on], fwd["image"][c][on], IMG_TOL, mask=ok[on], what=f"view {v} image[{c}]")
+        tf = st.view_slice(st.t_final, v, channels=1).cpu().numpy()
+        assert_block_close(tf[on], fwd["T_final"][on], IMG_TOL, mask=ok[on], what=f"view {v} T_final")
+        nc = st.view_slice(st.n_contrib, v, channels=1).cpu().numpy()
+        assert (nc[ok] == fwd["n_contrib"][ok]).all()
+        if cached:
+            cnt = st.view_slice(st.trace["count"], v, channels=1).cpu().numpy()
+            assert (cnt[ok] == fwd["count"][ok]).all()
         g2 = st.grad2d[v].cpu().numpy()[:, :9].T
         for f in range(9):
             assert_block_close(g2[f], r["g2d"][f], GRAD_TOL, mask=~r["taint"], what=f"view {v} grad2d[{f}]")
