@@ -26,11 +26,13 @@ count, penalties, path set or confidence measure):
     samples the reference Census at the nearest pixel
     (floor(fx_r x_r / z_r + cx_r + 0.5), likewise y); the cost is the
     Hamming distance of the two Census strings, 48 where z_r <= 0 or the
-    pixel falls outside the reference image.  The paper fixes no precision
-    for the sweep: M, m, d_k and the pixel rays are float64 values rounded
-    to float32, and the per pixel-plane products, sums, quotients and the
-    rounding to the nearest pixel are float32 operations (the kernel's
-    precision for this decision);
+    pixel falls outside the reference image.  The sweep is defined in
+    float64 (the paper fixes no precision).  An implementation that
+    evaluates it in a shorter precision may take a nearest-pixel or
+    in-front decision the other way where the exact coordinate lies within
+    its rounding error of a rounding step or an image edge; such cells are
+    reported as marginal (see sweep_pixels) and either outcome is accepted
+    for them, as for the marginal binning decisions of the splatting path;
   * SGM over 4 paths (left to right, right to left, top to bottom, bottom
     to top) with constant penalties P1, P2:
     L_r(p, k) = C(p, k) + min(L_r(p-r, k), L_r(p-r, k-1) + P1,
@@ -57,9 +59,9 @@ count, penalties, path set or confidence measure):
     of that sequence is kept when the cloud is thinned for seeding.
 Cameras are the float32-stored intrinsics and [R|t] taken as float64.  The
 decisions that turn floating point into integers (nearest reference pixel,
-inside tests, range membership) are written as explicit operations in a
-fixed order without fused multiply-adds (float32 for the sweep, float64
-for the range), so that they are reproducible.
+inside tests, range membership) are written as explicit float64 operations
+in a fixed order without fused multiply-adds, so that they are
+reproducible.
 """
 
 from __future__ import annotations
@@ -128,44 +130,83 @@ def relative_pose(cam_t, cam_r):
     return M, m
 
 
-def sweep_pixels(cam_t, cam_r, d_min, d_max, n_planes, xs, ys):
+# unit roundoff of float32, for the marginal-decision bound of the sweep
+U32 = 2.0 ** -24
+
+
+def sweep_pixels(cam_t, cam_r, d_min, d_max, n_planes, xs, ys, with_margin=False):
     """Nearest reference pixel (qx, qy) and validity for target pixels
-    (xs, ys) (1-D arrays) at every plane: arrays (n_planes, n)."""
-    f32 = np.float32
+    (xs, ys) (1-D arrays) at every plane: arrays (n_planes, n), in float64.
+
+    with_margin=True also returns `marginal` (n_planes, n): the cells whose
+    outcome (validity and pixel) an evaluation of the same formulas in
+    float32 could change.  For the reference coordinate
+    t = fx_r x_r / z_r + cx_r + 1/2 a first-order bound of that evaluation's
+    error is
+      e_q = 8u (S_x + |q| S_z) / |z_r| + u |q|,   q = x_r / z_r,
+      e_t = 2 (|fx_r| e_q + 4u (|fx_r q| + |cx_r| + 1)),
+    with S_x = |M_00 X| + |M_01 Y| + |M_02 Z| + |m_0| (S_z likewise), u = 2^-24:
+    every input (M, m, d, ray) is rounded once and every product, sum and
+    quotient once more.  A cell is marginal when floor(t - e_t) and
+    floor(t + e_t) differ and at least one of them lies on the image, for
+    x or y, or when |z_r| <= 16u S_z (the in-front test)."""
     fx, fy, cx, cy, _, _ = cam64(cam_t)
-    fxr, fyr, cxr, cyr = (f32(v) for v in cam64(cam_r)[:4])
+    fxr, fyr, cxr, cyr, _, _ = cam64(cam_r)
     Wr, Hr = cam_r["width"], cam_r["height"]
     M, m = relative_pose(cam_t, cam_r)
-    M, m = M.astype(f32), m.astype(f32)
     inv, _ = plane_inverse_depths(d_min, d_max, n_planes)
-    d = (1.0 / inv).astype(f32)[:, None]
-    a = ((np.asarray(xs, np.float64) - cx) / fx).astype(f32)[None, :]
-    b = ((np.asarray(ys, np.float64) - cy) / fy).astype(f32)[None, :]
+    d = (1.0 / inv)[:, None]
+    a = ((np.asarray(xs, np.float64) - cx) / fx)[None, :]
+    b = ((np.asarray(ys, np.float64) - cy) / fy)[None, :]
     X, Y, Z = d * a, d * b, np.broadcast_to(d, (d.shape[0], a.shape[1]))
-    xr = M[0, 0] * X + M[0, 1] * Y + M[0, 2] * Z + m[0]
-    yr = M[1, 0] * X + M[1, 1] * Y + M[1, 2] * Z + m[1]
-    zr = M[2, 0] * X + M[2, 1] * Y + M[2, 2] * Z + m[2]
+    rows = [((M[r, 0] * X + M[r, 1] * Y) + M[r, 2] * Z) + m[r] for r in range(3)]
+    xr, yr, zr = rows
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        u = np.floor(fxr * (xr / zr) + cxr + f32(0.5))
-        v = np.floor(fyr * (yr / zr) + cyr + f32(0.5))
-    assert u.dtype == f32 and v.dtype == f32
-    ok = (zr > 0) & (u >= 0) & (u <= f32(Wr - 1)) & (v >= 0) & (v <= f32(Hr - 1))
+        qx_, qy_ = xr / zr, yr / zr
+        tx = fxr * qx_ + cxr + 0.5
+        ty = fyr * qy_ + cyr + 0.5
+        u, v = np.floor(tx), np.floor(ty)
+    front = zr > 0
+    ok = front & (u >= 0) & (u <= Wr - 1) & (v >= 0) & (v <= Hr - 1)
     qx = np.where(ok, u, 0).astype(np.int64)
     qy = np.where(ok, v, 0).astype(np.int64)
-    return qx, qy, ok
+    if not with_margin:
+        return qx, qy, ok
+    S = [np.abs(M[r, 0] * X) + np.abs(M[r, 1] * Y) + np.abs(M[r, 2] * Z) + abs(m[r]) for r in range(3)]
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        az = np.abs(zr)
+
+        def step_marginal(t, q, Sq, f, c, n_pix):
+            e_q = 8 * U32 * (Sq + np.abs(q) * S[2]) / az + U32 * np.abs(q)
+            e_t = 2.0 * (abs(f) * e_q + 4 * U32 * (np.abs(f * q) + abs(c) + 1.0))
+            lo, hi = np.floor(t - e_t), np.floor(t + e_t)
+            on_image = ((lo >= 0) & (lo <= n_pix - 1)) | ((hi >= 0) & (hi <= n_pix - 1))
+            return (lo != hi) & on_image
+
+        mx = step_marginal(tx, qx_, S[0], fxr, cxr, Wr)
+        my = step_marginal(ty, qy_, S[1], fyr, cyr, Hr)
+    mz = az <= 16 * U32 * S[2]
+    marginal = mz | (front & (mx | my))
+    return qx, qy, ok, marginal
 
 
-def cost_volume(cen_t, cen_r, cam_t, cam_r, d_min, d_max, n_planes, rows=None):
+def cost_volume(cen_t, cen_r, cam_t, cam_r, d_min, d_max, n_planes, rows=None, with_margin=False):
     """C[y][x][k] (uint8): Hamming distance of the target Census and the
     reference Census at the swept pixel, COST_OUT where invalid.  `rows`
-    restricts to those target rows (the result then has len(rows) rows)."""
+    restricts to those target rows (the result then has len(rows) rows).
+    with_margin=True also returns the marginal cells of the sweep (same
+    shape, bool; see sweep_pixels)."""
     H, W = cen_t.shape
     rows = np.arange(H) if rows is None else np.asarray(rows)
     ys, xs = np.meshgrid(rows, np.arange(W), indexing="ij")
-    qx, qy, ok = sweep_pixels(cam_t, cam_r, d_min, d_max, n_planes, xs.ravel(), ys.ravel())
+    sw = sweep_pixels(cam_t, cam_r, d_min, d_max, n_planes, xs.ravel(), ys.ravel(), with_margin)
+    qx, qy, ok = sw[:3]
     ham = popcount64(cen_t[ys.ravel(), xs.ravel()][None, :] ^ cen_r[qy, qx])
     C = np.where(ok, ham, COST_OUT).astype(np.uint8)            # (n_planes, n)
-    return C.T.reshape(len(rows), W, n_planes)
+    C = C.T.reshape(len(rows), W, n_planes)
+    if not with_margin:
+        return C
+    return C, sw[3].T.reshape(len(rows), W, n_planes)
 
 
 def sgm_path(C, p1, p2):

@@ -3,7 +3,12 @@ against the FP64 oracle, on ray-cast views of the seeded scene.
 
 Integer results are compared bit for bit: Census strings, the depth range
 (float64 from unfused operations in the same order, so equal to the last
-bit), the cost volume, the SGM sums, the winner and the kept mask.  Float
+bit), the SGM sums, the winner and the kept mask.  The cost volume is
+compared cell by cell against the oracle's float64 sweep, except for the
+cells the oracle reports as marginal (the exact reference coordinate within
+the float32 evaluation's rounding bound of a rounding step or an image
+edge), whose count must stay small; the SGM sums and the winner are then
+checked by running the oracle's aggregation on the GPU cost volume.  Float
 outputs of float64 arithmetic rounded to float32 (depth, confidence, fused
 points) are compared at 1e-6 relative.  The reference choice is compared
 where it is unique: the GPU's choice must reach the oracle's best score
@@ -110,6 +115,17 @@ def _gpu_depth(cams, g, targets, refs, ranges, pr, want_agg=True):
             conf.cpu().numpy())
 
 
+def _assert_cost_close(got, want, marginal, what, max_marginal=0.01):
+    """Cost volume cell by cell outside the marginal cells; the marginal
+    fraction is reported and bounded (either outcome is accepted there)."""
+    frac = float(marginal.mean())
+    differ = got != want
+    say(f"[mvs] {what}: marginal cells {frac:.2e}, of them differing {int((differ & marginal).sum())}")
+    assert frac <= max_marginal, frac
+    bad = differ & ~marginal
+    assert not bad.any(), (what, int(bad.sum()), np.argwhere(bad)[:5].tolist())
+
+
 @pytest.mark.parametrize("W,H,D", [(160, 120, 64), (101, 77, 128), (96, 70, 192), (64, 40, 256)])
 def test_cost_sgm_depth_bit_exact(W, H, D):
     say(f"[mvs] {W}x{H} planes {D}")
@@ -125,9 +141,10 @@ def test_cost_sgm_depth_bit_exact(W, H, D):
     cost, agg, depth, conf = _gpu_depth(cams, g, targets, refs, ranges, pr)
     for i, t in enumerate(targets):
         r = refs[t]
-        C = omvs.cost_volume(omvs.census(g[t]), omvs.census(g[r]), cams[t], cams[r], ranges[t][0], ranges[t][1], D)
-        np.testing.assert_array_equal(cost[i], C)
-        S = omvs.sgm(C, pr.p1, pr.p2)
+        C, marg = omvs.cost_volume(omvs.census(g[t]), omvs.census(g[r]), cams[t], cams[r], ranges[t][0],
+                                   ranges[t][1], D, with_margin=True)
+        _assert_cost_close(cost[i], C, marg, f"target {t}")
+        S = omvs.sgm(cost[i], pr.p1, pr.p2)
         np.testing.assert_array_equal(agg[i].astype(np.int64), S)
         d, c, k = omvs.winner(S, ranges[t][0], ranges[t][1], pr.conf_min)
         np.testing.assert_array_equal(depth[i] > 0, d > 0)
@@ -212,10 +229,12 @@ def test_full_size_pipeline():
     for i, t in enumerate(targets):
         say(f"[mvs full] oracle target {t} ref {refs[t]}")
         ct, cr = omvs.census(g[t]), omvs.census(g[refs[t]])
-        C = np.concatenate([omvs.cost_volume(ct, cr, cams[t], cams[refs[t]], ranges[t][0], ranges[t][1], D,
-                                             rows=np.arange(y0, min(y0 + 90, H))) for y0 in range(0, H, 90)])
-        np.testing.assert_array_equal(cost[i], C)
-        S = omvs.sgm(C, pr.p1, pr.p2)
+        parts = [omvs.cost_volume(ct, cr, cams[t], cams[refs[t]], ranges[t][0], ranges[t][1], D,
+                                  rows=np.arange(y0, min(y0 + 90, H)), with_margin=True) for y0 in range(0, H, 90)]
+        C = np.concatenate([p[0] for p in parts])
+        marg = np.concatenate([p[1] for p in parts])
+        _assert_cost_close(cost[i], C, marg, f"target {t}")
+        S = omvs.sgm(cost[i], pr.p1, pr.p2)
         np.testing.assert_array_equal(agg[i].astype(np.int64), S)
         d, c, _ = omvs.winner(S, ranges[t][0], ranges[t][1], pr.conf_min)
         np.testing.assert_array_equal(depth[i] > 0, d > 0)

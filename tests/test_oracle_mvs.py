@@ -215,3 +215,51 @@ def test_depth_maps_of_ray_cast_views_match_the_exact_depth():
     kb = (bad["depth"] > 0) & (dep[0] > 0)
     relb = np.abs(bad["depth"][kb] - dep[0][kb]) / dep[0][kb]
     assert kb.mean() < 0.1 and np.median(relb) > 0.1
+
+
+def _sweep_f32(cam_t, cam_r, d_min, d_max, n_planes, xs, ys, reverse):
+    """The sweep's formulas evaluated in float32 (numpy), with the 3x3
+    transform's sums in one of two orders: a stand-in for any float32
+    implementation, to check what the oracle's marginal cells must cover."""
+    f32 = np.float32
+    fx, fy, cx, cy, _, _ = mvs.cam64(cam_t)
+    fxr, fyr, cxr, cyr = (f32(v) for v in mvs.cam64(cam_r)[:4])
+    M, m = (a.astype(f32) for a in mvs.relative_pose(cam_t, cam_r))
+    inv, _ = mvs.plane_inverse_depths(d_min, d_max, n_planes)
+    d = (1.0 / inv).astype(f32)[:, None]
+    a = ((np.asarray(xs, np.float64) - cx) / fx).astype(f32)[None, :]
+    b = ((np.asarray(ys, np.float64) - cy) / fy).astype(f32)[None, :]
+    X, Y, Z = d * a, d * b, np.broadcast_to(d, (d.shape[0], a.shape[1]))
+
+    def row(r):
+        if reverse:
+            return m[r] + (M[r, 2] * Z + (M[r, 1] * Y + M[r, 0] * X))
+        return ((M[r, 0] * X + M[r, 1] * Y) + M[r, 2] * Z) + m[r]
+    xr, yr, zr = row(0), row(1), row(2)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        u = np.floor(fxr * (xr / zr) + cxr + f32(0.5))
+        v = np.floor(fyr * (yr / zr) + cyr + f32(0.5))
+    Wr, Hr = cam_r["width"], cam_r["height"]
+    ok = (zr > 0) & (u >= 0) & (u <= Wr - 1) & (v >= 0) & (v <= Hr - 1)
+    return np.where(ok, u, 0).astype(np.int64), np.where(ok, v, 0).astype(np.int64), ok
+
+
+def test_marginal_cells_cover_every_float32_disagreement():
+    """The float64 sweep's marginal cells hold every cell where a float32
+    evaluation (two summation orders) lands on another pixel or another
+    validity, and they are few."""
+    W, H = 320, 240
+    cams = synth.ring_cameras(60, W, H)
+    ys, xs = np.mgrid[0:H:3, 0:W:3]
+    xs, ys = xs.ravel(), ys.ravel()
+    total = flagged = 0
+    for t, r, lo, hi in [(0, 1, 2.0, 9.0), (7, 9, 1.0, 14.0), (30, 28, 0.5, 30.0), (12, 45, 2.0, 8.0)]:
+        qx, qy, ok, marg = mvs.sweep_pixels(cams[t], cams[r], lo, hi, 64, xs, ys, with_margin=True)
+        for rev in (False, True):
+            fx_, fy_, fok = _sweep_f32(cams[t], cams[r], lo, hi, 64, xs, ys, rev)
+            differ = (fok != ok) | (ok & ((fx_ != qx) | (fy_ != qy)))
+            assert not (differ & ~marg).any(), (t, r, rev, int((differ & ~marg).sum()))
+            flagged += int(differ.sum())
+        total += marg.size
+        assert marg.mean() < 0.01, marg.mean()
+    assert flagged > 0          # the float32 evaluations do disagree somewhere
