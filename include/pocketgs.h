@@ -50,6 +50,7 @@ typedef enum pgs_status {
     PGS_OK = 0,
     PGS_ERR_INVALID_ARG = 1,
     PGS_ERR_HIP = 2,
+    PGS_ERR_CAPACITY = 3, /* pgs_check_flags: a pair or trace buffer overflowed */
 } pgs_status;
 
 /* Bits of the device flags word. */
@@ -165,6 +166,39 @@ const char* pgs_version(void);
 const char* pgs_last_error(void);
 
 /*
+ * pgs_check_flags - the overflow protocol's host side: waits for `stream`,
+ * copies the device flags word flags_dev (as given to pgs_bin_sort /
+ * pgs_render_fwd) into *flags_host and returns PGS_ERR_CAPACITY when
+ * PGS_FLAG_PAIR_OVERFLOW or PGS_FLAG_CACHE_OVERFLOW is set (the outputs of
+ * the calls since the flags were cleared are then incomplete: grow the pair
+ * capacity to *num_pairs_dev or the trace entries to *used_dev and run
+ * again), PGS_OK otherwise.  Unlike every other call it synchronises, so it
+ * must not be recorded in a graph.  The caller clears the word (a fill
+ * kernel, e.g. a tensor's zero_()) before the next pass.
+ */
+pgs_status pgs_check_flags(const uint32_t* flags_dev, uint32_t* flags_host, void* stream);
+
+/*
+ * Graphs of library calls (not part of PocketGS: the batched training step
+ * replays a whole step without host work).  pgs_graph_begin starts stream
+ * capture on `stream` (not the null stream; thread-local capture mode);
+ * every call enqueued on it until pgs_graph_end is recorded instead of run
+ * (library calls allocate and synchronise nothing, and clear their counters
+ * with kernels, so they record as kernel nodes only).  pgs_graph_end ends the
+ * capture and instantiates the graph into *graph_out (owned by the caller,
+ * freed by pgs_graph_destroy).  pgs_graph_launch replays it on a stream:
+ * the recorded calls run again on the same device pointers and with the
+ * same host arguments they were recorded with.  Errors: PGS_ERR_INVALID_ARG
+ * for null arguments, PGS_ERR_HIP when HIP refuses (e.g. a synchronising
+ * call was enqueued during capture).
+ */
+typedef struct pgs_graph pgs_graph;
+pgs_status pgs_graph_begin(void* stream);
+pgs_status pgs_graph_end(void* stream, pgs_graph** graph_out);
+pgs_status pgs_graph_launch(const pgs_graph* graph, void* stream);
+void pgs_graph_destroy(pgs_graph* graph);
+
+/*
  * pgs_project - EWA projection of one view (inherited by PocketGS from 3D
  * Gaussian Splatting; the compositing subsection consumes its "depth-sorted
  * visible Gaussians").
@@ -255,7 +289,8 @@ pgs_status pgs_sort_pairs_noalloc(uint64_t* keys_dev, uint32_t* values_dev, cons
  * per pixel and splat of its tile's sorted list, alpha = min(0.99, o e^power),
  * power = -1/2 d^T Q d; splats with power > 0 or alpha < 1/255 are skipped;
  * the pixel stops before a splat that would take T below 1e-4.
- *   width/height, tile_w/tile_h       image and tile shape (16x16 supported)
+ *   width/height, tile_w/tile_h       image and tile shape: 16x16, 8x8, 16x8,
+ *                                     32x8 or 8x32 tiles
  *   proj_dev, values_dev, ranges_dev  from pgs_project / pgs_bin_sort
  *   bg_host                           3 floats, background colour
  *   image_dev    out [3][H][W]

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpocketgs.so")
 PGS_OK = 0
 PGS_ERR_INVALID_ARG = 1
 PGS_ERR_HIP = 2
+PGS_ERR_CAPACITY = 3
 PGS_FLAG_PAIR_OVERFLOW = 1
 PGS_FLAG_CACHE_OVERFLOW = 2
 SORT_NOALLOC_MAX_PAIRS = 1 << 20
@@ -58,6 +59,11 @@ class PgsBaProblem(ctypes.Structure):
 SIGNATURES = {
     "pgs_version": (c_char_p, []),
     "pgs_last_error": (c_char_p, []),
+    "pgs_check_flags": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "pgs_graph_begin": (c_int32, [c_void_p]),
+    "pgs_graph_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
+    "pgs_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "pgs_graph_destroy": (None, [c_void_p]),
     "pgs_project": (c_int32, [c_void_p, c_int32, c_int32, POINTER(PgsCamera), c_int32, c_int32,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pgs_bin_sort_workspace": (c_size_t, [c_int32, c_uint32]),

@@ -10,10 +10,10 @@ with the trace in natural tile order)
 projection backward of every view in one pass into the canonical gradient
 (pgs_project_bwd_views) -> Adam with the
 step counter on the device (pgs_adam_step_dev).  Nothing in a step reads
-back to the host, so the whole step can be captured once
-(torch.cuda.CUDAGraph records the library's launches on the capture stream)
-and replayed; buffers are allocated beforehand and the overflow flags are
-read between replays.  Tile shape, LDS batch size and the persistent grid
+back to the host, so the whole step can be captured once (pgs_graph_begin /
+pgs_graph_end record the launches on the capture stream) and replayed with
+pgs_graph_launch; buffers are allocated beforehand and the overflow flags
+are read between replays (pgs_check_flags).  Tile shape, LDS batch size and the persistent grid
 are parameters, chosen by `autotune`.
 """
 
@@ -90,7 +90,7 @@ class BatchedStep:
         if entries is not None:
             self.entry_capacity = min(int(entries), MAX_ENTRIES)
         d = self.device
-        self.graph = None
+        self.release_graph()
         self.keys = self.values = self.workspace = self.trace = None
         self.capacity = capacity
         self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=d)
@@ -147,7 +147,7 @@ class BatchedStep:
 
     # -- overflow protocol -------------------------------------------------
     def read_flags(self) -> int:
-        return int(self.flags.item())
+        return B.pgs_check_flags(self.flags)[1]
 
     def prepare(self, max_retries=8, headroom=1.5):
         """Forward until the pair buffers fit (synchronises); drops any graph."""
@@ -176,23 +176,40 @@ class BatchedStep:
 
     # -- graph -------------------------------------------------------------
     def capture(self):
-        """Records one step as a graph (after a warm-up step on a side stream,
-        which advances the Adam state like any step)."""
+        """Records one step as a graph through the library's graph calls
+        (pgs_graph_begin / pgs_graph_end) on a side stream, after a warm-up
+        step there, which advances the Adam state like any step.  The step
+        allocates nothing, so the recorded nodes are kernels only."""
+        self.release_graph()
         s = torch.cuda.Stream(device=self.device)
         s.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(s):
             self.step()
+            B.pgs_graph_begin(s)
+            try:
+                self.step()
+            finally:
+                g = B.pgs_graph_end(s)
         torch.cuda.current_stream(self.device).wait_stream(s)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.step()
         self.graph = g
         return g
 
     def replay(self):
         if self.graph is None:
             raise RuntimeError("capture() first")
-        self.graph.replay()
+        B.pgs_graph_launch(self.graph)
+
+    def release_graph(self):
+        if self.graph is not None:
+            torch.cuda.synchronize(self.device)
+            B.pgs_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.release_graph()
+        except Exception:
+            pass
 
     def stats(self) -> dict:
         return dict(views=self.V, gaussians=self.n, pixels=self.npx, tiles=self.nt,

@@ -80,6 +80,38 @@ def pgs_version() -> str:
     return _lib.load().pgs_version().decode()
 
 
+def pgs_check_flags(flags, stream=None) -> tuple[int, int]:
+    """Waits for the stream and reads the device flags word: (status, word),
+    status PGS_OK or PGS_ERR_CAPACITY (a pair or trace buffer overflowed);
+    raises on any other status."""
+    host = ctypes.c_uint32(0)
+    st = _lib.load().pgs_check_flags(_ptr(flags, I32), ctypes.byref(host), _stream(stream))
+    if st not in (_lib.PGS_OK, _lib.PGS_ERR_CAPACITY):
+        check(st, "pgs_check_flags")
+    return int(st), int(host.value)
+
+
+def pgs_graph_begin(stream):
+    check(_lib.load().pgs_graph_begin(_stream(stream)), "pgs_graph_begin")
+
+
+def pgs_graph_end(stream) -> ctypes.c_void_p:
+    """Ends the capture begun on `stream`; returns the instantiated graph's
+    handle (free it with pgs_graph_destroy)."""
+    h = ctypes.c_void_p()
+    check(_lib.load().pgs_graph_end(_stream(stream), ctypes.byref(h)), "pgs_graph_end")
+    return h
+
+
+def pgs_graph_launch(graph, stream=None):
+    check(_lib.load().pgs_graph_launch(graph, _stream(stream)), "pgs_graph_launch")
+
+
+def pgs_graph_destroy(graph):
+    if graph is not None and graph.value:
+        _lib.load().pgs_graph_destroy(graph)
+
+
 def pgs_project(params, n, sh_degree, cam, tile_w, tile_h, proj, radius, rect, touched, stream=None):
     lib = _lib.load()
     c = camera_struct(cam)

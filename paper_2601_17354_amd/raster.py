@@ -135,7 +135,7 @@ class Rasterizer:
             B.pgs_tile_order(self.ranges, self.n_tiles, 0, self.n_tiles, self.tile_order)
 
     def read_flags(self) -> int:
-        return int(self.flags.item())
+        return B.pgs_check_flags(self.flags)[1]
 
     def forward_checked(self, params, cam, bg=(0.0, 0.0, 0.0), max_retries=8, headroom=1.25):
         """forward(), then grow the pair capacity / trace depth and rerun while

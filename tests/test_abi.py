@@ -136,3 +136,13 @@ def test_noalloc_sort_scratch_holds_its_largest_capacity_and_rejects_beyond():
     st = lib.pgs_sort_pairs_noalloc(None, None, None, _lib.SORT_NOALLOC_MAX_PAIRS + 1, 40, None)
     assert st == _lib.PGS_ERR_INVALID_ARG and b"exceeds" in lib.pgs_last_error()
     assert lib.pgs_sort_pairs_noalloc(None, None, None, 10, 65, None) == _lib.PGS_ERR_INVALID_ARG
+
+
+def test_runtime_helpers_reject_bad_arguments_on_the_host():
+    lib = _lib.load()
+    assert lib.pgs_check_flags(None, None, None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_graph_begin(None) == _lib.PGS_ERR_INVALID_ARG       # the null stream
+    assert b"null stream" in lib.pgs_last_error()
+    assert lib.pgs_graph_end(None, None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_graph_launch(None, None) == _lib.PGS_ERR_INVALID_ARG
+    lib.pgs_graph_destroy(None)                                         # no-op
