@@ -54,11 +54,16 @@ def parse():
                     help="skip the 100k / SH 3 / 1024x768 cached-vs-recompute comparison")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 4 views, 4 steps, one 1 GiB stream copy")
+    ap.add_argument("--work-log", default=None,
+                    help="write the pair count, trace entries and pixels of every compositing launch of the "
+                         "training step here (JSON; synchronises after each launch)")
+    ap.add_argument("--no-atomic", action="store_true", help="skip the float-atomic reference")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.profile:
         args.views, args.steps, args.warmup = 4, 4, 2
         args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = args.no_cfg2 = True
-        args.no_ba = args.no_mvs = args.no_capture = True
+        args.no_ba = args.no_mvs = args.no_capture = args.no_atomic = True
     return args
 
 
@@ -67,43 +72,67 @@ def log(msg):
 
 
 def kernel_times(trainer, steps, order, cams, targets):
-    """Per-stage average ms from HIP events recorded on the compute stream."""
+    """Per-stage times (HIP events recorded on the compute stream) and the
+    work (pair count P, trace entries E, pixels) of each of `steps` steps:
+    (mean ms per stage, per-step records {P, E, pixels, view, ms: {stage}})."""
     import torch
-    acc = {}
+    acc, recs = {}, []
     for k in range(steps):
         trainer.events = []
         cid = order[k % len(order)]
         trainer.step(cams[cid], targets[cid])
         torch.cuda.synchronize()
         evs = trainer.events
-        for (a, ea), (b, eb) in zip(evs[:-1], evs[1:]):
-            acc.setdefault(b, []).append(ea.elapsed_time(eb))
+        ms = {b: ea.elapsed_time(eb) for (a, ea), (b, eb) in zip(evs[:-1], evs[1:])}
+        for b, v in ms.items():
+            acc.setdefault(b, []).append(v)
+        w = trainer.rast.work()
+        w.update(view=int(cid), ms=ms)
+        recs.append(w)
     trainer.events = None
-    return {k: float(np.mean(v)) for k, v in acc.items()}
+    return {k: float(np.mean(v)) for k, v in acc.items()}, recs
 
 
-def run_variant(wl, cached, steps, warmup, order):
+def run_variant(wl, cached, steps, warmup, order, full_clear=False, work_log=None, trace_words=None):
+    """The training step timed over `steps` steps after `warmup` (cycling the
+    training views), then its per-stage times and work over min(20, steps)
+    more steps.  full_clear=True zeroes the whole replay trace (entries and
+    masks) inside every step before its forward: the ablation against the
+    counter reset the step otherwise relies on.  trace_words picks the
+    replay-trace entry layout (3: C_in only, the default; 4: C_in and alpha)."""
     import torch
     from paper_2601_17354_amd.train import Trainer
     tr = Trainer(wl["params0"].clone(), 0, wl["width"], wl["height"], cached=cached, lam=0.2,
-                 extent=4.5)
+                 extent=4.5, trace_words=trace_words)
     targets = wl["targets"]
+    if work_log is not None:
+        tr.rast.work_log = work_log
     # size buffers on every training view (synchronises), then warm up
     for cid in order:
+        tr.rast.log_tag = int(cid)
         tr.prepare(wl["cams"][cid])
     tr.rast.reserve(2.0)
-    for k in range(warmup):
+    full = [tr.rast.trace["entry"], tr.rast.trace["mask"]] if (full_clear and cached) else []
+
+    def one(k):
         cid = order[k % len(order)]
+        tr.rast.log_tag = int(cid)
+        for t in full:
+            t.zero_()
         tr.step(wl["cams"][cid], targets[cid])
+        return cid
+
+    for k in range(warmup):
+        one(k)
     torch.cuda.synchronize()
     tr.rast.flags.zero_()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     evs[0].record()
+    last = None
     for k in range(steps):
-        cid = order[(warmup + k) % len(order)]
-        tr.step(wl["cams"][cid], targets[cid])
+        last = one(warmup + k)
         evs[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -112,17 +141,65 @@ def run_variant(wl, cached, steps, warmup, order):
     flags = tr.rast.read_flags()
     if flags:
         raise RuntimeError(f"buffer overflow during the timed region (flags={flags})")
-    per = kernel_times(tr, min(20, steps), order, wl["cams"], targets)
-    # work counts of the last view for the algorithmic bytes
+    out = dict(ms=ms, wall_s=wall, trainer=tr, last_cam=wl["cams"][last],
+               pct={f"p{q}": float(np.percentile(per_step, q)) for q in (10, 50, 90)})
+    if full_clear:
+        out["cleared_bytes"] = sum(t.numel() * t.element_size() for t in full)
+        return out
+    out["entry_bytes"] = 4 * tr.rast.trace_words if cached else 0
+    per, recs = kernel_times(tr, min(20, steps), order, wl["cams"], targets)
     r = tr.rast
-    P = int(r.num_pairs.item())
-    E = int(r.trace["count"].sum().item()) if cached else 0
-    visible = int((r.radius > 0).sum().item())
-    stats = dict(pairs=P, entries=E, visible=visible, pixels=r.W * r.H, n=tr.n,
-                 trace_gb=r.trace_bytes() / 1e9, capacity=r.capacity,
-                 loss=float(tr.loss.item()))
-    pct = {f"p{q}": float(np.percentile(per_step, q)) for q in (10, 50, 90)}
-    return dict(ms=ms, wall_s=wall, kernels=per, stats=stats, trainer=tr, pct=pct)
+    out.update(kernels=per, work=recs,
+               stats=dict(pairs=int(np.mean([w["P"] for w in recs])), entries=int(np.mean([w["E"] for w in recs])),
+                          visible=int((r.radius > 0).sum().item()), pixels=r.W * r.H, n=tr.n,
+                          trace_gb=r.trace_bytes() / 1e9, capacity=r.capacity, loss=float(tr.loss.item()),
+                          work_steps=len(recs)))
+    return out
+
+
+def variants_ab(params, wl, order, views=20, reps=5):
+    """The backward variants on one model state, interleaved: in each of
+    `reps` rounds, for each of the first `views` training views, one step
+    without the Adam update (project .. project_bwd) of every variant in
+    turn, so that drifting clocks or state affect all of them alike.  The
+    variants: the replay trace with 12-byte entries (C_in; alpha recomputed
+    in the backward), with 16-byte entries (C_in and alpha), and the
+    recompute-T backward without a trace.  Returns per variant the median
+    and mean time of each stage and the trace size."""
+    import torch
+    from paper_2601_17354_amd.train import Trainer
+    kinds = {"cached_12B_entries": dict(cached=True, trace_words=3),
+             "cached_16B_entries": dict(cached=True, trace_words=4),
+             "recompute": dict(cached=False)}
+    trs = {}
+    for name, kw in kinds.items():
+        tr = Trainer(params.detach().clone(), 0, wl["width"], wl["height"], lam=0.2, extent=4.5, **kw)
+        for cid in order[:views]:
+            tr.prepare(wl["cams"][cid])
+        tr.rast.reserve(2.0)
+        tr.rast.flags.zero_()
+        trs[name] = tr
+    acc = {name: {} for name in kinds}
+    for _ in range(reps):
+        for cid in order[:views]:
+            for name, tr in trs.items():
+                tr.events = []
+                tr.step(wl["cams"][cid], wl["targets"][cid], adam=False)
+                torch.cuda.synchronize()
+                evs = tr.events
+                for (_, ea), (b, eb) in zip(evs[:-1], evs[1:]):
+                    acc[name].setdefault(b, []).append(ea.elapsed_time(eb))
+    out = {"views": views, "rounds": reps, "state": "parameters after the timed steps; no Adam update"}
+    for name, tr in trs.items():
+        if tr.rast.read_flags():
+            raise RuntimeError(f"buffer overflow in variant {name}")
+        med = {k: float(np.median(v)) for k, v in acc[name].items()}
+        out[name] = {"median_ms": med, "mean_ms": {k: float(np.mean(v)) for k, v in acc[name].items()},
+                     "sum_of_medians_ms": float(sum(med.values())), "trace_gb": tr.rast.trace_bytes() / 1e9}
+        tr.events = None
+    del trs
+    torch.cuda.empty_cache()
+    return out
 
 
 def trace_clear_ablation(tr, reps=5):
@@ -451,48 +528,24 @@ def render_fps(wl, params, order, frames=50):
     return 1000.0 * frames / a.elapsed_time(b)
 
 
-# Bytes one launch must move at least, per unit of work (16x16 tiles, four
-# waves of 64 pixels per tile):
-#   per (tile, Gaussian) pair: the sorted id 4 B, the splat's record 48 B
-#     (u, v, A, B, C, o, rgb and extents), the trace's ballot mask of each
-#     wave 4 x 8 B (written forward, read backward), and backward the nine
-#     gradient fields 36 B accumulated into the canonical record;
-#   per trace entry: (C_in, alpha) 16 B, written once forward, read once
-#     backward;
-#   per pixel: forward image 12 B + T_final 4 B + n_contrib 4 B + count 4 B,
-#     backward dL/dimage 12 B (recompute also T_final and n_contrib, 8 B).
-PAIR_FWD, PAIR_BWD, MASKS, ENTRY = 4 + 48, 4 + 48 + 36, 4 * 8, 16
-
-
-def render_bwd_bytes(st, cached):
-    """Algorithmic HBM bytes of one render_bwd launch (see above)."""
-    if cached:
-        return 12 * st["pixels"] + (PAIR_BWD + MASKS) * st["pairs"] + ENTRY * st["entries"]
-    return 20 * st["pixels"] + PAIR_BWD * st["pairs"]
-
-
-def render_fwd_bytes(st, cached):
-    """Algorithmic HBM bytes of one render_fwd launch (see above)."""
-    if cached:
-        return 24 * st["pixels"] + (PAIR_FWD + MASKS) * st["pairs"] + ENTRY * st["entries"]
-    return 20 * st["pixels"] + PAIR_FWD * st["pairs"]
-
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def psnr_runs(wl, order, iters=500, at=(0, 100, 500)):
     """Held-out PSNR after `iters` training steps (the same step as timed
     above, cached backward) from each initialisation: the plain seed, the
-    learned seed (committed network weights, plain-seed fall back) and an
-    isotropic seed (r_normal = 1) for context."""
+    learned seed (committed network weights, plain-seed fall back), the
+    control that adds the network's mean output to every point as one
+    constant offset, and an isotropic seed (r_normal = 1) for context."""
     import torch
-    from paper_2601_17354_amd.seed_mlp import load_weights, seed_learned
+    from paper_2601_17354_amd.seed_mlp import load_weights, seed_constant_offset, seed_learned
     from paper_2601_17354_amd.train import Trainer, seed_pca, train
     inits = {"plain_pca": wl["params0"]}
     pts, col = wl["cloud"]
     inits["learned"], nfb = seed_learned(pts, col, load_weights())
     log(f"learned seed: {nfb} of {pts.shape[1]} points fell back to the plain seed")
+    inits["constant_offset"], _, ybar = seed_constant_offset(pts, col, load_weights())
+    log(f"control: the network's mean output {ybar} as one offset for every point")
     inits["isotropic"] = seed_pca(pts, col, r_normal=1.0)
     out = {}
     for name, p0 in inits.items():
@@ -535,11 +588,12 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
     ms_eager = time_steps(st.step, steps, warmup)
     assert st.read_flags() == 0, "batched step overflowed during timing"
     stats = st.stats()
+    kern, roofs = batched_kernel_times(st)
     del st
     torch.cuda.empty_cache()
     if not compare:
         return {"tile": tuned["tile"], "batch": tuned["batch"], "ms_per_step_graph": ms_graph,
-                "ms_per_step_eager": ms_eager, "stats": stats}
+                "ms_per_step_eager": ms_eager, "stats": stats, "kernels_ms": kern, "roofline": roofs}
     # one view at a time, single-view kernels, one Adam step per eight views
     params = wl["params0"].clone()
     grads, m, v = torch.zeros_like(params), torch.zeros_like(params), torch.zeros_like(params)
@@ -572,7 +626,40 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
             "tile": tuned["tile"], "batch": tuned["batch"], "ms_per_step_graph": ms_graph,
             "ms_per_step_eager": ms_eager, "iters_per_s": 1000.0 / ms_graph,
             "views_per_s": len(cams) * 1000.0 / ms_graph, "ms_per_step_one_view_at_a_time": ms_views,
-            "one_view_at_a_time_flags": flags, "stats": stats, "tuning": tuned["table"]}
+            "one_view_at_a_time_flags": flags, "stats": stats, "kernels_ms": kern, "roofline": roofs,
+            "tuning": tuned["table"]}
+
+
+def batched_kernel_times(st, steps=5):
+    """Per-stage times of eager batched steps (HIP events on the compute
+    stream) and the persistent compositing launches' rooflines over those
+    steps (scope-table bytes of all views' pixels, pairs and trace entries)."""
+    import torch
+    from paper_2601_17354_amd.profiling import design_bytes, sec8d_bytes
+    acc, recs = {}, []
+    for _ in range(steps):
+        st.events = []
+        st.step()
+        torch.cuda.synchronize()
+        evs = st.events
+        ms = {b: ea.elapsed_time(eb) for (a, ea), (b, eb) in zip(evs[:-1], evs[1:])}
+        for b, v in ms.items():
+            acc.setdefault(b, []).append(v)
+        E = int(st.trace["used"].item()) if st.trace is not None else 0
+        recs.append(dict(P=min(int(st.num_pairs.item()), st.capacity), E=E, pixels=st.npx, ms=ms))
+    st.events = None
+    roofs = {}
+    for k in ("render_fwd", "render_bwd"):
+        t = sum(r["ms"][k] for r in recs)
+        b8 = sum(sec8d_bytes(k, st.cached, r["P"], r["E"], r["pixels"]) for r in recs)
+        bd = sum(design_bytes(k, st.cached, r["P"], r["E"], r["pixels"], waves=st.tw * st.th // 64) for r in recs)
+        ach = b8 / (t * 1e-3) / 1e9
+        roofs[k + "_views"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "avg_ms": t / len(recs),
+                               "algorithmic_bytes": b8 / len(recs), "pairs": recs[-1]["P"],
+                               "entries": recs[-1]["E"], "pixels": st.npx,
+                               "frac_design": bd / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return {k: float(np.mean(v)) for k, v in acc.items()}, roofs
 
 
 def mlp_runs(rows=200_000, batch=16384, reps=20):
@@ -645,61 +732,228 @@ def traffic_sources():
     return ",".join(os.path.join(pkg, f) for f in ("csrc/render.hip", "csrc/render_tile.hpp", "raster.py"))
 
 
-def roofline(kernel, avg_ms, nbytes, achievable, backward):
-    """Roofline entry for one kernel: algorithmic bytes over its average
-    event-timed duration, against the 8 TB/s HBM peak (and the measured
-    stream-copy rate); counter-measured traffic from profiles/ when it was
-    taken on the current kernel source."""
-    from paper_2601_17354_amd.profiling import read_traffic
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+def roofline(kernel, recs, cached, achievable, backward, entry_bytes=12):
+    """Roofline entry of one compositing kernel over exactly the steps whose
+    work was recorded: algorithmic bytes (the scope-table model; the design
+    model beside it) summed over those steps, divided by the summed event
+    times of the same launches, against the 8 TB/s HBM peak and the measured
+    stream-copy rate; HBM traffic from the rocprofv3 counters in profiles/
+    (with the algorithmic bytes of the very launches they were taken on)
+    when they describe the current kernel source."""
+    from paper_2601_17354_amd.profiling import design_bytes, read_summary, read_traffic, sec8d_bytes
+    t_ms = sum(r["ms"][kernel] for r in recs)
+    b8 = sum(sec8d_bytes(kernel, cached, r["P"], r["E"], r["pixels"]) for r in recs)
+    bd = sum(design_bytes(kernel, cached, r["P"], r["E"], r["pixels"], entry_bytes=entry_bytes) for r in recs)
+    achieved = b8 / (t_ms * 1e-3) / 1e9
+    achieved_d = bd / (t_ms * 1e-3) / 1e9
     summary = os.path.join(ROOT, "profiles", f"{kernel}_{backward}_300k_1920x1440_pmc.txt")
     traffic = read_traffic(summary, traffic_sources())
+    traffic_work = None
+    if traffic is not None:
+        kv = read_summary(summary)
+        if "algorithmic_bytes_per_launch" in kv:
+            traffic_work = dict(algorithmic_bytes=float(kv["algorithmic_bytes_per_launch"].split()[0]),
+                                pairs=float(kv["pairs_per_launch"]), entries=float(kv["entries_per_launch"]),
+                                views=kv.get("work_log", ""))
+    n = len(recs)
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": nbytes,
-            "avg_ms": avg_ms, "achievable": achievable, "frac_of_achievable": achieved / achievable}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_launches": traffic_work,
+            "algorithmic_bytes": b8 / n, "avg_ms": t_ms / n, "launches": n,
+            "pairs": sum(r["P"] for r in recs) / n, "entries": sum(r["E"] for r in recs) / n,
+            "views": sorted({r["view"] for r in recs}),
+            "achievable": achievable, "frac_of_achievable": achieved / achievable,
+            "algorithmic_bytes_design": bd / n, "achieved_design": achieved_d, "trace_entry_bytes": entry_bytes,
+            "frac_design": achieved_d / HBM_PEAK_GBS}
 
 
-def cpu_baseline(width, height, n):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same
-    workload shape: full projection and binning of n scene Gaussians, then
-    compositing forward + backward on 600 sampled tiles, the projection VJP of
-    all visible Gaussians; scaled to one full iteration."""
+def atomic_runs(tr, reps=5):
+    """Float-atomic throughput of the render backward's gradient scatter:
+    the backward's own targets (the sorted pair values of the last view, each
+    Gaussian once per tile it touches) against distinct records (no
+    contention) and all adds on 64 records (heavy contention), nine adds per
+    target as the backward issues them; beside it the atomic rate the cached
+    backward itself sustains (nine adds per pair)."""
     import torch
-    torch.set_num_threads(1)
-    import synth
-    from oracle import binning, projection, render
-    scene = synth.spheres_planes_scene(0)
-    P = synth.surface_gaussians(scene, n, seed=3000, sh_degree=0, logit_sigma=0.5)
-    cam = synth.ring_cameras(60, width, height)[1]
+    from paper_2601_17354_amd import binding as B
+    r = tr.rast
+    P = min(int(r.num_pairs.item()), r.capacity)
+    n = tr.n
+    dev = r.values.device
+    records = torch.zeros((max(n, P), 16), dtype=torch.float32, device=dev)
+    cases = {"backward_targets": (r.values[:P].contiguous(), n),
+             "distinct_records": (torch.arange(P, dtype=torch.int32, device=dev), P),
+             "64_hot_records": (torch.arange(P, dtype=torch.int32, device=dev) % 64, 64)}
+    out = {"adds_per_target": 9, "targets": P}
+    for name, (tg, nrec) in cases.items():
+        B.pgs_atomic_scatter(records, nrec, tg, P)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            B.pgs_atomic_scatter(records, nrec, tg, P)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        out[name] = {"ms": ms, "gatomics_per_s": 9 * P / (ms * 1e-3) / 1e9}
+    del records
+    return out
+
+
+# -- the CPU oracle baseline ------------------------------------------------
+#
+# Runs in a child process of its own (`bench.py --cpu-worker DIR`), which
+# never touches the GPU, so it can fork a pool of workers over tiles.  The
+# parent writes the state the GPU step trains (the parameters after the
+# timed steps and the camera of the last timed step) into DIR.
+
+_CPU = {}
+
+
+def _cpu_tiles(tiles):
+    """Oracle compositing forward + backward of a list of tiles (run in a pool
+    worker); returns the touched Gaussians' 2D gradients (ids, values)."""
+    from oracle import render
+    st = _CPU
+    grad = np.zeros((9, st["proj"]["n"]))
+    for k in range(0, len(tiles), 8):
+        fwd = render.render_forward(st["proj"], st["bins"], st["cam"], 16, 16, (0.0, 0.0, 0.0),
+                                    tiles=tiles[k:k + 8])
+        g2d, _ = render.render_backward(st["proj"], st["bins"], fwd, st["dl"], "cached")
+        grad += g2d
+    ids = np.nonzero(np.any(grad != 0.0, axis=0))[0]
+    return ids, grad[:, ids]
+
+
+def _split_by_pairs(tiles, lens, parts):
+    """Tiles dealt to `parts` lists of about equal pair counts (longest first)."""
+    order = sorted(tiles, key=lambda t: -int(lens[t]))
+    out, load = [[] for _ in range(parts)], np.zeros(parts)
+    for t in order:
+        k = int(np.argmin(load))
+        out[k].append(int(t))
+        load[k] += lens[t]
+    return [o for o in out if o]
+
+
+def _cpu_iteration(P, cam, loss, workers, pair_share=1.0, seed=0):
+    """One oracle fwd+bwd iteration (projection, binning and sort, compositing
+    forward + backward over tiles in a pool, the loss and its gradient, the
+    projection VJP).  With pair_share < 1 the compositing runs on seeded
+    random tiles holding about that share of the pairs and its wall time is
+    scaled by the share they hold.  Returns the stage times in seconds."""
+    import multiprocessing as mp
+
+    import torch
+    from oracle import binning, loss as oloss, projection
+    W, H = int(cam["width"]), int(cam["height"])
+    rng = np.random.default_rng(seed)
+    t = {}
     t0 = time.perf_counter()
     proj = projection.project(P, cam)
-    t1 = time.perf_counter()
+    t["projection"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
     bins = binning.bin_and_sort(proj)
-    t2 = time.perf_counter()
-    TX, TY = proj["tiles"]
+    t["binning_sort"] = time.perf_counter() - t0
     lens = bins["ranges"][:, 1] - bins["ranges"][:, 0]
-    busy = np.nonzero(lens > 0)[0]
-    rng = np.random.default_rng(0)
-    sample = rng.choice(busy, size=min(600, busy.size), replace=False)
-    fwd = render.render_forward(proj, bins, cam, tiles=sample)
-    dl = rng.normal(size=(3, height, width))
-    g2d, _ = render.render_backward(proj, bins, fwd, dl, "cached")
-    t3 = time.perf_counter()
+    busy = [int(x) for x in np.nonzero(lens > 0)[0]]
+    if pair_share < 1.0:
+        perm = rng.permutation(busy)
+        cum = np.cumsum(lens[perm])
+        k = int(np.searchsorted(cum, pair_share * lens.sum())) + 1
+        sample = [int(x) for x in perm[:k]]
+    else:
+        sample = busy
+    share = float(lens[sample].sum() / max(1, lens.sum()))
+    dl = rng.normal(size=(3, H, W))
+    _CPU.update(proj=proj, bins=bins, cam=cam, dl=dl)
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        parts = pool.map(_cpu_tiles, _split_by_pairs(sample, lens, workers * 4))
+        t["compositing_fwd_bwd"] = (time.perf_counter() - t0) / share
+    g2d = np.zeros((9, proj["n"]))
+    for ids, vals in parts:
+        g2d[:, ids] += vals
+    img = rng.uniform(size=(3, H, W))
+    t0 = time.perf_counter()
+    if loss == "l1":
+        oloss.l1(img, img * 0.5)
+    else:
+        oloss.l1_dssim(img, img * 0.5)
+    t["loss"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
     projection.project_vjp(P, cam, g2d, proj["visible"])
-    t4 = time.perf_counter()
-    # scale the sampled tiles by their share of all pairs
-    share = lens[sample].sum() / max(1, lens.sum())
-    per_iter = (t1 - t0) + (t2 - t1) + (t3 - t2) / max(share, 1e-9) + (t4 - t3)
-    return dict(value=1.0 / per_iter, unit="iters/s", cores=1, kind="oracle",
-                sample=(f"FP64 oracle, 1 thread, {n} scene Gaussians at {width}x{height}: full "
-                        f"projection ({t1 - t0:.1f} s), binning+sort of {bins['num_pairs']} pairs "
-                        f"({t2 - t1:.1f} s), compositing fwd+bwd on {len(sample)} tiles holding "
-                        f"{share * 100:.2f}% of the pairs ({t3 - t2:.1f} s, scaled to all tiles), "
-                        f"projection VJP ({t4 - t3:.1f} s); measured {t4 - t0:.1f} s"))
+    t["projection_vjp"] = time.perf_counter() - t0
+    _CPU.clear()
+    return dict(seconds=sum(t.values()), stages=t, pairs=int(bins["num_pairs"]), tiles_run=len(sample),
+                tiles=len(lens), pair_share=share, threads=torch.get_num_threads())
+
+
+def cpu_worker_main(d):
+    """The --cpu-worker leg: config 1 and config 2 iterations in full and the
+    benchmark iteration on the state in directory d on a bounded tile
+    sample; writes d/result.json."""
+    import torch
+    import synth
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    torch.set_num_threads(workers)
+    out = {"workers": workers, "cpu_model": _cpu_model()}
+    P1, cam1, _ = synth.cfg1_inputs(0)
+    out["cfg1"] = _cpu_iteration(P1, cam1, "l1", workers)
+    scene = synth.spheres_planes_scene(0)
+    P2 = synth.surface_gaussians(scene, 100_000, seed=300, sh_degree=3, logit_sigma=0.5)
+    out["cfg2"] = _cpu_iteration(P2, synth.ring_cameras(60, 1024, 768)[0], "l1", workers)
+    P3 = np.load(os.path.join(d, "params.npy"))
+    cam3 = json.load(open(os.path.join(d, "cam.json")))
+    cam3["viewmat"] = np.asarray(cam3["viewmat"], np.float32)
+    out["cfg3"] = _cpu_iteration(P3, cam3, "l1_dssim", workers,
+                                 pair_share=float(json.load(open(os.path.join(d, "share.json")))))
+    json.dump(out, open(os.path.join(d, "result.json"), "w"))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(trainer, cam, pair_share=0.1):
+    """The FP64 oracle timed on the host cores on the GPU step's own state:
+    the parameters after the timed steps and the camera of the last timed
+    step (compositing on seeded tiles holding pair_share of the pairs,
+    scaled), with config 1 and config 2 iterations in full beside it."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        np.save(os.path.join(d, "params.npy"), trainer.params.detach().cpu().numpy())
+        json.dump({k: np.asarray(v).tolist() for k, v in cam.items()}, open(os.path.join(d, "cam.json"), "w"))
+        json.dump(pair_share, open(os.path.join(d, "share.json"), "w"))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", d],
+                           capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"cpu worker failed:\n{r.stderr[-2000:]}")
+        res = json.load(open(os.path.join(d, "result.json")))
+    c3 = res["cfg3"]
+    return dict(value=1.0 / c3["seconds"], unit="iters/s", cores=res["workers"], kind="oracle",
+                cpu_model=res["cpu_model"],
+                sample=(f"FP64 oracle on the benchmark step's state (trained parameters, last timed camera): "
+                        f"projection, binning and sort of all {c3['pairs']} pairs, compositing fwd+bwd on "
+                        f"{c3['tiles_run']} seeded tiles holding {100 * c3['pair_share']:.1f}% of the pairs "
+                        f"({res['workers']} worker processes over tiles; wall time scaled by that share), "
+                        f"L1 + D-SSIM loss and its gradient, projection VJP"),
+                stages_s=c3["stages"], cfg1_fwd_bwd_s=res["cfg1"]["seconds"],
+                cfg2_fwd_bwd_s=res["cfg2"]["seconds"],
+                cfg1=res["cfg1"], cfg2=res["cfg2"])
 
 
 def main():
     args = parse()
+    if args.cpu_worker:
+        cpu_worker_main(args.cpu_worker)        # child process: no GPU
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this framework runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -737,31 +991,58 @@ def main():
                            target_cams=sorted(order) + ([] if args.no_psnr else test_ids))
     log(f"workload ready in {time.perf_counter() - t:.1f} s")
     cached = args.backward == "cached"
-    res = run_variant(wl, cached, args.steps, args.warmup, order)
+    work_log = [] if args.work_log else None
+    res = run_variant(wl, cached, args.steps, args.warmup, order, work_log=work_log)
     log(f"{args.backward}: {res['ms']:.3f} ms/step, kernels {res['kernels']}, stats {res['stats']}")
-    fps = render_fps(wl, res["trainer"].params, order)
+    if work_log is not None:
+        res["trainer"].rast.work_log = None
+        json.dump(work_log, open(args.work_log, "w"))
+    tr = res["trainer"]
+    cpu_state = None if args.no_cpu_baseline else (tr, res["last_cam"])
+    fps = render_fps(wl, tr.params, order)
     log(f"render-only: {fps:.1f} frames/s")
-    ablation = trace_clear_ablation(res["trainer"]) if cached else None
+    atomic = None if args.no_atomic else atomic_runs(tr)
+    if atomic:
+        log(f"float-atomic reference: {atomic}")
+    ablation = trace_clear_ablation(tr) if cached else None
     if ablation:
         log(f"trace clear vs counter reset: {ablation}")
+    ab = None
+    if not args.profile:
+        ab = variants_ab(tr.params, wl, order)
+        for name in ("cached_12B_entries", "cached_16B_entries", "recompute"):
+            log(f"same state, {name}: {ab[name]['sum_of_medians_ms']:.3f} ms, {ab[name]['median_ms']}")
+    if cpu_state is not None:
+        # keep what the CPU oracle will run on; free the trainer's buffers
+        cpu_state = (SimpleState(tr.params.detach().cpu()), res["last_cam"])
+    del res["trainer"], tr
+    torch.cuda.empty_cache()
+    if cached and not args.profile:
+        full = run_variant(wl, cached, args.steps, args.warmup, order, full_clear=True)
+        del full["trainer"]
+        torch.cuda.empty_cache()
+        ablation["step_full_clear_ms"] = full["ms"]
+        ablation["step_counter_reset_ms"] = res["ms"]
+        ablation["step_full_clear_extra_bytes"] = full["cleared_bytes"]
+        log(f"step with the whole trace cleared: {full['ms']:.3f} ms against {res['ms']:.3f} ms")
     other = None
     if not args.no_compare:
-        del res["trainer"]
-        torch.cuda.empty_cache()
-        other = run_variant(wl, not cached, max(10, args.steps // 4), args.warmup, order)
+        other = run_variant(wl, not cached, args.steps, args.warmup, order)
         log(f"other: {other['ms']:.3f} ms/step, kernels {other['kernels']}")
         del other["trainer"]
+        torch.cuda.empty_cache()
     kern = res["kernels"]
     st = res["stats"]
     achievable = achievable_bandwidth()
     log(f"stream copy: {achievable:.0f} GB/s")
-    roofs = {
-        "render_fwd": roofline("render_fwd", kern["render_fwd"], render_fwd_bytes(st, cached), achievable,
-                               args.backward),
-        "render_bwd": roofline("render_bwd", kern["render_bwd"], render_bwd_bytes(st, cached), achievable,
-                               args.backward),
-    }
+    roofs = {k: roofline(k, res["work"], cached, achievable, args.backward, res["entry_bytes"])
+             for k in ("render_fwd", "render_bwd")}
     dom = max(roofs, key=lambda k: roofs[k]["avg_ms"])
+    if atomic:
+        P = roofs["render_bwd"]["pairs"]
+        rate = 9 * P / (roofs["render_bwd"]["avg_ms"] * 1e-3) / 1e9
+        atomic["render_bwd_gatomics_per_s"] = rate
+        atomic["render_bwd_frac_of_backward_targets_rate"] = rate / atomic["backward_targets"]["gatomics_per_s"]
     out = {
         "metric": METRIC,
         "value": 1000.0 / res["ms"],
@@ -789,13 +1070,19 @@ def main():
         "work": st,
     }
     out["render_only_fps"] = fps
+    if atomic:
+        out["atomic_reference"] = atomic
     if ablation:
         out["ablation_trace_clear"] = ablation
+    if ab is not None:
+        out["backward_variants_same_state"] = ab
     if other is not None:
         out["other_backward"] = {"backward": "recompute" if cached else "cached",
                                  "ms_per_step": other["ms"], "iters_per_s": 1000.0 / other["ms"],
                                  "ms_per_step_percentiles": other["pct"],
-                                 "kernels_ms": other["kernels"], "trace_gb": other["stats"]["trace_gb"]}
+                                 "kernels_ms": other["kernels"], "trace_gb": other["stats"]["trace_gb"],
+                                 "roofline_render_bwd": roofline("render_bwd", other["work"], not cached,
+                                                                 achievable, "recompute" if cached else "cached")}
     if not args.no_psnr:
         log("held-out PSNR after 500 training steps per initialisation")
         out["psnr_held_out"] = psnr_runs(wl, order)
@@ -804,8 +1091,8 @@ def main():
         torch.cuda.empty_cache()
         from paper_2601_17354_amd.seed_mlp import load_weights
         from paper_2601_17354_amd.workloads import compare_inits
-        log("learned vs plain seeding on three fresh scenes (200k points, 1024x768)")
-        out["seeding_fresh_scenes"] = compare_inits(load_weights(), log=log)
+        log("learned vs plain seeding on three fresh scenes (200k points, 1024x768, GT opacity 0.95 / 0.75 / 0.55)")
+        out["seeding_fresh_scenes"] = compare_inits(load_weights(), log=log, gt_opacity=(0.95, 0.75, 0.55))
     if not args.no_batched:
         log("batched multi-view step")
         out["batched_views"] = batched_runs(args.batched_gaussians)
@@ -831,10 +1118,18 @@ def main():
     log("seeding network alone")
     out["seed_network"] = mlp_runs()
     log(f"seed network: {out['seed_network']}")
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(args.width, args.height, args.gaussians)
+    if cpu_state is not None:
+        log("timing the CPU oracle on the benchmark state (bounded tile sample, worker pool)")
+        out["cpu_baseline"] = cpu_baseline(*cpu_state)
+        log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out))
+
+
+class SimpleState:
+    """The parameters the CPU oracle runs on (a host copy of the trainer's)."""
+
+    def __init__(self, params):
+        self.params = params
 
 
 if __name__ == "__main__":

@@ -103,9 +103,14 @@ typedef struct pgs_camera {
  *   base_dev   [n_tiles][TW*TH/64] uint32: first entry of the wave's region
  *   used_dev   [1] uint64 device counter of entries handed out; reset by the
  *              forward, which leaves the total demand of the pass in it
- *   entry_dev  [entry_capacity][4] float32, 16-byte aligned: per entry
- *              (C_in r, g, b, alpha) - C_in the colour of everything behind
- *              the splat at that pixel, alpha the clamped alpha it had there
+ *   entry_dev  [entry_capacity][entry_words] float32, 16-byte aligned: per
+ *              entry (C_in r, g, b, alpha) with entry_words = 4, the cache of
+ *              the replay-cache subsection - C_in the colour of everything
+ *              behind the splat at that pixel, alpha the clamped alpha it had
+ *              there - or (C_in r, g, b) with entry_words = 3, the backward
+ *              then recomputing alpha from the splat it stages anyway with the
+ *              forward's arithmetic (the same bits; 12 instead of 16 bytes an
+ *              entry, written once and read once)
  *   count_dev  [H*W] uint32 entries per pixel, count(u)
  * A wave's entries are base + cursor, where cursor counts the wave's entries
  * of earlier groups and a group's entries follow in lane order; each wave
@@ -123,6 +128,7 @@ typedef struct pgs_replay {
     uint32_t* count_dev;
     uint64_t entry_capacity;
     uint32_t pair_capacity;
+    uint32_t entry_words; /* 3 or 4, see entry_dev */
 } pgs_replay;
 
 /* Entry capacity that no pass with at most `pair_capacity` pairs can exceed
@@ -487,12 +493,16 @@ pgs_status pgs_adam_step_dev(float* params_dev, const float* grads_dev, float* m
  * Estimation", K_n = 16): for every point i of points_dev [3][m] (float32),
  * the k other points with the smallest squared distance
  * ((dx*dx) + (dy*dy)) + (dz*dz) formed in float64, ties broken by the
- * smaller index.  k in 1..32, m > k.
- *   nbr_dev  out [k][m] int32 neighbour indices, nearest first
- *   d2_dev   out [k][m] float64 squared distances
+ * smaller index.  k in {4, 8, 16, 32}, m > k.  Searched through a uniform
+ * grid of at most 128^3 cells over the points' bounding box; the result
+ * equals a brute-force search bit for bit.
+ *   nbr_dev    out [k][m] int32 neighbour indices, nearest first
+ *   d2_dev     out [k][m] float64 squared distances
+ *   workspace  >= pgs_knn_workspace(m) bytes (grid cells, points in cell order)
  */
+size_t pgs_knn_workspace(int32_t m);
 pgs_status pgs_knn(const float* points_dev, int32_t m, int32_t k, int32_t* nbr_dev,
-                   double* d2_dev, void* stream);
+                   double* d2_dev, void* workspace_dev, size_t workspace_bytes, void* stream);
 
 /*
  * pgs_pca_seed - disc-like covariance seeding (Sec. "Disc-Like Covariance
@@ -834,6 +844,19 @@ pgs_status pgs_mvs_fuse(const pgs_camera* cams_dev, const int32_t* targets_dev, 
  * writes exactly `bytes`).
  */
 pgs_status pgs_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
+
+/*
+ * pgs_atomic_scatter - float-atomic throughput reference for the gradient
+ * scatter of pgs_render_bwd (index-mapping equation, the "+=" into the 2D
+ * gradient records): for every i < n_targets adds 1.0f to fields 0..8 of
+ * record targets_dev[i] of records_dev [n_records][PGS_GRAD2D_STRIDE]
+ * (targets >= n_records are skipped), 256 targets per workgroup in the
+ * order the render backward flushes a batch of splats.  Given the sorted
+ * pair values of a view as targets, it issues the backward's atomics at the
+ * backward's contention.  A measurement aid, not part of the method.
+ */
+pgs_status pgs_atomic_scatter(float* records_dev, uint32_t n_records, const uint32_t* targets_dev,
+                              uint32_t n_targets, void* stream);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ class PgsCamera(ctypes.Structure):
 class PgsReplay(ctypes.Structure):
     _fields_ = [("mask_dev", c_void_p), ("steps_dev", c_void_p), ("base_dev", c_void_p), ("used_dev", c_void_p),
                 ("entry_dev", c_void_p), ("count_dev", c_void_p), ("entry_capacity", c_uint64),
-                ("pair_capacity", c_uint32)]
+                ("pair_capacity", c_uint32), ("entry_words", c_uint32)]
 
 
 class PgsViewBatch(ctypes.Structure):
@@ -90,7 +90,8 @@ SIGNATURES = {
     "pgs_psnr": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "pgs_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                 POINTER(c_float), c_int32, c_float, c_float, c_float, c_void_p]),
-    "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "pgs_knn_workspace": (c_size_t, [c_int32]),
+    "pgs_knn": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "pgs_pca_seed": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_float,
                                c_void_p, c_void_p]),
     "pgs_views_layout": (c_int32, [POINTER(PgsViewBatch), POINTER(c_int32), POINTER(ctypes.c_int64)]),
@@ -123,6 +124,7 @@ SIGNATURES = {
     "pgs_seed_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                  c_void_p]),
     "pgs_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pgs_atomic_scatter": (c_int32, [c_void_p, c_uint32, c_void_p, c_uint32, c_void_p]),
     "pgs_ba_workspace": (c_size_t, [c_int32, c_int32, c_int32]),
     "pgs_ba_cost": (c_int32, [POINTER(PgsBaProblem), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                               c_void_p]),

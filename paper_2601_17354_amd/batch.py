@@ -25,7 +25,7 @@ import torch
 
 from . import binding as B
 from ._lib import GRAD2D_STRIDE, PGS_FLAG_CACHE_OVERFLOW, PGS_FLAG_PAIR_OVERFLOW, PROJ_STRIDE
-from .raster import MAX_ENTRIES, new_trace, param_rows
+from .raster import MAX_ENTRIES, TRACE_WORDS, new_trace, param_rows
 from .train import BETA1, BETA2, EPS, learning_rates
 
 
@@ -33,7 +33,7 @@ class BatchedStep:
     def __init__(self, params: torch.Tensor, sh_degree: int, cams: list, targets: list, tile=(16, 16),
                  batch: int = 256, blocks: int = 0, cached: bool = True, lam: float = 0.2, extent: float = 1.0,
                  capacity: int | None = None, bg=(0.0, 0.0, 0.0), ordered: bool = True,
-                 entries: int | None = None):
+                 entries: int | None = None, trace_words: int = TRACE_WORDS):
         self.params = params.contiguous()
         self.sh_degree = int(sh_degree)
         self.F, self.n = self.params.shape
@@ -43,6 +43,7 @@ class BatchedStep:
         self.cams = list(cams)
         self.V = len(cams)
         self.cached, self.lam, self.bg = cached, lam, tuple(float(x) for x in bg)
+        self.trace_words = int(trace_words)
         n, V = self.n, self.V
         self.tw, self.th = self.views.tile_w, self.views.tile_h
         self.nt = self.views.n_tiles
@@ -74,6 +75,7 @@ class BatchedStep:
         self.loss_ws = torch.empty(ws, dtype=torch.uint8, device=d)
         self.capacity = 0
         self.graph = None
+        self.events = None       # list: HIP events recorded after each stage (eager steps only)
         self.entry_capacity = int(entries) if entries is not None else max(1 << 20, 32 * self.npx)
         self._alloc_pairs(capacity if capacity is not None else max(4096, 4 * n * V))
 
@@ -98,7 +100,8 @@ class BatchedStep:
         self.workspace = torch.empty(B.pgs_bin_sort_workspace(self.n * self.V, capacity), dtype=torch.uint8,
                                      device=d)
         if self.cached:
-            self.trace = new_trace(capacity, self.tw * self.th // 64, self.nt, self.npx, self.entry_capacity, d)
+            self.trace = new_trace(capacity, self.tw * self.th // 64, self.nt, self.npx, self.entry_capacity, d,
+                                   self.trace_words)
 
     def memory_bytes(self) -> int:
         tot = 0
@@ -108,30 +111,43 @@ class BatchedStep:
         return tot
 
     # -- the step ----------------------------------------------------------
+    def _mark(self, name):
+        if self.events is not None:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            self.events.append((name, ev))
+
     def forward(self):
         n = self.n
+        self._mark("start")
         B.pgs_project_views(self.views, self.params, n, self.sh_degree, self.proj, self.radius, self.rect,
                             self.touched)
+        self._mark("project_views")
         B.pgs_bin_sort_views(self.views, n, self.proj, self.rect, self.touched, self.capacity, self.keys,
                              self.values, self.ranges, self.num_pairs, self.flags, self.workspace)
         if self.order is not None:
             B.pgs_tile_order(self.ranges, self.nt, 0, self.nt, self.order)
+        self._mark("bin_sort_views")
         # the forward that records the trace takes the tiles in natural order
         # (neighbouring pair ranges and mask runs together), the others
         # heavy-first, as in the single-view rasterizer
         B.pgs_render_fwd_views(self.views, self.proj, n, self.values, self.ranges, self.bg, self.image,
                                self.t_final, self.n_contrib, self.trace if self.cached else None, self.flags,
                                None if self.cached else self.order, self.queue)
+        self._mark("render_fwd")
 
     def backward_from(self, dl=None):
         """Render and projection backward from dL/dimage (default: self.dl);
         accumulates into self.grads (the caller zeroes it)."""
         n = self.n
         self.grad2d.zero_()
+        self._mark("zero")
         B.pgs_render_bwd_views(self.views, self.proj, n, self.values, self.ranges, self.bg, self.t_final,
                                self.n_contrib, self.trace if self.cached else None,
                                self.dl if dl is None else dl, self.grad2d, self.order, self.queue)
+        self._mark("render_bwd")
         B.pgs_project_bwd_views(self.views, self.params, n, self.sh_degree, self.radius, self.grad2d, self.grads)
+        self._mark("project_bwd_views")
 
     def step(self):
         """One full training step over every view (no host synchronisation)."""
@@ -140,10 +156,12 @@ class BatchedStep:
             B.pgs_loss_l1_dssim(self.view_slice(self.image, v), self.view_slice(self.target, v), cam["width"],
                                 cam["height"], self.lam, self.losses[v:v + 1], self.view_slice(self.dl, v),
                                 self.loss_ws)
+        self._mark("loss")
         self.grads.zero_()
         self.backward_from()
         B.pgs_adam_step_dev(self.params, self.grads, self.m, self.v, self.F, self.n, self.lr, self.adam_state,
                             BETA1, BETA2, EPS)
+        self._mark("adam")
 
     # -- overflow protocol -------------------------------------------------
     def read_flags(self) -> int:

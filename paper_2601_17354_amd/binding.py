@@ -57,11 +57,13 @@ def replay_struct(trace) -> PgsReplay | None:
     r.used_dev = _ptr(trace["used"], torch.int64).value
     r.entry_dev = _ptr(trace["entry"], torch.float32).value
     _need(trace["steps"], trace["base"].numel(), "trace base")
-    _need(trace["entry"], 4 * int(trace["entry_capacity"]), "trace entries")
+    words = int(trace["entry"].shape[1])
+    _need(trace["entry"], words * int(trace["entry_capacity"]), "trace entries")
     _need(trace["mask"], int(trace["pair_capacity"]) * trace["steps"].shape[-1], "trace masks")
     r.count_dev = _ptr(trace["count"], torch.int32).value
     r.entry_capacity = int(trace["entry_capacity"])
     r.pair_capacity = int(trace["pair_capacity"])
+    r.entry_words = words
     return r
 
 
@@ -227,10 +229,21 @@ def pgs_adam_step(params, grads, m, v, rows, n, lr, step, beta1, beta2, eps, str
           "pgs_adam_step")
 
 
-def pgs_knn(points, m, k, nbr, d2, stream=None):
+def pgs_knn_workspace(m) -> int:
+    return int(_lib.load().pgs_knn_workspace(m))
+
+
+def pgs_knn(points, m, k, nbr, d2, workspace, stream=None):
     lib = _lib.load()
-    check(lib.pgs_knn(_ptr(points, F32), m, k, _ptr(nbr, I32), _ptr(d2, torch.float64), _stream(stream)),
-          "pgs_knn")
+    check(lib.pgs_knn(_ptr(points, F32), m, k, _ptr(nbr, I32), _ptr(d2, torch.float64),
+                      _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)), "pgs_knn")
+
+
+def pgs_atomic_scatter(records, n_records, targets, n_targets, stream=None):
+    _need(records, 16 * n_records, "records")
+    _need(targets, n_targets, "targets")
+    check(_lib.load().pgs_atomic_scatter(_ptr(records, F32), n_records, _ptr(targets, I32), n_targets,
+                                         _stream(stream)), "pgs_atomic_scatter")
 
 
 def pgs_stream_copy(src, dst, nbytes, stream=None):

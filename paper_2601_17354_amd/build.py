@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpocketgs.so")
 
 SOURCES = ["api.hip", "project.hip", "binning.hip", "render.hip", "render_views.hip", "loss.hip", "adam.hip", "seed.hip",
-           "mlp.hip", "ba.hip", "mvs.hip", "stream_copy.hip", "runtime.hip"]
+           "mlp.hip", "ba.hip", "mvs.hip", "stream_copy.hip", "atomic_scatter.hip", "runtime.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -11,7 +11,7 @@ using pgs::Trace;
 using pgs::TileJob;
 using pgs::TileLds;
 
-template <int TW, int TH, bool CACHED>
+template <int TW, int TH, bool CACHED, int EW = 4>
 __global__ __launch_bounds__(TW* TH) void k_render_fwd(
     int W, int H, int TX, int tile_offset, int n_tiles_total, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, float bg0, float bg1,
@@ -22,10 +22,10 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
     __shared__ pgs::FwdLds<BG> L;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const TileJob j{W, H, tile % TX, tile / TX, tile_offset + tile, proj, image, t_final, n_contrib, tr.count};
-    pgs::fwd_tile<TW, TH, BG, CACHED>(j, n_tiles_total, n, values, ranges, bg0, bg1, bg2, tr, flags, L);
+    pgs::fwd_tile<TW, TH, BG, CACHED, EW>(j, n_tiles_total, n, values, ranges, bg0, bg1, bg2, tr, flags, L);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int EW>
 __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
     int W, int H, int TX, int tile_offset, int n_tiles_total, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, Trace tr,
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_cached(
     __shared__ TileLds<BG> L;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const TileJob j{W, H, tile % TX, tile / TX, tile_offset + tile, proj, nullptr, nullptr, nullptr, nullptr};
-    pgs::bwd_cached_tile<TW, TH, BG>(j, n_tiles_total, n, values, ranges, tr, dl_dimage, grad2d, L);
+    pgs::bwd_cached_tile<TW, TH, BG, EW>(j, n_tiles_total, n, values, ranges, tr, dl_dimage, grad2d, L);
 }
 
 template <int TW, int TH>
@@ -79,9 +79,10 @@ pgs_status pgs::make_trace(const pgs_replay* c, Trace& tr, const char* who) {
     PGS_REQUIRE(((uintptr_t)c->entry_dev % 16) == 0, "%s: trace entries must be 16-byte aligned", who);
     PGS_REQUIRE(c->entry_capacity <= 0xffffffffull, "%s: entry capacity %llu above 2^32 - 1", who,
                 (unsigned long long)c->entry_capacity);
+    PGS_REQUIRE(c->entry_words == 3 || c->entry_words == 4, "%s: entry_words %u is neither 3 nor 4", who,
+                c->entry_words);
     tr = Trace{c->mask_dev, c->steps_dev, c->base_dev, reinterpret_cast<unsigned long long*>(c->used_dev),
-               reinterpret_cast<float4*>(c->entry_dev), c->count_dev, (size_t)c->entry_capacity,
-               c->pair_capacity};
+               c->entry_dev, c->count_dev, (size_t)c->entry_capacity, c->pair_capacity, (int)c->entry_words};
     return PGS_OK;
 }
 
@@ -111,11 +112,18 @@ extern "C" pgs_status pgs_render_fwd(int32_t width, int32_t height, int32_t tile
     with_tile(tile_w, tile_h, [&](auto TWc, auto THc) {
         constexpr int TW = decltype(TWc)::value, TH = decltype(THc)::value;
         const dim3 grid(TX * TY), block(TW * TH);
-        if (cache)
-            k_render_fwd<TW, TH, true><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, n_tiles_total,
-                                                              proj_dev, n, values_dev, ranges_dev, bg_host[0],
-                                                              bg_host[1], bg_host[2], image_dev, t_final_dev,
-                                                              n_contrib_dev, tr, flags_dev, tile_order_dev);
+        if (cache && tr.words == 3)
+            k_render_fwd<TW, TH, true, 3><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset,
+                                                                 n_tiles_total, proj_dev, n, values_dev, ranges_dev,
+                                                                 bg_host[0], bg_host[1], bg_host[2], image_dev,
+                                                                 t_final_dev, n_contrib_dev, tr, flags_dev,
+                                                                 tile_order_dev);
+        else if (cache)
+            k_render_fwd<TW, TH, true, 4><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset,
+                                                                 n_tiles_total, proj_dev, n, values_dev, ranges_dev,
+                                                                 bg_host[0], bg_host[1], bg_host[2], image_dev,
+                                                                 t_final_dev, n_contrib_dev, tr, flags_dev,
+                                                                 tile_order_dev);
         else
             k_render_fwd<TW, TH, false><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset,
                                                                n_tiles_total, proj_dev, n, values_dev, ranges_dev,
@@ -152,10 +160,14 @@ extern "C" pgs_status pgs_render_bwd(int32_t width, int32_t height, int32_t tile
     with_tile(tile_w, tile_h, [&](auto TWc, auto THc) {
         constexpr int TW = decltype(TWc)::value, TH = decltype(THc)::value;
         const dim3 grid(TX * TY), block(TW * TH);
-        if (cache)
-            k_render_bwd_cached<TW, TH><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, n_tiles_total,
-                                                               proj_dev, n, values_dev, ranges_dev, tr,
-                                                               dl_dimage_dev, grad2d_dev, tile_order_dev);
+        if (cache && tr.words == 3)
+            k_render_bwd_cached<TW, TH, 3><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset,
+                                                                  n_tiles_total, proj_dev, n, values_dev, ranges_dev,
+                                                                  tr, dl_dimage_dev, grad2d_dev, tile_order_dev);
+        else if (cache)
+            k_render_bwd_cached<TW, TH, 4><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset,
+                                                                  n_tiles_total, proj_dev, n, values_dev, ranges_dev,
+                                                                  tr, dl_dimage_dev, grad2d_dev, tile_order_dev);
         else
             k_render_bwd_recompute<TW, TH><<<grid, block, 0, s>>>(width, height, TX, view_tile_offset, proj_dev, n,
                                                                   values_dev, ranges_dev, bg_host[0], bg_host[1],

@@ -172,10 +172,26 @@ struct Trace {
     uint32_t* steps;            // [n_tiles][NW]
     uint32_t* base;             // [n_tiles][NW] first entry of the wave's region
     unsigned long long* used;   // entries handed out in this forward
-    float4* entry;              // [entry_cap] (C_in r, g, b, alpha)
+    float* entry;               // [entry_cap][EW]: (C_in r, g, b[, alpha])
     uint32_t* count;            // [pixels]
     size_t entry_cap;
     uint32_t pair_cap;
+    int words;                  // EW of the launch: 4 with alpha, 3 without
+};
+
+// A trace entry of EW words: (C_in r, g, b, alpha) as one 16-byte record, or
+// (C_in r, g, b) as one 12-byte record when the backward recomputes alpha
+// from the staged splat with the forward's arithmetic (same bits).
+struct __attribute__((aligned(4))) Float3 {
+    float x, y, z;
+};
+template <int EW>
+struct EntryRec {
+    using T = float4;
+};
+template <>
+struct EntryRec<3> {
+    using T = Float3;
 };
 
 // One tile of one view.  Pixel arrays (image planes, t_final, n_contrib,
@@ -231,7 +247,7 @@ __device__ __forceinline__ void stage_batch(Lds& L, const float* __restrict__ pr
     }
 }
 
-template <int TW, int TH, int BG, bool CACHED>
+template <int TW, int TH, int BG, bool CACHED, int EW = 4>
 __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, int n,
                                          const uint32_t* __restrict__ values,
                                          const uint32_t* __restrict__ ranges, float bg0, float bg1,
@@ -394,7 +410,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     // than one per window.
     constexpr int kWin = BG >= 64 ? BG / 64 : 1;
     const uint64_t* wm = tr.mask + (size_t)wv * tr.pair_cap + start;
-    float4* went = tr.entry + ebase;  // the wave's entry region
+    typename EntryRec<EW>::T* went = reinterpret_cast<typename EntryRec<EW>::T*>(tr.entry) + ebase;
     for (int64_t lo = top; lo >= 0; lo -= BG) {
         const uint32_t hi = min((uint32_t)lo + BG, smax);
         __syncthreads();
@@ -445,7 +461,8 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
                 for (int q = 0; q < 4; ++q) {
                     if (lane_in(gm[q])) {
                         const float a = al[q];
-                        went[entry_slot(gm[q], gc[q])] = make_float4(a0, a1, a2, a);
+                        if constexpr (EW == 4) went[entry_slot(gm[q], gc[q])] = make_float4(a0, a1, a2, a);
+                        else went[entry_slot(gm[q], gc[q])] = Float3{a0, a1, a2};
                         a0 = a * sq[q].r + (1.f - a) * a0;
                         a1 = a * sq[q].g + (1.f - a) * a1;
                         a2 = a * sq[q].b + (1.f - a) * a2;
@@ -574,15 +591,21 @@ __device__ __forceinline__ void take_groups(uint64_t& any, uint64_t mv, uint32_t
 // Every lane loads: its own entry where it has one, else the wave's first
 // entry (the region is not empty when a group exists); alpha is taken as 0
 // for the latter in bwd_groups.
-__device__ __forceinline__ void load_groups(const float4* went, const TraceGroups& g, float4* e) {
+template <int EW>
+__device__ __forceinline__ void load_groups(const typename EntryRec<EW>::T* went, const TraceGroups& g,
+                                            float4* e) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) e[q] = went[lane_in(g.gm[q]) ? entry_slot(g.gm[q], g.gc[q]) : 0u];
+    for (int q = 0; q < 4; ++q) {
+        const typename EntryRec<EW>::T r = went[lane_in(g.gm[q]) ? entry_slot(g.gm[q], g.gc[q]) : 0u];
+        if constexpr (EW == 4) e[q] = r;
+        else e[q] = make_float4(r.x, r.y, r.z, 0.f);
+    }
 }
 
 // Gradients of four groups at this lane's pixel, reduced over the wave into
 // the batch accumulator; a lane without an entry in a group contributes
 // exact zeros there and keeps its dL/dC_out.
-template <int BG, class Lds>
+template <int BG, int EW, class Lds>
 __device__ __forceinline__ void bwd_groups(const TraceGroups& g, const float4* e, Lds& L, uint32_t slot0, float fpx,
                                            float fpy, int lane, float& g0, float& g1, float& g2) {
     float v[36];
@@ -590,8 +613,16 @@ __device__ __forceinline__ void bwd_groups(const TraceGroups& g, const float4* e
     for (int q = 0; q < 4; ++q) {
         const int jj = (int)slot0 + g.gi[q];
         const Splat s = load_splat(L.a, L.b, L.c, jj);
-        const float dx = s.u - fpx, dy = s.v - fpy;
-        const float a = lane_in(g.gm[q]) ? e[q].w : 0.f;
+        float dx = s.u - fpx, dy = s.v - fpy;
+        float a;
+        if constexpr (EW == 4) {
+            a = lane_in(g.gm[q]) ? e[q].w : 0.f;
+        } else {
+            // the entry's alpha, recomputed with the forward's arithmetic
+            float ar, gauss;
+            splat_alpha(s, fpx, fpy, ar, gauss, dx, dy);
+            a = lane_in(g.gm[q]) ? ar : 0.f;
+        }
         // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
         const float dla = g0 * (s.r - e[q].x) + g1 * (s.g - e[q].y) + g2 * (s.b - e[q].z);
         const bool clamped = a >= kAlphaMax;
@@ -605,7 +636,7 @@ __device__ __forceinline__ void bwd_groups(const TraceGroups& g, const float4* e
     accumulate_groups<BG, 4>(v, L.acc, lane, slot0, g.gi, g.gm);
 }
 
-template <int TW, int TH, int BG>
+template <int TW, int TH, int BG, int EW = 4>
 __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_total, int n,
                                                 const uint32_t* __restrict__ values,
                                                 const uint32_t* __restrict__ ranges, const Trace& tr,
@@ -621,7 +652,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
     const size_t ebase = tr.base[(size_t)j.gt * NW + wv];
-    const float4* went = tr.entry + ebase;  // the wave's entry region
+    const typename EntryRec<EW>::T* went = reinterpret_cast<const typename EntryRec<EW>::T*>(tr.entry) + ebase;
 
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;  // dL/dC_out of this pixel's next entry
     if (inside) {
@@ -658,22 +689,22 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
             TraceGroups ga, gb;
             float4 ea[4], eb[4];
             take_groups(any, mv, cursor, ga);
-            load_groups(went, ga, ea);
+            load_groups<EW>(went, ga, ea);
             for (;;) {
                 if (!any) {
-                    bwd_groups<BG>(ga, ea, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                    bwd_groups<BG, EW>(ga, ea, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
                     break;
                 }
                 take_groups(any, mv, cursor, gb);
-                load_groups(went, gb, eb);
-                bwd_groups<BG>(ga, ea, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                load_groups<EW>(went, gb, eb);
+                bwd_groups<BG, EW>(ga, ea, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
                 if (!any) {
-                    bwd_groups<BG>(gb, eb, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                    bwd_groups<BG, EW>(gb, eb, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
                     break;
                 }
                 take_groups(any, mv, cursor, ga);
-                load_groups(went, ga, ea);
-                bwd_groups<BG>(gb, eb, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
+                load_groups<EW>(went, ga, ea);
+                bwd_groups<BG, EW>(gb, eb, L, c0 - base, fpx, fpy, lane, g0, g1, g2);
             }
         }
         __syncthreads();

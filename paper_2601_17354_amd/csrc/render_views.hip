@@ -58,7 +58,7 @@ __global__ void k_clear_queue(uint32_t* queue) {
     if (threadIdx.x == 0) *queue = 0u;
 }
 
-template <int TW, int TH, int BG, bool CACHED>
+template <int TW, int TH, int BG, bool CACHED, int EW = 4>
 __global__ __launch_bounds__(TW* TH) void k_render_fwd_views(
     ViewTable vt, int n_tiles_total, const float* __restrict__ proj_all, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, float* __restrict__ image_all,
@@ -73,12 +73,12 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd_views(
         int v;
         const TileJob j = job_of(vt, gt, proj_all, n, image_all, t_final_all, n_contrib_all,
                                  CACHED ? tr.count : nullptr, v);
-        pgs::fwd_tile<TW, TH, BG, CACHED>(j, n_tiles_total, n, values, ranges, vt.bg[0], vt.bg[1], vt.bg[2],
-                                          tr, flags, L);
+        pgs::fwd_tile<TW, TH, BG, CACHED, EW>(j, n_tiles_total, n, values, ranges, vt.bg[0], vt.bg[1], vt.bg[2],
+                                              tr, flags, L);
     }
 }
 
-template <int TW, int TH, int BG, bool CACHED>
+template <int TW, int TH, int BG, bool CACHED, int EW = 4>
 __global__ __launch_bounds__(TW* TH) void k_render_bwd_views(
     ViewTable vt, int n_tiles_total, const float* __restrict__ proj_all, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges,
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd_views(
         const float* dl = dl_all + 3 * (size_t)vt.pix_off[v];
         float* g2 = grad2d_all + (size_t)v * PGS_GRAD2D_STRIDE * n;
         if constexpr (CACHED)
-            pgs::bwd_cached_tile<TW, TH, BG>(j, n_tiles_total, n, values, ranges, tr, dl, g2, L);
+            pgs::bwd_cached_tile<TW, TH, BG, EW>(j, n_tiles_total, n, values, ranges, tr, dl, g2, L);
         else
             pgs::bwd_recompute_tile<TW, TH, BG>(j, n, values, ranges, vt.bg[0], vt.bg[1], vt.bg[2], dl, g2, L);
     }
@@ -206,8 +206,14 @@ extern "C" pgs_status pgs_render_fwd_views(const pgs_view_batch* vb, const float
     if (cache) pgs::reset_trace_counter(tr, s);
     with_config(vb->tile_w, vb->tile_h, vb->batch, [&](auto TWc, auto THc, auto BGc) {
         constexpr int TW = decltype(TWc)::value, TH = decltype(THc)::value, BG = decltype(BGc)::value;
-        if (cache) {
-            auto k = k_render_fwd_views<TW, TH, BG, true>;
+        if (cache && tr.words == 3) {
+            auto k = k_render_fwd_views<TW, TH, BG, true, 3>;
+            const int blocks = resident_blocks(k, TW * TH, vb->blocks, total);
+            k<<<blocks, TW * TH, 0, s>>>(vt, total, proj_all_dev, n, values_dev, ranges_dev, image_all_dev,
+                                         t_final_all_dev, n_contrib_all_dev, tr, flags_dev, tile_order_dev,
+                                         queue_dev);
+        } else if (cache) {
+            auto k = k_render_fwd_views<TW, TH, BG, true, 4>;
             const int blocks = resident_blocks(k, TW * TH, vb->blocks, total);
             k<<<blocks, TW * TH, 0, s>>>(vt, total, proj_all_dev, n, values_dev, ranges_dev, image_all_dev,
                                          t_final_all_dev, n_contrib_all_dev, tr, flags_dev, tile_order_dev,
@@ -249,8 +255,14 @@ extern "C" pgs_status pgs_render_bwd_views(const pgs_view_batch* vb, const float
     k_clear_queue<<<1, 64, 0, s>>>(queue_dev);
     with_config(vb->tile_w, vb->tile_h, vb->batch, [&](auto TWc, auto THc, auto BGc) {
         constexpr int TW = decltype(TWc)::value, TH = decltype(THc)::value, BG = decltype(BGc)::value;
-        if (cache) {
-            auto k = k_render_bwd_views<TW, TH, BG, true>;
+        if (cache && tr.words == 3) {
+            auto k = k_render_bwd_views<TW, TH, BG, true, 3>;
+            const int blocks = resident_blocks(k, TW * TH, vb->blocks, total);
+            k<<<blocks, TW * TH, 0, s>>>(vt, total, proj_all_dev, n, values_dev, ranges_dev, t_final_all_dev,
+                                         n_contrib_all_dev, tr, dl_all_dev, grad2d_all_dev, tile_order_dev,
+                                         queue_dev);
+        } else if (cache) {
+            auto k = k_render_bwd_views<TW, TH, BG, true, 4>;
             const int blocks = resident_blocks(k, TW * TH, vb->blocks, total);
             k<<<blocks, TW * TH, 0, s>>>(vt, total, proj_all_dev, n, values_dev, ranges_dev, t_final_all_dev,
                                          n_contrib_all_dev, tr, dl_all_dev, grad2d_all_dev, tile_order_dev,

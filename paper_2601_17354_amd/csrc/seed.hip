@@ -1,13 +1,20 @@
 // KNN local surface statistics and disc-like covariance seeding (PocketGS
 // Sec. "Prior-Conditioned Gaussian Parameterization").
 //
-// pgs_knn: exact brute force.  One lane per query point; the workgroup stages
-// 256 candidate points at a time in LDS and every lane keeps its k best
-// (squared distance, index) pairs sorted in registers.  Squared distances
-// are ((dx*dx) + (dy*dy)) + (dz*dz) in float64 with contraction off, which
-// fixes every rounding, so neighbour sets and their order are reproducible
-// bit for bit.  Candidates arrive in increasing index order, so a candidate
-// only displaces strictly larger distances: ties keep the smaller index.
+// pgs_knn: exact k nearest neighbours through a uniform grid.  The points'
+// bounding box is cut into cubic cells (at most 128 along its longest side);
+// points are counted per cell, the counts scanned into cell starts and the
+// points' coordinates and indices gathered in cell order.  One lane per query
+// (queries in cell order, so a wave searches neighbouring cells) visits the
+// cells in shells of growing Chebyshev distance r around its own cell and
+// keeps its k best (squared distance, index) pairs sorted in registers,
+// ordered by distance and then index.  Every point of a cell r + 1 or more
+// cells away is farther than r cell widths, so the search stops after shell
+// r once the k-th distance is at most (r h)^2: no unvisited point can enter
+// or tie.  Squared distances are ((dx*dx) + (dy*dy)) + (dz*dz) in float64
+// with contraction off, which fixes every rounding, so the neighbour sets and
+// their order equal a brute-force search with ties broken by the smaller
+// index, bit for bit, whatever order the cells are visited in.
 //
 // pgs_pca_seed: per point, in float64: covariance of the 16 neighbours about
 // their centroid, cyclic Jacobi eigen-decomposition of the 3x3 matrix,
@@ -29,65 +36,273 @@ __device__ __forceinline__ double sqdist(double qx, double qy, double qz, double
     return (dx * dx + dy * dy) + dz * dz;
 }
 
-template <int K>
-__global__ __launch_bounds__(kKnnThreads) void k_knn(const float* __restrict__ pts, int m,
-                                                     int* __restrict__ nbr, double* __restrict__ d2out) {
-    __shared__ float sp[3][kKnnThreads];
-    const int q = blockIdx.x * kKnnThreads + threadIdx.x;
-    const bool live = q < m;
-    double qx = 0, qy = 0, qz = 0;
-    if (live) {
-        qx = pts[q];
-        qy = pts[(size_t)m + q];
-        qz = pts[2 * (size_t)m + q];
+// Grid of a KNN search: cubic cells of width h from the box corner lo,
+// dims[3] cells per axis (at most kGridMax).
+constexpr int kGridMax = 128;
+constexpr int kBoxBlocks = 256;
+
+struct GridDesc {
+    double lo[3];
+    double h;
+    int dims[3];
+};
+
+__device__ __forceinline__ int cell_axis(double v, double lo, double h, int dim) {
+    int c = (int)floor((v - lo) / h);
+    return c < 0 ? 0 : (c >= dim ? dim - 1 : c);
+}
+
+// Per-block partial bounding boxes: part[b][0..2] minima, [3..5] maxima.
+__global__ __launch_bounds__(256) void k_box_partial(const float* __restrict__ pts, int m, float* __restrict__ part) {
+    __shared__ float red[6][256];
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            const float v = pts[(size_t)a * m + i];
+            mn[a] = fminf(mn[a], v);
+            mx[a] = fmaxf(mx[a], v);
+        }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = mn[a];
+        red[3 + a][threadIdx.x] = mx[a];
     }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + off]);
+                red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + off]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// The grid from the partial boxes (every thread computes the same value).
+__device__ GridDesc grid_of(const float* __restrict__ part) {
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < kBoxBlocks; ++b)
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fminf(mn[a], part[b * 6 + a]);
+            mx[a] = fmaxf(mx[a], part[b * 6 + 3 + a]);
+        }
+    GridDesc g;
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) ext = fmax(ext, (double)mx[a] - (double)mn[a]);
+    g.h = ext > 0.0 ? ext / kGridMax : 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = mn[a];
+        const int d = (int)floor(((double)mx[a] - (double)mn[a]) / g.h) + 1;
+        g.dims[a] = d < 1 ? 1 : (d > kGridMax ? kGridMax : d);
+    }
+    return g;
+}
+
+__global__ __launch_bounds__(256) void k_cell_count(const float* __restrict__ pts, int m,
+                                                    const float* __restrict__ part, uint32_t* __restrict__ counts,
+                                                    uint32_t* __restrict__ cell_of) {
+    __shared__ GridDesc sg;
+    if (threadIdx.x == 0) sg = grid_of(part);
+    __syncthreads();
+    const GridDesc g = sg;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const int cx = cell_axis(pts[i], g.lo[0], g.h, g.dims[0]);
+        const int cy = cell_axis(pts[(size_t)m + i], g.lo[1], g.h, g.dims[1]);
+        const int cz = cell_axis(pts[2 * (size_t)m + i], g.lo[2], g.h, g.dims[2]);
+        const uint32_t c = ((uint32_t)cz * g.dims[1] + cy) * g.dims[0] + cx;
+        cell_of[i] = c;
+        atomicAdd(&counts[c], 1u);
+    }
+}
+
+// Exclusive scan of the cell counts into starts (one chunk of 4096 per
+// workgroup; the chunk totals are added up by each workgroup itself).
+constexpr int kCellScanItems = 4096;
+
+__global__ __launch_bounds__(256) void k_cell_total(const uint32_t* __restrict__ counts, uint32_t n,
+                                                    uint32_t* __restrict__ totals) {
+    __shared__ uint32_t red[256];
+    uint32_t s = 0;
+    for (uint32_t i = blockIdx.x * kCellScanItems + threadIdx.x; i < min(n, (blockIdx.x + 1) * kCellScanItems);
+         i += 256)
+        s += counts[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_cell_starts(const uint32_t* __restrict__ counts, uint32_t n,
+                                                     const uint32_t* __restrict__ totals,
+                                                     uint32_t* __restrict__ starts, uint32_t* __restrict__ cursor) {
+    __shared__ uint32_t sc[256];
+    __shared__ uint32_t s_before;
+    uint32_t b = 0;
+    for (uint32_t k = threadIdx.x; k < blockIdx.x; k += 256) b += totals[k];
+    sc[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < 256; ++k) t += sc[k];
+        s_before = t;
+    }
+    __syncthreads();
+    // 16 consecutive cells per thread
+    const uint32_t base = blockIdx.x * kCellScanItems + threadIdx.x * 16;
+    uint32_t loc[16], sum = 0;
+    for (int k = 0; k < 16; ++k) {
+        loc[k] = base + k < n ? counts[base + k] : 0u;
+        sum += loc[k];
+    }
+    sc[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t add = threadIdx.x >= (unsigned)off ? sc[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = s_before + sc[threadIdx.x] - sum;
+    for (int k = 0; k < 16; ++k) {
+        if (base + k < n) {
+            starts[base + k] = run;
+            cursor[base + k] = run;
+        }
+        run += loc[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_end(const uint32_t* __restrict__ counts, uint32_t n,
+                                                  uint32_t* __restrict__ starts) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) starts[n] = starts[n - 1] + counts[n - 1];
+}
+
+// Points in cell order (order inside a cell is arbitrary: the search's
+// tie rule does not depend on it).
+__global__ __launch_bounds__(256) void k_cell_scatter(const float* __restrict__ pts, int m,
+                                                      const uint32_t* __restrict__ cell_of,
+                                                      uint32_t* __restrict__ cursor, float4* __restrict__ sorted) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const uint32_t at = atomicAdd(&cursor[cell_of[i]], 1u);
+        sorted[at] = make_float4(pts[i], pts[(size_t)m + i], pts[2 * (size_t)m + i], __int_as_float(i));
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void knn_insert(double d, int idx, double (&bd)[K], int (&bi)[K]) {
+    // (d, idx) enters when it precedes the last entry in (distance, index)
+    // order; entries it precedes shift down one slot
+    if (!(d < bd[K - 1] || (d == bd[K - 1] && idx < bi[K - 1]))) return;
+    bool placed = false;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+        if (!placed) {
+            if (k > 0 && (bd[k - 1] > d || (bd[k - 1] == d && bi[k - 1] > idx))) {
+                bd[k] = bd[k - 1];
+                bi[k] = bi[k - 1];
+            } else {
+                bd[k] = d;
+                bi[k] = idx;
+                placed = true;
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kKnnThreads) void k_knn_grid(const float4* __restrict__ sorted, int m,
+                                                          const float* __restrict__ part,
+                                                          const uint32_t* __restrict__ starts,
+                                                          int* __restrict__ nbr, double* __restrict__ d2out) {
+    __shared__ GridDesc sg;
+    if (threadIdx.x == 0) sg = grid_of(part);
+    __syncthreads();
+    const GridDesc g = sg;
+    const int j = blockIdx.x * kKnnThreads + threadIdx.x;
+    if (j >= m) return;
+    const float4 qp = sorted[j];
+    const int q = __float_as_int(qp.w);
+    const double qx = qp.x, qy = qp.y, qz = qp.z;
+    const int cx = cell_axis(qx, g.lo[0], g.h, g.dims[0]);
+    const int cy = cell_axis(qy, g.lo[1], g.h, g.dims[1]);
+    const int cz = cell_axis(qz, g.lo[2], g.h, g.dims[2]);
     double bd[K];
     int bi[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         bd[k] = INFINITY;
-        bi[k] = -1;
+        bi[k] = 0x7fffffff;
     }
-    for (int base = 0; base < m; base += kKnnThreads) {
-        const int c = base + threadIdx.x;
-        __syncthreads();
-        if (c < m) {
-            sp[0][threadIdx.x] = pts[c];
-            sp[1][threadIdx.x] = pts[(size_t)m + c];
-            sp[2][threadIdx.x] = pts[2 * (size_t)m + c];
-        }
-        __syncthreads();
-        const int nc = min(kKnnThreads, m - base);
-        if (!live) continue;
-        for (int j = 0; j < nc; ++j) {
-            const int idx = base + j;
-            if (idx == q) continue;
-            const double d = sqdist(qx, qy, qz, sp[0][j], sp[1][j], sp[2][j]);
-            if (!(d < bd[K - 1])) continue;
-            // shift strictly larger entries down one slot (the last drops
-            // out) and place d after every entry with distance <= d
-            bool placed = false;
-#pragma unroll
-            for (int k = K - 1; k >= 0; --k) {
-                if (!placed) {
-                    if (k > 0 && bd[k - 1] > d) {
-                        bd[k] = bd[k - 1];
-                        bi[k] = bi[k - 1];
-                    } else {
-                        bd[k] = d;
-                        bi[k] = idx;
-                        placed = true;
+    const int rmax = max(g.dims[0], max(g.dims[1], g.dims[2]));
+    for (int r = 0; r <= rmax; ++r) {
+        for (int dz = -r; dz <= r; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= g.dims[2]) continue;
+            for (int dy = -r; dy <= r; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= g.dims[1]) continue;
+                const bool face = dz == -r || dz == r || dy == -r || dy == r;
+                // on the shell: every x of a face row, else only x = -r and x = +r
+                for (int dx = -r; dx <= r; dx += (face || r == 0) ? 1 : 2 * r) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= g.dims[0]) continue;
+                    const uint32_t c = ((uint32_t)z * g.dims[1] + y) * g.dims[0] + x;
+                    const uint32_t e = starts[c + 1];
+                    for (uint32_t t = starts[c]; t < e; ++t) {
+                        const float4 p = sorted[t];
+                        const int idx = __float_as_int(p.w);
+                        if (idx == q) continue;
+                        knn_insert<K>(sqdist(qx, qy, qz, p.x, p.y, p.z), idx, bd, bi);
                     }
                 }
             }
         }
+        // cells r + 1 or more away hold only points farther than r h
+        const double reach = (double)r * g.h;
+        if (bi[K - 1] != 0x7fffffff && bd[K - 1] <= reach * reach * (1.0 - 1e-12)) break;
     }
-    if (!live) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         nbr[(size_t)k * m + q] = bi[k];
         d2out[(size_t)k * m + q] = bd[k];
     }
+}
+
+// Workspace of pgs_knn for m points.
+struct KnnWs {
+    float* part;
+    uint32_t* counts;
+    uint32_t* starts;
+    uint32_t* cursor;
+    uint32_t* totals;
+    uint32_t* cell_of;
+    float4* sorted;
+    size_t bytes;
+};
+
+constexpr uint32_t kGridCells = (uint32_t)kGridMax * kGridMax * kGridMax;
+
+KnnWs knn_layout(void* base, int m) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    KnnWs w{};
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    w.part = reinterpret_cast<float*>(p + off); off += up((size_t)kBoxBlocks * 6 * 4);
+    w.counts = reinterpret_cast<uint32_t*>(p + off); off += up((size_t)kGridCells * 4);
+    w.starts = reinterpret_cast<uint32_t*>(p + off); off += up(((size_t)kGridCells + 1) * 4);
+    w.cursor = reinterpret_cast<uint32_t*>(p + off); off += up((size_t)kGridCells * 4);
+    w.totals = reinterpret_cast<uint32_t*>(p + off); off += up((size_t)(kGridCells / kCellScanItems + 1) * 4);
+    w.cell_of = reinterpret_cast<uint32_t*>(p + off); off += up((size_t)m * 4);
+    w.sorted = reinterpret_cast<float4*>(p + off); off += up((size_t)m * 16);
+    w.bytes = off;
+    return w;
+}
+
+__global__ void k_clear_cells(uint32_t* __restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
 // Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations.
@@ -379,18 +594,31 @@ __global__ __launch_bounds__(256) void k_seed_apply(const float* __restrict__ y,
 
 }  // namespace
 
+extern "C" size_t pgs_knn_workspace(int32_t m) { return knn_layout(nullptr, m > 0 ? m : 0).bytes; }
+
 extern "C" pgs_status pgs_knn(const float* points_dev, int32_t m, int32_t k, int32_t* nbr_dev,
-                              double* d2_dev, void* stream) {
+                              double* d2_dev, void* workspace_dev, size_t workspace_bytes, void* stream) {
     PGS_REQUIRE(k == 4 || k == 8 || k == 16 || k == kMaxK, "pgs_knn: k must be 4, 8, 16 or 32 (k=%d)", k);
     PGS_REQUIRE(m > k, "pgs_knn: need m > k (k=%d m=%d)", k, m);
-    PGS_REQUIRE(points_dev && nbr_dev && d2_dev, "pgs_knn: null pointer");
+    PGS_REQUIRE(points_dev && nbr_dev && d2_dev && workspace_dev, "pgs_knn: null pointer");
+    const KnnWs w = knn_layout(workspace_dev, m);
+    PGS_REQUIRE(workspace_bytes >= w.bytes, "pgs_knn: workspace %zu < %zu", workspace_bytes, w.bytes);
     hipStream_t s = pgs::as_stream(stream);
+    const int gm = (m + 255) / 256 < 4096 ? (m + 255) / 256 : 4096;
+    k_box_partial<<<kBoxBlocks, 256, 0, s>>>(points_dev, m, w.part);
+    k_clear_cells<<<1024, 256, 0, s>>>(w.counts, kGridCells);
+    k_cell_count<<<gm, 256, 0, s>>>(points_dev, m, w.part, w.counts, w.cell_of);
+    const uint32_t chunks = (kGridCells + kCellScanItems - 1) / kCellScanItems;
+    k_cell_total<<<chunks, 256, 0, s>>>(w.counts, kGridCells, w.totals);
+    k_cell_starts<<<chunks, 256, 0, s>>>(w.counts, kGridCells, w.totals, w.starts, w.cursor);
+    k_cell_end<<<1, 64, 0, s>>>(w.counts, kGridCells, w.starts);
+    k_cell_scatter<<<gm, 256, 0, s>>>(points_dev, m, w.cell_of, w.cursor, w.sorted);
     const dim3 grid((m + kKnnThreads - 1) / kKnnThreads), block(kKnnThreads);
     switch (k) {
-        case 4: k_knn<4><<<grid, block, 0, s>>>(points_dev, m, nbr_dev, d2_dev); break;
-        case 8: k_knn<8><<<grid, block, 0, s>>>(points_dev, m, nbr_dev, d2_dev); break;
-        case 16: k_knn<16><<<grid, block, 0, s>>>(points_dev, m, nbr_dev, d2_dev); break;
-        default: k_knn<kMaxK><<<grid, block, 0, s>>>(points_dev, m, nbr_dev, d2_dev); break;
+        case 4: k_knn_grid<4><<<grid, block, 0, s>>>(w.sorted, m, w.part, w.starts, nbr_dev, d2_dev); break;
+        case 8: k_knn_grid<8><<<grid, block, 0, s>>>(w.sorted, m, w.part, w.starts, nbr_dev, d2_dev); break;
+        case 16: k_knn_grid<16><<<grid, block, 0, s>>>(w.sorted, m, w.part, w.starts, nbr_dev, d2_dev); break;
+        default: k_knn_grid<kMaxK><<<grid, block, 0, s>>>(w.sorted, m, w.part, w.starts, nbr_dev, d2_dev); break;
     }
     PGS_CHECK_LAUNCH("pgs_knn");
     return PGS_OK;

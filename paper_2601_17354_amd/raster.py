@@ -26,17 +26,24 @@ def param_rows(sh_degree: int) -> int:
 MAX_ENTRIES = (1 << 32) - 1
 
 
-def new_trace(pair_capacity: int, nw: int, n_tiles: int, pixels: int, entries: int, device) -> dict:
+# Words per replay-trace entry: 3 = C_in (alpha recomputed by the backward
+# from the staged splat, same bits), 4 = (C_in, alpha) as the paper's cache
+# stores it.  The lean layout moves a quarter fewer trace bytes.
+TRACE_WORDS = 3
+
+
+def new_trace(pair_capacity: int, nw: int, n_tiles: int, pixels: int, entries: int, device,
+              words: int = TRACE_WORDS) -> dict:
     """Replay-trace buffers (layout of pgs_replay): masks per pair slot and
     wave, per-wave step counters and entry offsets, the entry counter,
-    `entries` 16-byte entries and per-pixel counts."""
+    `entries` entries of `words` floats and per-pixel counts."""
     entries = max(1, min(int(entries), MAX_ENTRIES))
     return dict(
         mask=torch.empty((nw, max(pair_capacity, 1)), dtype=torch.int64, device=device),
         steps=torch.empty((n_tiles, nw), dtype=torch.int32, device=device),
         base=torch.empty((n_tiles, nw), dtype=torch.int32, device=device),
         used=torch.zeros(1, dtype=torch.int64, device=device),
-        entry=torch.empty((entries, 4), dtype=torch.float32, device=device),
+        entry=torch.empty((entries, words), dtype=torch.float32, device=device),
         count=torch.empty(pixels, dtype=torch.int32, device=device),
         entry_capacity=entries, pair_capacity=int(pair_capacity),
     )
@@ -45,7 +52,8 @@ def new_trace(pair_capacity: int, nw: int, n_tiles: int, pixels: int, entries: i
 class Rasterizer:
     def __init__(self, n: int, sh_degree: int, width: int, height: int, tile=(16, 16),
                  cached: bool = True, capacity: int | None = None,
-                 device="cuda", ordered: bool = True, entries: int | None = None):
+                 device="cuda", ordered: bool = True, entries: int | None = None,
+                 trace_words: int = TRACE_WORDS):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.W, self.H = int(width), int(height)
@@ -54,6 +62,7 @@ class Rasterizer:
         self.TY = (self.H + self.th - 1) // self.th
         self.n_tiles = self.TX * self.TY
         self.cached = cached
+        self.trace_words = int(trace_words)
         self.device = torch.device(device)
         d = self.device
         n = max(self.n, 1)
@@ -78,6 +87,11 @@ class Rasterizer:
         self.nw = self.tw * self.th // 64
         self.entry_capacity = int(entries) if entries is not None else max(1 << 20, 32 * self.W * self.H)
         self._alloc_pairs(capacity if capacity is not None else max(1024, 4 * self.n))
+        # Work of each compositing launch, for measurement: when a list, every
+        # forward and backward appends its pair count P, trace entries E and
+        # pixels (reading them synchronises, so it is off by default).
+        self.work_log = None
+        self.log_tag = None       # recorded with each entry (e.g. the camera index)
 
     # -- buffers ---------------------------------------------------------
     def _alloc_pairs(self, capacity: int, entries: int | None = None):
@@ -94,7 +108,8 @@ class Rasterizer:
         ws = B.pgs_bin_sort_workspace(self.n, capacity)
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=d)
         if self.cached:
-            self.trace = new_trace(capacity, self.nw, self.n_tiles, self.H * self.W, self.entry_capacity, d)
+            self.trace = new_trace(capacity, self.nw, self.n_tiles, self.H * self.W, self.entry_capacity, d,
+                                   self.trace_words)
 
     def reserve(self, pair_factor: float = 2.0):
         """Enlarge the pair capacity and the trace entries ahead of training,
@@ -116,7 +131,22 @@ class Rasterizer:
         B.pgs_render_fwd(self.W, self.H, self.tw, self.th, self.proj, n, self.values, self.ranges,
                          0, bg, self.image, self.t_final, self.n_contrib,
                          self.trace if self.cached else None, self.flags, self.fwd_order)
+        self.log_work("render_fwd")
         return self.image
+
+    def work(self) -> dict:
+        """Pair count P, trace entries E (0 without a trace), pixels and
+        whether the buffers held the pass (no overflow flag) of the last
+        forward (synchronises)."""
+        P = min(int(self.num_pairs.item()), self.capacity)
+        E = int(self.trace["used"].item()) if self.cached else 0
+        return dict(P=P, E=E, pixels=self.W * self.H, ok=int(self.flags.item()) == 0)
+
+    def log_work(self, kernel: str):
+        if self.work_log is not None:
+            w = self.work()
+            w.update(kernel=kernel, cached=self.cached, tag=self.log_tag)
+            self.work_log.append(w)
 
     @property
     def fwd_order(self):
@@ -166,5 +196,6 @@ class Rasterizer:
         B.pgs_render_bwd(self.W, self.H, self.tw, self.th, self.proj, self.n, self.values,
                          self.ranges, 0, bg, self.t_final, self.n_contrib,
                          self.trace if self.cached else None, dl_dimage, self.grad2d, self.tile_order)
+        self.log_work("render_bwd")
         B.pgs_project_bwd(params, self.n, self.sh_degree, cam, self.radius, self.grad2d, grads)
         return grads

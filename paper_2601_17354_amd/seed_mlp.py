@@ -52,7 +52,8 @@ def neighbourhoods(points: torch.Tensor):
     m = points.shape[1]
     nbr = torch.empty((K_NN, m), dtype=torch.int32, device=points.device)
     d2 = torch.empty((K_NN, m), dtype=torch.float64, device=points.device)
-    B.pgs_knn(points, m, K_NN, nbr, d2)
+    ws = torch.empty(B.pgs_knn_workspace(m), dtype=torch.uint8, device=points.device)
+    B.pgs_knn(points, m, K_NN, nbr, d2, ws)
     return nbr, d2
 
 
@@ -83,6 +84,26 @@ def seed_learned(points: torch.Tensor, colours: torch.Tensor, weights: torch.Ten
     count = torch.zeros(1, dtype=torch.int32, device=points.device)
     B.pgs_seed_apply(y, base, pca, m, pca, None, count)
     return pca, int(count.item())
+
+
+def seed_constant_offset(points: torch.Tensor, colours: torch.Tensor, weights: torch.Tensor,
+                         r_normal: float = R_NORMAL):
+    """Control for the learned seed: the plain seed with the network's mean
+    output over the cloud applied to every point as one constant offset
+    (the same log-scale offsets, local rotation and logit offset for all),
+    which is what a network reduced to its output bias could learn; returns
+    (params, fallback count, the mean output)."""
+    m = points.shape[1]
+    nbr, d2 = neighbourhoods(points)
+    pca = torch.empty((14, m), dtype=torch.float32, device=points.device)
+    B.pgs_pca_seed(points, colours, m, nbr, d2, K_NN, r_normal, pca)
+    x, base = features(points, nbr, d2, r_normal)
+    y = forward(weights, x)
+    ybar = y.mean(0, dtype=torch.float64).to(torch.float32)
+    yc = ybar.expand(m, 8).contiguous()
+    count = torch.zeros(1, dtype=torch.int32, device=points.device)
+    B.pgs_seed_apply(yc, base, pca, m, pca, None, count)
+    return pca, int(count.item()), ybar.cpu().numpy().tolist()
 
 
 class SeedNetTrainer:

@@ -41,7 +41,8 @@ def seed_pca(points: torch.Tensor, colours: torch.Tensor, r_normal: float = R_NO
     k = 16
     nbr = torch.empty((k, m), dtype=torch.int32, device=points.device)
     d2 = torch.empty((k, m), dtype=torch.float64, device=points.device)
-    B.pgs_knn(points, m, k, nbr, d2)
+    ws = torch.empty(B.pgs_knn_workspace(m), dtype=torch.uint8, device=points.device)
+    B.pgs_knn(points, m, k, nbr, d2, ws)
     out = torch.empty((14, m), dtype=torch.float32, device=points.device)
     B.pgs_pca_seed(points, colours, m, nbr, d2, k, r_normal, out)
     return out
@@ -52,7 +53,7 @@ class Trainer:
 
     def __init__(self, params: torch.Tensor, sh_degree: int, width: int, height: int,
                  cached: bool = True, lam: float = 0.2, extent: float = 1.0,
-                 tile=(16, 16), ordered: bool = True):
+                 tile=(16, 16), ordered: bool = True, trace_words: int | None = None):
         self.params = params.contiguous()
         self.sh_degree = sh_degree
         self.F, self.n = self.params.shape
@@ -63,7 +64,8 @@ class Trainer:
         self.lr = learning_rates(sh_degree, extent)
         self.lam = lam
         self.W, self.H = width, height
-        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached, ordered=ordered)
+        kw = {} if trace_words is None else {"trace_words": trace_words}
+        self.rast = Rasterizer(self.n, sh_degree, width, height, tile=tile, cached=cached, ordered=ordered, **kw)
         self.dl = torch.empty((3, height, width), dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = torch.empty(B.pgs_loss_workspace(width, height), dtype=torch.uint8, device=dev)
@@ -96,6 +98,7 @@ class Trainer:
         B.pgs_render_fwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.image, r.t_final,
                          r.n_contrib, r.trace if r.cached else None, r.flags, r.fwd_order)
         self._mark("render_fwd")
+        r.log_work("render_fwd")
         if check and r.read_flags():
             r.forward_checked(self.params, cam, bg)
         B.pgs_loss_l1_dssim(r.image, target, r.W, r.H, self.lam, self.loss, self.dl, self.loss_ws)
@@ -106,6 +109,7 @@ class Trainer:
         B.pgs_render_bwd(r.W, r.H, r.tw, r.th, r.proj, n, r.values, r.ranges, 0, bg, r.t_final,
                          r.n_contrib, r.trace if r.cached else None, self.dl, r.grad2d, r.tile_order)
         self._mark("render_bwd")
+        r.log_work("render_bwd")
         B.pgs_project_bwd(self.params, n, self.sh_degree, cam, r.radius, r.grad2d, self.grads)
         self._mark("project_bwd")
         if adam:

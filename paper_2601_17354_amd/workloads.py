@@ -30,14 +30,14 @@ def render_targets(params: torch.Tensor, sh_degree: int, cams: list, width: int,
 
 
 def scene_views(scene_seed, n_points, n_gt=500_000, width=1920, height=1440, n_cams=60, target_cams=None,
-                device="cuda"):
-    """Seeded spheres-and-planes scene: ground truth = n_gt flat opaque
-    Gaussians on its surfaces (seed 1000 + scene_seed), targets = the ground
-    truth rendered at n_cams ring cameras (every 8th held out), and a noisy
-    n_points cloud of the same surfaces (seed 2000 + scene_seed)."""
+                device="cuda", gt_opacity=0.95):
+    """Seeded spheres-and-planes scene: ground truth = n_gt flat Gaussians of
+    opacity gt_opacity on its surfaces (seed 1000 + scene_seed), targets =
+    the ground truth rendered at n_cams ring cameras (every 8th held out),
+    and a noisy n_points cloud of the same surfaces (seed 2000 + scene_seed)."""
     dev = torch.device(device)
     scene = synth.spheres_planes_scene(scene_seed)
-    gt = synth.surface_gaussians(scene, n_gt, seed=1000 + scene_seed, sh_degree=0, opacity=0.95)
+    gt = synth.surface_gaussians(scene, n_gt, seed=1000 + scene_seed, sh_degree=0, opacity=gt_opacity)
     cams = synth.ring_cameras(n_cams, width, height)
     test_ids = [i for i in range(n_cams) if i % 8 == 0]
     train_ids = [i for i in range(n_cams) if i % 8 != 0]
@@ -64,21 +64,26 @@ def training_workload(n_train=300_000, n_gt=500_000, width=1920, height=1440, sc
 
 
 def compare_inits(weights, scene_seeds=(200, 201, 202), n_points=200_000, n_gt=400_000, width=1024,
-                  height=768, iters=500, eval_at=(0, 100, 500), isotropic=True, log=None):
+                  height=768, iters=500, eval_at=(0, 100, 500), isotropic=True, log=None,
+                  gt_opacity=(0.95, 0.95, 0.95)):
     """Held-out PSNR after training from the plain seed, the learned seed
-    (network `weights`, plain-seed fall back) and, for context, an isotropic
-    seed (r_normal = 1), on fresh scenes.  Returns per-scene histories, the
-    mean over scenes and the learned seed's fall-back counts."""
-    from .seed_mlp import seed_learned
+    (network `weights`, plain-seed fall back), the control that applies the
+    network's mean output to every point as a constant offset, and, for
+    context, an isotropic seed (r_normal = 1), on fresh scenes whose ground
+    truth has opacity gt_opacity[i].  Returns per-scene histories, the mean
+    over scenes, the learned seed's fall-back counts and the control's
+    constant offsets."""
+    from .seed_mlp import seed_constant_offset, seed_learned
     from .train import Trainer, train
     rng = np.random.default_rng(0)
-    per_scene, fallbacks = {}, {}
-    for s in scene_seeds:
-        wl = scene_views(s, n_points, n_gt, width, height)
+    per_scene, fallbacks, offsets = {}, {}, {}
+    for s, op in zip(scene_seeds, gt_opacity):
+        wl = scene_views(s, n_points, n_gt, width, height, gt_opacity=op)
         P, C = wl["cloud"]
         order = [int(i) for i in rng.permutation(wl["train_ids"])]
         inits = {"plain_pca": seed_pca(P, C)}
         inits["learned"], fallbacks[str(s)] = seed_learned(P, C, weights)
+        inits["constant_offset"], _, offsets[str(s)] = seed_constant_offset(P, C, weights)
         if isotropic:
             inits["isotropic"] = seed_pca(P, C, r_normal=1.0)
         res = {}
@@ -95,7 +100,8 @@ def compare_inits(weights, scene_seeds=(200, 201, 202), n_points=200_000, n_gt=4
     names = list(next(iter(per_scene.values())).keys())
     mean = {n: {str(k): round(float(np.mean([per_scene[sc][n][str(k)] for sc in per_scene])), 3)
                 for k in eval_at} for n in names}
-    return dict(per_scene=per_scene, mean=mean, fallbacks=fallbacks)
+    return dict(per_scene=per_scene, mean=mean, fallbacks=fallbacks, constant_offsets=offsets,
+                gt_opacity=dict(zip([str(x) for x in scene_seeds], gt_opacity)))
 
 
 def batched_workload(n=1_000_000, sh_degree=3, n_gt=500_000, scene_seed=0, device="cuda"):

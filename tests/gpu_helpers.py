@@ -76,14 +76,15 @@ def max_rel(got, want, floor_frac=1e-3):
 
 
 def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None,
-            capacity=None, tile=(16, 16)):
+            capacity=None, tile=(16, 16), trace_words=None):
     """One view through the HIP path; returns numpy copies of every output."""
     from paper_2601_17354_amd.raster import Rasterizer
     dev = torch.device("cuda")
     n = P.shape[1]
     params = torch.as_tensor(np.ascontiguousarray(P, np.float32), device=dev)
+    kw = {} if trace_words is None else {"trace_words": trace_words}
     R = Rasterizer(n, sh_degree, cam["width"], cam["height"], tile=tile, cached=cached,
-                   capacity=capacity)
+                   capacity=capacity, **kw)
     R.forward_checked(params, cam, bg)
     torch.cuda.synchronize()
     out = dict(
@@ -110,7 +111,8 @@ def run_gpu(P, cam, sh_degree, cached=True, bg=(0.0, 0.0, 0.0), dl_dimage=None,
 
 def trace_entries(out, cam, x, y, tile=(16, 16)):
     """Replay-trace entries (id, alpha, C_in) of pixel (x, y), decoded from the
-    per-wave groups of the GPU trace (layout documented at pgs_replay)."""
+    per-wave groups of the GPU trace (layout documented at pgs_replay); alpha
+    is None for the 3-word layout, which does not store it."""
     R = out["rast"]
     tw, th = tile
     nt = tw * th
@@ -130,5 +132,7 @@ def trace_entries(out, cam, x, y, tile=(16, 16)):
         cursor += bin(m).count("1")
     assert len(ents) == int(out["count"][y, x])
     e = torch.as_tensor([q for _, q in ents], dtype=torch.int64, device=R.device)
-    rec = R.trace["entry"][e].cpu().numpy().reshape(-1, 4)
-    return np.asarray([i for i, _ in ents], np.int64), rec[:, 3], rec[:, :3]
+    words = R.trace["entry"].shape[1]
+    rec = R.trace["entry"][e].cpu().numpy().reshape(-1, words)
+    alpha = rec[:, 3] if words == 4 else None
+    return np.asarray([i for i, _ in ents], np.int64), alpha, rec[:, :3]

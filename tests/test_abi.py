@@ -46,7 +46,7 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert b"n < 0" in lib.pgs_last_error()
     st = lib.pgs_project(None, 10, 4, ctypes.byref(cam), 16, 16, None, None, None, None, None)
     assert st == _lib.PGS_ERR_INVALID_ARG
-    assert lib.pgs_knn(None, 100, 5, None, None, None) == _lib.PGS_ERR_INVALID_ARG
+    assert lib.pgs_knn(None, 100, 5, None, None, None, 0, None) == _lib.PGS_ERR_INVALID_ARG
     assert lib.pgs_sort_pairs(None, None, None, 10, 70, None, 0, None) == _lib.PGS_ERR_INVALID_ARG
     lr = (ctypes.c_float * 1)(0.1)
     assert lib.pgs_adam_step(None, None, None, None, 65, 10, lr, 1, 0.9, 0.999, 1e-15, None) == \

@@ -62,9 +62,10 @@ def full(request):
     grads = project_vjp(P, cam, g2d, proj["visible"])
     say("[fullsize] HIP path, cached and recompute")
     gc = run_gpu(P, cam, deg, cached=True, dl_dimage=dl)
+    gc4 = run_gpu(P, cam, deg, cached=True, dl_dimage=dl, trace_words=4)
     gr = run_gpu(P, cam, deg, cached=False, dl_dimage=dl)
     return dict(P=P, cam=cam, proj=proj, bins=bins, tiles=tiles, on=on, fwd=fwd, g2d=g2d, tainted=tainted,
-                grads=grads, gc=gc, gr=gr)
+                grads=grads, gc=gc, gc4=gc4, gr=gr)
 
 
 def test_full_projection_and_sort(full):
@@ -97,10 +98,12 @@ def test_full_sampled_tiles_forward(full):
     assert (g["n_contrib"][ok] == fwd["n_contrib"][ok]).all()
     assert (g["count"][ok] == fwd["count"][ok]).all()
     np.testing.assert_array_equal(g["image"], full["gr"]["image"])
+    np.testing.assert_array_equal(g["image"], full["gc4"]["image"])
 
 
-def test_full_sampled_trace_entries(full):
-    fwd, g, cam, on = full["fwd"], full["gc"], full["cam"], full["on"]
+@pytest.mark.parametrize("layout", ["gc", "gc4"])
+def test_full_sampled_trace_entries(full, layout):
+    fwd, g, cam, on = full["fwd"], full[layout], full["cam"], full["on"]
     ys, xs = np.nonzero(on & ~fwd["marginal"])
     rng = np.random.default_rng(3)
     pick = rng.choice(xs.size, 24, replace=False)
@@ -113,13 +116,14 @@ def test_full_sampled_trace_entries(full):
         ids, al, cin = trace_entries(g, cam, x, y)
         assert list(ids) == [e[0] for e in want], (x, y)
         if want:
-            assert_block_close(al, [e[1] for e in want], IMG_TOL, what=f"alpha {(x, y)}")
+            if al is not None:
+                assert_block_close(al, [e[1] for e in want], IMG_TOL, what=f"alpha {(x, y)}")
             w = np.asarray([e[2] for e in want])
             worst = max(worst, assert_cin_close(cin, w, (x, y)))
     say(f"  C_in error / its rounding bound, worst entry: {worst:.3f}")
 
 
-@pytest.mark.parametrize("variant", ["gc", "gr"])
+@pytest.mark.parametrize("variant", ["gc", "gc4", "gr"])
 def test_full_gradients(full, variant):
     g, ok = full[variant], ~full["tainted"]
     say(f"[fullsize] {variant}: Gaussians with gradients {int((np.abs(full['g2d']).sum(0) > 0).sum())}")

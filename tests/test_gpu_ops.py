@@ -129,7 +129,8 @@ def _knn_gpu(pts, k=16):
     P = torch.as_tensor(np.ascontiguousarray(pts.T, np.float32), device=DEV)
     nbr = torch.empty((k, m), dtype=torch.int32, device=DEV)
     d2 = torch.empty((k, m), dtype=torch.float64, device=DEV)
-    B.pgs_knn(P, m, k, nbr, d2)
+    ws = torch.empty(B.pgs_knn_workspace(m), dtype=torch.uint8, device=DEV)
+    B.pgs_knn(P, m, k, nbr, d2, ws)
     return P, nbr, d2
 
 
@@ -360,3 +361,48 @@ def test_edge_cases(kind):
     floor = GRAD_TOL * 1e-6 * np.abs(og).max()
     for r in range(og.shape[0]):
         assert_block_close(g["grads"][r], og[r], GRAD_TOL, mask=~taint, what=f"row {r}", atol=floor)
+
+
+def test_atomic_scatter_adds_one_per_target_and_field():
+    # the float-atomic reference: every target adds 1 to fields 0..8 of its
+    # record, out-of-range targets are skipped, fields 9..15 are untouched
+    from paper_2601_17354_amd import binding as B
+    rng = np.random.default_rng(21)
+    n_rec, n_t = 5000, 70001
+    tg = rng.integers(0, n_rec + 10, n_t).astype(np.int32)
+    rec = torch.full((n_rec, 16), 0.5, device=DEV)
+    B.pgs_atomic_scatter(rec, n_rec, torch.as_tensor(tg, device=DEV), n_t)
+    got = rec.cpu().numpy()
+    want = 0.5 + np.bincount(tg[tg < n_rec], minlength=n_rec).astype(np.float64)
+    for f in range(9):
+        np.testing.assert_array_equal(got[:, f], want)
+    assert (got[:, 9:] == 0.5).all()
+
+
+@pytest.mark.parametrize("case", ["plane", "duplicates", "outlier", "tiny", "scene300k"])
+def test_knn_grid_search_cases(case):
+    # the grid search against the oracle's brute force with its tie rule:
+    # a flat box axis, exact duplicates, a far outlier that stretches the grid,
+    # the fewest points allowed, and the benchmark cloud's size (sampled
+    # queries)
+    rng = np.random.default_rng(31)
+    k = 16
+    if case == "plane":
+        pts = np.c_[rng.uniform(size=(3000, 2)), np.full(3000, 0.25)].astype(np.float32)
+    elif case == "duplicates":
+        pts = np.repeat(rng.uniform(size=(400, 3)).astype(np.float32), 5, axis=0)
+    elif case == "outlier":
+        pts = np.r_[rng.normal(size=(4000, 3)) * 0.01, [[60.0, -40.0, 25.0]]].astype(np.float32)
+    elif case == "tiny":
+        pts = (rng.uniform(size=(17, 3)) * 1e-3 + 5.0).astype(np.float32)
+    else:
+        pts = synth.noisy_cloud(synth.spheres_planes_scene(0), 300_000, seed=2000)[0].astype(np.float32)
+    say(f"[knn] {case}: {len(pts)} points")
+    _, nbr, d2 = _knn_gpu(pts, k)
+    torch.cuda.synchronize()
+    q = list(range(0, len(pts), max(1, len(pts) // 150)))
+    if case == "outlier":
+        q.append(len(pts) - 1)
+    ids, dd = o_seed.knn(pts, q, k)
+    np.testing.assert_array_equal(nbr.cpu().numpy()[:, q].T, ids)
+    np.testing.assert_array_equal(d2.cpu().numpy()[:, q].T, dd)

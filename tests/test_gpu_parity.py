@@ -52,9 +52,10 @@ def case(request):
     proj, bins, fwd = pipeline.forward(P, cam, bg=bg)
     o_grads, o_g2d, tainted = pipeline.backward(P, cam, proj, bins, fwd, dl, "cached")
     gpu_c = run_gpu(P, cam, deg, cached=True, bg=bg, dl_dimage=dl)
+    gpu_c4 = run_gpu(P, cam, deg, cached=True, bg=bg, dl_dimage=dl, trace_words=4)
     gpu_r = run_gpu(P, cam, deg, cached=False, bg=bg, dl_dimage=dl)
     return dict(name=name, P=P, cam=cam, bg=bg, dl=dl, proj=proj, bins=bins, fwd=fwd,
-                o_grads=o_grads, o_g2d=o_g2d, tainted=tainted, gc=gpu_c, gr=gpu_r)
+                o_grads=o_grads, o_g2d=o_g2d, tainted=tainted, gc=gpu_c, gc4=gpu_c4, gr=gpu_r)
 
 
 def test_projection(case):
@@ -108,14 +109,18 @@ def test_render_forward(case):
     assert_block_close(g["t_final"], fwd["T_final"], IMG_TOL, mask=ok, what="T_final")
     assert (g["n_contrib"][ok] == fwd["n_contrib"][ok]).all()
     assert (g["count"][ok] == fwd["count"][ok]).all()
-    # the no-trace forward writes the same image bits
-    np.testing.assert_array_equal(g["image"], case["gr"]["image"])
-    np.testing.assert_array_equal(g["n_contrib"], case["gr"]["n_contrib"])
+    # the no-trace forward and the 4-word trace layout write the same image bits
+    for other in ("gr", "gc4"):
+        np.testing.assert_array_equal(g["image"], case[other]["image"])
+        np.testing.assert_array_equal(g["n_contrib"], case[other]["n_contrib"])
+    np.testing.assert_array_equal(g["count"], case["gc4"]["count"])
 
 
-def test_replay_trace_entries(case):
+@pytest.mark.parametrize("layout", ["gc", "gc4"])
+def test_replay_trace_entries(case, layout):
+    # ids and C_in in both entry layouts; alpha where the entry stores it
     from oracle.render import replay_entries
-    fwd, g, cam = case["fwd"], case["gc"], case["cam"]
+    fwd, g, cam = case["fwd"], case[layout], case["cam"]
     H, W = cam["height"], cam["width"]
     rng = np.random.default_rng(5)
     pix = [(int(x), int(y)) for x, y in zip(rng.integers(0, W, 24), rng.integers(0, H, 24))]
@@ -129,13 +134,14 @@ def test_replay_trace_entries(case):
         ids, al, cin = trace_entries(g, cam, x, y)
         assert list(ids) == [e[0] for e in want], (x, y)
         if want:
-            assert_block_close(al, [e[1] for e in want], IMG_TOL, what=f"alpha {(x, y)}")
+            if al is not None:
+                assert_block_close(al, [e[1] for e in want], IMG_TOL, what=f"alpha {(x, y)}")
             w = np.asarray([e[2] for e in want])
             worst = max(worst, assert_cin_close(cin, w, (x, y)))
     say(f"  C_in error / its rounding bound, worst entry: {worst:.3f}")
 
 
-@pytest.mark.parametrize("variant", ["gc", "gr"])
+@pytest.mark.parametrize("variant", ["gc", "gc4", "gr"])
 def test_render_backward_2d(case, variant):
     g, og, taint = case[variant], case["o_g2d"], case["tainted"]
     ok = ~taint
@@ -144,7 +150,7 @@ def test_render_backward_2d(case, variant):
         assert_block_close(g["grad2d"][f], og[f], GRAD_TOL, mask=ok, what=f"{variant} d{name}")
 
 
-@pytest.mark.parametrize("variant", ["gc", "gr"])
+@pytest.mark.parametrize("variant", ["gc", "gc4", "gr"])
 def test_canonical_gradients(case, variant):
     g, og, taint = case[variant], case["o_grads"], case["tainted"]
     ok = ~taint

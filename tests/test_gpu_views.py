@@ -135,13 +135,13 @@ def test_views_match_oracle_per_view(tile, batch, cached, blocks):
 # SH degree 3 on the seeded scene seen by three ring cameras of uneven size
 # (6,147 tiles of 16x16): tile shape, LDS batch, backward variant and the
 # number of persistent workgroups (each walking many queue items).
-BIG = [((16, 16), 256, True, 64), ((16, 16), 256, False, 64), ((8, 32), 128, True, 3),
-       ((16, 8), 64, False, 3)]
+BIG = [((16, 16), 256, True, 64, 3), ((16, 16), 256, True, 64, 4), ((16, 16), 256, False, 64, 3),
+       ((8, 32), 128, True, 3, 3), ((16, 8), 64, False, 3, 3)]
 
 
-@pytest.mark.parametrize("tile,batch,cached,blocks", BIG,
-                         ids=[f"{t[0]}x{t[1]}-b{b}-{'c' if c else 'r'}-grid{g}" for t, b, c, g in BIG])
-def test_views_sh3_ring_sampled_tiles_match_oracle(tile, batch, cached, blocks):
+@pytest.mark.parametrize("tile,batch,cached,blocks,words", BIG,
+                         ids=[f"{t[0]}x{t[1]}-b{b}-{'c' if c else 'r'}-grid{g}-w{w}" for t, b, c, g, w in BIG])
+def test_views_sh3_ring_sampled_tiles_match_oracle(tile, batch, cached, blocks, words):
     """Every sorted pair in full; compositing, counts and T_final on sampled
     tiles of every view (the heaviest plus seeded random ones) that the
     oracle renders one by one; every Gaussian's 2D gradient per view and
@@ -180,7 +180,7 @@ def test_views_sh3_ring_sampled_tiles_match_oracle(tile, batch, cached, blocks):
         f"{[r['tiles'] for r in ref]}")
     targets = [torch.zeros((3, c["height"], c["width"]), device=DEV) for c in cams]
     st = BatchedStep(torch.as_tensor(P, device=DEV), 3, cams, targets, tile=tile, batch=batch, cached=cached,
-                     blocks=blocks)
+                     blocks=blocks, trace_words=words)
     st.prepare()
     torch.cuda.synchronize()
     assert st.nt > 20 * blocks
