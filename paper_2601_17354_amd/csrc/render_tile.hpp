@@ -214,6 +214,7 @@ struct FwdLds {
     float4 b[BG];
     float c[BG];
     float2 e[BG];
+    uint8_t reach[BG];  // bit w: the splat can reach a pixel of wave w
     uint32_t steps;
     // per wave of the tile: entries, steps, fit flag and region start
     uint32_t wcur[4], wsteps[4], wfit[4];
@@ -247,6 +248,78 @@ __device__ __forceinline__ void stage_batch(Lds& L, const float* __restrict__ pr
     }
 }
 
+// Which waves of a TW x TH tile a splat can reach: bit w is cleared only if
+// splat_alpha gives alpha < 1/255 at every pixel centre of wave w's rows
+// (the wave's pixel-centre rectangle R_w).  Alpha reaches 1/255 only where
+// q = A dx^2 + 2 B dx dy + C dy^2 <= 2 ln(255 o).  The minimum of q over R_w
+// is zero if the centre lies inside R_w, else the least of the four edge
+// minima, each the minimum of a convex quadratic in one variable, clamped to
+// the edge.  Rounding: with rho = |B| / sqrt(A C), the magnitudes of q's
+// three terms sum to at most q (1 + rho) / (1 - rho), and each term carries
+// a relative error of a few units of roundoff u in float32, both in
+// splat_alpha and here (an error in the position of an edge minimum changes q
+// only to second order), so both evaluations are within
+// kappa = 64 u (1 + rho) / (1 - rho) of q relative to it.  A wave is dropped
+// when the computed minimum, shrunk by 2 kappa, still exceeds 2 ln(255 o) by
+// 1e-4, which also covers the rounding of the exponential, the opacity
+// product and the threshold; and never when kappa >= 1/8.
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t reach_waves(float u, float v, float A, float B, float C, float o, int tx,
+                                                int ty) {
+    constexpr int NW = TW * TH / 64;
+    constexpr int R = 64 / TW;  // pixel rows per wave
+    constexpr uint32_t kAll = (1u << NW) - 1u;
+    if (!(o > kAlphaMin * 0.5f)) return 0u;  // alpha = o e^power <= o < 1/255 everywhere
+    if (!(A > 0.f && C > 0.f)) return kAll;
+    const float ac = A * C;
+    const float rho = fabsf(B) * __frsqrt_rn(ac);
+    // 1 - rho = (A C - B^2) / (A C (1 + rho)), the determinant taken with one rounding
+    const float det = __builtin_fmaf(A, C, -B * B);
+    const float omr = det / (ac * (1.f + rho));
+    const float kappa = 64.f * 0x1p-24f * (1.f + rho) / omr;
+    if (!(omr > 0.f && kappa < 0.125f)) return kAll;
+    const float thr = 2.f * __logf(255.f * o) + 1e-4f;
+    const float shrink = 1.f - 2.f * kappa;
+    const float ra = 1.f / A, rc = 1.f / C;
+    const float xlo = (float)(tx * TW) + 0.5f, xhi = xlo + (float)(TW - 1);
+    // dx over the rectangle's columns, dy over its rows (d = centre - pixel)
+    const float dxa = u - xhi, dxb = u - xlo;
+    const float ma = -B * dxa * rc, mb = -B * dxb * rc;  // best dy on the columns x = xhi, xlo
+    auto q = [&](float dx, float dy) { return A * dx * dx + 2.f * B * dx * dy + C * dy * dy; };
+    uint32_t bits = 0u;
+#pragma unroll 1
+    for (int w = 0; w < NW; ++w) {
+        const float ylo = (float)(ty * TH + w * R) + 0.5f, yhi = ylo + (float)(R - 1);
+        const float dya = v - yhi, dyb = v - ylo;
+        float m = 0.f;
+        if (!(dxa <= 0.f && dxb >= 0.f && dya <= 0.f && dyb >= 0.f)) {
+            m = fminf(q(dxa, fminf(fmaxf(ma, dya), dyb)), q(dxb, fminf(fmaxf(mb, dya), dyb)));
+            // rows y = yhi, ylo: dx minimising q at fixed dy is -B dy / A
+            m = fminf(m, q(fminf(fmaxf(-B * dya * ra, dxa), dxb), dya));
+            m = fminf(m, q(fminf(fmaxf(-B * dyb * ra, dxa), dxb), dyb));
+        }
+        if (!(m * shrink > thr)) bits |= 1u << w;
+    }
+    return bits;
+}
+
+// Stages splats base .. base+nb-1 of the sorted list into LDS slots 0..nb-1
+// with the waves each can reach.
+template <int TW, int TH, int NT, int BG>
+__device__ __forceinline__ void stage_batch_reach(FwdLds<BG>& L, const float* __restrict__ proj,
+                                                  const uint32_t* __restrict__ values, uint32_t base, int nb,
+                                                  int t, int tx, int ty) {
+    for (int q = t; q < nb; q += NT) {
+        const uint32_t g = values[base + q];
+        const float4* rec = reinterpret_cast<const float4*>(proj + (size_t)g * PGS_PROJ_STRIDE);
+        const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+        L.a[q] = make_float4(r0.x, r0.y, -0.5f * r0.w, -r1.x);   // u, v, hA, nB
+        L.b[q] = make_float4(-0.5f * r1.y, r1.z, r1.w, r2.x);    // hC, o, r, g
+        L.c[q] = r2.y;                                           // b
+        L.reach[q] = (uint8_t)reach_waves<TW, TH>(r0.x, r0.y, r0.w, r1.x, r1.y, r1.z, tx, ty);
+    }
+}
+
 template <int TW, int TH, int BG, bool CACHED, int EW = 4>
 __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, int n,
                                          const uint32_t* __restrict__ values,
@@ -266,11 +339,11 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     // the trace is recorded only if this tile's pairs fit the trace buffers
     const bool rec = CACHED && end <= tr.pair_cap;
     if (CACHED && !rec && t == 0) atomicOr(flags, PGS_FLAG_CACHE_OVERFLOW);
-    // Each lane keeps the composited bits of the current 64-step chunk
-    // (bit s: this pixel took step s); a full chunk is transposed over the
-    // wave into the chunk's 64 step masks and written as one coalesced
-    // 512-byte run (wave-major mask layout).  The lane's entry count and
-    // last contributing step come from the same bits.
+    // Each lane keeps the composited bits of the current window of 64
+    // steps (bit s: this pixel took step s); a window is transposed over the
+    // wave into its 64 step masks and written as one coalesced 512-byte run
+    // (wave-major mask layout).  The lane's entry count and last
+    // contributing step come from the same bits.
     uint64_t* wmask = tr.mask + (size_t)wv * tr.pair_cap + start;
     uint64_t hist = 0ull;
     uint32_t steps = 0, cnt = 0, last = 0;
@@ -290,56 +363,68 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     for (uint32_t base = start; base < end; base += BG) {
         if (__syncthreads_count(!done) == 0) break;
         const int nb = (int)min((uint32_t)BG, end - base);
-        stage_batch<NT, false>(L, j.proj, n, values, base, nb, t);
+        stage_batch_reach<TW, TH, NT, BG>(L, j.proj, values, base, nb, t, j.tx, j.ty);
         __syncthreads();
-        // The wave takes FWD_UNROLL splats at a time: all their LDS loads
-        // and alphas first, straight-line (slots past the batch hold stale,
-        // in-bounds data that the valid flag discards), then the steps in
-        // order, with a termination check per group.
-        for (int k0 = 0; k0 < nb; k0 += FWD_UNROLL) {
+        // Windows of 64 steps.  Of a window the wave visits only the steps
+        // whose splat can reach one of its pixels (a wave-uniform bit set,
+        // walked with scalar bit scans), FWD_UNROLL at a time: their LDS
+        // loads and alphas first, straight-line, then the steps in order,
+        // with a termination check per group.  Every step it skips has alpha
+        // < 1/255 at all of its pixels, so its mask bits are zero as if it
+        // had been visited.
+        for (int c0 = 0; c0 < nb; c0 += 64) {
             if (__ballot(!done) == 0) break;  // the whole wave has terminated
-            // geometry and opacity only; the colours are read by the steps
-            // that composite
-            Splat sp[FWD_UNROLL];
+            const int cn = min(64, nb - c0);
+            uint64_t todo = __ballot(lane < cn && ((L.reach[c0 + lane] >> wv) & 1u) != 0u);
+            while (todo) {
+                if (__ballot(!done) == 0) break;
+                int kq[FWD_UNROLL];
+                bool val[FWD_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FWD_UNROLL; ++u) sp[u] = load_shape(L.a, L.b, (k0 + u) & (BG - 1));
-            float al[FWD_UNROLL];
-            bool hit[FWD_UNROLL];
+                for (int u = 0; u < FWD_UNROLL; ++u) {
+                    val[u] = todo != 0ull;
+                    kq[u] = val[u] ? (int)__builtin_ctzll(todo) : 0;
+                    todo &= todo - 1ull;
+                }
+                // geometry and opacity only; the colours are read by the
+                // steps that composite
+                Splat sp[FWD_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FWD_UNROLL; ++u) {
-                float gauss, dx, dy;
-                hit[u] = splat_alpha(sp[u], fpx, fpy, al[u], gauss, dx, dy) && k0 + u < nb;
-            }
-            uint32_t bits = 0;
+                for (int u = 0; u < FWD_UNROLL; ++u) sp[u] = load_shape(L.a, L.b, c0 + kq[u]);
+                float al[FWD_UNROLL];
+                bool hit[FWD_UNROLL];
 #pragma unroll
-            for (int u = 0; u < FWD_UNROLL; ++u) {
-                // exec-masked: a step none of the wave's pixels takes is
-                // skipped by the whole wave
-                if (hit[u] && !done) {
-                    const float alpha = al[u];
-                    const float test_T = T * (1.f - alpha);
-                    if (test_T < kTMin) {
-                        done = true;
-                    } else {
-                        const int k = (k0 + u) & (BG - 1);
-                        const float2 rg = *reinterpret_cast<const float2*>(&L.b[k].z);
-                        const float w = alpha * T;
-                        C0 += w * rg.x;
-                        C1 += w * rg.y;
-                        C2 += w * L.c[k];
-                        T = test_T;
-                        bits |= 1u << u;
+                for (int u = 0; u < FWD_UNROLL; ++u) {
+                    float gauss, dx, dy;
+                    hit[u] = splat_alpha(sp[u], fpx, fpy, al[u], gauss, dx, dy) && val[u];
+                }
+#pragma unroll
+                for (int u = 0; u < FWD_UNROLL; ++u) {
+                    // exec-masked: a step none of the wave's pixels takes is
+                    // skipped by the whole wave
+                    if (hit[u] && !done) {
+                        const float alpha = al[u];
+                        const float test_T = T * (1.f - alpha);
+                        if (test_T < kTMin) {
+                            done = true;
+                        } else {
+                            const int k = c0 + kq[u];
+                            const float2 rg = *reinterpret_cast<const float2*>(&L.b[k].z);
+                            const float w = alpha * T;
+                            C0 += w * rg.x;
+                            C1 += w * rg.y;
+                            C2 += w * L.c[k];
+                            T = test_T;
+                            hist |= 1ull << kq[u];
+                        }
                     }
                 }
             }
-            const uint32_t rel0 = base + (uint32_t)k0 - start;
-            const uint32_t nv = (uint32_t)min(FWD_UNROLL, nb - k0);
-            steps = rel0 + nv;
-            hist |= (uint64_t)bits << (rel0 & 63u);
-            if (((rel0 + FWD_UNROLL) & 63u) == 0u && nv == FWD_UNROLL) flush_chunk(rel0 + FWD_UNROLL - 64u, 64u);
+            const uint32_t rel0 = base + (uint32_t)c0 - start;
+            flush_chunk(rel0, (uint32_t)cn);
+            steps = rel0 + (uint32_t)cn;
         }
     }
-    if (steps & 63u) flush_chunk(steps & ~63u, steps & 63u);
     uint32_t cursor = 0;
     if (rec) cursor = wave_sum_u32(cnt);
     // Entry regions: one bump-counter atomic per tile (a single device-wide

@@ -37,6 +37,17 @@ def _cases():
     P, _, _ = synth.cfg1_inputs(7, n=400, width=100, height=75, focal=90.0)
     cam = synth.make_camera(100, 75, 90.0, 90.0, 50.0, 37.5, np.eye(3), np.zeros(3))
     out.append(("ragged-100x75", P, cam, 0, (0.5, 0.5, 0.5)))
+    # long thin splats (conic correlations up to ~0.995), half of them with
+    # opacity within a few times 1/255: alpha contours that graze the row
+    # bands of the tiles' waves, for the forward's per-wave reach test
+    P, cam, _ = synth.cfg1_inputs(11, n=1500)
+    rng = np.random.default_rng(11)
+    n = P.shape[1]
+    P[3] = rng.uniform(-2.0, -0.5, n)
+    P[4:6] = rng.uniform(-7.0, -5.0, (2, n))
+    o = rng.uniform(0.5, 4.0, n) / 255.0
+    P[10] = np.where(np.arange(n) % 2 == 0, np.log(o / (1.0 - o)), P[10])
+    out.append(("needles-128x128", P.astype(np.float32), cam, 0, (0.0, 0.0, 0.0)))
     return out
 
 
