@@ -33,16 +33,17 @@
 //              entries in flight; a lane with a bit set reads its entry, takes
 //              dL/dC_out (starts at dL/dC, times (1 - alpha) after each own
 //              entry), dL/dalpha = <dL/dC_out, c - C_in> and dL/dc =
-//              alpha dL/dC_out, chains them to the nine 2D parameters, and the
-//              wave reduces the four groups' values together (lane swaps and
-//              DPP).
+//              alpha dL/dC_out, forms the nine per-pixel terms that the
+//              splat's 2D gradients are linear in, and the wave reduces the
+//              four groups' terms together (lane swaps and DPP).
 //   recompute  walks the list back to front from n_contrib, re-evaluates
 //              alpha with the forward's exact arithmetic, recovers
 //              T_k = T_{k+1} / (1 - alpha_k) from T_final and accumulates the
 //              colour behind as it goes (the 3D Gaussian Splatting backward).
-// Per-wave partial sums meet in LDS and leave with one float atomic per
-// field and (tile, splat), scattered to the canonical index values[id]
-// (index-mapping equation).
+// Per-wave partial sums meet in LDS; once per batch the splat's conic and
+// opacity turn them into its nine 2D gradients, which leave with one float
+// atomic per field and (tile, splat), scattered to the canonical index
+// values[id] (index-mapping equation).
 #pragma once
 
 #include "common.hpp"
@@ -558,23 +559,41 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     }
 }
 
-// Nine 2D gradients of one splat at one pixel from dL/dalpha and dL/dc.
-__device__ __forceinline__ void chain_2d(const Splat& s, float dx, float dy, float alpha,
-                                         float dgauss_do, bool clamped, float dl_dalpha,
-                                         float dc0, float dc1, float dc2, float* v) {
-    const float dpow = clamped ? 0.f : alpha * dl_dalpha;
-    const float d_o = clamped ? 0.f : dgauss_do * dl_dalpha;
-    const float px = dpow * dx, py = dpow * dy;
-    // -(A dx + B dy) dpow and -(B dx + C dy) dpow from the staged halves
-    v[0] = __builtin_fmaf(s.hA, px, __builtin_fmaf(s.hA, px, s.nB * py));
-    v[1] = __builtin_fmaf(s.hC, py, __builtin_fmaf(s.hC, py, s.nB * px));
-    v[2] = -0.5f * dx * px;
-    v[3] = -dy * px;
-    v[4] = -0.5f * dy * py;
-    v[5] = d_o;
+// Per-pixel terms of one splat's nine 2D gradients, all linear in what the
+// wave and the tile sum: with p = dL/dpower = alpha dL/dalpha (0 where alpha
+// is clamped) and d = (dx, dy) the offset from the pixel to the mean, the
+// terms are p dx, p dy, p dx^2, p dx dy, p dy^2, p and dL/dc = alpha dL/dC_out.
+// The splat's conic and opacity, the same for every pixel, are applied once
+// per splat and tile to the sums (grad2d_from_sums).
+__device__ __forceinline__ void raw_terms(float dx, float dy, float alpha, bool clamped, float dl_dalpha,
+                                          float dc0, float dc1, float dc2, float* v) {
+    const float p = clamped ? 0.f : alpha * dl_dalpha;
+    const float px = p * dx, py = p * dy;
+    v[0] = px;
+    v[1] = py;
+    v[2] = px * dx;
+    v[3] = px * dy;
+    v[4] = py * dy;
+    v[5] = p;
     v[6] = dc0;
     v[7] = dc1;
     v[8] = dc2;
+}
+
+// The nine 2D gradients from the summed terms of raw_terms.  With
+// power = hA dx^2 + nB dx dy + hC dy^2 (hA = -A/2, nB = -B, hC = -C/2) and
+// alpha = o e^power: dL/du = 2 hA S(p dx) + nB S(p dy),
+// dL/dv = nB S(p dx) + 2 hC S(p dy), dL/dA = -S(p dx^2) / 2,
+// dL/dB = -S(p dx dy), dL/dC = -S(p dy^2) / 2, dL/do = S(p) / o (the
+// derivative of o e^power by o is alpha / o), dL/dc unchanged.
+__device__ __forceinline__ void grad2d_from_sums(float hA, float nB, float hC, float inv_o, float* f) {
+    const float spx = f[0], spy = f[1];
+    f[0] = __builtin_fmaf(2.f * hA, spx, nB * spy);
+    f[1] = __builtin_fmaf(2.f * hC, spy, nB * spx);
+    f[2] = -0.5f * f[2];
+    f[3] = -f[3];
+    f[4] = -0.5f * f[4];
+    f[5] = f[5] * inv_o;
 }
 
 // Sums 36 per-lane values over the wave with two swap-and-add stages
@@ -629,13 +648,25 @@ __device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[B
     }
 }
 
-// One float atomic per field and splat of the batch into the canonical
+// The batch's summed terms become its splats' 2D gradients (one thread per
+// splat), then one float atomic per field and splat goes into the canonical
 // 2D-gradient records (index map values[id]); the nine fields of a splat
 // share one 64-byte record, so consecutive lanes hit the same line.
 template <int BG>
-__device__ __forceinline__ void flush_batch(float (*acc)[BG], const uint32_t* gid, int nb, int n,
-                                            float* __restrict__ grad2d, int t, int NT) {
+__device__ __forceinline__ void flush_batch(TileLds<BG>& L, int nb, int n, float* __restrict__ grad2d, int t,
+                                            int NT) {
     (void)n;
+    float (*acc)[BG] = L.acc;
+    const uint32_t* gid = L.g;
+    for (int jj = t; jj < nb; jj += NT) {
+        float f[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f[k] = acc[k][jj];
+        grad2d_from_sums(L.a[jj].z, L.a[jj].w, L.b[jj].x, L.io[jj], f);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k][jj] = f[k];
+    }
+    __syncthreads();
     for (int idx = t; idx < nb * 9; idx += NT) {
         const int jj = idx / 9, f = idx - jj * 9;
         const float s = acc[f][jj];
@@ -711,7 +742,7 @@ __device__ __forceinline__ void bwd_groups(const TraceGroups& g, const float4* e
         // dL/dalpha = <dL/dC_out, c - C_in>, dL/dc = alpha dL/dC_out
         const float dla = g0 * (s.r - e[q].x) + g1 * (s.g - e[q].y) + g2 * (s.b - e[q].z);
         const bool clamped = a >= kAlphaMax;
-        chain_2d(s, dx, dy, a, a * L.io[jj], clamped, dla, a * g0, a * g1, a * g2, &v[q * 9]);
+        raw_terms(dx, dy, a, clamped, dla, a * g0, a * g1, a * g2, &v[q * 9]);
         // dL/dC_in = dL/dC_out (1 - alpha): the next entry's dL/dC_out
         const float om = 1.f - a;
         g0 *= om;
@@ -793,7 +824,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
             }
         }
         __syncthreads();
-        flush_batch<BG>(L.acc, L.g, nb, n, grad2d, t, NT);
+        flush_batch<BG>(L, nb, n, grad2d, t, NT);
         __syncthreads();
     }
 }
@@ -866,8 +897,7 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
                         const float q0 = Tk * G0, q1 = Tk * G1, q2 = Tk * G2;
                         const float dla = q0 * (s.r - a0) + q1 * (s.g - a1) + q2 * (s.b - a2);
                         const bool clamped = s.o * gauss > kAlphaMax;
-                        chain_2d(s, dx, dy, alpha, gauss, clamped, dla, alpha * q0, alpha * q1, alpha * q2,
-                                 &v[q * 9]);
+                        raw_terms(dx, dy, alpha, clamped, dla, alpha * q0, alpha * q1, alpha * q2, &v[q * 9]);
                         a0 = alpha * s.r + (1.f - alpha) * a0;
                         a1 = alpha * s.g + (1.f - alpha) * a1;
                         a2 = alpha * s.b + (1.f - alpha) * a2;
@@ -881,7 +911,7 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
             accumulate_groups<BG, 4>(v, L.acc, lane, 0u, gi, gm);
         }
         __syncthreads();
-        flush_batch<BG>(L.acc, L.g, nb, n, grad2d, t, NT);
+        flush_batch<BG>(L, nb, n, grad2d, t, NT);
         __syncthreads();
         hi = lo;
     }
