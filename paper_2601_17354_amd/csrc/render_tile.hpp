@@ -77,40 +77,18 @@ __device__ __forceinline__ bool splat_alpha(const Splat& s, float px, float py, 
 }
 
 // One splat's record (u, v, depth, A | B, C, o, r | g, b, ex, ey) is one
-// 64-byte line: three 16-byte loads.  (ex, ey) are the half-extents of the
-// pixels where its alpha can reach 1/255 (conservative, from the FP64
-// projection); the recompute backward skips a splat for a whole wave with
-// them.  (In the forward the test costs more than the alpha it saves.)
+// 64-byte line: three 16-byte loads.  (The compositing kernels decide which
+// waves a splat can reach from its conic instead of the half-extents
+// (ex, ey).)
 __device__ __forceinline__ void stage_splat(const float* __restrict__ proj, int n, uint32_t g,
-                                            float4* sa, float4* sb, float* sc, float2* se, int slot) {
+                                            float4* sa, float4* sb, float* sc, int slot) {
     (void)n;
     const float4* rec = reinterpret_cast<const float4*>(proj + (size_t)g * PGS_PROJ_STRIDE);
     const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
     sa[slot] = make_float4(r0.x, r0.y, -0.5f * r0.w, -r1.x);   // u, v, hA, nB
     sb[slot] = make_float4(-0.5f * r1.y, r1.z, r1.w, r2.x);    // hC, o, r, g
     sc[slot] = r2.y;                                  // b
-    se[slot] = make_float2(r2.z, r2.w);               // extents
 }
-
-// Pixel-centre rectangle of one wave of a TW x TH tile (64 consecutive
-// row-major lanes).
-template <int TW>
-struct WaveRect {
-    float x0, x1, y0, y1;
-    __device__ __forceinline__ WaveRect(int tx, int ty, int TH, int wv) {
-        x0 = (float)(tx * TW) + 0.5f;
-        x1 = x0 + (float)(TW - 1);
-        y0 = (float)(ty * TH + (64 * wv) / TW) + 0.5f;
-        y1 = (float)(ty * TH + (64 * wv + 63) / TW) + 0.5f;
-    }
-    // whether a splat centred at (u, v) with extents e can reach a pixel of
-    // the wave; the same answer in every lane (LDS broadcast operands), made
-    // scalar so that the skip is a uniform branch
-    __device__ __forceinline__ bool hit(float u, float v, float2 e) const {
-        const float dx = u - fminf(fmaxf(u, x0), x1), dy = v - fminf(fmaxf(v, y0), y1);
-        return __builtin_amdgcn_readfirstlane((int)(fabsf(dx) <= e.x && fabsf(dy) <= e.y)) != 0;
-    }
-};
 
 __device__ __forceinline__ Splat load_splat(const float4* sa, const float4* sb, const float* sc, int k) {
     const float4 a = sa[k], b = sb[k];
@@ -214,7 +192,6 @@ struct FwdLds {
     float4 a[BG];
     float4 b[BG];
     float c[BG];
-    float2 e[BG];
     uint8_t reach[BG];  // bit w: the splat can reach a pixel of wave w
     uint32_t steps;
     // per wave of the tile: entries, steps, fit flag and region start
@@ -227,9 +204,9 @@ struct TileLds {
     float4 a[BG];
     float4 b[BG];
     float c[BG];
-    float2 e[BG];
     uint32_t g[BG];
     float io[BG];  // 1 / opacity
+    uint8_t reach[BG];  // bit w: the splat can reach a pixel of wave w (recompute backward)
     float acc[9][BG];
     uint32_t steps;
 };
@@ -241,7 +218,7 @@ __device__ __forceinline__ void stage_batch(Lds& L, const float* __restrict__ pr
                                             int t) {
     for (int q = t; q < nb; q += NT) {
         const uint32_t g = values[base + q];
-        stage_splat(proj, n, g, L.a, L.b, L.c, L.e, q);
+        stage_splat(proj, n, g, L.a, L.b, L.c, q);
         if constexpr (KEEP_IDS) {
             L.g[q] = g;
             L.io[q] = 1.f / L.b[q].y;
@@ -305,9 +282,10 @@ __device__ __forceinline__ uint32_t reach_waves(float u, float v, float A, float
 }
 
 // Stages splats base .. base+nb-1 of the sorted list into LDS slots 0..nb-1
-// with the waves each can reach.
-template <int TW, int TH, int NT, int BG>
-__device__ __forceinline__ void stage_batch_reach(FwdLds<BG>& L, const float* __restrict__ proj,
+// with the waves each can reach (and, for the backward, their canonical ids
+// and 1 / opacity).
+template <int TW, int TH, int NT, bool KEEP_IDS, class Lds>
+__device__ __forceinline__ void stage_batch_reach(Lds& L, const float* __restrict__ proj,
                                                   const uint32_t* __restrict__ values, uint32_t base, int nb,
                                                   int t, int tx, int ty) {
     for (int q = t; q < nb; q += NT) {
@@ -318,6 +296,10 @@ __device__ __forceinline__ void stage_batch_reach(FwdLds<BG>& L, const float* __
         L.b[q] = make_float4(-0.5f * r1.y, r1.z, r1.w, r2.x);    // hC, o, r, g
         L.c[q] = r2.y;                                           // b
         L.reach[q] = (uint8_t)reach_waves<TW, TH>(r0.x, r0.y, r0.w, r1.x, r1.y, r1.z, tx, ty);
+        if constexpr (KEEP_IDS) {
+            L.g[q] = g;
+            L.io[q] = 1.f / r1.z;
+        }
     }
 }
 
@@ -364,7 +346,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     for (uint32_t base = start; base < end; base += BG) {
         if (__syncthreads_count(!done) == 0) break;
         const int nb = (int)min((uint32_t)BG, end - base);
-        stage_batch_reach<TW, TH, NT, BG>(L, j.proj, values, base, nb, t, j.tx, j.ty);
+        stage_batch_reach<TW, TH, NT, false>(L, j.proj, values, base, nb, t, j.tx, j.ty);
         __syncthreads();
         // Windows of 64 steps.  Of a window the wave visits only the steps
         // whose splat can reach one of its pixels (a wave-uniform bit set,
@@ -859,18 +841,26 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
     if (last) atomicMax(&L.steps, last);
     __syncthreads();
     const uint32_t top = L.steps;
-    const WaveRect<TW> wr(j.tx, j.ty, TH, t >> 6);
+    const int wv = t >> 6;
 
     for (uint32_t hi = top; hi > 0;) {
         const uint32_t lo = hi > (uint32_t)BG ? hi - BG : 0u;
         const int nb = (int)(hi - lo);
-        stage_batch<NT, true>(L, j.proj, n, values, start + lo, nb, t);
+        stage_batch_reach<TW, TH, NT, true>(L, j.proj, values, start + lo, nb, t, j.tx, j.ty);
         zero_acc<BG>(L.acc, t, NT);
         __syncthreads();
-        // back to front; the gradients of four splats that some lane of
-        // the wave uses are reduced over the wave together
-        int jj = nb - 1;
-        while (jj >= 0) {
+        // back to front over the steps whose splat can reach one of the
+        // wave's pixels (windows of 64 last to first, scalar bit scans); the
+        // gradients of four splats that some lane uses are reduced over the
+        // wave together
+        int cw = (nb - 1) >> 6;
+        auto window = [&](int w) {
+            const int k = 64 * w + lane;
+            return __ballot(k < nb && ((L.reach[k] >> wv) & 1u) != 0u);
+        };
+        uint64_t todo = window(cw);
+        bool more = true;
+        while (more) {
             float v[36];
             int gi[4];
             uint64_t gm[4];
@@ -880,9 +870,15 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
                 gm[q] = 0ull;
 #pragma unroll
                 for (int f = 0; f < 9; ++f) v[q * 9 + f] = 0.f;
-                while (jj >= 0) {
-                    const int k = jj--;
-                    if (!wr.hit(L.a[k].x, L.a[k].y, L.e[k])) continue;  // uniform: no lane can use it
+                while (more) {
+                    while (todo == 0ull && cw > 0) todo = window(--cw);
+                    if (todo == 0ull) {
+                        more = false;
+                        break;
+                    }
+                    const int bit = 63 - __clzll(todo);
+                    todo &= ~(1ull << bit);
+                    const int k = 64 * cw + bit;
                     bool ok = false;
                     float alpha = 0.f, gauss = 0.f, dx = 0.f, dy = 0.f;
                     Splat s{};
