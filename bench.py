@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--no-cfg2", action="store_true",
                     help="skip the 100k / SH 3 / 1024x768 cached-vs-recompute comparison")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: 4 views, 4 steps, one 1 GiB stream copy")
+                    help="for rocprofv3: the headline training step only (its timed steps and the per-stage "
+                         "pass), then one 1 GiB stream copy")
     ap.add_argument("--work-log", default=None,
                     help="write the pair count, trace entries and pixels of every compositing launch of the "
                          "training step here (JSON; synchronises after each launch)")
@@ -61,7 +62,6 @@ def parse():
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.profile:
-        args.views, args.steps, args.warmup = 4, 4, 2
         args.no_compare = args.no_cpu_baseline = args.no_psnr = args.no_batched = args.no_cfg2 = True
         args.no_ba = args.no_mvs = args.no_capture = args.no_atomic = True
     return args
@@ -80,6 +80,7 @@ def kernel_times(trainer, steps, order, cams, targets):
     for k in range(steps):
         trainer.events = []
         cid = order[k % len(order)]
+        trainer.rast.log_tag = int(cid)
         trainer.step(cams[cid], targets[cid])
         torch.cuda.synchronize()
         evs = trainer.events
@@ -108,6 +109,7 @@ def run_variant(wl, cached, steps, warmup, order, full_clear=False, work_log=Non
     if work_log is not None:
         tr.rast.work_log = work_log
     # size buffers on every training view (synchronises), then warm up
+    tr.rast.log_phase = "prepare"
     for cid in order:
         tr.rast.log_tag = int(cid)
         tr.prepare(wl["cams"][cid])
@@ -122,10 +124,12 @@ def run_variant(wl, cached, steps, warmup, order, full_clear=False, work_log=Non
         tr.step(wl["cams"][cid], targets[cid])
         return cid
 
+    tr.rast.log_phase = "warmup"
     for k in range(warmup):
         one(k)
     torch.cuda.synchronize()
     tr.rast.flags.zero_()
+    tr.rast.log_phase = "timed"
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -147,7 +151,9 @@ def run_variant(wl, cached, steps, warmup, order, full_clear=False, work_log=Non
         out["cleared_bytes"] = sum(t.numel() * t.element_size() for t in full)
         return out
     out["entry_bytes"] = 4 * tr.rast.trace_words if cached else 0
+    tr.rast.log_phase = "stages"
     per, recs = kernel_times(tr, min(20, steps), order, wl["cams"], targets)
+    tr.rast.log_phase = None
     r = tr.rast
     out.update(kernels=per, work=recs,
                stats=dict(pairs=int(np.mean([w["P"] for w in recs])), entries=int(np.mean([w["E"] for w in recs])),
@@ -740,7 +746,8 @@ def roofline(kernel, recs, cached, achievable, backward, entry_bytes=12):
     stream-copy rate; HBM traffic from the rocprofv3 counters in profiles/
     (with the algorithmic bytes of the very launches they were taken on)
     when they describe the current kernel source."""
-    from paper_2601_17354_amd.profiling import design_bytes, read_summary, read_traffic, sec8d_bytes
+    from paper_2601_17354_amd.profiling import (design_bytes, read_issue_fraction, read_summary, read_traffic,
+                                                sec8d_bytes)
     t_ms = sum(r["ms"][kernel] for r in recs)
     b8 = sum(sec8d_bytes(kernel, cached, r["P"], r["E"], r["pixels"]) for r in recs)
     bd = sum(design_bytes(kernel, cached, r["P"], r["E"], r["pixels"], entry_bytes=entry_bytes) for r in recs)
@@ -755,6 +762,8 @@ def roofline(kernel, recs, cached, achievable, backward, entry_bytes=12):
             traffic_work = dict(algorithmic_bytes=float(kv["algorithmic_bytes_per_launch"].split()[0]),
                                 pairs=float(kv["pairs_per_launch"]), entries=float(kv["entries_per_launch"]),
                                 views=kv.get("work_log", ""))
+    issue = read_issue_fraction(os.path.join(ROOT, "profiles", f"{kernel}_{backward}_300k_1920x1440_counters.txt"),
+                                traffic_sources())
     n = len(recs)
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_launches": traffic_work,
@@ -763,7 +772,10 @@ def roofline(kernel, recs, cached, achievable, backward, entry_bytes=12):
             "views": sorted({r["view"] for r in recs}),
             "achievable": achievable, "frac_of_achievable": achieved / achievable,
             "algorithmic_bytes_design": bd / n, "achieved_design": achieved_d, "trace_entry_bytes": entry_bytes,
-            "frac_design": achieved_d / HBM_PEAK_GBS}
+            "frac_design": achieved_d / HBM_PEAK_GBS,
+            # vector-issue share of the kernel's GPU-active time from its
+            # instruction counters (VALU wave instructions / 614.4e9 per s)
+            "valu_issue_fraction": issue}
 
 
 def atomic_runs(tr, reps=5):
@@ -999,12 +1011,13 @@ def main():
         json.dump(work_log, open(args.work_log, "w"))
     tr = res["trainer"]
     cpu_state = None if args.no_cpu_baseline else (tr, res["last_cam"])
-    fps = render_fps(wl, tr.params, order)
-    log(f"render-only: {fps:.1f} frames/s")
+    fps = None if args.profile else render_fps(wl, tr.params, order)
+    if fps is not None:
+        log(f"render-only: {fps:.1f} frames/s")
     atomic = None if args.no_atomic else atomic_runs(tr)
     if atomic:
         log(f"float-atomic reference: {atomic}")
-    ablation = trace_clear_ablation(tr) if cached else None
+    ablation = trace_clear_ablation(tr) if cached and not args.profile else None
     if ablation:
         log(f"trace clear vs counter reset: {ablation}")
     ab = None

@@ -474,7 +474,12 @@ __global__ __launch_bounds__(256) void k_project_bwd_views(const float* __restri
     for (int k = 0; k < lv.nv; ++k) {
         const size_t v = (size_t)(lv.v0 + k);
         if (radius_all[v * n + i] == 0) continue;
-        project_bwd_view<D>(P, n, i, S3, lv.cam[k], g2d_all + (v * n + i) * PGS_GRAD2D_STRIDE,
+        // the parameter pointer made opaque per view: the parameters are
+        // re-read (from cache) by every view instead of being held in
+        // registers across the loop
+        const float* Pv = P;
+        asm volatile("" : "+s"(Pv));
+        project_bwd_view<D>(Pv, n, i, S3, lv.cam[k], g2d_all + (v * n + i) * PGS_GRAD2D_STRIDE,
                             [&](int r, double g) { acc[r] = (float)((double)acc[r] + g); });
     }
 #pragma unroll

@@ -3,10 +3,12 @@ summaries of rocprofv3 CSV output kept in profiles/.
 
     python -m paper_2601_17354_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
     python -m paper_2601_17354_amd.profiling pmc <fetch_dir> <write_dir> <kernel substring>
-           <copy_bytes> <source file[,file...]> <out.txt> "<command>" [<fetch_log.json>,<write_log.json> <kind>]
+           <copy_bytes> <source file[,file...]> <out.txt> "<command>"
+           [<fetch_log.json>,<write_log.json> <kind> [<phase>]]
     python -m paper_2601_17354_amd.profiling trace <kernel_trace.csv> <kernel substring> <work_log.json> <kind>
-           <out.txt> "<command>"
+           <out.txt> "<command>" [<phase>]
     python -m paper_2601_17354_amd.profiling counters <run_dir> <kernel substring> <out.txt> "<command>"
+           [<work_log.json> <kind> [<phase> [<source file[,file...]>]]]
 
 The PMC summary scales each kernel's FETCH_SIZE / WRITE_SIZE (KiB per
 dispatch) by the ratio known-bytes / counter-reading of the plain copy kernel
@@ -40,7 +42,8 @@ import sys
 # Design model (this implementation's layout): a splat record gathers 48 B
 # and its sorted id 4 B; the trace keeps per (tile, splat) one 8-byte ballot
 # mask per wave of 64 pixels (4 waves for 16x16 tiles: 32 B per pair,
-# written forward and read backward) and 16 B per entry; forward pixels
+# written forward and read backward) and 12 B per entry (C_in; 16 B with
+# alpha in the paper's layout); forward pixels
 # write 24 B with the trace (count too), backward pixels read 12 B
 # (dL/dimage; 20 B for recompute, which also reads T_final and n_contrib).
 def sec8d_bytes(kernel: str, cached: bool, P: int, E: int, pixels: int) -> int:
@@ -125,7 +128,8 @@ def _dispatch_rows(run_dir: str, counter: str, kernel: str):
 
 def _logged(work_log: str, kind: str, cached: bool, n_dispatch: int):
     """The logged launches of one kind, in launch order; the log must hold
-    exactly the profiled launches."""
+    exactly the profiled launches.  Entries carry P, E, pixels, ok (the
+    buffers held the pass), tag (camera) and phase (part of the run)."""
     log = [w for w in json.load(open(work_log)) if w["kernel"] == kind and w["cached"] == cached]
     if len(log) != n_dispatch:
         raise SystemExit(f"work log has {len(log)} {kind} launches, the counters {n_dispatch}")
@@ -143,12 +147,17 @@ def _work_means(log):
     return dict(P=mean("P"), E=mean("E"), pixels=mean("pixels"), sec8d=sec, design=des, views=tags)
 
 
+def _keep(w, phase):
+    return w.get("ok", True) and (phase is None or w.get("phase") == phase)
+
+
 def summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes, source, out_txt, command, work_log=None,
-                  kind=None):
+                  kind=None, phase=None):
     """FETCH_SIZE / WRITE_SIZE of one kernel scaled by the copy kernel's
     readings; with a work log, the means are over the launches whose buffers
     held the pass (launches that overflowed while the buffers were being
-    sized are dropped from counters and bytes alike)."""
+    sized are dropped from counters and bytes alike) and, if given, of one
+    phase of the run."""
     fr, name = _dispatch_rows(fetch_dir, "FETCH_SIZE", kernel)
     wr, _ = _dispatch_rows(write_dir, "WRITE_SIZE", kernel)
     _, fc, _ = _pick(_counter(fetch_dir, "FETCH_SIZE"), "k_copy16")
@@ -162,8 +171,8 @@ def summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes, source, out_txt, com
         cached = "true" in name or "cached" in name
         lf = _logged(logs[0], kind, cached, len(fr))
         lw = _logged(logs[-1], kind, cached, len(wr))
-        keep_f = [w.get("ok", True) for w in lf]
-        keep_w = [w.get("ok", True) for w in lw]
+        keep_f = [_keep(w, phase) for w in lf]
+        keep_w = [_keep(w, phase) for w in lw]
         work = _work_means([w for w, k in zip(lf, keep_f) if k])
     fk = [v for (_, v), k in zip(fr, keep_f) if k]
     wk = [v for (_, v), k in zip(wr, keep_w) if k]
@@ -188,7 +197,8 @@ def summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes, source, out_txt, com
     ]
     if work:
         lines += [
-            f"work_log: {kind} launches {sum(keep_f)}, views {work['views']}",
+            f"work_log: {kind} launches {sum(keep_f)}{'' if phase is None else ' of phase ' + phase}, "
+            f"views {work['views']}",
             f"pairs_per_launch: {work['P']:.0f}",
             f"entries_per_launch: {work['E']:.0f}",
             f"pixels_per_launch: {work['pixels']:.0f}",
@@ -199,7 +209,7 @@ def summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes, source, out_txt, com
     open(out_txt, "w").write("\n".join(lines) + "\n")
 
 
-def summarize_trace(trace_csv, kernel, work_log, kind, out_txt, command):
+def summarize_trace(trace_csv, kernel, work_log, kind, out_txt, command, phase=None):
     """Average duration of one kernel's dispatches from a kernel trace, over
     the launches that held the pass, with their work and the bandwidth the
     scope-table bytes imply at the profiler's own timing."""
@@ -214,13 +224,14 @@ def summarize_trace(trace_csv, kernel, work_log, kind, out_txt, command):
     rows.sort()
     cached = "true" in name or "cached" in name
     log = _logged(work_log, kind, cached, len(rows))
-    kept = [(d, w) for (_, d), w in zip(rows, log) if w.get("ok", True)]
+    kept = [(d, w) for (_, d), w in zip(rows, log) if _keep(w, phase)]
     avg = sum(d for d, _ in kept) / len(kept)
     work = _work_means([w for _, w in kept])
     lines = [
         f"command: {command}",
         f"kernel: {_short(name)}",
-        f"dispatches: {len(rows)}, used {len(kept)} (launches that held the pass), views {work['views']}",
+        f"dispatches: {len(rows)}, used {len(kept)} (launches that held the pass"
+        f"{'' if phase is None else ', phase ' + phase}), views {work['views']}",
         f"avg_duration_us: {avg * 1e6:.2f}",
         f"pairs_per_launch: {work['P']:.0f}",
         f"entries_per_launch: {work['E']:.0f}",
@@ -231,22 +242,54 @@ def summarize_trace(trace_csv, kernel, work_log, kind, out_txt, command):
     open(out_txt, "w").write("\n".join(lines) + "\n")
 
 
-def summarize_counters(run_dir, kernel, out_txt, command):
-    """Mean per dispatch of every counter collected for one kernel."""
+# Vector issue of the chip: a SIMD issues one wave64 VALU instruction every
+# 4 cycles (16 lanes per cycle without packed FP32), 4 SIMDs per CU, 256 CUs
+# at 2.4 GHz: 614.4e9 wave instructions/s (78.6 TFLOP/s of FP32 FMA).
+VALU_WAVE_INSTR_PER_S = 256 * 2.4e9
+XCDS = 8  # GRBM_GUI_ACTIVE is summed over the eight XCDs
+
+
+def summarize_counters(run_dir, kernel, out_txt, command, work_log=None, kind=None, phase=None, source=None):
+    """Mean per dispatch of every counter collected for one kernel, with the
+    vector-issue time its VALU instruction count implies, the GPU-active time
+    and the LDS bank-conflict rate.  With the run's work log (and a phase),
+    only the launches that held the pass (of that phase) are averaged."""
     files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
-    acc, name = {}, None
+    per, name = {}, None
     for fpath in files:
         for r in csv.DictReader(open(fpath)):
             if kernel not in r["Kernel_Name"]:
                 continue
             name = r["Kernel_Name"]
-            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    if not acc:
+            per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    if not per:
         raise SystemExit(f"no counters for {kernel!r}")
-    lines = [f"command: {command}", f"kernel: {_short(name)}"]
+    ids = sorted(per)
+    note = f"dispatches {len(ids)}"
+    if work_log:
+        log = _logged(work_log, kind, "true" in name or "cached" in name, len(ids))
+        ids = [d for d, w in zip(ids, log) if _keep(w, phase)]
+        note += f", used {len(ids)}" + ("" if phase is None else f" of phase {phase}")
+    acc = {}
+    for d in ids:
+        for c, v in per[d].items():
+            acc.setdefault(c, []).append(v)
+    lines = [f"command: {command}", f"kernel: {_short(name)}", f"averaged over: {note}"]
+    if source:
+        lines.append(f"source: {_names(source)} sha256[:16]={source_sha(source)}")
+    mean = {c: sum(v) / len(v) for c, v in acc.items()}
     for c in sorted(acc):
-        v = acc[c]
-        lines.append(f"{c}_per_dispatch: {sum(v) / len(v):.1f}  (dispatches {len(v)})")
+        lines.append(f"{c}_per_dispatch: {mean[c]:.1f}")
+    if "SQ_INSTS_VALU" in mean:
+        issue = mean["SQ_INSTS_VALU"] / VALU_WAVE_INSTR_PER_S
+        lines.append(f"valu_issue_time_us: {issue * 1e6:.1f}  (VALU wave instructions / 614.4e9 per s)")
+        if "GRBM_GUI_ACTIVE" in mean:
+            active = mean["GRBM_GUI_ACTIVE"] / XCDS / 2.4e9
+            lines.append(f"gpu_active_us: {active * 1e6:.1f}  (GRBM_GUI_ACTIVE / 8 XCDs / 2.4 GHz)")
+            lines.append(f"valu_issue_fraction: {issue / active:.3f}")
+    if mean.get("SQ_LDS_IDX_ACTIVE"):
+        lines.append(f"lds_bank_conflict_rate: {mean.get('SQ_LDS_BANK_CONFLICT', 0.0) / mean['SQ_LDS_IDX_ACTIVE']:.4f}"
+                     "  (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE)")
     open(out_txt, "w").write("\n".join(lines) + "\n")
 
 
@@ -257,6 +300,20 @@ def read_summary(summary_txt: str) -> dict:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     return kv
+
+
+def read_issue_fraction(summary_txt: str, source: str):
+    """valu_issue_fraction from a counters summary, or None if the summary is
+    missing or the kernel source changed since the counters were taken."""
+    if not os.path.exists(summary_txt):
+        return None
+    kv = read_summary(summary_txt)
+    if f"sha256[:16]={source_sha(source)}" not in kv.get("source", ""):
+        return None
+    try:
+        return float(kv["valu_issue_fraction"].split()[0])
+    except (KeyError, ValueError):
+        return None
 
 
 def read_traffic(summary_txt: str, source: str):
@@ -282,10 +339,10 @@ if __name__ == "__main__":
         summarize_stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "pmc":
         summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7],
-                      sys.argv[8], *(sys.argv[9:11]))
+                      sys.argv[8], *(sys.argv[9:12]))
     elif sys.argv[1] == "counters":
-        summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        summarize_counters(*sys.argv[2:10])
     elif sys.argv[1] == "trace":
-        summarize_trace(*sys.argv[2:8])
+        summarize_trace(*sys.argv[2:9])
     else:
         raise SystemExit(__doc__)

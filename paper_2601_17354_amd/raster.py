@@ -92,6 +92,7 @@ class Rasterizer:
         # pixels (reading them synchronises, so it is off by default).
         self.work_log = None
         self.log_tag = None       # recorded with each entry (e.g. the camera index)
+        self.log_phase = None     # and this label (e.g. the part of a measurement)
 
     # -- buffers ---------------------------------------------------------
     def _alloc_pairs(self, capacity: int, entries: int | None = None):
@@ -145,7 +146,7 @@ class Rasterizer:
     def log_work(self, kernel: str):
         if self.work_log is not None:
             w = self.work()
-            w.update(kernel=kernel, cached=self.cached, tag=self.log_tag)
+            w.update(kernel=kernel, cached=self.cached, tag=self.log_tag, phase=self.log_phase)
             self.work_log.append(w)
 
     @property
