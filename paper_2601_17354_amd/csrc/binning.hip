@@ -135,36 +135,59 @@ __device__ __forceinline__ void view_tiles(const EmitViews& ev, int v, int& TX, 
         }
 }
 
-// Depth keys of every item (float32 depth bits; culled items sort last),
-// values = item index, and the item count for the depth sort.
-__global__ __launch_bounds__(256) void k_depth_keys(uint32_t items, int n, const float* __restrict__ proj_all,
-                                                    const uint32_t* __restrict__ touched_all,
-                                                    uint64_t* __restrict__ dkeys, uint32_t* __restrict__ dvals,
-                                                    uint32_t* __restrict__ count) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *count = items;
-    if (i >= items) return;
-    const uint32_t bits = __float_as_uint(proj_all[(size_t)i * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
-    dkeys[i] = touched_all[i] ? (uint64_t)bits : 0xffffffffull;
-    dvals[i] = i;
+__global__ void k_clear_u32(uint32_t* __restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// tiles_touched in depth order (scanned in place afterwards).
-__global__ __launch_bounds__(256) void k_gather_touched(uint32_t items, const uint32_t* __restrict__ dvals,
-                                                        const uint32_t* __restrict__ touched_all,
-                                                        uint32_t* __restrict__ cnt) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < items) cnt[i] = touched_all[dvals[i]];
+// Depth keys of every item (float32 depth bits; culled items sort last),
+// values = item index, the item count for the depth sort, and the first
+// radix pass's digit histogram: workgroup b takes the same 256 R items as
+// the sort's workgroup b, so it writes its column of the digit-major
+// histogram itself.  Also clears the tile ranges and the pair count.
+template <int R>
+__global__ __launch_bounds__(kSortThreads) void k_depth_keys(uint32_t items, int n,
+                                                             const float* __restrict__ proj_all,
+                                                             const uint32_t* __restrict__ touched_all,
+                                                             uint64_t* __restrict__ dkeys,
+                                                             uint32_t* __restrict__ dvals,
+                                                             uint32_t* __restrict__ count, uint32_t nb,
+                                                             uint32_t* __restrict__ hist,
+                                                             uint32_t* __restrict__ ranges, uint32_t n_ranges,
+                                                             uint32_t* __restrict__ num_pairs) {
+    __shared__ uint32_t h[kRadix];
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && t == 0) {
+        *count = items;
+        *num_pairs = 0u;
+    }
+    for (uint32_t i = blockIdx.x * kSortThreads + t; i < n_ranges; i += gridDim.x * kSortThreads) ranges[i] = 0u;
+    h[t] = 0u;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortThreads * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = base + r * kSortThreads + t;
+        if (i < items) {
+            const uint32_t bits = __float_as_uint(proj_all[(size_t)i * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
+            const uint32_t key = touched_all[i] ? bits : 0xffffffffu;
+            dkeys[i] = (uint64_t)key;
+            dvals[i] = i;
+            atomicAdd(&h[key & 0xffu], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(size_t)t * nb + blockIdx.x] = h[t];
 }
 
 // Pairs of the items in depth order.  Workgroup b fills pairs
-// [1024 b, 1024 b + 1024): one binary search over the scanned counts finds
-// the item of its first pair; every item of the range has at least one pair
-// (empty items share their successor's offset), so the range spans at most
-// 1024 items, whose offsets go to LDS; each thread then finds its pairs'
-// items there.  The work per workgroup is even however unevenly the
-// rectangles are sized.
-constexpr int kEmitPairs = 1024;
+// [256 R b, 256 R (b + 1)), the range of the pair sort's workgroup b: one
+// binary search over the scanned counts finds the item of its first pair;
+// every item of the range has at least one pair (empty items share their
+// successor's offset), so the range spans at most 256 R items, whose offsets
+// go to LDS; each thread then finds its pairs' items there.  The work per
+// workgroup is even however unevenly the rectangles are sized.  Each
+// workgroup also writes its column of the pair sort's first digit-major
+// histogram (the tile's low 8 bits), zeros past the pair count.
 
 __device__ __forceinline__ uint32_t last_le(const uint32_t* off, uint32_t n, uint32_t p) {
     uint32_t lo = 0, hi = n - 1;  // last j with off[j] <= p (off[0] <= p)
@@ -176,43 +199,54 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* off, uint32_t n, uin
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_emit_sorted(uint32_t items, int n, EmitViews ev,
-                                                     const float* __restrict__ proj_all,
-                                                     const uint32_t* __restrict__ rect_all,
-                                                     const uint32_t* __restrict__ dvals,
-                                                     const uint32_t* __restrict__ off,
-                                                     const uint32_t* __restrict__ num_pairs, uint32_t capacity,
-                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ values,
-                                                     uint32_t* __restrict__ flags) {
-    __shared__ uint32_t s_off[kEmitPairs + 1];
+template <int R>
+__global__ __launch_bounds__(kSortThreads) void k_emit_sorted(uint32_t items, int n, EmitViews ev,
+                                                              const float* __restrict__ proj_all,
+                                                              const uint32_t* __restrict__ rect_all,
+                                                              const uint32_t* __restrict__ dvals,
+                                                              const uint32_t* __restrict__ off,
+                                                              const uint32_t* __restrict__ num_pairs,
+                                                              uint32_t capacity, uint64_t* __restrict__ keys,
+                                                              uint32_t* __restrict__ values,
+                                                              uint32_t* __restrict__ flags, uint32_t nb,
+                                                              uint32_t* __restrict__ hist) {
+    constexpr uint32_t kPairs = kSortThreads * R;
+    __shared__ uint32_t s_off[kPairs + 1];
     __shared__ uint32_t s_first;
+    __shared__ uint32_t h[kRadix];
+    const int t = threadIdx.x;
     const uint32_t total = *num_pairs;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && total > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
+    if (blockIdx.x == 0 && t == 0 && total > capacity) atomicOr(flags, PGS_FLAG_PAIR_OVERFLOW);
     const uint32_t count = min(total, capacity);
-    const uint32_t p0 = blockIdx.x * (uint32_t)kEmitPairs;
-    if (p0 >= count) return;  // uniform for the block
-    const uint32_t p1 = min(p0 + (uint32_t)kEmitPairs, count);
-    if (threadIdx.x == 0) s_first = last_le(off, items, p0);
-    __syncthreads();
-    const uint32_t i0 = s_first;
-    const uint32_t span = min((uint32_t)kEmitPairs + 1, items - i0);
-    for (uint32_t q = threadIdx.x; q < span; q += blockDim.x) s_off[q] = off[i0 + q];
-    __syncthreads();
-    for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const uint32_t j = last_le(s_off, span, p);
-        const uint32_t item = dvals[i0 + j], local = p - s_off[j];
-        const uint32_t v = item / (uint32_t)n, g = item - v * (uint32_t)n;
-        int TX, toff;
-        view_tiles(ev, (int)v, TX, toff);
-        const uint32_t r0 = rect_all[(size_t)v * 2 * n + g], r1 = rect_all[(size_t)v * 2 * n + n + g];
-        const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff;
-        const uint32_t w = x1 - x0 + 1;
-        const uint32_t ty = y0 + local / w, tx = x0 + local % w;
-        const uint64_t tile = (uint64_t)((uint32_t)toff + ty * (uint32_t)TX + tx);
-        const uint32_t dbits = __float_as_uint(proj_all[(size_t)item * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
-        keys[p] = (tile << 32) | (uint64_t)dbits;
-        values[p] = g;
+    const uint32_t p0 = blockIdx.x * kPairs;
+    h[t] = 0u;
+    if (p0 < count) {  // uniform for the block
+        const uint32_t p1 = min(p0 + kPairs, count);
+        if (t == 0) s_first = last_le(off, items, p0);
+        __syncthreads();
+        const uint32_t i0 = s_first;
+        const uint32_t span = min(kPairs + 1, items - i0);
+        for (uint32_t q = t; q < span; q += kSortThreads) s_off[q] = off[i0 + q];
+        __syncthreads();
+        for (uint32_t p = p0 + t; p < p1; p += kSortThreads) {
+            const uint32_t j = last_le(s_off, span, p);
+            const uint32_t item = dvals[i0 + j], local = p - s_off[j];
+            const uint32_t v = item / (uint32_t)n, g = item - v * (uint32_t)n;
+            int TX, toff;
+            view_tiles(ev, (int)v, TX, toff);
+            const uint32_t r0 = rect_all[(size_t)v * 2 * n + g], r1 = rect_all[(size_t)v * 2 * n + n + g];
+            const uint32_t x0 = r0 & 0xffff, y0 = r0 >> 16, x1 = r1 & 0xffff;
+            const uint32_t w = x1 - x0 + 1;
+            const uint32_t ty = y0 + local / w, tx = x0 + local % w;
+            const uint64_t tile = (uint64_t)((uint32_t)toff + ty * (uint32_t)TX + tx);
+            const uint32_t dbits = __float_as_uint(proj_all[(size_t)item * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
+            keys[p] = (tile << 32) | (uint64_t)dbits;
+            values[p] = g;
+            atomicAdd(&h[(uint32_t)tile & 0xffu], 1u);
+        }
     }
+    __syncthreads();
+    if (blockIdx.x < nb) hist[(size_t)t * nb + blockIdx.x] = h[t];
 }
 
 __device__ __forceinline__ uint32_t clamp_count(const uint32_t* num, uint32_t capacity) {
@@ -256,12 +290,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
 // of this round) + (same digit in lower lanes of its wave), the last found
 // by matching the 8 digit bits with wave ballots.  The keys go to LDS in
 // that order and leave as one contiguous run per digit, so the global
-// writes coalesce.
+// writes coalesce.  With gdst, the pass also writes gdst[pos] = gsrc[value]
+// (a gather in the output order).
 template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ num,
-    uint32_t capacity, int shift, uint32_t nb, const uint32_t* __restrict__ offs) {
+    uint32_t capacity, int shift, uint32_t nb, const uint32_t* __restrict__ offs,
+    const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gdst) {
     constexpr int NW = kSortThreads / 64;
     __shared__ uint64_t s_key[kSortThreads * R];
     __shared__ uint32_t s_val[kSortThreads * R];
@@ -330,6 +366,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t pos = s_gbase[d] + (i - s_lbase[d]);
         kout[pos] = key;
         vout[pos] = s_val[i];
+        if (gdst) gdst[pos] = gsrc[s_val[i]];
     }
 }
 
@@ -341,10 +378,6 @@ __global__ void k_copy_pairs(const uint64_t* __restrict__ ks, const uint32_t* __
         kd[i] = ks[i];
         vd[i] = vs[i];
     }
-}
-
-__global__ void k_clear_u32(uint32_t* __restrict__ p, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 __global__ void k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ num,
@@ -422,27 +455,37 @@ SortWs sort_layout(void* base, uint32_t capacity) {
     return w;
 }
 
-// Sorts key bits [start_bit, start_bit + key_bits) (stable).
+// Sorts key bits [start_bit, start_bit + key_bits) (stable).  first_hist:
+// the caller already wrote the first pass's digit histogram into w.hist.
+// With gdst, the last pass also writes gdst[i] = gsrc[value at i].
 pgs_status radix_sort(uint64_t* keys, uint32_t* vals, const uint32_t* num, uint32_t capacity,
-                      int key_bits, const SortWs& w, hipStream_t s, int start_bit = 0) {
+                      int key_bits, const SortWs& w, hipStream_t s, int start_bit = 0, bool first_hist = false,
+                      const uint32_t* gsrc = nullptr, uint32_t* gdst = nullptr) {
     if (capacity == 0) return PGS_OK;
     const int passes = (key_bits + 7) / 8;
     uint64_t* kin = keys; uint32_t* vin = vals;
     uint64_t* kout = w.keys_alt; uint32_t* vout = w.vals_alt;
     for (int p = 0; p < passes; ++p) {
         const int shift = start_bit + 8 * p;
-        if (w.rounds == kSortRoundsSmall)
-            k_radix_hist<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
-        else
-            k_radix_hist<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb, w.hist);
+        const bool last = p + 1 == passes;
+        const uint32_t* gs = last ? gsrc : nullptr;
+        uint32_t* gd = last ? gdst : nullptr;
+        if (p > 0 || !first_hist) {
+            if (w.rounds == kSortRoundsSmall)
+                k_radix_hist<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb,
+                                                                             w.hist);
+            else
+                k_radix_hist<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb,
+                                                                             w.hist);
+        }
         pgs_status st = scan_u32(w.hist, w.hist, w.nb * kRadix, nullptr, w.partial, s);
         if (st != PGS_OK) return st;
         if (w.rounds == kSortRoundsSmall)
             k_radix_scatter<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
-                                                                            shift, w.nb, w.hist);
+                                                                            shift, w.nb, w.hist, gs, gd);
         else
             k_radix_scatter<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
-                                                                            shift, w.nb, w.hist);
+                                                                            shift, w.nb, w.hist, gs, gd);
         PGS_CHECK_LAUNCH("radix pass");
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
@@ -579,24 +622,43 @@ pgs_status bin_sort_items(uint32_t items, int n, const EmitViews& ev, int n_tile
                           const uint32_t* rect_all, const uint32_t* touched_all, uint32_t capacity,
                           uint64_t* keys, uint32_t* values, uint32_t* ranges, uint32_t* num_pairs,
                           uint32_t* flags, const BinWs& w, hipStream_t s, const char* who) {
-    k_clear_u32<<<256, 256, 0, s>>>(ranges, 2u * (uint32_t)n_tiles);
-    k_clear_u32<<<1, 64, 0, s>>>(num_pairs, 1u);
+    if (items == 0) {
+        k_clear_u32<<<256, 256, 0, s>>>(ranges, 2u * (uint32_t)n_tiles);
+        k_clear_u32<<<1, 64, 0, s>>>(num_pairs, 1u);
+        PGS_CHECK_LAUNCH(who);
+        return PGS_OK;
+    }
+    // depth keys with the first depth pass's histogram (and the clears of
+    // ranges and pair count); the depth sort's last pass gathers
+    // tiles_touched into depth order; the emit writes the pair sort's first
+    // histogram
+    const SortWs& iw = w.items_ws;
+    if (iw.rounds == kSortRoundsSmall)
+        k_depth_keys<kSortRoundsSmall><<<iw.nb, kSortThreads, 0, s>>>(items, n, proj_all, touched_all, w.dkeys,
+                                                                      w.dvals, w.count, iw.nb, iw.hist, ranges,
+                                                                      2u * (uint32_t)n_tiles, num_pairs);
+    else
+        k_depth_keys<kSortRoundsLarge><<<iw.nb, kSortThreads, 0, s>>>(items, n, proj_all, touched_all, w.dkeys,
+                                                                      w.dvals, w.count, iw.nb, iw.hist, ranges,
+                                                                      2u * (uint32_t)n_tiles, num_pairs);
     PGS_CHECK_LAUNCH(who);
-    if (items == 0) return PGS_OK;
-    const uint32_t g = div_up(items, 256);
-    k_depth_keys<<<g, 256, 0, s>>>(items, n, proj_all, touched_all, w.dkeys, w.dvals, w.count);
-    PGS_CHECK_LAUNCH(who);
-    pgs_status st = radix_sort(w.dkeys, w.dvals, w.count, items, 32, w.items_ws, s);
+    pgs_status st = radix_sort(w.dkeys, w.dvals, w.count, items, 32, iw, s, 0, true, touched_all, w.off);
     if (st != PGS_OK) return st;
-    k_gather_touched<<<g, 256, 0, s>>>(items, w.dvals, touched_all, w.off);
     st = scan_u32(w.off, w.off, items, num_pairs, w.partial, s);
     if (st != PGS_OK) return st;
-    const uint32_t ge = div_up(capacity, kEmitPairs);
-    k_emit_sorted<<<ge > 0 ? ge : 1, 256, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals, w.off, num_pairs,
-                                                  capacity, keys, values, flags);
+    const SortWs& pw = w.pairs_ws;
+    const uint32_t ge = pw.nb > 0 ? pw.nb : 1u;
+    if (pw.rounds == kSortRoundsSmall)
+        k_emit_sorted<kSortRoundsSmall><<<ge, kSortThreads, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals,
+                                                                    w.off, num_pairs, capacity, keys, values,
+                                                                    flags, pw.nb, pw.hist);
+    else
+        k_emit_sorted<kSortRoundsLarge><<<ge, kSortThreads, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals,
+                                                                    w.off, num_pairs, capacity, keys, values,
+                                                                    flags, pw.nb, pw.hist);
     PGS_CHECK_LAUNCH(who);
     if (capacity == 0) return PGS_OK;
-    st = radix_sort(keys, values, num_pairs, capacity, bits_for((uint32_t)n_tiles), w.pairs_ws, s, 32);
+    st = radix_sort(keys, values, num_pairs, capacity, bits_for((uint32_t)n_tiles), pw, s, 32, true);
     if (st != PGS_OK) return st;
     const uint32_t grid = div_up(capacity, 256) < 4096 ? div_up(capacity, 256) : 4096;
     k_ranges<<<grid, 256, 0, s>>>(keys, num_pairs, capacity, (uint32_t)n_tiles, ranges);
