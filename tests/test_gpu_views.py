@@ -356,3 +356,64 @@ def test_tuner_times_candidates_and_caches_the_choice(tmp_path, monkeypatch):
     assert first["ms"] == min(r["ms"] for r in first["table"])
     second = tune(params, 0, cams, targets, steps=2, warmup=1, cands=cands)
     assert second["cached"] and second["tile"] == first["tile"] and second["batch"] == first["batch"]
+
+
+def test_bin_sort_views_past_one_million_items_matches_per_view_calls():
+    # Past 2^20 items the depth sort takes its 2048-key workgroups, with the
+    # first pass's histogram written by the depth-key kernel and
+    # tiles_touched gathered by the last pass: four views of 300k Gaussians
+    # bin and sort to the concatenation of the four single-view lists, whose
+    # bit-exactness against the oracle the full-size tests establish.
+    from paper_2601_17354_amd import binding as B
+    scene = synth.spheres_planes_scene(0)
+    P = synth.surface_gaussians(scene, 300_000, seed=1001, sh_degree=0)
+    sizes = [(1920, 1440), (1280, 960), (960, 720), (640, 480)]
+    ring = synth.ring_cameras(4, 1920, 1440)
+    cams = []
+    for (W, H), c0 in zip(sizes, ring):
+        c = dict(c0)
+        c.update(width=W, height=H, fx=c0["fx"] * W / 1920.0, fy=c0["fy"] * W / 1920.0, cx=W / 2.0, cy=H / 2.0)
+        cams.append(c)
+    n, V = P.shape[1], len(cams)
+    assert n * V > (1 << 20)
+    say(f"[views] bin_sort_views: n={n} views={V} items={n * V}")
+    views = B.ViewBatch(cams, (16, 16))
+    params = torch.as_tensor(P, device=DEV)
+    proj = torch.zeros((V, n, 16), device=DEV)
+    radius = torch.zeros((V, n), dtype=torch.int32, device=DEV)
+    rect = torch.zeros((V, 2, n), dtype=torch.int32, device=DEV)
+    touched = torch.zeros((V, n), dtype=torch.int32, device=DEV)
+    B.pgs_project_views(views, params, n, 0, proj, radius, rect, touched)
+    per_view = [int(x) for x in touched.sum(dim=1).cpu()]
+    cap = sum(per_view) + 1024
+    nt = views.n_tiles
+
+    def buffers(items):
+        return (torch.empty(cap, dtype=torch.int64, device=DEV), torch.empty(cap, dtype=torch.int32, device=DEV),
+                torch.empty((2, nt), dtype=torch.int32, device=DEV), torch.zeros(1, dtype=torch.int32, device=DEV),
+                torch.zeros(1, dtype=torch.int32, device=DEV),
+                torch.empty(B.pgs_bin_sort_workspace(items, cap), dtype=torch.uint8, device=DEV))
+
+    keys, values, ranges, num, flags, ws = buffers(n * V)
+    B.pgs_bin_sort_views(views, n, proj, rect, touched, cap, keys, values, ranges, num, flags, ws)
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0 and int(num.item()) == sum(per_view)
+    got_k, got_v, got_r = keys.cpu().numpy(), values.cpu().numpy(), ranges.cpu().numpy()
+    base = 0
+    for v in range(V):
+        k1, v1, r1, num1, f1, ws1 = buffers(n)
+        tx = (cams[v]["width"] + 15) // 16
+        B.pgs_bin_sort(n, proj[v], rect[v], touched[v], tx, nt, views.tile_offsets[v], cap, k1, v1, r1, num1, f1,
+                       ws1)
+        torch.cuda.synchronize()
+        m = int(num1.item())
+        assert int(f1.item()) == 0 and m == per_view[v]
+        np.testing.assert_array_equal(got_k[base:base + m], k1.cpu().numpy()[:m])
+        np.testing.assert_array_equal(got_v[base:base + m], v1.cpu().numpy()[:m])
+        t0, t1 = views.tile_offsets[v], views.tile_offsets[v + 1]
+        r1n = r1.cpu().numpy()
+        nonempty = r1n[1, t0:t1] > r1n[0, t0:t1]
+        np.testing.assert_array_equal(got_r[0, t0:t1][nonempty], r1n[0, t0:t1][nonempty] + base)
+        np.testing.assert_array_equal(got_r[1, t0:t1][nonempty], r1n[1, t0:t1][nonempty] + base)
+        np.testing.assert_array_equal(got_r[1, t0:t1][~nonempty] - got_r[0, t0:t1][~nonempty], 0)
+        base += m
