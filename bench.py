@@ -585,6 +585,10 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
                      extent=4.5)
     st.prepare()
     st._alloc_pairs(int(st.capacity * 1.25), int(st.entry_capacity * 1.25))
+    # per-stage times from eager steps before any graph is captured (after a
+    # capture the stage events of eager steps have read up to twice the
+    # kernel-trace durations of the persistent launches)
+    kern, roofs = batched_kernel_times(st)
     st.capture()
     # eager steps and graph replays from the same optimiser state, so that
     # both time the same work (training changes the pair and entry counts)
@@ -594,7 +598,6 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
     ms_eager = time_steps(st.step, steps, warmup)
     assert st.read_flags() == 0, "batched step overflowed during timing"
     stats = st.stats()
-    kern, roofs = batched_kernel_times(st)
     del st
     torch.cuda.empty_cache()
     if not compare:

@@ -59,7 +59,7 @@ __global__ void k_clear_queue(uint32_t* queue) {
 }
 
 template <int TW, int TH, int BG, bool CACHED, int EW = 4>
-__global__ __launch_bounds__(TW* TH) void k_render_fwd_views(
+__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(CACHED ? 5 : 1))) void k_render_fwd_views(
     ViewTable vt, int n_tiles_total, const float* __restrict__ proj_all, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, float* __restrict__ image_all,
     float* __restrict__ t_final_all, uint32_t* __restrict__ n_contrib_all, Trace tr,
