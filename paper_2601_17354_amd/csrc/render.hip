@@ -38,7 +38,7 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(EW == 3 
 }
 
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd_recompute(
+__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(6))) void k_render_bwd_recompute(
     int W, int H, int TX, int tile_offset, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, float bg0, float bg1,
     float bg2, const float* __restrict__ t_final, const uint32_t* __restrict__ n_contrib,
