@@ -781,6 +781,25 @@ def roofline(kernel, recs, cached, achievable, backward, entry_bytes=12):
             "valu_issue_fraction": issue}
 
 
+def bin_sort_roofline(recs, n):
+    """Roofline entry of the binning stage (depth sort, scan, emit, pair sort,
+    ranges and the tile order) over the recorded steps: scope-table bytes
+    (12 B per Gaussian for the scan; per pair 12 B emitted, 6 x 24 B for a
+    46-bit key sort, 8 B for the ranges) and the bytes of this design (depth
+    sort of the Gaussians: 4 passes x 24 B plus 12 B of keys and 8 B of
+    scan per Gaussian; per pair 12 B emitted, 2 x 24 B for the tile-bit
+    sort, 8 B for the ranges) over the stage's event time."""
+    t_ms = sum(r["ms"]["bin_sort"] for r in recs)
+    b8 = sum(12 * n + 164 * r["P"] for r in recs)
+    bd = sum(124 * n + 68 * r["P"] for r in recs)
+    k = len(recs)
+    return {"kernel": "bin_sort", "bound": "hbm", "achieved": b8 / (t_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": b8 / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "avg_ms": t_ms / k,
+            "algorithmic_bytes": b8 / k, "algorithmic_bytes_design": bd / k,
+            "frac_design": bd / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "launches_per_step": 28,
+            "note": "latency-bound: 28 dependent launches, most of them a few microseconds long"}
+
+
 def atomic_runs(tr, reps=5):
     """Float-atomic throughput of the render backward's gradient scatter:
     the backward's own targets (the sorted pair values of the last view, each
@@ -1081,6 +1100,7 @@ def main():
                    "render_bwd, project_bwd, adam"},
         "roofline": roofs[dom],
         "roofline_render_bwd": roofs["render_bwd"],
+        "roofline_bin_sort": bin_sort_roofline(res["work"], st["n"]),
         "achievable_hbm_gbs": achievable,
         "kernels_ms": kern,
         "work": st,
