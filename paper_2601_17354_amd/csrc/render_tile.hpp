@@ -889,7 +889,9 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
                     const uint64_t m = __ballot(ok);
                     if (m == 0) continue;
                     if (ok) {
-                        const float Tk = T / (1.f - alpha);
+                        // T_k = T_{k+1} / (1 - alpha_k), with the hardware reciprocal
+                        // (about one unit of roundoff, the size of the product's own)
+                        const float Tk = T * __builtin_amdgcn_rcpf(1.f - alpha);
                         const float q0 = Tk * G0, q1 = Tk * G1, q2 = Tk * G2;
                         const float dla = q0 * (s.r - a0) + q1 * (s.g - a1) + q2 * (s.b - a2);
                         const bool clamped = s.o * gauss > kAlphaMax;
