@@ -168,8 +168,10 @@ __global__ __launch_bounds__(kSortThreads) void k_depth_keys(uint32_t items, int
     for (int r = 0; r < R; ++r) {
         const uint32_t i = base + r * kSortThreads + t;
         if (i < items) {
-            const uint32_t bits = __float_as_uint(proj_all[(size_t)i * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
-            const uint32_t key = touched_all[i] ? bits : 0xffffffffu;
+            // the record's depth is read only for items with pairs (one
+            // 4-byte read per 64-byte record, so culled items cost a line)
+            uint32_t key = 0xffffffffu;
+            if (touched_all[i]) key = __float_as_uint(proj_all[(size_t)i * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
             dkeys[i] = (uint64_t)key;
             dvals[i] = i;
             atomicAdd(&h[key & 0xffu], 1u);
