@@ -208,6 +208,67 @@ def variants_ab(params, wl, order, views=20, reps=5):
     return out
 
 
+def graph_runs(wl, order, steps, warmup, views=20):
+    """The cached training step recorded as HIP graphs through the library's
+    graph calls (one graph per training view, the camera being a kernel
+    argument; Adam's step counter on the device) and replayed cycling the
+    views, against the same steps enqueued one call at a time, both from the
+    same state."""
+    import torch
+    from paper_2601_17354_amd import binding as B
+    from paper_2601_17354_amd.train import Trainer
+    ids = order[:views]
+    cams, targets = wl["cams"], wl["targets"]
+    tr = Trainer(wl["params0"].clone(), 0, wl["width"], wl["height"], cached=True, lam=0.2, extent=4.5,
+                 device_step_counter=True)
+    for cid in ids:
+        tr.prepare(cams[cid])
+    tr.rast.reserve(2.0)
+    for k in range(warmup):
+        cid = ids[k % len(ids)]
+        tr.step(cams[cid], targets[cid])
+    torch.cuda.synchronize()
+    tr.rast.flags.zero_()
+    state = (tr.params, tr.m, tr.v, tr.adam_state)
+    snap = [t.clone() for t in state]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graphs = []
+    with torch.cuda.stream(side):
+        for cid in ids:
+            B.pgs_graph_begin(side)
+            try:
+                tr.step(cams[cid], targets[cid])
+            finally:
+                graphs.append(B.pgs_graph_end(side))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+
+    def timed(run):
+        for dst, src in zip(state, snap):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(steps):
+            run(k)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms_graph = timed(lambda k: B.pgs_graph_launch(graphs[k % len(graphs)]))
+    ms_eager = timed(lambda k: tr.step(cams[ids[k % len(ids)]], targets[ids[k % len(ids)]]))
+    flags = tr.rast.read_flags()
+    for g in graphs:
+        B.pgs_graph_destroy(g)
+    del tr
+    torch.cuda.empty_cache()
+    if flags:
+        raise RuntimeError(f"buffer overflow during the graph timing (flags={flags})")
+    return {"views": len(ids), "steps": steps, "ms_per_step_graph": ms_graph, "ms_per_step_eager": ms_eager,
+            "state": f"after {warmup} eager steps, both from the same parameters and Adam state"}
+
+
 def trace_clear_ablation(tr, reps=5):
     """The replay-cache ablation: clearing the whole trace (entries and
     masks) before each iteration against the counter reset this design uses
@@ -1043,10 +1104,14 @@ def main():
     if ablation:
         log(f"trace clear vs counter reset: {ablation}")
     ab = None
+    graph = None
     if not args.profile:
         ab = variants_ab(tr.params, wl, order)
         for name in ("cached_12B_entries", "cached_16B_entries", "recompute"):
             log(f"same state, {name}: {ab[name]['sum_of_medians_ms']:.3f} ms, {ab[name]['median_ms']}")
+    if cached and not args.profile:
+        graph = graph_runs(wl, order, args.steps, args.warmup)
+        log(f"step as HIP graphs: {graph['ms_per_step_graph']:.3f} ms, eager {graph['ms_per_step_eager']:.3f} ms")
     if cpu_state is not None:
         # keep what the CPU oracle will run on; free the trainer's buffers
         cpu_state = (SimpleState(tr.params.detach().cpu()), res["last_cam"])
@@ -1112,6 +1177,8 @@ def main():
         out["ablation_trace_clear"] = ablation
     if ab is not None:
         out["backward_variants_same_state"] = ab
+    if graph is not None:
+        out["graph_vs_eager"] = graph
     if other is not None:
         out["other_backward"] = {"backward": "recompute" if cached else "cached",
                                  "ms_per_step": other["ms"], "iters_per_s": 1000.0 / other["ms"],

@@ -53,7 +53,8 @@ class Trainer:
 
     def __init__(self, params: torch.Tensor, sh_degree: int, width: int, height: int,
                  cached: bool = True, lam: float = 0.2, extent: float = 1.0,
-                 tile=(16, 16), ordered: bool = True, trace_words: int | None = None):
+                 tile=(16, 16), ordered: bool = True, trace_words: int | None = None,
+                 device_step_counter: bool = False):
         self.params = params.contiguous()
         self.sh_degree = sh_degree
         self.F, self.n = self.params.shape
@@ -70,6 +71,9 @@ class Trainer:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.loss_ws = torch.empty(B.pgs_loss_workspace(width, height), dtype=torch.uint8, device=dev)
         self.step_count = 0
+        # Adam's step counter on the device (pgs_adam_step_dev), so that a
+        # step recorded as a graph advances it on every replay
+        self.adam_state = torch.zeros(4, dtype=torch.int32, device=dev) if device_step_counter else None
         self.events = None
 
     def prepare(self, cam: dict, bg=(0.0, 0.0, 0.0)):
@@ -113,9 +117,13 @@ class Trainer:
         B.pgs_project_bwd(self.params, n, self.sh_degree, cam, r.radius, r.grad2d, self.grads)
         self._mark("project_bwd")
         if adam:
-            self.step_count += 1
-            B.pgs_adam_step(self.params, self.grads, self.m, self.v, self.F, n, self.lr, self.step_count,
-                            BETA1, BETA2, EPS)
+            if self.adam_state is not None:
+                B.pgs_adam_step_dev(self.params, self.grads, self.m, self.v, self.F, n, self.lr, self.adam_state,
+                                    BETA1, BETA2, EPS)
+            else:
+                self.step_count += 1
+                B.pgs_adam_step(self.params, self.grads, self.m, self.v, self.F, n, self.lr, self.step_count,
+                                BETA1, BETA2, EPS)
             self._mark("adam")
         return self.loss
 
