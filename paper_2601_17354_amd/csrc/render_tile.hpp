@@ -578,22 +578,28 @@ __device__ __forceinline__ void grad2d_from_sums(float hA, float nB, float hC, f
     f[5] = f[5] * inv_o;
 }
 
-// Sums 36 per-lane values over the wave with two swap-and-add stages
-// (v_permlane32_swap: lanes 0-31 of one register meet lanes 32-63 of
-// another; v_permlane16_swap: the same between 16-lane rows) and a DPP
-// scan inside each row.  Afterwards lane 16r + 15 holds in t[j] the total of
-// value 4j + c, c = (0, 2, 1, 3)[r].
+// Sums the nine terms of each of four groups over the wave (v[9q + f] is term
+// f of group q at this lane) with two swap-and-add stages and a DPP scan.
+// v_permlane32_swap meets lanes 0-31 of one register with lanes 32-63 of
+// another: pairing group q with group q + 2 leaves groups 0 and 1 in the lower
+// half and groups 2 and 3 in the upper one.  v_permlane16_swap does the same
+// between neighbouring 16-lane rows: pairing group q with q + 1 leaves row r
+// holding group r.  A shift scan inside each row then gives lane 16r + 15 the
+// total of term f of group r in t[f].
 __device__ __forceinline__ void wave_reduce36(const float* v, float* t) {
     float s[18];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) {
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]),
-                                                        false, false);
-        s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    for (int f = 0; f < 9; ++f) {
+        const auto r02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[f]), __float_as_uint(v[18 + f]),
+                                                          false, false);
+        const auto r13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[9 + f]), __float_as_uint(v[27 + f]),
+                                                          false, false);
+        s[2 * f] = __uint_as_float(r02[0]) + __uint_as_float(r02[1]);
+        s[2 * f + 1] = __uint_as_float(r13[0]) + __uint_as_float(r13[1]);
     }
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * j]), __float_as_uint(s[2 * j + 1]),
+    for (int f = 0; f < 9; ++f) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * f]), __float_as_uint(s[2 * f + 1]),
                                                         false, false);
         float x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
         int xi = __float_as_int(x);
@@ -604,29 +610,36 @@ __device__ __forceinline__ void wave_reduce36(const float* v, float* t) {
         x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x114, 0xf, 0xf, false));
         xi = __float_as_int(x);
         x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x118, 0xf, 0xf, false));
-        t[j] = x;
+        // keeps the last step beside the others for every lane, where the
+        // shifted move folds into the add, instead of letting it sink into
+        // the row leaders' branch as a move, a copy and an add
+        asm volatile("" : : "v"(x));
+        t[f] = x;
     }
 }
 
-// Adds the wave's nine gradients of each of KG = 4 groups (splat slots
-// slot0 + gi[q]; a group with an empty mask adds nothing) into the LDS
-// accumulator: one combined reduction, then the four row leaders add.
+// Adds the wave's nine gradient terms of each of KG = 4 groups (splat slots
+// slot0 + gi[q]; groups are taken in order, so the non-empty ones come first
+// and an empty one, whose mask is 0, adds nothing) into the LDS accumulator:
+// one combined reduction, then row r's leader adds group r's nine terms.
 template <int BG, int KG>
 __device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[BG], int lane, uint32_t slot0,
                                                   const int* gi, const uint64_t* gm) {
     static_assert(KG * 9 == 36, "the combined reduction takes four groups");
     float t[9];
     wave_reduce36(v, t);
-    if ((lane & 15) == 15) {
-        const int r = lane >> 4;
-        const int c = r == 0 ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
+    // row r takes group r's slot, or -1 for an empty group (lane selects
+    // of the uniform values, no branch)
+    int sq[4];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            const int idx = 4 * j + c, q = idx / 9, f = idx - 9 * q;
-            const int slot = (int)slot0 + (q == 0 ? gi[0] : q == 1 ? gi[1] : q == 2 ? gi[2] : gi[3]);
-            const uint64_t m = q == 0 ? gm[0] : q == 1 ? gm[1] : q == 2 ? gm[2] : gm[3];
-            if (m != 0ull) atomicAdd(&acc[f][slot], t[j]);
-        }
+    for (int q = 0; q < 4; ++q) sq[q] = gm[q] != 0ull ? (int)slot0 + gi[q] : -1;
+    const int s01 = (lane & 16) ? sq[1] : sq[0];
+    const int s23 = (lane & 16) ? sq[3] : sq[2];
+    const int slot = (lane & 32) ? s23 : s01;
+    if ((lane & 15) == 15 && slot >= 0) {
+        float* a = &acc[0][slot];
+#pragma unroll
+        for (int f = 0; f < 9; ++f) atomicAdd(a + f * BG, t[f]);
     }
 }
 
