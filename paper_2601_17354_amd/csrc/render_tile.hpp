@@ -115,6 +115,58 @@ __device__ __forceinline__ uint32_t entry_slot(uint64_t m, uint32_t base) {
 // becomes the execution mask directly).
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+// A wave's trace entries are addressed through a buffer resource on the
+// start of its region (kept in scalar registers) with 32-bit byte offsets:
+// a run's start as the scalar offset and the lane's rank in it as the vector
+// one, so an access takes no 64-bit per-lane address arithmetic.  A region
+// stays far below 4 GiB: a pixel composites at most ln(1e-4) / ln(1 - 1/255)
+// < 2400 splats before its transmittance ends it, so a wave's region holds
+// fewer than 64 * 2400 entries.  Word 3 of the resource selects the 32-bit
+// data format (value 4 in bits 15-18), which untyped buffer access on this
+// GPU family expects; the record count is left at its maximum.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t region_rsrc(const void* region) {
+    const uint64_t a = reinterpret_cast<uint64_t>(region);
+    const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), (short)0, -1, 0x00020000);
+}
+
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Entry `rank` (< 64) of the run of EW-word entries that starts `first`
+// entries into the region.
+template <int EW>
+__device__ __forceinline__ float4 load_entry(__amdgpu_buffer_rsrc_t rs, uint32_t first, uint32_t rank) {
+    const uint32_t voff = rank * (4u * EW), soff = first * (4u * EW);
+    if constexpr (EW == 4) {
+        const u32x4 r = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+        return make_float4(__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), __uint_as_float(r.w));
+    } else {
+        const u32x3 r = __builtin_amdgcn_raw_buffer_load_b96(rs, voff, soff, 0);
+        return make_float4(__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), 0.f);
+    }
+}
+
+// Stores take the whole offset in the vector operand and a zero scalar
+// offset: the compiler inserts the wait that a store of more than 8 bytes
+// needs before its data registers are overwritten only for that form, and
+// with a register scalar offset the store was measured to pick up the next
+// value of its data registers.
+template <int EW>
+__device__ __forceinline__ void store_entry(__amdgpu_buffer_rsrc_t rs, uint32_t first, uint32_t rank, float c0,
+                                            float c1, float c2, float alpha) {
+    const uint32_t voff = (first + rank) * (4u * EW);
+    if constexpr (EW == 4) {
+        u32x4 d = {__float_as_uint(c0), __float_as_uint(c1), __float_as_uint(c2), __float_as_uint(alpha)};
+        __builtin_amdgcn_raw_buffer_store_b128(d, rs, voff, 0, 0);
+    } else {
+        u32x3 d = {__float_as_uint(c0), __float_as_uint(c1), __float_as_uint(c2)};
+        __builtin_amdgcn_raw_buffer_store_b96(d, rs, voff, 0, 0);
+        (void)alpha;
+    }
+}
+
 __device__ __forceinline__ uint64_t read_lane64(uint64_t v, int lane) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
@@ -158,20 +210,9 @@ struct Trace {
     int words;                  // EW of the launch: 4 with alpha, 3 without
 };
 
-// A trace entry of EW words: (C_in r, g, b, alpha) as one 16-byte record, or
-// (C_in r, g, b) as one 12-byte record when the backward recomputes alpha
+// A trace entry holds EW words: (C_in r, g, b, alpha) as one 16-byte record,
+// or (C_in r, g, b) as one 12-byte record when the backward recomputes alpha
 // from the staged splat with the forward's arithmetic (same bits).
-struct __attribute__((aligned(4))) Float3 {
-    float x, y, z;
-};
-template <int EW>
-struct EntryRec {
-    using T = float4;
-};
-template <>
-struct EntryRec<3> {
-    using T = Float3;
-};
 
 // One tile of one view.  Pixel arrays (image planes, t_final, n_contrib,
 // count) are the view's own; gt is the tile's global index in the ranges.
@@ -313,7 +354,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     constexpr int NW = NT / 64;
     static_assert((BG & (BG - 1)) == 0 && BG % FWD_UNROLL == 0, "batch: a power of two, whole groups");
     static_assert(NW <= 4, "at most four waves per tile");
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
     const bool inside = px < j.W && py < j.H;
     const uint32_t start = ranges[j.gt], end = ranges[n_tiles_total + j.gt];
@@ -409,7 +450,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
         }
     }
     uint32_t cursor = 0;
-    if (rec) cursor = wave_sum_u32(cnt);
+    if (rec) cursor = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(cnt));  // the same in every lane
     // Entry regions: one bump-counter atomic per tile (a single device-wide
     // address, so per-wave atomics would queue there), split among the
     // waves in order.  A wave whose region does not fit the entry capacity
@@ -478,7 +519,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
     // than one per window.
     constexpr int kWin = BG >= 64 ? BG / 64 : 1;
     const uint64_t* wm = tr.mask + (size_t)wv * tr.pair_cap + start;
-    typename EntryRec<EW>::T* went = reinterpret_cast<typename EntryRec<EW>::T*>(tr.entry) + ebase;
+    const __amdgpu_buffer_rsrc_t went = region_rsrc(tr.entry + ebase * EW);
     for (int64_t lo = top; lo >= 0; lo -= BG) {
         const uint32_t hi = min((uint32_t)lo + BG, smax);
         __syncthreads();
@@ -529,8 +570,7 @@ __device__ __forceinline__ void fwd_tile(const TileJob& j, int n_tiles_total, in
                 for (int q = 0; q < 4; ++q) {
                     if (lane_in(gm[q])) {
                         const float a = al[q];
-                        if constexpr (EW == 4) went[entry_slot(gm[q], gc[q])] = make_float4(a0, a1, a2, a);
-                        else went[entry_slot(gm[q], gc[q])] = Float3{a0, a1, a2};
+                        store_entry<EW>(went, gc[q], lane_rank(gm[q]), a0, a1, a2, a);
                         a0 = a * sq[q].r + (1.f - a) * a0;
                         a1 = a * sq[q].g + (1.f - a) * a1;
                         a2 = a * sq[q].b + (1.f - a) * a2;
@@ -703,13 +743,11 @@ __device__ __forceinline__ void take_groups(uint64_t& any, uint64_t mv, uint32_t
 // entry (the region is not empty when a group exists); alpha is taken as 0
 // for the latter in bwd_groups.
 template <int EW>
-__device__ __forceinline__ void load_groups(const typename EntryRec<EW>::T* went, const TraceGroups& g,
-                                            float4* e) {
+__device__ __forceinline__ void load_groups(__amdgpu_buffer_rsrc_t went, const TraceGroups& g, float4* e) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const typename EntryRec<EW>::T r = went[lane_in(g.gm[q]) ? entry_slot(g.gm[q], g.gc[q]) : 0u];
-        if constexpr (EW == 4) e[q] = r;
-        else e[q] = make_float4(r.x, r.y, r.z, 0.f);
+        // an empty group (unused slot) reads the region's first entry
+        e[q] = load_entry<EW>(went, g.gm[q] != 0ull ? g.gc[q] : 0u, lane_in(g.gm[q]) ? lane_rank(g.gm[q]) : 0u);
     }
 }
 
@@ -755,7 +793,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
                                                 float* __restrict__ grad2d, TileLds<BG>& L) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int px = j.tx * TW + (t % TW), py = j.ty * TH + (t / TW);
     const bool inside = px < j.W && py < j.H;
     const uint32_t start = ranges[j.gt], end = ranges[n_tiles_total + j.gt];
@@ -763,7 +801,7 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const size_t pix = (size_t)py * j.W + px, plane = (size_t)j.W * j.H;
     const size_t ebase = tr.base[(size_t)j.gt * NW + wv];
-    const typename EntryRec<EW>::T* went = reinterpret_cast<const typename EntryRec<EW>::T*>(tr.entry) + ebase;
+    const __amdgpu_buffer_rsrc_t went = region_rsrc(tr.entry + ebase * EW);
 
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;  // dL/dC_out of this pixel's next entry
     if (inside) {
