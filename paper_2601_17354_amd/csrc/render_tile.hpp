@@ -138,7 +138,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // entries into the region.
 template <int EW>
 __device__ __forceinline__ float4 load_entry(__amdgpu_buffer_rsrc_t rs, uint32_t first, uint32_t rank) {
-    const uint32_t voff = rank * (4u * EW), soff = first * (4u * EW);
+    // first is the same in every lane; saying so keeps the offset scalar
+    const uint32_t voff = rank * (4u * EW),
+                   soff = (uint32_t)__builtin_amdgcn_readfirstlane((int)(first * (4u * EW)));
     if constexpr (EW == 4) {
         const u32x4 r = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
         return make_float4(__uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z), __uint_as_float(r.w));
@@ -248,7 +250,7 @@ struct TileLds {
     uint32_t g[BG];
     float io[BG];  // 1 / opacity
     uint8_t reach[BG];  // bit w: the splat can reach a pixel of wave w (recompute backward)
-    float acc[9][BG];
+    float acc[9][BG + 1];  // one word of padding per row: a splat's nine terms fall in nine banks
     uint32_t steps;
 };
 
@@ -618,15 +620,47 @@ __device__ __forceinline__ void grad2d_from_sums(float hA, float nB, float hC, f
     f[5] = f[5] * inv_o;
 }
 
+// x + y taken from the lane that the DPP control CTRL names inside a 16-lane
+// row (every control used here names a lane of the same row).
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float x, float y) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), CTRL, 0xf, 0xf, false));
+}
+
+// One transposing step for two values a and b with the partner lane that CTRL
+// names: lanes with lo set keep the sum of a over the pair of lanes, the
+// others the sum of b.
+template <int CTRL>
+__device__ __forceinline__ float fold_pair(float a, float b, bool lo) {
+    return dpp_add<CTRL>(lo ? a : b, lo ? b : a);
+}
+
+// The term that lane i of a 16-lane row holds after wave_reduce36: 8 in odd
+// lanes; in even lanes of quad k (k = i / 4) term (0, 2, 1, 3)[k] where bit 1
+// of i is clear, else term (4, 6, 5, 7)[k] (the first step leaves the even
+// terms of each pair in lanes 0-7, the second the first pair of each pair of
+// pairs in quads 0 and 2).
+__device__ __forceinline__ int term_of_lane(int i) {
+    if (i & 1) return 8;
+    const int k = i >> 2;
+    const int base = (i & 2) ? 4 : 0;
+    return base + (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 1 : 3);
+}
+
 // Sums the nine terms of each of four groups over the wave (v[9q + f] is term
-// f of group q at this lane) with two swap-and-add stages and a DPP scan.
-// v_permlane32_swap meets lanes 0-31 of one register with lanes 32-63 of
-// another: pairing group q with group q + 2 leaves groups 0 and 1 in the lower
-// half and groups 2 and 3 in the upper one.  v_permlane16_swap does the same
-// between neighbouring 16-lane rows: pairing group q with q + 1 leaves row r
-// holding group r.  A shift scan inside each row then gives lane 16r + 15 the
-// total of term f of group r in t[f].
-__device__ __forceinline__ void wave_reduce36(const float* v, float* t) {
+// f of group q at this lane).  v_permlane32_swap meets lanes 0-31 of one
+// register with lanes 32-63 of another: pairing group q with group q + 2
+// leaves groups 0 and 1 in the lower half and groups 2 and 3 in the upper
+// one.  v_permlane16_swap does the same between neighbouring 16-lane rows:
+// pairing group q with q + 1 leaves row r holding group r, each lane a sum
+// over four lanes.  Inside the row four transposing steps follow (partner
+// lane i ^ 8 by a rotation of 8, the mirror lane inside each half, then
+// i ^ 2 and i ^ 1 inside each quad): each step halves the number of values
+// a lane holds and doubles the lanes each value covers, so the row's nine
+// values take 27 instructions instead of the 36 of a scan of each.
+// Afterwards lane i of row r holds the row total of term term_of_lane(i) of
+// group r.
+__device__ __forceinline__ float wave_reduce36(const float* v, int lane) {
     float s[18];
 #pragma unroll
     for (int f = 0; f < 9; ++f) {
@@ -637,37 +671,41 @@ __device__ __forceinline__ void wave_reduce36(const float* v, float* t) {
         s[2 * f] = __uint_as_float(r02[0]) + __uint_as_float(r02[1]);
         s[2 * f + 1] = __uint_as_float(r13[0]) + __uint_as_float(r13[1]);
     }
+    float x[9];
 #pragma unroll
     for (int f = 0; f < 9; ++f) {
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * f]), __float_as_uint(s[2 * f + 1]),
                                                         false, false);
-        float x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-        int xi = __float_as_int(x);
-        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x111, 0xf, 0xf, false));
-        xi = __float_as_int(x);
-        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x112, 0xf, 0xf, false));
-        xi = __float_as_int(x);
-        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x114, 0xf, 0xf, false));
-        xi = __float_as_int(x);
-        x += __int_as_float(__builtin_amdgcn_update_dpp(0, xi, 0x118, 0xf, 0xf, false));
-        // keeps the last step beside the others for every lane, where the
-        // shifted move folds into the add, instead of letting it sink into
-        // the row leaders' branch as a move, a copy and an add
-        asm volatile("" : : "v"(x));
-        t[f] = x;
+        x[f] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
+    constexpr int kRor8 = 0x128, kHalfMirror = 0x141, kSwap2 = 0x4e, kSwap1 = 0xb1;
+    const bool lo8 = (lane & 8) == 0, lo4 = (lane & 4) == 0, lo2 = (lane & 2) == 0, lo1 = (lane & 1) == 0;
+    // each value covers lanes {i, i ^ 8}: pairs (0, 1), (2, 3), (4, 5), (6, 7)
+    const float p0 = fold_pair<kRor8>(x[0], x[1], lo8), p1 = fold_pair<kRor8>(x[2], x[3], lo8);
+    const float p2 = fold_pair<kRor8>(x[4], x[5], lo8), p3 = fold_pair<kRor8>(x[6], x[7], lo8);
+    float t8 = dpp_add<kRor8>(x[8], x[8]);
+    // four lanes each
+    const float q0 = fold_pair<kHalfMirror>(p0, p1, lo4), q1 = fold_pair<kHalfMirror>(p2, p3, lo4);
+    t8 = dpp_add<kHalfMirror>(t8, t8);
+    // eight lanes each
+    const float r0 = fold_pair<kSwap2>(q0, q1, lo2);
+    t8 = dpp_add<kSwap2>(t8, t8);
+    // the whole row; kept outside the adding lanes' branch, where the shifted
+    // move folds into the add
+    const float total = fold_pair<kSwap1>(r0, t8, lo1);
+    asm volatile("" : : "v"(total));
+    return total;
 }
 
 // Adds the wave's nine gradient terms of each of KG = 4 groups (splat slots
-// slot0 + gi[q]; groups are taken in order, so the non-empty ones come first
-// and an empty one, whose mask is 0, adds nothing) into the LDS accumulator:
-// one combined reduction, then row r's leader adds group r's nine terms.
+// slot0 + gi[q]; an empty group, whose mask is 0, adds nothing) into the LDS
+// accumulator: one combined reduction, then one LDS add in which lane i of
+// row r (i even, or i = 1) adds term term_of_lane(i) of group r.
 template <int BG, int KG>
-__device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[BG], int lane, uint32_t slot0,
+__device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[BG + 1], int lane, uint32_t slot0,
                                                   const int* gi, const uint64_t* gm) {
     static_assert(KG * 9 == 36, "the combined reduction takes four groups");
-    float t[9];
-    wave_reduce36(v, t);
+    const float x = wave_reduce36(v, lane);
     // row r takes group r's slot, or -1 for an empty group (lane selects
     // of the uniform values, no branch)
     int sq[4];
@@ -676,11 +714,8 @@ __device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[B
     const int s01 = (lane & 16) ? sq[1] : sq[0];
     const int s23 = (lane & 16) ? sq[3] : sq[2];
     const int slot = (lane & 32) ? s23 : s01;
-    if ((lane & 15) == 15 && slot >= 0) {
-        float* a = &acc[0][slot];
-#pragma unroll
-        for (int f = 0; f < 9; ++f) atomicAdd(a + f * BG, t[f]);
-    }
+    const int i = lane & 15;
+    if (((i & 1) == 0 || i == 1) && slot >= 0) atomicAdd(&acc[term_of_lane(i)][slot], x);
 }
 
 // The batch's summed terms become its splats' 2D gradients (one thread per
@@ -691,7 +726,7 @@ template <int BG>
 __device__ __forceinline__ void flush_batch(TileLds<BG>& L, int nb, int n, float* __restrict__ grad2d, int t,
                                             int NT) {
     (void)n;
-    float (*acc)[BG] = L.acc;
+    float (*acc)[BG + 1] = L.acc;
     const uint32_t* gid = L.g;
     for (int jj = t; jj < nb; jj += NT) {
         float f[6];
@@ -710,8 +745,8 @@ __device__ __forceinline__ void flush_batch(TileLds<BG>& L, int nb, int n, float
 }
 
 template <int BG>
-__device__ __forceinline__ void zero_acc(float (*acc)[BG], int t, int NT) {
-    for (int idx = t; idx < 9 * BG; idx += NT) (&acc[0][0])[idx] = 0.f;
+__device__ __forceinline__ void zero_acc(float (*acc)[BG + 1], int t, int NT) {
+    for (int idx = t; idx < 9 * (BG + 1); idx += NT) (&acc[0][0])[idx] = 0.f;
 }
 
 // Up to four non-empty groups of a 64-step window, front to back: the
@@ -734,7 +769,7 @@ __device__ __forceinline__ void take_groups(uint64_t& any, uint64_t mv, uint32_t
             any &= any - 1;
             g.gi[q] = i;
             g.gm[q] = read_lane64(mv, i);
-            cursor += __popcll(g.gm[q]);
+            cursor = (uint32_t)__builtin_amdgcn_readfirstlane((int)(cursor + __popcll(g.gm[q])));  // uniform
         }
     }
 }
