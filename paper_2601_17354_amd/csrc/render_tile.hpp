@@ -102,13 +102,9 @@ __device__ __forceinline__ Splat load_shape(const float4* sa, const float4* sb, 
     return Splat{a.x, a.y, a.z, a.w, b.x, b.y, 0.f, 0.f, 0.f};
 }
 
+// Set bits of m below this lane: its rank among the lanes of m.
 __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// base + (set bits of m below this lane): a lane's entry in a group of m.
-__device__ __forceinline__ uint32_t entry_slot(uint64_t m, uint32_t base) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
 }
 
 // Whether this lane's bit is set in the wave-uniform mask m (the mask
