@@ -152,6 +152,38 @@ def test_replay_trace_entries(case, layout):
     say(f"  C_in error / its rounding bound, worst entry: {worst:.3f}")
 
 
+def test_trace_layouts_hold_the_same_colours(case):
+    # Every (tile, wave) region of the 12-byte layout against the first three
+    # words of the 16-byte one, bit for bit: the same entries in the same
+    # order, only the region starts differ between the two launches.  (A
+    # store that picked up the next entry's colour registers showed up here
+    # as single mismatched words.)
+    a, b = case["gc"]["rast"], case["gc4"]["rast"]
+    steps_a, steps_b = a.trace["steps"].cpu().numpy(), b.trace["steps"].cpu().numpy()
+    np.testing.assert_array_equal(steps_a, steps_b)
+    base_a = a.trace["base"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    base_b = b.trace["base"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    masks = a.trace["mask"].cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(masks, b.trace["mask"].cpu().numpy().view(np.uint64))
+    ent_a, ent_b = a.trace["entry"].cpu().numpy(), b.trace["entry"].cpu().numpy()
+    ranges = case["gc"]["ranges"]
+    total = 0
+    for t in range(steps_a.shape[0]):
+        start = int(ranges[0, t])
+        for w in range(steps_a.shape[1]):
+            st = int(steps_a[t, w])
+            if st == 0:
+                continue
+            m = masks[w, start:start + st]
+            cnt = int(np.bitwise_count(m).sum())
+            ra = ent_a[base_a[t, w]:base_a[t, w] + cnt]
+            rb = ent_b[base_b[t, w]:base_b[t, w] + cnt, :3]
+            assert np.array_equal(ra.view(np.uint32), rb.view(np.uint32)), (t, w)
+            total += cnt
+    assert total == int(case["gc"]["count"].sum())
+    say(f"  {total} entries equal in both layouts")
+
+
 @pytest.mark.parametrize("variant", ["gc", "gc4", "gr"])
 def test_render_backward_2d(case, variant):
     g, og, taint = case[variant], case["o_g2d"], case["tainted"]
