@@ -26,7 +26,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(
 }
 
 template <int TW, int TH, int EW>
-__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(EW == 3 ? 5 : 1))) void k_render_bwd_cached(
+__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(EW == 3 ? 6 : 1))) void k_render_bwd_cached(
     int W, int H, int TX, int tile_offset, int n_tiles_total, const float* __restrict__ proj, int n,
     const uint32_t* __restrict__ values, const uint32_t* __restrict__ ranges, Trace tr,
     const float* __restrict__ dl_dimage, float* __restrict__ grad2d, const uint32_t* __restrict__ order) {
