@@ -17,14 +17,15 @@
 // entries in group order are its contributors front to back.  After the
 // front to back pass each wave knows how many entries it recorded and takes
 // a region of exactly that size from a device-wide bump counter (one 64-bit
-// atomic per wave); a wave whose region does not fit the entry capacity is
-// left unrecorded and the overflow flag is raised, the counter then holding
-// the demand the caller needs.  A per-wave step counter bounds the valid
-// groups, so masks of earlier iterations are never read and nothing is
-// cleared between iterations.  The tile's groups are then walked back to
-// front with the splat colours re-staged in LDS, and each entry is written
-// once as (C_in, alpha), one coalesced run per group: C_in is the colour of
-// everything behind the splat, the over-recursion
+// atomic per tile, split among its waves in order); a wave whose region does
+// not fit the entry capacity is left unrecorded and the overflow flag is
+// raised, the counter then holding the demand the caller needs.  A per-wave
+// step counter bounds the valid groups, so masks of earlier iterations are
+// never read and nothing is cleared between iterations.  The tile's groups
+// are then walked back to front with the splats re-staged in LDS, and each
+// entry is written once, one coalesced run per group: C_in (12 bytes; the
+// backward recomputes alpha) or (C_in, alpha) (16 bytes), C_in being the
+// colour of everything behind the splat, the over-recursion
 // C_out = C_in (1 - alpha) + alpha c run from the background.
 //
 // Backward (equation "backward_chain"), two variants:
