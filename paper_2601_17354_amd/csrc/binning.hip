@@ -203,7 +203,7 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* off, uint32_t n, uin
 
 template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_emit_sorted(uint32_t items, int n, EmitViews ev,
-                                                              const float* __restrict__ proj_all,
+                                                              const uint64_t* __restrict__ dkeys,
                                                               const uint32_t* __restrict__ rect_all,
                                                               const uint32_t* __restrict__ dvals,
                                                               const uint32_t* __restrict__ off,
@@ -241,7 +241,8 @@ __global__ __launch_bounds__(kSortThreads) void k_emit_sorted(uint32_t items, in
             const uint32_t w = x1 - x0 + 1;
             const uint32_t ty = y0 + local / w, tx = x0 + local % w;
             const uint64_t tile = (uint64_t)((uint32_t)toff + ty * (uint32_t)TX + tx);
-            const uint32_t dbits = __float_as_uint(proj_all[(size_t)item * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
+            // the depth bits are the sorted key itself (no read of the record)
+            const uint32_t dbits = (uint32_t)dkeys[i0 + j];
             keys[p] = (tile << 32) | (uint64_t)dbits;
             values[p] = g;
             atomicAdd(&h[(uint32_t)tile & 0xffu], 1u);
@@ -651,11 +652,11 @@ pgs_status bin_sort_items(uint32_t items, int n, const EmitViews& ev, int n_tile
     const SortWs& pw = w.pairs_ws;
     const uint32_t ge = pw.nb > 0 ? pw.nb : 1u;
     if (pw.rounds == kSortRoundsSmall)
-        k_emit_sorted<kSortRoundsSmall><<<ge, kSortThreads, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals,
+        k_emit_sorted<kSortRoundsSmall><<<ge, kSortThreads, 0, s>>>(items, n, ev, w.dkeys, rect_all, w.dvals,
                                                                     w.off, num_pairs, capacity, keys, values,
                                                                     flags, pw.nb, pw.hist);
     else
-        k_emit_sorted<kSortRoundsLarge><<<ge, kSortThreads, 0, s>>>(items, n, ev, proj_all, rect_all, w.dvals,
+        k_emit_sorted<kSortRoundsLarge><<<ge, kSortThreads, 0, s>>>(items, n, ev, w.dkeys, rect_all, w.dvals,
                                                                     w.off, num_pairs, capacity, keys, values,
                                                                     flags, pw.nb, pw.hist);
     PGS_CHECK_LAUNCH(who);
