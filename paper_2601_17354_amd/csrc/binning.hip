@@ -148,7 +148,7 @@ template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_depth_keys(uint32_t items, int n,
                                                              const float* __restrict__ proj_all,
                                                              const uint32_t* __restrict__ touched_all,
-                                                             uint64_t* __restrict__ dkeys,
+                                                             uint32_t* __restrict__ dkeys,
                                                              uint32_t* __restrict__ dvals,
                                                              uint32_t* __restrict__ count, uint32_t nb,
                                                              uint32_t* __restrict__ hist,
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kSortThreads) void k_depth_keys(uint32_t items, int
             // 4-byte read per 64-byte record, so culled items cost a line)
             uint32_t key = 0xffffffffu;
             if (touched_all[i]) key = __float_as_uint(proj_all[(size_t)i * PGS_PROJ_STRIDE + PGS_PROJ_DEPTH]);
-            dkeys[i] = (uint64_t)key;
+            dkeys[i] = key;
             dvals[i] = i;
             atomicAdd(&h[key & 0xffu], 1u);
         }
@@ -203,7 +203,7 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* off, uint32_t n, uin
 
 template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_emit_sorted(uint32_t items, int n, EmitViews ev,
-                                                              const uint64_t* __restrict__ dkeys,
+                                                              const uint32_t* __restrict__ dkeys,
                                                               const uint32_t* __restrict__ rect_all,
                                                               const uint32_t* __restrict__ dvals,
                                                               const uint32_t* __restrict__ off,
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kSortThreads) void k_emit_sorted(uint32_t items, in
             const uint32_t ty = y0 + local / w, tx = x0 + local % w;
             const uint64_t tile = (uint64_t)((uint32_t)toff + ty * (uint32_t)TX + tx);
             // the depth bits are the sorted key itself (no read of the record)
-            const uint32_t dbits = (uint32_t)dkeys[i0 + j];
+            const uint32_t dbits = dkeys[i0 + j];
             keys[p] = (tile << 32) | (uint64_t)dbits;
             values[p] = g;
             atomicAdd(&h[(uint32_t)tile & 0xffu], 1u);
@@ -260,8 +260,8 @@ __device__ __forceinline__ uint32_t clamp_count(const uint32_t* num, uint32_t ca
 // Digit histogram of each block's chunk of 256 R keys, stored digit-major
 // hist[d * nb + block] so that one exclusive scan yields every block's
 // output offset for every digit.
-template <int R>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
+template <int R, class K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict__ keys,
                                                              const uint32_t* __restrict__ num,
                                                              uint32_t capacity, int shift, uint32_t nb,
                                                              uint32_t* __restrict__ hist) {
@@ -295,14 +295,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
 // that order and leave as one contiguous run per digit, so the global
 // writes coalesce.  With gdst, the pass also writes gdst[pos] = gsrc[value]
 // (a gather in the output order).
-template <int R>
+template <int R, class K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ num,
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+    K* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ num,
     uint32_t capacity, int shift, uint32_t nb, const uint32_t* __restrict__ offs,
     const uint32_t* __restrict__ gsrc, uint32_t* __restrict__ gdst) {
     constexpr int NW = kSortThreads / 64;
-    __shared__ uint64_t s_key[kSortThreads * R];
+    __shared__ K s_key[kSortThreads * R];
     __shared__ uint32_t s_val[kSortThreads * R];
     __shared__ uint32_t s_run[kRadix];     // next local position per digit
     __shared__ uint32_t s_lbase[kRadix];   // digit start inside the block
@@ -324,12 +324,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     s_run[t] = lb;
     // All of the block's loads are issued before the first round, so the
     // rounds wait on LDS only.
-    uint64_t kreg[R];
+    K kreg[R];
     uint32_t vreg[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t idx = base + r * kSortThreads + t;
-        kreg[r] = idx < count ? kin[idx] : 0ull;
+        kreg[r] = idx < count ? kin[idx] : (K)0;
         vreg[r] = idx < count ? vin[idx] : 0u;
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     const uint32_t here = min((uint32_t)kSortThreads * R, count - base);
     for (uint32_t i = t; i < here; i += kSortThreads) {
-        const uint64_t key = s_key[i];
+        const K key = s_key[i];
         const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
         const uint32_t pos = s_gbase[d] + (i - s_lbase[d]);
         kout[pos] = key;
@@ -373,8 +373,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
 }
 
-__global__ void k_copy_pairs(const uint64_t* __restrict__ ks, const uint32_t* __restrict__ vs,
-                             uint64_t* __restrict__ kd, uint32_t* __restrict__ vd,
+template <class K>
+__global__ void k_copy_pairs(const K* __restrict__ ks, const uint32_t* __restrict__ vs,
+                             K* __restrict__ kd, uint32_t* __restrict__ vd,
                              const uint32_t* __restrict__ num, uint32_t capacity) {
     const uint32_t count = clamp_count(num, capacity);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
@@ -461,13 +462,17 @@ SortWs sort_layout(void* base, uint32_t capacity) {
 // Sorts key bits [start_bit, start_bit + key_bits) (stable).  first_hist:
 // the caller already wrote the first pass's digit histogram into w.hist.
 // With gdst, the last pass also writes gdst[i] = gsrc[value at i].
-pgs_status radix_sort(uint64_t* keys, uint32_t* vals, const uint32_t* num, uint32_t capacity,
+// Keys of type K (uint64_t, or uint32_t for the depth sort, whose keys are
+// 32 bits: a third less traffic per pass); the ping-pong key buffer is sized
+// for 64-bit keys and holds either.
+template <class K>
+pgs_status radix_sort(K* keys, uint32_t* vals, const uint32_t* num, uint32_t capacity,
                       int key_bits, const SortWs& w, hipStream_t s, int start_bit = 0, bool first_hist = false,
                       const uint32_t* gsrc = nullptr, uint32_t* gdst = nullptr) {
     if (capacity == 0) return PGS_OK;
     const int passes = (key_bits + 7) / 8;
-    uint64_t* kin = keys; uint32_t* vin = vals;
-    uint64_t* kout = w.keys_alt; uint32_t* vout = w.vals_alt;
+    K* kin = keys; uint32_t* vin = vals;
+    K* kout = reinterpret_cast<K*>(w.keys_alt); uint32_t* vout = w.vals_alt;
     for (int p = 0; p < passes; ++p) {
         const int shift = start_bit + 8 * p;
         const bool last = p + 1 == passes;
@@ -475,26 +480,26 @@ pgs_status radix_sort(uint64_t* keys, uint32_t* vals, const uint32_t* num, uint3
         uint32_t* gd = last ? gdst : nullptr;
         if (p > 0 || !first_hist) {
             if (w.rounds == kSortRoundsSmall)
-                k_radix_hist<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb,
-                                                                             w.hist);
+                k_radix_hist<kSortRoundsSmall, K><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb,
+                                                                                w.hist);
             else
-                k_radix_hist<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb,
-                                                                             w.hist);
+                k_radix_hist<kSortRoundsLarge, K><<<w.nb, kSortThreads, 0, s>>>(kin, num, capacity, shift, w.nb,
+                                                                                w.hist);
         }
         pgs_status st = scan_u32(w.hist, w.hist, w.nb * kRadix, nullptr, w.partial, s);
         if (st != PGS_OK) return st;
         if (w.rounds == kSortRoundsSmall)
-            k_radix_scatter<kSortRoundsSmall><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
-                                                                            shift, w.nb, w.hist, gs, gd);
+            k_radix_scatter<kSortRoundsSmall, K><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
+                                                                               shift, w.nb, w.hist, gs, gd);
         else
-            k_radix_scatter<kSortRoundsLarge><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
-                                                                            shift, w.nb, w.hist, gs, gd);
+            k_radix_scatter<kSortRoundsLarge, K><<<w.nb, kSortThreads, 0, s>>>(kin, vin, kout, vout, num, capacity,
+                                                                               shift, w.nb, w.hist, gs, gd);
         PGS_CHECK_LAUNCH("radix pass");
-        uint64_t* tk = kin; kin = kout; kout = tk;
+        K* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
     if (kin != keys) {
-        k_copy_pairs<<<1024, 256, 0, s>>>(kin, vin, keys, vals, num, capacity);
+        k_copy_pairs<K><<<1024, 256, 0, s>>>(kin, vin, keys, vals, num, capacity);
         PGS_CHECK_LAUNCH("radix copy");
     }
     return PGS_OK;
@@ -596,7 +601,7 @@ namespace {
 // pairs: depth keys and item ids, pair offsets, scan partials, the item
 // count word, and the two sorts' ping-pong buffers.
 struct BinWs {
-    uint64_t* dkeys;
+    uint32_t* dkeys;
     uint32_t* dvals;
     uint32_t* off;
     uint32_t* partial;
@@ -610,7 +615,7 @@ BinWs bin_layout(void* base, uint32_t items, uint32_t capacity) {
     BinWs w{};
     char* p = static_cast<char*>(base);
     size_t off = 0;
-    w.dkeys = reinterpret_cast<uint64_t*>(p + off); off += align_up((size_t)items * 8);
+    w.dkeys = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)items * 4);
     w.dvals = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)items * 4);
     w.off = reinterpret_cast<uint32_t*>(p + off); off += align_up((size_t)items * 4);
     w.partial = reinterpret_cast<uint32_t*>(p + off); off += scan_workspace(items);
