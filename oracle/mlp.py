@@ -5,7 +5,7 @@ PocketGS seeds each Gaussian from local surface statistics (Sec.
 The network here is not in the paper: it predicts corrections to that
 disc-like seed from the point's neighbourhood.  Its definition is this
 project's proposal; the oracle fixes the arithmetic, not the network's
-quality (parity of the trained network's usefulness is judged by PSNR only).
+quality (parity of the trained network's usefulness is measured by PSNR only).
 
 Features of point i (neighbours p_k = its 16 nearest, nearest first;
 C = covariance of the 16 about their centroid, as in the equation for C_i;
