@@ -718,7 +718,9 @@ __device__ __forceinline__ void accumulate_groups(const float* v, float (*acc)[B
 // The batch's summed terms become its splats' 2D gradients (one thread per
 // splat), then one float atomic per field and splat goes into the canonical
 // 2D-gradient records (index map values[id]); the nine fields of a splat
-// share one 64-byte record, so consecutive lanes hit the same line.
+// share one 64-byte record, so consecutive lanes hit the same line.  Each
+// accumulator word is cleared as it is read, so the next batch starts from
+// zeros (slots past nb are never written).
 template <int BG>
 __device__ __forceinline__ void flush_batch(TileLds<BG>& L, int nb, int n, float* __restrict__ grad2d, int t,
                                             int NT) {
@@ -737,6 +739,7 @@ __device__ __forceinline__ void flush_batch(TileLds<BG>& L, int nb, int n, float
     for (int idx = t; idx < nb * 9; idx += NT) {
         const int jj = idx / 9, f = idx - jj * 9;
         const float s = acc[f][jj];
+        acc[f][jj] = 0.f;
         if (s != 0.f) unsafeAtomicAdd(&grad2d[(size_t)gid[jj] * PGS_GRAD2D_STRIDE + f], s);
     }
 }
@@ -849,11 +852,11 @@ __device__ __forceinline__ void bwd_cached_tile(const TileJob& j, int n_tiles_to
     __syncthreads();
     const uint32_t smax = L.steps;
     uint32_t cursor = 0;
+    zero_acc<BG>(L.acc, t, NT);  // once: each flush leaves the accumulator cleared
 
     for (uint32_t base = 0; base < smax; base += BG) {
         const int nb = (int)min((uint32_t)BG, smax - base);
         stage_batch<NT, true>(L, j.proj, n, values, start + base, nb, t);
-        zero_acc<BG>(L.acc, t, NT);
         __syncthreads();
         const uint32_t whi = min(base + (uint32_t)nb, steps);
         for (uint32_t c0 = base; c0 < whi; c0 += 64) {
@@ -925,12 +928,12 @@ __device__ __forceinline__ void bwd_recompute_tile(const TileJob& j, int n,
     __syncthreads();
     const uint32_t top = L.steps;
     const int wv = t >> 6;
+    zero_acc<BG>(L.acc, t, NT);  // once: each flush leaves the accumulator cleared
 
     for (uint32_t hi = top; hi > 0;) {
         const uint32_t lo = hi > (uint32_t)BG ? hi - BG : 0u;
         const int nb = (int)(hi - lo);
         stage_batch_reach<TW, TH, NT, true>(L, j.proj, values, start + lo, nb, t, j.tx, j.ty);
-        zero_acc<BG>(L.acc, t, NT);
         __syncthreads();
         // back to front over the steps whose splat can reach one of the
         // wave's pixels (windows of 64 last to first, scalar bit scans); the
