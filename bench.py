@@ -231,18 +231,6 @@ def graph_runs(wl, order, steps, warmup, views=20):
     tr.rast.flags.zero_()
     state = (tr.params, tr.m, tr.v, tr.adam_state)
     snap = [t.clone() for t in state]
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    graphs = []
-    with torch.cuda.stream(side):
-        for cid in ids:
-            B.pgs_graph_begin(side)
-            try:
-                tr.step(cams[cid], targets[cid])
-            finally:
-                graphs.append(B.pgs_graph_end(side))
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
 
     def timed(run):
         for dst, src in zip(state, snap):
@@ -256,8 +244,22 @@ def graph_runs(wl, order, steps, warmup, views=20):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    ms_graph = timed(lambda k: B.pgs_graph_launch(graphs[k % len(graphs)]))
+    # the eager steps first: after a capture, event-timed eager steps have
+    # read slower than their kernels
     ms_eager = timed(lambda k: tr.step(cams[ids[k % len(ids)]], targets[ids[k % len(ids)]]))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graphs = []
+    with torch.cuda.stream(side):
+        for cid in ids:
+            B.pgs_graph_begin(side)
+            try:
+                tr.step(cams[cid], targets[cid])
+            finally:
+                graphs.append(B.pgs_graph_end(side))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ms_graph = timed(lambda k: B.pgs_graph_launch(graphs[k % len(graphs)]))
     flags = tr.rast.read_flags()
     for g in graphs:
         B.pgs_graph_destroy(g)
@@ -650,13 +652,16 @@ def batched_runs(n, steps=20, warmup=3, tuned=None, compare=True):
     # capture the stage events of eager steps have read up to twice the
     # kernel-trace durations of the persistent launches)
     kern, roofs = batched_kernel_times(st)
-    st.capture()
     # eager steps and graph replays from the same optimiser state, so that
-    # both time the same work (training changes the pair and entry counts)
+    # both time the same work (training changes the pair and entry counts);
+    # the eager steps are timed before the capture for the same reason as
+    # the stage times above
     snap = st.snapshot()
-    ms_graph = time_steps(st.replay, steps, warmup)
-    st.restore(snap)
     ms_eager = time_steps(st.step, steps, warmup)
+    st.restore(snap)
+    st.capture()
+    st.restore(snap)
+    ms_graph = time_steps(st.replay, steps, warmup)
     assert st.read_flags() == 0, "batched step overflowed during timing"
     stats = st.stats()
     del st
